@@ -1,0 +1,201 @@
+"""FP64 CPU oracle for the all-pairs N-body force evaluation.
+
+TEST INFRASTRUCTURE ONLY.  The only callers allowed are the test suite
+(``tests/``), the smoke check in ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py``.  The product package never imports this
+module and this module never imports the product package: the two share no
+code, header, helper or constant, and meet only at the seeded input arrays.
+
+The arithmetic lives in ``oracle.c`` (plain C, IEEE double, compensated sums
+over j, OpenMP over i).  This file only builds and loads it and converts
+numpy arrays to pointers.  Every function here follows the paper passage its C
+counterpart cites:
+
+* :func:`gravity` -- Eq. 1 (Section 3.3), Table 1 "Gravity (accel)", plus the
+  softened potential whose negative gradient is Eq. 1;
+* :func:`ljc_linear` -- Table 1 "LJC (linear)" (Coulomb with dielectric D*r
+  plus Lennard-Jones), read potential-consistently;
+* :func:`leapfrog` -- the force-then-update cycle of Section 1 as
+  kick-drift-kick leapfrog;
+* :func:`gravity_adjoint`, :func:`ljc_adjoint` -- derivatives of the two laws
+  (not in the paper; written out from the definitions above).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+GRAVITY = 0
+LJC_LINEAR = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` into ``liboracle.so`` with gcc (IEEE, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+               "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        I = ctypes.c_int
+        lib.oracle_threads.argtypes = [I]
+        lib.oracle_threads.restype = I
+        lib.oracle_gravity.argtypes = [P, P, I64, D, D, P, I64, I64, I64, P, P, I]
+        lib.oracle_ljc_linear.argtypes = [P, P, P, P, I64, D, D, P, I64, I64, I64, P, P, I]
+        lib.oracle_leapfrog.argtypes = [I, P, P, P, P, P, I64, D, D, D, ctypes.c_int32, P, I]
+        lib.oracle_gravity_adjoint.argtypes = [P, P, I64, D, D, P, P, I64, P, I]
+        lib.oracle_ljc_adjoint.argtypes = [P, P, P, P, I64, D, D, P, P, I64, P, P, P, P, I]
+        for f in (lib.oracle_gravity, lib.oracle_ljc_linear, lib.oracle_leapfrog,
+                  lib.oracle_gravity_adjoint, lib.oracle_ljc_adjoint):
+            f.restype = I
+        _lib = lib
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None and a.shape != shape:
+        raise ValueError("expected shape %s, got %s" % (shape, a.shape))
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _ilist(ilist, n):
+    if ilist is None:
+        return None, n
+    il = np.ascontiguousarray(ilist, dtype=np.int64)
+    if il.size and (il.min() < 0 or il.max() >= n):
+        raise ValueError("ilist out of range")
+    return il, il.size
+
+
+def threads(nthreads: int = 0) -> int:
+    """Threads the oracle's OpenMP loops use for a request of ``nthreads`` (0 = all)."""
+    return int(_load().oracle_threads(int(nthreads)))
+
+
+def gravity(pos, mass, G=1.0, eps=0.0, ilist=None, jrange=None, nthreads=0):
+    """Softened gravity of Eq. 1: returns (acc [ni,3], phi [ni]) in FP64.
+
+    ``ilist`` restricts the rows (i-subset); ``jrange=(j0, j1)`` restricts the
+    sources to a contiguous j range (for the replication identity of
+    Section 3.4)."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    pos = _f64(pos, (n, 3))
+    mass = _f64(mass, (n,))
+    il, ni = _ilist(ilist, n)
+    j0, j1 = (0, n) if jrange is None else (int(jrange[0]), int(jrange[1]))
+    acc = np.empty((ni, 3))
+    phi = np.empty(ni)
+    rc = _load().oracle_gravity(_ptr(pos), _ptr(mass), n, float(G), float(eps), _ptr(il), ni,
+                                j0, j1, _ptr(acc), _ptr(phi), int(nthreads))
+    if rc:
+        raise ValueError("oracle_gravity rc=%d" % rc)
+    return acc, phi
+
+
+def ljc_linear(pos, q, sigma, epsilon, kc=332.0637, D=4.0, ilist=None, jrange=None, nthreads=0):
+    """LJ + Coulomb(dielectric D*r) of Table 1: returns (force [ni,3], U_i [ni])."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    pos = _f64(pos, (n, 3))
+    q = _f64(q, (n,))
+    sigma = _f64(sigma, (n,))
+    epsilon = _f64(epsilon, (n,))
+    il, ni = _ilist(ilist, n)
+    j0, j1 = (0, n) if jrange is None else (int(jrange[0]), int(jrange[1]))
+    f = np.empty((ni, 3))
+    u = np.empty(ni)
+    rc = _load().oracle_ljc_linear(_ptr(pos), _ptr(q), _ptr(sigma), _ptr(epsilon), n, float(kc),
+                                   float(D), _ptr(il), ni, j0, j1, _ptr(f), _ptr(u), int(nthreads))
+    if rc:
+        raise ValueError("oracle_ljc_linear rc=%d" % rc)
+    return f, u
+
+
+def leapfrog(law, pos, vel, acc, params, dt, nsteps, inv_mass=None, G=1.0, eps=0.0,
+             kc=332.0637, D=4.0, nthreads=0):
+    """Kick-drift-kick leapfrog in FP64.  Returns (pos, vel, acc, pot) after ``nsteps``.
+
+    ``params`` is the mass [n] for gravity, or an [n,3] array of (q, sigma,
+    epsilon) for LJC(linear).  ``acc`` is a(t) on entry."""
+    pos = _f64(pos).copy()
+    n = pos.shape[0]
+    vel = _f64(vel, (n, 3)).copy()
+    acc = _f64(acc, (n, 3)).copy()
+    if law == GRAVITY:
+        par = _f64(params, (n,))
+        c0, c1 = float(G), float(eps)
+    elif law == LJC_LINEAR:
+        par = np.ascontiguousarray(_f64(params, (n, 3)).T)  # q | sigma | eps blocks
+        c0, c1 = float(kc), float(D)
+    else:
+        raise ValueError("law")
+    im = None if inv_mass is None else _f64(inv_mass, (n,))
+    pot = np.empty(n)
+    rc = _load().oracle_leapfrog(int(law), _ptr(pos), _ptr(vel), _ptr(acc), _ptr(par), _ptr(im), n,
+                                 c0, c1, float(dt), int(nsteps), _ptr(pot), int(nthreads))
+    if rc:
+        raise ValueError("oracle_leapfrog rc=%d" % rc)
+    return pos, vel, acc, pot
+
+
+def gravity_adjoint(pos, mass, g, G=1.0, eps=0.0, ilist=None, nthreads=0):
+    """dL/dr for L with dL/da = g under Eq. 1 (the Hessian-vector product)."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    pos = _f64(pos, (n, 3))
+    mass = _f64(mass, (n,))
+    g = _f64(g, (n, 3))
+    il, ni = _ilist(ilist, n)
+    out = np.empty((ni, 3))
+    rc = _load().oracle_gravity_adjoint(_ptr(pos), _ptr(mass), n, float(G), float(eps), _ptr(g),
+                                        _ptr(il), ni, _ptr(out), int(nthreads))
+    if rc:
+        raise ValueError("oracle_gravity_adjoint rc=%d" % rc)
+    return out
+
+
+def ljc_adjoint(pos, q, sigma, epsilon, g, kc=332.0637, D=4.0, ilist=None, nthreads=0):
+    """(dL/dr [ni,3], dL/dq [ni], dL/dsigma [ni], dL/depsilon [ni]) for dL/dF = g."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    pos = _f64(pos, (n, 3))
+    q = _f64(q, (n,))
+    sigma = _f64(sigma, (n,))
+    epsilon = _f64(epsilon, (n,))
+    g = _f64(g, (n, 3))
+    il, ni = _ilist(ilist, n)
+    gp = np.empty((ni, 3))
+    gq = np.empty(ni)
+    gs = np.empty(ni)
+    ge = np.empty(ni)
+    rc = _load().oracle_ljc_adjoint(_ptr(pos), _ptr(q), _ptr(sigma), _ptr(epsilon), n, float(kc),
+                                    float(D), _ptr(g), _ptr(il), ni, _ptr(gp), _ptr(gq), _ptr(gs),
+                                    _ptr(ge), int(nthreads))
+    if rc:
+        raise ValueError("oracle_ljc_adjoint rc=%d" % rc)
+    return gp, gq, gs, ge

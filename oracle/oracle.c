@@ -1,0 +1,332 @@
+/*
+ * FP64 CPU oracle for the all-pairs N-body force evaluation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or constant with the
+ * HIP library; the two meet only at the seeded input arrays.
+ *
+ * Every function is the plain definition written out: a double loop over the
+ * requested i and every j != i (Section 2, the naive all-pairs pseudo-code),
+ * pair arithmetic in IEEE double (built with -ffp-contract=off, no fast-math),
+ * and a Neumaier-compensated sum over j so that the reference itself is not
+ * the dominant error when force terms cancel.  OpenMP runs over i only; the
+ * j order is 0..N-1 for every i, so results do not depend on thread count.
+ *
+ * Readings of the paper used here (each is listed with its reason in the
+ * design notes):
+ *   - displacement d_ij = r_j - r_i; gravity attracts (Eq. 1 with the
+ *     Appendix listing's d = jpos - ipos and "+=");
+ *   - the softening constant added to r^2 in the Appendix listing is eps^2,
+ *     eps being the softening length passed in;
+ *   - the softened potential phi_i = -G sum_j m_j / sqrt(r^2 + eps^2) whose
+ *     negative gradient is Eq. 1;
+ *   - LJC(linear) of Table 1 is read potential-consistently: pair energy
+ *     u = k q_i q_j / (D r^2) + 4 e_ij [(s_ij/r)^12 - (s_ij/r)^6] with
+ *     Lorentz-Berthelot combining s_ij = (s_i+s_j)/2, e_ij = sqrt(e_i e_j),
+ *     and force F_i = -grad_i of the total energy.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ---- compensated summation (Neumaier's improvement of Kahan's method) ---- */
+typedef struct { double s, c; } nsum;
+
+static inline void nadd(nsum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static inline double nval(const nsum *a) { return a->s + a->c; }
+
+static int set_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+/* Number of threads the oracle's parallel loops will use after a call with
+ * the given request (0 = OpenMP default). */
+int oracle_threads(int nthreads) { return set_threads(nthreads); }
+
+static inline int64_t row(const int64_t *ilist, int64_t k) { return ilist ? ilist[k] : k; }
+
+/* ------------------------------------------------------------------------
+ * Softened gravity, Eq. 1 (Section 3.3) and Table 1 row "Gravity (accel)".
+ *   a_i   = G sum_{j != i, j0 <= j < j1} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2}
+ *   phi_i = -G sum_{same j} m_j / (|r_j - r_i|^2 + eps^2)^{1/2}
+ * i runs over ilist[0..ni) (or 0..ni when ilist is NULL).  The j range
+ * [j0, j1) exists so that the i-replication identity of Section 3.4
+ * (partial sums over disjoint j ranges add up to the full sum) can be
+ * checked.  acc is [ni][3]; phi is [ni] or NULL.
+ * ---------------------------------------------------------------------- */
+int oracle_gravity(const double *pos, const double *mass, int64_t n, double G, double eps,
+                   const int64_t *ilist, int64_t ni, int64_t j0, int64_t j1,
+                   double *acc, double *phi, int nthreads)
+{
+    if (n < 0 || ni < 0 || j0 < 0 || j1 > n || j0 > j1) return -1;
+    set_threads(nthreads);
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < ni; ++k) {
+        const int64_t i = row(ilist, k);
+        const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+        nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0}, ph = {0, 0};
+        for (int64_t j = j0; j < j1; ++j) {
+            if (j == i) continue;
+            const double dx = pos[3 * j] - xi;
+            const double dy = pos[3 * j + 1] - yi;
+            const double dz = pos[3 * j + 2] - zi;
+            const double s2 = dx * dx + dy * dy + dz * dz + eps2;
+            const double s = sqrt(s2);
+            const double inv_s3 = 1.0 / (s2 * s);
+            nadd(&ax, mass[j] * dx * inv_s3);
+            nadd(&ay, mass[j] * dy * inv_s3);
+            nadd(&az, mass[j] * dz * inv_s3);
+            nadd(&ph, mass[j] / s);
+        }
+        acc[3 * k] = G * nval(&ax);
+        acc[3 * k + 1] = G * nval(&ay);
+        acc[3 * k + 2] = G * nval(&az);
+        if (phi) phi[k] = -G * nval(&ph);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * LJ + Coulomb with a linear distance-dependent dielectric eps(r) = D r
+ * (Table 1 row "LJC (linear)"; Section 2 on continuum-solvent models).
+ *   u_ij = kc q_i q_j / (D r^2) + 4 e_ij [(s_ij/r)^12 - (s_ij/r)^6]
+ *   F_i  = sum_{j != i} [ 2 kc q_i q_j / (D r^4)
+ *                         + (24 e_ij / r^2) (2 (s_ij/r)^12 - (s_ij/r)^6) ] (r_i - r_j)
+ *   U_i  = sum_{j != i} u_ij      (total potential energy = U_tot = 1/2 sum_i U_i)
+ * params per atom: q (charge), sigma, epsilon.  force is [ni][3], energy
+ * [ni] or NULL.
+ * ---------------------------------------------------------------------- */
+int oracle_ljc_linear(const double *pos, const double *q, const double *sigma,
+                      const double *epsl, int64_t n, double kc, double D,
+                      const int64_t *ilist, int64_t ni, int64_t j0, int64_t j1,
+                      double *force, double *energy, int nthreads)
+{
+    if (n < 0 || ni < 0 || j0 < 0 || j1 > n || j0 > j1) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < ni; ++k) {
+        const int64_t i = row(ilist, k);
+        const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
+        nsum fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, en = {0, 0};
+        for (int64_t j = j0; j < j1; ++j) {
+            if (j == i) continue;
+            const double rx = xi - pos[3 * j];
+            const double ry = yi - pos[3 * j + 1];
+            const double rz = zi - pos[3 * j + 2];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double sij = 0.5 * (sigma[i] + sigma[j]);
+            const double eij = sqrt(epsl[i] * epsl[j]);
+            const double sr2 = sij * sij / r2;
+            const double sr6 = sr2 * sr2 * sr2;
+            const double sr12 = sr6 * sr6;
+            const double coul = kc * q[i] * q[j] / D;          /* u_C = coul / r^2 */
+            const double W = 2.0 * coul / (r2 * r2) + 24.0 * eij / r2 * (2.0 * sr12 - sr6);
+            nadd(&fx, W * rx);
+            nadd(&fy, W * ry);
+            nadd(&fz, W * rz);
+            nadd(&en, coul / r2 + 4.0 * eij * (sr12 - sr6));
+        }
+        force[3 * k] = nval(&fx);
+        force[3 * k + 1] = nval(&fy);
+        force[3 * k + 2] = nval(&fz);
+        if (energy) energy[k] = nval(&en);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Time-step cycle (Section 1: force evaluation, then the update step, then
+ * repeat).  The paper names no integrator; the reading is kick-drift-kick
+ * leapfrog (velocity Verlet) in FP64 with the acceleration carried:
+ *   v += dt/2 a(x);  x += dt v;  a = a(x);  v += dt/2 a.
+ * law 0 = gravity (params = mass [n]; a is the acceleration of Eq. 1);
+ * law 1 = LJC(linear) (params = q, sigma, eps as three [n] arrays packed
+ * one after another, i.e. params[0..n), params[n..2n), params[2n..3n));
+ * a = F * inv_mass.
+ * acc holds a(t) on entry and a(t + nsteps dt) on exit.  pot (or NULL)
+ * receives phi (gravity) or U_i (LJC) at the final positions.
+ * ---------------------------------------------------------------------- */
+static int eval_accel(int law, const double *pos, const double *params, const double *inv_mass,
+                      int64_t n, double c0, double c1, double *acc, double *pot, int nthreads)
+{
+    if (law == 0)
+        return oracle_gravity(pos, params, n, c0, c1, NULL, n, 0, n, acc, pot, nthreads);
+    if (law == 1) {
+        int rc = oracle_ljc_linear(pos, params, params + n, params + 2 * n, n, c0, c1, NULL, n, 0, n,
+                                   acc, pot, nthreads);
+        if (rc) return rc;
+        for (int64_t i = 0; i < n; ++i) {
+            const double w = inv_mass ? inv_mass[i] : 1.0;
+            acc[3 * i] *= w;
+            acc[3 * i + 1] *= w;
+            acc[3 * i + 2] *= w;
+        }
+        return 0;
+    }
+    return -1;
+}
+
+int oracle_leapfrog(int law, double *pos, double *vel, double *acc, const double *params,
+                    const double *inv_mass, int64_t n, double c0, double c1, double dt,
+                    int32_t nsteps, double *pot, int nthreads)
+{
+    if (n < 0 || nsteps < 0) return -1;
+    for (int32_t s = 0; s < nsteps; ++s) {
+        for (int64_t e = 0; e < 3 * n; ++e) {
+            vel[e] += 0.5 * dt * acc[e];
+            pos[e] += dt * vel[e];
+        }
+        const int last = (s == nsteps - 1);
+        int rc = eval_accel(law, pos, params, inv_mass, n, c0, c1, acc, last ? pot : NULL, nthreads);
+        if (rc) return rc;
+        for (int64_t e = 0; e < 3 * n; ++e) vel[e] += 0.5 * dt * acc[e];
+    }
+    if (nsteps == 0 && pot) {
+        double *tmp = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+        if (!tmp) return -2;
+        int rc = eval_accel(law, pos, params, inv_mass, n, c0, c1, tmp, pot, nthreads);
+        free(tmp);
+        return rc;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Adjoint of the gravity acceleration with respect to positions (the
+ * Hessian-vector product of the potential).  Not in the paper; it is the
+ * derivative of Eq. 1 written out.  With d = r_j - r_k, s^2 = |d|^2 + eps^2
+ * and K(d) v = v / s^3 - 3 (d.v) d / s^5 (the Jacobian of d / s^3):
+ *   dL/dr_k = G sum_{j != k} K(d) (m_k g_j - m_j g_k),     g_i = dL/da_i.
+ * out is [ni][3].
+ * ---------------------------------------------------------------------- */
+int oracle_gravity_adjoint(const double *pos, const double *mass, int64_t n, double G, double eps,
+                           const double *g, const int64_t *ilist, int64_t ni, double *out,
+                           int nthreads)
+{
+    if (n < 0 || ni < 0) return -1;
+    set_threads(nthreads);
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t kk = 0; kk < ni; ++kk) {
+        const int64_t k = row(ilist, kk);
+        nsum ox = {0, 0}, oy = {0, 0}, oz = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == k) continue;
+            const double dx = pos[3 * j] - pos[3 * k];
+            const double dy = pos[3 * j + 1] - pos[3 * k + 1];
+            const double dz = pos[3 * j + 2] - pos[3 * k + 2];
+            const double s2 = dx * dx + dy * dy + dz * dz + eps2;
+            const double s = sqrt(s2);
+            const double inv_s3 = 1.0 / (s2 * s);
+            const double inv_s5 = inv_s3 / s2;
+            const double vx = mass[k] * g[3 * j] - mass[j] * g[3 * k];
+            const double vy = mass[k] * g[3 * j + 1] - mass[j] * g[3 * k + 1];
+            const double vz = mass[k] * g[3 * j + 2] - mass[j] * g[3 * k + 2];
+            const double dv = dx * vx + dy * vy + dz * vz;
+            nadd(&ox, vx * inv_s3 - 3.0 * dv * dx * inv_s5);
+            nadd(&oy, vy * inv_s3 - 3.0 * dv * dy * inv_s5);
+            nadd(&oz, vz * inv_s3 - 3.0 * dv * dz * inv_s5);
+        }
+        out[3 * kk] = G * nval(&ox);
+        out[3 * kk + 1] = G * nval(&oy);
+        out[3 * kk + 2] = G * nval(&oz);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Adjoint of the LJC(linear) force (derivative of the Table 1 law as read
+ * above; not in the paper).  Write F_i = sum_j w(r_ij) d_ij with
+ * d_ij = r_j - r_i and
+ *   w = -[ C / r^4 + 24 e (2 s^12 / r^14 - s^6 / r^8) ],   C = 2 kc q_i q_j / D.
+ * Its Jacobian in d is M(d) = w I + (w'/r) d d^T with
+ *   w'/r = 4 C / r^6 + 24 e (28 s^12 / r^16 - 8 s^6 / r^10).
+ * For g_i = dL/dF_i:
+ *   dL/dr_k = sum_{j != k} M(d_kj) (g_j - g_k)
+ *   dL/dp_k = sum_{j != k} (dw_kj/dp_k) d_kj . (g_k - g_j)   for p in {q, sigma, eps}
+ * with dw/dq_k = -2 kc q_j / (D r^4),
+ *      dw/dsigma_k = 1/2 * dw/ds_kj = -(12 e / (s r^2)) (24 (s/r)^12 - 6 (s/r)^6),
+ *      dw/deps_k = (de_kj/deps_k) (w_LJ / e_kj),  de_kj/deps_k = eps_j / (2 e_kj),
+ *      w_LJ = -24 e (2 s^12 / r^14 - s^6 / r^8).
+ * Outputs are per atom ([ni][3] and [ni]); any output may be NULL.
+ * ---------------------------------------------------------------------- */
+int oracle_ljc_adjoint(const double *pos, const double *q, const double *sigma, const double *epsl,
+                       int64_t n, double kc, double D, const double *g, const int64_t *ilist,
+                       int64_t ni, double *grad_pos, double *grad_q, double *grad_sigma,
+                       double *grad_eps, int nthreads)
+{
+    if (n < 0 || ni < 0) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t kk = 0; kk < ni; ++kk) {
+        const int64_t k = row(ilist, kk);
+        nsum px = {0, 0}, py = {0, 0}, pz = {0, 0}, gq = {0, 0}, gs = {0, 0}, ge = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == k) continue;
+            const double dx = pos[3 * j] - pos[3 * k];
+            const double dy = pos[3 * j + 1] - pos[3 * k + 1];
+            const double dz = pos[3 * j + 2] - pos[3 * k + 2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double sij = 0.5 * (sigma[k] + sigma[j]);
+            const double eij = sqrt(epsl[k] * epsl[j]);
+            const double sr2 = sij * sij / r2;
+            const double sr6 = sr2 * sr2 * sr2;
+            const double sr12 = sr6 * sr6;
+            const double C = 2.0 * kc * q[k] * q[j] / D;
+            const double wlj = -24.0 * eij / r2 * (2.0 * sr12 - sr6);
+            const double w = -C / (r2 * r2) + wlj;
+            const double wpr = 4.0 * C / (r2 * r2 * r2) + 24.0 * eij / (r2 * r2) * (28.0 * sr12 - 8.0 * sr6);
+            /* position adjoint: M(d) (g_j - g_k) */
+            const double ux = g[3 * j] - g[3 * k];
+            const double uy = g[3 * j + 1] - g[3 * k + 1];
+            const double uz = g[3 * j + 2] - g[3 * k + 2];
+            const double du = dx * ux + dy * uy + dz * uz;
+            nadd(&px, w * ux + wpr * du * dx);
+            nadd(&py, w * uy + wpr * du * dy);
+            nadd(&pz, w * uz + wpr * du * dz);
+            /* parameter adjoints: (dw/dp_k) d . (g_k - g_j) = -(dw/dp_k) du */
+            const double dw_dq = -2.0 * kc * q[j] / (D * r2 * r2);
+            const double dw_ds = -(12.0 * eij / (sij * r2)) * (24.0 * sr12 - 6.0 * sr6);
+            /* w_LJ / e_kj is finite for every e_kj; e_kj = sqrt(eps_k eps_j) does not
+             * depend on eps_k when eps_j = 0, and its derivative is infinite when
+             * eps_k = 0 < eps_j (the square root's derivative at 0). */
+            const double wlj_per_e = -24.0 / r2 * (2.0 * sr12 - sr6);
+            const double de_de = (epsl[j] == 0.0) ? 0.0 : epsl[j] / (2.0 * eij);
+            const double dw_de = de_de * wlj_per_e;
+            nadd(&gq, -dw_dq * du);
+            nadd(&gs, -dw_ds * du);
+            nadd(&ge, -dw_de * du);
+        }
+        if (grad_pos) {
+            grad_pos[3 * kk] = nval(&px);
+            grad_pos[3 * kk + 1] = nval(&py);
+            grad_pos[3 * kk + 2] = nval(&pz);
+        }
+        if (grad_q) grad_q[kk] = nval(&gq);
+        if (grad_sigma) grad_sigma[kk] = nval(&gs);
+        if (grad_eps) grad_eps[kk] = nval(&ge);
+    }
+    return 0;
+}
