@@ -1,0 +1,255 @@
+/*
+ * nbody.h -- C ABI of the MI355X (gfx950) all-pairs N-body library (libnbody.so).
+ *
+ * The library evaluates the O(N^2) pairwise force and potential sums that the
+ * paper (Elsen et al., "N-Body Simulations on GPUs") identifies as the major
+ * cost of stellar and molecular dynamics steps (Section 1; the all-pairs
+ * pseudo-code and its stream form in Section 2), followed by the update step
+ * (Section 1).  Two pair laws are provided:
+ *
+ *   NBODY_LAW_GRAVITY     softened gravity, Eq. 1 (Section 3.3) and Table 1
+ *                         "Gravity (accel)":
+ *                           a_i   =  G sum_{j!=i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2}
+ *                           phi_i = -G sum_{j!=i} m_j / (|r_j - r_i|^2 + eps^2)^{1/2}
+ *   NBODY_LAW_LJC_LINEAR  Lennard-Jones + Coulomb with the linear distance-
+ *                         dependent dielectric eps(r) = D r (Table 1
+ *                         "LJC (linear)"; Section 2, continuum solvent),
+ *                         read as the gradient of
+ *                           u_ij = k q_i q_j / (D r^2) + 4 e_ij [(s_ij/r)^12 - (s_ij/r)^6],
+ *                           s_ij = (s_i + s_j)/2,  e_ij = sqrt(e_i e_j):
+ *                           F_i = sum_{j!=i} [2 k q_i q_j/(D r^4)
+ *                                 + (24 e_ij/r^2)(2 (s_ij/r)^12 - (s_ij/r)^6)] (r_i - r_j)
+ *                           U_i = sum_{j!=i} u_ij     (total energy = 1/2 sum_i U_i)
+ *
+ * Every i interacts with every j != i: all N^2 ordered pairs are evaluated
+ * and no pair is scattered to both partners (Section 2, the remark on
+ * Newton's third law), so results are deterministic run to run.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers (memory of the GPU that is current
+ *    when the call is made) unless marked "host".  All are FP64, row-major:
+ *    pos/vel/acc/force [N][3], params [N][P] with P = 1 (gravity: m_i) or
+ *    P = 3 (LJC: q_i, sigma_i, epsilon_i).
+ *  - The caller owns every array and the workspace `ws` (size from
+ *    nbody_workspace_bytes).  The library never allocates or frees device
+ *    memory and keeps no pointer after the call returns.  `law`, `offsets`
+ *    and `cfg` are host memory read before the call returns.
+ *  - Outputs must not alias inputs (leapfrog_step updates pos/vel/acc in
+ *    place by design).
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *    default stream).  Outputs are valid after the stream is synchronised.
+ *    Calls on different streams with different workspaces may overlap.
+ *  - Inputs are FP64.  FP32 precisions round positions and parameters to FP32
+ *    once (in the pack step) and compute the pair arithmetic in FP32; the
+ *    per-particle sums are carried per j-tile in FP32 and folded into an FP64
+ *    (NBODY_FP32_FP64ACC) or Kahan-compensated FP32 (NBODY_FP32_KAHAN) running
+ *    sum (Section 3.2: double precision only where needed).  Outputs are FP64.
+ *  - Return value: NBODY_OK (0) or a negative error code.  Arguments are
+ *    validated before anything is enqueued, so an error leaves every output
+ *    untouched.  nbody_last_error() gives the message of the last failure on
+ *    the calling thread.  Device faults surface at the next synchronisation.
+ *  - N = 0 is a no-op; N = 1 yields zero force and zero potential.
+ *    Coincident particles with zero softening (gravity) or any two LJC atoms
+ *    at distance 0 give Inf/NaN, as the mathematical definition does.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define NBODY_OK 0
+#define NBODY_EINVAL (-1)      /* bad argument: NULL pointer, N < 0, bad enum, ... */
+#define NBODY_ENOTSUP (-2)     /* law/precision/entry-point combination not provided */
+#define NBODY_EWORKSPACE (-3)  /* workspace NULL or smaller than nbody_workspace_bytes() */
+#define NBODY_EHIP (-4)        /* HIP runtime or launch error (message has the HIP text) */
+
+/* ---- laws and precisions ---- */
+enum nbody_law_kind { NBODY_LAW_GRAVITY = 0, NBODY_LAW_LJC_LINEAR = 1 };
+
+enum nbody_precision {
+    NBODY_FP64 = 0,          /* FP64 pair arithmetic, compensated FP64 sums (reference pass) */
+    NBODY_FP32_KAHAN = 1,    /* FP32 pairs, FP32 tile partials, Kahan-compensated FP32 running sum */
+    NBODY_FP32_FP64ACC = 2,  /* FP32 pairs, FP32 tile partials, FP64 running sum */
+    NBODY_FP32_PLAIN = 3     /* FP32 pairs, one plain FP32 running sum (accuracy ablation only) */
+};
+
+/* Law parameters (host struct).  `softening` is the length eps of Eq. 1 (the
+ * kernel adds eps^2 to r^2, as the Appendix listing adds its constant).
+ * `coulomb_k` is k (332.0637 kcal A / (mol e^2) for Angstrom/kcal/e units) and
+ * `dielectric` is D in eps(r) = D r.  Fields a law does not use are ignored. */
+typedef struct nbody_law {
+    int32_t kind;        /* enum nbody_law_kind */
+    int32_t precision;   /* enum nbody_precision */
+    double G;            /* gravity */
+    double softening;    /* gravity, >= 0 */
+    double coulomb_k;    /* LJC */
+    double dielectric;   /* LJC, > 0 */
+} nbody_law;
+
+/* Entry-point ids for nbody_workspace_bytes / nbody_set_config. */
+enum nbody_api {
+    NBODY_API_FORCES = 0,
+    NBODY_API_BATCHED = 1,
+    NBODY_API_BACKWARD = 2,
+    NBODY_API_LEAPFROG = 3
+};
+
+/* Launch configuration of the all-pairs kernels (see nbody_set_config).
+ *  block      threads per workgroup, a multiple of 64 in [64, 1024];
+ *  i_per_lane i-particles held in registers by each lane: 1, 2, 4 or 8
+ *             (the i-unrolling of Section 3.3, "4x4" kernels);
+ *  j_tile     j-particles per FP32 partial sum before it is folded into the
+ *             compensated running sum: a multiple of 64;
+ *  j_split    number of disjoint j ranges evaluated by separate waves and
+ *             added afterwards in a fixed order (the i-replication of
+ *             Section 3.4), 1..64.  Ignored by the batched entry point. */
+typedef struct nbody_config {
+    int32_t block;
+    int32_t i_per_lane;
+    int32_t j_tile;
+    int32_t j_split;
+} nbody_config;
+
+/* Forces and potential of one system (Section 2 all-pairs loop; Eq. 1 or
+ * Table 1 LJC(linear)).
+ *  pos        [n][3] device, FP64 positions.
+ *  params     [n][P] device, per-particle parameters (P = 1 or 3, see above).
+ *  n          number of particles, >= 0.
+ *  law        host, law and precision.
+ *  out_force  [n][3] device: accelerations a_i (gravity) or forces F_i (LJC).
+ *  out_potential [n] device or NULL: phi_i (gravity, per unit mass) or U_i (LJC).
+ *  ws/ws_bytes  device workspace of at least
+ *             nbody_workspace_bytes(NBODY_API_FORCES, n, 1, law) bytes.
+ *  stream     hipStream_t or NULL.
+ * Errors: NBODY_EINVAL (NULL pos/params/out_force/law with n > 0, n < 0,
+ * negative softening, D <= 0, bad enum), NBODY_EWORKSPACE, NBODY_EHIP. */
+int nbody_forces(const double *pos, const double *params, int64_t n, const nbody_law *law,
+                 double *out_force, double *out_potential, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/* Forces on an active subset of particles (the block time step of
+ * Section 3.4: forces on a subset of i against all j).  `ilist` [ni] device
+ * int64 holds indices in [0, n) (repeats allowed); row k of the outputs is
+ * the force and potential of particle ilist[k].  Outputs are [ni][3] and [ni].
+ * Workspace: nbody_workspace_bytes(NBODY_API_FORCES, max(n, ni), 1, law). */
+int nbody_forces_subset(const double *pos, const double *params, int64_t n, const int64_t *ilist,
+                        int64_t ni, const nbody_law *law, double *out_force,
+                        double *out_potential, void *ws, size_t ws_bytes, void *stream);
+
+/* Forces of many independent systems of uneven size in ONE persistent launch
+ * (small-system motivation of Section 3.4).  System s owns rows
+ * [offsets[s], offsets[s+1]) of pos/params/out_*; particles interact only
+ * within their system.
+ *  offsets    host int64 [n_systems + 1], offsets[0] = 0, non-decreasing.
+ *  n_systems  S >= 0 (empty systems are allowed).
+ * Other arguments as nbody_forces with N = offsets[S].  Workspace:
+ * nbody_workspace_bytes(NBODY_API_BATCHED, offsets[S], S, law). */
+int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
+                         const double *params, const nbody_law *law, double *out_force,
+                         double *out_potential, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of nbody_forces (not in the paper; the derivative of the same
+ * laws).  Given g = dL/d(out_force) [n][3] device:
+ *  grad_pos    [n][3] device or NULL: dL/dr_k.  For gravity this is the
+ *              Hessian-vector product
+ *                dL/dr_k = G sum_{j!=k} K(d)(m_k g_j - m_j g_k),
+ *                K(d)v = v/s^3 - 3 (d.v) d / s^5,  d = r_j - r_k;
+ *              for LJC, with F_i = sum_j w(r) d_ij,
+ *                dL/dr_k = sum_{j!=k} [w u + (w'/r)(d.u) d],  u = g_j - g_k.
+ *  grad_params [n][P] device or NULL: LJC only, per-atom dL/dq, dL/dsigma,
+ *              dL/depsilon (gravity: must be NULL).
+ *  types, n_types, grad_type_params: optional (LJC only).  When types
+ *              (device int32 [n], values in [0, n_types)) is non-NULL,
+ *              grad_type_params [n_types][2] device receives the sums of
+ *              dL/dsigma and dL/depsilon over the atoms of each type (the
+ *              gradient with respect to per-type sigma and epsilon), reduced
+ *              in a fixed order.
+ * Workspace: nbody_workspace_bytes(NBODY_API_BACKWARD, n, 1, law).
+ * Precisions: NBODY_FP64, NBODY_FP32_FP64ACC, NBODY_FP32_KAHAN. */
+int nbody_forces_backward(const double *pos, const double *params, int64_t n,
+                          const nbody_law *law, const double *grad_force, double *grad_pos,
+                          double *grad_params, const int32_t *types, int32_t n_types,
+                          double *grad_type_params, void *ws, size_t ws_bytes, void *stream);
+
+/* `nsteps` kick-drift-kick leapfrog steps in FP64 (the force-evaluation /
+ * update-step cycle of Section 1):
+ *   v += dt/2 a;  x += dt v;  a = accel(x);  v += dt/2 a.
+ *  pos, vel    [n][3] device, updated in place.
+ *  acc         [n][3] device: a(t) on entry, a(t + nsteps dt) on exit.
+ *  inv_mass    [n] device or NULL: acceleration = force * inv_mass (LJC);
+ *              NULL means the law's output is already an acceleration
+ *              (gravity) or unit masses.
+ *  out_potential [n] device or NULL: potential at the final positions.
+ * Forces use `law->precision`; the update is always FP64.  nsteps >= 0.
+ * Workspace: nbody_workspace_bytes(NBODY_API_LEAPFROG, n, 1, law). */
+int leapfrog_step(double *pos, double *vel, double *acc, const double *params,
+                  const double *inv_mass, int64_t n, const nbody_law *law, double dt,
+                  int32_t nsteps, double *out_potential, void *ws, size_t ws_bytes,
+                  void *stream);
+
+/* Workspace size in bytes needed by entry point `api` for `n_total`
+ * particles in `n_systems` systems (1 for the single-system entry points).
+ * Returns 0 when the arguments are invalid. */
+size_t nbody_workspace_bytes(int32_t api, int64_t n_total, int64_t n_systems,
+                             const nbody_law *law);
+
+/* Message of the last non-OK return on the calling thread ("" if none). */
+const char *nbody_last_error(void);
+
+/* ---- tuning (the unroll sweep of Section 3.3 and the replication sweep of
+ * Section 3.4, done by measurement) ---- */
+
+/* Force the launch configuration used by entry point `api` (cfg != NULL), or
+ * return to the automatic choice (cfg == NULL).  Host struct.  Returns
+ * NBODY_EINVAL for a configuration outside the documented ranges. */
+int nbody_set_config(int32_t api, const nbody_config *cfg);
+
+/* The configuration entry point `api` would use for n particles in
+ * n_systems systems under `law`, written to *out (host). */
+int nbody_get_config(int32_t api, int64_t n, int64_t n_systems, const nbody_law *law,
+                     nbody_config *out);
+
+/* Time candidate configurations on the given problem with HIP events on
+ * `stream` and remember the fastest for this (device, law, precision, entry
+ * point, size class).  Arguments as nbody_forces (api = NBODY_API_FORCES) or
+ * nbody_forces_batched (api = NBODY_API_BATCHED, offsets/n_systems used);
+ * the outputs are overwritten with the result of the winning configuration.
+ * Synchronises the stream.  `out_best` (host, may be NULL) receives the
+ * winner and `out_ms` (host, may be NULL) its time in milliseconds. */
+int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const double *pos,
+                   const double *params, int64_t n, const nbody_law *law, double *out_force,
+                   double *out_potential, void *ws, size_t ws_bytes, void *stream,
+                   nbody_config *out_best, double *out_ms);
+
+/* Save / load the tuning cache as a small JSON file (host path). */
+int nbody_tune_save(const char *path);
+int nbody_tune_load(const char *path);
+
+/* ---- measurement hooks ---- */
+
+/* When enabled, every launch of the all-pairs kernel is bracketed by HIP
+ * events on the launch stream and its duration is accumulated. */
+int nbody_timing_enable(int32_t on);
+/* Total milliseconds and number of all-pairs kernel launches recorded since
+ * the last reset; synchronises the recorded events.  reset != 0 clears. */
+int nbody_timing_read(double *total_ms, int64_t *launches, int32_t reset);
+
+/* Algorithmic flops per pair interaction counted from the kernel's own
+ * instruction sequence (multiply-add = 2, rsqrt/rcp = 1, the Appendix
+ * convention), for the given law, potential on/off and entry point. */
+int32_t nbody_flops_per_pair(int32_t api, int32_t law_kind, int32_t with_potential);
+
+/* Library version string. */
+const char *nbody_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

@@ -1,0 +1,403 @@
+// Adjoint (backward) all-pairs kernels.  Not in the paper: the derivative of
+// the same pair laws, evaluated with the same tiled, SGPR-streamed j loop as
+// the forward kernels.
+//
+// Gravity (Eq. 1), g_i = dL/da_i, d = r_j - r_k, s^2 = |d|^2 + eps^2:
+//   dL/dr_k = G sum_{j!=k} [ w / s^3 - 3 (d.w) d / s^5 ],   w = m_k g_j - m_j g_k
+// LJC(linear) with F_i = sum_j w(r) d_ij,
+//   w = -x (C x + 24 e s6 (2 s6 - 1)),   x = 1/r^2, C = qs_i qs_j, e = se_i se_j,
+//   s6 = (sigma_ij^2 x)^3,
+//   w'/r = x^2 (4 C x + 24 e s6 (28 s6 - 8)),
+//   u = g_j - g_k, du = d.u:
+//   dL/dr_k     = sum_j [ w u + (w'/r) du d ]
+//   dL/dq_k     = sqrt(2k/D) sum_j qs_j x^2 du
+//   dL/dsigma_k = 72 sum_j e s6 (4 s6 - 1) x du / sigma_kj
+//   dL/deps_k   = (12 / se_k) sum_j se_j s6 (2 s6 - 1) x du
+#include <type_traits>
+
+#include "device.h"
+#include "kernels.h"
+
+namespace nbk {
+
+template <typename T> struct alignas(4 * sizeof(T)) GravAdjRec { T x, y, z, m, gx, gy, gz, p0; };
+template <typename T> struct alignas(4 * sizeof(T)) LjcAdjRec {
+    T x, y, z, qs, sh, se, gx, gy, gz, p0, p1, p2;
+};
+
+// ------------------------------------------------------------------- pack ----
+template <typename T>
+__device__ __forceinline__ void adj_put(GravAdjRec<T> *rec, int64_t i, const double *x,
+                                        const double *par, const double *g, double)
+{
+    GravAdjRec<T> r;
+    r.x = (T)x[0];
+    r.y = (T)x[1];
+    r.z = (T)x[2];
+    r.m = (T)par[0];
+    r.gx = (T)g[0];
+    r.gy = (T)g[1];
+    r.gz = (T)g[2];
+    r.p0 = T(0);
+    rec[i] = r;
+}
+template <typename T>
+__device__ __forceinline__ void adj_put(LjcAdjRec<T> *rec, int64_t i, const double *x,
+                                        const double *par, const double *g, double qscale)
+{
+    LjcAdjRec<T> r;
+    r.x = (T)x[0];
+    r.y = (T)x[1];
+    r.z = (T)x[2];
+    r.qs = (T)(par[0] * qscale);
+    r.sh = (T)(0.5 * par[1]);
+    r.se = (T)__builtin_sqrt(par[2]);
+    r.gx = (T)g[0];
+    r.gy = (T)g[1];
+    r.gz = (T)g[2];
+    r.p0 = r.p1 = r.p2 = T(0);
+    rec[i] = r;
+}
+template <typename T> __device__ __forceinline__ void adj_pad(GravAdjRec<T> *rec, int64_t i)
+{
+    GravAdjRec<T> r;
+    r.x = r.y = r.z = (T)kPadCoord;
+    r.m = r.gx = r.gy = r.gz = r.p0 = T(0);
+    rec[i] = r;
+}
+template <typename T> __device__ __forceinline__ void adj_pad(LjcAdjRec<T> *rec, int64_t i)
+{
+    LjcAdjRec<T> r;
+    r.x = r.y = r.z = (T)kPadCoord;
+    r.qs = r.sh = r.se = r.gx = r.gy = r.gz = r.p0 = r.p1 = r.p2 = T(0);
+    rec[i] = r;
+}
+
+template <typename R, int P>
+__global__ __launch_bounds__(256) void k_pack_adj(AdjPackLaunch a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.npad) return;
+    R *rec = (R *)a.rec;
+    if (i < a.n) adj_put(rec, i, a.pos + 3 * i, a.params + (int64_t)P * i, a.g + 3 * i, a.qscale);
+    else adj_pad(rec, i);
+}
+
+hipError_t launch_pack_adjoint(const AdjPackLaunch &p, hipStream_t s)
+{
+    if (p.npad <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((p.npad + 255) / 256)), block(256);
+    const bool f32 = p.prec != P_FP64;
+    if (p.law == GRAVITY) {
+        if (f32) hipLaunchKernelGGL((k_pack_adj<GravAdjRec<float>, 1>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((k_pack_adj<GravAdjRec<double>, 1>), grid, block, 0, s, p);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_pack_adj<LjcAdjRec<float>, 3>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((k_pack_adj<LjcAdjRec<double>, 3>), grid, block, 0, s, p);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- pair math ----
+// Gravity adjoint, per pair: 3 sub, 3 fma, 1 rsq, 4 mul, 3 mul + 3 fma (w),
+// 1 mul + 2 fma (d.w), 1 mul, 6 fma: 41 flops (multiply-add = 2).
+template <bool MASK, typename T>
+__device__ __forceinline__ void grav_adj_pair(const GravAdjRec<T> &i, const GravAdjRec<T> &j, T eps2,
+                                              bool self, T (&o)[8])
+{
+    const T dx = j.x - i.x, dy = j.y - i.y, dz = j.z - i.z;
+    T r2 = fma_(dx, dx, eps2);
+    r2 = fma_(dy, dy, r2);
+    r2 = fma_(dz, dz, r2);
+    if (MASK) r2 = self ? T(1) : r2;
+    T ri = rsqrt_(r2);
+    if (MASK) ri = self ? T(0) : ri;
+    const T ri2 = ri * ri;
+    const T ri3 = ri2 * ri;
+    const T r5x3 = ri3 * (ri2 * T(3));
+    const T wx = fma_(-j.m, i.gx, i.m * j.gx);
+    const T wy = fma_(-j.m, i.gy, i.m * j.gy);
+    const T wz = fma_(-j.m, i.gz, i.m * j.gz);
+    T dw = dx * wx;
+    dw = fma_(dy, wy, dw);
+    dw = fma_(dz, wz, dw);
+    const T e = dw * r5x3;
+    o[0] = fma_(ri3, wx, o[0]);
+    o[1] = fma_(ri3, wy, o[1]);
+    o[2] = fma_(ri3, wz, o[2]);
+    o[0] = fma_(-e, dx, o[0]);
+    o[1] = fma_(-e, dy, o[1]);
+    o[2] = fma_(-e, dz, o[2]);
+}
+
+// LJC adjoint, per pair (position and parameter adjoints together).
+template <bool MASK, typename T>
+__device__ __forceinline__ void ljc_adj_pair(const LjcAdjRec<T> &i, const LjcAdjRec<T> &j, T,
+                                             bool self, T (&o)[8])
+{
+    const T dx = j.x - i.x, dy = j.y - i.y, dz = j.z - i.z;
+    T r2 = dx * dx;
+    r2 = fma_(dy, dy, r2);
+    r2 = fma_(dz, dz, r2);
+    T qq = i.qs * j.qs;
+    T e = i.se * j.se;
+    if (MASK) {
+        r2 = self ? T(1) : r2;
+        qq = self ? T(0) : qq;
+        e = self ? T(0) : e;
+    }
+    const T x = rcp_(r2);
+    const T sg = i.sh + j.sh;
+    const T s2 = (sg * sg) * x;
+    const T s6 = (s2 * s2) * s2;
+    const T lj = e * s6;
+    const T t = fma_(s6, T(2), T(-1));
+    const T cx = qq * x;
+    const T W = fma_(lj * t, T(24), cx) * x;                       // w = -W
+    const T x2 = x * x;
+    const T wpr = fma_(lj * fma_(s6, T(28), T(-8)), T(24), cx * T(4)) * x2;
+    const T ux = j.gx - i.gx, uy = j.gy - i.gy, uz = j.gz - i.gz;
+    T du = dx * ux;
+    du = fma_(dy, uy, du);
+    du = fma_(dz, uz, du);
+    const T tt = wpr * du;
+    o[0] = fma_(-W, ux, o[0]);
+    o[1] = fma_(-W, uy, o[1]);
+    o[2] = fma_(-W, uz, o[2]);
+    o[0] = fma_(tt, dx, o[0]);
+    o[1] = fma_(tt, dy, o[1]);
+    o[2] = fma_(tt, dz, o[2]);
+    const T xdu = x * du;
+    o[3] = fma_(j.qs, x * xdu, o[3]);
+    o[4] = fma_(lj * fma_(s6, T(4), T(-1)), xdu * rcp_(sg), o[4]);
+    o[5] = fma_(j.se, s6 * t * xdu, o[5]);
+}
+
+template <bool MASK, typename T>
+__device__ __forceinline__ void adj_pair(const GravAdjRec<T> &i, const GravAdjRec<T> &j, T eps2,
+                                         bool self, T (&o)[8])
+{
+    grav_adj_pair<MASK>(i, j, eps2, self, o);
+}
+template <bool MASK, typename T>
+__device__ __forceinline__ void adj_pair(const LjcAdjRec<T> &i, const LjcAdjRec<T> &j, T eps2,
+                                         bool self, T (&o)[8])
+{
+    ljc_adj_pair<MASK>(i, j, eps2, self, o);
+}
+
+template <bool MASK, int NC, int I, typename R, typename T>
+__device__ __forceinline__ void adj_tile(const R *__restrict__ rec, int64_t t0, int64_t t1,
+                                         const R (&is)[I], const int64_t (&pid)[I], T eps2,
+                                         T (&p)[I][8])
+{
+    constexpr int U = 4;
+    for (int64_t j = t0; j < t1; j += U) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const R r = rec[j + u];
+#pragma unroll
+            for (int k = 0; k < I; ++k) adj_pair<MASK>(is[k], r, eps2, MASK && (pid[k] == j + u), p[k]);
+        }
+    }
+}
+
+template <int LAW> struct AdjNC { static constexpr int value = LAW == GRAVITY ? 3 : 6; };
+
+__device__ __forceinline__ void adj_finish(const AdjLaunch &a, int law, int64_t k, const double *v)
+{
+    if (law == GRAVITY) {
+        if (a.grad_pos) {
+            a.grad_pos[3 * k] = a.G * v[0];
+            a.grad_pos[3 * k + 1] = a.G * v[1];
+            a.grad_pos[3 * k + 2] = a.G * v[2];
+        }
+        return;
+    }
+    if (a.grad_pos) {
+        a.grad_pos[3 * k] = v[0];
+        a.grad_pos[3 * k + 1] = v[1];
+        a.grad_pos[3 * k + 2] = v[2];
+    }
+    if (a.grad_params) {
+        const double se_k = __builtin_sqrt(a.params[3 * k + 2]);
+        a.grad_params[3 * k] = a.qscale * v[3];
+        a.grad_params[3 * k + 1] = 72.0 * v[4];
+        a.grad_params[3 * k + 2] = (12.0 / se_k) * v[5];
+    }
+}
+
+template <int LAW, int PREC, int I>
+__global__ __launch_bounds__(256) void k_adjoint(
+    const typename std::conditional<LAW == GRAVITY, GravAdjRec<typename RealOf<PREC>::type>,
+                                    LjcAdjRec<typename RealOf<PREC>::type>>::type *__restrict__ rec,
+    AdjLaunch a)
+{
+    using T = typename RealOf<PREC>::type;
+    using R = typename std::conditional<LAW == GRAVITY, GravAdjRec<T>, LjcAdjRec<T>>::type;
+    constexpr int NC = AdjNC<LAW>::value;
+    const int lane = lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t rbase = wave * (int64_t)(kWave * I);
+    if (rbase >= a.n) return;
+    const int64_t jb = (int64_t)blockIdx.y * a.split_len;
+    const int64_t je = (jb + a.split_len < a.npad) ? jb + a.split_len : a.npad;
+
+    R is[I];
+    int64_t pid[I];
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        int64_t r = rbase + lane + (int64_t)kWave * k;
+        pid[k] = r < a.n ? r : a.n - 1;
+        is[k] = rec[pid[k]];
+    }
+    RunSum<PREC> acc[I][NC];
+    T p[I][8];
+    for (int64_t t0 = jb; t0 < je; t0 += a.j_tile) {
+        const int64_t t1 = (t0 + a.j_tile < je) ? t0 + a.j_tile : je;
+        bool near = false;
+#pragma unroll
+        for (int k = 0; k < I; ++k) near |= (pid[k] >= t0) & (pid[k] < t1);
+#pragma unroll
+        for (int k = 0; k < I; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[k][c].begin(p[k][c]);
+        if (wave_any(near)) adj_tile<true, NC, I>(rec, t0, t1, is, pid, (T)a.eps2, p);
+        else adj_tile<false, NC, I>(rec, t0, t1, is, pid, (T)a.eps2, p);
+#pragma unroll
+        for (int k = 0; k < I; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[k][c].fold(p[k][c]);
+    }
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        const int64_t r = rbase + lane + (int64_t)kWave * k;
+        if (r >= a.n) continue;
+        double v[8];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c] = acc[k][c].value();
+        if (a.j_split > 1) {
+            double *o = a.partial + ((int64_t)blockIdx.y * a.n + r) * 8;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) o[c] = v[c];
+        } else {
+            adj_finish(a, LAW, r, v);
+        }
+    }
+}
+
+template <int LAW, int PREC, int I>
+static void launch_adj_one(const AdjLaunch &a, dim3 grid, hipStream_t s)
+{
+    using T = typename RealOf<PREC>::type;
+    using R = typename std::conditional<LAW == GRAVITY, GravAdjRec<T>, LjcAdjRec<T>>::type;
+    hipLaunchKernelGGL((k_adjoint<LAW, PREC, I>), grid, dim3(a.block), 0, s, (const R *)a.rec, a);
+}
+
+template <int LAW, int PREC>
+static bool adj_ipl(const AdjLaunch &a, dim3 grid, hipStream_t s)
+{
+    switch (a.ipl) {
+    case 1: launch_adj_one<LAW, PREC, 1>(a, grid, s); return true;
+    case 2: launch_adj_one<LAW, PREC, 2>(a, grid, s); return true;
+    case 4: launch_adj_one<LAW, PREC, 4>(a, grid, s); return true;
+    default: return false;
+    }
+}
+
+template <int LAW>
+static bool adj_prec(const AdjLaunch &a, dim3 grid, hipStream_t s)
+{
+    switch (a.prec) {
+    case P_FP64: return adj_ipl<LAW, P_FP64>(a, grid, s);
+    case P_KAHAN: return adj_ipl<LAW, P_KAHAN>(a, grid, s);
+    case P_FP64ACC: return adj_ipl<LAW, P_FP64ACC>(a, grid, s);
+    default: return false;
+    }
+}
+
+hipError_t launch_adjoint(const AdjLaunch &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    const int64_t waves = (a.n + (int64_t)kWave * a.ipl - 1) / ((int64_t)kWave * a.ipl);
+    const int64_t wpb = a.block / kWave;
+    const dim3 grid((unsigned)((waves + wpb - 1) / wpb), (unsigned)a.j_split);
+    const bool ok = a.law == GRAVITY ? adj_prec<GRAVITY>(a, grid, s) : adj_prec<LJC>(a, grid, s);
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_adj_reduce(AdjLaunch a)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n) return;
+    const int nc = a.law == GRAVITY ? 3 : 6;
+    NSum v[6];
+    for (int s = 0; s < a.j_split; ++s) {
+        const double *o = a.partial + ((int64_t)s * a.n + r) * 8;
+        for (int c = 0; c < nc; ++c) v[c].add(o[c]);
+    }
+    double out[8];
+    for (int c = 0; c < nc; ++c) out[c] = v[c].value();
+    adj_finish(a, a.law, r, out);
+}
+
+hipError_t launch_adjoint_reduce(const AdjLaunch &a, hipStream_t s)
+{
+    if (a.n <= 0 || a.j_split <= 1) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_reduce, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ per-type reduction ----
+// One workgroup per type: each lane accumulates a strided slice of the atoms
+// in a fixed order (Neumaier), then the 64 lanes of each wave are combined by
+// a fixed xor-shuffle butterfly and the waves by LDS in wave order, so the
+// result is bitwise reproducible.
+__global__ __launch_bounds__(256) void k_type_reduce(const double *__restrict__ gp,
+                                                     const int32_t *__restrict__ types, int64_t n,
+                                                     double *__restrict__ out)
+{
+    const int t = blockIdx.x;
+    NSum ss, se;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        if (types[i] == t) {
+            ss.add(gp[3 * i + 1]);
+            se.add(gp[3 * i + 2]);
+        }
+    }
+    double a = ss.value(), b = se.value();
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        a += __shfl_xor(a, m, 64);
+        b += __shfl_xor(b, m, 64);
+    }
+    __shared__ double part[2][16];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        part[0][w] = a;
+        part[1][w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        NSum x, y;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+            x.add(part[0][k]);
+            y.add(part[1][k]);
+        }
+        out[2 * t] = x.value();
+        out[2 * t + 1] = y.value();
+    }
+}
+
+hipError_t launch_type_reduce(const double *grad_params, const int32_t *types, int64_t n,
+                              int32_t n_types, double *out, hipStream_t s)
+{
+    if (n_types <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_type_reduce, dim3((unsigned)n_types), dim3(256), 0, s, grad_params, types,
+                       n, out);
+    return hipGetLastError();
+}
+
+}  // namespace nbk

@@ -1,0 +1,927 @@
+// Host runtime behind the C ABI of include/nbody.h: argument validation,
+// workspace carving, launch-configuration choice (heuristic, forced or
+// measured), kernel sequencing on the caller's stream, error reporting and
+// the measurement hooks.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/nbody.h"
+#include "kernels.h"
+
+namespace {
+
+using namespace nbk;
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    return fail(NBODY_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr int64_t kMaxPartialRows = int64_t(1) << 22;   // split partial buffer budget (rows)
+constexpr int kMaxSplit = 64;
+constexpr int kTargetWaves = 4096;                      // 4 resident waves per SIMD on 256 CUs
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+bool is_f32(int prec) { return prec != NBODY_FP64; }
+
+size_t rec_bytes(int law, int prec)
+{
+    const size_t t = is_f32(prec) ? 4 : 8;
+    return law == NBODY_LAW_GRAVITY ? 4 * t : 8 * t;
+}
+
+size_t adj_rec_bytes(int law, int prec)
+{
+    const size_t t = is_f32(prec) ? 4 : 8;
+    return law == NBODY_LAW_GRAVITY ? 8 * t : 12 * t;
+}
+
+int params_per_particle(int law) { return law == NBODY_LAW_GRAVITY ? 1 : 3; }
+
+int max_split(int64_t npad)
+{
+    if (npad <= 0) return 1;
+    const int64_t by_ws = std::max<int64_t>(1, kMaxPartialRows / npad);
+    const int64_t by_len = std::max<int64_t>(1, npad / 64);
+    return (int)std::min<int64_t>(kMaxSplit, std::min(by_ws, by_len));
+}
+
+int validate_law(const nbody_law *law, bool backward)
+{
+    if (!law) return fail(NBODY_EINVAL, "law is NULL");
+    if (law->kind != NBODY_LAW_GRAVITY && law->kind != NBODY_LAW_LJC_LINEAR)
+        return fail(NBODY_EINVAL, "unknown law kind %d", law->kind);
+    if (law->precision < NBODY_FP64 || law->precision > NBODY_FP32_PLAIN)
+        return fail(NBODY_EINVAL, "unknown precision %d", law->precision);
+    if (law->kind == NBODY_LAW_GRAVITY) {
+        if (!(law->softening >= 0.0) || !std::isfinite(law->softening))
+            return fail(NBODY_EINVAL, "softening must be finite and >= 0 (got %g)", law->softening);
+        if (!std::isfinite(law->G)) return fail(NBODY_EINVAL, "G must be finite");
+    } else {
+        if (!(law->dielectric > 0.0) || !std::isfinite(law->dielectric))
+            return fail(NBODY_EINVAL, "dielectric D must be finite and > 0 (got %g)", law->dielectric);
+        if (!std::isfinite(law->coulomb_k) || law->coulomb_k < 0.0)
+            return fail(NBODY_EINVAL, "coulomb_k must be finite and >= 0");
+    }
+    if (backward && law->precision == NBODY_FP32_PLAIN)
+        return fail(NBODY_ENOTSUP, "the adjoint is provided for FP64, FP32_FP64ACC and FP32_KAHAN");
+    return NBODY_OK;
+}
+
+// ------------------------------------------------------------ configuration
+struct Cfg {
+    int block = 256, ipl = 1, j_tile = 256, j_split = 1;
+};
+
+std::mutex g_mu;
+bool g_override_set[4] = {false, false, false, false};
+Cfg g_override[4];
+
+using TuneKey = std::tuple<int, int, int, int, int, int>;   // api, law, prec, pot, nbucket, sbucket
+std::map<TuneKey, std::pair<Cfg, double>> g_tuned;
+
+int size_bucket(int64_t n)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < n && b < 62) ++b;
+    return b;
+}
+
+int max_ipl(int api, int prec)
+{
+    if (api == NBODY_API_BATCHED || api == NBODY_API_BACKWARD) return 4;
+    return is_f32(prec) ? 8 : 4;
+}
+
+bool ipl_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
+
+Cfg sanitize(Cfg c, int api, int prec, int64_t npad)
+{
+    c.ipl = std::min(c.ipl, max_ipl(api, prec));
+    c.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
+    if (api == NBODY_API_BATCHED) c.j_split = 1;
+    return c;
+}
+
+Cfg heuristic(int api, int prec, int64_t n, int64_t S)
+{
+    Cfg c;
+    const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    if (api == NBODY_API_BATCHED) {
+        c.ipl = 1;
+        c.block = 256;
+        c.j_tile = 256;
+        c.j_split = 1;
+        (void)S;
+        return c;
+    }
+    if (is_f32(prec)) {
+        c.ipl = n >= (1 << 18) ? 4 : (n >= (1 << 16) ? 2 : 1);
+        c.j_tile = 256;
+    } else {
+        c.ipl = n >= (1 << 18) ? 2 : 1;
+        c.j_tile = 1024;
+    }
+    if (api == NBODY_API_BACKWARD) c.ipl = std::min(c.ipl, 2);
+    const int64_t waves = (n + 64 * c.ipl - 1) / (64 * c.ipl);
+    int split = 1;
+    while (split < kMaxSplit && waves * split < kTargetWaves) split *= 2;
+    c.j_split = split;
+    return sanitize(c, api, prec, npad);
+}
+
+Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot)
+{
+    const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_override_set[api]) return sanitize(g_override[api], api, law->precision, npad);
+    auto it = g_tuned.find(TuneKey(api, law->kind, law->precision, pot ? 1 : 0, size_bucket(n),
+                                   size_bucket(S)));
+    if (it != g_tuned.end()) return sanitize(it->second.first, api, law->precision, npad);
+    return heuristic(api, law->precision, n, S);
+}
+
+// ------------------------------------------------------------ measurement
+bool g_timing = false;
+struct TimedLaunch {
+    hipEvent_t a, b;
+};
+std::vector<TimedLaunch> g_timed;
+double g_timed_ms = 0.0;
+int64_t g_timed_count = 0;
+
+struct Timer {
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on;
+    explicit Timer(hipStream_t st) : s(st)
+    {
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            on = g_timing;
+        }
+        if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            hipEventRecord(a, s);
+        else
+            on = false;
+    }
+    void stop()
+    {
+        if (!on) return;
+        hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_timed.push_back({a, b});
+        on = false;
+    }
+};
+
+// ------------------------------------------------------------ workspace
+struct FwdWs {
+    size_t rec_off, part_off, scratch_off, total;
+};
+
+FwdWs fwd_layout(int api, const nbody_law *law, int64_t n)
+{
+    FwdWs w{};
+    const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    size_t off = 0;
+    w.rec_off = off;
+    off = align256(off + (size_t)npad * rec_bytes(law->kind, law->precision));
+    w.part_off = off;
+    off = align256(off + (size_t)max_split(npad) * (size_t)npad * 4 * sizeof(double));
+    w.scratch_off = off;
+    if (api == NBODY_API_LEAPFROG) off = align256(off + (size_t)npad * 3 * sizeof(double));
+    w.total = off;
+    return w;
+}
+
+struct AdjWs {
+    size_t rec_off, part_off, total;
+};
+
+AdjWs adj_layout(const nbody_law *law, int64_t n)
+{
+    AdjWs w{};
+    const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    size_t off = 0;
+    w.rec_off = off;
+    off = align256(off + (size_t)npad * adj_rec_bytes(law->kind, law->precision));
+    w.part_off = off;
+    off = align256(off + (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double));
+    w.total = off;
+    return w;
+}
+
+struct BatWs {
+    size_t rec_off, unit_off, off_off, poff_off, ticket_off, total;
+};
+
+BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
+{
+    BatWs w{};
+    const int64_t npad_max = n_total + 64 * std::max<int64_t>(S, 1);
+    const int64_t units_max = n_total / 64 + std::max<int64_t>(S, 1) + 1;
+    size_t off = 0;
+    w.rec_off = off;
+    off = align256(off + (size_t)npad_max * rec_bytes(law->kind, law->precision));
+    w.unit_off = off;
+    off = align256(off + (size_t)units_max * 2 * sizeof(int32_t));
+    w.off_off = off;
+    off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
+    w.poff_off = off;
+    off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
+    w.ticket_off = off;
+    off = align256(off + 256);
+    w.total = off;
+    return w;
+}
+
+double qscale_of(const nbody_law *law)
+{
+    return law->kind == NBODY_LAW_LJC_LINEAR ? std::sqrt(2.0 * law->coulomb_k / law->dielectric) : 0.0;
+}
+
+Epilogue make_epi(const nbody_law *law, double *out_force, double *out_pot)
+{
+    Epilogue e{};
+    if (law->kind == NBODY_LAW_GRAVITY) {
+        e.fscale = law->G;
+        e.pscale = -law->G;
+    } else {
+        e.fscale = 1.0;     // the pair function accumulates -W d = W (r_i - r_j) already
+        e.pscale = 0.5;     // sum_j 2 u_ij -> U_i
+    }
+    e.out_force = out_force;
+    e.out_pot = out_pot;
+    e.kick = 0;
+    return e;
+}
+
+// pack + all-pairs (+ split reduction) for one system already validated
+int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const double *params,
+                int64_t n, const int64_t *rows, int64_t nrows, const Epilogue &epi, bool pot,
+                void *ws, const FwdWs &lay, hipStream_t s, PackLaunch *pk_in)
+{
+    const int64_t npad = round_up(n, 64);
+    char *base = (char *)ws;
+    PackLaunch pk{};
+    if (pk_in) pk = *pk_in;
+    pk.law = law->kind;
+    pk.prec = law->precision;
+    pk.n = n;
+    pk.npad = npad;
+    if (!pk_in) pk.pos = const_cast<double *>(pos);
+    pk.params = params;
+    pk.qscale = qscale_of(law);
+    pk.rec = base + lay.rec_off;
+    hipError_t e = launch_pack(pk, s);
+    if (e != hipSuccess) return hip_fail(e, "pack");
+
+    FwdLaunch f{};
+    f.law = law->kind;
+    f.prec = law->precision;
+    f.ipl = c.ipl;
+    f.pot = pot ? 1 : 0;
+    f.block = c.block;
+    f.npad = npad;
+    f.nrows = nrows;
+    f.rows = rows;
+    f.j_split = c.j_split;
+    f.split_len = round_up((npad + c.j_split - 1) / c.j_split, 64);
+    f.j_tile = c.j_tile;
+    f.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    f.rec = base + lay.rec_off;
+    f.partial = (double *)(base + lay.part_off);
+    f.epi = epi;
+    Timer t(s);
+    e = launch_forces(f, s);
+    t.stop();
+    if (e != hipSuccess) return hip_fail(e, "all-pairs kernel");
+    e = launch_reduce_split(f, s);
+    if (e != hipSuccess) return hip_fail(e, "split reduction");
+    return NBODY_OK;
+}
+
+bool cfg_valid(const nbody_config *c)
+{
+    return c && c->block >= 64 && c->block <= 256 && c->block % 64 == 0 && ipl_ok(c->i_per_lane) &&
+           c->j_tile >= 64 && c->j_tile % 64 == 0 && c->j_tile <= (1 << 20) && c->j_split >= 1 &&
+           c->j_split <= kMaxSplit;
+}
+
+Cfg from_abi(const nbody_config *c)
+{
+    Cfg r;
+    r.block = c->block;
+    r.ipl = c->i_per_lane;
+    r.j_tile = c->j_tile;
+    r.j_split = c->j_split;
+    return r;
+}
+
+void to_abi(const Cfg &c, nbody_config *o)
+{
+    o->block = c.block;
+    o->i_per_lane = c.ipl;
+    o->j_tile = c.j_tile;
+    o->j_split = c.j_split;
+}
+
+// ------------------------------------------------------------ batched plan
+struct BatchPlan {
+    std::vector<int64_t> poff;
+    std::vector<int32_t> units;
+    int64_t npad_total = 0;
+};
+
+BatchPlan plan_batched(const int64_t *offsets, int64_t S, int ipl)
+{
+    BatchPlan p;
+    p.poff.assign((size_t)S + 1, 0);
+    struct U {
+        int64_t cost;
+        int32_t s, rb;
+    };
+    std::vector<U> us;
+    const int64_t rows = 64 * ipl;
+    for (int64_t s = 0; s < S; ++s) {
+        const int64_t ns = offsets[s + 1] - offsets[s];
+        const int64_t pn = round_up(ns, 64);
+        p.poff[s + 1] = p.poff[s] + pn;
+        for (int64_t rb = 0; rb * rows < ns; ++rb) {
+            const int64_t r = std::min(rows, ns - rb * rows);
+            us.push_back({r * pn, (int32_t)s, (int32_t)rb});
+        }
+    }
+    p.npad_total = p.poff[S];
+    // longest processing time first; ties keep system order (stable)
+    std::stable_sort(us.begin(), us.end(), [](const U &a, const U &b) { return a.cost > b.cost; });
+    p.units.resize(us.size() * 2);
+    for (size_t k = 0; k < us.size(); ++k) {
+        p.units[2 * k] = us[k].s;
+        p.units[2 * k + 1] = us[k].rb;
+    }
+    return p;
+}
+
+int g_num_cus = 0;
+
+int device_cus()
+{
+    if (g_num_cus > 0) return g_num_cus;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        g_num_cus = prop.multiProcessorCount;
+    if (g_num_cus <= 0) g_num_cus = 256;
+    return g_num_cus;
+}
+
+int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int64_t S,
+                const double *pos, const double *params, double *out_force, double *out_pot,
+                void *ws, const BatWs &lay, hipStream_t s)
+{
+    const BatchPlan plan = plan_batched(offsets, S, c.ipl);
+    if (plan.units.empty()) return NBODY_OK;
+    char *base = (char *)ws;
+    int32_t *d_units = (int32_t *)(base + lay.unit_off);
+    int64_t *d_off = (int64_t *)(base + lay.off_off);
+    int64_t *d_poff = (int64_t *)(base + lay.poff_off);
+    hipError_t e;
+    // Pageable sources: the runtime stages them before returning.
+    e = hipMemcpyAsync(d_units, plan.units.data(), plan.units.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_off, offsets, (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_poff, plan.poff.data(), (size_t)(S + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batched tables");
+
+    BatchPackLaunch pk{};
+    pk.law = law->kind;
+    pk.prec = law->precision;
+    pk.n_systems = S;
+    pk.npad_total = plan.npad_total;
+    pk.off = d_off;
+    pk.poff = d_poff;
+    pk.pos = pos;
+    pk.params = params;
+    pk.qscale = qscale_of(law);
+    pk.rec = base + lay.rec_off;
+    e = launch_pack_batched(pk, s);
+    if (e != hipSuccess) return hip_fail(e, "batched pack");
+
+    BatchLaunch b{};
+    b.law = law->kind;
+    b.prec = law->precision;
+    b.ipl = c.ipl;
+    b.pot = out_pot != nullptr;
+    b.block = c.block;
+    const int per_cu = std::max(1, batched_max_blocks_per_cu(b.law, b.prec, b.ipl, b.pot, b.block));
+    const int64_t n_units = (int64_t)plan.units.size() / 2;
+    const int64_t waves_needed = n_units;
+    const int64_t blocks_needed = (waves_needed + c.block / 64 - 1) / (c.block / 64);
+    b.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)device_cus() * per_cu, blocks_needed));
+    b.n_units = n_units;
+    b.units = d_units;
+    b.off = d_off;
+    b.poff = d_poff;
+    b.n_systems = S;
+    b.n_total = offsets[S];
+    b.npad_total = plan.npad_total;
+    b.j_tile = c.j_tile;
+    b.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    b.rec = base + lay.rec_off;
+    b.ticket = (int *)(base + lay.ticket_off);
+    b.epi = make_epi(law, out_force, out_pot);
+    Timer t(s);
+    e = launch_batched(b, s);
+    t.stop();
+    if (e != hipSuccess) return hip_fail(e, "batched kernel");
+    return NBODY_OK;
+}
+
+int check_ws(void *ws, size_t have, size_t need)
+{
+    if (!ws && need) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+    if (have < need) return fail(NBODY_EWORKSPACE, "workspace too small: %zu < %zu bytes", have, need);
+    return NBODY_OK;
+}
+
+int validate_offsets(const int64_t *offsets, int64_t S)
+{
+    if (S < 0) return fail(NBODY_EINVAL, "n_systems < 0");
+    if (!offsets) return fail(NBODY_EINVAL, "offsets is NULL");
+    if (offsets[0] != 0) return fail(NBODY_EINVAL, "offsets[0] must be 0");
+    for (int64_t s = 0; s < S; ++s) {
+        if (offsets[s + 1] < offsets[s]) return fail(NBODY_EINVAL, "offsets decrease at %lld", (long long)s);
+        if (offsets[s + 1] - offsets[s] > (int64_t(1) << 30))
+            return fail(NBODY_EINVAL, "system %lld is larger than 2^30 particles", (long long)s);
+    }
+    if (S > (int64_t(1) << 30)) return fail(NBODY_EINVAL, "too many systems");
+    return NBODY_OK;
+}
+
+int forces_impl(const double *pos, const double *params, int64_t n, const int64_t *rows,
+                int64_t nrows, const nbody_law *law, double *out_force, double *out_potential,
+                void *ws, size_t ws_bytes, void *stream, const Cfg *forced)
+{
+    int rc = validate_law(law, false);
+    if (rc) return rc;
+    if (n < 0 || nrows < 0) return fail(NBODY_EINVAL, "n < 0");
+    if (n > (int64_t(1) << 40)) return fail(NBODY_EINVAL, "n too large");
+    if (nrows > 0 && n == 0) return fail(NBODY_EINVAL, "rows requested from an empty system");
+    if (nrows == 0) return NBODY_OK;
+    if (!pos || !params || !out_force) return fail(NBODY_EINVAL, "pos, params and out_force must be non-NULL");
+    if (rows == nullptr && nrows != n) return fail(NBODY_EINVAL, "row count mismatch");
+    const FwdWs lay = fwd_layout(NBODY_API_FORCES, law, std::max(n, nrows));
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    const bool pot = out_potential != nullptr;
+    const Cfg c = forced ? *forced : choose(NBODY_API_FORCES, law, nrows, 1, pot);
+    return run_forward(law, sanitize(c, NBODY_API_FORCES, law->precision, round_up(std::max(n, nrows), 64)), pos,
+                       params, n, rows, nrows, make_epi(law, out_force, out_potential), pot, ws, lay,
+                       (hipStream_t)stream, nullptr);
+}
+
+int batched_impl(const int64_t *offsets, int64_t S, const double *pos, const double *params,
+                 const nbody_law *law, double *out_force, double *out_potential, void *ws,
+                 size_t ws_bytes, void *stream, const Cfg *forced)
+{
+    int rc = validate_law(law, false);
+    if (rc) return rc;
+    rc = validate_offsets(offsets, S);
+    if (rc) return rc;
+    const int64_t n = offsets[S];
+    if (n == 0) return NBODY_OK;
+    if (!pos || !params || !out_force) return fail(NBODY_EINVAL, "pos, params and out_force must be non-NULL");
+    const BatWs lay = bat_layout(law, n, S);
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    const Cfg c = forced ? *forced : choose(NBODY_API_BATCHED, law, n, S, out_potential != nullptr);
+    return run_batched(law, sanitize(c, NBODY_API_BATCHED, law->precision, 64), offsets, S, pos,
+                       params, out_force, out_potential, ws, lay, (hipStream_t)stream);
+}
+
+// candidate list for the measured search
+std::vector<Cfg> candidates(int api, int prec, int64_t n)
+{
+    std::vector<Cfg> out;
+    const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    const int ipls[] = {1, 2, 4, 8};
+    const int blocks[] = {64, 256};
+    if (api == NBODY_API_BATCHED) {
+        for (int ipl : {1, 2, 4})
+            for (int b : {64, 128, 256})
+                for (int jt : {64, 256}) {
+                    Cfg c;
+                    c.ipl = ipl;
+                    c.block = b;
+                    c.j_tile = jt;
+                    c.j_split = 1;
+                    out.push_back(c);
+                }
+        return out;
+    }
+    for (int ipl : ipls) {
+        if (ipl > max_ipl(api, prec)) continue;
+        const int64_t waves = (n + 64 * ipl - 1) / (64 * ipl);
+        for (int b : blocks)
+            for (int split = 1; split <= max_split(npad); split *= 2) {
+                const int64_t w = waves * split;
+                if (w > 8 * kTargetWaves && split > 1) break;
+                if (w < kTargetWaves / 8 && split < max_split(npad)) continue;
+                Cfg c;
+                c.ipl = ipl;
+                c.block = b;
+                c.j_tile = is_f32(prec) ? 256 : 1024;
+                c.j_split = split;
+                out.push_back(c);
+            }
+    }
+    return out;
+}
+
+}  // namespace
+
+// ======================================================================== ABI
+
+extern "C" {
+
+const char *nbody_last_error(void) { return g_err.c_str(); }
+
+const char *nbody_version(void) { return "nbody-mi355x 0.1 (gfx950)"; }
+
+size_t nbody_workspace_bytes(int32_t api, int64_t n_total, int64_t n_systems, const nbody_law *law)
+{
+    if (!law || n_total < 0 || n_systems < 0) return 0;
+    if (law->kind != NBODY_LAW_GRAVITY && law->kind != NBODY_LAW_LJC_LINEAR) return 0;
+    if (law->precision < NBODY_FP64 || law->precision > NBODY_FP32_PLAIN) return 0;
+    switch (api) {
+    case NBODY_API_FORCES: return fwd_layout(NBODY_API_FORCES, law, n_total).total;
+    case NBODY_API_LEAPFROG: return fwd_layout(NBODY_API_LEAPFROG, law, n_total).total;
+    case NBODY_API_BACKWARD: return adj_layout(law, n_total).total;
+    case NBODY_API_BATCHED: return bat_layout(law, n_total, n_systems).total;
+    default: return 0;
+    }
+}
+
+int nbody_forces(const double *pos, const double *params, int64_t n, const nbody_law *law,
+                 double *out_force, double *out_potential, void *ws, size_t ws_bytes, void *stream)
+{
+    return forces_impl(pos, params, n, nullptr, n, law, out_force, out_potential, ws, ws_bytes,
+                       stream, nullptr);
+}
+
+int nbody_forces_subset(const double *pos, const double *params, int64_t n, const int64_t *ilist,
+                        int64_t ni, const nbody_law *law, double *out_force, double *out_potential,
+                        void *ws, size_t ws_bytes, void *stream)
+{
+    if (ni > 0 && !ilist) return fail(NBODY_EINVAL, "ilist is NULL");
+    return forces_impl(pos, params, n, ilist, ni, law, out_force, out_potential, ws, ws_bytes,
+                       stream, nullptr);
+}
+
+int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
+                         const double *params, const nbody_law *law, double *out_force,
+                         double *out_potential, void *ws, size_t ws_bytes, void *stream)
+{
+    return batched_impl(offsets, n_systems, pos, params, law, out_force, out_potential, ws, ws_bytes,
+                        stream, nullptr);
+}
+
+int nbody_forces_backward(const double *pos, const double *params, int64_t n, const nbody_law *law,
+                          const double *grad_force, double *grad_pos, double *grad_params,
+                          const int32_t *types, int32_t n_types, double *grad_type_params,
+                          void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = validate_law(law, true);
+    if (rc) return rc;
+    if (n < 0) return fail(NBODY_EINVAL, "n < 0");
+    if (law->kind == NBODY_LAW_GRAVITY && (grad_params || types))
+        return fail(NBODY_EINVAL, "gravity has no parameter adjoint here: grad_params/types must be NULL");
+    if (types && (n_types <= 0 || !grad_type_params))
+        return fail(NBODY_EINVAL, "types given without n_types > 0 and grad_type_params");
+    if (types && !grad_params)
+        return fail(NBODY_EINVAL, "the per-type reduction needs grad_params");
+    if (n == 0) return NBODY_OK;
+    if (!pos || !params || !grad_force) return fail(NBODY_EINVAL, "pos, params and grad_force must be non-NULL");
+    if (!grad_pos && !grad_params) return NBODY_OK;
+    const AdjWs lay = adj_layout(law, n);
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const Cfg c = choose(NBODY_API_BACKWARD, law, n, 1, false);
+    const int64_t npad = round_up(n, 64);
+    char *base = (char *)ws;
+
+    AdjPackLaunch pk{};
+    pk.law = law->kind;
+    pk.prec = law->precision;
+    pk.n = n;
+    pk.npad = npad;
+    pk.pos = pos;
+    pk.params = params;
+    pk.g = grad_force;
+    pk.qscale = qscale_of(law);
+    pk.rec = base + lay.rec_off;
+    hipError_t e = launch_pack_adjoint(pk, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint pack");
+
+    AdjLaunch a{};
+    a.law = law->kind;
+    a.prec = law->precision;
+    a.ipl = std::min(c.ipl, 4);
+    a.block = c.block;
+    a.n = n;
+    a.npad = npad;
+    a.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
+    a.split_len = round_up((npad + a.j_split - 1) / a.j_split, 64);
+    a.j_tile = c.j_tile;
+    a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    a.G = law->G;
+    a.qscale = qscale_of(law);
+    a.rec = base + lay.rec_off;
+    a.partial = (double *)(base + lay.part_off);
+    a.grad_pos = grad_pos;
+    a.grad_params = grad_params;
+    a.params = params;
+    Timer t(s);
+    e = launch_adjoint(a, s);
+    t.stop();
+    if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
+    e = launch_adjoint_reduce(a, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint split reduction");
+    if (types) {
+        e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params, s);
+        if (e != hipSuccess) return hip_fail(e, "per-type reduction");
+    }
+    return NBODY_OK;
+}
+
+int leapfrog_step(double *pos, double *vel, double *acc, const double *params,
+                  const double *inv_mass, int64_t n, const nbody_law *law, double dt,
+                  int32_t nsteps, double *out_potential, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = validate_law(law, false);
+    if (rc) return rc;
+    if (n < 0) return fail(NBODY_EINVAL, "n < 0");
+    if (nsteps < 0) return fail(NBODY_EINVAL, "nsteps < 0");
+    if (!std::isfinite(dt)) return fail(NBODY_EINVAL, "dt must be finite");
+    if (n == 0) return NBODY_OK;
+    if (!pos || !vel || !acc || !params) return fail(NBODY_EINVAL, "pos, vel, acc and params must be non-NULL");
+    if (nsteps == 0 && !out_potential) return NBODY_OK;
+    const FwdWs lay = fwd_layout(NBODY_API_LEAPFROG, law, n);
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    if (nsteps == 0) {
+        const Cfg c = choose(NBODY_API_LEAPFROG, law, n, 1, true);
+        return run_forward(law, c, pos, params, n, nullptr, n,
+                           make_epi(law, (double *)(base + lay.scratch_off), out_potential), true, ws,
+                           lay, s, nullptr);
+    }
+    for (int32_t k = 0; k < nsteps; ++k) {
+        const bool last = (k == nsteps - 1);
+        const bool pot = last && out_potential;
+        const Cfg c = choose(NBODY_API_LEAPFROG, law, n, 1, pot);
+        PackLaunch pk{};
+        pk.pos = pos;
+        pk.kick_drift = 1;
+        pk.vel = vel;
+        pk.acc = acc;
+        pk.half_dt = 0.5 * dt;
+        pk.dt = dt;
+        Epilogue epi = make_epi(law, acc, pot ? out_potential : nullptr);
+        epi.kick = 1;
+        epi.half_dt = 0.5 * dt;
+        epi.vel = vel;
+        epi.inv_mass = inv_mass;
+        rc = run_forward(law, c, pos, params, n, nullptr, n, epi, pot, ws, lay, s, &pk);
+        if (rc) return rc;
+    }
+    return NBODY_OK;
+}
+
+int nbody_set_config(int32_t api, const nbody_config *cfg)
+{
+    if (api < 0 || api > 3) return fail(NBODY_EINVAL, "unknown api %d", api);
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!cfg) {
+        g_override_set[api] = false;
+        return NBODY_OK;
+    }
+    if (!cfg_valid(cfg)) return fail(NBODY_EINVAL, "configuration outside the documented ranges");
+    g_override[api] = from_abi(cfg);
+    g_override_set[api] = true;
+    return NBODY_OK;
+}
+
+int nbody_get_config(int32_t api, int64_t n, int64_t n_systems, const nbody_law *law, nbody_config *out)
+{
+    if (api < 0 || api > 3) return fail(NBODY_EINVAL, "unknown api %d", api);
+    int rc = validate_law(law, false);
+    if (rc) return rc;
+    if (!out || n < 0) return fail(NBODY_EINVAL, "bad arguments");
+    to_abi(choose(api, law, n, std::max<int64_t>(n_systems, 1), true), out);
+    return NBODY_OK;
+}
+
+int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const double *pos,
+                   const double *params, int64_t n, const nbody_law *law, double *out_force,
+                   double *out_potential, void *ws, size_t ws_bytes, void *stream,
+                   nbody_config *out_best, double *out_ms)
+{
+    if (api != NBODY_API_FORCES && api != NBODY_API_BATCHED)
+        return fail(NBODY_ENOTSUP, "autotune covers the forces and batched entry points");
+    int rc = validate_law(law, false);
+    if (rc) return rc;
+    int64_t ntot = n, S = 1;
+    if (api == NBODY_API_BATCHED) {
+        rc = validate_offsets(offsets, n_systems);
+        if (rc) return rc;
+        ntot = offsets[n_systems];
+        S = n_systems;
+    }
+    if (ntot <= 0) return fail(NBODY_EINVAL, "nothing to tune");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(NBODY_EHIP, "event creation failed");
+    Cfg best;
+    double best_ms = 1e300;
+    const bool saved_timing = g_timing;
+    g_timing = false;
+    for (const Cfg &c : candidates(api, law->precision, ntot)) {
+        double ms_min = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            hipEventRecord(a, s);
+            rc = api == NBODY_API_FORCES
+                     ? forces_impl(pos, params, n, nullptr, n, law, out_force, out_potential, ws,
+                                   ws_bytes, stream, &c)
+                     : batched_impl(offsets, n_systems, pos, params, law, out_force, out_potential,
+                                    ws, ws_bytes, stream, &c);
+            hipEventRecord(b, s);
+            if (rc) break;
+            if (hipEventSynchronize(b) != hipSuccess) {
+                rc = fail(NBODY_EHIP, "autotune synchronisation failed");
+                break;
+            }
+            float ms = 0;
+            hipEventElapsedTime(&ms, a, b);
+            ms_min = std::min(ms_min, (double)ms);
+        }
+        if (rc) break;
+        if (ms_min < best_ms) {
+            best_ms = ms_min;
+            best = c;
+        }
+    }
+    g_timing = saved_timing;
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tuned[TuneKey(api, law->kind, law->precision, out_potential ? 1 : 0, size_bucket(ntot),
+                        size_bucket(S))] = {best, best_ms};
+    }
+    // leave the winner's result in the outputs
+    rc = api == NBODY_API_FORCES
+             ? forces_impl(pos, params, n, nullptr, n, law, out_force, out_potential, ws, ws_bytes,
+                           stream, &best)
+             : batched_impl(offsets, n_systems, pos, params, law, out_force, out_potential, ws,
+                            ws_bytes, stream, &best);
+    if (rc) return rc;
+    if (out_best) to_abi(best, out_best);
+    if (out_ms) *out_ms = best_ms;
+    return NBODY_OK;
+}
+
+int nbody_tune_save(const char *path)
+{
+    if (!path) return fail(NBODY_EINVAL, "path is NULL");
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(NBODY_EINVAL, "cannot open %s", path);
+    std::lock_guard<std::mutex> lk(g_mu);
+    fprintf(f, "{\"device_cus\": %d, \"entries\": [\n", device_cus());
+    size_t k = 0;
+    for (const auto &kv : g_tuned) {
+        const TuneKey &t = kv.first;
+        const Cfg &c = kv.second.first;
+        fprintf(f,
+                "  {\"api\": %d, \"law\": %d, \"precision\": %d, \"potential\": %d, \"n_bucket\": %d, "
+                "\"s_bucket\": %d, \"block\": %d, \"i_per_lane\": %d, \"j_tile\": %d, \"j_split\": %d, "
+                "\"ms\": %.6f}%s\n",
+                std::get<0>(t), std::get<1>(t), std::get<2>(t), std::get<3>(t), std::get<4>(t),
+                std::get<5>(t), c.block, c.ipl, c.j_tile, c.j_split, kv.second.second,
+                (++k < g_tuned.size()) ? "," : "");
+    }
+    fprintf(f, "]}\n");
+    fclose(f);
+    return NBODY_OK;
+}
+
+int nbody_tune_load(const char *path)
+{
+    if (!path) return fail(NBODY_EINVAL, "path is NULL");
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(NBODY_EINVAL, "cannot open %s", path);
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+    fclose(f);
+    int loaded = 0;
+    size_t pos = 0;
+    while ((pos = txt.find("{\"api\"", pos)) != std::string::npos) {
+        int api, law, prec, pot, nb, sb, block, ipl, jt, js;
+        double ms;
+        if (sscanf(txt.c_str() + pos,
+                   "{\"api\": %d, \"law\": %d, \"precision\": %d, \"potential\": %d, \"n_bucket\": %d, "
+                   "\"s_bucket\": %d, \"block\": %d, \"i_per_lane\": %d, \"j_tile\": %d, \"j_split\": %d, "
+                   "\"ms\": %lf}",
+                   &api, &law, &prec, &pot, &nb, &sb, &block, &ipl, &jt, &js, &ms) == 11) {
+            nbody_config cc{block, ipl, jt, js};
+            if (cfg_valid(&cc) && api >= 0 && api <= 3) {
+                std::lock_guard<std::mutex> lk(g_mu);
+                g_tuned[TuneKey(api, law, prec, pot, nb, sb)] = {from_abi(&cc), ms};
+                ++loaded;
+            }
+        }
+        ++pos;
+    }
+    return loaded > 0 ? NBODY_OK : fail(NBODY_EINVAL, "no entries in %s", path);
+}
+
+int nbody_timing_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_timing = on != 0;
+    return NBODY_OK;
+}
+
+int nbody_timing_read(double *total_ms, int64_t *launches, int32_t reset)
+{
+    std::vector<TimedLaunch> pending;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        pending.swap(g_timed);
+    }
+    int rc = NBODY_OK;
+    for (auto &t : pending) {
+        float ms = 0;
+        if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
+            rc = fail(NBODY_EHIP, "timing events failed");
+        hipEventDestroy(t.a);
+        hipEventDestroy(t.b);
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_timed_ms += ms;
+        ++g_timed_count;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (total_ms) *total_ms = g_timed_ms;
+    if (launches) *launches = g_timed_count;
+    if (reset) {
+        g_timed_ms = 0.0;
+        g_timed_count = 0;
+    }
+    return rc;
+}
+
+int32_t nbody_flops_per_pair(int32_t api, int32_t law_kind, int32_t with_potential)
+{
+    if (api == NBODY_API_BACKWARD) return law_kind == NBODY_LAW_GRAVITY ? 41 : 68;
+    if (law_kind == NBODY_LAW_GRAVITY) return with_potential ? 20 : 19;
+    if (law_kind == NBODY_LAW_LJC_LINEAR) return with_potential ? 35 : 30;
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,359 @@
+// All-pairs force / potential kernels for one system (gfx950).
+//
+// Structure (Section 2's stream formulation: one output per i, the j loop
+// inside; Section 3.3's i-unrolling; Section 3.4's replication of the i
+// stream over disjoint j ranges):
+//   pack          FP64 inputs -> padded records (FP32 or FP64), optionally
+//                 after the kick-drift half of a leapfrog step;
+//   k_forces      each wave owns 64*I output rows (I per lane, in VGPRs) and
+//                 streams the records of its j range through SGPRs, tile by
+//                 tile; FP32 tile partials are folded into FP64 / Kahan sums;
+//   reduce_split  when the j range is split over several waves, the split
+//                 partials are added in a fixed order (deterministic).
+#include "device.h"
+#include "kernels.h"
+
+namespace nbk {
+
+// ------------------------------------------------------------------ pack ----
+template <typename T>
+__device__ __forceinline__ void store_rec(GravRec<T> *rec, int64_t i, double x, double y, double z,
+                                          const double *par, double)
+{
+    GravRec<T> r;
+    r.x = (T)x;
+    r.y = (T)y;
+    r.z = (T)z;
+    r.m = (T)par[0];
+    rec[i] = r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_rec(LjcRec<T> *rec, int64_t i, double x, double y, double z,
+                                          const double *par, double qscale)
+{
+    LjcRec<T> r;
+    r.x = (T)x;
+    r.y = (T)y;
+    r.z = (T)z;
+    r.qs = (T)(par[0] * qscale);
+    r.sh = (T)(0.5 * par[1]);
+    r.se = (T)__builtin_sqrt(par[2]);
+    r.p0 = T(0);
+    r.p1 = T(0);
+    rec[i] = r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_pad(GravRec<T> *rec, int64_t i)
+{
+    GravRec<T> r;
+    r.x = r.y = r.z = (T)kPadCoord;
+    r.m = T(0);
+    rec[i] = r;
+}
+
+template <typename T>
+__device__ __forceinline__ void store_pad(LjcRec<T> *rec, int64_t i)
+{
+    LjcRec<T> r;
+    r.x = r.y = r.z = (T)kPadCoord;
+    r.qs = r.sh = r.se = r.p0 = r.p1 = T(0);
+    rec[i] = r;
+}
+
+template <typename R, int P>
+__global__ __launch_bounds__(256) void k_pack(PackLaunch a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.npad) return;
+    R *rec = (R *)a.rec;
+    if (i >= a.n) {
+        store_pad(rec, i);
+        return;
+    }
+    double x = a.pos[3 * i], y = a.pos[3 * i + 1], z = a.pos[3 * i + 2];
+    if (a.kick_drift) {
+        const double vx = a.vel[3 * i] + a.half_dt * a.acc[3 * i];
+        const double vy = a.vel[3 * i + 1] + a.half_dt * a.acc[3 * i + 1];
+        const double vz = a.vel[3 * i + 2] + a.half_dt * a.acc[3 * i + 2];
+        x += a.dt * vx;
+        y += a.dt * vy;
+        z += a.dt * vz;
+        a.vel[3 * i] = vx;
+        a.vel[3 * i + 1] = vy;
+        a.vel[3 * i + 2] = vz;
+        a.pos[3 * i] = x;
+        a.pos[3 * i + 1] = y;
+        a.pos[3 * i + 2] = z;
+    }
+    store_rec(rec, i, x, y, z, a.params + (int64_t)P * i, a.qscale);
+}
+
+hipError_t launch_pack(const PackLaunch &p, hipStream_t s)
+{
+    if (p.npad <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((p.npad + 255) / 256)), block(256);
+    const bool f32 = p.prec != P_FP64;
+    if (p.law == GRAVITY) {
+        if (f32) hipLaunchKernelGGL((k_pack<GravRec<float>, 1>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((k_pack<GravRec<double>, 1>), grid, block, 0, s, p);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_pack<LjcRec<float>, 3>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((k_pack<LjcRec<double>, 3>), grid, block, 0, s, p);
+    }
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- epilogue ----
+__device__ __forceinline__ void finish_row(const Epilogue &e, int64_t r, double v0, double v1,
+                                           double v2, double v3, bool pot)
+{
+    double f0 = e.fscale * v0, f1 = e.fscale * v1, f2 = e.fscale * v2;
+    if (e.kick) {
+        const double w = e.inv_mass ? e.inv_mass[r] : 1.0;
+        f0 *= w;
+        f1 *= w;
+        f2 *= w;
+        e.vel[3 * r] += e.half_dt * f0;
+        e.vel[3 * r + 1] += e.half_dt * f1;
+        e.vel[3 * r + 2] += e.half_dt * f2;
+    }
+    e.out_force[3 * r] = f0;
+    e.out_force[3 * r + 1] = f1;
+    e.out_force[3 * r + 2] = f2;
+    if (pot && e.out_pot) e.out_pot[r] = e.pscale * v3;
+}
+
+// ------------------------------------------------------- per-law i / j I/O ----
+template <typename T>
+__device__ __forceinline__ void load_i(const GravRec<T> *rec, int64_t p, GravI<T> &s)
+{
+    const GravRec<T> r = rec[p];
+    s.x = r.x;
+    s.y = r.y;
+    s.z = r.z;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_i(const LjcRec<T> *rec, int64_t p, LjcI<T> &s)
+{
+    const LjcRec<T> r = rec[p];
+    s.x = r.x;
+    s.y = r.y;
+    s.z = r.z;
+    s.qs = r.qs;
+    s.sh = r.sh;
+    s.se = r.se;
+}
+
+template <typename T> struct IStateOf;
+template <typename T> struct IStateOf<GravRec<T>> { using type = GravI<T>; };
+template <typename T> struct IStateOf<LjcRec<T>> { using type = LjcI<T>; };
+
+template <bool MASK, bool POT, typename T>
+__device__ __forceinline__ void pair(const GravI<T> &i, const GravRec<T> &j, T eps2, bool self,
+                                     T (&p)[4])
+{
+    grav_pair<MASK, POT>(i, j.x, j.y, j.z, j.m, eps2, self, p);
+}
+
+template <bool MASK, bool POT, typename T>
+__device__ __forceinline__ void pair(const LjcI<T> &i, const LjcRec<T> &j, T, bool self, T (&p)[4])
+{
+    ljc_pair<MASK, POT>(i, j.x, j.y, j.z, j.qs, j.sh, j.se, self, p);
+}
+
+// The j loop over one tile [t0, t1) (a multiple of 8 records).  `rec` is a
+// restrict-qualified read-only pointer and j is wave-uniform, so each record
+// load is a scalar load shared by the 64 lanes.
+template <bool MASK, bool POT, int I, typename R, typename IS, typename T>
+__device__ __forceinline__ void tile_loop(const R *__restrict__ rec, int64_t t0, int64_t t1,
+                                          const IS (&is)[I], const int64_t (&pid)[I], T eps2,
+                                          T (&p)[I][4])
+{
+    constexpr int U = 8;
+    R cur[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cur[u] = rec[t0 + u];
+    for (int64_t j = t0; j < t1; j += U) {
+        // prefetch the next group (the last group re-reads itself: always in bounds)
+        const int64_t jn = (j + U < t1) ? j + U : j;
+        R nxt[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) nxt[u] = rec[jn + u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int k = 0; k < I; ++k)
+                pair<MASK, POT>(is[k], cur[u], eps2, MASK && (pid[k] == j + u), p[k]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+    }
+}
+
+// ------------------------------------------------------------- all pairs ----
+template <int LAW, int PREC, int I, bool POT>
+__global__ __launch_bounds__(256) void k_forces(
+    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec, int64_t npad,
+    int64_t nrows, const int64_t *__restrict__ rows, int64_t split_len, int j_tile,
+    typename RealOf<PREC>::type eps2, double *__restrict__ partial, Epilogue epi)
+{
+    using T = typename RealOf<PREC>::type;
+    using R = typename RecOf<T, LAW>::type;
+    using IS = typename IStateOf<R>::type;
+    constexpr int NC = POT ? 4 : 3;
+
+    const int lane = lane_id();
+    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
+                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t rbase = wave * (int64_t)(kWave * I);
+    if (rbase >= nrows) return;
+    const int64_t jb = (int64_t)blockIdx.y * split_len;
+    const int64_t je = (jb + split_len < npad) ? jb + split_len : npad;
+
+    IS is[I];
+    int64_t pid[I];
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        int64_t r = rbase + lane + (int64_t)kWave * k;
+        r = r < nrows ? r : nrows - 1;
+        int64_t q = rows ? rows[r] : r;
+        q = q < 0 ? 0 : (q < npad ? q : npad - 1);        // never read outside the records
+        pid[k] = q;
+        load_i(rec, pid[k], is[k]);
+    }
+
+    RunSum<PREC> acc[I][NC];
+    T p[I][4];
+#pragma unroll
+    for (int k = 0; k < I; ++k) p[k][3] = T(0);
+
+    for (int64_t t0 = jb; t0 < je; t0 += j_tile) {
+        const int64_t t1 = (t0 + j_tile < je) ? t0 + j_tile : je;
+        bool near = false;
+#pragma unroll
+        for (int k = 0; k < I; ++k) near |= (pid[k] >= t0) & (pid[k] < t1);
+#pragma unroll
+        for (int k = 0; k < I; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[k][c].begin(p[k][c]);
+        if (wave_any(near))
+            tile_loop<true, POT, I>(rec, t0, t1, is, pid, (T)eps2, p);
+        else
+            tile_loop<false, POT, I>(rec, t0, t1, is, pid, (T)eps2, p);
+#pragma unroll
+        for (int k = 0; k < I; ++k)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[k][c].fold(p[k][c]);
+    }
+
+#pragma unroll
+    for (int k = 0; k < I; ++k) {
+        const int64_t r = rbase + lane + (int64_t)kWave * k;
+        if (r >= nrows) continue;
+        const double v0 = acc[k][0].value(), v1 = acc[k][1].value(), v2 = acc[k][2].value();
+        const double v3 = POT ? acc[k][NC - 1].value() : 0.0;
+        if (partial) {
+            double *o = partial + ((int64_t)blockIdx.y * nrows + r) * 4;
+            o[0] = v0;
+            o[1] = v1;
+            o[2] = v2;
+            o[3] = v3;
+        } else {
+            finish_row(epi, r, v0, v1, v2, v3, POT);
+        }
+    }
+}
+
+template <int LAW, int PREC, int I, bool POT>
+static void launch_one(const FwdLaunch &f, dim3 grid, hipStream_t s)
+{
+    using T = typename RealOf<PREC>::type;
+    using R = typename RecOf<T, LAW>::type;
+    hipLaunchKernelGGL((k_forces<LAW, PREC, I, POT>), grid, dim3(f.block), 0, s, (const R *)f.rec,
+                       f.npad, f.nrows, f.rows, f.split_len, f.j_tile, (T)f.eps2,
+                       f.j_split > 1 ? f.partial : nullptr, f.epi);
+}
+
+template <int LAW, int PREC, bool POT>
+static bool dispatch_ipl(const FwdLaunch &f, dim3 grid, hipStream_t s)
+{
+    switch (f.ipl) {
+    case 1: launch_one<LAW, PREC, 1, POT>(f, grid, s); return true;
+    case 2: launch_one<LAW, PREC, 2, POT>(f, grid, s); return true;
+    case 4: launch_one<LAW, PREC, 4, POT>(f, grid, s); return true;
+    case 8: launch_one<LAW, PREC, 8, POT>(f, grid, s); return true;
+    default: return false;
+    }
+}
+
+template <int LAW, bool POT>
+static bool dispatch_prec(const FwdLaunch &f, dim3 grid, hipStream_t s)
+{
+    switch (f.prec) {
+    case P_FP64: return dispatch_ipl<LAW, P_FP64, POT>(f, grid, s);
+    case P_KAHAN: return dispatch_ipl<LAW, P_KAHAN, POT>(f, grid, s);
+    case P_FP64ACC: return dispatch_ipl<LAW, P_FP64ACC, POT>(f, grid, s);
+    case P_PLAIN: return dispatch_ipl<LAW, P_PLAIN, POT>(f, grid, s);
+    default: return false;
+    }
+}
+
+hipError_t launch_forces(const FwdLaunch &f, hipStream_t s)
+{
+    if (f.nrows <= 0) return hipSuccess;
+    const int64_t waves = (f.nrows + (int64_t)kWave * f.ipl - 1) / ((int64_t)kWave * f.ipl);
+    const int64_t wpb = f.block / kWave;
+    const dim3 grid((unsigned)((waves + wpb - 1) / wpb), (unsigned)f.j_split);
+    bool ok;
+    if (f.law == GRAVITY)
+        ok = f.pot ? dispatch_prec<GRAVITY, true>(f, grid, s) : dispatch_prec<GRAVITY, false>(f, grid, s);
+    else
+        ok = f.pot ? dispatch_prec<LJC, true>(f, grid, s) : dispatch_prec<LJC, false>(f, grid, s);
+    if (!ok) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- fixed-order split sum ----
+__global__ __launch_bounds__(256) void k_reduce_split(const double *__restrict__ partial,
+                                                      int64_t nrows, int j_split, int pot,
+                                                      Epilogue epi)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    NSum v[4];
+    for (int s = 0; s < j_split; ++s) {
+        const double *o = partial + ((int64_t)s * nrows + r) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c].add(o[c]);
+    }
+    finish_row(epi, r, v[0].value(), v[1].value(), v[2].value(), v[3].value(), pot != 0);
+}
+
+hipError_t launch_reduce_split(const FwdLaunch &f, hipStream_t s)
+{
+    if (f.nrows <= 0 || f.j_split <= 1) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((f.nrows + 255) / 256)), dim3(256), 0, s,
+                       (const double *)f.partial, f.nrows, f.j_split, f.pot, f.epi);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- zero fill ----
+__global__ __launch_bounds__(256) void k_fill_zero(uint32_t *p, int64_t words)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
+{
+    const int64_t words = (int64_t)(bytes / 4);
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s,
+                       (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+}  // namespace nbk

@@ -1,0 +1,119 @@
+// Internal interface between the host runtime (api.cpp) and the HIP kernels.
+// Not part of the public ABI (include/nbody.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace nbk {
+
+// What the all-pairs kernels do with the four finished sums of a row.
+struct Epilogue {
+    double fscale;              // out_force = fscale * sum_vec   (G for gravity, 1 for LJC)
+    double pscale;              // out_pot   = pscale * sum_pot   (-G for gravity, 1/2 for LJC)
+    double *out_force;          // [rows][3]
+    double *out_pot;            // [rows] or null
+    // leapfrog kick (kick != 0): acc = force * inv_mass; acc -> acc_out; vel += half_dt * acc
+    int kick;
+    double half_dt;
+    double *vel;                // [rows][3]
+    const double *inv_mass;     // [rows] or null
+};
+
+struct FwdLaunch {
+    int law, prec, ipl, pot;     // template selectors
+    int block;                   // threads per workgroup
+    int64_t npad;                // padded record count (multiple of 64)
+    int64_t nrows;               // output rows
+    const int64_t *rows;         // row -> particle index, or null (identity)
+    int64_t split_len;           // j range per split (multiple of 64)
+    int j_split;
+    int j_tile;
+    double eps2;                 // gravity softening squared
+    const void *rec;             // packed records
+    double *partial;             // [j_split][nrows][4] when j_split > 1
+    Epilogue epi;
+};
+
+// Pack FP64 inputs into padded records (FP32 or FP64) for one system.
+// When kick_drift != 0 the positions are first advanced in place:
+//   vel += half_dt * acc;  pos += dt * vel.
+struct PackLaunch {
+    int law, prec;
+    int64_t n, npad;
+    double *pos;                 // [n][3] (written only when kick_drift)
+    const double *params;        // [n][P]
+    double qscale;               // sqrt(2k/D) for LJC
+    void *rec;
+    int kick_drift;
+    double *vel;
+    const double *acc;
+    double half_dt, dt;
+};
+
+hipError_t launch_pack(const PackLaunch &p, hipStream_t s);
+hipError_t launch_forces(const FwdLaunch &f, hipStream_t s);
+hipError_t launch_reduce_split(const FwdLaunch &f, hipStream_t s);
+
+// ---- batched (one persistent launch over (system, row-block) work units) ----
+struct BatchLaunch {
+    int law, prec, ipl, pot;
+    int block;
+    int grid;                    // persistent workgroups
+    int64_t n_units;
+    const int32_t *units;        // [n_units][2] = (system, row block), cost-descending
+    const int64_t *off;          // [S+1] caller row offsets
+    const int64_t *poff;         // [S+1] padded record offsets
+    int64_t n_systems;
+    int64_t n_total, npad_total;
+    int j_tile;
+    double eps2;
+    const void *rec;
+    int *ticket;                 // zeroed by launch_batched before the kernel
+    Epilogue epi;
+};
+struct BatchPackLaunch {
+    int law, prec;
+    int64_t n_systems, npad_total;
+    const int64_t *off, *poff;
+    const double *pos, *params;
+    double qscale;
+    void *rec;
+};
+hipError_t launch_pack_batched(const BatchPackLaunch &p, hipStream_t s);
+hipError_t launch_batched(const BatchLaunch &b, hipStream_t s);
+int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int block);
+
+// ---- adjoint ----
+struct AdjLaunch {
+    int law, prec, ipl;
+    int block;
+    int64_t n, npad;
+    int64_t split_len;
+    int j_split, j_tile;
+    double eps2;
+    double G;                    // gravity
+    double qscale;               // LJC sqrt(2k/D)
+    const void *rec;
+    double *partial;             // [j_split][n][8] when j_split > 1
+    double *grad_pos;            // [n][3] or null
+    double *grad_params;         // [n][3] or null (LJC)
+    const double *params;        // caller params (for the per-atom scale factors)
+};
+struct AdjPackLaunch {
+    int law, prec;
+    int64_t n, npad;
+    const double *pos, *params, *g;
+    double qscale;
+    void *rec;
+};
+hipError_t launch_pack_adjoint(const AdjPackLaunch &p, hipStream_t s);
+hipError_t launch_adjoint(const AdjLaunch &a, hipStream_t s);
+hipError_t launch_adjoint_reduce(const AdjLaunch &a, hipStream_t s);
+hipError_t launch_type_reduce(const double *grad_params, const int32_t *types, int64_t n,
+                              int32_t n_types, double *out, hipStream_t s);
+
+// zero-fill with a kernel (no memset nodes, so the calls stay capturable)
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+
+}  // namespace nbk

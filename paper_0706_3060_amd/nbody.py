@@ -1,0 +1,335 @@
+"""Torch-facing binding of libnbody.so: argument marshalling only.
+
+Every step of the computation (packing, the all-pairs kernels, reductions,
+the leapfrog update, the adjoint, the per-type gradient sums) runs in the HIP
+kernels of libnbody.so.  PyTorch supplies device memory (inputs, outputs and
+the workspace) and the current stream.  There is no CPU or PyTorch fallback:
+when the library is missing, or a tensor is not on a GPU, the call raises.
+
+Laws (see include/nbody.h for the full statement and citations):
+  gravity:    Eq. 1 softened gravity, params = masses [N]
+  ljc_linear: Table 1 LJC(linear), params = [N, 3] rows (q, sigma, epsilon)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+GRAVITY, LJC_LINEAR = 0, 1
+FP64, FP32_KAHAN, FP32_FP64ACC, FP32_PLAIN = 0, 1, 2, 3
+API_FORCES, API_BATCHED, API_BACKWARD, API_LEAPFROG = (N.API_FORCES, N.API_BATCHED,
+                                                       N.API_BACKWARD, N.API_LEAPFROG)
+PRECISIONS = {"fp64": FP64, "fp32_kahan": FP32_KAHAN, "fp32_fp64acc": FP32_FP64ACC,
+              "fp32_plain": FP32_PLAIN}
+
+
+@dataclass(frozen=True)
+class Law:
+    kind: int = GRAVITY
+    precision: int = FP32_FP64ACC
+    G: float = 1.0
+    softening: float = 0.0
+    coulomb_k: float = 332.0637
+    dielectric: float = 4.0
+
+    def c(self) -> N.NBodyLaw:
+        return N.NBodyLaw(self.kind, self.precision, self.G, self.softening, self.coulomb_k,
+                          self.dielectric)
+
+    @property
+    def n_params(self) -> int:
+        return 1 if self.kind == GRAVITY else 3
+
+
+def gravity(precision=FP32_FP64ACC, G=1.0, softening=0.0) -> Law:
+    return Law(GRAVITY, PRECISIONS.get(precision, precision), float(G), float(softening))
+
+
+def ljc_linear(precision=FP32_FP64ACC, coulomb_k=332.0637, dielectric=4.0) -> Law:
+    return Law(LJC_LINEAR, PRECISIONS.get(precision, precision), 1.0, 0.0, float(coulomb_k),
+               float(dielectric))
+
+
+# ------------------------------------------------------------------ helpers
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev_f64(t, shape, name, device=None):
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t, dtype=torch.float64, device=device)
+    if not t.is_cuda:
+        raise ValueError("%s must be a GPU tensor (got %s)" % (name, t.device))
+    if t.dtype != torch.float64:
+        t = t.to(torch.float64)
+    t = t.contiguous()
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(t.shape)))
+    return t
+
+
+def _params(params, n, law, device):
+    p = params if isinstance(params, torch.Tensor) else torch.as_tensor(params, device=device)
+    if law.kind == GRAVITY and p.dim() == 1:
+        p = p.reshape(n, 1)
+    return _dev_f64(p, (n, law.n_params), "params")
+
+
+_ws = {}
+
+
+def workspace(api, n_total, n_systems, law: Law, device) -> torch.Tensor:
+    """A cached uint8 device buffer at least nbody_workspace_bytes() long (per device and stream)."""
+    nbytes = N.lib().nbody_workspace_bytes(api, int(n_total), int(n_systems), ctypes.byref(law.c()))
+    if nbytes == 0 and n_total > 0:
+        raise ValueError("invalid workspace request")
+    dev = torch.device(device)
+    key = (dev.index, torch.cuda.current_stream(dev).cuda_stream)
+    buf = _ws.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)
+        _ws[key] = buf
+    return buf
+
+
+def clear_workspace_cache():
+    _ws.clear()
+
+
+# --------------------------------------------------------------- forward
+def forces(pos, params, law: Law, potential: bool = True, out=None):
+    """All-pairs forces (gravity: accelerations) and optionally potentials.
+
+    Returns (force [N,3] float64, potential [N] float64 or None)."""
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    pos = _dev_f64(pos, (n, 3), "pos")
+    par = _params(params, n, law, pos.device)
+    f = out if out is not None else torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    p = torch.empty(n, dtype=torch.float64, device=pos.device) if potential else None
+    ws = workspace(API_FORCES, n, 1, law, pos.device)
+    N.check(N.lib().nbody_forces(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(f), _ptr(p),
+                                 _ptr(ws), ws.numel(), _stream(pos.device)))
+    return f, p
+
+
+def forces_subset(pos, params, ilist, law: Law, potential: bool = True):
+    """Forces on particles ilist (int64 indices) against all particles (block time step)."""
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    pos = _dev_f64(pos, (n, 3), "pos")
+    par = _params(params, n, law, pos.device)
+    il = torch.as_tensor(ilist, device=pos.device).to(torch.int64).contiguous()
+    ni = il.numel()
+    if ni and (int(il.min()) < 0 or int(il.max()) >= n):
+        raise ValueError("ilist indices must lie in [0, %d)" % n)
+    f = torch.empty((ni, 3), dtype=torch.float64, device=pos.device)
+    p = torch.empty(ni, dtype=torch.float64, device=pos.device) if potential else None
+    ws = workspace(API_FORCES, max(n, ni), 1, law, pos.device)
+    N.check(N.lib().nbody_forces_subset(_ptr(pos), _ptr(par), n, _ptr(il), ni,
+                                        ctypes.byref(law.c()), _ptr(f), _ptr(p), _ptr(ws),
+                                        ws.numel(), _stream(pos.device)))
+    return f, p
+
+
+def _host_offsets(offsets):
+    if isinstance(offsets, torch.Tensor):
+        offsets = offsets.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+
+
+def forces_batched(offsets, pos, params, law: Law, potential: bool = True):
+    """Forces of independent systems (rows offsets[s]..offsets[s+1]) in one persistent launch."""
+    off = _host_offsets(offsets)
+    S = off.size - 1
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    if S < 0 or (S >= 0 and off[-1] != n):
+        raise ValueError("offsets[-1] must equal the number of rows of pos")
+    pos = _dev_f64(pos, (n, 3), "pos")
+    par = _params(params, n, law, pos.device)
+    f = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    p = torch.empty(n, dtype=torch.float64, device=pos.device) if potential else None
+    ws = workspace(API_BATCHED, n, S, law, pos.device)
+    N.check(N.lib().nbody_forces_batched(off.ctypes.data_as(ctypes.c_void_p), S, _ptr(pos),
+                                         _ptr(par), ctypes.byref(law.c()), _ptr(f), _ptr(p),
+                                         _ptr(ws), ws.numel(), _stream(pos.device)))
+    return f, p
+
+
+# --------------------------------------------------------------- adjoint
+def forces_backward(pos, params, grad_force, law: Law, want_pos=True, want_params=None,
+                    types=None, n_types=0):
+    """Adjoint of forces(): returns (dL/dpos [N,3] or None, dL/dparams [N,P] or None,
+    per-type (dL/dsigma, dL/depsilon) [n_types, 2] or None)."""
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    pos = _dev_f64(pos, (n, 3), "pos")
+    par = _params(params, n, law, pos.device)
+    g = _dev_f64(grad_force, (n, 3), "grad_force")
+    if want_params is None:
+        want_params = law.kind == LJC_LINEAR
+    dev = pos.device
+    gp = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_pos else None
+    gq = torch.empty((n, law.n_params), dtype=torch.float64, device=dev) if want_params else None
+    ty = gt = None
+    if types is not None:
+        ty = torch.as_tensor(types, device=dev).to(torch.int32).contiguous()
+        if ty.shape != (n,):
+            raise ValueError("types must have shape (%d,)" % n)
+        if n and (int(ty.min()) < 0 or int(ty.max()) >= n_types):
+            raise ValueError("types must lie in [0, n_types)")
+        gt = torch.empty((int(n_types), 2), dtype=torch.float64, device=dev)
+    ws = workspace(API_BACKWARD, n, 1, law, dev)
+    N.check(N.lib().nbody_forces_backward(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(g),
+                                          _ptr(gp), _ptr(gq), _ptr(ty), int(n_types), _ptr(gt),
+                                          _ptr(ws), ws.numel(), _stream(dev)))
+    return gp, gq, gt
+
+
+# --------------------------------------------------------------- leapfrog
+def leapfrog(pos, vel, acc, params, law: Law, dt: float, nsteps: int, inv_mass=None,
+             potential: bool = False):
+    """nsteps kick-drift-kick steps, updating pos, vel and acc IN PLACE (FP64 tensors on the
+    GPU).  Returns the potential at the final positions, or None."""
+    for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous()):
+            raise ValueError("%s must be a contiguous float64 GPU tensor (updated in place)" % name)
+    n = pos.shape[0]
+    for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc")):
+        if tuple(t.shape) != (n, 3):
+            raise ValueError("%s must have shape (%d, 3)" % (name, n))
+    par = _params(params, n, law, pos.device)
+    im = None if inv_mass is None else _dev_f64(inv_mass, (n,), "inv_mass")
+    p = torch.empty(n, dtype=torch.float64, device=pos.device) if potential else None
+    ws = workspace(API_LEAPFROG, n, 1, law, pos.device)
+    N.check(N.lib().leapfrog_step(_ptr(pos), _ptr(vel), _ptr(acc), _ptr(par), _ptr(im), n,
+                                  ctypes.byref(law.c()), float(dt), int(nsteps), _ptr(p),
+                                  _ptr(ws), ws.numel(), _stream(pos.device)))
+    return p
+
+
+# ------------------------------------------------------------- tuning etc.
+def set_config(api, block=256, i_per_lane=1, j_tile=256, j_split=1):
+    cfg = N.NBodyConfig(block, i_per_lane, j_tile, j_split)
+    N.check(N.lib().nbody_set_config(api, ctypes.byref(cfg)))
+
+
+def clear_config(api):
+    N.check(N.lib().nbody_set_config(api, None))
+
+
+def get_config(api, n, law: Law, n_systems=1):
+    cfg = N.NBodyConfig()
+    N.check(N.lib().nbody_get_config(api, int(n), int(n_systems), ctypes.byref(law.c()),
+                                     ctypes.byref(cfg)))
+    return dict(block=cfg.block, i_per_lane=cfg.i_per_lane, j_tile=cfg.j_tile, j_split=cfg.j_split)
+
+
+def autotune(pos, params, law: Law, offsets=None, potential=True):
+    """Measure candidate launch configurations on this problem and remember the fastest.
+    Returns (config dict, milliseconds)."""
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    par = _params(params, n, law, pos.device)
+    f = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    p = torch.empty(n, dtype=torch.float64, device=pos.device) if potential else None
+    best = N.NBodyConfig()
+    ms = ctypes.c_double()
+    if offsets is None:
+        ws = workspace(API_FORCES, n, 1, law, pos.device)
+        N.check(N.lib().nbody_autotune(API_FORCES, None, 0, _ptr(pos), _ptr(par), n,
+                                       ctypes.byref(law.c()), _ptr(f), _ptr(p), _ptr(ws), ws.numel(),
+                                       _stream(pos.device), ctypes.byref(best), ctypes.byref(ms)))
+    else:
+        off = _host_offsets(offsets)
+        S = off.size - 1
+        ws = workspace(API_BATCHED, n, S, law, pos.device)
+        N.check(N.lib().nbody_autotune(API_BATCHED, off.ctypes.data_as(ctypes.c_void_p), S,
+                                       _ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(f),
+                                       _ptr(p), _ptr(ws), ws.numel(), _stream(pos.device),
+                                       ctypes.byref(best), ctypes.byref(ms)))
+    return (dict(block=best.block, i_per_lane=best.i_per_lane, j_tile=best.j_tile,
+                 j_split=best.j_split), ms.value)
+
+
+def tune_save(path):
+    N.check(N.lib().nbody_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    N.check(N.lib().nbody_tune_load(str(path).encode()))
+
+
+def timing_enable(on=True):
+    N.check(N.lib().nbody_timing_enable(1 if on else 0))
+
+
+def timing_read(reset=True):
+    """(total milliseconds, launches) of the all-pairs kernels since the last reset."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    N.check(N.lib().nbody_timing_read(ctypes.byref(ms), ctypes.byref(cnt), 1 if reset else 0))
+    return ms.value, cnt.value
+
+
+def flops_per_pair(api, law_kind, with_potential):
+    return int(N.lib().nbody_flops_per_pair(api, law_kind, 1 if with_potential else 0))
+
+
+# ---------------------------------------------------------------- autograd
+class NBodyForcesFn(torch.autograd.Function):
+    """F = forces(pos, params) with a hand-written adjoint (nbody_forces_backward).
+
+    Gradients: pos always; params for LJC(linear) (per-atom q, sigma, epsilon)."""
+
+    @staticmethod
+    def forward(ctx, pos, params, law: Law):
+        f, _ = forces(pos, params, law, potential=False)
+        ctx.save_for_backward(pos, params)
+        ctx.law = law
+        return f
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        pos, params = ctx.saved_tensors
+        law = ctx.law
+        need_pos = ctx.needs_input_grad[0]
+        need_par = ctx.needs_input_grad[1] and law.kind == LJC_LINEAR
+        gp, gq, _ = forces_backward(pos.detach(), params.detach(), grad_f.contiguous(), law,
+                                    want_pos=need_pos, want_params=need_par)
+        if gq is not None:
+            gq = gq.reshape(params.shape)
+        return gp, gq, None
+
+
+class LJCTypedForcesFn(torch.autograd.Function):
+    """LJC(linear) forces with per-type sigma/epsilon tables; the per-type gradient
+    sums are reduced on the GPU in a fixed order."""
+
+    @staticmethod
+    def forward(ctx, pos, q, sigma_t, eps_t, types, law: Law):
+        types = types.to(torch.int64)
+        params = torch.stack([q, sigma_t[types], eps_t[types]], dim=1).contiguous()
+        f, _ = forces(pos, params, law, potential=False)
+        ctx.save_for_backward(pos, params, types)
+        ctx.law = law
+        ctx.n_types = sigma_t.shape[0]
+        return f
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        pos, params, types = ctx.saved_tensors
+        gp, gq, gt = forces_backward(pos, params, grad_f.contiguous(), ctx.law, want_pos=True,
+                                     want_params=True, types=types, n_types=ctx.n_types)
+        return gp, gq[:, 0].contiguous(), gt[:, 0].contiguous(), gt[:, 1].contiguous(), None, None

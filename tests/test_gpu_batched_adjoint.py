@@ -1,0 +1,186 @@
+"""GPU parity of the batched (one persistent launch) and adjoint paths against the
+FP64 CPU oracle, plus the autograd Functions.
+
+Batched: every system of an uneven ensemble (including empty and one-particle
+systems) matches the oracle evaluated on that system alone.  Adjoint: the
+Hessian-vector product of gravity and the position / parameter adjoints of
+LJC(linear) match the oracle's analytic derivatives; gradcheck passes on the
+FP64 path.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0706_3060_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0706_3060_amd import nbody
+    return nbody
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_rows(x, ref):
+    return np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)
+
+
+SIZES = [0, 1, 2, 63, 64, 65, 300, 0, 777, 1500, 129, 5]
+
+
+@pytest.fixture(scope="module")
+def ensemble():
+    return W.batched_md(len(SIZES), seed=4, sizes=SIZES, workers=1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan", "fp32_fp64acc"])
+def test_batched_matches_per_system_oracle(nb, ensemble, prec):
+    off, pos, par, systems = ensemble
+    f, u = nb.forces_batched(off, dev(pos), dev(par), nb.ljc_linear(prec))
+    f, u = host(f), host(u)
+    for s, sy in enumerate(systems):
+        a, b = off[s], off[s + 1]
+        if b - a == 0:
+            continue
+        x = sy.pos if prec == "fp64" else W.round_to_f32(sy.pos)
+        fr, ur = oracle.ljc_linear(x, sy.q, sy.sigma, sy.epsilon)
+        if b - a == 1:
+            assert np.all(f[a:b] == 0) and np.all(u[a:b] == 0)
+            continue
+        e = rel_rows(f[a:b], fr)
+        if prec == "fp64":
+            assert e.max() <= 1e-12, (s, e.max())
+            assert np.abs(u[a:b] - ur).max() <= 1e-12 * np.abs(ur).max()
+        else:
+            assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (s, np.median(e), e.max())
+
+
+def test_batched_gravity_and_configs(nb):
+    sizes = [100, 0, 513, 64, 1, 2000]
+    rng = np.random.default_rng(9)
+    pos = np.concatenate([W.plummer(n, 100 + k)[0] if n else np.zeros((0, 3))
+                          for k, n in enumerate(sizes)])
+    m = rng.uniform(0.5, 1.5, pos.shape[0]) / pos.shape[0]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    law = nb.gravity("fp64", softening=0.01)
+    ref = []
+    for s in range(len(sizes)):
+        a, b = off[s], off[s + 1]
+        ref.append(oracle.gravity(pos[a:b], m[a:b], eps=0.01) if b > a else None)
+    for cfg in [None, (64, 1, 64), (256, 2, 256), (128, 4, 128)]:
+        if cfg:
+            nb.set_config(nb.API_BATCHED, cfg[0], cfg[1], cfg[2], 1)
+        try:
+            f, p = nb.forces_batched(off, dev(pos), dev(m), law)
+        finally:
+            nb.clear_config(nb.API_BATCHED)
+        f, p = host(f), host(p)
+        for s in range(len(sizes)):
+            a, b = off[s], off[s + 1]
+            if b - a < 2:
+                continue
+            assert rel_rows(f[a:b], ref[s][0]).max() <= 1e-12
+            assert (np.abs(p[a:b] - ref[s][1]) / np.abs(ref[s][1])).max() <= 1e-12
+
+
+def test_batched_equals_single_system_calls(nb, ensemble):
+    off, pos, par, systems = ensemble
+    law = nb.ljc_linear("fp32_kahan")
+    fb, ub = nb.forces_batched(off, dev(pos), dev(par), law)
+    for s in range(len(systems)):
+        a, b = off[s], off[s + 1]
+        if b - a == 0:
+            continue
+        fs, us = nb.forces(dev(pos[a:b]), dev(par[a:b]), law)
+        d = (fb[a:b] - fs).abs().max().item()
+        assert d <= 1e-5 * max(1.0, fs.abs().max().item())
+
+
+# --------------------------------------------------------------- adjoint
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32_fp64acc", 1e-4), ("fp32_kahan", 1e-4)])
+def test_gravity_adjoint_matches_oracle(nb, prec, tol):
+    n = 3000
+    pos, _, m = W.plummer(n, 6)
+    m = m * np.random.default_rng(1).uniform(0.5, 1.5, n)
+    g = W.unit_cotangent(n, 56)
+    gp, gq, _ = nb.forces_backward(dev(pos), dev(m), dev(g), nb.gravity(prec, softening=0.01))
+    assert gq is None
+    x = pos if prec == "fp64" else W.round_to_f32(pos)
+    ref = oracle.gravity_adjoint(x, m, g, eps=0.01)
+    e = rel_rows(host(gp), ref)
+    if prec == "fp64":
+        assert e.max() <= tol
+    else:
+        assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_fp64acc", "fp32_kahan"])
+def test_ljc_adjoint_matches_oracle(nb, prec):
+    s = W.md_system(1200, 8, box=34.0)
+    g = W.unit_cotangent(s.n, 57)
+    gp, gq, gt = nb.forces_backward(dev(s.pos), dev(s.params()), dev(g), nb.ljc_linear(prec),
+                                    types=torch.tensor(s.types, device="cuda"), n_types=4)
+    x = s.pos if prec == "fp64" else W.round_to_f32(s.pos)
+    rp, rq, rs, re = oracle.ljc_adjoint(x, s.q, s.sigma, s.epsilon, g)
+    gp, gq, gt = host(gp), host(gq), host(gt)
+    tol_med, tol_max = (1e-12, 1e-10) if prec == "fp64" else (1e-5, 1e-3)
+    e = rel_rows(gp, rp)
+    assert np.median(e) <= tol_med and e.max() <= tol_max, (np.median(e), e.max())
+    for got, ref in ((gq[:, 0], rq), (gq[:, 1], rs), (gq[:, 2], re)):
+        err = np.abs(got - ref) / np.abs(ref).max()
+        assert np.median(err) <= tol_med and err.max() <= tol_max, (np.median(err), err.max())
+    # per-type sums of dL/dsigma, dL/deps
+    for t in range(4):
+        sel = s.types == t
+        np.testing.assert_allclose(gt[t, 0], gq[sel, 1].sum(), rtol=1e-12, atol=1e-12 * np.abs(gq[:, 1]).sum())
+        np.testing.assert_allclose(gt[t, 1], gq[sel, 2].sum(), rtol=1e-12, atol=1e-12 * np.abs(gq[:, 2]).sum())
+
+
+def test_autograd_gradcheck_fp64(nb):
+    s = W.md_system(6, 2, box=9.0)
+    law = nb.ljc_linear("fp64")
+    pos = dev(s.pos).requires_grad_(True)
+    par = dev(s.params()).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x, p: nb.NBodyForcesFn.apply(x, p, law), (pos, par),
+                                    eps=1e-6, atol=1e-7, rtol=1e-6)
+    pg, _, mg = W.plummer(5, 3)
+    lawg = nb.gravity("fp64", softening=0.1)
+    x = dev(pg).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda y: nb.NBodyForcesFn.apply(y, dev(mg), lawg), (x,),
+                                    eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_typed_force_matching_gradient(nb):
+    # L = ||F(theta) - F_target||^2 with F_target from 5%-perturbed parameters
+    s = W.md_system(400, 3, box=24.0)
+    t = W.perturbed(s, 33)
+    law = nb.ljc_linear("fp64")
+    ftarget, _ = nb.forces(dev(s.pos), dev(t.params()), law)
+    pos = dev(s.pos).requires_grad_(True)
+    q = dev(s.q).requires_grad_(True)
+    st = dev(s.sigma_t).requires_grad_(True)
+    et = dev(s.eps_t).requires_grad_(True)
+    types = torch.tensor(s.types, device="cuda")
+    F = nb.LJCTypedForcesFn.apply(pos, q, st, et, types, law)
+    L = ((F - ftarget) ** 2).sum()
+    L.backward()
+    g = 2.0 * (host(F) - host(ftarget))
+    rp, rq, rs, re = oracle.ljc_adjoint(s.pos, s.q, s.sigma, s.epsilon, g)
+    np.testing.assert_allclose(host(pos.grad), rp, rtol=1e-9, atol=1e-11 * np.abs(rp).max())
+    np.testing.assert_allclose(host(q.grad), rq, rtol=1e-9, atol=1e-11 * np.abs(rq).max())
+    for k in range(4):
+        sel = s.types == k
+        np.testing.assert_allclose(host(st.grad)[k], rs[sel].sum(), rtol=1e-9)
+        np.testing.assert_allclose(host(et.grad)[k], re[sel].sum(), rtol=1e-9)

@@ -1,0 +1,166 @@
+"""GPU parity of the forward all-pairs path (C ABI via the torch binding) against
+the FP64 CPU oracle.
+
+Tolerances: FP64 paths <= 1e-12 in the maximum per-particle relative error;
+FP32 paths median <= 1e-5 and maximum <= 1e-3, measured against the oracle fed
+the FP32-rounded inputs (so input quantisation is not counted).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0706_3060_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS = 0.01
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0706_3060_amd import nbody
+    return nbody
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_rows(x, ref):
+    return np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)
+
+
+def rel_scalar(x, ref):
+    return np.abs(x - ref) / np.abs(ref)
+
+
+def test_library_is_native_and_single_runtime(nb):
+    from paper_0706_3060_amd import _native
+    assert _native.lib()._name.endswith("libnbody.so")
+    assert "torch" in _native.runtime_path()
+
+
+# ------------------------------------------------------------------ FP64
+@pytest.mark.parametrize("n", [4096, 1000, 63, 64, 65, 2])
+def test_gravity_fp64_matches_oracle(nb, n):
+    pos, _, m = W.plummer(n, 1)
+    f, p = nb.forces(dev(pos), dev(m), nb.gravity("fp64", softening=EPS))
+    a_ref, phi_ref = oracle.gravity(pos, m, eps=EPS)
+    assert rel_rows(host(f), a_ref).max() <= 1e-12
+    assert rel_scalar(host(p), phi_ref).max() <= 1e-12
+
+
+def test_gravity_fp64_one_leapfrog_step(nb):
+    # N=4096 Plummer, eps=0.01, dt=1e-3: a0, phi0, then one KDK step (x1, v1, a1)
+    pos, vel, m = W.plummer(4096, 1)
+    law = nb.gravity("fp64", softening=EPS)
+    x, v = dev(pos), dev(vel)
+    a, _ = nb.forces(x, dev(m), law)
+    a0_ref, _ = oracle.gravity(pos, m, eps=EPS)
+    phi1 = nb.leapfrog(x, v, a, dev(m), law, 1e-3, 1, potential=True)
+    xr, vr, ar, pr = oracle.leapfrog(oracle.GRAVITY, pos, vel, a0_ref, m, 1e-3, 1, eps=EPS)
+    assert np.abs(host(x) - xr).max() <= 1e-12 * np.abs(xr).max()
+    assert np.abs(host(v) - vr).max() <= 1e-12 * np.abs(vr).max()
+    assert rel_rows(host(a), ar).max() <= 1e-12
+    assert rel_scalar(host(phi1), pr).max() <= 1e-12
+
+
+def test_ljc_fp64_matches_oracle(nb):
+    s = W.md_system(1500, 3, box=36.0)
+    f, u = nb.forces(dev(s.pos), dev(s.params()), nb.ljc_linear("fp64"))
+    f_ref, u_ref = oracle.ljc_linear(s.pos, s.q, s.sigma, s.epsilon)
+    assert rel_rows(host(f), f_ref).max() <= 1e-12
+    assert (np.abs(host(u) - u_ref) / np.abs(u_ref).max()).max() <= 1e-12
+
+
+# ------------------------------------------------------------------ FP32
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp32_fp64acc"])
+@pytest.mark.parametrize("n", [4096, 20000, 777])
+def test_gravity_fp32_matches_oracle(nb, prec, n):
+    pos, _, m = W.plummer(n, 2)
+    f, p = nb.forces(dev(pos), dev(m), nb.gravity(prec, softening=EPS))
+    a_ref, phi_ref = oracle.gravity(W.round_to_f32(pos), W.round_to_f32(m), eps=EPS)
+    e = rel_rows(host(f), a_ref)
+    ep = rel_scalar(host(p), phi_ref)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
+    assert np.median(ep) <= 1e-5 and ep.max() <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp32_fp64acc"])
+def test_ljc_fp32_matches_oracle(nb, prec):
+    s = W.md_system(3000, 5, box=45.0)
+    f, u = nb.forces(dev(s.pos), dev(s.params()), nb.ljc_linear(prec))
+    f_ref, u_ref = oracle.ljc_linear(W.round_to_f32(s.pos), s.q, s.sigma, s.epsilon)
+    e = rel_rows(host(f), f_ref)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
+    eu = np.abs(host(u) - u_ref) / np.abs(u_ref).max()
+    assert np.median(eu) <= 1e-5
+
+
+def test_fp32_plain_ablation_runs(nb):
+    pos, _, m = W.plummer(20000, 3)
+    f, _ = nb.forces(dev(pos), dev(m), nb.gravity("fp32_plain", softening=EPS))
+    a_ref, _ = oracle.gravity(W.round_to_f32(pos), W.round_to_f32(m), eps=EPS)
+    e = rel_rows(host(f), a_ref)
+    assert np.median(e) <= 1e-4
+
+
+# ------------------------------------------------------- configurations
+CONFIGS = [(64, 1, 64, 1), (256, 2, 256, 3), (128, 4, 128, 7), (256, 8, 512, 2), (64, 1, 1024, 64)]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_launch_configurations_agree(nb, cfg):
+    block, ipl, jt, js = cfg
+    pos, _, m = W.plummer(3001, 4)
+    x, mm = dev(pos), dev(m)
+    law64 = nb.gravity("fp64", softening=EPS)
+    law32 = nb.gravity("fp32_fp64acc", softening=EPS)
+    a_ref, phi_ref = oracle.gravity(pos, m, eps=EPS)
+    try:
+        nb.set_config(nb.API_FORCES, block, ipl, jt, js)
+        f64, p64 = nb.forces(x, mm, law64)
+        f32, _ = nb.forces(x, mm, law32)
+    finally:
+        nb.clear_config(nb.API_FORCES)
+    assert rel_rows(host(f64), a_ref).max() <= 1e-12
+    assert rel_scalar(host(p64), phi_ref).max() <= 1e-12
+    a32_ref, _ = oracle.gravity(W.round_to_f32(pos), W.round_to_f32(m), eps=EPS)
+    e = rel_rows(host(f32), a32_ref)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3
+
+
+def test_deterministic(nb):
+    pos, _, m = W.plummer(5000, 5)
+    law = nb.gravity("fp32_kahan", softening=EPS)
+    f1, p1 = nb.forces(dev(pos), dev(m), law)
+    f2, p2 = nb.forces(dev(pos), dev(m), law)
+    assert torch.equal(f1, f2) and torch.equal(p1, p2)
+
+
+def test_subset_rows(nb):
+    pos, _, m = W.plummer(6000, 6)
+    il = np.random.default_rng(0).integers(0, 6000, 700)
+    f, p = nb.forces_subset(dev(pos), dev(m), torch.tensor(il, device="cuda"),
+                            nb.gravity("fp64", softening=EPS))
+    a_ref, phi_ref = oracle.gravity(pos, m, eps=EPS, ilist=il)
+    assert rel_rows(host(f), a_ref).max() <= 1e-12
+    assert rel_scalar(host(p), phi_ref).max() <= 1e-12
+
+
+def test_edge_cases(nb):
+    law = nb.gravity("fp64", softening=EPS)
+    f, p = nb.forces(dev(np.zeros((0, 3))), dev(np.zeros(0)), law)
+    assert f.shape == (0, 3)
+    f, p = nb.forces(dev([[1.0, 2.0, 3.0]]), dev([2.0]), law)
+    assert torch.all(f == 0) and torch.all(p == 0)
+    # coincident particles with zero softening: undefined, as in the oracle
+    f, p = nb.forces(dev(np.zeros((2, 3))), dev([1.0, 1.0]), nb.gravity("fp64", softening=0.0))
+    assert not torch.isfinite(f).all()
