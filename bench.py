@@ -1,0 +1,297 @@
+#!/usr/bin/env python3
+"""Benchmark of the all-pairs N-body hot path on one MI355X.
+
+Headline workload: softened gravity on a Plummer sphere, N = 1,048,576
+(seed 5, eps = 0.005, G = 1, equal masses 1/N), FP32 pair arithmetic with
+Kahan-compensated accumulation.  One timed step is one kick-drift-kick
+leapfrog step in FP64 (pack + kick/drift, the all-pairs force and potential
+evaluation with its FP64 finalize, and the closing kick) -- N^2 ordered pair
+interactions.  The launch configuration comes from the autotuner, run before
+the timed region.
+
+Printed (one JSON line on stdout): interactions per second, the roofline of
+the all-pairs kernel (algorithmic flops per launch / its mean launch time,
+measured with HIP events on the launch stream), the oracle timed on a bounded
+sample on the host cores, the accuracy of the timed path against the FP64 GPU
+pass and the oracle, and two secondary legs: the batched ensemble (256 LJC
+systems, N_s in [500, 5000], one persistent launch vs one FP64 launch per
+system) and the position adjoint at N = 262,144 (FP32 vs FP64).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3   # 256 CU x 64 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+N_MAIN = 1 << 20
+EPS_MAIN = 0.005
+DT = 1e-3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=N_MAIN, help="particles of the headline workload")
+    ap.add_argument("--legs", default="all", choices=["all", "main"],
+                    help="'main' runs only the headline workload (for counter runs)")
+    ap.add_argument("--no-tune", action="store_true", help="use the heuristic configuration")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target host time of the oracle sample")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        msg = ("bench.py measures one GPU: this build has no multi-GPU path (the forward would "
+               "shard the i range and all-gather the FP32 j records; see the design notes). "
+               "Run with --gpus 1.")
+        log(msg)
+        if int(os.environ.get("RANK", "0")) == 0:
+            print(json.dumps({"error": msg, "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    from paper_0706_3060_amd import workloads as W
+
+    # ---- inputs drawn before any GPU work (the ensemble uses a fork pool)
+    t0 = time.time()
+    pos, vel, mass = W.plummer(args.n, 5)
+    ens = W.batched_md(256, seed=4) if args.legs == "all" else None
+    log("inputs drawn in %.1f s" % (time.time() - t0))
+
+    import torch
+    from paper_0706_3060_amd import nbody as nb
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    props = torch.cuda.get_device_properties(dev)
+    log("device:", props.name, "CUs:", props.multi_processor_count)
+
+    # calibration copy of known size (bytes moved are known exactly; used to
+    # scale hardware traffic counters in counter runs)
+    cal = torch.empty(64 << 20, dtype=torch.float32, device=dev)   # 256 MiB
+    cal2 = cal.clone()
+    del cal, cal2
+
+    n = args.n
+    x = torch.tensor(pos, device=dev)
+    v = torch.tensor(vel, device=dev)
+    m = torch.tensor(mass, device=dev)
+    law = nb.gravity("fp32_kahan", softening=EPS_MAIN)
+    law64 = nb.gravity("fp64", softening=EPS_MAIN)
+
+    # ---- accuracy of the timed precision at t = 0 (FP64 GPU pass over all N,
+    #      oracle on a random row sample)
+    if not args.no_tune:
+        cfg, tune_ms = nb.autotune(x, m, law, potential=True)
+        log("autotuned forces config:", cfg, "%.2f ms" % tune_ms)
+    a32, p32 = nb.forces(x, m, law)
+    a64, p64 = nb.forces(x, m, law64)
+    torch.cuda.synchronize()
+    e = (torch.linalg.norm(a32 - a64, dim=1) / torch.linalg.norm(a64, dim=1)).cpu().numpy()
+    ep = ((p32 - p64).abs() / p64.abs()).cpu().numpy()
+    acc = {"fp32_kahan_vs_fp64_gpu": {"median": float(np.median(e)), "p99": float(np.quantile(e, 0.99)),
+                                      "max": float(e.max()), "potential_median": float(np.median(ep)),
+                                      "potential_max": float(ep.max())}}
+    log("fp32 vs fp64 gpu:", acc["fp32_kahan_vs_fp64_gpu"])
+
+    # ---- timed region: K leapfrog steps (inputs resident in HBM)
+    acc_t = a32.clone()
+    for _ in range(args.warmup):
+        nb.leapfrog(x, v, acc_t, m, law, DT, 1)
+    torch.cuda.synchronize()
+    nb.timing_read(reset=True)
+    nb.timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        nb.leapfrog(x, v, acc_t, m, law, DT, 1, potential=True)
+    torch.cuda.synchronize()
+    t_el = time.perf_counter() - t_start
+    nb.timing_enable(False)
+    k_ms, k_launches = nb.timing_read(reset=True)
+    ms_step = 1e3 * t_el / args.steps
+    pairs = float(n) * float(n)
+    value = pairs / (t_el / args.steps) / 1e9
+    flops_pair = nb.flops_per_pair(nb.API_FORCES, nb.GRAVITY, True)
+    k_avg_s = (k_ms / max(k_launches, 1)) * 1e-3
+    achieved = flops_pair * pairs / k_avg_s / 1e12
+    cfg_used = nb.get_config(nb.API_LEAPFROG, n, law)
+    log("step %.3f ms, %.1f G pairs/s; all-pairs kernel %.3f ms/launch over %d launches, %.2f TFLOP/s"
+        % (ms_step, value, k_ms / max(k_launches, 1), k_launches, achieved))
+
+    # oracle on a row sample of the same (t = 0) workload, same FP32-rounded inputs
+    import oracle
+    rng = np.random.default_rng(55)
+    rows = np.sort(rng.choice(n, 256, replace=False))
+    xr = W.round_to_f32(pos)
+    mr = W.round_to_f32(mass)
+    t1 = time.perf_counter()
+    a_ref, phi_ref = oracle.gravity(xr, mr, eps=EPS_MAIN, ilist=rows)
+    t_cal = time.perf_counter() - t1
+    e_or = np.linalg.norm(a32.cpu().numpy()[rows] - a_ref, axis=1) / np.linalg.norm(a_ref, axis=1)
+    a64_or, _ = oracle.gravity(pos, mass, eps=EPS_MAIN, ilist=rows)
+    e64_or = np.linalg.norm(a64.cpu().numpy()[rows] - a64_or, axis=1) / np.linalg.norm(a64_or, axis=1)
+    acc["fp32_kahan_vs_oracle_sample"] = {"rows": int(rows.size), "median": float(np.median(e_or)),
+                                          "max": float(e_or.max())}
+    acc["fp64_gpu_vs_oracle_sample"] = {"rows": int(rows.size), "max": float(e64_or.max())}
+
+    # cpu baseline: the oracle as it stands, on a bounded row sample sized to ~cpu_seconds
+    rate = rows.size * n / t_cal
+    k_rows = int(max(256, min(n, args.cpu_seconds * rate / n)))
+    sample = np.sort(rng.choice(n, k_rows, replace=False))
+    threads = oracle.threads(0)
+    t1 = time.perf_counter()
+    oracle.gravity(pos, mass, eps=EPS_MAIN, ilist=sample)
+    t_cpu = time.perf_counter() - t1
+    cpu_value = k_rows * n / t_cpu / 1e9
+    log("oracle: %d rows x %d in %.1f s on %d threads = %.3f G pairs/s" % (k_rows, n, t_cpu, threads, cpu_value))
+
+    traffic = measured_traffic(n, cfg_used)
+    out = {
+        "metric": "G pair-interactions/s & %FP32 VALU peak, N=1M; batched vs loop @1e-5 err",
+        "value": value,
+        "unit": "G pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "plummer_gravity_kdk_step", "n": n, "softening": EPS_MAIN,
+                   "G": 1.0, "dt": DT, "seed": 5, "precision": "fp32_kahan",
+                   "pairs_per_step": pairs, "flops_per_pair": flops_pair,
+                   "launch": cfg_used, "parallelism": "single_gpu"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "kernel_ms": k_ms / max(k_launches, 1), "launches": k_launches},
+        "cpu_baseline": {"value": cpu_value, "unit": "G pair-interactions/s", "cores": threads,
+                         "kind": "oracle",
+                         "sample": "%d random rows of the N=%d Plummer workload against all N "
+                                   "(FP64 oracle, compensated sums), %.1f s" % (k_rows, n, t_cpu)},
+        "accuracy": acc,
+    }
+
+    if args.legs == "all":
+        out["batched"] = batched_leg(nb, torch, dev, ens)
+        out["backward"] = backward_leg(nb, torch, dev, W)
+    print(json.dumps(out), flush=True)
+
+
+def measured_traffic(n, cfg):
+    """HBM bytes per launch of the all-pairs kernel from the committed counter runs
+    (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the kernel sources or
+    the launch configuration differ from the ones the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_forces_gravity_fp32kahan_n1048576.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read()
+                                    for s in rec["sources"])).hexdigest()
+    except (OSError, KeyError, ValueError):
+        return None
+    if h != rec.get("sources_sha256") or rec.get("config") != cfg or rec.get("n") != n:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def batched_leg(nb, torch, dev, ens):
+    """256 LJC systems: one persistent FP32+Kahan launch vs one FP64 launch per system."""
+    off, pos, par, systems = ens
+    S = len(systems)
+    x = torch.tensor(pos, device=dev)
+    p = torch.tensor(par, device=dev)
+    law = nb.ljc_linear("fp32_kahan")
+    law64 = nb.ljc_linear("fp64")
+    cfg, _ = nb.autotune(x, p, law, offsets=off, potential=True)
+    log("autotuned batched config:", cfg)
+    pairs = float(sum(int(off[s + 1] - off[s]) ** 2 for s in range(S)))
+
+    def run_batched():
+        return nb.forces_batched(off, x, p, law)
+
+    views = [(x[off[s]:off[s + 1]], p[off[s]:off[s + 1]]) for s in range(S)]
+
+    def run_loop(l):
+        outs = []
+        for xs, ps in views:
+            outs.append(nb.forces(xs, ps, l))
+        return outs
+
+    def timeit(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return best, r
+
+    tb, (fb, ub) = timeit(run_batched)
+    tl64, outs64 = timeit(lambda: run_loop(law64))
+    tl32, _ = timeit(lambda: run_loop(law))
+    f64 = torch.cat([o[0] for o in outs64])
+    e = (torch.linalg.norm(fb - f64, dim=1) / torch.linalg.norm(f64, dim=1)).cpu().numpy()
+    med_sys = [float(np.median(e[off[s]:off[s + 1]])) for s in range(S) if off[s + 1] > off[s]]
+    res = {"systems": S, "atoms": int(off[-1]), "pairs": pairs, "config": cfg,
+           "batched_fp32_kahan_ms": tb * 1e3, "loop_fp64_ms": tl64 * 1e3, "loop_fp32_kahan_ms": tl32 * 1e3,
+           "speedup_vs_loop_fp64": tl64 / tb, "speedup_vs_loop_fp32": tl32 / tb,
+           "batched_g_pairs_per_s": pairs / tb / 1e9,
+           "err_vs_fp64_per_system_median_max": max(med_sys), "err_vs_fp64_max": float(e.max())}
+    log("batched:", res)
+    return res
+
+
+def backward_leg(nb, torch, dev, W):
+    """Position adjoint (Hessian-vector product) of gravity at N = 262,144, FP32 vs FP64."""
+    n = 262144
+    pos, _, m = W.plummer(n, 6)
+    g = W.unit_cotangent(n, 56)
+    x = torch.tensor(pos, device=dev)
+    mm = torch.tensor(m, device=dev)
+    gg = torch.tensor(g, device=dev)
+    res = {"n": n}
+    outs = {}
+    for name in ("fp32_fp64acc", "fp64"):
+        law = nb.gravity(name, softening=EPS_MAIN)
+        nb.forces_backward(x, mm, gg, law)
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(3):
+            t = time.perf_counter()
+            gp, _, _ = nb.forces_backward(x, mm, gg, law)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        outs[name] = gp
+        res[name + "_ms"] = best * 1e3
+    e = (torch.linalg.norm(outs["fp32_fp64acc"] - outs["fp64"], dim=1)
+         / torch.linalg.norm(outs["fp64"], dim=1)).cpu().numpy()
+    res["speedup_fp32_vs_fp64"] = res["fp64_ms"] / res["fp32_fp64acc_ms"]
+    res["flops_per_pair"] = nb.flops_per_pair(nb.API_BACKWARD, nb.GRAVITY, False)
+    res["fp32_tflops"] = res["flops_per_pair"] * float(n) ** 2 / (res["fp32_fp64acc_ms"] * 1e-3) / 1e12
+    res["err_vs_fp64"] = {"median": float(np.median(e)), "max": float(e.max())}
+    log("backward:", res)
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,9 @@ Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot)
     if (g_override_set[api]) return sanitize(g_override[api], api, law->precision, npad);
     auto it = g_tuned.find(TuneKey(api, law->kind, law->precision, pot ? 1 : 0, size_bucket(n),
                                    size_bucket(S)));
+    if (it == g_tuned.end() && api == NBODY_API_LEAPFROG)   // a leapfrog step runs the forces kernel
+        it = g_tuned.find(TuneKey(NBODY_API_FORCES, law->kind, law->precision, pot ? 1 : 0,
+                                  size_bucket(n), size_bucket(S)));
     if (it != g_tuned.end()) return sanitize(it->second.first, api, law->precision, npad);
     return heuristic(api, law->precision, n, S);
 }
@@ -555,7 +558,7 @@ std::vector<Cfg> candidates(int api, int prec, int64_t n)
         for (int b : blocks)
             for (int split = 1; split <= max_split(npad); split *= 2) {
                 const int64_t w = waves * split;
-                if (w > 8 * kTargetWaves && split > 1) break;
+                if (w > 2 * kTargetWaves && split > 1) break;
                 if (w < kTargetWaves / 8 && split < max_split(npad)) continue;
                 Cfg c;
                 c.ipl = ipl;
