@@ -18,3 +18,28 @@ def oracle_mod():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+# The full 256-system ensemble takes ~1 minute to draw serially; draw it once,
+# in a fork pool, after collection and before any test touches the GPU.
+_FULL_ENSEMBLE = {}
+
+
+def pytest_collection_finish(session):
+    wants = any(item.get_closest_marker("gpu") and "full_ensemble" in getattr(item, "fixturenames", ())
+                for item in session.items)
+    if not wants:
+        return
+    torch = sys.modules.get("torch")
+    if torch is not None and torch.cuda.is_initialized():
+        return
+    from paper_0706_3060_amd import workloads as W
+    _FULL_ENSEMBLE["data"] = W.batched_md(256, seed=4)
+
+
+@pytest.fixture(scope="session")
+def full_ensemble():
+    if "data" not in _FULL_ENSEMBLE:
+        from paper_0706_3060_amd import workloads as W
+        _FULL_ENSEMBLE["data"] = W.batched_md(256, seed=4)
+    return _FULL_ENSEMBLE["data"]

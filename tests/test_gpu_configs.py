@@ -1,0 +1,244 @@
+"""The five measured workloads at their full sizes, on the GPU, against the oracle.
+
+Where the oracle cannot evaluate every output in seconds, it evaluates sampled
+rows one by one (seeded samples) and the rest is checked against the FP64 GPU
+pass, which is itself pinned to the oracle.
+
+1. gravity, Plummer N=4096, FP64: forward + one KDK step            (tests/test_gpu_forward.py)
+2. gravity, Plummer N=65,536, FP32 + FP64/Kahan sums, 100 KDK steps: force error at t=0 and
+   t=100, relative energy drift next to the FP64 trajectory's
+3. LJC(linear), N=8192 MD box, FP32 forward + force-matching backward; FD and Euler checks
+4. 256 LJC systems, N_s in [500, 5000], one persistent launch vs per-system FP64
+5. gravity, Plummer N=1,048,576, eps=0.005, FP32 + Kahan vs the FP64 GPU pass, oracle on
+   sampled rows; Hessian-vector product at N=262,144
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0706_3060_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+BENCH_CFG = (256, 1, 256, 1)      # the launch configuration the benchmark's autotuner picked
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0706_3060_amd import nbody
+    return nbody
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_rows(x, ref):
+    return np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)
+
+
+def energy(nb, x, v, m, eps):
+    """Total energy with the potential from the FP64 pass (so FP32 potential error is not
+    counted as drift)."""
+    _, phi = nb.forces(x, m, nb.gravity("fp64", softening=eps))
+    return float((0.5 * m * (v * v).sum(1)).sum() + 0.5 * (m * phi).sum())
+
+
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp32_fp64acc"])
+def test_config2_plummer_65536_100_steps(nb, prec):
+    n, eps, dt = 65536, 0.01, 1e-3
+    pos, vel, m = W.plummer(n, 2)
+    law = nb.gravity(prec, softening=eps)
+    law64 = nb.gravity("fp64", softening=eps)
+    x, v, mm = dev(pos), dev(vel), dev(m)
+    a, _ = nb.forces(x, mm, law)
+    # t = 0 against the full oracle on the FP32-rounded inputs
+    a_ref, _ = oracle.gravity(W.round_to_f32(pos), W.round_to_f32(m), eps=eps)
+    e0 = rel_rows(host(a), a_ref)
+    assert np.median(e0) <= 1e-5 and e0.max() <= 1e-3, (np.median(e0), e0.max())
+    E0 = energy(nb, x, v, mm, eps)
+    nb.leapfrog(x, v, a, mm, law, dt, 100)
+    # FP64 trajectory from the same state
+    x64, v64 = dev(pos), dev(vel)
+    a64, _ = nb.forces(x64, mm, law64)
+    nb.leapfrog(x64, v64, a64, mm, law64, dt, 100)
+    drift32 = abs(energy(nb, x, v, mm, eps) - E0) / abs(E0)
+    drift64 = abs(energy(nb, x64, v64, mm, eps) - E0) / abs(E0)
+    assert drift64 < 1e-4
+    assert abs(drift32 - drift64) <= 1e-6 + 0.05 * drift64, (drift32, drift64)
+    # t = 100: oracle at the GPU's own positions, 4096 sampled rows
+    rows = np.sort(np.random.default_rng(22).choice(n, 4096, replace=False))
+    xr = W.round_to_f32(host(x))
+    a100_ref, _ = oracle.gravity(xr, W.round_to_f32(m), eps=eps, ilist=rows)
+    e100 = rel_rows(host(a)[rows], a100_ref)
+    assert np.median(e100) <= 1e-5 and e100.max() <= 1e-3, (np.median(e100), e100.max())
+
+
+def _md_target(nb):
+    s = W.md_system(8192, 3)
+    t = W.perturbed(s, 33)
+    return s, t
+
+
+def test_config3_md_8192_forward_and_force_matching_gradient(nb):
+    s, t = _md_target(nb)
+    law = nb.ljc_linear("fp32_fp64acc")
+    law64 = nb.ljc_linear("fp64")
+    x = dev(s.pos)
+    f, u = nb.forces(x, dev(s.params()), law)
+    f_ref, u_ref = oracle.ljc_linear(W.round_to_f32(s.pos), s.q, s.sigma, s.epsilon)
+    e = rel_rows(host(f), f_ref)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
+    # backward of L = ||F - F_target||^2 through the typed autograd Function
+    ftarget, _ = nb.forces(x, dev(t.params()), law64)
+    pos = x.clone().requires_grad_(True)
+    q = dev(s.q).requires_grad_(True)
+    st = dev(s.sigma_t).requires_grad_(True)
+    et = dev(s.eps_t).requires_grad_(True)
+    types = torch.tensor(s.types, device="cuda")
+    F = nb.LJCTypedForcesFn.apply(pos, q, st, et, types, law)
+    L = ((F - ftarget) ** 2).sum()
+    L.backward()
+    g = 2.0 * (host(F) - host(ftarget))
+    rp, rq, rs, re = oracle.ljc_adjoint(W.round_to_f32(s.pos), s.q, s.sigma, s.epsilon, g)
+    ep = rel_rows(host(pos.grad), rp)
+    assert np.median(ep) <= 1e-5 and ep.max() <= 1e-3, (np.median(ep), ep.max())
+    eq = np.abs(host(q.grad) - rq) / np.abs(rq).max()
+    assert np.median(eq) <= 1e-5 and eq.max() <= 1e-3
+    for k in range(4):
+        sel = s.types == k
+        assert abs(host(st.grad)[k] - rs[sel].sum()) <= 1e-5 * np.abs(rs[sel]).sum()
+        assert abs(host(et.grad)[k] - re[sel].sum()) <= 1e-5 * np.abs(re[sel]).sum()
+
+
+def test_config3_gradient_finite_differences_fp64(nb):
+    # FD of L(theta) on the FP64 GPU path against the FP64 GPU adjoint
+    s, t = _md_target(nb)
+    law = nb.ljc_linear("fp64")
+    x = dev(s.pos)
+    types = torch.tensor(s.types, device="cuda")
+    ftarget, _ = nb.forces(x, dev(t.params()), law)
+
+    def L(pos, q, st, et):
+        par = torch.stack([q, st[types.long()], et[types.long()]], 1)
+        f, _ = nb.forces(pos, par, law, potential=False)
+        return float(((f - ftarget) ** 2).sum())
+
+    pos = x.clone().requires_grad_(True)
+    q = dev(s.q).requires_grad_(True)
+    st = dev(s.sigma_t).requires_grad_(True)
+    et = dev(s.eps_t).requires_grad_(True)
+    F = nb.LJCTypedForcesFn.apply(pos, q, st, et, types, law)
+    ((F - ftarget) ** 2).sum().backward()
+    rng = np.random.default_rng(3)
+    base = (x, dev(s.q), dev(s.sigma_t), dev(s.eps_t))
+    grads = (pos.grad, q.grad, st.grad, et.grad)
+    checks = [(0, (int(i), int(c))) for i, c in zip(rng.integers(0, 8192, 6), rng.integers(0, 3, 6))]
+    checks += [(1, (int(i),)) for i in rng.integers(0, 8192, 4)]
+    checks += [(2, (k,)) for k in range(4)] + [(3, (k,)) for k in range(4)]
+    for which, idx in checks:
+        h = 1e-5 * max(1.0, abs(float(base[which][idx])))
+        plus = [b.clone() for b in base]
+        minus = [b.clone() for b in base]
+        plus[which][idx] += h
+        minus[which][idx] -= h
+        fd = (L(*plus) - L(*minus)) / (2 * h)
+        an = float(grads[which][idx])
+        assert abs(fd - an) <= 1e-5 * max(abs(an), 1e-3 * float(grads[which].abs().max())), (which, idx, fd, an)
+
+
+def test_config3_euler_identities_on_gpu(nb):
+    s, _ = _md_target(nb)
+    law = nb.ljc_linear("fp64")
+    x = dev(s.pos)
+    g = W.unit_cotangent(s.n, 57)
+    gp, gpar, _ = nb.forces_backward(x, dev(s.params()), dev(g), law)
+    p0 = s.params()
+    pc, plj = p0.copy(), p0.copy()
+    pc[:, 2] = 0.0
+    plj[:, 0] = 0.0
+    fc, _ = nb.forces(x, dev(pc), law)
+    flj, _ = nb.forces(x, dev(plj), law)
+    gfc, gflj = float((g * host(fc)).sum()), float((g * host(flj)).sum())
+    gp, gpar = host(gp), host(gpar)
+    scale = np.abs(g * host(fc)).sum() + np.abs(g * host(flj)).sum()
+    assert abs((s.q * gpar[:, 0]).sum() - 2 * gfc) <= 1e-10 * scale
+    assert abs((s.epsilon * gpar[:, 2]).sum() - gflj) <= 1e-10 * scale
+    assert abs((s.sigma * gpar[:, 1]).sum() + (s.pos * gp).sum() + gflj + 3 * gfc) <= 1e-9 * scale
+
+
+def test_config4_full_ensemble(nb, full_ensemble):
+    off, pos, par, systems = full_ensemble
+    S = len(systems)
+    x, p = dev(pos), dev(par)
+    law = nb.ljc_linear("fp32_kahan")
+    law64 = nb.ljc_linear("fp64")
+    fb, ub = nb.forces_batched(off, x, p, law)
+    fb, ub = host(fb), host(ub)
+    meds = []
+    for s in range(S):
+        a, b = off[s], off[s + 1]
+        f64, u64 = nb.forces(x[a:b], p[a:b], law64)
+        e = rel_rows(fb[a:b], host(f64))
+        meds.append(np.median(e))
+        assert e.max() <= 1e-3, (s, e.max())
+    assert max(meds) <= 1e-5, max(meds)
+    # the oracle on 8 sampled systems, 64 sampled rows each
+    rng = np.random.default_rng(44)
+    for s in rng.choice(S, 8, replace=False):
+        a, b = off[s], off[s + 1]
+        sy = systems[s]
+        rows = np.sort(rng.choice(b - a, min(64, b - a), replace=False))
+        fr, _ = oracle.ljc_linear(W.round_to_f32(sy.pos), sy.q, sy.sigma, sy.epsilon, ilist=rows)
+        e = rel_rows(fb[a:b][rows], fr)
+        assert np.median(e) <= 1e-5 and e.max() <= 1e-3
+
+
+def test_config5_plummer_1m(nb):
+    n, eps = 1 << 20, 0.005
+    pos, _, m = W.plummer(n, 5)
+    x, mm = dev(pos), dev(m)
+    try:
+        nb.set_config(nb.API_FORCES, *BENCH_CFG)
+        f32, p32 = nb.forces(x, mm, nb.gravity("fp32_kahan", softening=eps))
+    finally:
+        nb.clear_config(nb.API_FORCES)
+    f64, p64 = nb.forces(x, mm, nb.gravity("fp64", softening=eps))
+    f32, f64, p32, p64 = host(f32), host(f64), host(p32), host(p64)
+    e = rel_rows(f32, f64)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
+    ep = np.abs(p32 - p64) / np.abs(p64)
+    assert np.median(ep) <= 1e-5 and ep.max() <= 1e-3
+    rows = np.sort(np.random.default_rng(55).choice(n, 512, replace=False))
+    a_ref, phi_ref = oracle.gravity(pos, m, eps=eps, ilist=rows)
+    assert rel_rows(f64[rows], a_ref).max() <= 1e-12
+    assert (np.abs(p64[rows] - phi_ref) / np.abs(phi_ref)).max() <= 1e-12
+    a32_ref, _ = oracle.gravity(W.round_to_f32(pos), W.round_to_f32(m), eps=eps, ilist=rows)
+    e32 = rel_rows(f32[rows], a32_ref)
+    assert np.median(e32) <= 1e-5 and e32.max() <= 1e-3
+
+
+def test_config5_hvp_262144(nb):
+    n, eps = 262144, 0.005
+    pos, _, m = W.plummer(n, 6)
+    g = W.unit_cotangent(n, 56)
+    x, mm, gg = dev(pos), dev(m), dev(g)
+    h32, _, _ = nb.forces_backward(x, mm, gg, nb.gravity("fp32_fp64acc", softening=eps))
+    h64, _, _ = nb.forces_backward(x, mm, gg, nb.gravity("fp64", softening=eps))
+    h32, h64 = host(h32), host(h64)
+    e = rel_rows(h32, h64)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
+    rows = np.sort(np.random.default_rng(56).choice(n, 256, replace=False))
+    ref = oracle.gravity_adjoint(pos, m, g, eps=eps, ilist=rows)
+    assert rel_rows(h64[rows], ref).max() <= 1e-11
+    ref32 = oracle.gravity_adjoint(W.round_to_f32(pos), W.round_to_f32(m), W.round_to_f32(g),
+                                   eps=eps, ilist=rows)
+    e32 = rel_rows(h32[rows], ref32)
+    assert np.median(e32) <= 1e-5 and e32.max() <= 1e-3
