@@ -102,19 +102,24 @@ enum nbody_api {
 };
 
 /* Launch configuration of the all-pairs kernels (see nbody_set_config).
- *  block      threads per workgroup, a multiple of 64 in [64, 1024];
+ *  block      threads per workgroup, a multiple of 64 in [64, 256];
  *  i_per_lane i-particles held in registers by each lane: 1, 2, 4 or 8
  *             (the i-unrolling of Section 3.3, "4x4" kernels);
  *  j_tile     j-particles per FP32 partial sum before it is folded into the
  *             compensated running sum: a multiple of 64;
  *  j_split    number of disjoint j ranges evaluated by separate waves and
  *             added afterwards in a fixed order (the i-replication of
- *             Section 3.4), 1..64.  Ignored by the batched entry point. */
+ *             Section 3.4), 1..64.  Ignored by the batched entry point;
+ *  j_stage    how j records reach the arithmetic: 0 = wave-uniform scalar
+ *             loads into SGPRs, 1 = a wave-private LDS slot read back as
+ *             broadcasts into VGPRs (so the pair arithmetic has only VGPR
+ *             operands). */
 typedef struct nbody_config {
     int32_t block;
     int32_t i_per_lane;
     int32_t j_tile;
     int32_t j_split;
+    int32_t j_stage;
 } nbody_config;
 
 /* Forces and potential of one system (Section 2 all-pairs loop; Eq. 1 or

@@ -41,7 +41,8 @@ class NBodyLaw(ctypes.Structure):
 
 class NBodyConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("i_per_lane", ctypes.c_int32),
-                ("j_tile", ctypes.c_int32), ("j_split", ctypes.c_int32)]
+                ("j_tile", ctypes.c_int32), ("j_split", ctypes.c_int32),
+                ("j_stage", ctypes.c_int32)]
 
 
 class NBodyError(RuntimeError):

@@ -32,7 +32,7 @@ def hipcc() -> str:
 
 def common_flags():
     return ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
-            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-cuda-compat",
             "-I" + INCLUDE, "-I" + CSRC]
 
 

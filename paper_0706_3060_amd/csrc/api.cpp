@@ -40,7 +40,7 @@ int hip_fail(hipError_t e, const char *where)
     return fail(NBODY_EHIP, "%s: %s", where, hipGetErrorString(e));
 }
 
-constexpr int64_t kMaxPartialRows = int64_t(1) << 22;   // split partial buffer budget (rows)
+constexpr int64_t kMaxPartialRows = int64_t(1) << 23;   // split partial buffer budget (rows, 256 MiB)
 constexpr int kMaxSplit = 64;
 constexpr int kTargetWaves = 4096;                      // 4 resident waves per SIMD on 256 CUs
 
@@ -95,7 +95,7 @@ int validate_law(const nbody_law *law, bool backward)
 
 // ------------------------------------------------------------ configuration
 struct Cfg {
-    int block = 256, ipl = 1, j_tile = 256, j_split = 1;
+    int block = 256, ipl = 1, j_tile = 256, j_split = 1, j_stage = 0;
 };
 
 std::mutex g_mu;
@@ -123,12 +123,64 @@ bool ipl_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 Cfg sanitize(Cfg c, int api, int prec, int64_t npad)
 {
     c.ipl = std::min(c.ipl, max_ipl(api, prec));
+    if (c.j_stage == 1) c.ipl = std::min(c.ipl, 4);    // LDS staging: up to 4 rows per lane
     c.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
     if (api == NBODY_API_BATCHED) c.j_split = 1;
     return c;
 }
 
-Cfg heuristic(int api, int prec, int64_t n, int64_t S)
+int device_cus();
+
+// Resident waves of the all-pairs kernel for this configuration (whole chip).
+int64_t resident_waves(int law, int prec, int ipl, bool pot, int js, int block)
+{
+    const int bpc = forces_blocks_per_cu(law, prec, ipl, pot ? 1 : 0, js, block);
+    return bpc > 0 ? (int64_t)bpc * (block / 64) * device_cus() : 0;
+}
+
+// Modelled time of one evaluation with a j split of s (seconds, up to a common
+// scale): waves run in rounds of `resident` concurrent waves, each doing 1/s of
+// the j range, plus the fixed-order reduction of the split partials.
+double split_cost(int64_t n, int64_t waves, int64_t resident, int s, double pairs_per_s)
+{
+    const double w = (double)waves * s;
+    const double R = (double)std::max<int64_t>(resident, 1);
+    const double fill = w >= R ? std::ceil(w / R) * R / w : R / w;
+    const double t_compute = (double)n * (double)n / pairs_per_s * fill;
+    const double t_reduce = s > 1 ? 5e-6 + (double)n * s * 32.0 / 4e11 : 0.0;
+    return t_compute + t_reduce;
+}
+
+double nominal_rate(int law, int prec)
+{
+    const bool f32 = is_f32(prec);
+    if (law == NBODY_LAW_GRAVITY) return f32 ? 3.3e12 : 1.4e12;
+    return f32 ? 1.8e12 : 0.6e12;
+}
+
+// splits 1..smax ordered by modelled cost
+std::vector<int> ranked_splits(int law, int prec, int64_t n, int ipl, bool pot, int js, int block,
+                               int smax)
+{
+    const int64_t waves = (n + 64 * ipl - 1) / (64 * ipl);
+    const int64_t R = resident_waves(law, prec, ipl, pot, js, block);
+    std::vector<std::pair<double, int>> c;
+    for (int sp = 1; sp <= smax; ++sp) {
+        double cost;
+        if (R > 0) {
+            cost = split_cost(n, waves, R, sp, nominal_rate(law, prec));
+        } else {   // occupancy unknown: aim at kTargetWaves waves
+            cost = std::abs(std::log((double)(waves * sp) / kTargetWaves)) + 0.01 * sp;
+        }
+        c.push_back({cost, sp});
+    }
+    std::stable_sort(c.begin(), c.end());
+    std::vector<int> out;
+    for (auto &e : c) out.push_back(e.second);
+    return out;
+}
+
+Cfg heuristic(int api, int law, int prec, int64_t n, int64_t S, bool pot)
 {
     Cfg c;
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
@@ -137,21 +189,29 @@ Cfg heuristic(int api, int prec, int64_t n, int64_t S)
         c.block = 256;
         c.j_tile = 256;
         c.j_split = 1;
+        c.j_stage = is_f32(prec) ? 1 : 0;
         (void)S;
         return c;
     }
     if (is_f32(prec)) {
-        c.ipl = n >= (1 << 18) ? 4 : (n >= (1 << 16) ? 2 : 1);
+        c.ipl = 1;
         c.j_tile = 256;
+        c.j_stage = 1;
     } else {
         c.ipl = n >= (1 << 18) ? 2 : 1;
         c.j_tile = 1024;
+        c.j_stage = 0;
     }
-    if (api == NBODY_API_BACKWARD) c.ipl = std::min(c.ipl, 2);
-    const int64_t waves = (n + 64 * c.ipl - 1) / (64 * c.ipl);
-    int split = 1;
-    while (split < kMaxSplit && waves * split < kTargetWaves) split *= 2;
-    c.j_split = split;
+    if (api == NBODY_API_BACKWARD) {
+        c.ipl = std::min(c.ipl, 2);
+        c.j_stage = 0;
+        const int64_t waves = (n + 64 * c.ipl - 1) / (64 * c.ipl);
+        int split = 1;
+        while (split < kMaxSplit && waves * split < kTargetWaves) split *= 2;
+        c.j_split = split;
+        return sanitize(c, api, prec, npad);
+    }
+    c.j_split = ranked_splits(law, prec, n, c.ipl, pot, c.j_stage, c.block, max_split(npad))[0];
     return sanitize(c, api, prec, npad);
 }
 
@@ -166,7 +226,7 @@ Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot)
         it = g_tuned.find(TuneKey(NBODY_API_FORCES, law->kind, law->precision, pot ? 1 : 0,
                                   size_bucket(n), size_bucket(S)));
     if (it != g_tuned.end()) return sanitize(it->second.first, api, law->precision, npad);
-    return heuristic(api, law->precision, n, S);
+    return heuristic(api, law->kind, law->precision, n, S, pot);
 }
 
 // ------------------------------------------------------------ measurement
@@ -317,6 +377,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
     f.j_split = c.j_split;
     f.split_len = round_up((npad + c.j_split - 1) / c.j_split, 64);
     f.j_tile = c.j_tile;
+    f.j_stage = c.j_stage;
     f.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
     f.rec = base + lay.rec_off;
     f.partial = (double *)(base + lay.part_off);
@@ -334,7 +395,7 @@ bool cfg_valid(const nbody_config *c)
 {
     return c && c->block >= 64 && c->block <= 256 && c->block % 64 == 0 && ipl_ok(c->i_per_lane) &&
            c->j_tile >= 64 && c->j_tile % 64 == 0 && c->j_tile <= (1 << 20) && c->j_split >= 1 &&
-           c->j_split <= kMaxSplit;
+           c->j_split <= kMaxSplit && (c->j_stage == 0 || c->j_stage == 1);
 }
 
 Cfg from_abi(const nbody_config *c)
@@ -344,6 +405,7 @@ Cfg from_abi(const nbody_config *c)
     r.ipl = c->i_per_lane;
     r.j_tile = c->j_tile;
     r.j_split = c->j_split;
+    r.j_stage = c->j_stage;
     return r;
 }
 
@@ -353,6 +415,7 @@ void to_abi(const Cfg &c, nbody_config *o)
     o->i_per_lane = c.ipl;
     o->j_tile = c.j_tile;
     o->j_split = c.j_split;
+    o->j_stage = c.j_stage;
 }
 
 // ------------------------------------------------------------ batched plan
@@ -446,7 +509,9 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     b.ipl = c.ipl;
     b.pot = out_pot != nullptr;
     b.block = c.block;
-    const int per_cu = std::max(1, batched_max_blocks_per_cu(b.law, b.prec, b.ipl, b.pot, b.block));
+    b.j_stage = c.j_stage;
+    const int per_cu =
+        std::max(1, batched_max_blocks_per_cu(b.law, b.prec, b.ipl, b.pot, b.j_stage, b.block));
     const int64_t n_units = (int64_t)plan.units.size() / 2;
     const int64_t waves_needed = n_units;
     const int64_t blocks_needed = (waves_needed + c.block / 64 - 1) / (c.block / 64);
@@ -533,41 +598,47 @@ int batched_impl(const int64_t *offsets, int64_t S, const double *pos, const dou
 }
 
 // candidate list for the measured search
-std::vector<Cfg> candidates(int api, int prec, int64_t n)
+std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
 {
     std::vector<Cfg> out;
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
-    const int ipls[] = {1, 2, 4, 8};
-    const int blocks[] = {64, 256};
     if (api == NBODY_API_BATCHED) {
-        for (int ipl : {1, 2, 4})
-            for (int b : {64, 128, 256})
-                for (int jt : {64, 256}) {
-                    Cfg c;
-                    c.ipl = ipl;
-                    c.block = b;
-                    c.j_tile = jt;
-                    c.j_split = 1;
-                    out.push_back(c);
-                }
+        for (int js : {0, 1})
+            for (int ipl : {1, 2})
+                for (int b : {64, 128, 256})
+                    for (int jt : {64, 256}) {
+                        if (js == 0 && !is_f32(prec) && ipl > 1) continue;
+                        Cfg c;
+                        c.ipl = ipl;
+                        c.block = b;
+                        c.j_tile = jt;
+                        c.j_split = 1;
+                        c.j_stage = js;
+                        out.push_back(c);
+                    }
         return out;
     }
-    for (int ipl : ipls) {
-        if (ipl > max_ipl(api, prec)) continue;
-        const int64_t waves = (n + 64 * ipl - 1) / (64 * ipl);
-        for (int b : blocks)
-            for (int split = 1; split <= max_split(npad); split *= 2) {
-                const int64_t w = waves * split;
-                if (w > 2 * kTargetWaves && split > 1) break;
-                if (w < kTargetWaves / 8 && split < max_split(npad)) continue;
+    for (int js : {0, 1})
+        for (int ipl : {1, 2, 4, 8}) {
+            if (ipl > max_ipl(api, prec) || (js == 1 && ipl > 4)) continue;
+            const int block = 256;
+            std::vector<int> splits = ranked_splits(law, prec, n, ipl, pot, js, block, max_split(npad));
+            std::vector<int> pick;
+            for (int sp : splits) {
+                if ((int)pick.size() >= 3) break;
+                pick.push_back(sp);
+            }
+            if (std::find(pick.begin(), pick.end(), 1) == pick.end()) pick.push_back(1);
+            for (int sp : pick) {
                 Cfg c;
                 c.ipl = ipl;
-                c.block = b;
+                c.block = block;
                 c.j_tile = is_f32(prec) ? 256 : 1024;
-                c.j_split = split;
+                c.j_split = sp;
+                c.j_stage = js;
                 out.push_back(c);
             }
-    }
+        }
     return out;
 }
 
@@ -782,7 +853,7 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
     double best_ms = 1e300;
     const bool saved_timing = g_timing;
     g_timing = false;
-    for (const Cfg &c : candidates(api, law->precision, ntot)) {
+    for (const Cfg &c : candidates(api, law->kind, law->precision, ntot, out_potential != nullptr)) {
         double ms_min = 1e300;
         for (int rep = 0; rep < 2; ++rep) {
             hipEventRecord(a, s);
@@ -842,9 +913,9 @@ int nbody_tune_save(const char *path)
         fprintf(f,
                 "  {\"api\": %d, \"law\": %d, \"precision\": %d, \"potential\": %d, \"n_bucket\": %d, "
                 "\"s_bucket\": %d, \"block\": %d, \"i_per_lane\": %d, \"j_tile\": %d, \"j_split\": %d, "
-                "\"ms\": %.6f}%s\n",
+                "\"j_stage\": %d, \"ms\": %.6f}%s\n",
                 std::get<0>(t), std::get<1>(t), std::get<2>(t), std::get<3>(t), std::get<4>(t),
-                std::get<5>(t), c.block, c.ipl, c.j_tile, c.j_split, kv.second.second,
+                std::get<5>(t), c.block, c.ipl, c.j_tile, c.j_split, c.j_stage, kv.second.second,
                 (++k < g_tuned.size()) ? "," : "");
     }
     fprintf(f, "]}\n");
@@ -865,14 +936,14 @@ int nbody_tune_load(const char *path)
     int loaded = 0;
     size_t pos = 0;
     while ((pos = txt.find("{\"api\"", pos)) != std::string::npos) {
-        int api, law, prec, pot, nb, sb, block, ipl, jt, js;
+        int api, law, prec, pot, nb, sb, block, ipl, jt, js, jst;
         double ms;
         if (sscanf(txt.c_str() + pos,
                    "{\"api\": %d, \"law\": %d, \"precision\": %d, \"potential\": %d, \"n_bucket\": %d, "
                    "\"s_bucket\": %d, \"block\": %d, \"i_per_lane\": %d, \"j_tile\": %d, \"j_split\": %d, "
-                   "\"ms\": %lf}",
-                   &api, &law, &prec, &pot, &nb, &sb, &block, &ipl, &jt, &js, &ms) == 11) {
-            nbody_config cc{block, ipl, jt, js};
+                   "\"j_stage\": %d, \"ms\": %lf}",
+                   &api, &law, &prec, &pot, &nb, &sb, &block, &ipl, &jt, &js, &jst, &ms) == 12) {
+            nbody_config cc{block, ipl, jt, js, jst};
             if (cfg_valid(&cc) && api >= 0 && api <= 3) {
                 std::lock_guard<std::mutex> lk(g_mu);
                 g_tuned[TuneKey(api, law, prec, pot, nb, sb)] = {from_abi(&cc), ms};

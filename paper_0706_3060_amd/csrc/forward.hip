@@ -10,58 +10,12 @@
 //                 tile; FP32 tile partials are folded into FP64 / Kahan sums;
 //   reduce_split  when the j range is split over several waves, the split
 //                 partials are added in a fixed order (deterministic).
-#include "device.h"
+#include "allpairs.h"
 #include "kernels.h"
 
 namespace nbk {
 
 // ------------------------------------------------------------------ pack ----
-template <typename T>
-__device__ __forceinline__ void store_rec(GravRec<T> *rec, int64_t i, double x, double y, double z,
-                                          const double *par, double)
-{
-    GravRec<T> r;
-    r.x = (T)x;
-    r.y = (T)y;
-    r.z = (T)z;
-    r.m = (T)par[0];
-    rec[i] = r;
-}
-
-template <typename T>
-__device__ __forceinline__ void store_rec(LjcRec<T> *rec, int64_t i, double x, double y, double z,
-                                          const double *par, double qscale)
-{
-    LjcRec<T> r;
-    r.x = (T)x;
-    r.y = (T)y;
-    r.z = (T)z;
-    r.qs = (T)(par[0] * qscale);
-    r.sh = (T)(0.5 * par[1]);
-    r.se = (T)__builtin_sqrt(par[2]);
-    r.p0 = T(0);
-    r.p1 = T(0);
-    rec[i] = r;
-}
-
-template <typename T>
-__device__ __forceinline__ void store_pad(GravRec<T> *rec, int64_t i)
-{
-    GravRec<T> r;
-    r.x = r.y = r.z = (T)kPadCoord;
-    r.m = T(0);
-    rec[i] = r;
-}
-
-template <typename T>
-__device__ __forceinline__ void store_pad(LjcRec<T> *rec, int64_t i)
-{
-    LjcRec<T> r;
-    r.x = r.y = r.z = (T)kPadCoord;
-    r.qs = r.sh = r.se = r.p0 = r.p1 = T(0);
-    rec[i] = r;
-}
-
 template <typename R, int P>
 __global__ __launch_bounds__(256) void k_pack(PackLaunch a)
 {
@@ -125,76 +79,8 @@ __device__ __forceinline__ void finish_row(const Epilogue &e, int64_t r, double 
     if (pot && e.out_pot) e.out_pot[r] = e.pscale * v3;
 }
 
-// ------------------------------------------------------- per-law i / j I/O ----
-template <typename T>
-__device__ __forceinline__ void load_i(const GravRec<T> *rec, int64_t p, GravI<T> &s)
-{
-    const GravRec<T> r = rec[p];
-    s.x = r.x;
-    s.y = r.y;
-    s.z = r.z;
-}
-
-template <typename T>
-__device__ __forceinline__ void load_i(const LjcRec<T> *rec, int64_t p, LjcI<T> &s)
-{
-    const LjcRec<T> r = rec[p];
-    s.x = r.x;
-    s.y = r.y;
-    s.z = r.z;
-    s.qs = r.qs;
-    s.sh = r.sh;
-    s.se = r.se;
-}
-
-template <typename T> struct IStateOf;
-template <typename T> struct IStateOf<GravRec<T>> { using type = GravI<T>; };
-template <typename T> struct IStateOf<LjcRec<T>> { using type = LjcI<T>; };
-
-template <bool MASK, bool POT, typename T>
-__device__ __forceinline__ void pair(const GravI<T> &i, const GravRec<T> &j, T eps2, bool self,
-                                     T (&p)[4])
-{
-    grav_pair<MASK, POT>(i, j.x, j.y, j.z, j.m, eps2, self, p);
-}
-
-template <bool MASK, bool POT, typename T>
-__device__ __forceinline__ void pair(const LjcI<T> &i, const LjcRec<T> &j, T, bool self, T (&p)[4])
-{
-    ljc_pair<MASK, POT>(i, j.x, j.y, j.z, j.qs, j.sh, j.se, self, p);
-}
-
-// The j loop over one tile [t0, t1) (a multiple of 8 records).  `rec` is a
-// restrict-qualified read-only pointer and j is wave-uniform, so each record
-// load is a scalar load shared by the 64 lanes.
-template <bool MASK, bool POT, int I, typename R, typename IS, typename T>
-__device__ __forceinline__ void tile_loop(const R *__restrict__ rec, int64_t t0, int64_t t1,
-                                          const IS (&is)[I], const int64_t (&pid)[I], T eps2,
-                                          T (&p)[I][4])
-{
-    constexpr int U = 8;
-    R cur[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) cur[u] = rec[t0 + u];
-    for (int64_t j = t0; j < t1; j += U) {
-        // prefetch the next group (the last group re-reads itself: always in bounds)
-        const int64_t jn = (j + U < t1) ? j + U : j;
-        R nxt[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) nxt[u] = rec[jn + u];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-            for (int k = 0; k < I; ++k)
-                pair<MASK, POT>(is[k], cur[u], eps2, MASK && (pid[k] == j + u), p[k]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
-    }
-}
-
 // ------------------------------------------------------------- all pairs ----
-template <int LAW, int PREC, int I, bool POT>
+template <int LAW, int PREC, int I, bool POT, int JS>
 __global__ __launch_bounds__(256) void k_forces(
     const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec, int64_t npad,
     int64_t nrows, const int64_t *__restrict__ rows, int64_t split_len, int j_tile,
@@ -230,24 +116,9 @@ __global__ __launch_bounds__(256) void k_forces(
 #pragma unroll
     for (int k = 0; k < I; ++k) p[k][3] = T(0);
 
-    for (int64_t t0 = jb; t0 < je; t0 += j_tile) {
-        const int64_t t1 = (t0 + j_tile < je) ? t0 + j_tile : je;
-        bool near = false;
-#pragma unroll
-        for (int k = 0; k < I; ++k) near |= (pid[k] >= t0) & (pid[k] < t1);
-#pragma unroll
-        for (int k = 0; k < I; ++k)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[k][c].begin(p[k][c]);
-        if (wave_any(near))
-            tile_loop<true, POT, I>(rec, t0, t1, is, pid, (T)eps2, p);
-        else
-            tile_loop<false, POT, I>(rec, t0, t1, is, pid, (T)eps2, p);
-#pragma unroll
-        for (int k = 0; k < I; ++k)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[k][c].fold(p[k][c]);
-    }
+    __shared__ R lds_j[JS ? 4 : 1][2][kWave];
+    j_range<JS, POT, PREC, I>(rec, jb, je, j_tile, is, pid, eps2, acc, p,
+                              lds_j[JS ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0]);
 
 #pragma unroll
     for (int k = 0; k < I; ++k) {
@@ -266,15 +137,22 @@ __global__ __launch_bounds__(256) void k_forces(
         }
     }
 }
-
 template <int LAW, int PREC, int I, bool POT>
 static void launch_one(const FwdLaunch &f, dim3 grid, hipStream_t s)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename RecOf<T, LAW>::type;
-    hipLaunchKernelGGL((k_forces<LAW, PREC, I, POT>), grid, dim3(f.block), 0, s, (const R *)f.rec,
-                       f.npad, f.nrows, f.rows, f.split_len, f.j_tile, (T)f.eps2,
-                       f.j_split > 1 ? f.partial : nullptr, f.epi);
+    if constexpr (I <= 4) {     // LDS staging is instantiated up to 4 rows per lane
+        if (f.j_stage == 1) {
+            hipLaunchKernelGGL((k_forces<LAW, PREC, I, POT, 1>), grid, dim3(f.block), 0, s,
+                               (const R *)f.rec, f.npad, f.nrows, f.rows, f.split_len, f.j_tile,
+                               (T)f.eps2, f.j_split > 1 ? f.partial : nullptr, f.epi);
+            return;
+        }
+    }
+        hipLaunchKernelGGL((k_forces<LAW, PREC, I, POT, 0>), grid, dim3(f.block), 0, s,
+                           (const R *)f.rec, f.npad, f.nrows, f.rows, f.split_len, f.j_tile,
+                           (T)f.eps2, f.j_split > 1 ? f.partial : nullptr, f.epi);
 }
 
 template <int LAW, int PREC, bool POT>
@@ -299,6 +177,54 @@ static bool dispatch_prec(const FwdLaunch &f, dim3 grid, hipStream_t s)
     case P_PLAIN: return dispatch_ipl<LAW, P_PLAIN, POT>(f, grid, s);
     default: return false;
     }
+}
+
+// Resident workgroups per CU of the all-pairs kernel a launch would use
+// (from the compiled register and LDS footprint), 0 if unknown.
+template <int LAW, int PREC, int I, bool POT>
+static const void *forces_ptr(int js)
+{
+    if constexpr (I <= 4) {
+        if (js == 1) return (const void *)&k_forces<LAW, PREC, I, POT, 1>;
+    }
+    return (const void *)&k_forces<LAW, PREC, I, POT, 0>;
+}
+
+template <int LAW, int PREC, bool POT>
+static const void *forces_ptr_ipl(int ipl, int js)
+{
+    switch (ipl) {
+    case 1: return forces_ptr<LAW, PREC, 1, POT>(js);
+    case 2: return forces_ptr<LAW, PREC, 2, POT>(js);
+    case 4: return forces_ptr<LAW, PREC, 4, POT>(js);
+    case 8: return forces_ptr<LAW, PREC, 8, POT>(js);
+    default: return nullptr;
+    }
+}
+
+template <int LAW, bool POT>
+static const void *forces_ptr_prec(int prec, int ipl, int js)
+{
+    switch (prec) {
+    case P_FP64: return forces_ptr_ipl<LAW, P_FP64, POT>(ipl, js);
+    case P_KAHAN: return forces_ptr_ipl<LAW, P_KAHAN, POT>(ipl, js);
+    case P_FP64ACC: return forces_ptr_ipl<LAW, P_FP64ACC, POT>(ipl, js);
+    case P_PLAIN: return forces_ptr_ipl<LAW, P_PLAIN, POT>(ipl, js);
+    default: return nullptr;
+    }
+}
+
+int forces_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block)
+{
+    const void *fn = law == GRAVITY
+                         ? (pot ? forces_ptr_prec<GRAVITY, true>(prec, ipl, js)
+                                : forces_ptr_prec<GRAVITY, false>(prec, ipl, js))
+                         : (pot ? forces_ptr_prec<LJC, true>(prec, ipl, js)
+                                : forces_ptr_prec<LJC, false>(prec, ipl, js));
+    if (!fn) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, 0) != hipSuccess) return 0;
+    return nb;
 }
 
 hipError_t launch_forces(const FwdLaunch &f, hipStream_t s)

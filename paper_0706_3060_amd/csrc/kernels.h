@@ -29,6 +29,7 @@ struct FwdLaunch {
     int64_t split_len;           // j range per split (multiple of 64)
     int j_split;
     int j_tile;
+    int j_stage;                 // 0: j records through SGPRs (scalar loads); 1: through LDS into VGPRs
     double eps2;                 // gravity softening squared
     const void *rec;             // packed records
     double *partial;             // [j_split][nrows][4] when j_split > 1
@@ -54,6 +55,7 @@ struct PackLaunch {
 hipError_t launch_pack(const PackLaunch &p, hipStream_t s);
 hipError_t launch_forces(const FwdLaunch &f, hipStream_t s);
 hipError_t launch_reduce_split(const FwdLaunch &f, hipStream_t s);
+int forces_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block);
 
 // ---- batched (one persistent launch over (system, row-block) work units) ----
 struct BatchLaunch {
@@ -67,6 +69,7 @@ struct BatchLaunch {
     int64_t n_systems;
     int64_t n_total, npad_total;
     int j_tile;
+    int j_stage;                 // as FwdLaunch::j_stage
     double eps2;
     const void *rec;
     int *ticket;                 // zeroed by launch_batched before the kernel
@@ -82,7 +85,7 @@ struct BatchPackLaunch {
 };
 hipError_t launch_pack_batched(const BatchPackLaunch &p, hipStream_t s);
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t s);
-int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int block);
+int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block);
 
 // ---- adjoint ----
 struct AdjLaunch {

@@ -220,8 +220,8 @@ def leapfrog(pos, vel, acc, params, law: Law, dt: float, nsteps: int, inv_mass=N
 
 
 # ------------------------------------------------------------- tuning etc.
-def set_config(api, block=256, i_per_lane=1, j_tile=256, j_split=1):
-    cfg = N.NBodyConfig(block, i_per_lane, j_tile, j_split)
+def set_config(api, block=256, i_per_lane=1, j_tile=256, j_split=1, j_stage=0):
+    cfg = N.NBodyConfig(block, i_per_lane, j_tile, j_split, j_stage)
     N.check(N.lib().nbody_set_config(api, ctypes.byref(cfg)))
 
 
@@ -233,7 +233,8 @@ def get_config(api, n, law: Law, n_systems=1):
     cfg = N.NBodyConfig()
     N.check(N.lib().nbody_get_config(api, int(n), int(n_systems), ctypes.byref(law.c()),
                                      ctypes.byref(cfg)))
-    return dict(block=cfg.block, i_per_lane=cfg.i_per_lane, j_tile=cfg.j_tile, j_split=cfg.j_split)
+    return dict(block=cfg.block, i_per_lane=cfg.i_per_lane, j_tile=cfg.j_tile, j_split=cfg.j_split,
+                j_stage=cfg.j_stage)
 
 
 def autotune(pos, params, law: Law, offsets=None, potential=True):
@@ -260,7 +261,7 @@ def autotune(pos, params, law: Law, offsets=None, potential=True):
                                        _ptr(p), _ptr(ws), ws.numel(), _stream(pos.device),
                                        ctypes.byref(best), ctypes.byref(ms)))
     return (dict(block=best.block, i_per_lane=best.i_per_lane, j_tile=best.j_tile,
-                 j_split=best.j_split), ms.value)
+                 j_split=best.j_split, j_stage=best.j_stage), ms.value)
 
 
 def tune_save(path):

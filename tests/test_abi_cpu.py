@@ -1,0 +1,184 @@
+"""The C ABI boundary on a machine without a GPU.
+
+* libnbody.so loads (after torch, so it binds to torch's HIP runtime) and
+  exports every function include/nbody.h declares.
+* Host-side validation returns the documented error codes before any work is
+  enqueued (these calls return before any HIP call is made).
+* nbody_workspace_bytes / nbody_flops_per_pair / nbody_version are pure host
+  functions.
+No kernel is launched here.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_0706_3060_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_0706_3060_amd import build
+        build.build(verbose=False)
+    _native.lib()
+    return _native
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "return")))
+
+
+def test_header_declares_the_boundary():
+    fns = declared_functions()
+    for name in ("nbody_forces", "nbody_forces_batched", "nbody_forces_backward", "leapfrog_step",
+                 "nbody_workspace_bytes", "nbody_last_error"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol(N):
+    lib = N.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(N.EXPORTED)
+
+
+def test_single_hip_runtime(N):
+    maps = [l.split()[-1] for l in open("/proc/self/maps") if "libamdhip64" in l]
+    assert len(set(maps)) == 1, set(maps)
+    assert "torch" in maps[0]
+
+
+def law(N, kind=0, prec=2, G=1.0, eps=0.01, k=332.0637, D=4.0):
+    return N.NBodyLaw(kind, prec, G, eps, k, D)
+
+
+def test_workspace_bytes(N):
+    lib = N.lib()
+    g = law(N)
+    a = lib.nbody_workspace_bytes(0, 1 << 20, 1, ctypes.byref(g))
+    assert a >= (1 << 20) * 16            # FP32 gravity records alone
+    assert lib.nbody_workspace_bytes(0, 0, 1, ctypes.byref(g)) > 0
+    assert lib.nbody_workspace_bytes(0, -1, 1, ctypes.byref(g)) == 0
+    assert lib.nbody_workspace_bytes(9, 100, 1, ctypes.byref(g)) == 0
+    assert lib.nbody_workspace_bytes(0, 100, 1, None) == 0
+    bad = law(N, kind=7)
+    assert lib.nbody_workspace_bytes(0, 100, 1, ctypes.byref(bad)) == 0
+    f64 = law(N, prec=0)
+    assert lib.nbody_workspace_bytes(0, 4096, 1, ctypes.byref(f64)) > \
+        lib.nbody_workspace_bytes(0, 4096, 1, ctypes.byref(g)) - 4096 * 16
+    assert lib.nbody_workspace_bytes(1, 10000, 50, ctypes.byref(law(N, kind=1))) > 10000 * 32
+    assert lib.nbody_workspace_bytes(2, 8192, 1, ctypes.byref(law(N, kind=1))) >= 8192 * 48
+    assert lib.nbody_workspace_bytes(3, 8192, 1, ctypes.byref(g)) > \
+        lib.nbody_workspace_bytes(0, 8192, 1, ctypes.byref(g))
+
+
+def fake(addr=0x1000):
+    # a non-NULL pointer value that validation never dereferences
+    return ctypes.c_void_p(addr)
+
+
+def call_forces(N, n, lw, ws_bytes=1 << 30, pos=True, out=True):
+    return N.lib().nbody_forces(fake() if pos else None, fake(), n,
+                                ctypes.byref(lw) if lw is not None else None,
+                                fake() if out else None, None, fake(), ws_bytes, None)
+
+
+def test_forces_validation(N):
+    lib = N.lib()
+    assert call_forces(N, 10, None) == N.NBODY_EINVAL
+    assert b"law is NULL" in lib.nbody_last_error()
+    assert call_forces(N, -1, law(N)) == N.NBODY_EINVAL
+    assert call_forces(N, 10, law(N, kind=5)) == N.NBODY_EINVAL
+    assert call_forces(N, 10, law(N, prec=9)) == N.NBODY_EINVAL
+    assert call_forces(N, 10, law(N, eps=-1.0)) == N.NBODY_EINVAL
+    assert call_forces(N, 10, law(N, eps=float("nan"))) == N.NBODY_EINVAL
+    assert call_forces(N, 10, law(N, kind=1, D=0.0)) == N.NBODY_EINVAL
+    assert call_forces(N, 10, law(N), pos=False) == N.NBODY_EINVAL
+    assert call_forces(N, 10, law(N), out=False) == N.NBODY_EINVAL
+    assert call_forces(N, 10, law(N), ws_bytes=16) == N.NBODY_EWORKSPACE
+    assert b"workspace too small" in lib.nbody_last_error()
+    assert lib.nbody_forces(fake(), fake(), 10, ctypes.byref(law(N)), fake(), None, None, 1 << 30,
+                            None) == N.NBODY_EWORKSPACE
+    # N = 0 is a no-op that needs no pointers at all
+    assert lib.nbody_forces(None, None, 0, ctypes.byref(law(N)), None, None, None, 0, None) == 0
+
+
+def test_batched_validation(N):
+    lib = N.lib()
+    lw = law(N, kind=1)
+
+    def off(vals):
+        a = (ctypes.c_int64 * len(vals))(*vals)
+        return ctypes.cast(a, ctypes.c_void_p), a
+
+    p, keep = off([0, 5, 3])
+    assert lib.nbody_forces_batched(p, 2, fake(), fake(), ctypes.byref(lw), fake(), None, fake(),
+                                    1 << 30, None) == N.NBODY_EINVAL
+    p, keep = off([1, 5])
+    assert lib.nbody_forces_batched(p, 1, fake(), fake(), ctypes.byref(lw), fake(), None, fake(),
+                                    1 << 30, None) == N.NBODY_EINVAL
+    assert lib.nbody_forces_batched(None, 1, fake(), fake(), ctypes.byref(lw), fake(), None, fake(),
+                                    1 << 30, None) == N.NBODY_EINVAL
+    p, keep = off([0, 0, 0])       # only empty systems: nothing to do
+    assert lib.nbody_forces_batched(p, 2, None, None, ctypes.byref(lw), None, None, None, 0,
+                                    None) == 0
+    p, keep = off([0, 100])
+    assert lib.nbody_forces_batched(p, 1, fake(), fake(), ctypes.byref(lw), fake(), None, fake(),
+                                    64, None) == N.NBODY_EWORKSPACE
+
+
+def test_backward_and_leapfrog_validation(N):
+    lib = N.lib()
+    g = law(N)
+    assert lib.nbody_forces_backward(fake(), fake(), 10, ctypes.byref(g), fake(), fake(), fake(),
+                                     None, 0, None, fake(), 1 << 30, None) == N.NBODY_EINVAL
+    plain = law(N, prec=3)
+    assert lib.nbody_forces_backward(fake(), fake(), 10, ctypes.byref(plain), fake(), fake(), None,
+                                     None, 0, None, fake(), 1 << 30, None) == N.NBODY_ENOTSUP
+    lj = law(N, kind=1)
+    assert lib.nbody_forces_backward(fake(), fake(), 10, ctypes.byref(lj), fake(), fake(), fake(),
+                                     fake(), 0, fake(), fake(), 1 << 30, None) == N.NBODY_EINVAL
+    assert lib.leapfrog_step(fake(), fake(), fake(), fake(), None, 10, ctypes.byref(g),
+                             float("inf"), 1, None, fake(), 1 << 30, None) == N.NBODY_EINVAL
+    assert lib.leapfrog_step(fake(), fake(), fake(), fake(), None, 10, ctypes.byref(g), 1e-3, -1,
+                             None, fake(), 1 << 30, None) == N.NBODY_EINVAL
+    # zero steps and no potential requested: nothing to do
+    assert lib.leapfrog_step(fake(), fake(), fake(), fake(), None, 10, ctypes.byref(g), 1e-3, 0,
+                             None, None, 0, None) == 0
+
+
+def test_config_validation(N):
+    lib = N.lib()
+    good = N.NBodyConfig(256, 1, 256, 4, 1)
+    assert lib.nbody_set_config(0, ctypes.byref(good)) == 0
+    assert lib.nbody_set_config(0, None) == 0
+    for bad in [N.NBodyConfig(96, 1, 256, 1, 0), N.NBodyConfig(256, 3, 256, 1, 0),
+                N.NBodyConfig(256, 1, 100, 1, 0), N.NBodyConfig(256, 1, 256, 65, 0),
+                N.NBodyConfig(256, 1, 256, 1, 2), N.NBodyConfig(512, 1, 256, 1, 0)]:
+        assert lib.nbody_set_config(0, ctypes.byref(bad)) == N.NBODY_EINVAL
+    assert lib.nbody_set_config(7, ctypes.byref(good)) == N.NBODY_EINVAL
+
+
+def test_flop_convention_and_version(N):
+    lib = N.lib()
+    # the Appendix convention: 19 flops per gravity interaction, 20 with the potential
+    assert lib.nbody_flops_per_pair(0, 0, 0) == 19
+    assert lib.nbody_flops_per_pair(0, 0, 1) == 20
+    assert lib.nbody_flops_per_pair(0, 1, 0) == 30      # Table 1 lists 30 for LJC
+    assert lib.nbody_flops_per_pair(2, 0, 0) == 41
+    assert b"gfx950" in lib.nbody_version()
+
+
+def test_python_binding_rejects_cpu_tensors(N):
+    import torch
+    from paper_0706_3060_amd import nbody as nb
+    with pytest.raises(ValueError):
+        nb.forces(torch.zeros(4, 3, dtype=torch.float64), torch.ones(4, dtype=torch.float64),
+                  nb.gravity("fp64"))

@@ -113,21 +113,25 @@ def test_fp32_plain_ablation_runs(nb):
 
 
 # ------------------------------------------------------- configurations
-CONFIGS = [(64, 1, 64, 1), (256, 2, 256, 3), (128, 4, 128, 7), (256, 8, 512, 2), (64, 1, 1024, 64)]
+CONFIGS = [(64, 1, 64, 1, 0), (256, 2, 256, 3, 0), (128, 4, 128, 7, 0), (256, 8, 512, 2, 0),
+           (64, 1, 1024, 64, 0), (256, 1, 256, 1, 1), (128, 2, 64, 5, 1), (256, 4, 512, 2, 1),
+           (64, 1, 64, 64, 1)]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)
 def test_launch_configurations_agree(nb, cfg):
-    block, ipl, jt, js = cfg
+    block, ipl, jt, js, stage = cfg
     pos, _, m = W.plummer(3001, 4)
     x, mm = dev(pos), dev(m)
     law64 = nb.gravity("fp64", softening=EPS)
     law32 = nb.gravity("fp32_fp64acc", softening=EPS)
     a_ref, phi_ref = oracle.gravity(pos, m, eps=EPS)
     try:
-        nb.set_config(nb.API_FORCES, block, ipl, jt, js)
+        nb.set_config(nb.API_FORCES, block, ipl, jt, js, stage)
         f64, p64 = nb.forces(x, mm, law64)
         f32, _ = nb.forces(x, mm, law32)
+        s = W.md_system(700, 12, box=30.0)
+        fl, ul = nb.forces(dev(s.pos), dev(s.params()), nb.ljc_linear("fp32_kahan"))
     finally:
         nb.clear_config(nb.API_FORCES)
     assert rel_rows(host(f64), a_ref).max() <= 1e-12
@@ -135,6 +139,25 @@ def test_launch_configurations_agree(nb, cfg):
     a32_ref, _ = oracle.gravity(W.round_to_f32(pos), W.round_to_f32(m), eps=EPS)
     e = rel_rows(host(f32), a32_ref)
     assert np.median(e) <= 1e-5 and e.max() <= 1e-3
+    fl_ref, ul_ref = oracle.ljc_linear(W.round_to_f32(s.pos), s.q, s.sigma, s.epsilon)
+    el = rel_rows(host(fl), fl_ref)
+    assert np.median(el) <= 1e-5 and el.max() <= 1e-3
+    assert np.median(np.abs(host(ul) - ul_ref) / np.abs(ul_ref).max()) <= 1e-5
+
+
+def test_j_stages_agree(nb):
+    # both ways of bringing j records to the arithmetic give the same sums
+    pos, _, m = W.plummer(4000, 9)
+    x, mm = dev(pos), dev(m)
+    law = nb.gravity("fp64", softening=EPS)
+    out = []
+    for stage in (0, 1):
+        try:
+            nb.set_config(nb.API_FORCES, 256, 1, 256, 1, stage)
+            out.append(nb.forces(x, mm, law))
+        finally:
+            nb.clear_config(nb.API_FORCES)
+    assert (out[0][0] - out[1][0]).abs().max().item() <= 1e-14 * out[0][0].abs().max().item()
 
 
 def test_deterministic(nb):
