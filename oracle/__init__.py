@@ -15,6 +15,8 @@ counterpart cites:
   softened potential whose negative gradient is Eq. 1;
 * :func:`ljc_linear` -- Table 1 "LJC (linear)" (Coulomb with dielectric D*r
   plus Lennard-Jones), read potential-consistently;
+* :func:`ljc_constant`, :func:`ljc_sigmoidal` -- Table 1 "LJC (constant)" and
+  "LJC (sigmoidal)" (the latter with caller-given dielectric constants);
 * :func:`leapfrog` -- the force-then-update cycle of Section 1 as
   kick-drift-kick leapfrog;
 * :func:`gravity_adjoint`, :func:`ljc_adjoint` -- derivatives of the two laws
@@ -61,10 +63,13 @@ def _load():
         lib.oracle_threads.restype = I
         lib.oracle_gravity.argtypes = [P, P, I64, D, D, P, I64, I64, I64, P, P, I]
         lib.oracle_ljc_linear.argtypes = [P, P, P, P, I64, D, D, P, I64, I64, I64, P, P, I]
+        lib.oracle_ljc_constant.argtypes = [P, P, P, P, I64, D, D, P, I64, P, P, I]
+        lib.oracle_ljc_sigmoidal.argtypes = [P, P, P, P, I64, D, P, P, I64, P, P, I]
         lib.oracle_leapfrog.argtypes = [I, P, P, P, P, P, I64, D, D, D, ctypes.c_int32, P, I]
         lib.oracle_gravity_adjoint.argtypes = [P, P, I64, D, D, P, P, I64, P, I]
         lib.oracle_ljc_adjoint.argtypes = [P, P, P, P, I64, D, D, P, P, I64, P, P, P, P, I]
-        for f in (lib.oracle_gravity, lib.oracle_ljc_linear, lib.oracle_leapfrog,
+        for f in (lib.oracle_gravity, lib.oracle_ljc_linear, lib.oracle_ljc_constant,
+                  lib.oracle_ljc_sigmoidal, lib.oracle_leapfrog,
                   lib.oracle_gravity_adjoint, lib.oracle_ljc_adjoint):
             f.restype = I
         _lib = lib
@@ -133,6 +138,43 @@ def ljc_linear(pos, q, sigma, epsilon, kc=332.0637, D=4.0, ilist=None, jrange=No
                                    float(D), _ptr(il), ni, j0, j1, _ptr(f), _ptr(u), int(nthreads))
     if rc:
         raise ValueError("oracle_ljc_linear rc=%d" % rc)
+    return f, u
+
+
+def _ljc_args(pos, q, sigma, epsilon, ilist):
+    pos = _f64(pos)
+    n = pos.shape[0]
+    pos = _f64(pos, (n, 3))
+    q = _f64(q, (n,))
+    sigma = _f64(sigma, (n,))
+    epsilon = _f64(epsilon, (n,))
+    il, ni = _ilist(ilist, n)
+    return pos, q, sigma, epsilon, n, il, ni
+
+
+def ljc_constant(pos, q, sigma, epsilon, kc=332.0637, D=4.0, ilist=None, nthreads=0):
+    """LJ + Coulomb with constant dielectric D (Table 1 LJC(constant)): (force, U_i)."""
+    pos, q, sigma, epsilon, n, il, ni = _ljc_args(pos, q, sigma, epsilon, ilist)
+    f = np.empty((ni, 3))
+    u = np.empty(ni)
+    rc = _load().oracle_ljc_constant(_ptr(pos), _ptr(q), _ptr(sigma), _ptr(epsilon), n, float(kc),
+                                     float(D), _ptr(il), ni, _ptr(f), _ptr(u), int(nthreads))
+    if rc:
+        raise ValueError("oracle_ljc_constant rc=%d" % rc)
+    return f, u
+
+
+def ljc_sigmoidal(pos, q, sigma, epsilon, zeta_coef, kc=332.0637, ilist=None, nthreads=0):
+    """LJ + Coulomb with dielectric zeta(r) = exp(a r^3 + b r^2 + c r + d), zeta_coef = (a, b, c, d)
+    (Table 1 LJC(sigmoidal), read potential-consistently): (force, U_i)."""
+    pos, q, sigma, epsilon, n, il, ni = _ljc_args(pos, q, sigma, epsilon, ilist)
+    zc = _f64(zeta_coef, (4,))
+    f = np.empty((ni, 3))
+    u = np.empty(ni)
+    rc = _load().oracle_ljc_sigmoidal(_ptr(pos), _ptr(q), _ptr(sigma), _ptr(epsilon), n, float(kc),
+                                      _ptr(zc), _ptr(il), ni, _ptr(f), _ptr(u), int(nthreads))
+    if rc:
+        raise ValueError("oracle_ljc_sigmoidal rc=%d" % rc)
     return f, u
 
 

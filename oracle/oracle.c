@@ -157,6 +157,104 @@ int oracle_ljc_linear(const double *pos, const double *q, const double *sigma,
 }
 
 /* ------------------------------------------------------------------------
+ * LJ + Coulomb with a constant dielectric D (Table 1 row "LJC (constant)").
+ *   u_ij = kc q_i q_j / (D r) + 4 e_ij [(s_ij/r)^12 - (s_ij/r)^6]
+ *   F_i  = sum_{j != i} [ kc q_i q_j / (D r^3)
+ *                         + (24 e_ij / r^2) (2 (s_ij/r)^12 - (s_ij/r)^6) ] (r_i - r_j)
+ * (the Coulomb term is Table 1's q_i q_j r_ij / (eps r^3) with the constant kc / D).
+ * ---------------------------------------------------------------------- */
+int oracle_ljc_constant(const double *pos, const double *q, const double *sigma,
+                        const double *epsl, int64_t n, double kc, double D,
+                        const int64_t *ilist, int64_t ni, double *force, double *energy,
+                        int nthreads)
+{
+    if (n < 0 || ni < 0) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < ni; ++k) {
+        const int64_t i = row(ilist, k);
+        nsum fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, en = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double rx = pos[3 * i] - pos[3 * j];
+            const double ry = pos[3 * i + 1] - pos[3 * j + 1];
+            const double rz = pos[3 * i + 2] - pos[3 * j + 2];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double r = sqrt(r2);
+            const double sij = 0.5 * (sigma[i] + sigma[j]);
+            const double eij = sqrt(epsl[i] * epsl[j]);
+            const double sr2 = sij * sij / r2;
+            const double sr6 = sr2 * sr2 * sr2;
+            const double sr12 = sr6 * sr6;
+            const double coul = kc * q[i] * q[j] / D;          /* u_C = coul / r */
+            const double W = coul / (r2 * r) + 24.0 * eij / r2 * (2.0 * sr12 - sr6);
+            nadd(&fx, W * rx);
+            nadd(&fy, W * ry);
+            nadd(&fz, W * rz);
+            nadd(&en, coul / r + 4.0 * eij * (sr12 - sr6));
+        }
+        force[3 * k] = nval(&fx);
+        force[3 * k + 1] = nval(&fy);
+        force[3 * k + 2] = nval(&fz);
+        if (energy) energy[k] = nval(&en);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * LJ + Coulomb with a distance-dependent dielectric zeta(r) (Table 1 row
+ * "LJC (sigmoidal)").  The printed zeta(r) = exp(alpha r^3 + beta r^2 + gamma
+ * + delta) is read as exp(alpha r^3 + beta r^2 + gamma r + delta) (the
+ * constants are not given; they are inputs here), and the law is read
+ * potential-consistently:
+ *   u_ij = kc q_i q_j / (zeta(r) r) + 4 e_ij [(s_ij/r)^12 - (s_ij/r)^6]
+ *   F_i  = sum_{j != i} [ kc q_i q_j (1 + r zeta'(r)/zeta(r)) / (zeta(r) r^3)
+ *                         + (24 e_ij / r^2) (2 (s_ij/r)^12 - (s_ij/r)^6) ] (r_i - r_j)
+ * with zeta'/zeta = 3 alpha r^2 + 2 beta r + gamma.
+ * ---------------------------------------------------------------------- */
+int oracle_ljc_sigmoidal(const double *pos, const double *q, const double *sigma,
+                         const double *epsl, int64_t n, double kc, const double *zc,
+                         const int64_t *ilist, int64_t ni, double *force, double *energy,
+                         int nthreads)
+{
+    if (n < 0 || ni < 0 || !zc) return -1;
+    set_threads(nthreads);
+    const double al = zc[0], be = zc[1], ga = zc[2], de = zc[3];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < ni; ++k) {
+        const int64_t i = row(ilist, k);
+        nsum fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, en = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double rx = pos[3 * i] - pos[3 * j];
+            const double ry = pos[3 * i + 1] - pos[3 * j + 1];
+            const double rz = pos[3 * i + 2] - pos[3 * j + 2];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double r = sqrt(r2);
+            const double zeta = exp(al * r * r * r + be * r * r + ga * r + de);
+            const double dlog = 3.0 * al * r * r + 2.0 * be * r + ga;      /* zeta' / zeta */
+            const double sij = 0.5 * (sigma[i] + sigma[j]);
+            const double eij = sqrt(epsl[i] * epsl[j]);
+            const double sr2 = sij * sij / r2;
+            const double sr6 = sr2 * sr2 * sr2;
+            const double sr12 = sr6 * sr6;
+            const double coul = kc * q[i] * q[j];
+            const double W = coul * (1.0 + r * dlog) / (zeta * r2 * r) +
+                             24.0 * eij / r2 * (2.0 * sr12 - sr6);
+            nadd(&fx, W * rx);
+            nadd(&fy, W * ry);
+            nadd(&fz, W * rz);
+            nadd(&en, coul / (zeta * r) + 4.0 * eij * (sr12 - sr6));
+        }
+        force[3 * k] = nval(&fx);
+        force[3 * k + 1] = nval(&fy);
+        force[3 * k + 2] = nval(&fz);
+        if (energy) energy[k] = nval(&en);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
  * Time-step cycle (Section 1: force evaluation, then the update step, then
  * repeat).  The paper names no integrator; the reading is kick-drift-kick
  * leapfrog (velocity Verlet) in FP64 with the acceleration carried:
