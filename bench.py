@@ -13,9 +13,10 @@ Printed (one JSON line on stdout): interactions per second, the roofline of
 the all-pairs kernel (algorithmic flops per launch / its mean launch time,
 measured with HIP events on the launch stream), the oracle timed on a bounded
 sample on the host cores, the accuracy of the timed path against the FP64 GPU
-pass and the oracle, and two secondary legs: the batched ensemble (256 LJC
-systems, N_s in [500, 5000], one persistent launch vs one FP64 launch per
-system) and the position adjoint at N = 262,144 (FP32 vs FP64).
+pass and the oracle, and three secondary legs: the batched ensemble (256 LJC
+systems, N_s in [500, 5000], one persistent launch vs one launch per system,
+each side autotuned), the position adjoint at N = 262,144 (FP32 vs FP64), and
+every pair law of Table 1 at N = 65,536.
 """
 from __future__ import annotations
 
@@ -31,10 +32,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_FP32_TFLOPS = 157.3   # 256 CU x 64 lanes x 2 (FMA) x 2 (packed) x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector: 256 CUs x 256 flops/cycle/CU x 2.4 GHz
 N_MAIN = 1 << 20
 EPS_MAIN = 0.005
 DT = 1e-3
+N_LAWS = 65536
+# sigmoidal dielectric zeta(r) = exp(a r^3 + b r^2 + c r + d): 4.6 at 5 A, about 100 at 20 A
+ZETA_SIGMOIDAL = (2e-4, -6e-3, 0.25, 0.4)
 
 
 def log(*a):
@@ -70,6 +74,7 @@ def main():
     t0 = time.time()
     pos, vel, mass = W.plummer(args.n, 5)
     ens = W.batched_md(256, seed=4) if args.legs == "all" else None
+    md = W.md_system(N_LAWS, 3, box=(32.0 * N_LAWS) ** (1.0 / 3.0)) if args.legs == "all" else None
     log("inputs drawn in %.1f s" % (time.time() - t0))
 
     import torch
@@ -191,6 +196,7 @@ def main():
     if args.legs == "all":
         out["batched"] = batched_leg(nb, torch, dev, ens)
         out["backward"] = backward_leg(nb, torch, dev, W)
+        out["laws"] = laws_leg(nb, torch, dev, W, md)
     print(json.dumps(out), flush=True)
 
 
@@ -228,6 +234,22 @@ def batched_leg(nb, torch, dev, ens):
         return nb.forces_batched(off, x, p, law)
 
     views = [(x[off[s]:off[s + 1]], p[off[s]:off[s + 1]]) for s in range(S)]
+
+    # the per-system baselines get the same treatment as the batched launch: the
+    # autotuner picks their configuration, once per power-of-two size bucket (the
+    # granularity at which tuned configurations are remembered), on the largest
+    # system of the bucket
+    sizes = np.diff(off)
+    buckets = {}
+    for s in range(S):
+        if sizes[s] > 0:
+            b = int(np.ceil(np.log2(sizes[s])))
+            if b not in buckets or sizes[s] > sizes[buckets[b]]:
+                buckets[b] = s
+    for l in (law64, law):
+        for b, s in sorted(buckets.items()):
+            nb.autotune(views[s][0], views[s][1], l, potential=True)
+    log("autotuned per-system loop baselines for size buckets", sorted(buckets))
 
     def run_loop(l):
         outs = []
@@ -290,6 +312,50 @@ def backward_leg(nb, torch, dev, W):
     res["fp32_tflops"] = res["flops_per_pair"] * float(n) ** 2 / (res["fp32_fp64acc_ms"] * 1e-3) / 1e12
     res["err_vs_fp64"] = {"median": float(np.median(e)), "max": float(e.max())}
     log("backward:", res)
+    return res
+
+
+def laws_leg(nb, torch, dev, W, md):
+    """Every pair law of Table 1 at N = 65,536 (Plummer sphere for gravity, the MD box at
+    density 1/32 A^-3 for the LJC laws), FP32 + Kahan with the potential: throughput, the
+    all-pairs kernel's FLOP/s against the FP32 vector peak, and the error against an FP64
+    pass over the same inputs."""
+    n = md.n
+    x = torch.tensor(md.pos, device=dev)
+    p = torch.tensor(md.params(), device=dev)
+    pg, _, mg = W.plummer(n, 2)
+    xg = torch.tensor(pg, device=dev)
+    mgt = torch.tensor(mg, device=dev)
+    laws = [("gravity", nb.GRAVITY, xg, mgt, lambda pr: nb.gravity(pr, softening=0.01)),
+            ("ljc_linear", nb.LJC_LINEAR, x, p, lambda pr: nb.ljc_linear(pr)),
+            ("ljc_constant", nb.LJC_CONSTANT, x, p, lambda pr: nb.ljc_constant(pr)),
+            ("ljc_sigmoidal", nb.LJC_SIGMOIDAL, x, p, lambda pr: nb.ljc_sigmoidal(ZETA_SIGMOIDAL, pr))]
+    res = {"n": n, "pairs": float(n) * n, "zeta_sigmoidal": list(ZETA_SIGMOIDAL)}
+    reps = 10
+    for name, kind, xx, pp, mk in laws:
+        law = mk("fp32_kahan")
+        cfg, _ = nb.autotune(xx, pp, law, potential=True)
+        f32, u32 = nb.forces(xx, pp, law)
+        torch.cuda.synchronize()
+        nb.timing_read(reset=True)
+        nb.timing_enable(True)
+        t = time.perf_counter()
+        for _ in range(reps):
+            nb.forces(xx, pp, law)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t) / reps
+        nb.timing_enable(False)
+        k_ms, k_n = nb.timing_read(reset=True)
+        k_s = k_ms / max(k_n, 1) * 1e-3
+        fpp = nb.flops_per_pair(nb.API_FORCES, kind, True)
+        f64, u64 = nb.forces(xx, pp, mk("fp64"))
+        e = (torch.linalg.norm(f32 - f64, dim=1) / torch.linalg.norm(f64, dim=1)).cpu().numpy()
+        tf = fpp * float(n) * n / k_s / 1e12
+        res[name] = {"config": cfg, "ms": wall * 1e3, "kernel_ms": k_s * 1e3,
+                     "g_pairs_per_s": float(n) * n / wall / 1e9, "flops_per_pair": fpp,
+                     "kernel_tflops": tf, "frac_fp32_peak": tf / PEAK_FP32_TFLOPS,
+                     "err_vs_fp64": {"median": float(np.median(e)), "max": float(e.max())}}
+        log("law %s:" % name, res[name])
     return res
 
 

@@ -71,7 +71,12 @@ extern "C" {
 #define NBODY_EHIP (-4)        /* HIP runtime or launch error (message has the HIP text) */
 
 /* ---- laws and precisions ---- */
-enum nbody_law_kind { NBODY_LAW_GRAVITY = 0, NBODY_LAW_LJC_LINEAR = 1 };
+enum nbody_law_kind {
+    NBODY_LAW_GRAVITY = 0,       /* Eq. 1 */
+    NBODY_LAW_LJC_LINEAR = 1,    /* Table 1 LJC (linear): dielectric D r */
+    NBODY_LAW_LJC_CONSTANT = 2,  /* Table 1 LJC (constant): dielectric D */
+    NBODY_LAW_LJC_SIGMOIDAL = 3  /* Table 1 LJC (sigmoidal): dielectric zeta(r), see nbody_law */
+};
 
 enum nbody_precision {
     NBODY_FP64 = 0,          /* FP64 pair arithmetic, compensated FP64 sums (reference pass) */
@@ -83,14 +88,23 @@ enum nbody_precision {
 /* Law parameters (host struct).  `softening` is the length eps of Eq. 1 (the
  * kernel adds eps^2 to r^2, as the Appendix listing adds its constant).
  * `coulomb_k` is k (332.0637 kcal A / (mol e^2) for Angstrom/kcal/e units) and
- * `dielectric` is D in eps(r) = D r.  Fields a law does not use are ignored. */
+ * `dielectric` is D in eps(r) = D r (LJC linear) or eps = D (LJC constant).
+ * LJC(sigmoidal) uses zeta(r) = exp(zeta[0] r^3 + zeta[1] r^2 + zeta[2] r +
+ * zeta[3]) (Table 1's exponent, whose printed "gamma + delta" is read as
+ * gamma r + delta; the paper gives no constants) with the potential
+ * u = k q_i q_j / (zeta(r) r) + LJ and F = -grad U:
+ *   F_i = sum_j [k q_i q_j (1 + r zeta'/zeta) / (zeta r^3) + LJ] (r_i - r_j).
+ * The other LJC laws: u = k q_i q_j / (D r^2) (linear), k q_i q_j / (D r)
+ * (constant).  U_i = sum_j u_ij for every LJC law.  Fields a law does not
+ * use are ignored. */
 typedef struct nbody_law {
     int32_t kind;        /* enum nbody_law_kind */
     int32_t precision;   /* enum nbody_precision */
     double G;            /* gravity */
     double softening;    /* gravity, >= 0 */
     double coulomb_k;    /* LJC */
-    double dielectric;   /* LJC, > 0 */
+    double dielectric;   /* LJC linear / constant, > 0 */
+    double zeta[4];      /* LJC sigmoidal, finite */
 } nbody_law;
 
 /* Entry-point ids for nbody_workspace_bytes / nbody_set_config. */
@@ -177,6 +191,7 @@ int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double
  *              gradient with respect to per-type sigma and epsilon), reduced
  *              in a fixed order.
  * Workspace: nbody_workspace_bytes(NBODY_API_BACKWARD, n, 1, law).
+ * Laws: gravity and LJC(linear) (other laws: NBODY_ENOTSUP).
  * Precisions: NBODY_FP64, NBODY_FP32_FP64ACC, NBODY_FP32_KAHAN. */
 int nbody_forces_backward(const double *pos, const double *params, int64_t n,
                           const nbody_law *law, const double *grad_force, double *grad_pos,

@@ -37,6 +37,7 @@ _lib = None
 
 GRAVITY = 0
 LJC_LINEAR = 1
+LJC_CONSTANT = 2
 
 
 def build(force: bool = True) -> str:
@@ -183,7 +184,7 @@ def leapfrog(law, pos, vel, acc, params, dt, nsteps, inv_mass=None, G=1.0, eps=0
     """Kick-drift-kick leapfrog in FP64.  Returns (pos, vel, acc, pot) after ``nsteps``.
 
     ``params`` is the mass [n] for gravity, or an [n,3] array of (q, sigma,
-    epsilon) for LJC(linear).  ``acc`` is a(t) on entry."""
+    epsilon) for LJC(linear) and LJC(constant).  ``acc`` is a(t) on entry."""
     pos = _f64(pos).copy()
     n = pos.shape[0]
     vel = _f64(vel, (n, 3)).copy()
@@ -191,7 +192,7 @@ def leapfrog(law, pos, vel, acc, params, dt, nsteps, inv_mass=None, G=1.0, eps=0
     if law == GRAVITY:
         par = _f64(params, (n,))
         c0, c1 = float(G), float(eps)
-    elif law == LJC_LINEAR:
+    elif law in (LJC_LINEAR, LJC_CONSTANT):
         par = np.ascontiguousarray(_f64(params, (n, 3)).T)  # q | sigma | eps blocks
         c0, c1 = float(kc), float(D)
     else:

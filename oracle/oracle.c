@@ -260,9 +260,9 @@ int oracle_ljc_sigmoidal(const double *pos, const double *q, const double *sigma
  * leapfrog (velocity Verlet) in FP64 with the acceleration carried:
  *   v += dt/2 a(x);  x += dt v;  a = a(x);  v += dt/2 a.
  * law 0 = gravity (params = mass [n]; a is the acceleration of Eq. 1);
- * law 1 = LJC(linear) (params = q, sigma, eps as three [n] arrays packed
- * one after another, i.e. params[0..n), params[n..2n), params[2n..3n));
- * a = F * inv_mass.
+ * law 1 = LJC(linear), law 2 = LJC(constant) (c0 = kc, c1 = D; params = q,
+ * sigma, eps as three [n] arrays packed one after another, i.e.
+ * params[0..n), params[n..2n), params[2n..3n)); a = F * inv_mass.
  * acc holds a(t) on entry and a(t + nsteps dt) on exit.  pot (or NULL)
  * receives phi (gravity) or U_i (LJC) at the final positions.
  * ---------------------------------------------------------------------- */
@@ -271,9 +271,11 @@ static int eval_accel(int law, const double *pos, const double *params, const do
 {
     if (law == 0)
         return oracle_gravity(pos, params, n, c0, c1, NULL, n, 0, n, acc, pot, nthreads);
-    if (law == 1) {
-        int rc = oracle_ljc_linear(pos, params, params + n, params + 2 * n, n, c0, c1, NULL, n, 0, n,
-                                   acc, pot, nthreads);
+    if (law == 1 || law == 2) {
+        int rc = law == 1 ? oracle_ljc_linear(pos, params, params + n, params + 2 * n, n, c0, c1, NULL,
+                                              n, 0, n, acc, pot, nthreads)
+                          : oracle_ljc_constant(pos, params, params + n, params + 2 * n, n, c0, c1,
+                                                NULL, n, acc, pot, nthreads);
         if (rc) return rc;
         for (int64_t i = 0; i < n; ++i) {
             const double w = inv_mass ? inv_mass[i] : 1.0;

@@ -36,7 +36,7 @@ EXPORTED = (
 class NBodyLaw(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("precision", ctypes.c_int32), ("G", ctypes.c_double),
                 ("softening", ctypes.c_double), ("coulomb_k", ctypes.c_double),
-                ("dielectric", ctypes.c_double)]
+                ("dielectric", ctypes.c_double), ("zeta", ctypes.c_double * 4)]
 
 
 class NBodyConfig(ctypes.Structure):

@@ -15,14 +15,14 @@
 //   dL/deps_k   = (12 / se_k) sum_j se_j s6 (2 s6 - 1) x du
 #include <type_traits>
 
-#include "device.h"
+#include "allpairs.h"
 #include "kernels.h"
 
 namespace nbk {
 
 template <typename T> struct alignas(4 * sizeof(T)) GravAdjRec { T x, y, z, m, gx, gy, gz, p0; };
 template <typename T> struct alignas(4 * sizeof(T)) LjcAdjRec {
-    T x, y, z, qs, sh, se, gx, gy, gz, p0, p1, p2;
+    T x, y, z, qs, sh, se, gx, gy, gz, p0, p1, p2, p3, p4, p5, p6;   // padded to 16 values
 };
 
 // ------------------------------------------------------------------- pack ----
@@ -55,7 +55,7 @@ __device__ __forceinline__ void adj_put(LjcAdjRec<T> *rec, int64_t i, const doub
     r.gx = (T)g[0];
     r.gy = (T)g[1];
     r.gz = (T)g[2];
-    r.p0 = r.p1 = r.p2 = T(0);
+    r.p0 = r.p1 = r.p2 = r.p3 = r.p4 = r.p5 = r.p6 = T(0);
     rec[i] = r;
 }
 template <typename T> __device__ __forceinline__ void adj_pad(GravAdjRec<T> *rec, int64_t i)
@@ -69,7 +69,8 @@ template <typename T> __device__ __forceinline__ void adj_pad(LjcAdjRec<T> *rec,
 {
     LjcAdjRec<T> r;
     r.x = r.y = r.z = (T)kPadCoord;
-    r.qs = r.sh = r.se = r.gx = r.gy = r.gz = r.p0 = r.p1 = r.p2 = T(0);
+    r.qs = r.sh = r.se = r.gx = r.gy = r.gz = T(0);
+    r.p0 = r.p1 = r.p2 = r.p3 = r.p4 = r.p5 = r.p6 = T(0);
     rec[i] = r;
 }
 
@@ -186,23 +187,27 @@ __device__ __forceinline__ void adj_pair(const LjcAdjRec<T> &i, const LjcAdjRec<
     ljc_adj_pair<MASK>(i, j, eps2, self, o);
 }
 
-template <bool MASK, int NC, int I, typename R, typename T>
-__device__ __forceinline__ void adj_tile(const R *__restrict__ rec, int64_t t0, int64_t t1,
-                                         const R (&is)[I], const int64_t (&pid)[I], T eps2,
-                                         T (&p)[I][8])
-{
-    constexpr int U = 4;
-    for (int64_t j = t0; j < t1; j += U) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const R r = rec[j + u];
-#pragma unroll
-            for (int k = 0; k < I; ++k) adj_pair<MASK>(is[k], r, eps2, MASK && (pid[k] == j + u), p[k]);
-        }
+// The pair operation of the adjoint kernels for the shared j loop.
+template <int LAW> struct AdjOp {
+    static constexpr int NC = LAW == GRAVITY ? 3 : 6;
+    static constexpr int NP = 8;
+    template <bool MASK, typename R, typename T>
+    static __device__ __forceinline__ void run(const R &i, const R &j, const PairK<T> &k, bool self,
+                                               T (&o)[NP])
+    {
+        adj_pair<MASK>(i, j, k.eps2, self, o);
     }
-}
+};
 
-template <int LAW> struct AdjNC { static constexpr int value = LAW == GRAVITY ? 3 : 6; };
+template <typename T> __device__ __forceinline__ void settle(const GravAdjRec<T> &s)
+{
+    asm volatile("" ::"v"(s.x), "v"(s.y), "v"(s.z), "v"(s.m), "v"(s.gx), "v"(s.gy), "v"(s.gz));
+}
+template <typename T> __device__ __forceinline__ void settle(const LjcAdjRec<T> &s)
+{
+    asm volatile("" ::"v"(s.x), "v"(s.y), "v"(s.z), "v"(s.qs), "v"(s.sh), "v"(s.se), "v"(s.gx),
+                 "v"(s.gy), "v"(s.gz));
+}
 
 __device__ __forceinline__ void adj_finish(const AdjLaunch &a, int law, int64_t k, const double *v)
 {
@@ -227,7 +232,7 @@ __device__ __forceinline__ void adj_finish(const AdjLaunch &a, int law, int64_t 
     }
 }
 
-template <int LAW, int PREC, int I>
+template <int LAW, int PREC, int I, int JS>
 __global__ __launch_bounds__(256) void k_adjoint(
     const typename std::conditional<LAW == GRAVITY, GravAdjRec<typename RealOf<PREC>::type>,
                                     LjcAdjRec<typename RealOf<PREC>::type>>::type *__restrict__ rec,
@@ -235,7 +240,8 @@ __global__ __launch_bounds__(256) void k_adjoint(
 {
     using T = typename RealOf<PREC>::type;
     using R = typename std::conditional<LAW == GRAVITY, GravAdjRec<T>, LjcAdjRec<T>>::type;
-    constexpr int NC = AdjNC<LAW>::value;
+    using Op = AdjOp<LAW>;
+    constexpr int NC = Op::NC;
     const int lane = lane_id();
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
                          __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -253,23 +259,12 @@ __global__ __launch_bounds__(256) void k_adjoint(
         is[k] = rec[pid[k]];
     }
     RunSum<PREC> acc[I][NC];
-    T p[I][8];
-    for (int64_t t0 = jb; t0 < je; t0 += a.j_tile) {
-        const int64_t t1 = (t0 + a.j_tile < je) ? t0 + a.j_tile : je;
-        bool near = false;
-#pragma unroll
-        for (int k = 0; k < I; ++k) near |= (pid[k] >= t0) & (pid[k] < t1);
-#pragma unroll
-        for (int k = 0; k < I; ++k)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[k][c].begin(p[k][c]);
-        if (wave_any(near)) adj_tile<true, NC, I>(rec, t0, t1, is, pid, (T)a.eps2, p);
-        else adj_tile<false, NC, I>(rec, t0, t1, is, pid, (T)a.eps2, p);
-#pragma unroll
-        for (int k = 0; k < I; ++k)
-#pragma unroll
-            for (int c = 0; c < NC; ++c) acc[k][c].fold(p[k][c]);
-    }
+    T p[I][Op::NP];
+    __shared__ R lds_j[JS ? 4 : 1][2][kWave];
+    PairK<T> kc{};
+    kc.eps2 = (T)a.eps2;
+    j_range<JS, Op, PREC, I>(rec, jb, je, a.j_tile, is, pid, kc, acc, p,
+                             lds_j[JS ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0]);
 #pragma unroll
     for (int k = 0; k < I; ++k) {
         const int64_t r = rbase + lane + (int64_t)kWave * k;
@@ -292,7 +287,10 @@ static void launch_adj_one(const AdjLaunch &a, dim3 grid, hipStream_t s)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename std::conditional<LAW == GRAVITY, GravAdjRec<T>, LjcAdjRec<T>>::type;
-    hipLaunchKernelGGL((k_adjoint<LAW, PREC, I>), grid, dim3(a.block), 0, s, (const R *)a.rec, a);
+    if (a.j_stage == 1)
+        hipLaunchKernelGGL((k_adjoint<LAW, PREC, I, 1>), grid, dim3(a.block), 0, s, (const R *)a.rec, a);
+    else
+        hipLaunchKernelGGL((k_adjoint<LAW, PREC, I, 0>), grid, dim3(a.block), 0, s, (const R *)a.rec, a);
 }
 
 template <int LAW, int PREC>

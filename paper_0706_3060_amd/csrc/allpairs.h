@@ -100,26 +100,40 @@ template <typename T> struct IStateOf;
 template <typename T> struct IStateOf<GravRec<T>> { using type = GravI<T>; };
 template <typename T> struct IStateOf<LjcRec<T>> { using type = LjcI<T>; };
 
-template <bool MASK, bool POT, typename T>
-__device__ __forceinline__ void pair(const GravI<T> &i, const GravRec<T> &j, T eps2, bool self,
-                                     T (&p)[4])
+template <bool MASK, bool POT, int LAW, typename T>
+__device__ __forceinline__ void pair(const GravI<T> &i, const GravRec<T> &j, const PairK<T> &k,
+                                     bool self, T (&p)[4])
 {
-    grav_pair<MASK, POT>(i, j.x, j.y, j.z, j.m, eps2, self, p);
+    grav_pair<MASK, POT>(i, j.x, j.y, j.z, j.m, k, self, p);
 }
 
-template <bool MASK, bool POT, typename T>
-__device__ __forceinline__ void pair(const LjcI<T> &i, const LjcRec<T> &j, T, bool self, T (&p)[4])
+template <bool MASK, bool POT, int LAW, typename T>
+__device__ __forceinline__ void pair(const LjcI<T> &i, const LjcRec<T> &j, const PairK<T> &k,
+                                     bool self, T (&p)[4])
 {
-    ljc_pair<MASK, POT>(i, j.x, j.y, j.z, j.qs, j.sh, j.se, self, p);
+    ljc_pair<MASK, POT, LAW>(i, j.x, j.y, j.z, j.qs, j.sh, j.se, k, self, p);
 }
+
+// The pair operation of the forward kernels: Op::NC running sums
+// (force and, with POT, potential) from the pair functions above.
+template <bool POT, int LAW> struct ForceOp {
+    static constexpr int NC = POT ? 4 : 3;
+    static constexpr int NP = 4;
+    template <bool MASK, typename IS, typename R, typename T>
+    static __device__ __forceinline__ void run(const IS &i, const R &j, const PairK<T> &k, bool self,
+                                               T (&p)[NP])
+    {
+        pair<MASK, POT, LAW>(i, j, k, self, p);
+    }
+};
 
 // The j loop over one tile [t0, t1) (a multiple of 8 records).  `rec` is a
 // restrict-qualified read-only pointer and j is wave-uniform, so each record
 // load is a scalar load shared by the 64 lanes.
-template <bool MASK, bool POT, int I, typename R, typename IS, typename T>
+template <bool MASK, typename Op, int I, typename R, typename IS, typename T>
 __device__ __forceinline__ void tile_loop(const R *__restrict__ rec, int64_t t0, int64_t t1,
-                                          const IS (&is)[I], const int64_t (&pid)[I], T eps2,
-                                          T (&p)[I][4])
+                                          const IS (&is)[I], const int64_t (&pid)[I],
+                                          const PairK<T> &kc, T (&p)[I][Op::NP])
 {
     constexpr int U = 8;
     R cur[U];
@@ -135,7 +149,7 @@ __device__ __forceinline__ void tile_loop(const R *__restrict__ rec, int64_t t0,
         for (int u = 0; u < U; ++u) {
 #pragma unroll
             for (int k = 0; k < I; ++k)
-                pair<MASK, POT>(is[k], cur[u], eps2, MASK && (pid[k] == j + u), p[k]);
+                Op::template run<MASK>(is[k], cur[u], kc, MASK && (pid[k] == j + u), p[k]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) cur[u] = nxt[u];
@@ -145,28 +159,29 @@ __device__ __forceinline__ void tile_loop(const R *__restrict__ rec, int64_t t0,
 // The j loop over one 64-record chunk held in the wave's LDS slot (j_stage 1).
 // Every lane reads the same record (an LDS broadcast) into VGPRs, so the pair
 // arithmetic has only VGPR operands.
-template <bool MASK, bool POT, int I, typename R, typename IS, typename T>
+template <bool MASK, typename Op, int I, typename R, typename IS, typename T>
 __device__ __forceinline__ void chunk_loop(const R *wl, int64_t c, const IS (&is)[I],
-                                           const int64_t (&pid)[I], T eps2, T (&p)[I][4])
+                                           const int64_t (&pid)[I], const PairK<T> &kc,
+                                           T (&p)[I][Op::NP])
 {
 #pragma unroll 16
     for (int jj = 0; jj < kWave; ++jj) {
         const R r = wl[jj];
 #pragma unroll
         for (int k = 0; k < I; ++k)
-            pair<MASK, POT>(is[k], r, eps2, MASK && (pid[k] == c + jj), p[k]);
+            Op::template run<MASK>(is[k], r, kc, MASK && (pid[k] == c + jj), p[k]);
     }
 }
 
 // Run the j range [jb, je) for one wave's rows.  `wl` is the wave's pair of
 // 64-record LDS slots (used when JS == 1).
-template <int JS, bool POT, int PREC, int I, typename R, typename IS, typename T>
+template <int JS, typename Op, int PREC, int I, typename R, typename IS, typename T>
 __device__ __forceinline__ void j_range(const R *__restrict__ rec, int64_t jb, int64_t je,
                                         int j_tile, const IS (&is)[I], const int64_t (&pid)[I],
-                                        T eps2, RunSum<PREC> (&acc)[I][POT ? 4 : 3], T (&p)[I][4],
-                                        R (*wl)[kWave])
+                                        const PairK<T> &kc, RunSum<PREC> (&acc)[I][Op::NC],
+                                        T (&p)[I][Op::NP], R (*wl)[kWave])
 {
-    constexpr int NC = POT ? 4 : 3;
+    constexpr int NC = Op::NC;
     const int lane = lane_id();
     if constexpr (JS == 0) {
         for (int64_t t0 = jb; t0 < je; t0 += j_tile) {
@@ -179,9 +194,9 @@ __device__ __forceinline__ void j_range(const R *__restrict__ rec, int64_t jb, i
 #pragma unroll
                 for (int c = 0; c < NC; ++c) acc[k][c].begin(p[k][c]);
             if (wave_any(near))
-                tile_loop<true, POT, I>(rec, t0, t1, is, pid, (T)eps2, p);
+                tile_loop<true, Op, I>(rec, t0, t1, is, pid, kc, p);
             else
-                tile_loop<false, POT, I>(rec, t0, t1, is, pid, (T)eps2, p);
+                tile_loop<false, Op, I>(rec, t0, t1, is, pid, kc, p);
 #pragma unroll
             for (int k = 0; k < I; ++k)
 #pragma unroll
@@ -196,8 +211,8 @@ __device__ __forceinline__ void j_range(const R *__restrict__ rec, int64_t jb, i
         // reordering them (a memory fence here would also wait for the
         // prefetch load in flight).
         // softening in a VGPR so that r^2 + eps^2 is an all-VGPR multiply-add
-        T eps2v = (T)eps2;
-        if constexpr (sizeof(T) == 4) asm volatile("v_mov_b32 %0, %1" : "=v"(eps2v) : "s"(eps2));
+        PairK<T> kv = kc;
+        if constexpr (sizeof(T) == 4) asm volatile("v_mov_b32 %0, %1" : "=v"(kv.eps2) : "s"(kc.eps2));
         // Prefetch distance: the record stored into the free slot at the end of
         // chunk c was loaded at the end of chunk c - 64, one full chunk of
         // arithmetic earlier (the value is carried across the loop back-edge,
@@ -226,9 +241,9 @@ __device__ __forceinline__ void j_range(const R *__restrict__ rec, int64_t jb, i
 #pragma unroll
                 for (int k = 0; k < I; ++k) near |= (pid[k] >= c) & (pid[k] < c + kWave);
                 if (wave_any(near))
-                    chunk_loop<true, POT, I>(wl[buf], c, is, pid, eps2v, p);
+                    chunk_loop<true, Op, I>(wl[buf], c, is, pid, kv, p);
                 else
-                    chunk_loop<false, POT, I>(wl[buf], c, is, pid, eps2v, p);
+                    chunk_loop<false, Op, I>(wl[buf], c, is, pid, kv, p);
                 if (c + kWave >= tile_end) {
 #pragma unroll
                     for (int k = 0; k < I; ++k)

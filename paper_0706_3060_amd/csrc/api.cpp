@@ -58,7 +58,7 @@ size_t rec_bytes(int law, int prec)
 size_t adj_rec_bytes(int law, int prec)
 {
     const size_t t = is_f32(prec) ? 4 : 8;
-    return law == NBODY_LAW_GRAVITY ? 8 * t : 12 * t;
+    return law == NBODY_LAW_GRAVITY ? 8 * t : 16 * t;
 }
 
 int params_per_particle(int law) { return law == NBODY_LAW_GRAVITY ? 1 : 3; }
@@ -74,7 +74,7 @@ int max_split(int64_t npad)
 int validate_law(const nbody_law *law, bool backward)
 {
     if (!law) return fail(NBODY_EINVAL, "law is NULL");
-    if (law->kind != NBODY_LAW_GRAVITY && law->kind != NBODY_LAW_LJC_LINEAR)
+    if (law->kind < NBODY_LAW_GRAVITY || law->kind > NBODY_LAW_LJC_SIGMOIDAL)
         return fail(NBODY_EINVAL, "unknown law kind %d", law->kind);
     if (law->precision < NBODY_FP64 || law->precision > NBODY_FP32_PLAIN)
         return fail(NBODY_EINVAL, "unknown precision %d", law->precision);
@@ -83,13 +83,21 @@ int validate_law(const nbody_law *law, bool backward)
             return fail(NBODY_EINVAL, "softening must be finite and >= 0 (got %g)", law->softening);
         if (!std::isfinite(law->G)) return fail(NBODY_EINVAL, "G must be finite");
     } else {
-        if (!(law->dielectric > 0.0) || !std::isfinite(law->dielectric))
+        if (law->kind != NBODY_LAW_LJC_SIGMOIDAL &&
+            (!(law->dielectric > 0.0) || !std::isfinite(law->dielectric)))
             return fail(NBODY_EINVAL, "dielectric D must be finite and > 0 (got %g)", law->dielectric);
         if (!std::isfinite(law->coulomb_k) || law->coulomb_k < 0.0)
             return fail(NBODY_EINVAL, "coulomb_k must be finite and >= 0");
+        if (law->kind == NBODY_LAW_LJC_SIGMOIDAL)
+            for (int c = 0; c < 4; ++c)
+                if (!std::isfinite(law->zeta[c])) return fail(NBODY_EINVAL, "zeta coefficients must be finite");
+        if (law->kind >= NBODY_LAW_LJC_CONSTANT && law->precision == NBODY_FP32_PLAIN)
+            return fail(NBODY_ENOTSUP, "FP32_PLAIN is provided for gravity and LJC(linear) only");
     }
     if (backward && law->precision == NBODY_FP32_PLAIN)
         return fail(NBODY_ENOTSUP, "the adjoint is provided for FP64, FP32_FP64ACC and FP32_KAHAN");
+    if (backward && law->kind > NBODY_LAW_LJC_LINEAR)
+        return fail(NBODY_ENOTSUP, "the adjoint is provided for gravity and LJC(linear)");
     return NBODY_OK;
 }
 
@@ -120,9 +128,10 @@ int max_ipl(int api, int prec)
 
 bool ipl_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 
-Cfg sanitize(Cfg c, int api, int prec, int64_t npad)
+Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
 {
     c.ipl = std::min(c.ipl, max_ipl(api, prec));
+    if (law >= NBODY_LAW_LJC_CONSTANT) c.ipl = std::min(c.ipl, 2);
     if (c.j_stage == 1) c.ipl = std::min(c.ipl, 4);    // LDS staging: up to 4 rows per lane
     c.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
     if (api == NBODY_API_BATCHED) c.j_split = 1;
@@ -132,10 +141,24 @@ Cfg sanitize(Cfg c, int api, int prec, int64_t npad)
 int device_cus();
 
 // Resident waves of the all-pairs kernel for this configuration (whole chip).
+// The occupancy query is a runtime call of a few microseconds; its answer
+// depends only on the kernel and the block size, so it is asked once.
 int64_t resident_waves(int law, int prec, int ipl, bool pot, int js, int block)
 {
+    using Key = std::tuple<int, int, int, int, int, int>;
+    static std::map<Key, int64_t> cache;
+    static std::mutex mu;
+    const Key key(law, prec, ipl, pot ? 1 : 0, js, block);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
     const int bpc = forces_blocks_per_cu(law, prec, ipl, pot ? 1 : 0, js, block);
-    return bpc > 0 ? (int64_t)bpc * (block / 64) * device_cus() : 0;
+    const int64_t r = bpc > 0 ? (int64_t)bpc * (block / 64) * device_cus() : 0;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = r;
+    return r;
 }
 
 // Modelled time of one evaluation with a j split of s (seconds, up to a common
@@ -155,6 +178,7 @@ double nominal_rate(int law, int prec)
 {
     const bool f32 = is_f32(prec);
     if (law == NBODY_LAW_GRAVITY) return f32 ? 3.3e12 : 1.4e12;
+    if (law == NBODY_LAW_LJC_SIGMOIDAL) return f32 ? 1.2e12 : 0.4e12;
     return f32 ? 1.8e12 : 0.6e12;
 }
 
@@ -204,28 +228,28 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t S, bool pot)
     }
     if (api == NBODY_API_BACKWARD) {
         c.ipl = std::min(c.ipl, 2);
-        c.j_stage = 0;
+        c.j_stage = is_f32(prec) ? 1 : 0;
         const int64_t waves = (n + 64 * c.ipl - 1) / (64 * c.ipl);
         int split = 1;
         while (split < kMaxSplit && waves * split < kTargetWaves) split *= 2;
         c.j_split = split;
-        return sanitize(c, api, prec, npad);
+        return sanitize(c, api, law, prec, npad);
     }
     c.j_split = ranked_splits(law, prec, n, c.ipl, pot, c.j_stage, c.block, max_split(npad))[0];
-    return sanitize(c, api, prec, npad);
+    return sanitize(c, api, law, prec, npad);
 }
 
 Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot)
 {
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
     std::lock_guard<std::mutex> lk(g_mu);
-    if (g_override_set[api]) return sanitize(g_override[api], api, law->precision, npad);
+    if (g_override_set[api]) return sanitize(g_override[api], api, law->kind, law->precision, npad);
     auto it = g_tuned.find(TuneKey(api, law->kind, law->precision, pot ? 1 : 0, size_bucket(n),
                                    size_bucket(S)));
     if (it == g_tuned.end() && api == NBODY_API_LEAPFROG)   // a leapfrog step runs the forces kernel
         it = g_tuned.find(TuneKey(NBODY_API_FORCES, law->kind, law->precision, pot ? 1 : 0,
                                   size_bucket(n), size_bucket(S)));
-    if (it != g_tuned.end()) return sanitize(it->second.first, api, law->precision, npad);
+    if (it != g_tuned.end()) return sanitize(it->second.first, api, law->kind, law->precision, npad);
     return heuristic(api, law->kind, law->precision, n, S, pot);
 }
 
@@ -324,9 +348,15 @@ BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
     return w;
 }
 
+// Charge scaling packed into the records so that qs_i qs_j is the Coulomb prefactor.
 double qscale_of(const nbody_law *law)
 {
-    return law->kind == NBODY_LAW_LJC_LINEAR ? std::sqrt(2.0 * law->coulomb_k / law->dielectric) : 0.0;
+    switch (law->kind) {
+    case NBODY_LAW_LJC_LINEAR: return std::sqrt(2.0 * law->coulomb_k / law->dielectric);
+    case NBODY_LAW_LJC_CONSTANT: return std::sqrt(law->coulomb_k / law->dielectric);
+    case NBODY_LAW_LJC_SIGMOIDAL: return std::sqrt(law->coulomb_k);
+    default: return 0.0;
+    }
 }
 
 Epilogue make_epi(const nbody_law *law, double *out_force, double *out_pot)
@@ -337,7 +367,8 @@ Epilogue make_epi(const nbody_law *law, double *out_force, double *out_pot)
         e.pscale = -law->G;
     } else {
         e.fscale = 1.0;     // the pair function accumulates -W d = W (r_i - r_j) already
-        e.pscale = 0.5;     // sum_j 2 u_ij -> U_i
+        // LJC(linear) accumulates 2 u_ij, the other dielectrics u_ij
+        e.pscale = law->kind == NBODY_LAW_LJC_LINEAR ? 0.5 : 1.0;
     }
     e.out_force = out_force;
     e.out_pot = out_pot;
@@ -379,6 +410,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
     f.j_tile = c.j_tile;
     f.j_stage = c.j_stage;
     f.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    for (int c = 0; c < 4; ++c) f.zeta[c] = law->kind == NBODY_LAW_LJC_SIGMOIDAL ? law->zeta[c] : 0.0;
     f.rec = base + lay.rec_off;
     f.partial = (double *)(base + lay.part_off);
     f.epi = epi;
@@ -525,6 +557,7 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     b.npad_total = plan.npad_total;
     b.j_tile = c.j_tile;
     b.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    for (int c = 0; c < 4; ++c) b.zeta[c] = law->kind == NBODY_LAW_LJC_SIGMOIDAL ? law->zeta[c] : 0.0;
     b.rec = base + lay.rec_off;
     b.ticket = (int *)(base + lay.ticket_off);
     b.epi = make_epi(law, out_force, out_pot);
@@ -573,7 +606,7 @@ int forces_impl(const double *pos, const double *params, int64_t n, const int64_
     if (rc) return rc;
     const bool pot = out_potential != nullptr;
     const Cfg c = forced ? *forced : choose(NBODY_API_FORCES, law, nrows, 1, pot);
-    return run_forward(law, sanitize(c, NBODY_API_FORCES, law->precision, round_up(std::max(n, nrows), 64)), pos,
+    return run_forward(law, sanitize(c, NBODY_API_FORCES, law->kind, law->precision, round_up(std::max(n, nrows), 64)), pos,
                        params, n, rows, nrows, make_epi(law, out_force, out_potential), pot, ws, lay,
                        (hipStream_t)stream, nullptr);
 }
@@ -593,7 +626,7 @@ int batched_impl(const int64_t *offsets, int64_t S, const double *pos, const dou
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     const Cfg c = forced ? *forced : choose(NBODY_API_BATCHED, law, n, S, out_potential != nullptr);
-    return run_batched(law, sanitize(c, NBODY_API_BATCHED, law->precision, 64), offsets, S, pos,
+    return run_batched(law, sanitize(c, NBODY_API_BATCHED, law->kind, law->precision, 64), offsets, S, pos,
                        params, out_force, out_potential, ws, lay, (hipStream_t)stream);
 }
 
@@ -608,6 +641,7 @@ std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
                 for (int b : {64, 128, 256})
                     for (int jt : {64, 256}) {
                         if (js == 0 && !is_f32(prec) && ipl > 1) continue;
+                        (void)law;
                         Cfg c;
                         c.ipl = ipl;
                         c.block = b;
@@ -621,6 +655,7 @@ std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
     for (int js : {0, 1})
         for (int ipl : {1, 2, 4, 8}) {
             if (ipl > max_ipl(api, prec) || (js == 1 && ipl > 4)) continue;
+            if (law >= NBODY_LAW_LJC_CONSTANT && ipl > 2) continue;
             const int block = 256;
             std::vector<int> splits = ranked_splits(law, prec, n, ipl, pot, js, block, max_split(npad));
             std::vector<int> pick;
@@ -655,7 +690,7 @@ const char *nbody_version(void) { return "nbody-mi355x 0.1 (gfx950)"; }
 size_t nbody_workspace_bytes(int32_t api, int64_t n_total, int64_t n_systems, const nbody_law *law)
 {
     if (!law || n_total < 0 || n_systems < 0) return 0;
-    if (law->kind != NBODY_LAW_GRAVITY && law->kind != NBODY_LAW_LJC_LINEAR) return 0;
+    if (law->kind < NBODY_LAW_GRAVITY || law->kind > NBODY_LAW_LJC_SIGMOIDAL) return 0;
     if (law->precision < NBODY_FP64 || law->precision > NBODY_FP32_PLAIN) return 0;
     switch (api) {
     case NBODY_API_FORCES: return fwd_layout(NBODY_API_FORCES, law, n_total).total;
@@ -733,6 +768,7 @@ int nbody_forces_backward(const double *pos, const double *params, int64_t n, co
     a.prec = law->precision;
     a.ipl = std::min(c.ipl, 4);
     a.block = c.block;
+    a.j_stage = c.j_stage;
     a.n = n;
     a.npad = npad;
     a.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
@@ -993,9 +1029,13 @@ int nbody_timing_read(double *total_ms, int64_t *launches, int32_t reset)
 int32_t nbody_flops_per_pair(int32_t api, int32_t law_kind, int32_t with_potential)
 {
     if (api == NBODY_API_BACKWARD) return law_kind == NBODY_LAW_GRAVITY ? 41 : 68;
-    if (law_kind == NBODY_LAW_GRAVITY) return with_potential ? 20 : 19;
-    if (law_kind == NBODY_LAW_LJC_LINEAR) return with_potential ? 35 : 30;
-    return 0;
+    switch (law_kind) {
+    case NBODY_LAW_GRAVITY: return with_potential ? 20 : 19;
+    case NBODY_LAW_LJC_LINEAR: return with_potential ? 35 : 30;
+    case NBODY_LAW_LJC_CONSTANT: return with_potential ? 36 : 31;
+    case NBODY_LAW_LJC_SIGMOIDAL: return with_potential ? 53 : 48;
+    default: return 0;
+    }
 }
 
 }  // extern "C"

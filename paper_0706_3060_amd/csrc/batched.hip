@@ -18,8 +18,8 @@ template <int LAW, int PREC, int I, bool POT, int JS>
 __global__ __launch_bounds__(256) void k_batched(
     const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec,
     const int32_t *__restrict__ units, int64_t n_units, const int64_t *__restrict__ off,
-    const int64_t *__restrict__ poff, int j_tile, typename RealOf<PREC>::type eps2, int *ticket,
-    Epilogue epi)
+    const int64_t *__restrict__ poff, int j_tile, PairK<typename RealOf<PREC>::type> kc,
+    int *ticket, Epilogue epi)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename RecOf<T, LAW>::type;
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_batched(
         T p[I][4];
 #pragma unroll
         for (int k = 0; k < I; ++k) p[k][3] = T(0);
-        j_range<JS, POT, PREC, I>(rec, po, pe, j_tile, is, pid, eps2, acc, p, wl);
+        j_range<JS, ForceOp<POT, LAW>, PREC, I>(rec, po, pe, j_tile, is, pid, kc, acc, p, wl);
 #pragma unroll
         for (int k = 0; k < I; ++k) {
             const int64_t l = lbase + lane + (int64_t)kWave * k;
@@ -120,14 +120,22 @@ static void launch_b(const BatchLaunch &b, hipStream_t s)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename RecOf<T, LAW>::type;
+    PairK<T> kc;
+    kc.eps2 = (T)b.eps2;
+    kc.za = (T)b.zeta[0];
+    kc.zb = (T)b.zeta[1];
+    kc.zc = (T)b.zeta[2];
+    kc.zd = (T)b.zeta[3];
+    kc.za3 = (T)(3.0 * b.zeta[0]);
+    kc.zb2 = (T)(2.0 * b.zeta[1]);
     if (b.j_stage == 1)
         hipLaunchKernelGGL((k_batched<LAW, PREC, I, POT, 1>), dim3(b.grid), dim3(b.block), 0, s,
-                           (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile,
-                           (T)b.eps2, b.ticket, b.epi);
+                           (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile, kc,
+                           b.ticket, b.epi);
     else
         hipLaunchKernelGGL((k_batched<LAW, PREC, I, POT, 0>), dim3(b.grid), dim3(b.block), 0, s,
-                           (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile,
-                           (T)b.eps2, b.ticket, b.epi);
+                           (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile, kc,
+                           b.ticket, b.epi);
 }
 
 // Calls f.run<LAW, PREC, I, POT>() for the runtime selectors (I in {1, 2, 4});
@@ -138,11 +146,20 @@ static bool batched_dispatch(int law, int prec, int ipl, bool pot, F &f)
     auto by_ipl = [&](auto law_c, auto prec_c, auto pot_c) -> bool {
         constexpr int L = decltype(law_c)::value, P = decltype(prec_c)::value;
         constexpr bool O = decltype(pot_c)::value;
-        switch (ipl) {
-        case 1: f.template run<L, P, 1, O>(); return true;
-        case 2: f.template run<L, P, 2, O>(); return true;
-        case 4: f.template run<L, P, 4, O>(); return true;
-        default: return false;
+        if constexpr (L > LJC && P == P_PLAIN) {
+            return false;            // the ablation precision exists for gravity and LJC(linear)
+        } else {
+            switch (ipl) {
+            case 1: f.template run<L, P, 1, O>(); return true;
+            case 2: f.template run<L, P, 2, O>(); return true;
+            case 4:
+                if constexpr (L <= LJC) {
+                    f.template run<L, P, 4, O>();
+                    return true;
+                }
+                return false;
+            default: return false;
+            }
         }
     };
     auto by_pot = [&](auto law_c, auto prec_c) -> bool {
@@ -157,9 +174,13 @@ static bool batched_dispatch(int law, int prec, int ipl, bool pot, F &f)
         default: return false;
         }
     };
-    if (law == GRAVITY) return by_prec(std::integral_constant<int, GRAVITY>{});
-    if (law == LJC) return by_prec(std::integral_constant<int, LJC>{});
-    return false;
+    switch (law) {
+    case GRAVITY: return by_prec(std::integral_constant<int, GRAVITY>{});
+    case LJC: return by_prec(std::integral_constant<int, LJC>{});
+    case LJC_CONST: return by_prec(std::integral_constant<int, LJC_CONST>{});
+    case LJC_SIG: return by_prec(std::integral_constant<int, LJC_SIG>{});
+    default: return false;
+    }
 }
 
 struct LaunchB {

@@ -10,11 +10,11 @@
 //            se = sqrt(eps)     so that se_i se_j = sqrt(eps_i eps_j).
 //   adjoint records append the cotangent g_j = dL/dF_j (see adjoint.hip).
 //
-// The j index of the inner loop is wave-uniform, so record loads compile to
-// scalar loads (s_load) into SGPRs and every VALU instruction of the pair
-// arithmetic takes its j operand straight from an SGPR: the j stream costs no
-// VGPRs, no LDS and no barriers.  The i-particles live in VGPRs, I of them per
-// lane (the i-unrolling of Section 3.3).
+// The j index of the inner loop is wave-uniform.  The j records reach the
+// arithmetic either through scalar loads into SGPRs (j_stage 0) or through a
+// wave-private double-buffered LDS slot read back as broadcasts (j_stage 1);
+// see allpairs.h.  The i-particles live in VGPRs, I of them per lane (the
+// i-unrolling of Section 3.3).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -24,7 +24,15 @@ namespace nbk {
 constexpr int kWave = 64;
 constexpr double kPadCoord = 1.0e18;   // position of padding records (weight 0)
 
-enum Law { GRAVITY = 0, LJC = 1 };
+enum Law { GRAVITY = 0, LJC = 1, LJC_CONST = 2, LJC_SIG = 3 };
+
+// Law constants seen by every pair: the gravity softening squared and, for
+// the sigmoidal dielectric, zeta(r) = exp(za r^3 + zb r^2 + zc r + zd) with
+// zb2 = 2 zb and za3 = 3 za precomputed for zeta'/zeta = (za3 r + zb2) r + zc.
+template <typename T> struct PairK {
+    T eps2;
+    T za, zb, zc, zd, za3, zb2;
+};
 enum Prec { P_FP64 = 0, P_KAHAN = 1, P_FP64ACC = 2, P_PLAIN = 3 };
 
 template <int PREC> struct RealOf { using type = float; };
@@ -33,9 +41,8 @@ template <> struct RealOf<P_FP64> { using type = double; };
 template <typename T> struct alignas(4 * sizeof(T)) GravRec { T x, y, z, m; };
 template <typename T> struct alignas(4 * sizeof(T)) LjcRec { T x, y, z, qs, sh, se, p0, p1; };
 
-template <typename T, int LAW> struct RecOf;
+template <typename T, int LAW> struct RecOf { using type = LjcRec<T>; };   // every LJC variant
 template <typename T> struct RecOf<T, GRAVITY> { using type = GravRec<T>; };
-template <typename T> struct RecOf<T, LJC> { using type = LjcRec<T>; };
 
 // ---------------------------------------------------------------- reciprocals
 // FP32: the hardware v_rsq_f32 / v_rcp_f32 (about 1 ulp).
@@ -43,6 +50,9 @@ template <typename T> struct RecOf<T, LJC> { using type = LjcRec<T>; };
 // convergence: y <- y (3 - x y^2) / 2 for x^-1/2, y <- y (2 - x y) for x^-1).
 __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+// e^{-y}: the hardware 2^x (v_exp_f32, about 1 ulp) of -y log2(e) in FP32; libm exp in FP64
+__device__ __forceinline__ float exp_neg_(float y) { return __builtin_amdgcn_exp2f(-1.44269504088896341f * y); }
+__device__ __forceinline__ double exp_neg_(double y) { return ::exp(-y); }
 __device__ __forceinline__ double rsqrt_(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
@@ -63,6 +73,26 @@ __device__ __forceinline__ double rcp_(double x)
 }
 __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// v clamped to [lo, hi]: one v_med3_f32 in FP32
+__device__ __forceinline__ float clamp_(float v, float lo, float hi) { return __builtin_amdgcn_fmed3f(v, lo, hi); }
+__device__ __forceinline__ double clamp_(double v, double lo, double hi)
+{
+    return __builtin_fmin(__builtin_fmax(v, lo), hi);
+}
+
+// Bounds on the sigmoidal-dielectric factors.  The exponent of zeta(r) and
+// r zeta'/zeta are clamped so that both stay finite for every pair, including
+// the zero-charge padding records at 1e18 (whose factors would otherwise be
+// 0 * inf).  The exponent bound is reached only where zeta < e^-80 or
+// zeta > e^80 (FP32; e^+-700 in FP64), i.e. for Coulomb terms below 1e-35 of
+// their unscreened value, so no physical pair is affected.
+template <typename T> struct ZetaBound;
+template <> struct ZetaBound<float> {
+    static constexpr float poly = 80.0f, rdl = 1.0e30f;
+};
+template <> struct ZetaBound<double> {
+    static constexpr double poly = 700.0, rdl = 1.0e300;
+};
 
 // ----------------------------------------------------------------- pair laws
 // Per-lane i state and the pair contribution to the four running sums
@@ -76,11 +106,11 @@ template <typename T> struct GravI { T x, y, z; };
 // 3 fma (+1 add for the potential): 19 flops, 20 with the potential
 // (multiply-add = 2, rsq = 1).
 template <bool MASK, bool POT, typename T>
-__device__ __forceinline__ void grav_pair(const GravI<T> &i, T xj, T yj, T zj, T mj, T eps2,
-                                          bool self, T (&p)[4])
+__device__ __forceinline__ void grav_pair(const GravI<T> &i, T xj, T yj, T zj, T mj,
+                                          const PairK<T> &k, bool self, T (&p)[4])
 {
     const T dx = xj - i.x, dy = yj - i.y, dz = zj - i.z;
-    T r2 = fma_(dx, dx, eps2);
+    T r2 = fma_(dx, dx, k.eps2);
     r2 = fma_(dy, dy, r2);
     r2 = fma_(dz, dz, r2);
     T m = mj;
@@ -99,15 +129,23 @@ __device__ __forceinline__ void grav_pair(const GravI<T> &i, T xj, T yj, T zj, T
 
 template <typename T> struct LjcI { T x, y, z, qs, sh, se; };
 
-// LJC(linear): p -= W d with W = 2kqq/(D r^4) + (24 e/r^2)(2 s^12/r^12 - s^6/r^6),
-// p3 += 2 u_ij = kqq/(D r^2) * 2 + 8 e ((s/r)^12 - (s/r)^6).
-// FP32 instruction count without the potential: 3 sub, 1 mul + 2 fma (r^2),
-// 1 rcp, 3 mul (qq, e, s^2 x) + 1 add (sigma) + 1 mul (sigma^2), 2 mul (s^6),
-// 1 fma (2 s6 - 1), 2 mul, 1 mul (C x), 1 fma + 1 mul (W), 3 fma: 30 flops;
-// the potential adds 2 fma + 1 add: 35 flops.
-template <bool MASK, bool POT, typename T>
+// LJ + Coulomb, F_i += W (r_i - r_j) = -W d with the Lennard-Jones part
+// (24 e x)(2 s6^2 - s6), x = 1/r^2, s6 = (sigma_ij^2 x)^3, and a Coulomb part
+// per dielectric (qs carries sqrt of the Coulomb prefactor):
+//   LJC       eps(r) = D r : W_C = qq x^2,              p3 += 2u = qq x + 8 e (s6^2 - s6)
+//   LJC_CONST eps = D      : W_C = qq / r^3,            p3 += u = qq / r + 4 e (s6^2 - s6)
+//   LJC_SIG   eps = zeta(r): W_C = qq (1 + r zeta'/zeta) / (zeta r^3),
+//                                                       p3 += u = qq / (zeta r) + 4 e (...)
+// FP32 instruction count of LJC without the potential: 3 sub, 1 mul + 2 fma
+// (r^2), 1 rcp, 3 mul (qq, e, s^2 x) + 1 add (sigma) + 1 mul (sigma^2), 2 mul
+// (s^6), 1 fma (2 s6 - 1), 2 mul, 1 mul (C x), 1 fma + 1 mul (W), 3 fma: 30
+// flops; the potential adds 2 fma + 1 add: 35.  LJC_CONST replaces the rcp by
+// rsq + 1 mul (31 / 36 flops); LJC_SIG adds r, the two polynomials, exp and
+// the (1 + r zeta'/zeta) factor (48 / 53 flops; the two clamps of the zeta
+// factors are comparisons, not counted).
+template <bool MASK, bool POT, int LAW, typename T>
 __device__ __forceinline__ void ljc_pair(const LjcI<T> &i, T xj, T yj, T zj, T qsj, T shj, T sej,
-                                         bool self, T (&p)[4])
+                                         const PairK<T> &k, bool self, T (&p)[4])
 {
     const T dx = xj - i.x, dy = yj - i.y, dz = zj - i.z;
     T r2 = dx * dx;
@@ -120,21 +158,43 @@ __device__ __forceinline__ void ljc_pair(const LjcI<T> &i, T xj, T yj, T zj, T q
         qq = self ? T(0) : qq;
         e = self ? T(0) : e;
     }
-    const T x = rcp_(r2);
+    T x, cx, wc;
+    if constexpr (LAW == LJC) {
+        x = rcp_(r2);
+        cx = qq * x;
+        wc = cx;
+    } else if constexpr (LAW == LJC_CONST) {
+        const T ri = rsqrt_(r2);
+        x = ri * ri;
+        cx = qq * ri;
+        wc = cx;
+    } else {
+        const T ri = rsqrt_(r2);
+        x = ri * ri;
+        const T r = r2 * ri;
+        T poly = fma_(fma_(fma_(k.za, r, k.zb), r, k.zc), r, k.zd);
+        poly = clamp_(poly, -ZetaBound<T>::poly, ZetaBound<T>::poly);
+        const T dl = fma_(fma_(k.za3, r, k.zb2), r, k.zc);
+        const T rdl = clamp_(r * dl, -ZetaBound<T>::rdl, ZetaBound<T>::rdl);
+        cx = (qq * ri) * exp_neg_(poly);
+        wc = fma_(cx, rdl, cx);
+    }
     const T sg = i.sh + shj;
     const T s2 = (sg * sg) * x;
     const T s6 = (s2 * s2) * s2;
     const T lj = e * s6;
     const T t = fma_(s6, T(2), T(-1));
     const T wl = lj * t;
-    const T cx = qq * x;
-    const T W = fma_(wl, T(24), cx) * x;
+    const T W = fma_(wl, T(24), wc) * x;
     p[0] = fma_(-W, dx, p[0]);
     p[1] = fma_(-W, dy, p[1]);
     p[2] = fma_(-W, dz, p[2]);
     if (POT) {
         const T v = fma_(lj, s6, -lj);       // e (s6^2 - s6)
-        p[3] += fma_(v, T(8), cx);           // 2 u_ij
+        if constexpr (LAW == LJC)
+            p[3] += fma_(v, T(8), cx);       // 2 u_ij
+        else
+            p[3] += fma_(v, T(4), cx);       // u_ij
     }
 }
 

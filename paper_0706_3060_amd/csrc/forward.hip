@@ -84,7 +84,7 @@ template <int LAW, int PREC, int I, bool POT, int JS>
 __global__ __launch_bounds__(256) void k_forces(
     const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec, int64_t npad,
     int64_t nrows, const int64_t *__restrict__ rows, int64_t split_len, int j_tile,
-    typename RealOf<PREC>::type eps2, double *__restrict__ partial, Epilogue epi)
+    PairK<typename RealOf<PREC>::type> kc, double *__restrict__ partial, Epilogue epi)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename RecOf<T, LAW>::type;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_forces(
     for (int k = 0; k < I; ++k) p[k][3] = T(0);
 
     __shared__ R lds_j[JS ? 4 : 1][2][kWave];
-    j_range<JS, POT, PREC, I>(rec, jb, je, j_tile, is, pid, eps2, acc, p,
+    j_range<JS, ForceOp<POT, LAW>, PREC, I>(rec, jb, je, j_tile, is, pid, kc, acc, p,
                               lds_j[JS ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0]);
 
 #pragma unroll
@@ -137,32 +137,55 @@ __global__ __launch_bounds__(256) void k_forces(
         }
     }
 }
+template <typename T> static PairK<T> pair_constants(const FwdLaunch &f)
+{
+    PairK<T> k;
+    k.eps2 = (T)f.eps2;
+    k.za = (T)f.zeta[0];
+    k.zb = (T)f.zeta[1];
+    k.zc = (T)f.zeta[2];
+    k.zd = (T)f.zeta[3];
+    k.za3 = (T)(3.0 * f.zeta[0]);
+    k.zb2 = (T)(2.0 * f.zeta[1]);
+    return k;
+}
+
+// rows per lane instantiated for each law: the two dielectric variants beyond
+// the linear one are built for up to 2 rows per lane
+template <int LAW> constexpr int kMaxIpl = LAW >= LJC_CONST ? 2 : 8;
+
 template <int LAW, int PREC, int I, bool POT>
-static void launch_one(const FwdLaunch &f, dim3 grid, hipStream_t s)
+static bool launch_one(const FwdLaunch &f, dim3 grid, hipStream_t s)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename RecOf<T, LAW>::type;
-    if constexpr (I <= 4) {     // LDS staging is instantiated up to 4 rows per lane
-        if (f.j_stage == 1) {
-            hipLaunchKernelGGL((k_forces<LAW, PREC, I, POT, 1>), grid, dim3(f.block), 0, s,
-                               (const R *)f.rec, f.npad, f.nrows, f.rows, f.split_len, f.j_tile,
-                               (T)f.eps2, f.j_split > 1 ? f.partial : nullptr, f.epi);
-            return;
+    if constexpr (I > kMaxIpl<LAW>) {
+        return false;
+    } else {
+        const PairK<T> kc = pair_constants<T>(f);
+        if constexpr (I <= 4) {     // LDS staging is instantiated up to 4 rows per lane
+            if (f.j_stage == 1) {
+                hipLaunchKernelGGL((k_forces<LAW, PREC, I, POT, 1>), grid, dim3(f.block), 0, s,
+                                   (const R *)f.rec, f.npad, f.nrows, f.rows, f.split_len,
+                                   f.j_tile, kc, f.j_split > 1 ? f.partial : nullptr, f.epi);
+                return true;
+            }
         }
-    }
         hipLaunchKernelGGL((k_forces<LAW, PREC, I, POT, 0>), grid, dim3(f.block), 0, s,
-                           (const R *)f.rec, f.npad, f.nrows, f.rows, f.split_len, f.j_tile,
-                           (T)f.eps2, f.j_split > 1 ? f.partial : nullptr, f.epi);
+                           (const R *)f.rec, f.npad, f.nrows, f.rows, f.split_len, f.j_tile, kc,
+                           f.j_split > 1 ? f.partial : nullptr, f.epi);
+        return true;
+    }
 }
 
 template <int LAW, int PREC, bool POT>
 static bool dispatch_ipl(const FwdLaunch &f, dim3 grid, hipStream_t s)
 {
     switch (f.ipl) {
-    case 1: launch_one<LAW, PREC, 1, POT>(f, grid, s); return true;
-    case 2: launch_one<LAW, PREC, 2, POT>(f, grid, s); return true;
-    case 4: launch_one<LAW, PREC, 4, POT>(f, grid, s); return true;
-    case 8: launch_one<LAW, PREC, 8, POT>(f, grid, s); return true;
+    case 1: return launch_one<LAW, PREC, 1, POT>(f, grid, s);
+    case 2: return launch_one<LAW, PREC, 2, POT>(f, grid, s);
+    case 4: return launch_one<LAW, PREC, 4, POT>(f, grid, s);
+    case 8: return launch_one<LAW, PREC, 8, POT>(f, grid, s);
     default: return false;
     }
 }
@@ -174,7 +197,9 @@ static bool dispatch_prec(const FwdLaunch &f, dim3 grid, hipStream_t s)
     case P_FP64: return dispatch_ipl<LAW, P_FP64, POT>(f, grid, s);
     case P_KAHAN: return dispatch_ipl<LAW, P_KAHAN, POT>(f, grid, s);
     case P_FP64ACC: return dispatch_ipl<LAW, P_FP64ACC, POT>(f, grid, s);
-    case P_PLAIN: return dispatch_ipl<LAW, P_PLAIN, POT>(f, grid, s);
+    case P_PLAIN:
+        if constexpr (LAW <= LJC) return dispatch_ipl<LAW, P_PLAIN, POT>(f, grid, s);
+        return false;
     default: return false;
     }
 }
@@ -184,10 +209,14 @@ static bool dispatch_prec(const FwdLaunch &f, dim3 grid, hipStream_t s)
 template <int LAW, int PREC, int I, bool POT>
 static const void *forces_ptr(int js)
 {
-    if constexpr (I <= 4) {
-        if (js == 1) return (const void *)&k_forces<LAW, PREC, I, POT, 1>;
+    if constexpr (I > kMaxIpl<LAW> || (LAW > LJC && PREC == P_PLAIN)) {
+        return nullptr;
+    } else {
+        if constexpr (I <= 4) {
+            if (js == 1) return (const void *)&k_forces<LAW, PREC, I, POT, 1>;
+        }
+        return (const void *)&k_forces<LAW, PREC, I, POT, 0>;
     }
-    return (const void *)&k_forces<LAW, PREC, I, POT, 0>;
 }
 
 template <int LAW, int PREC, bool POT>
@@ -216,15 +245,37 @@ static const void *forces_ptr_prec(int prec, int ipl, int js)
 
 int forces_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block)
 {
-    const void *fn = law == GRAVITY
-                         ? (pot ? forces_ptr_prec<GRAVITY, true>(prec, ipl, js)
-                                : forces_ptr_prec<GRAVITY, false>(prec, ipl, js))
-                         : (pot ? forces_ptr_prec<LJC, true>(prec, ipl, js)
-                                : forces_ptr_prec<LJC, false>(prec, ipl, js));
+    const void *fn = nullptr;
+    switch (law) {
+    case GRAVITY:
+        fn = pot ? forces_ptr_prec<GRAVITY, true>(prec, ipl, js) : forces_ptr_prec<GRAVITY, false>(prec, ipl, js);
+        break;
+    case LJC: fn = pot ? forces_ptr_prec<LJC, true>(prec, ipl, js) : forces_ptr_prec<LJC, false>(prec, ipl, js); break;
+    case LJC_CONST:
+        fn = pot ? forces_ptr_prec<LJC_CONST, true>(prec, ipl, js)
+                 : forces_ptr_prec<LJC_CONST, false>(prec, ipl, js);
+        break;
+    case LJC_SIG:
+        fn = pot ? forces_ptr_prec<LJC_SIG, true>(prec, ipl, js) : forces_ptr_prec<LJC_SIG, false>(prec, ipl, js);
+        break;
+    default: break;
+    }
     if (!fn) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, 0) != hipSuccess) return 0;
     return nb;
+}
+
+template <bool POT>
+static bool dispatch_law(const FwdLaunch &f, dim3 grid, hipStream_t s)
+{
+    switch (f.law) {
+    case GRAVITY: return dispatch_prec<GRAVITY, POT>(f, grid, s);
+    case LJC: return dispatch_prec<LJC, POT>(f, grid, s);
+    case LJC_CONST: return dispatch_prec<LJC_CONST, POT>(f, grid, s);
+    case LJC_SIG: return dispatch_prec<LJC_SIG, POT>(f, grid, s);
+    default: return false;
+    }
 }
 
 hipError_t launch_forces(const FwdLaunch &f, hipStream_t s)
@@ -233,11 +284,7 @@ hipError_t launch_forces(const FwdLaunch &f, hipStream_t s)
     const int64_t waves = (f.nrows + (int64_t)kWave * f.ipl - 1) / ((int64_t)kWave * f.ipl);
     const int64_t wpb = f.block / kWave;
     const dim3 grid((unsigned)((waves + wpb - 1) / wpb), (unsigned)f.j_split);
-    bool ok;
-    if (f.law == GRAVITY)
-        ok = f.pot ? dispatch_prec<GRAVITY, true>(f, grid, s) : dispatch_prec<GRAVITY, false>(f, grid, s);
-    else
-        ok = f.pot ? dispatch_prec<LJC, true>(f, grid, s) : dispatch_prec<LJC, false>(f, grid, s);
+    const bool ok = f.pot ? dispatch_law<true>(f, grid, s) : dispatch_law<false>(f, grid, s);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -31,6 +31,7 @@ struct FwdLaunch {
     int j_tile;
     int j_stage;                 // 0: j records through SGPRs (scalar loads); 1: through LDS into VGPRs
     double eps2;                 // gravity softening squared
+    double zeta[4];              // sigmoidal dielectric exp(z0 r^3 + z1 r^2 + z2 r + z3)
     const void *rec;             // packed records
     double *partial;             // [j_split][nrows][4] when j_split > 1
     Epilogue epi;
@@ -71,6 +72,7 @@ struct BatchLaunch {
     int j_tile;
     int j_stage;                 // as FwdLaunch::j_stage
     double eps2;
+    double zeta[4];              // as FwdLaunch::zeta
     const void *rec;
     int *ticket;                 // zeroed by launch_batched before the kernel
     Epilogue epi;
@@ -91,6 +93,7 @@ int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int b
 struct AdjLaunch {
     int law, prec, ipl;
     int block;
+    int j_stage;                 // as FwdLaunch::j_stage
     int64_t n, npad;
     int64_t split_len;
     int j_split, j_tile;

@@ -20,7 +20,7 @@ import torch
 
 from . import _native as N
 
-GRAVITY, LJC_LINEAR = 0, 1
+GRAVITY, LJC_LINEAR, LJC_CONSTANT, LJC_SIGMOIDAL = 0, 1, 2, 3
 FP64, FP32_KAHAN, FP32_FP64ACC, FP32_PLAIN = 0, 1, 2, 3
 API_FORCES, API_BATCHED, API_BACKWARD, API_LEAPFROG = (N.API_FORCES, N.API_BATCHED,
                                                        N.API_BACKWARD, N.API_LEAPFROG)
@@ -36,10 +36,11 @@ class Law:
     softening: float = 0.0
     coulomb_k: float = 332.0637
     dielectric: float = 4.0
+    zeta: tuple = (0.0, 0.0, 0.0, 0.0)
 
     def c(self) -> N.NBodyLaw:
         return N.NBodyLaw(self.kind, self.precision, self.G, self.softening, self.coulomb_k,
-                          self.dielectric)
+                          self.dielectric, (ctypes.c_double * 4)(*[float(z) for z in self.zeta]))
 
     @property
     def n_params(self) -> int:
@@ -51,8 +52,24 @@ def gravity(precision=FP32_FP64ACC, G=1.0, softening=0.0) -> Law:
 
 
 def ljc_linear(precision=FP32_FP64ACC, coulomb_k=332.0637, dielectric=4.0) -> Law:
+    """Table 1 LJC(linear): Coulomb with dielectric D r plus Lennard-Jones."""
     return Law(LJC_LINEAR, PRECISIONS.get(precision, precision), 1.0, 0.0, float(coulomb_k),
                float(dielectric))
+
+
+def ljc_constant(precision=FP32_FP64ACC, coulomb_k=332.0637, dielectric=4.0) -> Law:
+    """Table 1 LJC(constant): Coulomb with a constant dielectric D plus Lennard-Jones."""
+    return Law(LJC_CONSTANT, PRECISIONS.get(precision, precision), 1.0, 0.0, float(coulomb_k),
+               float(dielectric))
+
+
+def ljc_sigmoidal(zeta, precision=FP32_FP64ACC, coulomb_k=332.0637) -> Law:
+    """Table 1 LJC(sigmoidal): dielectric zeta(r) = exp(z0 r^3 + z1 r^2 + z2 r + z3)."""
+    z = tuple(float(v) for v in zeta)
+    if len(z) != 4:
+        raise ValueError("zeta needs four coefficients")
+    return Law(LJC_SIGMOIDAL, PRECISIONS.get(precision, precision), 1.0, 0.0, float(coulomb_k),
+               1.0, z)
 
 
 # ------------------------------------------------------------------ helpers
@@ -177,7 +194,7 @@ def forces_backward(pos, params, grad_force, law: Law, want_pos=True, want_param
     par = _params(params, n, law, pos.device)
     g = _dev_f64(grad_force, (n, 3), "grad_force")
     if want_params is None:
-        want_params = law.kind == LJC_LINEAR
+        want_params = law.kind != GRAVITY
     dev = pos.device
     gp = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_pos else None
     gq = torch.empty((n, law.n_params), dtype=torch.float64, device=dev) if want_params else None

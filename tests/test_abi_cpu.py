@@ -74,7 +74,7 @@ def test_workspace_bytes(N):
     assert lib.nbody_workspace_bytes(0, 4096, 1, ctypes.byref(f64)) > \
         lib.nbody_workspace_bytes(0, 4096, 1, ctypes.byref(g)) - 4096 * 16
     assert lib.nbody_workspace_bytes(1, 10000, 50, ctypes.byref(law(N, kind=1))) > 10000 * 32
-    assert lib.nbody_workspace_bytes(2, 8192, 1, ctypes.byref(law(N, kind=1))) >= 8192 * 48
+    assert lib.nbody_workspace_bytes(2, 8192, 1, ctypes.byref(law(N, kind=1))) >= 8192 * 64
     assert lib.nbody_workspace_bytes(3, 8192, 1, ctypes.byref(g)) > \
         lib.nbody_workspace_bytes(0, 8192, 1, ctypes.byref(g))
 

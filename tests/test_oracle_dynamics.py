@@ -202,3 +202,29 @@ def test_adjoint_subset_rows(oracle_mod):
     pg, mg = _grav_sys(20, 18)
     gg = oracle_mod.gravity_adjoint(pg, mg, g, eps=0.1)
     np.testing.assert_array_equal(oracle_mod.gravity_adjoint(pg, mg, g, eps=0.1, ilist=il), gg[il])
+
+
+def test_ljc_constant_leapfrog_conserves_energy(oracle_mod):
+    # an ion pair (opposite charges, constant dielectric) bound against the LJ
+    # wall: energy, momentum conserved over many oscillations
+    pos = np.array([[0.0, 0.0, 0.0], [0.0, 4.6, 0.3]])
+    vel = np.zeros((2, 3))
+    par = np.array([[0.4, 3.2, 0.1], [-0.4, 3.6, 0.15]])
+    mass = np.array([23.0, 35.5])
+    inv_mass = 1.0 / mass
+    f, u = oracle_mod.ljc_constant(pos, par[:, 0], par[:, 1], par[:, 2], D=4.0)
+    e0 = 0.5 * u.sum()
+    x, v, a, pot = oracle_mod.leapfrog(oracle_mod.LJC_CONSTANT, pos, vel, f * inv_mass[:, None], par,
+                                       0.005, 4000, inv_mass=inv_mass, D=4.0)
+    e1 = 0.5 * (mass * (v * v).sum(1)).sum() + 0.5 * pot.sum()
+    assert abs(e1 - e0) < 1e-4 * abs(e0)
+    np.testing.assert_allclose((mass[:, None] * v).sum(0), 0, atol=1e-12)
+    assert np.abs(v).max() > 1e-2
+    # one step equals the hand-written kick-drift-kick around the oracle's forces
+    x1, v1, a1, _ = oracle_mod.leapfrog(oracle_mod.LJC_CONSTANT, pos, vel, f * inv_mass[:, None], par,
+                                        0.005, 1, inv_mass=inv_mass, D=4.0)
+    vh = vel + 0.0025 * f * inv_mass[:, None]
+    xe = pos + 0.005 * vh
+    fe, _ = oracle_mod.ljc_constant(xe, par[:, 0], par[:, 1], par[:, 2], D=4.0)
+    np.testing.assert_allclose(x1, xe, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(v1, vh + 0.0025 * fe * inv_mass[:, None], rtol=1e-13, atol=1e-16)
