@@ -5,10 +5,11 @@
  * paper (Elsen et al., "N-Body Simulations on GPUs") identifies as the major
  * cost of stellar and molecular dynamics steps (Section 1; the all-pairs
  * pseudo-code and its stream form in Section 2), followed by the update step
- * (Section 1).  Two pair laws are provided:
+ * (Section 1).  The pair laws are those of Table 1:
  *
  *   NBODY_LAW_GRAVITY     softened gravity, Eq. 1 (Section 3.3) and Table 1
- *                         "Gravity (accel)":
+ *                         "Gravity (accel)"; with nbody_forces_jerk also its
+ *                         time derivative, Table 1 "Gravity (accel & jerk)":
  *                           a_i   =  G sum_{j!=i} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2}
  *                           phi_i = -G sum_{j!=i} m_j / (|r_j - r_i|^2 + eps^2)^{1/2}
  *   NBODY_LAW_LJC_LINEAR  Lennard-Jones + Coulomb with the linear distance-
@@ -20,6 +21,12 @@
  *                           F_i = sum_{j!=i} [2 k q_i q_j/(D r^4)
  *                                 + (24 e_ij/r^2)(2 (s_ij/r)^12 - (s_ij/r)^6)] (r_i - r_j)
  *                           U_i = sum_{j!=i} u_ij     (total energy = 1/2 sum_i U_i)
+ *   NBODY_LAW_LJC_CONSTANT, NBODY_LAW_LJC_SIGMOIDAL   the constant and sigmoidal
+ *                         dielectrics of Table 1 (see nbody_law).
+ *
+ * Updates: kick-drift-kick leapfrog (leapfrog_step) and the fourth-order
+ * Hermite scheme on acceleration and jerk, with a shared step (hermite_step)
+ * or block individual steps (hermite_block_steps).
  *
  * Every i interacts with every j != i: all N^2 ordered pairs are evaluated
  * and no pair is scattered to both partners (Section 2, the remark on
@@ -112,7 +119,9 @@ enum nbody_api {
     NBODY_API_FORCES = 0,
     NBODY_API_BATCHED = 1,
     NBODY_API_BACKWARD = 2,
-    NBODY_API_LEAPFROG = 3
+    NBODY_API_LEAPFROG = 3,
+    NBODY_API_JERK = 4,       /* nbody_forces_jerk */
+    NBODY_API_HERMITE = 5     /* hermite_step, hermite_block_steps */
 };
 
 /* Launch configuration of the all-pairs kernels (see nbody_set_config).
@@ -214,6 +223,75 @@ int leapfrog_step(double *pos, double *vel, double *acc, const double *params,
                   int32_t nsteps, double *out_potential, void *ws, size_t ws_bytes,
                   void *stream);
 
+/* Acceleration, jerk and potential of softened gravity (Table 1 "Gravity
+ * (accel & jerk)", the GAJ kernel of Section 2), for every particle or for an
+ * index list of them:
+ *   a_i    =  G sum_{j!=i} m_j d / s^3
+ *   jerk_i =  G sum_{j!=i} m_j [ w / s^3 - 3 (d.w) d / s^5 ]
+ *   phi_i  = -G sum_{j!=i} m_j / s,
+ *   d = r_j - r_i,  w = v_j - v_i,  s^2 = |d|^2 + eps^2.
+ *  pos, vel   [n][3] device; mass [n] device.
+ *  ilist      [ni] device int64 indices in [0, n) (repeats allowed), or NULL
+ *             for every particle (then ni must equal n).  Row k of the
+ *             outputs belongs to particle ilist[k].
+ *  law        host; kind NBODY_LAW_GRAVITY; precision NBODY_FP64,
+ *             NBODY_FP32_FP64ACC or NBODY_FP32_KAHAN (else NBODY_ENOTSUP).
+ *  out_acc, out_jerk [ni][3] device; out_potential [ni] device or NULL.
+ * Workspace: nbody_workspace_bytes(NBODY_API_JERK, max(n, ni), 1, law). */
+int nbody_forces_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                      const int64_t *ilist, int64_t ni, const nbody_law *law, double *out_acc,
+                      double *out_jerk, double *out_potential, void *ws, size_t ws_bytes,
+                      void *stream);
+
+/* `nsteps` shared steps h = dt of the fourth-order Hermite predictor-
+ * corrector (Makino & Aarseth 1992), the integrator that acceleration and
+ * jerk serve (the paper names none):
+ *   predict  xp = x + v h + a h^2/2 + j h^3/6,  vp = v + a h + j h^2/2
+ *   a1, j1 = acceleration and jerk at (xp, vp) of every particle
+ *   a2 = (-6 (a - a1) - h (4 j + 2 j1)) / h^2,  a3 = (12 (a - a1) + 6 h (j + j1)) / h^3
+ *   correct  x = xp + a2 h^4/24 + a3 h^5/120,  v = vp + a2 h^3/6 + a3 h^4/24,
+ *            a = a1, jerk = j1.
+ *  pos, vel, acc, jerk [n][3] device, updated in place; acc and jerk hold
+ *  the values at the entry state (e.g. from nbody_forces_jerk).  mass [n]
+ *  device.  law as nbody_forces_jerk.  dt > 0 finite, nsteps >= 0.  The
+ *  update is FP64; the pair arithmetic follows law->precision.
+ * Workspace: nbody_workspace_bytes(NBODY_API_HERMITE, n, 1, law). */
+int hermite_step(double *pos, double *vel, double *acc, double *jerk, const double *mass,
+                 int64_t n, const nbody_law *law, double dt, int32_t nsteps, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* Initial block time steps for hermite_block_steps: t_i = 0 and dt_i = the
+ * largest dt_max / 2^k not above eta_s |a_i| / |jerk_i| (dt_max where
+ * jerk_i = 0).  acc, jerk [n][3] device; t_i, dt_i [n] device outputs.
+ * dt_max must be a power of two; eta_s > 0. */
+int hermite_block_init(const double *acc, const double *jerk, int64_t n, double eta_s,
+                       double dt_max, double *t_i, double *dt_i, void *stream);
+
+/* `nblocks` block steps of the Hermite scheme with individual block time
+ * steps: the setting in which Section 3.4 evaluates forces on a subset of
+ * the particles.  One block step:
+ *   t = min_i (t_i + dt_i); the due set A = { i : t_i + dt_i == t };
+ *   every particle is predicted to t from its own t_i (predictor above);
+ *   acceleration and jerk of each i in A against all predicted particles;
+ *   each i in A is corrected over h = dt_i, gets t_i = t and the next step
+ *     dt* = sqrt(eta (|a1| |a2'| + |j1|^2) / (|j1| |a3| + |a2'|^2)),
+ *     a2' = a2 + a3 h (Aarseth's criterion), quantised to the largest
+ *     dt_max / 2^k <= dt* that is at most 2 h and divides t.
+ *  pos, vel, acc, jerk [n][3], t_i, dt_i [n]: device, updated in place
+ *    (t_i, dt_i from hermite_block_init or a previous call).
+ *  mass [n] device; law as nbody_forces_jerk; eta > 0; dt_max as given to
+ *    hermite_block_init (a power of two).
+ *  active_counts host int64 [nblocks] or NULL: |A| of each block step.
+ *  t_now host or NULL: the time of the last block step.
+ * The scheduling (the next time and the due list, in increasing index order)
+ * runs on the device; the call synchronises `stream` once per block step to
+ * size the launches by |A|.
+ * Workspace: nbody_workspace_bytes(NBODY_API_HERMITE, n, 1, law). */
+int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, double *t_i,
+                        double *dt_i, const double *mass, int64_t n, const nbody_law *law,
+                        double eta, double dt_max, int32_t nblocks, int64_t *active_counts,
+                        double *t_now, void *ws, size_t ws_bytes, void *stream);
+
 /* Workspace size in bytes needed by entry point `api` for `n_total`
  * particles in `n_systems` systems (1 for the single-system entry points).
  * Returns 0 when the arguments are invalid. */
@@ -247,6 +325,14 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
                    const double *params, int64_t n, const nbody_law *law, double *out_force,
                    double *out_potential, void *ws, size_t ws_bytes, void *stream,
                    nbody_config *out_best, double *out_ms);
+
+/* As nbody_autotune for nbody_forces_jerk over all n particles (arguments as
+ * nbody_forces_jerk with ilist = NULL); the winner is remembered for
+ * NBODY_API_JERK and used by the Hermite steps of the same size class. */
+int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                        const nbody_law *law, double *out_acc, double *out_jerk,
+                        double *out_potential, void *ws, size_t ws_bytes, void *stream,
+                        nbody_config *out_best, double *out_ms);
 
 /* Save / load the tuning cache as a small JSON file (host path). */
 int nbody_tune_save(const char *path);

@@ -20,7 +20,13 @@ counterpart cites:
 * :func:`leapfrog` -- the force-then-update cycle of Section 1 as
   kick-drift-kick leapfrog;
 * :func:`gravity_adjoint`, :func:`ljc_adjoint` -- derivatives of the two laws
-  (not in the paper; written out from the definitions above).
+  (not in the paper; written out from the definitions above);
+* :func:`gravity_jerk` -- Table 1 "Gravity (accel & jerk)", the GAJ kernel of
+  Section 2;
+* :func:`hermite`, :func:`hermite_block_init`, :func:`hermite_block` -- the
+  fourth-order Hermite scheme that consumes acceleration and jerk, with a
+  shared step or with block individual steps (the particle-subset setting of
+  Section 3.4).
 """
 from __future__ import annotations
 
@@ -69,9 +75,15 @@ def _load():
         lib.oracle_leapfrog.argtypes = [I, P, P, P, P, P, I64, D, D, D, ctypes.c_int32, P, I]
         lib.oracle_gravity_adjoint.argtypes = [P, P, I64, D, D, P, P, I64, P, I]
         lib.oracle_ljc_adjoint.argtypes = [P, P, P, P, I64, D, D, P, P, I64, P, P, P, P, I]
+        lib.oracle_gravity_jerk.argtypes = [P, P, P, I64, D, D, P, I64, P, P, P, I]
+        lib.oracle_hermite.argtypes = [P, P, P, P, P, I64, D, D, D, ctypes.c_int32, I]
+        lib.oracle_hermite_block_init.argtypes = [P, P, I64, D, D, P, P]
+        lib.oracle_hermite_block.argtypes = [P, P, P, P, P, P, P, I64, D, D, D, D,
+                                             ctypes.c_int32, P, P, I]
         for f in (lib.oracle_gravity, lib.oracle_ljc_linear, lib.oracle_ljc_constant,
                   lib.oracle_ljc_sigmoidal, lib.oracle_leapfrog,
-                  lib.oracle_gravity_adjoint, lib.oracle_ljc_adjoint):
+                  lib.oracle_gravity_adjoint, lib.oracle_ljc_adjoint, lib.oracle_gravity_jerk,
+                  lib.oracle_hermite, lib.oracle_hermite_block_init, lib.oracle_hermite_block):
             f.restype = I
         _lib = lib
     return _lib
@@ -242,3 +254,73 @@ def ljc_adjoint(pos, q, sigma, epsilon, g, kc=332.0637, D=4.0, ilist=None, nthre
     if rc:
         raise ValueError("oracle_ljc_adjoint rc=%d" % rc)
     return gp, gq, gs, ge
+
+
+def gravity_jerk(pos, vel, mass, G=1.0, eps=0.0, ilist=None, nthreads=0):
+    """(acc [ni,3], jerk [ni,3], phi [ni]) of Table 1's "Gravity (accel & jerk)"."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    pos = _f64(pos, (n, 3))
+    vel = _f64(vel, (n, 3))
+    mass = _f64(mass, (n,))
+    il, ni = _ilist(ilist, n)
+    acc = np.empty((ni, 3))
+    jerk = np.empty((ni, 3))
+    phi = np.empty(ni)
+    rc = _load().oracle_gravity_jerk(_ptr(pos), _ptr(vel), _ptr(mass), n, float(G), float(eps),
+                                     _ptr(il), ni, _ptr(acc), _ptr(jerk), _ptr(phi), int(nthreads))
+    if rc:
+        raise ValueError("oracle_gravity_jerk rc=%d" % rc)
+    return acc, jerk, phi
+
+
+def hermite(pos, vel, acc, jerk, mass, dt, nsteps, G=1.0, eps=0.0, nthreads=0):
+    """Shared-step fourth-order Hermite: returns (pos, vel, acc, jerk) after nsteps."""
+    pos = _f64(pos).copy()
+    n = pos.shape[0]
+    vel = _f64(vel, (n, 3)).copy()
+    acc = _f64(acc, (n, 3)).copy()
+    jerk = _f64(jerk, (n, 3)).copy()
+    mass = _f64(mass, (n,))
+    rc = _load().oracle_hermite(_ptr(pos), _ptr(vel), _ptr(acc), _ptr(jerk), _ptr(mass), n,
+                                float(G), float(eps), float(dt), int(nsteps), int(nthreads))
+    if rc:
+        raise ValueError("oracle_hermite rc=%d" % rc)
+    return pos, vel, acc, jerk
+
+
+def hermite_block_init(acc, jerk, eta_s, dt_max):
+    """Initial block steps (t_i = 0, dt_i quantised from eta_s |a| / |jerk|)."""
+    acc = _f64(acc)
+    n = acc.shape[0]
+    jerk = _f64(jerk, (n, 3))
+    t = np.empty(n)
+    dt = np.empty(n)
+    rc = _load().oracle_hermite_block_init(_ptr(acc), _ptr(jerk), n, float(eta_s), float(dt_max),
+                                           _ptr(t), _ptr(dt))
+    if rc:
+        raise ValueError("oracle_hermite_block_init rc=%d" % rc)
+    return t, dt
+
+
+def hermite_block(pos, vel, acc, jerk, t_i, dt_i, mass, nblocks, eta, dt_max, G=1.0, eps=0.0,
+                  nthreads=0):
+    """nblocks block steps of the individual-step Hermite scheme.  Returns
+    (pos, vel, acc, jerk, t_i, dt_i, active_counts [nblocks], t_now)."""
+    pos = _f64(pos).copy()
+    n = pos.shape[0]
+    vel = _f64(vel, (n, 3)).copy()
+    acc = _f64(acc, (n, 3)).copy()
+    jerk = _f64(jerk, (n, 3)).copy()
+    t_i = _f64(t_i, (n,)).copy()
+    dt_i = _f64(dt_i, (n,)).copy()
+    mass = _f64(mass, (n,))
+    active = np.zeros(max(int(nblocks), 1), dtype=np.int64)
+    t_now = ctypes.c_double(0.0)
+    rc = _load().oracle_hermite_block(_ptr(pos), _ptr(vel), _ptr(acc), _ptr(jerk), _ptr(t_i),
+                                      _ptr(dt_i), _ptr(mass), n, float(G), float(eps), float(eta),
+                                      float(dt_max), int(nblocks), _ptr(active),
+                                      ctypes.byref(t_now), int(nthreads))
+    if rc:
+        raise ValueError("oracle_hermite_block rc=%d" % rc)
+    return pos, vel, acc, jerk, t_i, dt_i, active[:int(nblocks)], t_now.value

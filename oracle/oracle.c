@@ -430,3 +430,228 @@ int oracle_ljc_adjoint(const double *pos, const double *q, const double *sigma, 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Softened gravity with its time derivative, Table 1 row "Gravity (accel &
+ * jerk)"; Section 2 names this kernel (GAJ) for integration schemes that use
+ * the derivative of the force.  With d = r_j - r_i, w = v_j - v_i and
+ * s^2 = |d|^2 + eps^2:
+ *   a_i    = G sum_{j != i} m_j d / s^3
+ *   jerk_i = G sum_{j != i} m_j [ w / s^3 - 3 (d.w) d / s^5 ]
+ *   phi_i  = -G sum_{j != i} m_j / s
+ * (jerk_i is d a_i / dt along the motion: the derivative of d / s^3 with
+ * d' = w and s' = (d.w) / s).  acc and jerk are [ni][3], phi [ni] or NULL.
+ * ---------------------------------------------------------------------- */
+int oracle_gravity_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                        double G, double eps, const int64_t *ilist, int64_t ni, double *acc,
+                        double *jerk, double *phi, int nthreads)
+{
+    if (n < 0 || ni < 0) return -1;
+    set_threads(nthreads);
+    const double eps2 = eps * eps;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < ni; ++k) {
+        const int64_t i = row(ilist, k);
+        nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0}, jx = {0, 0}, jy = {0, 0}, jz = {0, 0},
+             ph = {0, 0};
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = pos[3 * j] - pos[3 * i];
+            const double dy = pos[3 * j + 1] - pos[3 * i + 1];
+            const double dz = pos[3 * j + 2] - pos[3 * i + 2];
+            const double wx = vel[3 * j] - vel[3 * i];
+            const double wy = vel[3 * j + 1] - vel[3 * i + 1];
+            const double wz = vel[3 * j + 2] - vel[3 * i + 2];
+            const double s2 = dx * dx + dy * dy + dz * dz + eps2;
+            const double s = sqrt(s2);
+            const double inv_s3 = 1.0 / (s2 * s);
+            const double inv_s5 = inv_s3 / s2;
+            const double dw = dx * wx + dy * wy + dz * wz;
+            nadd(&ax, mass[j] * dx * inv_s3);
+            nadd(&ay, mass[j] * dy * inv_s3);
+            nadd(&az, mass[j] * dz * inv_s3);
+            nadd(&jx, mass[j] * (wx * inv_s3 - 3.0 * dw * dx * inv_s5));
+            nadd(&jy, mass[j] * (wy * inv_s3 - 3.0 * dw * dy * inv_s5));
+            nadd(&jz, mass[j] * (wz * inv_s3 - 3.0 * dw * dz * inv_s5));
+            nadd(&ph, mass[j] / s);
+        }
+        acc[3 * k] = G * nval(&ax);
+        acc[3 * k + 1] = G * nval(&ay);
+        acc[3 * k + 2] = G * nval(&az);
+        jerk[3 * k] = G * nval(&jx);
+        jerk[3 * k + 1] = G * nval(&jy);
+        jerk[3 * k + 2] = G * nval(&jz);
+        if (phi) phi[k] = -G * nval(&ph);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Fourth-order Hermite predictor-corrector (Makino & Aarseth 1992), the
+ * integrator that the acceleration-and-jerk kernel serves.  The paper names
+ * no integrator; this scheme is the reading.  For one particle advanced by
+ * h from (x0, v0, a0, j0), with a1, j1 evaluated at the predicted state:
+ *   predict  xp = x0 + v0 h + a0 h^2/2 + j0 h^3/6,   vp = v0 + a0 h + j0 h^2/2
+ *   a2 = (-6 (a0 - a1) - h (4 j0 + 2 j1)) / h^2      (second derivative of a at t0)
+ *   a3 = (12 (a0 - a1) + 6 h (j0 + j1)) / h^3        (third derivative)
+ *   correct  x1 = xp + a2 h^4/24 + a3 h^5/120,  v1 = vp + a2 h^3/6 + a3 h^4/24
+ * ---------------------------------------------------------------------- */
+static void hermite_predict(const double *x, const double *v, const double *a, const double *j,
+                            double h, double *xp, double *vp)
+{
+    for (int c = 0; c < 3; ++c) {
+        xp[c] = x[c] + h * (v[c] + h * (a[c] / 2.0 + h * j[c] / 6.0));
+        vp[c] = v[c] + h * (a[c] + h * j[c] / 2.0);
+    }
+}
+
+/* corrector; writes x1, v1 and the derivatives a2 (moved to t1: a2 + a3 h)
+ * and a3 used by the time-step criterion */
+static void hermite_correct(const double *xp, const double *vp, const double *a0, const double *j0,
+                            const double *a1, const double *j1, double h, double *x1, double *v1,
+                            double *a2_t1, double *a3_out)
+{
+    for (int c = 0; c < 3; ++c) {
+        const double a2 = (-6.0 * (a0[c] - a1[c]) - h * (4.0 * j0[c] + 2.0 * j1[c])) / (h * h);
+        const double a3 = (12.0 * (a0[c] - a1[c]) + 6.0 * h * (j0[c] + j1[c])) / (h * h * h);
+        x1[c] = xp[c] + h * h * h * h * (a2 / 24.0 + h * a3 / 120.0);
+        v1[c] = vp[c] + h * h * h * (a2 / 6.0 + h * a3 / 24.0);
+        if (a2_t1) a2_t1[c] = a2 + a3 * h;
+        if (a3_out) a3_out[c] = a3;
+    }
+}
+
+/* Shared time step: nsteps steps of dt for all particles.  acc and jerk hold
+ * a and jerk at the current state on entry and are replaced by the values at
+ * the last predicted state on exit (the PEC scheme). */
+int oracle_hermite(double *pos, double *vel, double *acc, double *jerk, const double *mass,
+                   int64_t n, double G, double eps, double dt, int32_t nsteps, int nthreads)
+{
+    if (n < 0 || nsteps < 0 || !(dt > 0.0)) return -1;
+    double *xp = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double *vp = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double *a1 = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double *j1 = (double *)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    if (!xp || !vp || !a1 || !j1) {
+        free(xp), free(vp), free(a1), free(j1);
+        return -2;
+    }
+    int rc = 0;
+    for (int32_t s = 0; s < nsteps && rc == 0; ++s) {
+        for (int64_t i = 0; i < n; ++i)
+            hermite_predict(pos + 3 * i, vel + 3 * i, acc + 3 * i, jerk + 3 * i, dt, xp + 3 * i,
+                            vp + 3 * i);
+        rc = oracle_gravity_jerk(xp, vp, mass, n, G, eps, NULL, n, a1, j1, NULL, nthreads);
+        for (int64_t i = 0; rc == 0 && i < n; ++i) {
+            hermite_correct(xp + 3 * i, vp + 3 * i, acc + 3 * i, jerk + 3 * i, a1 + 3 * i,
+                            j1 + 3 * i, dt, pos + 3 * i, vel + 3 * i, NULL, NULL);
+            for (int c = 0; c < 3; ++c) {
+                acc[3 * i + c] = a1[3 * i + c];
+                jerk[3 * i + c] = j1[3 * i + c];
+            }
+        }
+    }
+    free(xp), free(vp), free(a1), free(j1);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Block (hierarchical) individual time steps for the Hermite scheme: the
+ * setting in which Section 3.4 needs forces on a subset of the particles at
+ * a time.  Every particle i carries its own time t_i and step dt_i, a power
+ * of two fraction of dt_max (itself a power of two).  One block step:
+ *   t = min_i (t_i + dt_i);  the active set is { i : t_i + dt_i == t }
+ *   every particle is predicted to t from its own t_j (the predictor above)
+ *   a and jerk of each active i are evaluated against all predicted j
+ *   each active i is corrected with h = dt_i and gets t_i = t and a new step
+ * New step (Aarseth's criterion, with a2' = a2 + a3 h the second derivative
+ * at t):  dt* = sqrt( eta (|a1| |a2'| + |j1|^2) / (|j1| |a3| + |a2'|^2) ),
+ * quantised to the largest dt_max / 2^k <= dt* that is at most twice the old
+ * step and divides t.  Initial steps: dt* = eta_s |a| / |j|, quantised the
+ * same way at t = 0.
+ * ---------------------------------------------------------------------- */
+static double norm3(const double *v) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+static double quantise_step(double dts, double dt_max, double t, double dt_old)
+{
+    double h = dt_max;
+    int k = 0;
+    while (h > dts && k < 60) {
+        h *= 0.5;
+        ++k;
+    }
+    if (dt_old > 0.0 && h > 2.0 * dt_old) h = 2.0 * dt_old;
+    while (fmod(t, h) != 0.0 && k < 60) {
+        h *= 0.5;
+        ++k;
+    }
+    return h;
+}
+
+int oracle_hermite_block_init(const double *acc, const double *jerk, int64_t n, double eta_s,
+                              double dt_max, double *t_i, double *dt_i)
+{
+    if (n < 0 || !(dt_max > 0.0)) return -1;
+    for (int64_t i = 0; i < n; ++i) {
+        const double aj = norm3(jerk + 3 * i);
+        const double dts = aj > 0.0 ? eta_s * norm3(acc + 3 * i) / aj : dt_max;
+        t_i[i] = 0.0;
+        dt_i[i] = quantise_step(dts, dt_max, 0.0, 0.0);
+    }
+    return 0;
+}
+
+/* nblocks block steps.  pos, vel, acc, jerk, t_i, dt_i are per particle and
+ * updated for the active particles of each block step; active[b] (or NULL)
+ * receives the size of the active set of block step b and t_now the time
+ * reached. */
+int oracle_hermite_block(double *pos, double *vel, double *acc, double *jerk, double *t_i,
+                         double *dt_i, const double *mass, int64_t n, double G, double eps,
+                         double eta, double dt_max, int32_t nblocks, int64_t *active,
+                         double *t_now, int nthreads)
+{
+    if (n <= 0 || nblocks < 0 || !(dt_max > 0.0)) return -1;
+    const size_t sz = sizeof(double) * 3 * (size_t)n;
+    double *xp = (double *)malloc(sz), *vp = (double *)malloc(sz);
+    double *a1 = (double *)malloc(sz), *j1 = (double *)malloc(sz);
+    int64_t *il = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+    if (!xp || !vp || !a1 || !j1 || !il) {
+        free(xp), free(vp), free(a1), free(j1), free(il);
+        return -2;
+    }
+    int rc = 0;
+    double t = 0.0;
+    for (int32_t b = 0; b < nblocks && rc == 0; ++b) {
+        t = t_i[0] + dt_i[0];
+        for (int64_t i = 1; i < n; ++i)
+            if (t_i[i] + dt_i[i] < t) t = t_i[i] + dt_i[i];
+        int64_t na = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (t_i[i] + dt_i[i] == t) il[na++] = i;
+        if (active) active[b] = na;
+        for (int64_t i = 0; i < n; ++i)
+            hermite_predict(pos + 3 * i, vel + 3 * i, acc + 3 * i, jerk + 3 * i, t - t_i[i],
+                            xp + 3 * i, vp + 3 * i);
+        rc = oracle_gravity_jerk(xp, vp, mass, n, G, eps, il, na, a1, j1, NULL, nthreads);
+        for (int64_t k = 0; rc == 0 && k < na; ++k) {
+            const int64_t i = il[k];
+            const double h = dt_i[i];
+            double a2[3], a3[3];
+            hermite_correct(xp + 3 * i, vp + 3 * i, acc + 3 * i, jerk + 3 * i, a1 + 3 * k,
+                            j1 + 3 * k, h, pos + 3 * i, vel + 3 * i, a2, a3);
+            for (int c = 0; c < 3; ++c) {
+                acc[3 * i + c] = a1[3 * k + c];
+                jerk[3 * i + c] = j1[3 * k + c];
+            }
+            const double na1 = norm3(a1 + 3 * k), nj1 = norm3(j1 + 3 * k);
+            const double na2 = norm3(a2), na3 = norm3(a3);
+            const double den = nj1 * na3 + na2 * na2;
+            const double dts = den > 0.0 ? sqrt(eta * (na1 * na2 + nj1 * nj1) / den) : dt_max;
+            t_i[i] = t;
+            dt_i[i] = quantise_step(dts, dt_max, t, h);
+        }
+    }
+    if (t_now) *t_now = t;
+    free(xp), free(vp), free(a1), free(j1), free(il);
+    return rc;
+}

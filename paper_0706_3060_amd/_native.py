@@ -23,13 +23,15 @@ NBODY_ENOTSUP = -2
 NBODY_EWORKSPACE = -3
 NBODY_EHIP = -4
 
-API_FORCES, API_BATCHED, API_BACKWARD, API_LEAPFROG = 0, 1, 2, 3
+API_FORCES, API_BATCHED, API_BACKWARD, API_LEAPFROG, API_JERK, API_HERMITE = 0, 1, 2, 3, 4, 5
 
 EXPORTED = (
     "nbody_forces", "nbody_forces_subset", "nbody_forces_batched", "nbody_forces_backward",
     "leapfrog_step", "nbody_workspace_bytes", "nbody_last_error", "nbody_set_config",
     "nbody_get_config", "nbody_autotune", "nbody_tune_save", "nbody_tune_load",
     "nbody_timing_enable", "nbody_timing_read", "nbody_flops_per_pair", "nbody_version",
+    "nbody_forces_jerk", "hermite_step", "hermite_block_init", "hermite_block_steps",
+    "nbody_autotune_jerk",
 )
 
 
@@ -85,6 +87,13 @@ def lib():
                                   ctypes.c_int),
             "nbody_flops_per_pair": ([I32, I32, I32], I32),
             "nbody_version": ([], ctypes.c_char_p),
+            "nbody_forces_jerk": ([P, P, P, I64, P, I64, LAW, P, P, P, P, SZ, P], ctypes.c_int),
+            "hermite_step": ([P, P, P, P, P, I64, LAW, D, I32, P, SZ, P], ctypes.c_int),
+            "hermite_block_init": ([P, P, I64, D, D, P, P, P], ctypes.c_int),
+            "hermite_block_steps": ([P, P, P, P, P, P, P, I64, LAW, D, D, I32, P, P, P, SZ, P],
+                                    ctypes.c_int),
+            "nbody_autotune_jerk": ([P, P, P, I64, LAW, P, P, P, P, SZ, P, CFG,
+                                     ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)

@@ -61,8 +61,6 @@ size_t adj_rec_bytes(int law, int prec)
     return law == NBODY_LAW_GRAVITY ? 8 * t : 16 * t;
 }
 
-int params_per_particle(int law) { return law == NBODY_LAW_GRAVITY ? 1 : 3; }
-
 int max_split(int64_t npad)
 {
     if (npad <= 0) return 1;
@@ -107,8 +105,9 @@ struct Cfg {
 };
 
 std::mutex g_mu;
-bool g_override_set[4] = {false, false, false, false};
-Cfg g_override[4];
+constexpr int kNumApi = 6;
+bool g_override_set[kNumApi] = {false, false, false, false, false, false};
+Cfg g_override[kNumApi];
 
 using TuneKey = std::tuple<int, int, int, int, int, int>;   // api, law, prec, pot, nbucket, sbucket
 std::map<TuneKey, std::pair<Cfg, double>> g_tuned;
@@ -132,6 +131,7 @@ Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
 {
     c.ipl = std::min(c.ipl, max_ipl(api, prec));
     if (law >= NBODY_LAW_LJC_CONSTANT) c.ipl = std::min(c.ipl, 2);
+    if (api == NBODY_API_JERK || api == NBODY_API_HERMITE) c.ipl = std::min(c.ipl, 2);
     if (c.j_stage == 1) c.ipl = std::min(c.ipl, 4);    // LDS staging: up to 4 rows per lane
     c.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
     if (api == NBODY_API_BATCHED) c.j_split = 1;
@@ -174,6 +174,25 @@ double split_cost(int64_t n, int64_t waves, int64_t resident, int s, double pair
     return t_compute + t_reduce;
 }
 
+// as resident_waves, for the acceleration-and-jerk kernel
+int64_t resident_waves_jerk(int prec, int ipl, bool pot, int js, int block)
+{
+    using Key = std::tuple<int, int, int, int, int>;
+    static std::map<Key, int64_t> cache;
+    static std::mutex mu;
+    const Key key(prec, ipl, pot ? 1 : 0, js, block);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int bpc = jerk_blocks_per_cu(prec, ipl, pot ? 1 : 0, js, block);
+    const int64_t r = bpc > 0 ? (int64_t)bpc * (block / 64) * device_cus() : 0;
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = r;
+    return r;
+}
+
 double nominal_rate(int law, int prec)
 {
     const bool f32 = is_f32(prec);
@@ -182,17 +201,19 @@ double nominal_rate(int law, int prec)
     return f32 ? 1.8e12 : 0.6e12;
 }
 
-// splits 1..smax ordered by modelled cost
+// splits 1..smax ordered by modelled cost (n output rows against npad records
+// for the jerk kernel, whose flop count is about twice the force kernel's)
 std::vector<int> ranked_splits(int law, int prec, int64_t n, int ipl, bool pot, int js, int block,
-                               int smax)
+                               int smax, bool jerk = false)
 {
     const int64_t waves = (n + 64 * ipl - 1) / (64 * ipl);
-    const int64_t R = resident_waves(law, prec, ipl, pot, js, block);
+    const int64_t R = jerk ? resident_waves_jerk(prec, ipl, pot, js, block)
+                           : resident_waves(law, prec, ipl, pot, js, block);
     std::vector<std::pair<double, int>> c;
     for (int sp = 1; sp <= smax; ++sp) {
         double cost;
         if (R > 0) {
-            cost = split_cost(n, waves, R, sp, nominal_rate(law, prec));
+            cost = split_cost(n, waves, R, sp, nominal_rate(law, prec) * (jerk ? 0.5 : 1.0));
         } else {   // occupancy unknown: aim at kTargetWaves waves
             cost = std::abs(std::log((double)(waves * sp) / kTargetWaves)) + 0.01 * sp;
         }
@@ -226,6 +247,11 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t S, bool pot)
         c.j_tile = 1024;
         c.j_stage = 0;
     }
+    if (api == NBODY_API_JERK || api == NBODY_API_HERMITE) {
+        c.ipl = 1;
+        c.j_split = ranked_splits(law, prec, n, c.ipl, pot, c.j_stage, c.block, max_split(npad), true)[0];
+        return sanitize(c, api, law, prec, npad);
+    }
     if (api == NBODY_API_BACKWARD) {
         c.ipl = std::min(c.ipl, 2);
         c.j_stage = is_f32(prec) ? 1 : 0;
@@ -246,9 +272,11 @@ Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot)
     if (g_override_set[api]) return sanitize(g_override[api], api, law->kind, law->precision, npad);
     auto it = g_tuned.find(TuneKey(api, law->kind, law->precision, pot ? 1 : 0, size_bucket(n),
                                    size_bucket(S)));
-    if (it == g_tuned.end() && api == NBODY_API_LEAPFROG)   // a leapfrog step runs the forces kernel
-        it = g_tuned.find(TuneKey(NBODY_API_FORCES, law->kind, law->precision, pot ? 1 : 0,
-                                  size_bucket(n), size_bucket(S)));
+    if (it == g_tuned.end() && (api == NBODY_API_LEAPFROG || api == NBODY_API_HERMITE))
+        // a leapfrog step runs the forces kernel, a Hermite step the jerk kernel
+        it = g_tuned.find(TuneKey(api == NBODY_API_LEAPFROG ? NBODY_API_FORCES : NBODY_API_JERK,
+                                  law->kind, law->precision, pot ? 1 : 0, size_bucket(n),
+                                  size_bucket(S)));
     if (it != g_tuned.end()) return sanitize(it->second.first, api, law->kind, law->precision, npad);
     return heuristic(api, law->kind, law->precision, n, S, pot);
 }
@@ -273,14 +301,14 @@ struct Timer {
             on = g_timing;
         }
         if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
-            hipEventRecord(a, s);
+            (void)hipEventRecord(a, s);
         else
             on = false;
     }
     void stop()
     {
         if (!on) return;
-        hipEventRecord(b, s);
+        (void)hipEventRecord(b, s);
         std::lock_guard<std::mutex> lk(g_mu);
         g_timed.push_back({a, b});
         on = false;
@@ -320,6 +348,43 @@ AdjWs adj_layout(const nbody_law *law, int64_t n)
     off = align256(off + (size_t)npad * adj_rec_bytes(law->kind, law->precision));
     w.part_off = off;
     off = align256(off + (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double));
+    w.total = off;
+    return w;
+}
+
+// Acceleration + jerk (and the Hermite integrator): records, split partials
+// and, for the integrator, the new acceleration / jerk of the evaluated rows,
+// the due list and the scheduling scratch.
+constexpr int kSchedBlocks = 1024;
+
+struct JerkWs {
+    size_t rec_off, part_off, a1_off, j1_off, list_off, pmin_off, pcnt_off, out_off, total;
+};
+
+JerkWs jerk_layout(int api, const nbody_law *law, int64_t n)
+{
+    JerkWs w{};
+    const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    const size_t t = is_f32(law->precision) ? 4 : 8;
+    size_t off = 0;
+    w.rec_off = off;
+    off = align256(off + (size_t)npad * 8 * t);
+    w.part_off = off;
+    off = align256(off + (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double));
+    if (api == NBODY_API_HERMITE) {
+        w.a1_off = off;
+        off = align256(off + (size_t)npad * 3 * sizeof(double));
+        w.j1_off = off;
+        off = align256(off + (size_t)npad * 3 * sizeof(double));
+        w.list_off = off;
+        off = align256(off + (size_t)npad * sizeof(int64_t));
+        w.pmin_off = off;
+        off = align256(off + (size_t)kSchedBlocks * sizeof(double));
+        w.pcnt_off = off;
+        off = align256(off + (size_t)kSchedBlocks * sizeof(int64_t));
+        w.out_off = off;
+        off = align256(off + 2 * sizeof(double));
+    }
     w.total = off;
     return w;
 }
@@ -421,6 +486,92 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
     e = launch_reduce_split(f, s);
     if (e != hipSuccess) return hip_fail(e, "split reduction");
     return NBODY_OK;
+}
+
+int check_ws(void *ws, size_t have, size_t need)
+{
+    if (!ws && need) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
+    if (have < need) return fail(NBODY_EWORKSPACE, "workspace too small: %zu < %zu bytes", have, need);
+    return NBODY_OK;
+}
+
+int validate_jerk_law(const nbody_law *law)
+{
+    int rc = validate_law(law, false);
+    if (rc) return rc;
+    if (law->kind != NBODY_LAW_GRAVITY) return fail(NBODY_ENOTSUP, "the jerk is provided for gravity only");
+    if (law->precision == NBODY_FP32_PLAIN)
+        return fail(NBODY_ENOTSUP, "the jerk kernel is provided for FP64, FP32_FP64ACC and FP32_KAHAN");
+    return NBODY_OK;
+}
+
+// pack (optionally predicted) records + acceleration/jerk kernel (+ split reduction)
+int run_jerk(const nbody_law *law, const Cfg &c, const JerkPackLaunch &pk_in, const int64_t *rows,
+             int64_t nrows, double *out_acc, double *out_jerk, double *out_pot, void *ws,
+             const JerkWs &lay, hipStream_t s)
+{
+    const int64_t npad = round_up(pk_in.n, 64);
+    char *base = (char *)ws;
+    JerkPackLaunch pk = pk_in;
+    pk.prec = law->precision;
+    pk.npad = npad;
+    pk.rec = base + lay.rec_off;
+    hipError_t e = launch_pack_jerk(pk, s);
+    if (e != hipSuccess) return hip_fail(e, "jerk pack");
+    JerkLaunch a{};
+    a.prec = law->precision;
+    a.ipl = c.ipl;
+    a.pot = out_pot != nullptr;
+    a.block = c.block;
+    a.j_stage = c.j_stage;
+    a.npad = npad;
+    a.nrows = nrows;
+    a.rows = rows;
+    a.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
+    a.split_len = round_up((npad + a.j_split - 1) / a.j_split, 64);
+    a.j_tile = c.j_tile;
+    a.eps2 = law->softening * law->softening;
+    a.G = law->G;
+    a.rec = base + lay.rec_off;
+    a.partial = (double *)(base + lay.part_off);
+    a.out_acc = out_acc;
+    a.out_jerk = out_jerk;
+    a.out_pot = out_pot;
+    Timer t(s);
+    e = launch_jerk(a, s);
+    t.stop();
+    if (e != hipSuccess) return hip_fail(e, "jerk kernel");
+    e = launch_jerk_reduce(a, s);
+    if (e != hipSuccess) return hip_fail(e, "jerk split reduction");
+    return NBODY_OK;
+}
+
+int jerk_impl(const double *pos, const double *vel, const double *mass, int64_t n,
+              const int64_t *ilist, int64_t ni, const nbody_law *law, double *out_acc,
+              double *out_jerk, double *out_potential, void *ws, size_t ws_bytes, void *stream,
+              const Cfg *forced)
+{
+    int rc = validate_jerk_law(law);
+    if (rc) return rc;
+    if (n < 0 || ni < 0) return fail(NBODY_EINVAL, "n < 0 or ni < 0");
+    if (n > (int64_t(1) << 40)) return fail(NBODY_EINVAL, "n too large");
+    if (!ilist && ni != n) return fail(NBODY_EINVAL, "without ilist, ni must equal n");
+    if (ni > 0 && n == 0) return fail(NBODY_EINVAL, "rows requested from an empty system");
+    if (ni == 0) return NBODY_OK;
+    if (!pos || !vel || !mass || !out_acc || !out_jerk)
+        return fail(NBODY_EINVAL, "pos, vel, mass, out_acc and out_jerk must be non-NULL");
+    const JerkWs lay = jerk_layout(NBODY_API_JERK, law, std::max(n, ni));
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    const int64_t npad = round_up(std::max(n, ni), 64);
+    const Cfg c = sanitize(forced ? *forced : choose(NBODY_API_JERK, law, ni, 1, out_potential != nullptr),
+                           NBODY_API_JERK, law->kind, law->precision, npad);
+    JerkPackLaunch pk{};
+    pk.n = n;
+    pk.pos = pos;
+    pk.vel = vel;
+    pk.mass = mass;
+    return run_jerk(law, c, pk, ilist, ni, out_acc, out_jerk, out_potential, ws, lay, (hipStream_t)stream);
 }
 
 bool cfg_valid(const nbody_config *c)
@@ -568,12 +719,6 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     return NBODY_OK;
 }
 
-int check_ws(void *ws, size_t have, size_t need)
-{
-    if (!ws && need) return fail(NBODY_EWORKSPACE, "workspace is NULL (need %zu bytes)", need);
-    if (have < need) return fail(NBODY_EWORKSPACE, "workspace too small: %zu < %zu bytes", have, need);
-    return NBODY_OK;
-}
 
 int validate_offsets(const int64_t *offsets, int64_t S)
 {
@@ -652,12 +797,14 @@ std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
                     }
         return out;
     }
+    const bool jerk = api == NBODY_API_JERK;
     for (int js : {0, 1})
         for (int ipl : {1, 2, 4, 8}) {
             if (ipl > max_ipl(api, prec) || (js == 1 && ipl > 4)) continue;
+            if (jerk && ipl > 2) continue;
             if (law >= NBODY_LAW_LJC_CONSTANT && ipl > 2) continue;
             const int block = 256;
-            std::vector<int> splits = ranked_splits(law, prec, n, ipl, pot, js, block, max_split(npad));
+            std::vector<int> splits = ranked_splits(law, prec, n, ipl, pot, js, block, max_split(npad), jerk);
             std::vector<int> pick;
             for (int sp : splits) {
                 if ((int)pick.size() >= 3) break;
@@ -697,6 +844,10 @@ size_t nbody_workspace_bytes(int32_t api, int64_t n_total, int64_t n_systems, co
     case NBODY_API_LEAPFROG: return fwd_layout(NBODY_API_LEAPFROG, law, n_total).total;
     case NBODY_API_BACKWARD: return adj_layout(law, n_total).total;
     case NBODY_API_BATCHED: return bat_layout(law, n_total, n_systems).total;
+    case NBODY_API_JERK:
+    case NBODY_API_HERMITE:
+        if (law->kind != NBODY_LAW_GRAVITY) return 0;
+        return jerk_layout(api, law, n_total).total;
     default: return 0;
     }
 }
@@ -840,9 +991,224 @@ int leapfrog_step(double *pos, double *vel, double *acc, const double *params,
     return NBODY_OK;
 }
 
+int nbody_forces_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                      const int64_t *ilist, int64_t ni, const nbody_law *law, double *out_acc,
+                      double *out_jerk, double *out_potential, void *ws, size_t ws_bytes,
+                      void *stream)
+{
+    return jerk_impl(pos, vel, mass, n, ilist, ni, law, out_acc, out_jerk, out_potential, ws,
+                     ws_bytes, stream, nullptr);
+}
+
+int hermite_step(double *pos, double *vel, double *acc, double *jerk, const double *mass,
+                 int64_t n, const nbody_law *law, double dt, int32_t nsteps, void *ws,
+                 size_t ws_bytes, void *stream)
+{
+    int rc = validate_jerk_law(law);
+    if (rc) return rc;
+    if (n < 0 || nsteps < 0) return fail(NBODY_EINVAL, "n < 0 or nsteps < 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(NBODY_EINVAL, "dt must be finite and > 0");
+    if (n == 0 || nsteps == 0) return NBODY_OK;
+    if (!pos || !vel || !acc || !jerk || !mass)
+        return fail(NBODY_EINVAL, "pos, vel, acc, jerk and mass must be non-NULL");
+    const JerkWs lay = jerk_layout(NBODY_API_HERMITE, law, n);
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    double *a1 = (double *)(base + lay.a1_off), *j1 = (double *)(base + lay.j1_off);
+    const Cfg c = sanitize(choose(NBODY_API_HERMITE, law, n, 1, false), NBODY_API_HERMITE, law->kind,
+                           law->precision, round_up(n, 64));
+    for (int32_t k = 0; k < nsteps; ++k) {
+        JerkPackLaunch pk{};
+        pk.n = n;
+        pk.pos = pos;
+        pk.vel = vel;
+        pk.mass = mass;
+        pk.predict = 1;
+        pk.acc = acc;
+        pk.jerk = jerk;
+        pk.tau = dt;
+        rc = run_jerk(law, c, pk, nullptr, n, a1, j1, nullptr, ws, lay, s);
+        if (rc) return rc;
+        HermiteLaunch h{};
+        h.nrows = n;
+        h.pos = pos;
+        h.vel = vel;
+        h.acc = acc;
+        h.jerk = jerk;
+        h.a1 = a1;
+        h.j1 = j1;
+        h.h = dt;
+        hipError_t e = launch_hermite_correct(h, s);
+        if (e != hipSuccess) return hip_fail(e, "Hermite corrector");
+    }
+    return NBODY_OK;
+}
+
+bool power_of_two(double x)
+{
+    int e = 0;
+    return x > 0.0 && std::isfinite(x) && std::frexp(x, &e) == 0.5;
+}
+
+int hermite_block_init(const double *acc, const double *jerk, int64_t n, double eta_s, double dt_max,
+                       double *t_i, double *dt_i, void *stream)
+{
+    if (n < 0) return fail(NBODY_EINVAL, "n < 0");
+    if (!(eta_s > 0.0) || !std::isfinite(eta_s)) return fail(NBODY_EINVAL, "eta_s must be finite and > 0");
+    if (!power_of_two(dt_max)) return fail(NBODY_EINVAL, "dt_max must be a power of two");
+    if (n == 0) return NBODY_OK;
+    if (!acc || !jerk || !t_i || !dt_i) return fail(NBODY_EINVAL, "acc, jerk, t_i and dt_i must be non-NULL");
+    hipError_t e = launch_block_init(acc, jerk, n, eta_s, dt_max, t_i, dt_i, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "block-step initialisation");
+    return NBODY_OK;
+}
+
+int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, double *t_i,
+                        double *dt_i, const double *mass, int64_t n, const nbody_law *law,
+                        double eta, double dt_max, int32_t nblocks, int64_t *active_counts,
+                        double *t_now, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = validate_jerk_law(law);
+    if (rc) return rc;
+    if (n < 0 || nblocks < 0) return fail(NBODY_EINVAL, "n < 0 or nblocks < 0");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(NBODY_EINVAL, "eta must be finite and > 0");
+    if (!power_of_two(dt_max)) return fail(NBODY_EINVAL, "dt_max must be a power of two");
+    if (n == 0 || nblocks == 0) return NBODY_OK;
+    if (!pos || !vel || !acc || !jerk || !t_i || !dt_i || !mass)
+        return fail(NBODY_EINVAL, "pos, vel, acc, jerk, t_i, dt_i and mass must be non-NULL");
+    const JerkWs lay = jerk_layout(NBODY_API_HERMITE, law, n);
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)ws;
+    double *a1 = (double *)(base + lay.a1_off), *j1 = (double *)(base + lay.j1_off);
+    int64_t *list = (int64_t *)(base + lay.list_off);
+    double *out = (double *)(base + lay.out_off);
+    SchedLaunch sl{};
+    sl.n = n;
+    sl.nb = (int)std::min<int64_t>(kSchedBlocks, (n + 255) / 256);
+    sl.chunk = (n + sl.nb - 1) / sl.nb;
+    sl.t_i = t_i;
+    sl.dt_i = dt_i;
+    sl.part_min = (double *)(base + lay.pmin_off);
+    sl.part_cnt = (int64_t *)(base + lay.pcnt_off);
+    sl.list = list;
+    sl.out = out;
+    for (int32_t b = 0; b < nblocks; ++b) {
+        hipError_t e = launch_schedule(sl, s);
+        if (e != hipSuccess) return hip_fail(e, "block scheduling");
+        double host[2];
+        e = hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "block scheduling read-back");
+        const double t = host[0];
+        int64_t na = 0;
+        std::memcpy(&na, &host[1], sizeof na);
+        if (!(na >= 1 && na <= n) || !std::isfinite(t))
+            return fail(NBODY_EHIP, "block scheduling produced an invalid due set (%lld)", (long long)na);
+        if (active_counts) active_counts[b] = na;
+        if (t_now) *t_now = t;
+        const Cfg c = sanitize(choose(NBODY_API_HERMITE, law, na, 1, false), NBODY_API_HERMITE,
+                               law->kind, law->precision, round_up(n, 64));
+        JerkPackLaunch pk{};
+        pk.n = n;
+        pk.pos = pos;
+        pk.vel = vel;
+        pk.mass = mass;
+        pk.predict = 1;
+        pk.acc = acc;
+        pk.jerk = jerk;
+        pk.t_i = t_i;
+        pk.t_pred = t;
+        rc = run_jerk(law, c, pk, list, na, a1, j1, nullptr, ws, lay, s);
+        if (rc) return rc;
+        HermiteLaunch h{};
+        h.nrows = na;
+        h.rows = list;
+        h.pos = pos;
+        h.vel = vel;
+        h.acc = acc;
+        h.jerk = jerk;
+        h.a1 = a1;
+        h.j1 = j1;
+        h.t_i = t_i;
+        h.dt_i = dt_i;
+        h.t_next = out;
+        h.eta = eta;
+        h.dt_max = dt_max;
+        e = launch_hermite_correct(h, s);
+        if (e != hipSuccess) return hip_fail(e, "Hermite corrector");
+    }
+    return NBODY_OK;
+}
+
+int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
+                        const nbody_law *law, double *out_acc, double *out_jerk,
+                        double *out_potential, void *ws, size_t ws_bytes, void *stream,
+                        nbody_config *out_best, double *out_ms)
+{
+    int rc = validate_jerk_law(law);
+    if (rc) return rc;
+    if (n <= 0) return fail(NBODY_EINVAL, "nothing to tune");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(NBODY_EHIP, "event creation failed");
+    Cfg best;
+    double best_ms = 1e300;
+    bool saved_timing;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        saved_timing = g_timing;
+        g_timing = false;
+    }
+    for (const Cfg &c : candidates(NBODY_API_JERK, law->kind, law->precision, n, out_potential != nullptr)) {
+        double ms_min = 1e300;
+        for (int rep = 0; rep < 2; ++rep) {
+            (void)hipEventRecord(a, s);
+            rc = jerk_impl(pos, vel, mass, n, nullptr, n, law, out_acc, out_jerk, out_potential, ws,
+                           ws_bytes, stream, &c);
+            (void)hipEventRecord(b, s);
+            if (rc) break;
+            if (hipEventSynchronize(b) != hipSuccess) {
+                rc = fail(NBODY_EHIP, "autotune synchronisation failed");
+                break;
+            }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, a, b);
+            ms_min = std::min(ms_min, (double)ms);
+        }
+        if (rc) break;
+        if (ms_min < best_ms) {
+            best_ms = ms_min;
+            best = c;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_timing = saved_timing;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_tuned[TuneKey(NBODY_API_JERK, law->kind, law->precision, out_potential ? 1 : 0,
+                        size_bucket(n), size_bucket(1))] = {best, best_ms};
+    }
+    rc = jerk_impl(pos, vel, mass, n, nullptr, n, law, out_acc, out_jerk, out_potential, ws, ws_bytes,
+                   stream, &best);
+    if (rc) return rc;
+    if (out_best) to_abi(best, out_best);
+    if (out_ms) *out_ms = best_ms;
+    return NBODY_OK;
+}
+
 int nbody_set_config(int32_t api, const nbody_config *cfg)
 {
-    if (api < 0 || api > 3) return fail(NBODY_EINVAL, "unknown api %d", api);
+    if (api < 0 || api >= kNumApi) return fail(NBODY_EINVAL, "unknown api %d", api);
     std::lock_guard<std::mutex> lk(g_mu);
     if (!cfg) {
         g_override_set[api] = false;
@@ -856,7 +1222,7 @@ int nbody_set_config(int32_t api, const nbody_config *cfg)
 
 int nbody_get_config(int32_t api, int64_t n, int64_t n_systems, const nbody_law *law, nbody_config *out)
 {
-    if (api < 0 || api > 3) return fail(NBODY_EINVAL, "unknown api %d", api);
+    if (api < 0 || api >= kNumApi) return fail(NBODY_EINVAL, "unknown api %d", api);
     int rc = validate_law(law, false);
     if (rc) return rc;
     if (!out || n < 0) return fail(NBODY_EINVAL, "bad arguments");
@@ -887,25 +1253,29 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
         return fail(NBODY_EHIP, "event creation failed");
     Cfg best;
     double best_ms = 1e300;
-    const bool saved_timing = g_timing;
-    g_timing = false;
+    bool saved_timing;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        saved_timing = g_timing;
+        g_timing = false;
+    }
     for (const Cfg &c : candidates(api, law->kind, law->precision, ntot, out_potential != nullptr)) {
         double ms_min = 1e300;
         for (int rep = 0; rep < 2; ++rep) {
-            hipEventRecord(a, s);
+            (void)hipEventRecord(a, s);
             rc = api == NBODY_API_FORCES
                      ? forces_impl(pos, params, n, nullptr, n, law, out_force, out_potential, ws,
                                    ws_bytes, stream, &c)
                      : batched_impl(offsets, n_systems, pos, params, law, out_force, out_potential,
                                     ws, ws_bytes, stream, &c);
-            hipEventRecord(b, s);
+            (void)hipEventRecord(b, s);
             if (rc) break;
             if (hipEventSynchronize(b) != hipSuccess) {
                 rc = fail(NBODY_EHIP, "autotune synchronisation failed");
                 break;
             }
             float ms = 0;
-            hipEventElapsedTime(&ms, a, b);
+            (void)hipEventElapsedTime(&ms, a, b);
             ms_min = std::min(ms_min, (double)ms);
         }
         if (rc) break;
@@ -914,9 +1284,12 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
             best = c;
         }
     }
-    g_timing = saved_timing;
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_timing = saved_timing;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -980,7 +1353,7 @@ int nbody_tune_load(const char *path)
                    "\"j_stage\": %d, \"ms\": %lf}",
                    &api, &law, &prec, &pot, &nb, &sb, &block, &ipl, &jt, &js, &jst, &ms) == 12) {
             nbody_config cc{block, ipl, jt, js, jst};
-            if (cfg_valid(&cc) && api >= 0 && api <= 3) {
+            if (cfg_valid(&cc) && api >= 0 && api < kNumApi) {
                 std::lock_guard<std::mutex> lk(g_mu);
                 g_tuned[TuneKey(api, law, prec, pot, nb, sb)] = {from_abi(&cc), ms};
                 ++loaded;
@@ -1010,8 +1383,8 @@ int nbody_timing_read(double *total_ms, int64_t *launches, int32_t reset)
         float ms = 0;
         if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&ms, t.a, t.b) != hipSuccess)
             rc = fail(NBODY_EHIP, "timing events failed");
-        hipEventDestroy(t.a);
-        hipEventDestroy(t.b);
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
         std::lock_guard<std::mutex> lk(g_mu);
         g_timed_ms += ms;
         ++g_timed_count;
@@ -1029,6 +1402,8 @@ int nbody_timing_read(double *total_ms, int64_t *launches, int32_t reset)
 int32_t nbody_flops_per_pair(int32_t api, int32_t law_kind, int32_t with_potential)
 {
     if (api == NBODY_API_BACKWARD) return law_kind == NBODY_LAW_GRAVITY ? 41 : 68;
+    if (api == NBODY_API_JERK || api == NBODY_API_HERMITE)
+        return law_kind == NBODY_LAW_GRAVITY ? (with_potential ? 42 : 41) : 0;
     switch (law_kind) {
     case NBODY_LAW_GRAVITY: return with_potential ? 20 : 19;
     case NBODY_LAW_LJC_LINEAR: return with_potential ? 35 : 30;

@@ -119,6 +119,60 @@ hipError_t launch_adjoint_reduce(const AdjLaunch &a, hipStream_t s);
 hipError_t launch_type_reduce(const double *grad_params, const int32_t *types, int64_t n,
                               int32_t n_types, double *out, hipStream_t s);
 
+// ---- acceleration + jerk and the Hermite integrator ----
+struct JerkPackLaunch {
+    int prec;
+    int64_t n, npad;
+    const double *pos, *vel, *mass;   // [n][3], [n][3], [n]
+    int predict;                      // 0: records from (pos, vel); 1: Hermite-predicted state
+    const double *acc, *jerk;         // [n][3] (predict)
+    const double *t_i;                // [n] per-particle times, or null: tau for every particle
+    double t_pred;                    // prediction time (with t_i)
+    double tau;                       // prediction interval (without t_i)
+    void *rec;                        // GajRec records [npad]
+};
+struct JerkLaunch {
+    int prec, ipl, pot;
+    int block, j_stage;
+    int64_t npad;
+    int64_t nrows;
+    const int64_t *rows;              // row -> particle, or null (identity)
+    int64_t split_len;
+    int j_split, j_tile;
+    double eps2, G;
+    const void *rec;
+    double *partial;                  // [j_split][nrows][8] when j_split > 1
+    double *out_acc, *out_jerk;       // [nrows][3]
+    double *out_pot;                  // [nrows] or null
+};
+struct HermiteLaunch {
+    int64_t nrows;
+    const int64_t *rows;              // active particles, or null (all)
+    double *pos, *vel, *acc, *jerk;   // [n][3], updated for the rows
+    const double *a1, *j1;            // [nrows][3] at the predicted state, in row order
+    double h;                         // shared step (when dt_i is null)
+    double *t_i, *dt_i;               // block steps: per-particle time and step, or null
+    const double *t_next;             // block steps: device scalar, the block time
+    double eta, dt_max;
+};
+struct SchedLaunch {
+    int64_t n, chunk;
+    int nb;                           // scheduling blocks, each owns `chunk` particles
+    const double *t_i, *dt_i;
+    double *part_min;                 // [nb]
+    int64_t *part_cnt;                // [nb]
+    int64_t *list;                    // [n] due particles, increasing
+    double *out;                      // out[0] = t_next, out[1] holds the due count (int64)
+};
+hipError_t launch_pack_jerk(const JerkPackLaunch &p, hipStream_t s);
+hipError_t launch_jerk(const JerkLaunch &a, hipStream_t s);
+hipError_t launch_jerk_reduce(const JerkLaunch &a, hipStream_t s);
+int jerk_blocks_per_cu(int prec, int ipl, int pot, int js, int block);
+hipError_t launch_hermite_correct(const HermiteLaunch &a, hipStream_t s);
+hipError_t launch_block_init(const double *acc, const double *jerk, int64_t n, double eta_s,
+                             double dt_max, double *t_i, double *dt_i, hipStream_t s);
+hipError_t launch_schedule(const SchedLaunch &a, hipStream_t s);
+
 // zero-fill with a kernel (no memset nodes, so the calls stay capturable)
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 

@@ -7,8 +7,12 @@ the workspace) and the current stream.  There is no CPU or PyTorch fallback:
 when the library is missing, or a tensor is not on a GPU, the call raises.
 
 Laws (see include/nbody.h for the full statement and citations):
-  gravity:    Eq. 1 softened gravity, params = masses [N]
-  ljc_linear: Table 1 LJC(linear), params = [N, 3] rows (q, sigma, epsilon)
+  gravity:       Eq. 1 softened gravity, params = masses [N]; with forces_jerk
+                 also its time derivative (Table 1 "Gravity (accel & jerk)")
+  ljc_linear, ljc_constant, ljc_sigmoidal:
+                 Table 1's LJC laws, params = [N, 3] rows (q, sigma, epsilon)
+Integrators: leapfrog (kick-drift-kick), hermite (fourth-order Hermite, shared
+step) and hermite_block (Hermite with block individual steps).
 """
 from __future__ import annotations
 
@@ -24,6 +28,7 @@ GRAVITY, LJC_LINEAR, LJC_CONSTANT, LJC_SIGMOIDAL = 0, 1, 2, 3
 FP64, FP32_KAHAN, FP32_FP64ACC, FP32_PLAIN = 0, 1, 2, 3
 API_FORCES, API_BATCHED, API_BACKWARD, API_LEAPFROG = (N.API_FORCES, N.API_BATCHED,
                                                        N.API_BACKWARD, N.API_LEAPFROG)
+API_JERK, API_HERMITE = N.API_JERK, N.API_HERMITE
 PRECISIONS = {"fp64": FP64, "fp32_kahan": FP32_KAHAN, "fp32_fp64acc": FP32_FP64ACC,
               "fp32_plain": FP32_PLAIN}
 
@@ -234,6 +239,114 @@ def leapfrog(pos, vel, acc, params, law: Law, dt: float, nsteps: int, inv_mass=N
                                   ctypes.byref(law.c()), float(dt), int(nsteps), _ptr(p),
                                   _ptr(ws), ws.numel(), _stream(pos.device)))
     return p
+
+
+# ------------------------------------------------------- jerk and Hermite
+def _vec3(t, n, name):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous float64 GPU tensor (updated in place)" % name)
+    if tuple(t.shape) != (n, 3):
+        raise ValueError("%s must have shape (%d, 3)" % (name, n))
+    return t
+
+
+def forces_jerk(pos, vel, mass, law: Law, ilist=None, potential: bool = True):
+    """Acceleration, jerk and (optionally) potential of softened gravity for every
+    particle, or for the int64 indices `ilist`.  Returns (acc, jerk, phi or None)."""
+    if law.kind != GRAVITY:
+        raise ValueError("the jerk is provided for gravity")
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    pos = _dev_f64(pos, (n, 3), "pos")
+    vel = _dev_f64(vel, (n, 3), "vel", pos.device)
+    m = _dev_f64(mass, (n,), "mass", pos.device)
+    il = None
+    ni = n
+    if ilist is not None:
+        il = torch.as_tensor(ilist, device=pos.device).to(torch.int64).contiguous()
+        ni = il.numel()
+        if ni and (int(il.min()) < 0 or int(il.max()) >= n):
+            raise ValueError("ilist indices must lie in [0, %d)" % n)
+    dev = pos.device
+    a = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+    j = torch.empty((ni, 3), dtype=torch.float64, device=dev)
+    p = torch.empty(ni, dtype=torch.float64, device=dev) if potential else None
+    ws = workspace(API_JERK, max(n, ni), 1, law, dev)
+    N.check(N.lib().nbody_forces_jerk(_ptr(pos), _ptr(vel), _ptr(m), n, _ptr(il), ni,
+                                      ctypes.byref(law.c()), _ptr(a), _ptr(j), _ptr(p), _ptr(ws),
+                                      ws.numel(), _stream(dev)))
+    return a, j, p
+
+
+def hermite(pos, vel, acc, jerk, mass, law: Law, dt: float, nsteps: int):
+    """nsteps shared fourth-order Hermite steps, updating pos, vel, acc, jerk IN PLACE
+    (acc and jerk must hold the values at the entry state, e.g. from forces_jerk)."""
+    n = pos.shape[0]
+    for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc"), (jerk, "jerk")):
+        _vec3(t, n, name)
+    m = _dev_f64(mass, (n,), "mass", pos.device)
+    ws = workspace(API_HERMITE, n, 1, law, pos.device)
+    N.check(N.lib().hermite_step(_ptr(pos), _ptr(vel), _ptr(acc), _ptr(jerk), _ptr(m), n,
+                                 ctypes.byref(law.c()), float(dt), int(nsteps), _ptr(ws), ws.numel(),
+                                 _stream(pos.device)))
+
+
+def hermite_block_init(acc, jerk, eta_s: float, dt_max: float):
+    """Initial block steps: (t_i, dt_i) float64 GPU tensors [N]."""
+    n = acc.shape[0]
+    a = _dev_f64(acc, (n, 3), "acc")
+    j = _dev_f64(jerk, (n, 3), "jerk", a.device)
+    t = torch.empty(n, dtype=torch.float64, device=a.device)
+    dt = torch.empty(n, dtype=torch.float64, device=a.device)
+    N.check(N.lib().hermite_block_init(_ptr(a), _ptr(j), n, float(eta_s), float(dt_max), _ptr(t),
+                                       _ptr(dt), _stream(a.device)))
+    return t, dt
+
+
+def hermite_block(pos, vel, acc, jerk, t_i, dt_i, mass, law: Law, eta: float, dt_max: float,
+                  nblocks: int):
+    """nblocks block steps of the individual-step Hermite scheme, updating pos, vel,
+    acc, jerk, t_i, dt_i IN PLACE.  Returns (active counts per block step [nblocks]
+    int64 numpy array, time of the last block step)."""
+    n = pos.shape[0]
+    for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc"), (jerk, "jerk")):
+        _vec3(t, n, name)
+    for t, name in ((t_i, "t_i"), (dt_i, "dt_i")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+                and t.is_contiguous() and tuple(t.shape) == (n,)):
+            raise ValueError("%s must be a contiguous float64 GPU tensor of shape (%d,)" % (name, n))
+    m = _dev_f64(mass, (n,), "mass", pos.device)
+    counts = np.zeros(max(int(nblocks), 1), dtype=np.int64)
+    t_now = ctypes.c_double(0.0)
+    ws = workspace(API_HERMITE, n, 1, law, pos.device)
+    N.check(N.lib().hermite_block_steps(_ptr(pos), _ptr(vel), _ptr(acc), _ptr(jerk), _ptr(t_i),
+                                        _ptr(dt_i), _ptr(m), n, ctypes.byref(law.c()), float(eta),
+                                        float(dt_max), int(nblocks),
+                                        counts.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t_now),
+                                        _ptr(ws), ws.numel(), _stream(pos.device)))
+    return counts[:int(nblocks)], t_now.value
+
+
+def autotune_jerk(pos, vel, mass, law: Law, potential=True):
+    """Measure launch configurations of the jerk kernel on this problem and remember
+    the fastest (also used by the Hermite steps).  Returns (config dict, ms)."""
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    vel = _dev_f64(vel, (n, 3), "vel", pos.device)
+    m = _dev_f64(mass, (n,), "mass", pos.device)
+    dev = pos.device
+    a = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    j = torch.empty((n, 3), dtype=torch.float64, device=dev)
+    p = torch.empty(n, dtype=torch.float64, device=dev) if potential else None
+    ws = workspace(API_JERK, n, 1, law, dev)
+    best = N.NBodyConfig()
+    ms = ctypes.c_double()
+    N.check(N.lib().nbody_autotune_jerk(_ptr(pos), _ptr(vel), _ptr(m), n, ctypes.byref(law.c()),
+                                        _ptr(a), _ptr(j), _ptr(p), _ptr(ws), ws.numel(), _stream(dev),
+                                        ctypes.byref(best), ctypes.byref(ms)))
+    return (dict(block=best.block, i_per_lane=best.i_per_lane, j_tile=best.j_tile,
+                 j_split=best.j_split, j_stage=best.j_stage), ms.value)
 
 
 # ------------------------------------------------------------- tuning etc.

@@ -182,3 +182,60 @@ def test_python_binding_rejects_cpu_tensors(N):
     with pytest.raises(ValueError):
         nb.forces(torch.zeros(4, 3, dtype=torch.float64), torch.ones(4, dtype=torch.float64),
                   nb.gravity("fp64"))
+
+
+def test_jerk_and_hermite_validation(N):
+    lib = N.lib()
+    g = law(N)
+    lj = law(N, kind=1)
+    plain = law(N, prec=3)
+
+    def jerk(lw, n=10, ilist=None, ni=10, ws_bytes=1 << 30):
+        return lib.nbody_forces_jerk(fake(), fake(), fake(), n, ilist, ni, ctypes.byref(lw), fake(),
+                                     fake(), None, fake(), ws_bytes, None)
+
+    assert jerk(lj) == N.NBODY_ENOTSUP
+    assert b"gravity only" in lib.nbody_last_error()
+    assert jerk(plain) == N.NBODY_ENOTSUP
+    assert jerk(g, ni=5) == N.NBODY_EINVAL                 # no ilist: ni must equal n
+    assert jerk(g, n=-1, ni=-1) == N.NBODY_EINVAL
+    assert jerk(g, ws_bytes=64) == N.NBODY_EWORKSPACE
+    assert jerk(g, n=0, ni=0) == 0
+    assert lib.hermite_step(fake(), fake(), fake(), fake(), fake(), 10, ctypes.byref(g), 0.0, 1, fake(),
+                            1 << 30, None) == N.NBODY_EINVAL
+    assert lib.hermite_step(fake(), fake(), fake(), fake(), fake(), 10, ctypes.byref(g), float("nan"),
+                            1, fake(), 1 << 30, None) == N.NBODY_EINVAL
+    assert lib.hermite_step(fake(), fake(), fake(), fake(), fake(), 10, ctypes.byref(lj), 0.1, 1,
+                            fake(), 1 << 30, None) == N.NBODY_ENOTSUP
+    assert lib.hermite_step(None, None, None, None, None, 10, ctypes.byref(g), 0.1, 0, None, 0,
+                            None) == 0
+    assert lib.hermite_block_init(fake(), fake(), 10, 0.01, 0.1, fake(), fake(), None) == N.NBODY_EINVAL
+    assert b"power of two" in lib.nbody_last_error()
+    assert lib.hermite_block_init(fake(), fake(), 10, -1.0, 0.125, fake(), fake(), None) == N.NBODY_EINVAL
+    assert lib.hermite_block_init(None, None, 0, 0.01, 0.125, None, None, None) == 0
+
+    def block(eta=0.02, dt_max=0.125, nb=3, lw=g, ws_bytes=1 << 30):
+        return lib.hermite_block_steps(fake(), fake(), fake(), fake(), fake(), fake(), fake(), 10,
+                                       ctypes.byref(lw), eta, dt_max, nb, None, None, fake(),
+                                       ws_bytes, None)
+
+    assert block(eta=0.0) == N.NBODY_EINVAL
+    assert block(dt_max=0.3) == N.NBODY_EINVAL
+    assert block(nb=-1) == N.NBODY_EINVAL
+    assert block(lw=lj) == N.NBODY_ENOTSUP
+    assert block(ws_bytes=1024) == N.NBODY_EWORKSPACE
+    assert block(nb=0) == 0
+    # workspaces: records, partials, and for the integrator the scheduling state
+    assert lib.nbody_workspace_bytes(4, 4096, 1, ctypes.byref(g)) >= 4096 * 32
+    assert lib.nbody_workspace_bytes(5, 4096, 1, ctypes.byref(g)) > \
+        lib.nbody_workspace_bytes(4, 4096, 1, ctypes.byref(g)) + 4096 * 56
+    assert lib.nbody_workspace_bytes(4, 4096, 1, ctypes.byref(lj)) == 0
+    # Table 1 counts 42 flops for the acceleration-and-jerk kernel (with the potential here)
+    assert lib.nbody_flops_per_pair(4, 0, 1) == 42
+    assert lib.nbody_flops_per_pair(4, 0, 0) == 41
+    assert lib.nbody_flops_per_pair(5, 1, 0) == 0
+    good = N.NBodyConfig(256, 2, 256, 4, 1)
+    assert lib.nbody_set_config(4, ctypes.byref(good)) == 0
+    assert lib.nbody_set_config(5, ctypes.byref(good)) == 0
+    assert lib.nbody_set_config(4, None) == 0 and lib.nbody_set_config(5, None) == 0
+    assert lib.nbody_set_config(6, ctypes.byref(good)) == N.NBODY_EINVAL

@@ -1,0 +1,187 @@
+"""GPU parity of the acceleration-and-jerk path (Table 1 "Gravity (accel &
+jerk)") and of the Hermite integrators built on it, against the FP64 oracle.
+
+Tolerances as for the force kernels: FP64 <= 1e-12 (per-row relative
+error of acceleration, jerk and potential); FP32 paths median <= 1e-5 and
+max <= 1e-3 against the oracle fed FP32-rounded positions and velocities.
+Integrators (FP64): positions and velocities agree with the oracle's to
+1e-12 of their scale after several steps; block steps reproduce the oracle's
+schedule exactly (the same due sets, times and steps), and with every step at
+dt_max they reproduce the shared-step scheme bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_0706_3060_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EPS = 0.01
+
+
+@pytest.fixture(scope="module")
+def nb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0706_3060_amd import nbody
+    return nbody
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel_rows(x, ref):
+    return np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)
+
+
+def check(prec, got, ref):
+    (a, j, p), (ar, jr, pr) = got, ref
+    ea, ej = rel_rows(a, ar), rel_rows(j, jr)
+    ep = np.abs(p - pr) / np.abs(pr)
+    if prec == "fp64":
+        assert ea.max() <= 1e-12 and ej.max() <= 1e-12 and ep.max() <= 1e-12, (ea.max(), ej.max())
+    else:
+        for e in (ea, ej, ep):
+            assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan", "fp32_fp64acc"])
+@pytest.mark.parametrize("n", [4096, 1000, 65, 2])
+def test_jerk_matches_oracle(nb, prec, n):
+    x, v, m = W.plummer(n, 11)
+    a, j, p = nb.forces_jerk(dev(x), dev(v), dev(m), nb.gravity(prec, softening=EPS))
+    if prec != "fp64":
+        x, v, m = W.round_to_f32(x), W.round_to_f32(v), W.round_to_f32(m)
+    check(prec, (host(a), host(j), host(p)), oracle.gravity_jerk(x, v, m, eps=EPS))
+
+
+def test_jerk_subset_and_no_potential(nb):
+    x, v, m = W.plummer(3000, 12)
+    il = np.random.default_rng(4).integers(0, 3000, 500)
+    il[:3] = 7                                              # repeats allowed
+    a, j, p = nb.forces_jerk(dev(x), dev(v), dev(m), nb.gravity("fp64", softening=EPS), ilist=il)
+    check("fp64", (host(a), host(j), host(p)), oracle.gravity_jerk(x, v, m, eps=EPS, ilist=il))
+    a2, j2, p2 = nb.forces_jerk(dev(x), dev(v), dev(m), nb.gravity("fp64", softening=EPS), ilist=il,
+                                potential=False)
+    assert p2 is None
+    assert torch.equal(a, a2) and torch.equal(j, j2)
+
+
+CONFIGS = [(64, 1, 64, 1, 0), (256, 2, 256, 3, 0), (128, 1, 1024, 9, 0), (256, 1, 256, 1, 1),
+           (128, 2, 64, 5, 1), (64, 2, 512, 64, 1)]
+
+
+@pytest.mark.parametrize("cfg", CONFIGS)
+def test_jerk_launch_configurations(nb, cfg):
+    block, ipl, jt, js, stage = cfg
+    x, v, m = W.plummer(2500, 13)
+    ref64 = oracle.gravity_jerk(x, v, m, eps=EPS)
+    ref32 = oracle.gravity_jerk(W.round_to_f32(x), W.round_to_f32(v), W.round_to_f32(m), eps=EPS)
+    try:
+        nb.set_config(nb.API_JERK, block, ipl, jt, js, stage)
+        g64 = nb.forces_jerk(dev(x), dev(v), dev(m), nb.gravity("fp64", softening=EPS))
+        g32 = nb.forces_jerk(dev(x), dev(v), dev(m), nb.gravity("fp32_kahan", softening=EPS))
+    finally:
+        nb.clear_config(nb.API_JERK)
+    check("fp64", tuple(host(t) for t in g64), ref64)
+    check("fp32_kahan", tuple(host(t) for t in g32), ref32)
+
+
+def test_hermite_shared_step_matches_oracle(nb):
+    x, v, m = W.plummer(1024, 14)
+    law = nb.gravity("fp64", softening=EPS)
+    a0, j0, _ = oracle.gravity_jerk(x, v, m, eps=EPS)
+    X, V, A, J = dev(x), dev(v), dev(a0), dev(j0)
+    nb.hermite(X, V, A, J, dev(m), law, 1.0 / 1024, 8)
+    xr, vr, ar, jr = oracle.hermite(x, v, a0, j0, m, 1.0 / 1024, 8, eps=EPS)
+    assert np.abs(host(X) - xr).max() <= 1e-12 * np.abs(xr).max()
+    assert np.abs(host(V) - vr).max() <= 1e-12 * np.abs(vr).max()
+    assert rel_rows(host(A), ar).max() <= 1e-11
+    assert rel_rows(host(J), jr).max() <= 1e-10
+
+
+def test_hermite_fp32_conserves_energy(nb):
+    x, v, m = W.plummer(4096, 15)
+    eps = 0.05
+    law = nb.gravity("fp32_kahan", softening=eps)
+    X, V = dev(x), dev(v)
+    A, J, _ = nb.forces_jerk(X, V, dev(m), law, potential=False)
+
+    def energy(xx, vv):
+        _, phi = oracle.gravity(xx, m, eps=eps)
+        return 0.5 * (m * (vv * vv).sum(1)).sum() + 0.5 * (m * phi).sum()
+
+    e0 = energy(x, v)
+    nb.hermite(X, V, A, J, dev(m), law, 1.0 / 256, 32)
+    assert abs(energy(host(X), host(V)) - e0) < 1e-6 * abs(e0)
+
+
+def test_block_steps_match_oracle_schedule(nb):
+    x, v, m = W.plummer(512, 16)
+    eta_s, eta, dt_max = 0.01, 0.02, 1.0 / 64
+    law = nb.gravity("fp64", softening=EPS)
+    a0, j0, _ = oracle.gravity_jerk(x, v, m, eps=EPS)
+    t_r, dt_r = oracle.hermite_block_init(a0, j0, eta_s, dt_max)
+    X, V, A, J = dev(x), dev(v), dev(a0), dev(j0)
+    T, DT = nb.hermite_block_init(A, J, eta_s, dt_max)
+    np.testing.assert_array_equal(host(T), t_r)
+    np.testing.assert_array_equal(host(DT), dt_r)
+    assert len(np.unique(dt_r)) > 2                              # genuinely individual steps
+    nblocks = 40
+    counts, t_now = nb.hermite_block(X, V, A, J, T, DT, dev(m), law, eta, dt_max, nblocks)
+    xr, vr, ar, jr, tr, dtr, cr, tnr = oracle.hermite_block(x, v, a0, j0, t_r, dt_r, m, nblocks, eta,
+                                                            dt_max, eps=EPS)
+    np.testing.assert_array_equal(counts, cr)
+    assert t_now == tnr
+    np.testing.assert_array_equal(host(T), tr)
+    np.testing.assert_array_equal(host(DT), dtr)
+    assert counts.min() >= 1 and counts.min() < 512              # some steps were partial
+    assert np.abs(host(X) - xr).max() <= 1e-12 * np.abs(xr).max()
+    assert np.abs(host(V) - vr).max() <= 1e-12 * np.abs(vr).max()
+    assert rel_rows(host(A), ar).max() <= 1e-10
+
+
+def test_block_steps_reduce_to_shared_step(nb):
+    x, v, m = W.plummer(700, 17)
+    dt_max = 1.0 / 256
+    law = nb.gravity("fp64", softening=EPS)
+    A0, J0, _ = nb.forces_jerk(dev(x), dev(v), dev(m), law, potential=False)
+    Xb, Vb, Ab, Jb = dev(x), dev(v), A0.clone(), J0.clone()
+    T, DT = nb.hermite_block_init(Ab, Jb, 1e6, dt_max)
+    assert torch.all(DT == dt_max)
+    counts, t_now = nb.hermite_block(Xb, Vb, Ab, Jb, T, DT, dev(m), law, 1e6, dt_max, 5)
+    assert np.all(counts == 700) and t_now == 5 * dt_max
+    Xs, Vs, As, Js = dev(x), dev(v), A0.clone(), J0.clone()
+    nb.hermite(Xs, Vs, As, Js, dev(m), law, dt_max, 5)
+    for b, s in ((Xb, Xs), (Vb, Vs), (Ab, As), (Jb, Js)):
+        assert torch.equal(b, s)
+
+
+def test_block_steps_fp32_energy(nb):
+    x, v, m = W.plummer(2048, 18)
+    eps, eta, dt_max = 0.02, 0.02, 1.0 / 32
+    law = nb.gravity("fp32_fp64acc", softening=eps)
+    X, V = dev(x), dev(v)
+    A, J, _ = nb.forces_jerk(X, V, dev(m), law, potential=False)
+    T, DT = nb.hermite_block_init(A, J, 0.01, dt_max)
+
+    def energy(xx, vv):
+        _, phi = oracle.gravity(xx, m, eps=eps)
+        return 0.5 * (m * (vv * vv).sum(1)).sum() + 0.5 * (m * phi).sum()
+
+    e0 = energy(x, v)
+    total = 0
+    t_now = 0.0
+    while t_now < dt_max:                                   # run to the next synchronisation point
+        counts, t_now = nb.hermite_block(X, V, A, J, T, DT, dev(m), law, eta, dt_max, 1)
+        total += int(counts[0])
+    assert t_now == dt_max and torch.all(T == dt_max)
+    assert total > 2048                                     # several block steps
+    assert abs(energy(host(X), host(V)) - e0) < 1e-6 * abs(e0)
