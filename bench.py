@@ -16,7 +16,8 @@ sample on the host cores, the accuracy of the timed path against the FP64 GPU
 pass and the oracle, and three secondary legs: the batched ensemble (256 LJC
 systems, N_s in [500, 5000], one persistent launch vs one launch per system,
 each side autotuned), the position adjoint at N = 262,144 (FP32 vs FP64), and
-every pair law of Table 1 at N = 65,536.
+every pair law of Table 1 at N = 65,536, plus the acceleration-and-jerk kernel
+and the block-time-step Hermite integrator on a Plummer sphere of 65,536.
 """
 from __future__ import annotations
 
@@ -197,6 +198,7 @@ def main():
         out["batched"] = batched_leg(nb, torch, dev, ens)
         out["backward"] = backward_leg(nb, torch, dev, W)
         out["laws"] = laws_leg(nb, torch, dev, W, md)
+        out["jerk"] = jerk_leg(nb, torch, dev, W)
     print(json.dumps(out), flush=True)
 
 
@@ -356,6 +358,78 @@ def laws_leg(nb, torch, dev, W, md):
                      "kernel_tflops": tf, "frac_fp32_peak": tf / PEAK_FP32_TFLOPS,
                      "err_vs_fp64": {"median": float(np.median(e)), "max": float(e.max())}}
         log("law %s:" % name, res[name])
+    return res
+
+
+def jerk_leg(nb, torch, dev, W):
+    """Acceleration + jerk (Table 1 "Gravity (accel & jerk)") on a Plummer sphere with
+    N = 65,536, FP32 + Kahan with the potential; then the Hermite scheme with block
+    individual steps (FP32 + FP64 accumulation, eta = 0.02, dt_max = 1/16) run from
+    t = 0 to the first synchronisation point t = 1/16, with its energy error."""
+    n = 65536
+    eps = 0.01
+    x, v, m = W.plummer(n, 2)
+    X = torch.tensor(x, device=dev)
+    V = torch.tensor(v, device=dev)
+    M = torch.tensor(m, device=dev)
+    law = nb.gravity("fp32_kahan", softening=eps)
+    cfg, _ = nb.autotune_jerk(X, V, M, law, potential=True)
+    a32, j32, _ = nb.forces_jerk(X, V, M, law)
+    torch.cuda.synchronize()
+    reps = 10
+    nb.timing_read(reset=True)
+    nb.timing_enable(True)
+    t = time.perf_counter()
+    for _ in range(reps):
+        nb.forces_jerk(X, V, M, law)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t) / reps
+    nb.timing_enable(False)
+    k_ms, k_n = nb.timing_read(reset=True)
+    k_s = k_ms / max(k_n, 1) * 1e-3
+    fpp = nb.flops_per_pair(nb.API_JERK, nb.GRAVITY, True)
+    a64, j64, _ = nb.forces_jerk(X, V, M, nb.gravity("fp64", softening=eps))
+    ea = (torch.linalg.norm(a32 - a64, dim=1) / torch.linalg.norm(a64, dim=1)).cpu().numpy()
+    ej = (torch.linalg.norm(j32 - j64, dim=1) / torch.linalg.norm(j64, dim=1)).cpu().numpy()
+    tf = fpp * float(n) * n / k_s / 1e12
+    res = {"n": n, "config": cfg, "ms": wall * 1e3, "kernel_ms": k_s * 1e3,
+           "g_pairs_per_s": float(n) * n / wall / 1e9, "flops_per_pair": fpp,
+           "kernel_tflops": tf, "frac_fp32_peak": tf / PEAK_FP32_TFLOPS,
+           "acc_err_vs_fp64": {"median": float(np.median(ea)), "max": float(ea.max())},
+           "jerk_err_vs_fp64": {"median": float(np.median(ej)), "max": float(ej.max())}}
+    log("jerk:", res)
+
+    # block individual time steps to the first synchronisation point
+    lawb = nb.gravity("fp32_fp64acc", softening=eps)
+    law64 = nb.gravity("fp64", softening=eps)
+    dt_max, eta = 1.0 / 16, 0.02
+
+    def energy():
+        _, phi = nb.forces(X, M, law64)
+        return float((0.5 * (M * (V * V).sum(1)).sum() + 0.5 * (M * phi).sum()).item())
+
+    A, J, _ = nb.forces_jerk(X, V, M, lawb, potential=False)
+    T, DT = nb.hermite_block_init(A, J, 0.01, dt_max)
+    e0 = energy()
+    torch.cuda.synchronize()
+    counts = []
+    t_now = 0.0
+    t = time.perf_counter()
+    while t_now < dt_max:               # one block step per call: stop exactly at t = dt_max
+        c, t_now = nb.hermite_block(X, V, A, J, T, DT, M, lawb, eta, dt_max, 1)
+        counts.append(int(c[0]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    e1 = energy()
+    steps = np.asarray(counts)
+    pairs = float(steps.sum()) * n
+    res["block_steps"] = {"law": "fp32_fp64acc", "eta": eta, "dt_max": dt_max, "t_end": t_now,
+                          "block_steps": int(steps.size), "particle_steps": int(steps.sum()),
+                          "mean_active": float(steps.mean()), "min_active": int(steps.min()),
+                          "max_active": int(steps.max()), "wall_s": wall,
+                          "g_pairs_per_s": pairs / wall / 1e9,
+                          "rel_energy_error": abs(e1 - e0) / abs(e0)}
+    log("block steps:", res["block_steps"])
     return res
 
 
