@@ -21,6 +21,8 @@ counterpart cites:
   kick-drift-kick leapfrog;
 * :func:`gravity_adjoint`, :func:`ljc_adjoint` -- derivatives of the two laws
   (not in the paper; written out from the definitions above);
+* :func:`ljc_excl`, :func:`ljc_adjoint_excl` -- the LJC laws and the LJC(linear)
+  adjoint with per-particle exclusion lists (Section 5);
 * :func:`gravity_jerk` -- Table 1 "Gravity (accel & jerk)", the GAJ kernel of
   Section 2;
 * :func:`hermite`, :func:`hermite_block_init`, :func:`hermite_block` -- the
@@ -75,6 +77,8 @@ def _load():
         lib.oracle_leapfrog.argtypes = [I, P, P, P, P, P, I64, D, D, D, ctypes.c_int32, P, I]
         lib.oracle_gravity_adjoint.argtypes = [P, P, I64, D, D, P, P, I64, P, I]
         lib.oracle_ljc_adjoint.argtypes = [P, P, P, P, I64, D, D, P, P, I64, P, P, P, P, I]
+        lib.oracle_ljc_excl.argtypes = [I, P, P, P, P, I64, D, D, P, P, P, P, P, I]
+        lib.oracle_ljc_adjoint_excl.argtypes = [P, P, P, P, I64, D, D, P, P, P, P, P, P, P, I]
         lib.oracle_gravity_jerk.argtypes = [P, P, P, I64, D, D, P, I64, P, P, P, I]
         lib.oracle_hermite.argtypes = [P, P, P, P, P, I64, D, D, D, ctypes.c_int32, I]
         lib.oracle_hermite_block_init.argtypes = [P, P, I64, D, D, P, P]
@@ -83,7 +87,8 @@ def _load():
         for f in (lib.oracle_gravity, lib.oracle_ljc_linear, lib.oracle_ljc_constant,
                   lib.oracle_ljc_sigmoidal, lib.oracle_leapfrog,
                   lib.oracle_gravity_adjoint, lib.oracle_ljc_adjoint, lib.oracle_gravity_jerk,
-                  lib.oracle_hermite, lib.oracle_hermite_block_init, lib.oracle_hermite_block):
+                  lib.oracle_hermite, lib.oracle_hermite_block_init, lib.oracle_hermite_block,
+                  lib.oracle_ljc_excl, lib.oracle_ljc_adjoint_excl):
             f.restype = I
         _lib = lib
     return _lib
@@ -324,3 +329,50 @@ def hermite_block(pos, vel, acc, jerk, t_i, dt_i, mass, nblocks, eta, dt_max, G=
     if rc:
         raise ValueError("oracle_hermite_block rc=%d" % rc)
     return pos, vel, acc, jerk, t_i, dt_i, active[:int(nblocks)], t_now.value
+
+
+def _excl(eoff, eidx, n):
+    eoff = np.ascontiguousarray(eoff, dtype=np.int64)
+    eidx = np.ascontiguousarray(eidx, dtype=np.int64)
+    if eoff.shape != (n + 1,) or eoff[0] != 0 or np.any(np.diff(eoff) < 0) or eoff[-1] != eidx.size:
+        raise ValueError("bad exclusion offsets")
+    if eidx.size and (eidx.min() < 0 or eidx.max() >= n):
+        raise ValueError("exclusion index out of range")
+    if eidx.size == 0:
+        eidx = np.zeros(1, dtype=np.int64)     # a valid pointer; never read
+    return eoff, eidx
+
+
+def ljc_excl(kind, pos, q, sigma, epsilon, excl_offsets, excl_index, kc=332.0637, D=4.0,
+             zeta_coef=(0.0, 0.0, 0.0, 0.0), nthreads=0):
+    """LJC law `kind` (LJC_LINEAR, LJC_CONSTANT or 3 = sigmoidal) with exclusion lists:
+    pair (i, j) is left out of atom i's sums when j is in its list.  (force, U_i)."""
+    pos, q, sigma, epsilon, n, _, _ = _ljc_args(pos, q, sigma, epsilon, None)
+    eoff, eidx = _excl(excl_offsets, excl_index, n)
+    zc = _f64(zeta_coef, (4,))
+    f = np.empty((n, 3))
+    u = np.empty(n)
+    rc = _load().oracle_ljc_excl(int(kind), _ptr(pos), _ptr(q), _ptr(sigma), _ptr(epsilon), n,
+                                 float(kc), float(D), _ptr(zc), _ptr(eoff), _ptr(eidx), _ptr(f),
+                                 _ptr(u), int(nthreads))
+    if rc:
+        raise ValueError("oracle_ljc_excl rc=%d" % rc)
+    return f, u
+
+
+def ljc_adjoint_excl(pos, q, sigma, epsilon, g, excl_offsets, excl_index, kc=332.0637, D=4.0,
+                     nthreads=0):
+    """LJC(linear) adjoint with (symmetric) exclusion lists: (dL/dr, dL/dq, dL/dsigma, dL/deps)."""
+    pos, q, sigma, epsilon, n, _, _ = _ljc_args(pos, q, sigma, epsilon, None)
+    g = _f64(g, (n, 3))
+    eoff, eidx = _excl(excl_offsets, excl_index, n)
+    gp = np.empty((n, 3))
+    gq = np.empty(n)
+    gs = np.empty(n)
+    ge = np.empty(n)
+    rc = _load().oracle_ljc_adjoint_excl(_ptr(pos), _ptr(q), _ptr(sigma), _ptr(epsilon), n,
+                                         float(kc), float(D), _ptr(g), _ptr(eoff), _ptr(eidx),
+                                         _ptr(gp), _ptr(gq), _ptr(gs), _ptr(ge), int(nthreads))
+    if rc:
+        raise ValueError("oracle_ljc_adjoint_excl rc=%d" % rc)
+    return gp, gq, gs, ge

@@ -66,6 +66,17 @@ int oracle_threads(int nthreads) { return set_threads(nthreads); }
 
 static inline int64_t row(const int64_t *ilist, int64_t k) { return ilist ? ilist[k] : k; }
 
+/* Exclusion lists (Section 5: the LJC kernels read an exclusion list for each
+ * particle).  Pair (i, j) is left out of particle i's sums when j appears in
+ * eidx[eoff[i] .. eoff[i+1]).  eoff == NULL means no exclusions. */
+static inline int excluded(const int64_t *eoff, const int64_t *eidx, int64_t i, int64_t j)
+{
+    if (!eoff) return 0;
+    for (int64_t e = eoff[i]; e < eoff[i + 1]; ++e)
+        if (eidx[e] == j) return 1;
+    return 0;
+}
+
 /* ------------------------------------------------------------------------
  * Softened gravity, Eq. 1 (Section 3.3) and Table 1 row "Gravity (accel)".
  *   a_i   = G sum_{j != i, j0 <= j < j1} m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2}
@@ -118,10 +129,11 @@ int oracle_gravity(const double *pos, const double *mass, int64_t n, double G, d
  * params per atom: q (charge), sigma, epsilon.  force is [ni][3], energy
  * [ni] or NULL.
  * ---------------------------------------------------------------------- */
-int oracle_ljc_linear(const double *pos, const double *q, const double *sigma,
-                      const double *epsl, int64_t n, double kc, double D,
-                      const int64_t *ilist, int64_t ni, int64_t j0, int64_t j1,
-                      double *force, double *energy, int nthreads)
+static int ljc_linear_impl(const double *pos, const double *q, const double *sigma,
+                           const double *epsl, int64_t n, double kc, double D,
+                           const int64_t *ilist, int64_t ni, int64_t j0, int64_t j1,
+                           const int64_t *eoff, const int64_t *eidx,
+                           double *force, double *energy, int nthreads)
 {
     if (n < 0 || ni < 0 || j0 < 0 || j1 > n || j0 > j1) return -1;
     set_threads(nthreads);
@@ -131,7 +143,7 @@ int oracle_ljc_linear(const double *pos, const double *q, const double *sigma,
         const double xi = pos[3 * i], yi = pos[3 * i + 1], zi = pos[3 * i + 2];
         nsum fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, en = {0, 0};
         for (int64_t j = j0; j < j1; ++j) {
-            if (j == i) continue;
+            if (j == i || excluded(eoff, eidx, i, j)) continue;
             const double rx = xi - pos[3 * j];
             const double ry = yi - pos[3 * j + 1];
             const double rz = zi - pos[3 * j + 2];
@@ -156,6 +168,15 @@ int oracle_ljc_linear(const double *pos, const double *q, const double *sigma,
     return 0;
 }
 
+int oracle_ljc_linear(const double *pos, const double *q, const double *sigma,
+                      const double *epsl, int64_t n, double kc, double D,
+                      const int64_t *ilist, int64_t ni, int64_t j0, int64_t j1,
+                      double *force, double *energy, int nthreads)
+{
+    return ljc_linear_impl(pos, q, sigma, epsl, n, kc, D, ilist, ni, j0, j1, NULL, NULL, force,
+                           energy, nthreads);
+}
+
 /* ------------------------------------------------------------------------
  * LJ + Coulomb with a constant dielectric D (Table 1 row "LJC (constant)").
  *   u_ij = kc q_i q_j / (D r) + 4 e_ij [(s_ij/r)^12 - (s_ij/r)^6]
@@ -163,10 +184,10 @@ int oracle_ljc_linear(const double *pos, const double *q, const double *sigma,
  *                         + (24 e_ij / r^2) (2 (s_ij/r)^12 - (s_ij/r)^6) ] (r_i - r_j)
  * (the Coulomb term is Table 1's q_i q_j r_ij / (eps r^3) with the constant kc / D).
  * ---------------------------------------------------------------------- */
-int oracle_ljc_constant(const double *pos, const double *q, const double *sigma,
-                        const double *epsl, int64_t n, double kc, double D,
-                        const int64_t *ilist, int64_t ni, double *force, double *energy,
-                        int nthreads)
+static int ljc_constant_impl(const double *pos, const double *q, const double *sigma,
+                             const double *epsl, int64_t n, double kc, double D,
+                             const int64_t *ilist, int64_t ni, const int64_t *eoff,
+                             const int64_t *eidx, double *force, double *energy, int nthreads)
 {
     if (n < 0 || ni < 0) return -1;
     set_threads(nthreads);
@@ -175,7 +196,7 @@ int oracle_ljc_constant(const double *pos, const double *q, const double *sigma,
         const int64_t i = row(ilist, k);
         nsum fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, en = {0, 0};
         for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
+            if (j == i || excluded(eoff, eidx, i, j)) continue;
             const double rx = pos[3 * i] - pos[3 * j];
             const double ry = pos[3 * i + 1] - pos[3 * j + 1];
             const double rz = pos[3 * i + 2] - pos[3 * j + 2];
@@ -201,6 +222,15 @@ int oracle_ljc_constant(const double *pos, const double *q, const double *sigma,
     return 0;
 }
 
+int oracle_ljc_constant(const double *pos, const double *q, const double *sigma,
+                        const double *epsl, int64_t n, double kc, double D,
+                        const int64_t *ilist, int64_t ni, double *force, double *energy,
+                        int nthreads)
+{
+    return ljc_constant_impl(pos, q, sigma, epsl, n, kc, D, ilist, ni, NULL, NULL, force, energy,
+                             nthreads);
+}
+
 /* ------------------------------------------------------------------------
  * LJ + Coulomb with a distance-dependent dielectric zeta(r) (Table 1 row
  * "LJC (sigmoidal)").  The printed zeta(r) = exp(alpha r^3 + beta r^2 + gamma
@@ -212,10 +242,10 @@ int oracle_ljc_constant(const double *pos, const double *q, const double *sigma,
  *                         + (24 e_ij / r^2) (2 (s_ij/r)^12 - (s_ij/r)^6) ] (r_i - r_j)
  * with zeta'/zeta = 3 alpha r^2 + 2 beta r + gamma.
  * ---------------------------------------------------------------------- */
-int oracle_ljc_sigmoidal(const double *pos, const double *q, const double *sigma,
-                         const double *epsl, int64_t n, double kc, const double *zc,
-                         const int64_t *ilist, int64_t ni, double *force, double *energy,
-                         int nthreads)
+static int ljc_sigmoidal_impl(const double *pos, const double *q, const double *sigma,
+                              const double *epsl, int64_t n, double kc, const double *zc,
+                              const int64_t *ilist, int64_t ni, const int64_t *eoff,
+                              const int64_t *eidx, double *force, double *energy, int nthreads)
 {
     if (n < 0 || ni < 0 || !zc) return -1;
     set_threads(nthreads);
@@ -225,7 +255,7 @@ int oracle_ljc_sigmoidal(const double *pos, const double *q, const double *sigma
         const int64_t i = row(ilist, k);
         nsum fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, en = {0, 0};
         for (int64_t j = 0; j < n; ++j) {
-            if (j == i) continue;
+            if (j == i || excluded(eoff, eidx, i, j)) continue;
             const double rx = pos[3 * i] - pos[3 * j];
             const double ry = pos[3 * i + 1] - pos[3 * j + 1];
             const double rz = pos[3 * i + 2] - pos[3 * j + 2];
@@ -252,6 +282,35 @@ int oracle_ljc_sigmoidal(const double *pos, const double *q, const double *sigma
         if (energy) energy[k] = nval(&en);
     }
     return 0;
+}
+
+int oracle_ljc_sigmoidal(const double *pos, const double *q, const double *sigma,
+                         const double *epsl, int64_t n, double kc, const double *zc,
+                         const int64_t *ilist, int64_t ni, double *force, double *energy,
+                         int nthreads)
+{
+    return ljc_sigmoidal_impl(pos, q, sigma, epsl, n, kc, zc, ilist, ni, NULL, NULL, force, energy,
+                              nthreads);
+}
+
+/* Any of the three LJC laws (kind 1 linear, 2 constant, 3 sigmoidal; c1 is D
+ * for the first two, zc the sigmoidal coefficients) with exclusion lists
+ * eoff [n+1], eidx [eoff[n]] (pair (i, j) skipped when j is in i's list). */
+int oracle_ljc_excl(int kind, const double *pos, const double *q, const double *sigma,
+                    const double *epsl, int64_t n, double kc, double D, const double *zc,
+                    const int64_t *eoff, const int64_t *eidx, double *force, double *energy,
+                    int nthreads)
+{
+    if (!eoff || !eidx) return -1;
+    switch (kind) {
+    case 1: return ljc_linear_impl(pos, q, sigma, epsl, n, kc, D, NULL, n, 0, n, eoff, eidx, force,
+                                   energy, nthreads);
+    case 2: return ljc_constant_impl(pos, q, sigma, epsl, n, kc, D, NULL, n, eoff, eidx, force,
+                                     energy, nthreads);
+    case 3: return ljc_sigmoidal_impl(pos, q, sigma, epsl, n, kc, zc, NULL, n, eoff, eidx, force,
+                                      energy, nthreads);
+    default: return -1;
+    }
 }
 
 /* ------------------------------------------------------------------------
@@ -372,10 +431,11 @@ int oracle_gravity_adjoint(const double *pos, const double *mass, int64_t n, dou
  *      w_LJ = -24 e (2 s^12 / r^14 - s^6 / r^8).
  * Outputs are per atom ([ni][3] and [ni]); any output may be NULL.
  * ---------------------------------------------------------------------- */
-int oracle_ljc_adjoint(const double *pos, const double *q, const double *sigma, const double *epsl,
-                       int64_t n, double kc, double D, const double *g, const int64_t *ilist,
-                       int64_t ni, double *grad_pos, double *grad_q, double *grad_sigma,
-                       double *grad_eps, int nthreads)
+static int ljc_adjoint_impl(const double *pos, const double *q, const double *sigma,
+                            const double *epsl, int64_t n, double kc, double D, const double *g,
+                            const int64_t *ilist, int64_t ni, const int64_t *eoff,
+                            const int64_t *eidx, double *grad_pos, double *grad_q,
+                            double *grad_sigma, double *grad_eps, int nthreads)
 {
     if (n < 0 || ni < 0) return -1;
     set_threads(nthreads);
@@ -384,7 +444,7 @@ int oracle_ljc_adjoint(const double *pos, const double *q, const double *sigma, 
         const int64_t k = row(ilist, kk);
         nsum px = {0, 0}, py = {0, 0}, pz = {0, 0}, gq = {0, 0}, gs = {0, 0}, ge = {0, 0};
         for (int64_t j = 0; j < n; ++j) {
-            if (j == k) continue;
+            if (j == k || excluded(eoff, eidx, k, j)) continue;
             const double dx = pos[3 * j] - pos[3 * k];
             const double dy = pos[3 * j + 1] - pos[3 * k + 1];
             const double dz = pos[3 * j + 2] - pos[3 * k + 2];
@@ -429,6 +489,28 @@ int oracle_ljc_adjoint(const double *pos, const double *q, const double *sigma, 
         if (grad_eps) grad_eps[kk] = nval(&ge);
     }
     return 0;
+}
+
+int oracle_ljc_adjoint(const double *pos, const double *q, const double *sigma, const double *epsl,
+                       int64_t n, double kc, double D, const double *g, const int64_t *ilist,
+                       int64_t ni, double *grad_pos, double *grad_q, double *grad_sigma,
+                       double *grad_eps, int nthreads)
+{
+    return ljc_adjoint_impl(pos, q, sigma, epsl, n, kc, D, g, ilist, ni, NULL, NULL, grad_pos,
+                            grad_q, grad_sigma, grad_eps, nthreads);
+}
+
+/* The LJC(linear) adjoint with exclusion lists.  It is the derivative of the
+ * excluded forward when the lists are symmetric (j in E(i) exactly when i is
+ * in E(j)), which bonded topologies are. */
+int oracle_ljc_adjoint_excl(const double *pos, const double *q, const double *sigma,
+                            const double *epsl, int64_t n, double kc, double D, const double *g,
+                            const int64_t *eoff, const int64_t *eidx, double *grad_pos,
+                            double *grad_q, double *grad_sigma, double *grad_eps, int nthreads)
+{
+    if (!eoff || !eidx) return -1;
+    return ljc_adjoint_impl(pos, q, sigma, epsl, n, kc, D, g, NULL, n, eoff, eidx, grad_pos, grad_q,
+                            grad_sigma, grad_eps, nthreads);
 }
 
 /* ------------------------------------------------------------------------

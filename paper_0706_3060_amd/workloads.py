@@ -148,6 +148,96 @@ def md_system(n: int, seed: int, box: float = 64.0, min_sep: float = 2.5, qmax: 
     return MDSystem(pos=pos, q=q, types=types.astype(np.int32), sigma_t=sig, eps_t=eps, box=box)
 
 
+def bonded_chains(n_chains: int, chain_len: int, seed: int, box: float = None,
+                  density: float = 1.0 / 32.0, bond: float = 1.53, angle_deg: float = 111.0,
+                  min_sep: float = 2.5, qmax: float = 0.8, n_types: int = 4, excl_depth: int = 2):
+    """Synthetic bonded molecules: ``n_chains`` linear chains of ``chain_len`` atoms in a cube.
+
+    Each chain grows as a fixed-bond, fixed-angle walk (bond length ``bond`` A, bond angle
+    ``angle_deg``, uniformly random dihedral) and every new atom keeps ``min_sep`` from every
+    atom placed before it except its own bonded predecessor.  Atoms are numbered chain by
+    chain.  The exclusion list of atom i holds the atoms of its chain within ``excl_depth``
+    bonds (1-2 and 1-3 pairs for depth 2), so the lists are symmetric.  Types, charges and the
+    per-type sigma / epsilon follow the md_system recipe.
+    Returns (MDSystem, excl_offsets [n+1] int64, excl_index [nnz] int64)."""
+    rng = np.random.default_rng(seed)
+    n = n_chains * chain_len
+    if box is None:
+        box = (max(n, 1) / density) ** (1.0 / 3.0)
+    cell = min_sep
+    grid = {}
+    pts = np.zeros((n, 3))
+    d2min = min_sep * min_sep
+    cos_t, sin_t = np.cos(np.radians(angle_deg)), np.sin(np.radians(angle_deg))
+
+    def clear(p, skip):
+        c = np.floor(p / cell).astype(np.int64)
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    for k in grid.get((c[0] + dx, c[1] + dy, c[2] + dz), ()):
+                        if k != skip and ((pts[k] - p) ** 2).sum() < d2min:
+                            return False
+        return True
+
+    def put(k, p):
+        pts[k] = p
+        c = np.floor(p / cell).astype(np.int64)
+        grid.setdefault((c[0], c[1], c[2]), []).append(k)
+
+    def unit(v):
+        return v / np.linalg.norm(v)
+
+    k = 0
+    for _ in range(n_chains):
+        for attempt in range(1000):
+            start = k
+            placed = []
+            ok = True
+            for a in range(chain_len):
+                for _try in range(100):
+                    if a == 0:
+                        p = rng.uniform(0.0, box, 3)
+                    elif a == 1:
+                        p = pts[k - 1] + bond * unit(rng.standard_normal(3))
+                    else:
+                        b1 = unit(pts[k - 1] - pts[k - 2])
+                        e1 = unit(np.cross(b1, rng.standard_normal(3)))
+                        # the next bond makes angle_deg with the previous one (reversed)
+                        p = pts[k - 1] + bond * (-cos_t * b1 + sin_t * e1)
+                    if clear(p, k - 1 if a > 0 else -1):
+                        break
+                else:
+                    ok = False
+                    break
+                put(k, p)
+                placed.append(k)
+                k += 1
+            if ok:
+                break
+            for idx in placed:                      # undo the failed chain
+                c = np.floor(pts[idx] / cell).astype(np.int64)
+                grid[(c[0], c[1], c[2])].remove(idx)
+            k = start
+        else:
+            raise RuntimeError("could not place a chain")
+    types = rng.integers(0, n_types, n).astype(np.int32)
+    q = rng.uniform(-qmax, qmax, n)
+    if n:
+        q -= q.mean()
+    sys_ = MDSystem(pos=pts, q=q, types=types, sigma_t=np.linspace(3.0, 3.8, n_types),
+                    eps_t=np.linspace(0.05, 0.2, n_types), box=box)
+    lists = []
+    for i in range(n):
+        c0 = (i // chain_len) * chain_len
+        lists.append([j for j in range(max(c0, i - excl_depth), min(c0 + chain_len, i + excl_depth + 1))
+                      if j != i])
+    eoff = np.zeros(n + 1, dtype=np.int64)
+    eoff[1:] = np.cumsum([len(l) for l in lists])
+    eidx = np.array([j for l in lists for j in l], dtype=np.int64)
+    return sys_, eoff, eidx
+
+
 def perturbed(sys: MDSystem, seed: int, rel: float = 0.05) -> MDSystem:
     """Same atoms, parameters scaled by (1 + rel*xi), xi ~ U[-1, 1] (charges per atom,
     sigma and epsilon per type)."""
