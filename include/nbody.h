@@ -121,8 +121,27 @@ enum nbody_api {
     NBODY_API_BACKWARD = 2,
     NBODY_API_LEAPFROG = 3,
     NBODY_API_JERK = 4,       /* nbody_forces_jerk */
-    NBODY_API_HERMITE = 5     /* hermite_step, hermite_block_steps */
+    NBODY_API_HERMITE = 5,    /* hermite_step, hermite_block_steps */
+    NBODY_API_BACKWARD_BATCHED = 6   /* nbody_forces_backward_batched */
 };
+
+/* Per-particle exclusion lists for bonded molecular systems (Section 5: the
+ * LJC kernels read an exclusion list for each particle).  Particle x leaves
+ * out of its sums every particle listed in index[offsets[x] .. offsets[x+1])
+ * (caller particle indices; any order; repeats allowed).  Bonded topologies
+ * give symmetric lists (y in x's list exactly when x is in y's), which keeps
+ * Newton's third law; the adjoint assumes symmetric lists.
+ *  offsets  [n + 1] device int64, non-decreasing, offsets[0] = 0;
+ *  index    [count] device int64 (may be NULL when count == 0);
+ *  count    number of entries of index.
+ * List ranges are clamped to [0, count) and entries are only compared, never
+ * dereferenced, so entries outside [0, n) (or naming another system of a
+ * batch) have no effect. */
+typedef struct nbody_exclusions {
+    const int64_t *offsets;
+    const int64_t *index;
+    int64_t count;
+} nbody_exclusions;
 
 /* Launch configuration of the all-pairs kernels (see nbody_set_config).
  *  block      threads per workgroup, a multiple of 64 in [64, 256];
@@ -206,6 +225,43 @@ int nbody_forces_backward(const double *pos, const double *params, int64_t n,
                           const nbody_law *law, const double *grad_force, double *grad_pos,
                           double *grad_params, const int32_t *types, int32_t n_types,
                           double *grad_type_params, void *ws, size_t ws_bytes, void *stream);
+
+/* nbody_forces with exclusion lists (LJC laws; NBODY_ENOTSUP for gravity and
+ * NBODY_FP32_PLAIN).  `excl` (host struct, device arrays) must be non-NULL.
+ * Workspace: nbody_workspace_bytes(NBODY_API_FORCES, n, 1, law). */
+int nbody_forces_excl(const double *pos, const double *params, int64_t n,
+                      const nbody_exclusions *excl, const nbody_law *law, double *out_force,
+                      double *out_potential, void *ws, size_t ws_bytes, void *stream);
+
+/* nbody_forces_batched with exclusion lists over the concatenated rows
+ * (offsets / index name rows of pos; partners outside a row's own system are
+ * ignored).  Laws and precisions as nbody_forces_excl.  Workspace:
+ * nbody_workspace_bytes(NBODY_API_BATCHED, offsets[S], S, law). */
+int nbody_forces_batched_excl(const int64_t *offsets, int64_t n_systems, const double *pos,
+                              const double *params, const nbody_exclusions *excl,
+                              const nbody_law *law, double *out_force, double *out_potential,
+                              void *ws, size_t ws_bytes, void *stream);
+
+/* nbody_forces_backward with (symmetric) exclusion lists, LJC(linear) only:
+ * the adjoint of nbody_forces_excl.  Workspace as nbody_forces_backward. */
+int nbody_forces_backward_excl(const double *pos, const double *params, int64_t n,
+                               const nbody_exclusions *excl, const nbody_law *law,
+                               const double *grad_force, double *grad_pos, double *grad_params,
+                               const int32_t *types, int32_t n_types, double *grad_type_params,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/* The adjoint of nbody_forces_batched (or, with excl != NULL, of
+ * nbody_forces_batched_excl): many independent systems in ONE persistent
+ * launch, as the batched forward.  Arguments as nbody_forces_backward over
+ * the concatenated rows; with types, grad_type_params sums over the atoms of
+ * each type across all systems.  Laws: gravity and LJC(linear) (exclusions:
+ * LJC(linear)).  Workspace:
+ * nbody_workspace_bytes(NBODY_API_BACKWARD_BATCHED, offsets[S], S, law). */
+int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
+                                  const double *params, const nbody_exclusions *excl,
+                                  const nbody_law *law, const double *grad_force, double *grad_pos,
+                                  double *grad_params, const int32_t *types, int32_t n_types,
+                                  double *grad_type_params, void *ws, size_t ws_bytes, void *stream);
 
 /* `nsteps` kick-drift-kick leapfrog steps in FP64 (the force-evaluation /
  * update-step cycle of Section 1):

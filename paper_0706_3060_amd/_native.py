@@ -24,6 +24,7 @@ NBODY_EWORKSPACE = -3
 NBODY_EHIP = -4
 
 API_FORCES, API_BATCHED, API_BACKWARD, API_LEAPFROG, API_JERK, API_HERMITE = 0, 1, 2, 3, 4, 5
+API_BACKWARD_BATCHED = 6
 
 EXPORTED = (
     "nbody_forces", "nbody_forces_subset", "nbody_forces_batched", "nbody_forces_backward",
@@ -31,7 +32,8 @@ EXPORTED = (
     "nbody_get_config", "nbody_autotune", "nbody_tune_save", "nbody_tune_load",
     "nbody_timing_enable", "nbody_timing_read", "nbody_flops_per_pair", "nbody_version",
     "nbody_forces_jerk", "hermite_step", "hermite_block_init", "hermite_block_steps",
-    "nbody_autotune_jerk",
+    "nbody_autotune_jerk", "nbody_forces_excl", "nbody_forces_batched_excl",
+    "nbody_forces_backward_excl", "nbody_forces_backward_batched",
 )
 
 
@@ -45,6 +47,10 @@ class NBodyConfig(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("i_per_lane", ctypes.c_int32),
                 ("j_tile", ctypes.c_int32), ("j_split", ctypes.c_int32),
                 ("j_stage", ctypes.c_int32)]
+
+
+class NBodyExclusions(ctypes.Structure):
+    _fields_ = [("offsets", ctypes.c_void_p), ("index", ctypes.c_void_p), ("count", ctypes.c_int64)]
 
 
 class NBodyError(RuntimeError):
@@ -67,6 +73,7 @@ def lib():
         P, I64, I32, D, SZ = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
                               ctypes.c_size_t)
         LAW = ctypes.POINTER(NBodyLaw)
+        EXC = ctypes.POINTER(NBodyExclusions)
         CFG = ctypes.POINTER(NBodyConfig)
         sig = {
             "nbody_forces": ([P, P, I64, LAW, P, P, P, SZ, P], ctypes.c_int),
@@ -94,6 +101,12 @@ def lib():
                                     ctypes.c_int),
             "nbody_autotune_jerk": ([P, P, P, I64, LAW, P, P, P, P, SZ, P, CFG,
                                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+            "nbody_forces_excl": ([P, P, I64, EXC, LAW, P, P, P, SZ, P], ctypes.c_int),
+            "nbody_forces_batched_excl": ([P, I64, P, P, EXC, LAW, P, P, P, SZ, P], ctypes.c_int),
+            "nbody_forces_backward_excl": ([P, P, I64, EXC, LAW, P, P, P, P, I32, P, P, SZ, P],
+                                           ctypes.c_int),
+            "nbody_forces_backward_batched": ([P, I64, P, P, EXC, LAW, P, P, P, P, I32, P, P, SZ, P],
+                                              ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)

@@ -161,6 +161,10 @@ __device__ __forceinline__ void ljc_adj_pair(const LjcAdjRec<T> &i, const LjcAdj
     T du = dx * ux;
     du = fma_(dy, uy, du);
     du = fma_(dz, uz, du);
+    // a masked pair must contribute nothing: its qq and e are zeroed above, and
+    // d.u is zeroed here because the charge and epsilon terms below do not
+    // carry qq or e (for the self pair d = 0 anyway; an excluded pair has d != 0)
+    if (MASK) du = self ? T(0) : du;
     const T tt = wpr * du;
     o[0] = fma_(-W, ux, o[0]);
     o[1] = fma_(-W, uy, o[1]);
@@ -232,11 +236,13 @@ __device__ __forceinline__ void adj_finish(const AdjLaunch &a, int law, int64_t 
     }
 }
 
-template <int LAW, int PREC, int I, int JS>
-__global__ __launch_bounds__(256) void k_adjoint(
-    const typename std::conditional<LAW == GRAVITY, GravAdjRec<typename RealOf<PREC>::type>,
-                                    LjcAdjRec<typename RealOf<PREC>::type>>::type *__restrict__ rec,
-    AdjLaunch a)
+template <int LAW, int PREC>
+using AdjRecOf = typename std::conditional<LAW == GRAVITY, GravAdjRec<typename RealOf<PREC>::type>,
+                                           LjcAdjRec<typename RealOf<PREC>::type>>::type;
+
+// One wave's rows against its j split (EX: with exclusion lists, LDS staging only).
+template <int LAW, int PREC, int I, int JS, bool EX>
+__device__ __forceinline__ void adjoint_body(const AdjRecOf<LAW, PREC> *__restrict__ rec, const AdjLaunch &a)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename std::conditional<LAW == GRAVITY, GravAdjRec<T>, LjcAdjRec<T>>::type;
@@ -261,10 +267,19 @@ __global__ __launch_bounds__(256) void k_adjoint(
     RunSum<PREC> acc[I][NC];
     T p[I][Op::NP];
     __shared__ R lds_j[JS ? 4 : 1][2][kWave];
+    R(*wl)[kWave] = lds_j[JS ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
     PairK<T> kc{};
     kc.eps2 = (T)a.eps2;
-    j_range<JS, Op, PREC, I>(rec, jb, je, a.j_tile, is, pid, kc, acc, p,
-                             lds_j[JS ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0]);
+    if constexpr (EX) {
+        static_assert(JS == 1, "exclusion lists use the LDS staging");
+        ExclMask<I> mask;
+#pragma unroll
+        for (int k = 0; k < I; ++k) mask.pid[k] = pid[k];
+        mask.init(a.excl, pid, 0);
+        j_range_masked<JS, Op, PREC, I>(rec, jb, je, a.j_tile, is, mask, kc, acc, p, wl);
+    } else {
+        j_range<JS, Op, PREC, I>(rec, jb, je, a.j_tile, is, pid, kc, acc, p, wl);
+    }
 #pragma unroll
     for (int k = 0; k < I; ++k) {
         const int64_t r = rbase + lane + (int64_t)kWave * k;
@@ -282,11 +297,28 @@ __global__ __launch_bounds__(256) void k_adjoint(
     }
 }
 
+template <int LAW, int PREC, int I, int JS>
+__global__ __launch_bounds__(256) void k_adjoint(const AdjRecOf<LAW, PREC> *__restrict__ rec, AdjLaunch a)
+{
+    adjoint_body<LAW, PREC, I, JS, false>(rec, a);
+}
+
+template <int PREC, int I>
+__global__ __launch_bounds__(256) void k_adjoint_excl(const AdjRecOf<LJC, PREC> *__restrict__ rec, AdjLaunch a)
+{
+    adjoint_body<LJC, PREC, I, 1, true>(rec, a);
+}
+
 template <int LAW, int PREC, int I>
 static void launch_adj_one(const AdjLaunch &a, dim3 grid, hipStream_t s)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename std::conditional<LAW == GRAVITY, GravAdjRec<T>, LjcAdjRec<T>>::type;
+    if (a.excl.off) {
+        if constexpr (LAW == LJC && I <= 2)
+            hipLaunchKernelGGL((k_adjoint_excl<PREC, I>), grid, dim3(a.block), 0, s, (const R *)a.rec, a);
+        return;
+    }
     if (a.j_stage == 1)
         hipLaunchKernelGGL((k_adjoint<LAW, PREC, I, 1>), grid, dim3(a.block), 0, s, (const R *)a.rec, a);
     else
@@ -318,6 +350,7 @@ static bool adj_prec(const AdjLaunch &a, dim3 grid, hipStream_t s)
 hipError_t launch_adjoint(const AdjLaunch &a, hipStream_t s)
 {
     if (a.n <= 0) return hipSuccess;
+    if (a.excl.off && (a.law != LJC || a.ipl > 2)) return hipErrorInvalidValue;
     const int64_t waves = (a.n + (int64_t)kWave * a.ipl - 1) / ((int64_t)kWave * a.ipl);
     const int64_t wpb = a.block / kWave;
     const dim3 grid((unsigned)((waves + wpb - 1) / wpb), (unsigned)a.j_split);
@@ -346,6 +379,182 @@ hipError_t launch_adjoint_reduce(const AdjLaunch &a, hipStream_t s)
     if (a.n <= 0 || a.j_split <= 1) return hipSuccess;
     hipLaunchKernelGGL(k_adj_reduce, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
+}
+
+// ----------------------------------------------------------- batched adjoint ----
+// Many independent systems in one persistent launch, as the batched forward:
+// (system, row-block) units in decreasing order of cost, pulled with an
+// integer ticket; each unit runs the adjoint j loop over its own system's
+// records (padded per system) and writes its rows' adjoints.
+template <typename R, int P>
+__global__ __launch_bounds__(256) void k_pack_adj_batched(AdjBatchLaunch a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.npad_total) return;
+    int64_t lo = 0, hi = a.n_systems;          // poff[lo] <= i < poff[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.poff[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    const int64_t l = i - a.poff[lo];
+    R *rec = (R *)a.rec;
+    if (l < a.off[lo + 1] - a.off[lo]) {
+        const int64_t src = a.off[lo] + l;
+        adj_put(rec, i, a.pos + 3 * src, a.params + (int64_t)P * src, a.g + 3 * src, a.qscale);
+    } else {
+        adj_pad(rec, i);
+    }
+}
+
+hipError_t launch_pack_adjoint_batched(const AdjBatchLaunch &p, hipStream_t s)
+{
+    if (p.npad_total <= 0 || p.n_systems <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((p.npad_total + 255) / 256)), block(256);
+    const bool f32 = p.prec != P_FP64;
+    if (p.law == GRAVITY) {
+        if (f32) hipLaunchKernelGGL((k_pack_adj_batched<GravAdjRec<float>, 1>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((k_pack_adj_batched<GravAdjRec<double>, 1>), grid, block, 0, s, p);
+    } else {
+        if (f32) hipLaunchKernelGGL((k_pack_adj_batched<LjcAdjRec<float>, 3>), grid, block, 0, s, p);
+        else hipLaunchKernelGGL((k_pack_adj_batched<LjcAdjRec<double>, 3>), grid, block, 0, s, p);
+    }
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void adj_finish_b(const AdjBatchLaunch &a, int law, int64_t k, const double *v)
+{
+    AdjLaunch t{};
+    t.G = a.G;
+    t.qscale = a.qscale;
+    t.grad_pos = a.grad_pos;
+    t.grad_params = a.grad_params;
+    t.params = a.params;
+    adj_finish(t, law, k, v);
+}
+
+template <int LAW, int PREC, int I, int JS, bool EX>
+__global__ __launch_bounds__(256) void k_adjoint_batched(const AdjRecOf<LAW, PREC> *__restrict__ rec,
+                                                         AdjBatchLaunch a)
+{
+    using T = typename RealOf<PREC>::type;
+    using R = AdjRecOf<LAW, PREC>;
+    using Op = AdjOp<LAW>;
+    constexpr int NC = Op::NC;
+    const int lane = lane_id();
+    __shared__ R lds_j[JS ? 4 : 1][2][kWave];
+    R(*wl)[kWave] = lds_j[JS ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
+    PairK<T> kc{};
+    kc.eps2 = (T)a.eps2;
+    for (;;) {
+        int u = 0;
+        if (lane == 0) u = atomicAdd(a.ticket, 1);
+        u = __builtin_amdgcn_readfirstlane(u);
+        if ((int64_t)u >= a.n_units) break;      // every wave leaves once the list is drained
+        const int s = a.units[2 * (int64_t)u];
+        const int64_t rb = a.units[2 * (int64_t)u + 1];
+        const int64_t o = a.off[s], ns = a.off[s + 1] - o;
+        const int64_t po = a.poff[s], pe = a.poff[s + 1];
+        const int64_t lbase = rb * (int64_t)(kWave * I);
+        R is[I];
+        int64_t pid[I], gid[I];
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            int64_t l = lbase + lane + (int64_t)kWave * k;
+            l = l < ns ? l : ns - 1;
+            pid[k] = po + l;
+            gid[k] = o + l;
+            is[k] = rec[pid[k]];
+        }
+        RunSum<PREC> acc[I][NC];
+        T p[I][Op::NP];
+        if constexpr (EX) {
+            static_assert(JS == 1, "exclusion lists use the LDS staging");
+            ExclMask<I> mask;
+#pragma unroll
+            for (int k = 0; k < I; ++k) mask.pid[k] = pid[k];
+            mask.init(a.excl, gid, po - o);
+            j_range_masked<JS, Op, PREC, I>(rec, po, pe, a.j_tile, is, mask, kc, acc, p, wl);
+        } else {
+            j_range<JS, Op, PREC, I>(rec, po, pe, a.j_tile, is, pid, kc, acc, p, wl);
+        }
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            const int64_t l = lbase + lane + (int64_t)kWave * k;
+            if (l >= ns) continue;
+            double v[8];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c] = acc[k][c].value();
+            adj_finish_b(a, LAW, o + l, v);
+        }
+    }
+}
+
+template <int LAW, int PREC, int I>
+static bool adjb_one(const AdjBatchLaunch &a, hipStream_t s, const void **fn)
+{
+    using R = AdjRecOf<LAW, PREC>;
+    const dim3 grid((unsigned)a.grid), block((unsigned)a.block);
+    if (a.excl.off) {
+        if constexpr (LAW == LJC) {
+            if (fn) *fn = (const void *)&k_adjoint_batched<LAW, PREC, I, 1, true>;
+            else hipLaunchKernelGGL((k_adjoint_batched<LAW, PREC, I, 1, true>), grid, block, 0, s, (const R *)a.rec, a);
+            return true;
+        }
+        return false;
+    }
+    if (a.j_stage == 1) {
+        if (fn) *fn = (const void *)&k_adjoint_batched<LAW, PREC, I, 1, false>;
+        else hipLaunchKernelGGL((k_adjoint_batched<LAW, PREC, I, 1, false>), grid, block, 0, s, (const R *)a.rec, a);
+    } else {
+        if (fn) *fn = (const void *)&k_adjoint_batched<LAW, PREC, I, 0, false>;
+        else hipLaunchKernelGGL((k_adjoint_batched<LAW, PREC, I, 0, false>), grid, block, 0, s, (const R *)a.rec, a);
+    }
+    return true;
+}
+
+template <int LAW, int PREC>
+static bool adjb_ipl(const AdjBatchLaunch &a, hipStream_t s, const void **fn)
+{
+    switch (a.ipl) {
+    case 1: return adjb_one<LAW, PREC, 1>(a, s, fn);
+    case 2: return adjb_one<LAW, PREC, 2>(a, s, fn);
+    default: return false;
+    }
+}
+
+template <int LAW>
+static bool adjb_prec(const AdjBatchLaunch &a, hipStream_t s, const void **fn)
+{
+    switch (a.prec) {
+    case P_FP64: return adjb_ipl<LAW, P_FP64>(a, s, fn);
+    case P_KAHAN: return adjb_ipl<LAW, P_KAHAN>(a, s, fn);
+    case P_FP64ACC: return adjb_ipl<LAW, P_FP64ACC>(a, s, fn);
+    default: return false;
+    }
+}
+
+static bool adjb_dispatch(const AdjBatchLaunch &a, hipStream_t s, const void **fn)
+{
+    return a.law == GRAVITY ? adjb_prec<GRAVITY>(a, s, fn) : (a.law == LJC ? adjb_prec<LJC>(a, s, fn) : false);
+}
+
+hipError_t launch_adjoint_batched(const AdjBatchLaunch &a, hipStream_t s)
+{
+    if (a.n_units <= 0) return hipSuccess;
+    hipError_t e = launch_fill_zero(a.ticket, 256, s);
+    if (e != hipSuccess) return e;
+    if (!adjb_dispatch(a, s, nullptr)) return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+int adjoint_batched_blocks_per_cu(const AdjBatchLaunch &a)
+{
+    const void *fn = nullptr;
+    if (!adjb_dispatch(a, nullptr, &fn) || !fn) return 0;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, a.block, 0) != hipSuccess) return 0;
+    return nb;
 }
 
 // ------------------------------------------------------ per-type reduction ----

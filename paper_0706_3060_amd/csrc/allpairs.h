@@ -9,10 +9,13 @@
 //   JS = 1  a wave-private, double-buffered LDS slot of 64 records, read back
 //           as broadcasts into VGPRs (all-VGPR arithmetic, which gfx950 issues
 //           at a higher rate than instructions with an SGPR operand).
-// The self pair (j == i) is neutralised only in tiles or chunks that hold
-// one of the wave's own indices (a wave-uniform test).
+// The self pair (j == i), and with exclusion lists the listed pairs, are
+// neutralised only in tiles or chunks that may hold them (a wave-uniform test).
 #pragma once
+#include <type_traits>
+
 #include "device.h"
+#include "kernels.h"
 
 namespace nbk {
 
@@ -156,34 +159,112 @@ __device__ __forceinline__ void tile_loop(const R *__restrict__ rec, int64_t t0,
     }
 }
 
+// ------------------------------------------------------------ pair masks
+// Which pairs of a 64-record chunk [c, c + 64) are left out of row k's sums.
+// SelfMask: only j == i.  ExclMask: j == i and the particles on the row's
+// exclusion list (Section 5: the LJC kernels read an exclusion list per
+// particle).  `near` is the lane's test of whether the chunk may hold an
+// excluded pair (the wave runs the masked loop when any lane says so); `load`
+// prepares the chunk's masks; `excluded` is the per-pair test.
+template <int I> struct SelfMask {
+    int64_t pid[I];
+    __device__ __forceinline__ bool near(int64_t c) const
+    {
+        bool b = false;
+#pragma unroll
+        for (int k = 0; k < I; ++k) b |= (pid[k] >= c) & (pid[k] < c + kWave);
+        return b;
+    }
+    __device__ __forceinline__ void load(int64_t) {}
+    __device__ __forceinline__ bool excluded(int k, int64_t c, int jj) const { return pid[k] == c + jj; }
+};
+
+// Row k is particle g[k] of the caller's arrays and record pid[k]; the
+// record of particle x is x + shift.  List entries are only compared, never
+// used as addresses, and the list ranges are clamped to [0, count), so any
+// content of the lists is safe to read.
+template <int I> struct ExclMask {
+    const int64_t *idx;
+    int64_t shift;
+    int64_t pid[I], lo[I], hi[I], b[I], e[I];
+    uint64_t m[I];
+    __device__ __forceinline__ void init(const ExclArgs &ex, const int64_t (&g)[I], int64_t sh)
+    {
+        idx = ex.idx;
+        shift = sh;
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            int64_t e0 = ex.off[g[k] + 1];
+            e0 = e0 < ex.count ? (e0 > 0 ? e0 : 0) : ex.count;
+            int64_t b0 = ex.off[g[k]];
+            b0 = b0 < e0 ? (b0 > 0 ? b0 : 0) : e0;
+            b[k] = b0;
+            e[k] = e0;
+            lo[k] = hi[k] = pid[k];
+            for (int64_t t = b0; t < e0; ++t) {
+                const int64_t r = idx[t] + shift;
+                lo[k] = r < lo[k] ? r : lo[k];
+                hi[k] = r > hi[k] ? r : hi[k];
+            }
+            m[k] = 0;
+        }
+    }
+    __device__ __forceinline__ bool near(int64_t c) const
+    {
+        bool x = false;
+#pragma unroll
+        for (int k = 0; k < I; ++k) x |= (lo[k] < c + kWave) & (hi[k] >= c);
+        return x;
+    }
+    __device__ __forceinline__ void load(int64_t c)
+    {
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            uint64_t bits = 0;
+            if ((lo[k] < c + kWave) & (hi[k] >= c)) {
+                const int64_t d0 = pid[k] - c;
+                if (d0 >= 0 && d0 < kWave) bits |= uint64_t(1) << d0;
+                for (int64_t t = b[k]; t < e[k]; ++t) {
+                    const int64_t d = idx[t] + shift - c;
+                    if (d >= 0 && d < kWave) bits |= uint64_t(1) << d;
+                }
+            }
+            m[k] = bits;
+        }
+    }
+    __device__ __forceinline__ bool excluded(int k, int64_t, int jj) const { return (m[k] >> jj) & 1; }
+};
+
 // The j loop over one 64-record chunk held in the wave's LDS slot (j_stage 1).
 // Every lane reads the same record (an LDS broadcast) into VGPRs, so the pair
 // arithmetic has only VGPR operands.
-template <bool MASK, typename Op, int I, typename R, typename IS, typename T>
-__device__ __forceinline__ void chunk_loop(const R *wl, int64_t c, const IS (&is)[I],
-                                           const int64_t (&pid)[I], const PairK<T> &kc,
-                                           T (&p)[I][Op::NP])
+template <bool MASK, typename Op, int I, typename R, typename IS, typename T, typename M>
+__device__ __forceinline__ void chunk_loop(const R *wl, int64_t c, const IS (&is)[I], const M &mask,
+                                           const PairK<T> &kc, T (&p)[I][Op::NP])
 {
 #pragma unroll 16
     for (int jj = 0; jj < kWave; ++jj) {
         const R r = wl[jj];
 #pragma unroll
         for (int k = 0; k < I; ++k)
-            Op::template run<MASK>(is[k], r, kc, MASK && (pid[k] == c + jj), p[k]);
+            Op::template run<MASK>(is[k], r, kc, MASK && mask.excluded(k, c, jj), p[k]);
     }
 }
 
 // Run the j range [jb, je) for one wave's rows.  `wl` is the wave's pair of
-// 64-record LDS slots (used when JS == 1).
-template <int JS, typename Op, int PREC, int I, typename R, typename IS, typename T>
-__device__ __forceinline__ void j_range(const R *__restrict__ rec, int64_t jb, int64_t je,
-                                        int j_tile, const IS (&is)[I], const int64_t (&pid)[I],
-                                        const PairK<T> &kc, RunSum<PREC> (&acc)[I][Op::NC],
-                                        T (&p)[I][Op::NP], R (*wl)[kWave])
+// 64-record LDS slots (used when JS == 1).  `mask` decides which pairs are
+// left out (SelfMask, or ExclMask with JS == 1 only).
+template <int JS, typename Op, int PREC, int I, typename R, typename IS, typename T, typename M>
+__device__ __forceinline__ void j_range_masked(const R *__restrict__ rec, int64_t jb, int64_t je,
+                                               int j_tile, const IS (&is)[I], M &mask,
+                                               const PairK<T> &kc, RunSum<PREC> (&acc)[I][Op::NC],
+                                               T (&p)[I][Op::NP], R (*wl)[kWave])
 {
     constexpr int NC = Op::NC;
     const int lane = lane_id();
     if constexpr (JS == 0) {
+        static_assert(std::is_same<M, SelfMask<I>>::value, "scalar staging masks the self pair only");
+        const int64_t(&pid)[I] = mask.pid;
         for (int64_t t0 = jb; t0 < je; t0 += j_tile) {
             const int64_t t1 = (t0 + j_tile < je) ? t0 + j_tile : je;
             bool near = false;
@@ -237,13 +318,12 @@ __device__ __forceinline__ void j_range(const R *__restrict__ rec, int64_t jb, i
             int64_t tile_end = (jb + j_tile < je) ? jb + j_tile : je;
             int buf = 0;
             for (int64_t c = jb; c < je; c += kWave) {
-                bool near = false;
-#pragma unroll
-                for (int k = 0; k < I; ++k) near |= (pid[k] >= c) & (pid[k] < c + kWave);
-                if (wave_any(near))
-                    chunk_loop<true, Op, I>(wl[buf], c, is, pid, kv, p);
-                else
-                    chunk_loop<false, Op, I>(wl[buf], c, is, pid, kv, p);
+                if (wave_any(mask.near(c))) {
+                    mask.load(c);
+                    chunk_loop<true, Op, I>(wl[buf], c, is, mask, kv, p);
+                } else {
+                    chunk_loop<false, Op, I>(wl[buf], c, is, mask, kv, p);
+                }
                 if (c + kWave >= tile_end) {
 #pragma unroll
                     for (int k = 0; k < I; ++k)
@@ -262,6 +342,19 @@ __device__ __forceinline__ void j_range(const R *__restrict__ rec, int64_t jb, i
         }
     }
 
+}
+
+// j_range with the self pair as the only exclusion.
+template <int JS, typename Op, int PREC, int I, typename R, typename IS, typename T>
+__device__ __forceinline__ void j_range(const R *__restrict__ rec, int64_t jb, int64_t je,
+                                        int j_tile, const IS (&is)[I], const int64_t (&pid)[I],
+                                        const PairK<T> &kc, RunSum<PREC> (&acc)[I][Op::NC],
+                                        T (&p)[I][Op::NP], R (*wl)[kWave])
+{
+    SelfMask<I> mask;
+#pragma unroll
+    for (int k = 0; k < I; ++k) mask.pid[k] = pid[k];
+    j_range_masked<JS, Op, PREC, I>(rec, jb, je, j_tile, is, mask, kc, acc, p, wl);
 }
 
 }  // namespace nbk

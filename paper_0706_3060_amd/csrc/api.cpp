@@ -61,13 +61,19 @@ size_t adj_rec_bytes(int law, int prec)
     return law == NBODY_LAW_GRAVITY ? 8 * t : 16 * t;
 }
 
-int max_split(int64_t npad)
+// Largest j split for `rows` output rows against `nj` j records: the split
+// partials of every row must fit the partial buffer, and every split keeps at
+// least one 64-record chunk.
+int max_split_rows(int64_t rows, int64_t nj)
 {
-    if (npad <= 0) return 1;
-    const int64_t by_ws = std::max<int64_t>(1, kMaxPartialRows / npad);
-    const int64_t by_len = std::max<int64_t>(1, npad / 64);
+    const int64_t rpad = round_up(std::max<int64_t>(rows, 1), 64);
+    const int64_t jpad = round_up(std::max<int64_t>(nj, 1), 64);
+    const int64_t by_ws = std::max<int64_t>(1, kMaxPartialRows / rpad);
+    const int64_t by_len = std::max<int64_t>(1, jpad / 64);
     return (int)std::min<int64_t>(kMaxSplit, std::min(by_ws, by_len));
 }
+
+int max_split(int64_t npad) { return npad <= 0 ? 1 : max_split_rows(npad, npad); }
 
 int validate_law(const nbody_law *law, bool backward)
 {
@@ -105,8 +111,8 @@ struct Cfg {
 };
 
 std::mutex g_mu;
-constexpr int kNumApi = 6;
-bool g_override_set[kNumApi] = {false, false, false, false, false, false};
+constexpr int kNumApi = 7;
+bool g_override_set[kNumApi] = {false, false, false, false, false, false, false};
 Cfg g_override[kNumApi];
 
 using TuneKey = std::tuple<int, int, int, int, int, int>;   // api, law, prec, pot, nbucket, sbucket
@@ -134,7 +140,8 @@ Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
     if (api == NBODY_API_JERK || api == NBODY_API_HERMITE) c.ipl = std::min(c.ipl, 2);
     if (c.j_stage == 1) c.ipl = std::min(c.ipl, 4);    // LDS staging: up to 4 rows per lane
     c.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
-    if (api == NBODY_API_BATCHED) c.j_split = 1;
+    if (api == NBODY_API_BATCHED || api == NBODY_API_BACKWARD_BATCHED) c.j_split = 1;
+    if (api == NBODY_API_BACKWARD_BATCHED) c.ipl = std::min(c.ipl, 2);
     return c;
 }
 
@@ -161,16 +168,18 @@ int64_t resident_waves(int law, int prec, int ipl, bool pot, int js, int block)
     return r;
 }
 
-// Modelled time of one evaluation with a j split of s (seconds, up to a common
-// scale): waves run in rounds of `resident` concurrent waves, each doing 1/s of
-// the j range, plus the fixed-order reduction of the split partials.
-double split_cost(int64_t n, int64_t waves, int64_t resident, int s, double pairs_per_s)
+// Modelled time of one evaluation of `rows` rows against `nj` j records with
+// a j split of s (seconds, up to a common scale): waves run in rounds of
+// `resident` concurrent waves, each doing 1/s of the j range, plus the
+// fixed-order reduction of the split partials.
+double split_cost(int64_t rows, int64_t nj, int64_t waves, int64_t resident, int s,
+                  double pairs_per_s)
 {
     const double w = (double)waves * s;
     const double R = (double)std::max<int64_t>(resident, 1);
     const double fill = w >= R ? std::ceil(w / R) * R / w : R / w;
-    const double t_compute = (double)n * (double)n / pairs_per_s * fill;
-    const double t_reduce = s > 1 ? 5e-6 + (double)n * s * 32.0 / 4e11 : 0.0;
+    const double t_compute = (double)rows * (double)nj / pairs_per_s * fill;
+    const double t_reduce = s > 1 ? 5e-6 + (double)rows * s * 32.0 / 4e11 : 0.0;
     return t_compute + t_reduce;
 }
 
@@ -201,19 +210,19 @@ double nominal_rate(int law, int prec)
     return f32 ? 1.8e12 : 0.6e12;
 }
 
-// splits 1..smax ordered by modelled cost (n output rows against npad records
-// for the jerk kernel, whose flop count is about twice the force kernel's)
-std::vector<int> ranked_splits(int law, int prec, int64_t n, int ipl, bool pot, int js, int block,
-                               int smax, bool jerk = false)
+// splits 1..smax ordered by modelled cost for `rows` output rows against `nj`
+// records (jerk: the acceleration-and-jerk kernel, about twice the flops)
+std::vector<int> ranked_splits(int law, int prec, int64_t rows, int64_t nj, int ipl, bool pot, int js,
+                               int block, int smax, bool jerk = false)
 {
-    const int64_t waves = (n + 64 * ipl - 1) / (64 * ipl);
+    const int64_t waves = (rows + 64 * ipl - 1) / (64 * ipl);
     const int64_t R = jerk ? resident_waves_jerk(prec, ipl, pot, js, block)
                            : resident_waves(law, prec, ipl, pot, js, block);
     std::vector<std::pair<double, int>> c;
     for (int sp = 1; sp <= smax; ++sp) {
         double cost;
         if (R > 0) {
-            cost = split_cost(n, waves, R, sp, nominal_rate(law, prec) * (jerk ? 0.5 : 1.0));
+            cost = split_cost(rows, nj, waves, R, sp, nominal_rate(law, prec) * (jerk ? 0.5 : 1.0));
         } else {   // occupancy unknown: aim at kTargetWaves waves
             cost = std::abs(std::log((double)(waves * sp) / kTargetWaves)) + 0.01 * sp;
         }
@@ -225,11 +234,13 @@ std::vector<int> ranked_splits(int law, int prec, int64_t n, int ipl, bool pot, 
     return out;
 }
 
-Cfg heuristic(int api, int law, int prec, int64_t n, int64_t S, bool pot)
+// n output rows against nj j records (nj = n for a whole system)
+Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool pot)
 {
     Cfg c;
-    const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
-    if (api == NBODY_API_BATCHED) {
+    const int64_t npad = round_up(std::max<int64_t>(std::max(n, nj), 1), 64);
+    const int smax = max_split_rows(n, nj);
+    if (api == NBODY_API_BATCHED || api == NBODY_API_BACKWARD_BATCHED) {
         c.ipl = 1;
         c.block = 256;
         c.j_tile = 256;
@@ -249,7 +260,7 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t S, bool pot)
     }
     if (api == NBODY_API_JERK || api == NBODY_API_HERMITE) {
         c.ipl = 1;
-        c.j_split = ranked_splits(law, prec, n, c.ipl, pot, c.j_stage, c.block, max_split(npad), true)[0];
+        c.j_split = ranked_splits(law, prec, n, nj, c.ipl, pot, c.j_stage, c.block, smax, true)[0];
         return sanitize(c, api, law, prec, npad);
     }
     if (api == NBODY_API_BACKWARD) {
@@ -261,24 +272,32 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t S, bool pot)
         c.j_split = split;
         return sanitize(c, api, law, prec, npad);
     }
-    c.j_split = ranked_splits(law, prec, n, c.ipl, pot, c.j_stage, c.block, max_split(npad))[0];
+    c.j_split = ranked_splits(law, prec, n, nj, c.ipl, pot, c.j_stage, c.block, smax)[0];
     return sanitize(c, api, law, prec, npad);
 }
 
-Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot)
+bool is_batched_api(int api) { return api == NBODY_API_BATCHED || api == NBODY_API_BACKWARD_BATCHED; }
+
+// Second component of a tuning key: the system count for the batched entry
+// points, the j-record count otherwise (so that a row subset of a large system
+// is not served the configuration tuned for a whole system of that row count).
+int tune_sbucket(int api, int64_t S, int64_t nj) { return size_bucket(is_batched_api(api) ? S : nj); }
+
+// The configuration for n output rows in S systems; nj j records (0: nj = n).
+Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot, int64_t nj = 0)
 {
-    const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    if (nj <= 0) nj = n;
+    const int64_t npad = round_up(std::max<int64_t>(std::max(n, nj), 1), 64);
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_override_set[api]) return sanitize(g_override[api], api, law->kind, law->precision, npad);
-    auto it = g_tuned.find(TuneKey(api, law->kind, law->precision, pot ? 1 : 0, size_bucket(n),
-                                   size_bucket(S)));
+    const int sb = tune_sbucket(api, S, nj);
+    auto it = g_tuned.find(TuneKey(api, law->kind, law->precision, pot ? 1 : 0, size_bucket(n), sb));
     if (it == g_tuned.end() && (api == NBODY_API_LEAPFROG || api == NBODY_API_HERMITE))
         // a leapfrog step runs the forces kernel, a Hermite step the jerk kernel
         it = g_tuned.find(TuneKey(api == NBODY_API_LEAPFROG ? NBODY_API_FORCES : NBODY_API_JERK,
-                                  law->kind, law->precision, pot ? 1 : 0, size_bucket(n),
-                                  size_bucket(S)));
+                                  law->kind, law->precision, pot ? 1 : 0, size_bucket(n), sb));
     if (it != g_tuned.end()) return sanitize(it->second.first, api, law->kind, law->precision, npad);
-    return heuristic(api, law->kind, law->precision, n, S, pot);
+    return heuristic(api, law->kind, law->precision, n, nj, S, pot);
 }
 
 // ------------------------------------------------------------ measurement
@@ -413,6 +432,31 @@ BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
     return w;
 }
 
+// Batched adjoint: adjoint records padded per system plus the unit tables.
+struct AdjBatWs {
+    size_t rec_off, unit_off, off_off, poff_off, ticket_off, total;
+};
+
+AdjBatWs adjb_layout(const nbody_law *law, int64_t n_total, int64_t S)
+{
+    AdjBatWs w{};
+    const int64_t npad_max = n_total + 64 * std::max<int64_t>(S, 1);
+    const int64_t units_max = n_total / 64 + std::max<int64_t>(S, 1) + 1;
+    size_t off = 0;
+    w.rec_off = off;
+    off = align256(off + (size_t)npad_max * adj_rec_bytes(law->kind, law->precision));
+    w.unit_off = off;
+    off = align256(off + (size_t)units_max * 2 * sizeof(int32_t));
+    w.off_off = off;
+    off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
+    w.poff_off = off;
+    off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
+    w.ticket_off = off;
+    off = align256(off + 256);
+    w.total = off;
+    return w;
+}
+
 // Charge scaling packed into the records so that qs_i qs_j is the Coulomb prefactor.
 double qscale_of(const nbody_law *law)
 {
@@ -444,7 +488,8 @@ Epilogue make_epi(const nbody_law *law, double *out_force, double *out_pot)
 // pack + all-pairs (+ split reduction) for one system already validated
 int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const double *params,
                 int64_t n, const int64_t *rows, int64_t nrows, const Epilogue &epi, bool pot,
-                void *ws, const FwdWs &lay, hipStream_t s, PackLaunch *pk_in)
+                void *ws, const FwdWs &lay, hipStream_t s, PackLaunch *pk_in,
+                const ExclArgs &excl = ExclArgs{})
 {
     const int64_t npad = round_up(n, 64);
     char *base = (char *)ws;
@@ -479,6 +524,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
     f.rec = base + lay.rec_off;
     f.partial = (double *)(base + lay.part_off);
     f.epi = epi;
+    f.excl = excl;
     Timer t(s);
     e = launch_forces(f, s);
     t.stop();
@@ -564,7 +610,7 @@ int jerk_impl(const double *pos, const double *vel, const double *mass, int64_t 
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     const int64_t npad = round_up(std::max(n, ni), 64);
-    const Cfg c = sanitize(forced ? *forced : choose(NBODY_API_JERK, law, ni, 1, out_potential != nullptr),
+    const Cfg c = sanitize(forced ? *forced : choose(NBODY_API_JERK, law, ni, 1, out_potential != nullptr, n),
                            NBODY_API_JERK, law->kind, law->precision, npad);
     JerkPackLaunch pk{};
     pk.n = n;
@@ -653,7 +699,7 @@ int device_cus()
 
 int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int64_t S,
                 const double *pos, const double *params, double *out_force, double *out_pot,
-                void *ws, const BatWs &lay, hipStream_t s)
+                void *ws, const BatWs &lay, hipStream_t s, const ExclArgs &excl = ExclArgs{})
 {
     const BatchPlan plan = plan_batched(offsets, S, c.ipl);
     if (plan.units.empty()) return NBODY_OK;
@@ -694,7 +740,8 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     b.block = c.block;
     b.j_stage = c.j_stage;
     const int per_cu =
-        std::max(1, batched_max_blocks_per_cu(b.law, b.prec, b.ipl, b.pot, b.j_stage, b.block));
+        std::max(1, batched_max_blocks_per_cu(b.law, b.prec, b.ipl, b.pot, b.j_stage, b.block,
+                                              excl.off != nullptr));
     const int64_t n_units = (int64_t)plan.units.size() / 2;
     const int64_t waves_needed = n_units;
     const int64_t blocks_needed = (waves_needed + c.block / 64 - 1) / (c.block / 64);
@@ -712,6 +759,7 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     b.rec = base + lay.rec_off;
     b.ticket = (int *)(base + lay.ticket_off);
     b.epi = make_epi(law, out_force, out_pot);
+    b.excl = excl;
     Timer t(s);
     e = launch_batched(b, s);
     t.stop();
@@ -734,12 +782,54 @@ int validate_offsets(const int64_t *offsets, int64_t S)
     return NBODY_OK;
 }
 
+// Exclusion lists: host struct of device arrays.  The kernels clamp every
+// list range to [0, count) and only compare entries, so list content cannot
+// cause an out-of-bounds access; `offsets` must hold n + 1 entries.
+int validate_excl(const nbody_exclusions *ex, const nbody_law *law, bool backward)
+{
+    if (!ex) return NBODY_OK;
+    if (!ex->offsets) return fail(NBODY_EINVAL, "exclusions.offsets is NULL");
+    if (ex->count < 0) return fail(NBODY_EINVAL, "exclusions.count < 0");
+    if (ex->count > 0 && !ex->index) return fail(NBODY_EINVAL, "exclusions.index is NULL");
+    if (law->kind == NBODY_LAW_GRAVITY) return fail(NBODY_ENOTSUP, "exclusion lists apply to the LJC laws");
+    if (backward && law->kind != NBODY_LAW_LJC_LINEAR)
+        return fail(NBODY_ENOTSUP, "the adjoint with exclusions is provided for LJC(linear)");
+    if (law->precision == NBODY_FP32_PLAIN)
+        return fail(NBODY_ENOTSUP, "exclusion lists are provided for FP64, FP32_FP64ACC and FP32_KAHAN");
+    return NBODY_OK;
+}
+
+ExclArgs excl_args(const nbody_exclusions *ex)
+{
+    ExclArgs a{};
+    if (ex) {
+        a.off = ex->offsets;
+        a.idx = ex->index;
+        a.count = ex->count;
+    }
+    return a;
+}
+
+// the exclusion kernels use LDS staging with up to 2 rows per lane
+Cfg with_excl(Cfg c, bool excl)
+{
+    if (excl) {
+        c.j_stage = 1;
+        c.ipl = std::min(c.ipl, 2);
+    }
+    return c;
+}
+
 int forces_impl(const double *pos, const double *params, int64_t n, const int64_t *rows,
                 int64_t nrows, const nbody_law *law, double *out_force, double *out_potential,
-                void *ws, size_t ws_bytes, void *stream, const Cfg *forced)
+                void *ws, size_t ws_bytes, void *stream, const Cfg *forced,
+                const nbody_exclusions *excl = nullptr)
 {
     int rc = validate_law(law, false);
     if (rc) return rc;
+    rc = validate_excl(excl, law, false);
+    if (rc) return rc;
+    if (excl && rows) return fail(NBODY_EINVAL, "exclusion lists apply to whole-system evaluations");
     if (n < 0 || nrows < 0) return fail(NBODY_EINVAL, "n < 0");
     if (n > (int64_t(1) << 40)) return fail(NBODY_EINVAL, "n too large");
     if (nrows > 0 && n == 0) return fail(NBODY_EINVAL, "rows requested from an empty system");
@@ -750,17 +840,21 @@ int forces_impl(const double *pos, const double *params, int64_t n, const int64_
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     const bool pot = out_potential != nullptr;
-    const Cfg c = forced ? *forced : choose(NBODY_API_FORCES, law, nrows, 1, pot);
-    return run_forward(law, sanitize(c, NBODY_API_FORCES, law->kind, law->precision, round_up(std::max(n, nrows), 64)), pos,
-                       params, n, rows, nrows, make_epi(law, out_force, out_potential), pot, ws, lay,
-                       (hipStream_t)stream, nullptr);
+    const Cfg c = forced ? *forced : choose(NBODY_API_FORCES, law, nrows, 1, pot, n);
+    const Cfg cs = with_excl(sanitize(c, NBODY_API_FORCES, law->kind, law->precision,
+                                      round_up(std::max(n, nrows), 64)), excl != nullptr);
+    return run_forward(law, cs, pos, params, n, rows, nrows, make_epi(law, out_force, out_potential),
+                       pot, ws, lay, (hipStream_t)stream, nullptr, excl_args(excl));
 }
 
 int batched_impl(const int64_t *offsets, int64_t S, const double *pos, const double *params,
                  const nbody_law *law, double *out_force, double *out_potential, void *ws,
-                 size_t ws_bytes, void *stream, const Cfg *forced)
+                 size_t ws_bytes, void *stream, const Cfg *forced,
+                 const nbody_exclusions *excl = nullptr)
 {
     int rc = validate_law(law, false);
+    if (rc) return rc;
+    rc = validate_excl(excl, law, false);
     if (rc) return rc;
     rc = validate_offsets(offsets, S);
     if (rc) return rc;
@@ -771,8 +865,9 @@ int batched_impl(const int64_t *offsets, int64_t S, const double *pos, const dou
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     const Cfg c = forced ? *forced : choose(NBODY_API_BATCHED, law, n, S, out_potential != nullptr);
-    return run_batched(law, sanitize(c, NBODY_API_BATCHED, law->kind, law->precision, 64), offsets, S, pos,
-                       params, out_force, out_potential, ws, lay, (hipStream_t)stream);
+    return run_batched(law, with_excl(sanitize(c, NBODY_API_BATCHED, law->kind, law->precision, 64),
+                                      excl != nullptr), offsets, S, pos,
+                       params, out_force, out_potential, ws, lay, (hipStream_t)stream, excl_args(excl));
 }
 
 // candidate list for the measured search
@@ -804,7 +899,7 @@ std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
             if (jerk && ipl > 2) continue;
             if (law >= NBODY_LAW_LJC_CONSTANT && ipl > 2) continue;
             const int block = 256;
-            std::vector<int> splits = ranked_splits(law, prec, n, ipl, pot, js, block, max_split(npad), jerk);
+            std::vector<int> splits = ranked_splits(law, prec, n, n, ipl, pot, js, block, max_split(npad), jerk);
             std::vector<int> pick;
             for (int sp : splits) {
                 if ((int)pick.size() >= 3) break;
@@ -844,6 +939,7 @@ size_t nbody_workspace_bytes(int32_t api, int64_t n_total, int64_t n_systems, co
     case NBODY_API_LEAPFROG: return fwd_layout(NBODY_API_LEAPFROG, law, n_total).total;
     case NBODY_API_BACKWARD: return adj_layout(law, n_total).total;
     case NBODY_API_BATCHED: return bat_layout(law, n_total, n_systems).total;
+    case NBODY_API_BACKWARD_BATCHED: return adjb_layout(law, n_total, n_systems).total;
     case NBODY_API_JERK:
     case NBODY_API_HERMITE:
         if (law->kind != NBODY_LAW_GRAVITY) return 0;
@@ -876,12 +972,14 @@ int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double
                         stream, nullptr);
 }
 
-int nbody_forces_backward(const double *pos, const double *params, int64_t n, const nbody_law *law,
-                          const double *grad_force, double *grad_pos, double *grad_params,
-                          const int32_t *types, int32_t n_types, double *grad_type_params,
-                          void *ws, size_t ws_bytes, void *stream)
+int backward_impl(const double *pos, const double *params, int64_t n, const nbody_law *law,
+                  const double *grad_force, double *grad_pos, double *grad_params,
+                  const int32_t *types, int32_t n_types, double *grad_type_params, void *ws,
+                  size_t ws_bytes, void *stream, const nbody_exclusions *excl)
 {
     int rc = validate_law(law, true);
+    if (rc) return rc;
+    rc = validate_excl(excl, law, true);
     if (rc) return rc;
     if (n < 0) return fail(NBODY_EINVAL, "n < 0");
     if (law->kind == NBODY_LAW_GRAVITY && (grad_params || types))
@@ -897,7 +995,7 @@ int nbody_forces_backward(const double *pos, const double *params, int64_t n, co
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const Cfg c = choose(NBODY_API_BACKWARD, law, n, 1, false);
+    const Cfg c = with_excl(choose(NBODY_API_BACKWARD, law, n, 1, false), excl != nullptr);
     const int64_t npad = round_up(n, 64);
     char *base = (char *)ws;
 
@@ -933,12 +1031,133 @@ int nbody_forces_backward(const double *pos, const double *params, int64_t n, co
     a.grad_pos = grad_pos;
     a.grad_params = grad_params;
     a.params = params;
+    a.excl = excl_args(excl);
     Timer t(s);
     e = launch_adjoint(a, s);
     t.stop();
     if (e != hipSuccess) return hip_fail(e, "adjoint kernel");
     e = launch_adjoint_reduce(a, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint split reduction");
+    if (types) {
+        e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params, s);
+        if (e != hipSuccess) return hip_fail(e, "per-type reduction");
+    }
+    return NBODY_OK;
+}
+
+int nbody_forces_backward(const double *pos, const double *params, int64_t n, const nbody_law *law,
+                          const double *grad_force, double *grad_pos, double *grad_params,
+                          const int32_t *types, int32_t n_types, double *grad_type_params,
+                          void *ws, size_t ws_bytes, void *stream)
+{
+    return backward_impl(pos, params, n, law, grad_force, grad_pos, grad_params, types, n_types,
+                         grad_type_params, ws, ws_bytes, stream, nullptr);
+}
+
+int nbody_forces_backward_excl(const double *pos, const double *params, int64_t n,
+                               const nbody_exclusions *excl, const nbody_law *law,
+                               const double *grad_force, double *grad_pos, double *grad_params,
+                               const int32_t *types, int32_t n_types, double *grad_type_params,
+                               void *ws, size_t ws_bytes, void *stream)
+{
+    if (!excl) return fail(NBODY_EINVAL, "excl is NULL");
+    return backward_impl(pos, params, n, law, grad_force, grad_pos, grad_params, types, n_types,
+                         grad_type_params, ws, ws_bytes, stream, excl);
+}
+
+int nbody_forces_excl(const double *pos, const double *params, int64_t n,
+                      const nbody_exclusions *excl, const nbody_law *law, double *out_force,
+                      double *out_potential, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!excl) return fail(NBODY_EINVAL, "excl is NULL");
+    return forces_impl(pos, params, n, nullptr, n, law, out_force, out_potential, ws, ws_bytes,
+                       stream, nullptr, excl);
+}
+
+int nbody_forces_batched_excl(const int64_t *offsets, int64_t n_systems, const double *pos,
+                              const double *params, const nbody_exclusions *excl,
+                              const nbody_law *law, double *out_force, double *out_potential,
+                              void *ws, size_t ws_bytes, void *stream)
+{
+    if (!excl) return fail(NBODY_EINVAL, "excl is NULL");
+    return batched_impl(offsets, n_systems, pos, params, law, out_force, out_potential, ws,
+                        ws_bytes, stream, nullptr, excl);
+}
+
+int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
+                                  const double *params, const nbody_exclusions *excl,
+                                  const nbody_law *law, const double *grad_force, double *grad_pos,
+                                  double *grad_params, const int32_t *types, int32_t n_types,
+                                  double *grad_type_params, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = validate_law(law, true);
+    if (rc) return rc;
+    rc = validate_excl(excl, law, true);
+    if (rc) return rc;
+    rc = validate_offsets(offsets, n_systems);
+    if (rc) return rc;
+    if (law->kind == NBODY_LAW_GRAVITY && (grad_params || types))
+        return fail(NBODY_EINVAL, "gravity has no parameter adjoint here: grad_params/types must be NULL");
+    if (types && (n_types <= 0 || !grad_type_params))
+        return fail(NBODY_EINVAL, "types given without n_types > 0 and grad_type_params");
+    if (types && !grad_params) return fail(NBODY_EINVAL, "the per-type reduction needs grad_params");
+    const int64_t n = offsets[n_systems];
+    if (n == 0) return NBODY_OK;
+    if (!pos || !params || !grad_force) return fail(NBODY_EINVAL, "pos, params and grad_force must be non-NULL");
+    if (!grad_pos && !grad_params) return NBODY_OK;
+    const AdjBatWs lay = adjb_layout(law, n, n_systems);
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const Cfg c = with_excl(choose(NBODY_API_BACKWARD_BATCHED, law, n, n_systems, false), excl != nullptr);
+    const int ipl = std::min(c.ipl, 2);
+    const BatchPlan plan = plan_batched(offsets, n_systems, ipl);
+    if (plan.units.empty()) return NBODY_OK;
+    char *base = (char *)ws;
+    int32_t *d_units = (int32_t *)(base + lay.unit_off);
+    int64_t *d_off = (int64_t *)(base + lay.off_off);
+    int64_t *d_poff = (int64_t *)(base + lay.poff_off);
+    hipError_t e = hipMemcpyAsync(d_units, plan.units.data(), plan.units.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_off, offsets, (size_t)(n_systems + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_poff, plan.poff.data(), (size_t)(n_systems + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batched adjoint tables");
+    AdjBatchLaunch a{};
+    a.law = law->kind;
+    a.prec = law->precision;
+    a.ipl = ipl;
+    a.block = c.block;
+    a.j_stage = c.j_stage;
+    a.j_tile = c.j_tile;
+    a.n_units = (int64_t)plan.units.size() / 2;
+    a.units = d_units;
+    a.off = d_off;
+    a.poff = d_poff;
+    a.n_systems = n_systems;
+    a.npad_total = plan.npad_total;
+    a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    a.G = law->G;
+    a.qscale = qscale_of(law);
+    a.pos = pos;
+    a.params = params;
+    a.g = grad_force;
+    a.rec = base + lay.rec_off;
+    a.ticket = (int *)(base + lay.ticket_off);
+    a.grad_pos = grad_pos;
+    a.grad_params = grad_params;
+    a.excl = excl_args(excl);
+    e = launch_pack_adjoint_batched(a, s);
+    if (e != hipSuccess) return hip_fail(e, "batched adjoint pack");
+    const int per_cu = std::max(1, adjoint_batched_blocks_per_cu(a));
+    const int64_t blocks_needed = (a.n_units + c.block / 64 - 1) / (c.block / 64);
+    a.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)device_cus() * per_cu, blocks_needed));
+    Timer t(s);
+    e = launch_adjoint_batched(a, s);
+    t.stop();
+    if (e != hipSuccess) return hip_fail(e, "batched adjoint kernel");
     if (types) {
         e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params, s);
         if (e != hipSuccess) return hip_fail(e, "per-type reduction");
@@ -1110,7 +1329,7 @@ int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, dou
             return fail(NBODY_EHIP, "block scheduling produced an invalid due set (%lld)", (long long)na);
         if (active_counts) active_counts[b] = na;
         if (t_now) *t_now = t;
-        const Cfg c = sanitize(choose(NBODY_API_HERMITE, law, na, 1, false), NBODY_API_HERMITE,
+        const Cfg c = sanitize(choose(NBODY_API_HERMITE, law, na, 1, false, n), NBODY_API_HERMITE,
                                law->kind, law->precision, round_up(n, 64));
         JerkPackLaunch pk{};
         pk.n = n;
@@ -1196,7 +1415,7 @@ int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_tuned[TuneKey(NBODY_API_JERK, law->kind, law->precision, out_potential ? 1 : 0,
-                        size_bucket(n), size_bucket(1))] = {best, best_ms};
+                        size_bucket(n), tune_sbucket(NBODY_API_JERK, 1, n))] = {best, best_ms};
     }
     rc = jerk_impl(pos, vel, mass, n, nullptr, n, law, out_acc, out_jerk, out_potential, ws, ws_bytes,
                    stream, &best);
@@ -1294,7 +1513,7 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_tuned[TuneKey(api, law->kind, law->precision, out_potential ? 1 : 0, size_bucket(ntot),
-                        size_bucket(S))] = {best, best_ms};
+                        tune_sbucket(api, S, ntot))] = {best, best_ms};
     }
     // leave the winner's result in the outputs
     rc = api == NBODY_API_FORCES
@@ -1401,7 +1620,8 @@ int nbody_timing_read(double *total_ms, int64_t *launches, int32_t reset)
 
 int32_t nbody_flops_per_pair(int32_t api, int32_t law_kind, int32_t with_potential)
 {
-    if (api == NBODY_API_BACKWARD) return law_kind == NBODY_LAW_GRAVITY ? 41 : 68;
+    if (api == NBODY_API_BACKWARD || api == NBODY_API_BACKWARD_BATCHED)
+        return law_kind == NBODY_LAW_GRAVITY ? 41 : 68;
     if (api == NBODY_API_JERK || api == NBODY_API_HERMITE)
         return law_kind == NBODY_LAW_GRAVITY ? (with_potential ? 42 : 41) : 0;
     switch (law_kind) {

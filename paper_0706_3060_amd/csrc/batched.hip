@@ -14,12 +14,14 @@
 
 namespace nbk {
 
-template <int LAW, int PREC, int I, bool POT, int JS>
-__global__ __launch_bounds__(256) void k_batched(
+// EX: with per-particle exclusion lists over the caller's (global) particle
+// indices; only partners in the particle's own system can match.
+template <int LAW, int PREC, int I, bool POT, int JS, bool EX>
+__device__ __forceinline__ void batched_body(
     const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec,
     const int32_t *__restrict__ units, int64_t n_units, const int64_t *__restrict__ off,
     const int64_t *__restrict__ poff, int j_tile, PairK<typename RealOf<PREC>::type> kc,
-    int *ticket, Epilogue epi)
+    int *ticket, const Epilogue &epi, const ExclArgs &ex)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename RecOf<T, LAW>::type;
@@ -41,19 +43,29 @@ __global__ __launch_bounds__(256) void k_batched(
         const int64_t lbase = rb * (int64_t)(kWave * I);
 
         IS is[I];
-        int64_t pid[I];
+        int64_t pid[I], gid[I];
 #pragma unroll
         for (int k = 0; k < I; ++k) {
             int64_t l = lbase + lane + (int64_t)kWave * k;
             l = l < ns ? l : ns - 1;
             pid[k] = po + l;
+            gid[k] = o + l;
             load_i(rec, pid[k], is[k]);
         }
         RunSum<PREC> acc[I][NC];
         T p[I][4];
 #pragma unroll
         for (int k = 0; k < I; ++k) p[k][3] = T(0);
-        j_range<JS, ForceOp<POT, LAW>, PREC, I>(rec, po, pe, j_tile, is, pid, kc, acc, p, wl);
+        if constexpr (EX) {
+            static_assert(JS == 1, "exclusion lists use the LDS staging");
+            ExclMask<I> mask;
+#pragma unroll
+            for (int k = 0; k < I; ++k) mask.pid[k] = pid[k];
+            mask.init(ex, gid, po - o);
+            j_range_masked<JS, ForceOp<POT, LAW>, PREC, I>(rec, po, pe, j_tile, is, mask, kc, acc, p, wl);
+        } else {
+            j_range<JS, ForceOp<POT, LAW>, PREC, I>(rec, po, pe, j_tile, is, pid, kc, acc, p, wl);
+        }
 #pragma unroll
         for (int k = 0; k < I; ++k) {
             const int64_t l = lbase + lane + (int64_t)kWave * k;
@@ -65,6 +77,28 @@ __global__ __launch_bounds__(256) void k_batched(
             if (POT && epi.out_pot) epi.out_pot[r] = epi.pscale * acc[k][NC - 1].value();
         }
     }
+}
+
+template <int LAW, int PREC, int I, bool POT, int JS>
+__global__ __launch_bounds__(256) void k_batched(
+    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec,
+    const int32_t *__restrict__ units, int64_t n_units, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ poff, int j_tile, PairK<typename RealOf<PREC>::type> kc,
+    int *ticket, Epilogue epi)
+{
+    batched_body<LAW, PREC, I, POT, JS, false>(rec, units, n_units, off, poff, j_tile, kc, ticket, epi,
+                                               ExclArgs{});
+}
+
+template <int LAW, int PREC, int I, bool POT>
+__global__ __launch_bounds__(256) void k_batched_excl(
+    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec,
+    const int32_t *__restrict__ units, int64_t n_units, const int64_t *__restrict__ off,
+    const int64_t *__restrict__ poff, int j_tile, PairK<typename RealOf<PREC>::type> kc,
+    int *ticket, Epilogue epi, ExclArgs ex)
+{
+    batched_body<LAW, PREC, I, POT, 1, true>(rec, units, n_units, off, poff, j_tile, kc, ticket, epi,
+                                             ex);
 }
 
 // ---------------------------------------------------------------- packing ----
@@ -109,8 +143,13 @@ hipError_t launch_pack_batched(const BatchPackLaunch &p, hipStream_t s)
 
 // --------------------------------------------------------------- dispatch ----
 template <int LAW, int PREC, int I, bool POT>
-static const void *batched_ptr(int js)
+static const void *batched_ptr(int js, bool excl)
 {
+    if (excl) {
+        if constexpr (LAW != GRAVITY && I <= 2 && PREC != P_PLAIN)
+            return (const void *)&k_batched_excl<LAW, PREC, I, POT>;
+        return nullptr;
+    }
     if (js == 1) return (const void *)&k_batched<LAW, PREC, I, POT, 1>;
     return (const void *)&k_batched<LAW, PREC, I, POT, 0>;
 }
@@ -128,6 +167,14 @@ static void launch_b(const BatchLaunch &b, hipStream_t s)
     kc.zd = (T)b.zeta[3];
     kc.za3 = (T)(3.0 * b.zeta[0]);
     kc.zb2 = (T)(2.0 * b.zeta[1]);
+    if (b.excl.off) {
+        if constexpr (LAW != GRAVITY && I <= 2 && PREC != P_PLAIN) {
+            hipLaunchKernelGGL((k_batched_excl<LAW, PREC, I, POT>), dim3(b.grid), dim3(b.block), 0, s,
+                               (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile, kc,
+                               b.ticket, b.epi, b.excl);
+        }
+        return;
+    }
     if (b.j_stage == 1)
         hipLaunchKernelGGL((k_batched<LAW, PREC, I, POT, 1>), dim3(b.grid), dim3(b.block), 0, s,
                            (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile, kc,
@@ -191,8 +238,9 @@ struct LaunchB {
 
 struct PtrB {
     int js;
+    bool excl;
     const void *fn = nullptr;
-    template <int L, int P, int I, bool O> void run() { fn = batched_ptr<L, P, I, O>(js); }
+    template <int L, int P, int I, bool O> void run() { fn = batched_ptr<L, P, I, O>(js, excl); }
 };
 
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t s)
@@ -200,14 +248,15 @@ hipError_t launch_batched(const BatchLaunch &b, hipStream_t s)
     if (b.n_units <= 0) return hipSuccess;
     hipError_t e = launch_fill_zero(b.ticket, 256, s);
     if (e != hipSuccess) return e;
+    if (b.excl.off && (b.law == GRAVITY || b.ipl > 2 || b.prec == P_PLAIN)) return hipErrorInvalidValue;
     LaunchB l{b, s};
     if (!batched_dispatch(b.law, b.prec, b.ipl, b.pot != 0, l)) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
-int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block)
+int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block, int excl)
 {
-    PtrB g{js};
+    PtrB g{js, excl != 0};
     if (!batched_dispatch(law, prec, ipl, pot != 0, g) || !g.fn) return 0;
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, g.fn, block, 0) != hipSuccess) return 0;

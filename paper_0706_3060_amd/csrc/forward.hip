@@ -80,11 +80,14 @@ __device__ __forceinline__ void finish_row(const Epilogue &e, int64_t r, double 
 }
 
 // ------------------------------------------------------------- all pairs ----
-template <int LAW, int PREC, int I, bool POT, int JS>
-__global__ __launch_bounds__(256) void k_forces(
+// One wave's rows against the j range of its split (EX: with exclusion lists,
+// LDS staging only).
+template <int LAW, int PREC, int I, bool POT, int JS, bool EX>
+__device__ __forceinline__ void forces_body(
     const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec, int64_t npad,
     int64_t nrows, const int64_t *__restrict__ rows, int64_t split_len, int j_tile,
-    PairK<typename RealOf<PREC>::type> kc, double *__restrict__ partial, Epilogue epi)
+    PairK<typename RealOf<PREC>::type> kc, double *__restrict__ partial, const Epilogue &epi,
+    const ExclArgs &ex)
 {
     using T = typename RealOf<PREC>::type;
     using R = typename RecOf<T, LAW>::type;
@@ -117,8 +120,17 @@ __global__ __launch_bounds__(256) void k_forces(
     for (int k = 0; k < I; ++k) p[k][3] = T(0);
 
     __shared__ R lds_j[JS ? 4 : 1][2][kWave];
-    j_range<JS, ForceOp<POT, LAW>, PREC, I>(rec, jb, je, j_tile, is, pid, kc, acc, p,
-                              lds_j[JS ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0]);
+    R(*wl)[kWave] = lds_j[JS ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : 0];
+    if constexpr (EX) {
+        static_assert(JS == 1, "exclusion lists use the LDS staging");
+        ExclMask<I> mask;
+#pragma unroll
+        for (int k = 0; k < I; ++k) mask.pid[k] = pid[k];
+        mask.init(ex, pid, 0);
+        j_range_masked<JS, ForceOp<POT, LAW>, PREC, I>(rec, jb, je, j_tile, is, mask, kc, acc, p, wl);
+    } else {
+        j_range<JS, ForceOp<POT, LAW>, PREC, I>(rec, jb, je, j_tile, is, pid, kc, acc, p, wl);
+    }
 
 #pragma unroll
     for (int k = 0; k < I; ++k) {
@@ -137,6 +149,29 @@ __global__ __launch_bounds__(256) void k_forces(
         }
     }
 }
+
+template <int LAW, int PREC, int I, bool POT, int JS>
+__global__ __launch_bounds__(256) void k_forces(
+    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec, int64_t npad,
+    int64_t nrows, const int64_t *__restrict__ rows, int64_t split_len, int j_tile,
+    PairK<typename RealOf<PREC>::type> kc, double *__restrict__ partial, Epilogue epi)
+{
+    forces_body<LAW, PREC, I, POT, JS, false>(rec, npad, nrows, rows, split_len, j_tile, kc, partial,
+                                              epi, ExclArgs{});
+}
+
+// The same with per-particle exclusion lists (the particle of row r is rows[r]
+// or r, and its records are the particle indices themselves).
+template <int LAW, int PREC, int I, bool POT>
+__global__ __launch_bounds__(256) void k_forces_excl(
+    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec, int64_t npad,
+    int64_t nrows, const int64_t *__restrict__ rows, int64_t split_len, int j_tile,
+    PairK<typename RealOf<PREC>::type> kc, double *__restrict__ partial, Epilogue epi, ExclArgs ex)
+{
+    forces_body<LAW, PREC, I, POT, 1, true>(rec, npad, nrows, rows, split_len, j_tile, kc, partial,
+                                            epi, ex);
+}
+
 template <typename T> static PairK<T> pair_constants(const FwdLaunch &f)
 {
     PairK<T> k;
@@ -163,6 +198,15 @@ static bool launch_one(const FwdLaunch &f, dim3 grid, hipStream_t s)
         return false;
     } else {
         const PairK<T> kc = pair_constants<T>(f);
+        if (f.excl.off) {           // exclusion lists: LJC laws, LDS staging, up to 2 rows per lane
+            if constexpr (LAW != GRAVITY && I <= 2 && PREC != P_PLAIN) {
+                hipLaunchKernelGGL((k_forces_excl<LAW, PREC, I, POT>), grid, dim3(f.block), 0, s,
+                                   (const R *)f.rec, f.npad, f.nrows, f.rows, f.split_len, f.j_tile,
+                                   kc, f.j_split > 1 ? f.partial : nullptr, f.epi, f.excl);
+                return true;
+            }
+            return false;
+        }
         if constexpr (I <= 4) {     // LDS staging is instantiated up to 4 rows per lane
             if (f.j_stage == 1) {
                 hipLaunchKernelGGL((k_forces<LAW, PREC, I, POT, 1>), grid, dim3(f.block), 0, s,

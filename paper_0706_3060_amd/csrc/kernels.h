@@ -7,6 +7,15 @@
 
 namespace nbk {
 
+// Per-particle exclusion lists (CSR over the caller's particle indices):
+// particle x excludes idx[off[x] .. off[x+1]) (ranges clamped to [0, count)).
+// off == nullptr: no exclusions.
+struct ExclArgs {
+    const int64_t *off;
+    const int64_t *idx;
+    int64_t count;
+};
+
 // What the all-pairs kernels do with the four finished sums of a row.
 struct Epilogue {
     double fscale;              // out_force = fscale * sum_vec   (G for gravity, 1 for LJC)
@@ -35,6 +44,7 @@ struct FwdLaunch {
     const void *rec;             // packed records
     double *partial;             // [j_split][nrows][4] when j_split > 1
     Epilogue epi;
+    ExclArgs excl;               // per-particle exclusion lists, or off == nullptr
 };
 
 // Pack FP64 inputs into padded records (FP32 or FP64) for one system.
@@ -76,6 +86,7 @@ struct BatchLaunch {
     const void *rec;
     int *ticket;                 // zeroed by launch_batched before the kernel
     Epilogue epi;
+    ExclArgs excl;               // exclusion lists over the caller's rows, or off == nullptr
 };
 struct BatchPackLaunch {
     int law, prec;
@@ -87,7 +98,7 @@ struct BatchPackLaunch {
 };
 hipError_t launch_pack_batched(const BatchPackLaunch &p, hipStream_t s);
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t s);
-int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block);
+int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block, int excl);
 
 // ---- adjoint ----
 struct AdjLaunch {
@@ -105,7 +116,29 @@ struct AdjLaunch {
     double *grad_pos;            // [n][3] or null
     double *grad_params;         // [n][3] or null (LJC)
     const double *params;        // caller params (for the per-atom scale factors)
+    ExclArgs excl;               // exclusion lists (LJC), or off == nullptr
 };
+// Batched adjoint: (system, row-block) units in one persistent launch.
+struct AdjBatchLaunch {
+    int law, prec, ipl;
+    int block, grid;
+    int j_stage;
+    int j_tile;
+    int64_t n_units;
+    const int32_t *units;        // [n_units][2]
+    const int64_t *off, *poff;   // [S+1] caller rows and padded record offsets
+    int64_t n_systems, npad_total;
+    double eps2, G, qscale;
+    const double *pos, *params, *g;   // caller arrays (pack)
+    void *rec;
+    int *ticket;
+    double *grad_pos;            // [n][3] or null
+    double *grad_params;         // [n][3] or null (LJC)
+    ExclArgs excl;
+};
+hipError_t launch_pack_adjoint_batched(const AdjBatchLaunch &p, hipStream_t s);
+hipError_t launch_adjoint_batched(const AdjBatchLaunch &a, hipStream_t s);
+int adjoint_batched_blocks_per_cu(const AdjBatchLaunch &a);
 struct AdjPackLaunch {
     int law, prec;
     int64_t n, npad;

@@ -28,7 +28,31 @@ GRAVITY, LJC_LINEAR, LJC_CONSTANT, LJC_SIGMOIDAL = 0, 1, 2, 3
 FP64, FP32_KAHAN, FP32_FP64ACC, FP32_PLAIN = 0, 1, 2, 3
 API_FORCES, API_BATCHED, API_BACKWARD, API_LEAPFROG = (N.API_FORCES, N.API_BATCHED,
                                                        N.API_BACKWARD, N.API_LEAPFROG)
-API_JERK, API_HERMITE = N.API_JERK, N.API_HERMITE
+API_JERK, API_HERMITE, API_BACKWARD_BATCHED = N.API_JERK, N.API_HERMITE, N.API_BACKWARD_BATCHED
+
+
+@dataclass
+class Exclusions:
+    """Per-particle exclusion lists (bonded pairs left out of the LJC sums; Section 5):
+    particle x excludes index[offsets[x]:offsets[x+1]].  `offsets` [n+1] and `index`
+    [count] are int64 GPU tensors (index may be None when there are no entries)."""
+    offsets: torch.Tensor
+    index: torch.Tensor = None
+
+    def c(self, n):
+        off = self.offsets
+        if not (isinstance(off, torch.Tensor) and off.is_cuda and off.dtype == torch.int64
+                and off.is_contiguous() and tuple(off.shape) == (n + 1,)):
+            raise ValueError("exclusion offsets must be a contiguous int64 GPU tensor of shape (%d,)"
+                             % (n + 1))
+        idx = self.index
+        count = 0
+        if idx is not None:
+            if not (isinstance(idx, torch.Tensor) and idx.is_cuda and idx.dtype == torch.int64
+                    and idx.is_contiguous() and idx.dim() == 1):
+                raise ValueError("exclusion index must be a contiguous 1-d int64 GPU tensor")
+            count = idx.numel()
+        return N.NBodyExclusions(_ptr(off), _ptr(idx) if count else None, count)
 PRECISIONS = {"fp64": FP64, "fp32_kahan": FP32_KAHAN, "fp32_fp64acc": FP32_FP64ACC,
               "fp32_plain": FP32_PLAIN}
 
@@ -128,8 +152,9 @@ def clear_workspace_cache():
 
 
 # --------------------------------------------------------------- forward
-def forces(pos, params, law: Law, potential: bool = True, out=None):
-    """All-pairs forces (gravity: accelerations) and optionally potentials.
+def forces(pos, params, law: Law, potential: bool = True, out=None, exclusions: Exclusions = None):
+    """All-pairs forces (gravity: accelerations) and optionally potentials, with optional
+    exclusion lists (LJC laws).
 
     Returns (force [N,3] float64, potential [N] float64 or None)."""
     pos = _dev_f64(pos, None, "pos")
@@ -139,8 +164,14 @@ def forces(pos, params, law: Law, potential: bool = True, out=None):
     f = out if out is not None else torch.empty((n, 3), dtype=torch.float64, device=pos.device)
     p = torch.empty(n, dtype=torch.float64, device=pos.device) if potential else None
     ws = workspace(API_FORCES, n, 1, law, pos.device)
-    N.check(N.lib().nbody_forces(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(f), _ptr(p),
-                                 _ptr(ws), ws.numel(), _stream(pos.device)))
+    if exclusions is None:
+        N.check(N.lib().nbody_forces(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(f), _ptr(p),
+                                     _ptr(ws), ws.numel(), _stream(pos.device)))
+    else:
+        ex = exclusions.c(n)
+        N.check(N.lib().nbody_forces_excl(_ptr(pos), _ptr(par), n, ctypes.byref(ex),
+                                          ctypes.byref(law.c()), _ptr(f), _ptr(p), _ptr(ws),
+                                          ws.numel(), _stream(pos.device)))
     return f, p
 
 
@@ -169,8 +200,10 @@ def _host_offsets(offsets):
     return np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
 
 
-def forces_batched(offsets, pos, params, law: Law, potential: bool = True):
-    """Forces of independent systems (rows offsets[s]..offsets[s+1]) in one persistent launch."""
+def forces_batched(offsets, pos, params, law: Law, potential: bool = True,
+                   exclusions: Exclusions = None):
+    """Forces of independent systems (rows offsets[s]..offsets[s+1]) in one persistent launch,
+    with optional exclusion lists over the concatenated rows."""
     off = _host_offsets(offsets)
     S = off.size - 1
     pos = _dev_f64(pos, None, "pos")
@@ -182,15 +215,62 @@ def forces_batched(offsets, pos, params, law: Law, potential: bool = True):
     f = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
     p = torch.empty(n, dtype=torch.float64, device=pos.device) if potential else None
     ws = workspace(API_BATCHED, n, S, law, pos.device)
-    N.check(N.lib().nbody_forces_batched(off.ctypes.data_as(ctypes.c_void_p), S, _ptr(pos),
-                                         _ptr(par), ctypes.byref(law.c()), _ptr(f), _ptr(p),
-                                         _ptr(ws), ws.numel(), _stream(pos.device)))
+    if exclusions is None:
+        N.check(N.lib().nbody_forces_batched(off.ctypes.data_as(ctypes.c_void_p), S, _ptr(pos),
+                                             _ptr(par), ctypes.byref(law.c()), _ptr(f), _ptr(p),
+                                             _ptr(ws), ws.numel(), _stream(pos.device)))
+    else:
+        ex = exclusions.c(n)
+        N.check(N.lib().nbody_forces_batched_excl(off.ctypes.data_as(ctypes.c_void_p), S, _ptr(pos),
+                                                  _ptr(par), ctypes.byref(ex), ctypes.byref(law.c()),
+                                                  _ptr(f), _ptr(p), _ptr(ws), ws.numel(),
+                                                  _stream(pos.device)))
     return f, p
 
 
 # --------------------------------------------------------------- adjoint
+def _types(types, n, n_types, dev):
+    if types is None:
+        return None, None
+    ty = torch.as_tensor(types, device=dev).to(torch.int32).contiguous()
+    if ty.shape != (n,):
+        raise ValueError("types must have shape (%d,)" % n)
+    if n and (int(ty.min()) < 0 or int(ty.max()) >= n_types):
+        raise ValueError("types must lie in [0, n_types)")
+    return ty, torch.empty((int(n_types), 2), dtype=torch.float64, device=dev)
+
+
+def forces_backward_batched(offsets, pos, params, grad_force, law: Law, want_pos=True,
+                            want_params=None, types=None, n_types=0, exclusions: Exclusions = None):
+    """Adjoint of forces_batched() (optionally with exclusion lists), every system in one
+    persistent launch: (dL/dpos [N,3] or None, dL/dparams [N,P] or None, per-type
+    (dL/dsigma, dL/depsilon) [n_types, 2] summed over all systems, or None)."""
+    off = _host_offsets(offsets)
+    S = off.size - 1
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    if S < 0 or off[-1] != n:
+        raise ValueError("offsets[-1] must equal the number of rows of pos")
+    pos = _dev_f64(pos, (n, 3), "pos")
+    par = _params(params, n, law, pos.device)
+    g = _dev_f64(grad_force, (n, 3), "grad_force")
+    if want_params is None:
+        want_params = law.kind != GRAVITY
+    dev = pos.device
+    gp = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_pos else None
+    gq = torch.empty((n, law.n_params), dtype=torch.float64, device=dev) if want_params else None
+    ty, gt = _types(types, n, n_types, dev)
+    ex = exclusions.c(n) if exclusions is not None else None
+    ws = workspace(API_BACKWARD_BATCHED, n, S, law, dev)
+    N.check(N.lib().nbody_forces_backward_batched(
+        off.ctypes.data_as(ctypes.c_void_p), S, _ptr(pos), _ptr(par),
+        ctypes.byref(ex) if ex is not None else None, ctypes.byref(law.c()), _ptr(g), _ptr(gp),
+        _ptr(gq), _ptr(ty), int(n_types), _ptr(gt), _ptr(ws), ws.numel(), _stream(dev)))
+    return gp, gq, gt
+
+
 def forces_backward(pos, params, grad_force, law: Law, want_pos=True, want_params=None,
-                    types=None, n_types=0):
+                    types=None, n_types=0, exclusions: Exclusions = None):
     """Adjoint of forces(): returns (dL/dpos [N,3] or None, dL/dparams [N,P] or None,
     per-type (dL/dsigma, dL/depsilon) [n_types, 2] or None)."""
     pos = _dev_f64(pos, None, "pos")
@@ -212,9 +292,16 @@ def forces_backward(pos, params, grad_force, law: Law, want_pos=True, want_param
             raise ValueError("types must lie in [0, n_types)")
         gt = torch.empty((int(n_types), 2), dtype=torch.float64, device=dev)
     ws = workspace(API_BACKWARD, n, 1, law, dev)
-    N.check(N.lib().nbody_forces_backward(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(g),
-                                          _ptr(gp), _ptr(gq), _ptr(ty), int(n_types), _ptr(gt),
-                                          _ptr(ws), ws.numel(), _stream(dev)))
+    if exclusions is None:
+        N.check(N.lib().nbody_forces_backward(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(g),
+                                              _ptr(gp), _ptr(gq), _ptr(ty), int(n_types), _ptr(gt),
+                                              _ptr(ws), ws.numel(), _stream(dev)))
+    else:
+        ex = exclusions.c(n)
+        N.check(N.lib().nbody_forces_backward_excl(_ptr(pos), _ptr(par), n, ctypes.byref(ex),
+                                                   ctypes.byref(law.c()), _ptr(g), _ptr(gp), _ptr(gq),
+                                                   _ptr(ty), int(n_types), _ptr(gt), _ptr(ws),
+                                                   ws.numel(), _stream(dev)))
     return gp, gq, gt
 
 

@@ -238,4 +238,58 @@ def test_jerk_and_hermite_validation(N):
     assert lib.nbody_set_config(4, ctypes.byref(good)) == 0
     assert lib.nbody_set_config(5, ctypes.byref(good)) == 0
     assert lib.nbody_set_config(4, None) == 0 and lib.nbody_set_config(5, None) == 0
-    assert lib.nbody_set_config(6, ctypes.byref(good)) == N.NBODY_EINVAL
+    assert lib.nbody_set_config(6, ctypes.byref(good)) == 0
+    assert lib.nbody_set_config(6, None) == 0
+    assert lib.nbody_set_config(7, ctypes.byref(good)) == N.NBODY_EINVAL
+
+
+def test_exclusions_and_batched_adjoint_validation(N):
+    lib = N.lib()
+    g = law(N)
+    lj = law(N, kind=1)
+    ljs = law(N, kind=3)
+    plain = law(N, kind=1, prec=3)
+    ex = N.NBodyExclusions(fake(), fake(), 4)
+
+    def fx(lw, e=ex, n=10, ws_bytes=1 << 30):
+        return lib.nbody_forces_excl(fake(), fake(), n, ctypes.byref(e) if e is not None else None,
+                                     ctypes.byref(lw), fake(), None, fake(), ws_bytes, None)
+
+    assert fx(g) == N.NBODY_ENOTSUP                        # exclusions are an LJC matter
+    assert fx(plain) == N.NBODY_ENOTSUP
+    assert fx(lj, e=None) == N.NBODY_EINVAL
+    assert fx(lj, e=N.NBodyExclusions(None, fake(), 4)) == N.NBODY_EINVAL
+    assert fx(lj, e=N.NBodyExclusions(fake(), None, 4)) == N.NBODY_EINVAL
+    assert fx(lj, e=N.NBodyExclusions(fake(), fake(), -1)) == N.NBODY_EINVAL
+    assert fx(lj, ws_bytes=64) == N.NBODY_EWORKSPACE
+    assert fx(lj, n=0) == 0
+
+    def off(vals):
+        a = (ctypes.c_int64 * len(vals))(*vals)
+        return ctypes.cast(a, ctypes.c_void_p), a
+
+    p, keep = off([0, 5, 12])
+    assert lib.nbody_forces_batched_excl(p, 2, fake(), fake(), ctypes.byref(ex), ctypes.byref(g), fake(),
+                                         None, fake(), 1 << 30, None) == N.NBODY_ENOTSUP
+    assert lib.nbody_forces_batched_excl(p, 2, fake(), fake(), None, ctypes.byref(lj), fake(), None,
+                                         fake(), 1 << 30, None) == N.NBODY_EINVAL
+    assert lib.nbody_forces_backward_excl(fake(), fake(), 10, ctypes.byref(ex), ctypes.byref(ljs), fake(),
+                                          fake(), fake(), None, 0, None, fake(), 1 << 30,
+                                          None) == N.NBODY_ENOTSUP
+
+    def bb(lw, e=None, gp=True, gq=True, ws_bytes=1 << 30, o=p, S=2):
+        return lib.nbody_forces_backward_batched(o, S, fake(), fake(),
+                                                 ctypes.byref(e) if e is not None else None,
+                                                 ctypes.byref(lw), fake(), fake() if gp else None,
+                                                 fake() if gq else None, None, 0, None, fake(),
+                                                 ws_bytes, None)
+
+    assert bb(g) == N.NBODY_EINVAL                         # gravity: no parameter adjoint
+    assert bb(g, e=ex, gq=False) == N.NBODY_ENOTSUP
+    assert bb(ljs) == N.NBODY_ENOTSUP
+    assert bb(lj, ws_bytes=64) == N.NBODY_EWORKSPACE
+    assert bb(lj, gp=False, gq=False) == 0
+    bad, keep2 = off([0, 7, 3])
+    assert bb(lj, o=bad) == N.NBODY_EINVAL
+    assert lib.nbody_workspace_bytes(6, 10000, 50, ctypes.byref(lj)) > 10000 * 64
+    assert lib.nbody_flops_per_pair(6, 1, 0) == 68
