@@ -17,7 +17,9 @@ pass and the oracle, and three secondary legs: the batched ensemble (256 LJC
 systems, N_s in [500, 5000], one persistent launch vs one launch per system,
 each side autotuned), the position adjoint at N = 262,144 (FP32 vs FP64), and
 every pair law of Table 1 at N = 65,536, plus the acceleration-and-jerk kernel
-and the block-time-step Hermite integrator on a Plummer sphere of 65,536.
+and the block-time-step Hermite integrator on a Plummer sphere of 65,536;
+bonded chains with exclusion lists (N = 8192) and the batched adjoint of the
+256-system ensemble.
 """
 from __future__ import annotations
 
@@ -76,6 +78,7 @@ def main():
     pos, vel, mass = W.plummer(args.n, 5)
     ens = W.batched_md(256, seed=4) if args.legs == "all" else None
     md = W.md_system(N_LAWS, 3, box=(32.0 * N_LAWS) ** (1.0 / 3.0)) if args.legs == "all" else None
+    chains = W.bonded_chains(256, 32, 3) if args.legs == "all" else None
     log("inputs drawn in %.1f s" % (time.time() - t0))
 
     import torch
@@ -199,6 +202,8 @@ def main():
         out["backward"] = backward_leg(nb, torch, dev, W)
         out["laws"] = laws_leg(nb, torch, dev, W, md)
         out["jerk"] = jerk_leg(nb, torch, dev, W)
+        out["bonded"] = bonded_leg(nb, torch, dev, W, chains)
+        out["batched_backward"] = batched_backward_leg(nb, torch, dev, ens)
     print(json.dumps(out), flush=True)
 
 
@@ -430,6 +435,83 @@ def jerk_leg(nb, torch, dev, W):
                           "g_pairs_per_s": pairs / wall / 1e9,
                           "rel_energy_error": abs(e1 - e0) / abs(e0)}
     log("block steps:", res["block_steps"])
+    return res
+
+
+def _time(torch, fn, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t)
+    return best
+
+
+def bonded_leg(nb, torch, dev, W, chains):
+    """Bonded molecules with exclusion lists (Section 5): 256 chains of 32 atoms (N = 8192,
+    1-2 and 1-3 pairs excluded), LJC(linear), FP32 + Kahan with the energy: forces with
+    and without the lists, and the force-matching adjoint with them."""
+    sy, eo, ei = chains
+    x = torch.tensor(sy.pos, device=dev)
+    p = torch.tensor(sy.params(), device=dev)
+    ex = nb.Exclusions(torch.tensor(eo, device=dev), torch.tensor(ei, device=dev))
+    law = nb.ljc_linear("fp32_kahan")
+    law64 = nb.ljc_linear("fp64")
+    t_ex = _time(torch, lambda: nb.forces(x, p, law, exclusions=ex))
+    t_plain = _time(torch, lambda: nb.forces(x, p, law))
+    f32, _ = nb.forces(x, p, law, exclusions=ex)
+    f64, _ = nb.forces(x, p, law64, exclusions=ex)
+    e = (torch.linalg.norm(f32 - f64, dim=1) / torch.linalg.norm(f64, dim=1)).cpu().numpy()
+    g = torch.tensor(W.unit_cotangent(sy.n, 57), device=dev)
+    t_adj = _time(torch, lambda: nb.forces_backward(x, p, g, law, exclusions=ex))
+    t_adj64 = _time(torch, lambda: nb.forces_backward(x, p, g, law64, exclusions=ex))
+    n = sy.n
+    res = {"n": n, "chains": 256, "chain_len": 32, "excluded_pairs": int(eo[-1]),
+           "forces_ms": t_ex * 1e3, "forces_no_exclusions_ms": t_plain * 1e3,
+           "g_pairs_per_s": float(n) * n / t_ex / 1e9,
+           "err_vs_fp64": {"median": float(np.median(e)), "max": float(e.max())},
+           "adjoint_fp32_ms": t_adj * 1e3, "adjoint_fp64_ms": t_adj64 * 1e3,
+           "adjoint_speedup_fp32_vs_fp64": t_adj64 / t_adj}
+    log("bonded:", res)
+    return res
+
+
+def batched_backward_leg(nb, torch, dev, ens):
+    """The adjoint of the 256-system LJC ensemble in one persistent FP32 launch against one
+    FP64 adjoint launch per system (both with per-type sums)."""
+    off, pos, par, systems = ens
+    S = len(systems)
+    x = torch.tensor(pos, device=dev)
+    p = torch.tensor(par, device=dev)
+    n = x.shape[0]
+    rng = np.random.default_rng(58)
+    g = torch.tensor(rng.standard_normal((n, 3)) / np.sqrt(3 * n), device=dev)
+    types = torch.tensor(np.concatenate([s.types for s in systems]), device=dev)
+    law = nb.ljc_linear("fp32_kahan")
+    law64 = nb.ljc_linear("fp64")
+    t_b = _time(torch, lambda: nb.forces_backward_batched(off, x, p, g, law, types=types, n_types=4))
+    views = [(x[off[s]:off[s + 1]], p[off[s]:off[s + 1]], g[off[s]:off[s + 1]],
+              types[off[s]:off[s + 1]]) for s in range(S)]
+
+    def loop(l):
+        return [nb.forces_backward(xs, ps, gs, l, types=ts, n_types=4) for xs, ps, gs, ts in views]
+
+    t_l64 = _time(torch, lambda: loop(law64), reps=3)
+    gb, qb, _ = nb.forces_backward_batched(off, x, p, g, law, types=types, n_types=4)
+    outs = loop(law64)
+    g64 = torch.cat([o[0] for o in outs])
+    e = (torch.linalg.norm(gb - g64, dim=1) / torch.linalg.norm(g64, dim=1)).cpu().numpy()
+    med_sys = [float(np.median(e[off[s]:off[s + 1]])) for s in range(S) if off[s + 1] > off[s]]
+    pairs = float(sum(int(off[s + 1] - off[s]) ** 2 for s in range(S)))
+    res = {"systems": S, "atoms": int(n), "pairs": pairs, "batched_fp32_kahan_ms": t_b * 1e3,
+           "loop_fp64_ms": t_l64 * 1e3, "speedup_vs_loop_fp64": t_l64 / t_b,
+           "flops_per_pair": nb.flops_per_pair(nb.API_BACKWARD_BATCHED, nb.LJC_LINEAR, False),
+           "batched_tflops": 68 * pairs / t_b / 1e12,
+           "err_vs_fp64_per_system_median_max": max(med_sys), "err_vs_fp64_max": float(e.max())}
+    log("batched backward:", res)
     return res
 
 
