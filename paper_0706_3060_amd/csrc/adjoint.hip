@@ -451,8 +451,9 @@ __global__ __launch_bounds__(256) void k_adjoint_batched(const AdjRecOf<LAW, PRE
         if (lane == 0) u = atomicAdd(a.ticket, 1);
         u = __builtin_amdgcn_readfirstlane(u);
         if ((int64_t)u >= a.n_units) break;      // every wave leaves once the list is drained
-        const int s = a.units[2 * (int64_t)u];
-        const int64_t rb = a.units[2 * (int64_t)u + 1];
+        const int s = a.units[4 * (int64_t)u];
+        if (s < 0 || (int64_t)s >= a.n_systems) continue;   // never index outside the tables
+        const int64_t rb = a.units[4 * (int64_t)u + 1];
         const int64_t o = a.off[s], ns = a.off[s + 1] - o;
         const int64_t po = a.poff[s], pe = a.poff[s + 1];
         const int64_t lbase = rb * (int64_t)(kWave * I);

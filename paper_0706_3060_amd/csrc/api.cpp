@@ -408,24 +408,51 @@ JerkWs jerk_layout(int api, const nbody_law *law, int64_t n)
     return w;
 }
 
+// Partial slots of the batched forward's j parts: a slot holds the part sums
+// of one row block (64 x ipl rows, 4 doubles each); the buffer is sized for
+// kMaxBatchSlots slots of 128 rows.
+constexpr int64_t kMaxBatchSlots = int64_t(1) << 15;
+constexpr int64_t kMinJUnit = 256;
+
+int64_t batch_slot_cap(int64_t n_total, int64_t S)
+{
+    // j parts are at least kMinJUnit records: at most (row blocks) x (pn / kMinJUnit + 1)
+    const int64_t rb = n_total / 64 + std::max<int64_t>(S, 1) + 1;
+    const int64_t parts = (n_total + 64 * std::max<int64_t>(S, 1)) / kMinJUnit + 1;
+    const double bound = (double)rb * (double)parts;
+    return bound < (double)kMaxBatchSlots ? (int64_t)bound : kMaxBatchSlots;
+}
+
 struct BatWs {
-    size_t rec_off, unit_off, off_off, poff_off, ticket_off, total;
+    size_t rec_off, unit_off, off_off, poff_off, systab_off, part_off, ticket_off, total;
+    int64_t max_slots;       // partial budget: max_slots slots of 128 rows
+    int64_t max_units;       // capacity of the unit table
+    int64_t max_records;     // capacity of the record buffer
 };
 
 BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
 {
     BatWs w{};
     const int64_t npad_max = n_total + 64 * std::max<int64_t>(S, 1);
-    const int64_t units_max = n_total / 64 + std::max<int64_t>(S, 1) + 1;
+    w.max_slots = batch_slot_cap(n_total, S);
+    // units = (row blocks of single-part systems) + (slots of split systems); the
+    // planner admits up to 2 * max_slots / ipl slots (ipl >= 1)
+    const int64_t units_max = n_total / 64 + std::max<int64_t>(S, 1) + 1 + 2 * w.max_slots;
+    w.max_units = units_max;
+    w.max_records = npad_max;
     size_t off = 0;
     w.rec_off = off;
     off = align256(off + (size_t)npad_max * rec_bytes(law->kind, law->precision));
     w.unit_off = off;
-    off = align256(off + (size_t)units_max * 2 * sizeof(int32_t));
+    off = align256(off + (size_t)units_max * 4 * sizeof(int32_t));
     w.off_off = off;
     off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
     w.poff_off = off;
     off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
+    w.systab_off = off;
+    off = align256(off + (size_t)std::max<int64_t>(S, 1) * 3 * sizeof(int64_t));
+    w.part_off = off;
+    off = align256(off + (size_t)w.max_slots * 128 * 4 * sizeof(double));
     w.ticket_off = off;
     off = align256(off + 256);
     w.total = off;
@@ -446,7 +473,7 @@ AdjBatWs adjb_layout(const nbody_law *law, int64_t n_total, int64_t S)
     w.rec_off = off;
     off = align256(off + (size_t)npad_max * adj_rec_bytes(law->kind, law->precision));
     w.unit_off = off;
-    off = align256(off + (size_t)units_max * 2 * sizeof(int32_t));
+    off = align256(off + (size_t)units_max * 4 * sizeof(int32_t));
     w.off_off = off;
     off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
     w.poff_off = off;
@@ -650,36 +677,59 @@ void to_abi(const Cfg &c, nbody_config *o)
 // ------------------------------------------------------------ batched plan
 struct BatchPlan {
     std::vector<int64_t> poff;
-    std::vector<int32_t> units;
+    std::vector<int64_t> systab;      // [S][3] parts, records per part, first slot
+    std::vector<int32_t> units;       // [n][4]
     int64_t npad_total = 0;
+    int64_t n_slots = 0;
 };
 
-BatchPlan plan_batched(const int64_t *offsets, int64_t S, int ipl)
+// Work units (system, row block, j part).  A system's padded j range of pn
+// records is cut into P = ceil(pn / j_unit) parts of equal length (a multiple
+// of 64; j_unit = 0: one part), so that large systems yield enough units to
+// balance the persistent grid; each row block of a system with P > 1 owns P
+// consecutive partial slots.
+BatchPlan plan_batched(const int64_t *offsets, int64_t S, int ipl, int64_t j_unit)
 {
     BatchPlan p;
     p.poff.assign((size_t)S + 1, 0);
+    p.systab.assign((size_t)S * 3, 0);
     struct U {
         int64_t cost;
-        int32_t s, rb;
+        int32_t s, rb, part;
     };
     std::vector<U> us;
     const int64_t rows = 64 * ipl;
+    int64_t slots = 0;
     for (int64_t s = 0; s < S; ++s) {
         const int64_t ns = offsets[s + 1] - offsets[s];
         const int64_t pn = round_up(ns, 64);
         p.poff[s + 1] = p.poff[s] + pn;
-        for (int64_t rb = 0; rb * rows < ns; ++rb) {
+        int64_t parts = (j_unit > 0 && pn > j_unit) ? (pn + j_unit - 1) / j_unit : 1;
+        const int64_t plen = std::max<int64_t>(64, round_up((pn + parts - 1) / std::max<int64_t>(parts, 1), 64));
+        parts = pn > 0 ? (pn + plen - 1) / plen : 1;
+        const int64_t nrb = (ns + rows - 1) / rows;
+        p.systab[3 * s] = parts;
+        p.systab[3 * s + 1] = plen;
+        p.systab[3 * s + 2] = parts > 1 ? slots : 0;
+        if (parts > 1) slots += nrb * parts;
+        for (int64_t rb = 0; rb < nrb; ++rb) {
             const int64_t r = std::min(rows, ns - rb * rows);
-            us.push_back({r * pn, (int32_t)s, (int32_t)rb});
+            for (int64_t q = 0; q < parts; ++q) {
+                const int64_t len = std::min(plen, pn - q * plen);
+                us.push_back({r * len, (int32_t)s, (int32_t)rb, (int32_t)q});
+            }
         }
     }
     p.npad_total = p.poff[S];
+    p.n_slots = slots;
     // longest processing time first; ties keep system order (stable)
     std::stable_sort(us.begin(), us.end(), [](const U &a, const U &b) { return a.cost > b.cost; });
-    p.units.resize(us.size() * 2);
+    p.units.resize(us.size() * 4);
     for (size_t k = 0; k < us.size(); ++k) {
-        p.units[2 * k] = us[k].s;
-        p.units[2 * k + 1] = us[k].rb;
+        p.units[4 * k] = us[k].s;
+        p.units[4 * k + 1] = us[k].rb;
+        p.units[4 * k + 2] = us[k].part;
+        p.units[4 * k + 3] = 0;
     }
     return p;
 }
@@ -701,12 +751,36 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
                 const double *pos, const double *params, double *out_force, double *out_pot,
                 void *ws, const BatWs &lay, hipStream_t s, const ExclArgs &excl = ExclArgs{})
 {
-    const BatchPlan plan = plan_batched(offsets, S, c.ipl);
+    const int per_cu =
+        std::max(1, batched_max_blocks_per_cu(law->kind, law->precision, c.ipl, out_pot != nullptr,
+                                              c.j_stage, c.block, excl.off != nullptr));
+    const int64_t resident = (int64_t)device_cus() * per_cu * (c.block / 64);
+    // j parts: about 8 units per resident wave, no part shorter than kMinJUnit
+    // records, within the workspace's partial slots
+    double work = 0.0;
+    for (int64_t q = 0; q < S; ++q) {
+        const int64_t ns = offsets[q + 1] - offsets[q];
+        work += (double)ns * (double)round_up(ns, 64);
+    }
+    int64_t j_unit = round_up((int64_t)(work / (8.0 * (double)resident * 64.0 * c.ipl)) + 1, 64);
+    j_unit = std::max(kMinJUnit, j_unit);
+    BatchPlan plan = plan_batched(offsets, S, c.ipl, j_unit);
+    // the slot budget holds max_slots x 128 rows; a slot takes 64 x ipl rows
+    while (plan.n_slots * c.ipl > 2 * lay.max_slots) {
+        j_unit *= 2;
+        plan = plan_batched(offsets, S, c.ipl, j_unit);
+    }
     if (plan.units.empty()) return NBODY_OK;
+    // the plan must fit the workspace regions it is copied into
+    if ((int64_t)plan.units.size() / 4 > lay.max_units || plan.npad_total > lay.max_records ||
+        plan.n_slots * c.ipl > 2 * lay.max_slots)
+        return fail(NBODY_EWORKSPACE, "internal: batched plan exceeds its workspace regions "
+                    "(%lld units, %lld slots)", (long long)(plan.units.size() / 4), (long long)plan.n_slots);
     char *base = (char *)ws;
     int32_t *d_units = (int32_t *)(base + lay.unit_off);
     int64_t *d_off = (int64_t *)(base + lay.off_off);
     int64_t *d_poff = (int64_t *)(base + lay.poff_off);
+    int64_t *d_systab = (int64_t *)(base + lay.systab_off);
     hipError_t e;
     // Pageable sources: the runtime stages them before returning.
     e = hipMemcpyAsync(d_units, plan.units.data(), plan.units.size() * sizeof(int32_t),
@@ -715,6 +789,9 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
         e = hipMemcpyAsync(d_off, offsets, (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_poff, plan.poff.data(), (size_t)(S + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_systab, plan.systab.data(), plan.systab.size() * sizeof(int64_t),
                            hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "batched tables");
 
@@ -739,10 +816,7 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     b.pot = out_pot != nullptr;
     b.block = c.block;
     b.j_stage = c.j_stage;
-    const int per_cu =
-        std::max(1, batched_max_blocks_per_cu(b.law, b.prec, b.ipl, b.pot, b.j_stage, b.block,
-                                              excl.off != nullptr));
-    const int64_t n_units = (int64_t)plan.units.size() / 2;
+    const int64_t n_units = (int64_t)plan.units.size() / 4;
     const int64_t waves_needed = n_units;
     const int64_t blocks_needed = (waves_needed + c.block / 64 - 1) / (c.block / 64);
     b.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)device_cus() * per_cu, blocks_needed));
@@ -750,6 +824,9 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     b.units = d_units;
     b.off = d_off;
     b.poff = d_poff;
+    b.systab = d_systab;
+    b.partial = (double *)(base + lay.part_off);
+    b.any_parts = plan.n_slots > 0;
     b.n_systems = S;
     b.n_total = offsets[S];
     b.npad_total = plan.npad_total;
@@ -1111,8 +1188,10 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     hipStream_t s = (hipStream_t)stream;
     const Cfg c = with_excl(choose(NBODY_API_BACKWARD_BATCHED, law, n, n_systems, false), excl != nullptr);
     const int ipl = std::min(c.ipl, 2);
-    const BatchPlan plan = plan_batched(offsets, n_systems, ipl);
+    const BatchPlan plan = plan_batched(offsets, n_systems, ipl, 0);
     if (plan.units.empty()) return NBODY_OK;
+    if ((int64_t)plan.units.size() / 4 > n / 64 + std::max<int64_t>(n_systems, 1) + 1)
+        return fail(NBODY_EWORKSPACE, "internal: batched adjoint plan exceeds its unit table");
     char *base = (char *)ws;
     int32_t *d_units = (int32_t *)(base + lay.unit_off);
     int64_t *d_off = (int64_t *)(base + lay.off_off);
@@ -1132,7 +1211,7 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     a.block = c.block;
     a.j_stage = c.j_stage;
     a.j_tile = c.j_tile;
-    a.n_units = (int64_t)plan.units.size() / 2;
+    a.n_units = (int64_t)plan.units.size() / 4;
     a.units = d_units;
     a.off = d_off;
     a.poff = d_poff;

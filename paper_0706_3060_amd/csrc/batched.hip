@@ -2,11 +2,14 @@
 //
 // The paper's small-system problem (Section 3.4: too few i-particles to fill
 // the machine, fixed per-kernel overhead) is addressed here by batching: the
-// host lists (system, row-block) work units in decreasing order of cost
-// (longest-processing-time first), and a persistent grid sized to the chip's
-// resident-wave capacity pulls units with an integer ticket until the list
-// is exhausted.  Each unit is the same tiled j loop as the single-system
-// kernel, restricted to the records of its own system.
+// host lists (system, row-block, j-part) work units in decreasing order of
+// cost (longest-processing-time first), and a persistent grid sized to the
+// chip's resident-wave capacity pulls units with an integer ticket until the
+// list is exhausted.  Each unit is the same tiled j loop as the single-system
+// kernel, restricted to one part of the records of its own system.  A system
+// whose j range is cut into P > 1 parts (Section 3.4's replication, applied
+// per system so that there are enough units to balance the machine) writes
+// per-part partial sums, which k_batched_reduce adds in part order.
 #include <type_traits>
 
 #include "allpairs.h"
@@ -19,10 +22,12 @@ namespace nbk {
 template <int LAW, int PREC, int I, bool POT, int JS, bool EX>
 __device__ __forceinline__ void batched_body(
     const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec,
-    const int32_t *__restrict__ units, int64_t n_units, const int64_t *__restrict__ off,
-    const int64_t *__restrict__ poff, int j_tile, PairK<typename RealOf<PREC>::type> kc,
-    int *ticket, const Epilogue &epi, const ExclArgs &ex)
+    const BatchLaunch &b, PairK<typename RealOf<PREC>::type> kc)
 {
+    const int32_t *__restrict__ units = b.units;
+    const int64_t *__restrict__ off = b.off;
+    const int64_t *__restrict__ poff = b.poff;
+    const Epilogue &epi = b.epi;
     using T = typename RealOf<PREC>::type;
     using R = typename RecOf<T, LAW>::type;
     using IS = typename IStateOf<R>::type;
@@ -33,13 +38,18 @@ __device__ __forceinline__ void batched_body(
 
     for (;;) {
         int u = 0;
-        if (lane == 0) u = atomicAdd(ticket, 1);
+        if (lane == 0) u = atomicAdd(b.ticket, 1);
         u = __builtin_amdgcn_readfirstlane(u);
-        if ((int64_t)u >= n_units) break;      // every wave leaves once the list is drained
-        const int s = units[2 * (int64_t)u];
-        const int64_t rb = units[2 * (int64_t)u + 1];
+        if ((int64_t)u >= b.n_units) break;    // every wave leaves once the list is drained
+        const int s = units[4 * (int64_t)u];
+        if (s < 0 || (int64_t)s >= b.n_systems) continue;   // never index outside the tables
+        const int64_t rb = units[4 * (int64_t)u + 1];
+        const int64_t part = units[4 * (int64_t)u + 2];
         const int64_t o = off[s], ns = off[s + 1] - o;
         const int64_t po = poff[s], pe = poff[s + 1];
+        const int64_t nparts = b.systab[3 * (int64_t)s], plen = b.systab[3 * (int64_t)s + 1];
+        const int64_t jb = po + part * plen;
+        const int64_t je = jb + plen < pe ? jb + plen : pe;
         const int64_t lbase = rb * (int64_t)(kWave * I);
 
         IS is[I];
@@ -61,15 +71,24 @@ __device__ __forceinline__ void batched_body(
             ExclMask<I> mask;
 #pragma unroll
             for (int k = 0; k < I; ++k) mask.pid[k] = pid[k];
-            mask.init(ex, gid, po - o);
-            j_range_masked<JS, ForceOp<POT, LAW>, PREC, I>(rec, po, pe, j_tile, is, mask, kc, acc, p, wl);
+            mask.init(b.excl, gid, po - o);
+            j_range_masked<JS, ForceOp<POT, LAW>, PREC, I>(rec, jb, je, b.j_tile, is, mask, kc, acc, p, wl);
         } else {
-            j_range<JS, ForceOp<POT, LAW>, PREC, I>(rec, po, pe, j_tile, is, pid, kc, acc, p, wl);
+            j_range<JS, ForceOp<POT, LAW>, PREC, I>(rec, jb, je, b.j_tile, is, pid, kc, acc, p, wl);
         }
+        const int64_t slot = b.systab[3 * (int64_t)s + 2] + rb * nparts + part;
 #pragma unroll
         for (int k = 0; k < I; ++k) {
             const int64_t l = lbase + lane + (int64_t)kWave * k;
             if (l >= ns) continue;
+            if (nparts > 1) {            // partial sums of this part, added by k_batched_reduce
+                double *q = b.partial + (slot * (kWave * I) + lane + kWave * k) * 4;
+                q[0] = acc[k][0].value();
+                q[1] = acc[k][1].value();
+                q[2] = acc[k][2].value();
+                q[3] = POT ? acc[k][NC - 1].value() : 0.0;
+                continue;
+            }
             const int64_t r = o + l;
             epi.out_force[3 * r] = epi.fscale * acc[k][0].value();
             epi.out_force[3 * r + 1] = epi.fscale * acc[k][1].value();
@@ -79,26 +98,51 @@ __device__ __forceinline__ void batched_body(
     }
 }
 
+// The rows of systems cut into several j parts: the part sums in part order
+// (Neumaier, so the result does not depend on the schedule).
+__global__ __launch_bounds__(256) void k_batched_reduce(BatchLaunch b)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= b.n_total) return;
+    int64_t lo = 0, hi = b.n_systems;          // off[lo] <= r < off[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (b.off[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    const int64_t nparts = b.systab[3 * lo];
+    if (nparts <= 1) return;
+    const int64_t rows = (int64_t)kWave * b.ipl;
+    const int64_t l = r - b.off[lo];
+    const int64_t rb = l / rows, rr = l - rb * rows;
+    const int64_t slot0 = b.systab[3 * lo + 2] + rb * nparts;
+    NSum v[4];
+    for (int64_t p = 0; p < nparts; ++p) {
+        const double *q = b.partial + ((slot0 + p) * rows + rr) * 4;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c].add(q[c]);
+    }
+    const Epilogue &e = b.epi;
+    e.out_force[3 * r] = e.fscale * v[0].value();
+    e.out_force[3 * r + 1] = e.fscale * v[1].value();
+    e.out_force[3 * r + 2] = e.fscale * v[2].value();
+    if (b.pot && e.out_pot) e.out_pot[r] = e.pscale * v[3].value();
+}
+
 template <int LAW, int PREC, int I, bool POT, int JS>
 __global__ __launch_bounds__(256) void k_batched(
-    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec,
-    const int32_t *__restrict__ units, int64_t n_units, const int64_t *__restrict__ off,
-    const int64_t *__restrict__ poff, int j_tile, PairK<typename RealOf<PREC>::type> kc,
-    int *ticket, Epilogue epi)
+    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec, BatchLaunch b,
+    PairK<typename RealOf<PREC>::type> kc)
 {
-    batched_body<LAW, PREC, I, POT, JS, false>(rec, units, n_units, off, poff, j_tile, kc, ticket, epi,
-                                               ExclArgs{});
+    batched_body<LAW, PREC, I, POT, JS, false>(rec, b, kc);
 }
 
 template <int LAW, int PREC, int I, bool POT>
 __global__ __launch_bounds__(256) void k_batched_excl(
-    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec,
-    const int32_t *__restrict__ units, int64_t n_units, const int64_t *__restrict__ off,
-    const int64_t *__restrict__ poff, int j_tile, PairK<typename RealOf<PREC>::type> kc,
-    int *ticket, Epilogue epi, ExclArgs ex)
+    const typename RecOf<typename RealOf<PREC>::type, LAW>::type *__restrict__ rec, BatchLaunch b,
+    PairK<typename RealOf<PREC>::type> kc)
 {
-    batched_body<LAW, PREC, I, POT, 1, true>(rec, units, n_units, off, poff, j_tile, kc, ticket, epi,
-                                             ex);
+    batched_body<LAW, PREC, I, POT, 1, true>(rec, b, kc);
 }
 
 // ---------------------------------------------------------------- packing ----
@@ -170,19 +214,16 @@ static void launch_b(const BatchLaunch &b, hipStream_t s)
     if (b.excl.off) {
         if constexpr (LAW != GRAVITY && I <= 2 && PREC != P_PLAIN) {
             hipLaunchKernelGGL((k_batched_excl<LAW, PREC, I, POT>), dim3(b.grid), dim3(b.block), 0, s,
-                               (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile, kc,
-                               b.ticket, b.epi, b.excl);
+                               (const R *)b.rec, b, kc);
         }
         return;
     }
     if (b.j_stage == 1)
         hipLaunchKernelGGL((k_batched<LAW, PREC, I, POT, 1>), dim3(b.grid), dim3(b.block), 0, s,
-                           (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile, kc,
-                           b.ticket, b.epi);
+                           (const R *)b.rec, b, kc);
     else
         hipLaunchKernelGGL((k_batched<LAW, PREC, I, POT, 0>), dim3(b.grid), dim3(b.block), 0, s,
-                           (const R *)b.rec, b.units, b.n_units, b.off, b.poff, b.j_tile, kc,
-                           b.ticket, b.epi);
+                           (const R *)b.rec, b, kc);
 }
 
 // Calls f.run<LAW, PREC, I, POT>() for the runtime selectors (I in {1, 2, 4});
@@ -251,6 +292,9 @@ hipError_t launch_batched(const BatchLaunch &b, hipStream_t s)
     if (b.excl.off && (b.law == GRAVITY || b.ipl > 2 || b.prec == P_PLAIN)) return hipErrorInvalidValue;
     LaunchB l{b, s};
     if (!batched_dispatch(b.law, b.prec, b.ipl, b.pot != 0, l)) return hipErrorInvalidValue;
+    e = hipGetLastError();
+    if (e != hipSuccess || !b.any_parts) return e;
+    hipLaunchKernelGGL(k_batched_reduce, dim3((unsigned)((b.n_total + 255) / 256)), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

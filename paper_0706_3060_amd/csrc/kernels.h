@@ -74,9 +74,12 @@ struct BatchLaunch {
     int block;
     int grid;                    // persistent workgroups
     int64_t n_units;
-    const int32_t *units;        // [n_units][2] = (system, row block), cost-descending
+    const int32_t *units;        // [n_units][4] = (system, row block, j part, 0), cost-descending
     const int64_t *off;          // [S+1] caller row offsets
     const int64_t *poff;         // [S+1] padded record offsets
+    const int64_t *systab;       // [S][3] = (j parts P, records per part, first partial slot)
+    double *partial;             // [slots][64 * ipl][4] part sums of systems with P > 1
+    int any_parts;               // some system has P > 1 (the part sums need reducing)
     int64_t n_systems;
     int64_t n_total, npad_total;
     int j_tile;
@@ -125,7 +128,7 @@ struct AdjBatchLaunch {
     int j_stage;
     int j_tile;
     int64_t n_units;
-    const int32_t *units;        // [n_units][2]
+    const int32_t *units;        // [n_units][4] (system, row block, 0, 0)
     const int64_t *off, *poff;   // [S+1] caller rows and padded record offsets
     int64_t n_systems, npad_total;
     double eps2, G, qscale;
