@@ -454,8 +454,12 @@ __global__ __launch_bounds__(256) void k_adjoint_batched(const AdjRecOf<LAW, PRE
         const int s = a.units[4 * (int64_t)u];
         if (s < 0 || (int64_t)s >= a.n_systems) continue;   // never index outside the tables
         const int64_t rb = a.units[4 * (int64_t)u + 1];
+        const int64_t part = a.units[4 * (int64_t)u + 2];
         const int64_t o = a.off[s], ns = a.off[s + 1] - o;
         const int64_t po = a.poff[s], pe = a.poff[s + 1];
+        const int64_t nparts = a.systab[3 * (int64_t)s], plen = a.systab[3 * (int64_t)s + 1];
+        const int64_t jb = po + part * plen;
+        const int64_t je = jb + plen < pe ? jb + plen : pe;
         const int64_t lbase = rb * (int64_t)(kWave * I);
         R is[I];
         int64_t pid[I], gid[I];
@@ -475,10 +479,11 @@ __global__ __launch_bounds__(256) void k_adjoint_batched(const AdjRecOf<LAW, PRE
 #pragma unroll
             for (int k = 0; k < I; ++k) mask.pid[k] = pid[k];
             mask.init(a.excl, gid, po - o);
-            j_range_masked<JS, Op, PREC, I>(rec, po, pe, a.j_tile, is, mask, kc, acc, p, wl);
+            j_range_masked<JS, Op, PREC, I>(rec, jb, je, a.j_tile, is, mask, kc, acc, p, wl);
         } else {
-            j_range<JS, Op, PREC, I>(rec, po, pe, a.j_tile, is, pid, kc, acc, p, wl);
+            j_range<JS, Op, PREC, I>(rec, jb, je, a.j_tile, is, pid, kc, acc, p, wl);
         }
+        const int64_t slot = a.systab[3 * (int64_t)s + 2] + rb * nparts + part;
 #pragma unroll
         for (int k = 0; k < I; ++k) {
             const int64_t l = lbase + lane + (int64_t)kWave * k;
@@ -486,6 +491,12 @@ __global__ __launch_bounds__(256) void k_adjoint_batched(const AdjRecOf<LAW, PRE
             double v[8];
 #pragma unroll
             for (int c = 0; c < NC; ++c) v[c] = acc[k][c].value();
+            if (nparts > 1) {            // partial sums of this part, added by the reduction
+                double *q = a.partial + (slot * (kWave * I) + lane + kWave * k) * 8;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) q[c] = v[c];
+                continue;
+            }
             adj_finish_b(a, LAW, o + l, v);
         }
     }
@@ -540,12 +551,44 @@ static bool adjb_dispatch(const AdjBatchLaunch &a, hipStream_t s, const void **f
     return a.law == GRAVITY ? adjb_prec<GRAVITY>(a, s, fn) : (a.law == LJC ? adjb_prec<LJC>(a, s, fn) : false);
 }
 
+// Rows of systems cut into several j parts: the part sums in part order.
+__global__ __launch_bounds__(256) void k_adjoint_batched_reduce(AdjBatchLaunch a)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n_total) return;
+    int64_t lo = 0, hi = a.n_systems;          // off[lo] <= r < off[hi]
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a.off[mid] <= r) lo = mid;
+        else hi = mid;
+    }
+    const int64_t nparts = a.systab[3 * lo];
+    if (nparts <= 1) return;
+    const int nc = a.law == GRAVITY ? 3 : 6;
+    const int64_t rows = (int64_t)kWave * a.ipl;
+    const int64_t l = r - a.off[lo];
+    const int64_t rb = l / rows, rr = l - rb * rows;
+    const int64_t slot0 = a.systab[3 * lo + 2] + rb * nparts;
+    NSum v[6];
+    for (int64_t p = 0; p < nparts; ++p) {
+        const double *q = a.partial + ((slot0 + p) * rows + rr) * 8;
+        for (int c = 0; c < nc; ++c) v[c].add(q[c]);
+    }
+    double out[8];
+    for (int c = 0; c < nc; ++c) out[c] = v[c].value();
+    adj_finish_b(a, a.law, r, out);
+}
+
 hipError_t launch_adjoint_batched(const AdjBatchLaunch &a, hipStream_t s)
 {
     if (a.n_units <= 0) return hipSuccess;
     hipError_t e = launch_fill_zero(a.ticket, 256, s);
     if (e != hipSuccess) return e;
     if (!adjb_dispatch(a, s, nullptr)) return hipErrorInvalidValue;
+    e = hipGetLastError();
+    if (e != hipSuccess || !a.any_parts) return e;
+    hipLaunchKernelGGL(k_adjoint_batched_reduce, dim3((unsigned)((a.n_total + 255) / 256)), dim3(256), 0,
+                       s, a);
     return hipGetLastError();
 }
 

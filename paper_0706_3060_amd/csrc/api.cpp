@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <tuple>
@@ -459,16 +460,21 @@ BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
     return w;
 }
 
-// Batched adjoint: adjoint records padded per system plus the unit tables.
+// Batched adjoint: adjoint records padded per system, the unit tables and the
+// part sums of split systems (8 doubles per row; half the forward's slot count).
 struct AdjBatWs {
-    size_t rec_off, unit_off, off_off, poff_off, ticket_off, total;
+    size_t rec_off, unit_off, off_off, poff_off, systab_off, part_off, ticket_off, total;
+    int64_t max_slots, max_units, max_records;
 };
 
 AdjBatWs adjb_layout(const nbody_law *law, int64_t n_total, int64_t S)
 {
     AdjBatWs w{};
     const int64_t npad_max = n_total + 64 * std::max<int64_t>(S, 1);
-    const int64_t units_max = n_total / 64 + std::max<int64_t>(S, 1) + 1;
+    w.max_slots = std::max<int64_t>(1, batch_slot_cap(n_total, S) / 2);
+    const int64_t units_max = n_total / 64 + std::max<int64_t>(S, 1) + 1 + 2 * w.max_slots;
+    w.max_units = units_max;
+    w.max_records = npad_max;
     size_t off = 0;
     w.rec_off = off;
     off = align256(off + (size_t)npad_max * adj_rec_bytes(law->kind, law->precision));
@@ -478,6 +484,10 @@ AdjBatWs adjb_layout(const nbody_law *law, int64_t n_total, int64_t S)
     off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
     w.poff_off = off;
     off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
+    w.systab_off = off;
+    off = align256(off + (size_t)std::max<int64_t>(S, 1) * 3 * sizeof(int64_t));
+    w.part_off = off;
+    off = align256(off + (size_t)w.max_slots * 128 * 8 * sizeof(double));
     w.ticket_off = off;
     off = align256(off + 256);
     w.total = off;
@@ -734,6 +744,42 @@ BatchPlan plan_batched(const int64_t *offsets, int64_t S, int ipl, int64_t j_uni
     return p;
 }
 
+// Plans depend only on (offsets, ipl, j_unit), and a simulation evaluates the
+// same ensemble step after step: the last few plans are kept (exact match of
+// the offsets, least recently used first out), so planning (a sort of all
+// units) is paid once per ensemble.
+struct CachedPlan {
+    std::vector<int64_t> offsets;
+    int ipl;
+    int64_t j_unit;
+    std::shared_ptr<const BatchPlan> plan;
+};
+std::mutex g_plan_mu;
+std::vector<CachedPlan> g_plans;     // most recently used last
+constexpr size_t kPlanCache = 8;
+
+std::shared_ptr<const BatchPlan> cached_plan(const int64_t *offsets, int64_t S, int ipl, int64_t j_unit)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        for (size_t k = 0; k < g_plans.size(); ++k) {
+            const CachedPlan &c = g_plans[k];
+            if (c.ipl == ipl && c.j_unit == j_unit && (int64_t)c.offsets.size() == S + 1 &&
+                std::equal(c.offsets.begin(), c.offsets.end(), offsets)) {
+                CachedPlan hit = c;
+                g_plans.erase(g_plans.begin() + (std::ptrdiff_t)k);
+                g_plans.push_back(hit);
+                return hit.plan;
+            }
+        }
+    }
+    auto plan = std::make_shared<const BatchPlan>(plan_batched(offsets, S, ipl, j_unit));
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    if (g_plans.size() >= kPlanCache) g_plans.erase(g_plans.begin());
+    g_plans.push_back({std::vector<int64_t>(offsets, offsets + S + 1), ipl, j_unit, plan});
+    return plan;
+}
+
 int g_num_cus = 0;
 
 int device_cus()
@@ -764,12 +810,13 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     }
     int64_t j_unit = round_up((int64_t)(work / (8.0 * (double)resident * 64.0 * c.ipl)) + 1, 64);
     j_unit = std::max(kMinJUnit, j_unit);
-    BatchPlan plan = plan_batched(offsets, S, c.ipl, j_unit);
+    std::shared_ptr<const BatchPlan> pp = cached_plan(offsets, S, c.ipl, j_unit);
     // the slot budget holds max_slots x 128 rows; a slot takes 64 x ipl rows
-    while (plan.n_slots * c.ipl > 2 * lay.max_slots) {
+    while (pp->n_slots * c.ipl > 2 * lay.max_slots) {
         j_unit *= 2;
-        plan = plan_batched(offsets, S, c.ipl, j_unit);
+        pp = cached_plan(offsets, S, c.ipl, j_unit);
     }
+    const BatchPlan &plan = *pp;
     if (plan.units.empty()) return NBODY_OK;
     // the plan must fit the workspace regions it is copied into
     if ((int64_t)plan.units.size() / 4 > lay.max_units || plan.npad_total > lay.max_records ||
@@ -1188,14 +1235,35 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     hipStream_t s = (hipStream_t)stream;
     const Cfg c = with_excl(choose(NBODY_API_BACKWARD_BATCHED, law, n, n_systems, false), excl != nullptr);
     const int ipl = std::min(c.ipl, 2);
-    const BatchPlan plan = plan_batched(offsets, n_systems, ipl, 0);
+    AdjBatchLaunch a{};
+    a.law = law->kind;
+    a.prec = law->precision;
+    a.ipl = ipl;
+    a.block = c.block;
+    a.j_stage = c.j_stage;
+    a.excl = excl_args(excl);
+    const int per_cu = std::max(1, adjoint_batched_blocks_per_cu(a));
+    const int64_t resident = (int64_t)device_cus() * per_cu * (c.block / 64);
+    double work = 0.0;
+    for (int64_t q = 0; q < n_systems; ++q) {
+        const int64_t ns = offsets[q + 1] - offsets[q];
+        work += (double)ns * (double)round_up(ns, 64);
+    }
+    int64_t j_unit = std::max(kMinJUnit, round_up((int64_t)(work / (8.0 * (double)resident * 64.0 * ipl)) + 1, 64));
+    std::shared_ptr<const BatchPlan> pp = cached_plan(offsets, n_systems, ipl, j_unit);
+    while (pp->n_slots * ipl > 2 * lay.max_slots) {
+        j_unit *= 2;
+        pp = cached_plan(offsets, n_systems, ipl, j_unit);
+    }
+    const BatchPlan &plan = *pp;
     if (plan.units.empty()) return NBODY_OK;
-    if ((int64_t)plan.units.size() / 4 > n / 64 + std::max<int64_t>(n_systems, 1) + 1)
-        return fail(NBODY_EWORKSPACE, "internal: batched adjoint plan exceeds its unit table");
+    if ((int64_t)plan.units.size() / 4 > lay.max_units || plan.npad_total > lay.max_records)
+        return fail(NBODY_EWORKSPACE, "internal: batched adjoint plan exceeds its workspace regions");
     char *base = (char *)ws;
     int32_t *d_units = (int32_t *)(base + lay.unit_off);
     int64_t *d_off = (int64_t *)(base + lay.off_off);
     int64_t *d_poff = (int64_t *)(base + lay.poff_off);
+    int64_t *d_systab = (int64_t *)(base + lay.systab_off);
     hipError_t e = hipMemcpyAsync(d_units, plan.units.data(), plan.units.size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -1203,13 +1271,10 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_poff, plan.poff.data(), (size_t)(n_systems + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_systab, plan.systab.data(), plan.systab.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "batched adjoint tables");
-    AdjBatchLaunch a{};
-    a.law = law->kind;
-    a.prec = law->precision;
-    a.ipl = ipl;
-    a.block = c.block;
-    a.j_stage = c.j_stage;
     a.j_tile = c.j_tile;
     a.n_units = (int64_t)plan.units.size() / 4;
     a.units = d_units;
@@ -1217,6 +1282,10 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     a.poff = d_poff;
     a.n_systems = n_systems;
     a.npad_total = plan.npad_total;
+    a.n_total = n;
+    a.systab = d_systab;
+    a.partial = (double *)(base + lay.part_off);
+    a.any_parts = plan.n_slots > 0;
     a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
     a.G = law->G;
     a.qscale = qscale_of(law);
@@ -1227,10 +1296,8 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     a.ticket = (int *)(base + lay.ticket_off);
     a.grad_pos = grad_pos;
     a.grad_params = grad_params;
-    a.excl = excl_args(excl);
     e = launch_pack_adjoint_batched(a, s);
     if (e != hipSuccess) return hip_fail(e, "batched adjoint pack");
-    const int per_cu = std::max(1, adjoint_batched_blocks_per_cu(a));
     const int64_t blocks_needed = (a.n_units + c.block / 64 - 1) / (c.block / 64);
     a.grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)device_cus() * per_cu, blocks_needed));
     Timer t(s);

@@ -128,9 +128,12 @@ struct AdjBatchLaunch {
     int j_stage;
     int j_tile;
     int64_t n_units;
-    const int32_t *units;        // [n_units][4] (system, row block, 0, 0)
+    const int32_t *units;        // [n_units][4] (system, row block, j part, 0)
     const int64_t *off, *poff;   // [S+1] caller rows and padded record offsets
-    int64_t n_systems, npad_total;
+    const int64_t *systab;       // [S][3] = (j parts P, records per part, first partial slot)
+    double *partial;             // [slots][64 * ipl][8] part sums of systems with P > 1
+    int any_parts;
+    int64_t n_systems, npad_total, n_total;
     double eps2, G, qscale;
     const double *pos, *params, *g;   // caller arrays (pack)
     void *rec;
