@@ -507,15 +507,17 @@ def flops_per_pair(api, law_kind, with_potential):
 
 # ---------------------------------------------------------------- autograd
 class NBodyForcesFn(torch.autograd.Function):
-    """F = forces(pos, params) with a hand-written adjoint (nbody_forces_backward).
+    """F = forces(pos, params) with a hand-written adjoint (nbody_forces_backward), optionally
+    with exclusion lists (LJC).
 
     Gradients: pos always; params for LJC(linear) (per-atom q, sigma, epsilon)."""
 
     @staticmethod
-    def forward(ctx, pos, params, law: Law):
-        f, _ = forces(pos, params, law, potential=False)
+    def forward(ctx, pos, params, law: Law, exclusions: Exclusions = None):
+        f, _ = forces(pos, params, law, potential=False, exclusions=exclusions)
         ctx.save_for_backward(pos, params)
         ctx.law = law
+        ctx.exclusions = exclusions
         return f
 
     @staticmethod
@@ -525,29 +527,61 @@ class NBodyForcesFn(torch.autograd.Function):
         need_pos = ctx.needs_input_grad[0]
         need_par = ctx.needs_input_grad[1] and law.kind == LJC_LINEAR
         gp, gq, _ = forces_backward(pos.detach(), params.detach(), grad_f.contiguous(), law,
-                                    want_pos=need_pos, want_params=need_par)
+                                    want_pos=need_pos, want_params=need_par,
+                                    exclusions=ctx.exclusions)
         if gq is not None:
             gq = gq.reshape(params.shape)
-        return gp, gq, None
+        return gp, gq, None, None
+
+
+class NBodyBatchedForcesFn(torch.autograd.Function):
+    """Forces of a batch of independent systems (rows offsets[s]..offsets[s+1]) in one
+    persistent launch, with the batched adjoint (nbody_forces_backward_batched) as backward;
+    optional exclusion lists over the concatenated rows."""
+
+    @staticmethod
+    def forward(ctx, pos, params, offsets, law: Law, exclusions: Exclusions = None):
+        f, _ = forces_batched(offsets, pos, params, law, potential=False, exclusions=exclusions)
+        ctx.save_for_backward(pos, params)
+        ctx.offsets = _host_offsets(offsets)
+        ctx.law = law
+        ctx.exclusions = exclusions
+        return f
+
+    @staticmethod
+    def backward(ctx, grad_f):
+        pos, params = ctx.saved_tensors
+        law = ctx.law
+        need_pos = ctx.needs_input_grad[0]
+        need_par = ctx.needs_input_grad[1] and law.kind == LJC_LINEAR
+        gp, gq, _ = forces_backward_batched(ctx.offsets, pos.detach(), params.detach(),
+                                            grad_f.contiguous(), law, want_pos=need_pos,
+                                            want_params=need_par, exclusions=ctx.exclusions)
+        if gq is not None:
+            gq = gq.reshape(params.shape)
+        return gp, gq, None, None, None
 
 
 class LJCTypedForcesFn(torch.autograd.Function):
-    """LJC(linear) forces with per-type sigma/epsilon tables; the per-type gradient
-    sums are reduced on the GPU in a fixed order."""
+    """LJC(linear) forces with per-type sigma/epsilon tables (optionally with exclusion lists);
+    the per-type gradient sums are reduced on the GPU in a fixed order."""
 
     @staticmethod
-    def forward(ctx, pos, q, sigma_t, eps_t, types, law: Law):
+    def forward(ctx, pos, q, sigma_t, eps_t, types, law: Law, exclusions: Exclusions = None):
         types = types.to(torch.int64)
         params = torch.stack([q, sigma_t[types], eps_t[types]], dim=1).contiguous()
-        f, _ = forces(pos, params, law, potential=False)
+        f, _ = forces(pos, params, law, potential=False, exclusions=exclusions)
         ctx.save_for_backward(pos, params, types)
         ctx.law = law
         ctx.n_types = sigma_t.shape[0]
+        ctx.exclusions = exclusions
         return f
 
     @staticmethod
     def backward(ctx, grad_f):
         pos, params, types = ctx.saved_tensors
         gp, gq, gt = forces_backward(pos, params, grad_f.contiguous(), ctx.law, want_pos=True,
-                                     want_params=True, types=types, n_types=ctx.n_types)
-        return gp, gq[:, 0].contiguous(), gt[:, 0].contiguous(), gt[:, 1].contiguous(), None, None
+                                     want_params=True, types=types, n_types=ctx.n_types,
+                                     exclusions=ctx.exclusions)
+        return (gp, gq[:, 0].contiguous(), gt[:, 0].contiguous(), gt[:, 1].contiguous(), None, None,
+                None)

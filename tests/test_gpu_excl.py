@@ -217,3 +217,38 @@ def test_batched_adjoint(nb, prec):
         ref = oracle.gravity_adjoint(x, mg[a:b], gg[a:b], eps=0.01)
         e = rel_rows(gpg[a:b], ref)
         assert np.median(e) <= tol_med and e.max() <= (1e-11 if prec == "fp64" else 1e-3), (s, e.max())
+
+
+def test_autograd_with_exclusions_and_batched(nb):
+    # gradcheck (FP64) of the exclusion-aware and the batched autograd Functions
+    sy, eo, ei = W.bonded_chains(2, 4, 71, box=9.0)
+    law = nb.ljc_linear("fp64")
+    excl = nb.Exclusions(dev(eo, torch.int64), dev(ei, torch.int64))
+    pos = dev(sy.pos).requires_grad_(True)
+    par = dev(sy.params()).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x, p: nb.NBodyForcesFn.apply(x, p, law, excl), (pos, par),
+                                    eps=1e-6, atol=1e-6, rtol=1e-6)
+    off, pos2, par2, _, geo, gei, _ = _bonded_ensemble([1, 0, 2], 81)
+    ex2 = nb.Exclusions(dev(geo, torch.int64), dev(gei, torch.int64))
+    x2 = dev(pos2).requires_grad_(True)
+    p2 = dev(par2).requires_grad_(True)
+    assert torch.autograd.gradcheck(lambda x, p: nb.NBodyBatchedForcesFn.apply(x, p, off, law, ex2),
+                                    (x2, p2), eps=1e-6, atol=1e-6, rtol=1e-6)
+    # typed force matching through the exclusion-aware Function equals the oracle's gradient
+    t = W.perturbed(sy, 5)
+    ft, _ = nb.forces(dev(sy.pos), dev(t.params()), law, exclusions=excl)
+    x3 = dev(sy.pos).requires_grad_(True)
+    q = dev(sy.q).requires_grad_(True)
+    st = dev(sy.sigma_t).requires_grad_(True)
+    et = dev(sy.eps_t).requires_grad_(True)
+    F = nb.LJCTypedForcesFn.apply(x3, q, st, et, dev(sy.types, torch.int32), law, excl)
+    ((F - ft) ** 2).sum().backward()
+    g = 2.0 * (host(F) - host(ft))
+    rp, rq, rs, re = oracle.ljc_adjoint_excl(sy.pos, sy.q, sy.sigma, sy.epsilon, g, eo, ei)
+    np.testing.assert_allclose(host(x3.grad), rp, rtol=1e-9, atol=1e-11 * np.abs(rp).max())
+    np.testing.assert_allclose(host(q.grad), rq, rtol=1e-9, atol=1e-11 * np.abs(rq).max())
+    for k in range(4):
+        sel = sy.types == k
+        if sel.any():
+            np.testing.assert_allclose(host(st.grad)[k], rs[sel].sum(), rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(host(et.grad)[k], re[sel].sum(), rtol=1e-9, atol=1e-12)
