@@ -19,7 +19,7 @@ each side autotuned), the position adjoint at N = 262,144 (FP32 vs FP64), and
 every pair law of Table 1 at N = 65,536, plus the acceleration-and-jerk kernel
 and the block-time-step Hermite integrator on a Plummer sphere of 65,536;
 bonded chains with exclusion lists (N = 8192) and the batched adjoint of the
-256-system ensemble.
+256-system ensemble; and the oracle timed in full on the small configurations.
 """
 from __future__ import annotations
 
@@ -204,6 +204,7 @@ def main():
         out["jerk"] = jerk_leg(nb, torch, dev, W)
         out["bonded"] = bonded_leg(nb, torch, dev, W, chains)
         out["batched_backward"] = batched_backward_leg(nb, torch, dev, ens)
+        out["oracle_configs"] = oracle_configs_leg(nb, torch, dev, W, ens, out)
     print(json.dumps(out), flush=True)
 
 
@@ -417,16 +418,14 @@ def jerk_leg(nb, torch, dev, W):
     T, DT = nb.hermite_block_init(A, J, 0.01, dt_max)
     e0 = energy()
     torch.cuda.synchronize()
-    counts = []
-    t_now = 0.0
     t = time.perf_counter()
-    while t_now < dt_max:               # one block step per call: stop exactly at t = dt_max
-        c, t_now = nb.hermite_block(X, V, A, J, T, DT, M, lawb, eta, dt_max, 1)
-        counts.append(int(c[0]))
+    # one call: block steps are enqueued without host waits and end exactly at t = dt_max
+    counts, t_now = nb.hermite_block(X, V, A, J, T, DT, M, lawb, eta, dt_max, 1 << 20, t_end=dt_max)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
     e1 = energy()
-    steps = np.asarray(counts)
+    steps = counts[counts > 0]
+    assert t_now == dt_max and bool(torch.all(T == dt_max)), "block steps did not reach t_end"
     pairs = float(steps.sum()) * n
     res["block_steps"] = {"law": "fp32_fp64acc", "eta": eta, "dt_max": dt_max, "t_end": t_now,
                           "block_steps": int(steps.size), "particle_steps": int(steps.sum()),
@@ -512,6 +511,55 @@ def batched_backward_leg(nb, torch, dev, ens):
            "batched_tflops": 68 * pairs / t_b / 1e12,
            "err_vs_fp64_per_system_median_max": max(med_sys), "err_vs_fp64_max": float(e.max())}
     log("batched backward:", res)
+    return res
+
+
+def oracle_configs_leg(nb, torch, dev, W, ens, out):
+    """The FP64 oracle, as it stands, timed in full on the host cores for the small
+    configurations (N = 4096 gravity forces; the t = 0 force evaluation at N = 65,536; the
+    N = 8192 MD forward and its force-matching adjoint; the 256-system ensemble), next to
+    the GPU path on the same work.  A different kind of baseline from the paper's
+    hand-vectorised CPU code: the plain double loop with compensated sums."""
+    import oracle
+    res = {"threads": oracle.threads(0)}
+
+    def clock(fn):
+        t = time.perf_counter()
+        fn()
+        return time.perf_counter() - t
+
+    def gpu(fn, reps=5):
+        return _time(torch, fn, reps=reps)
+
+    # config 1: gravity N = 4096, FP64
+    x1, _, m1 = W.plummer(4096, 1)
+    t_or = clock(lambda: oracle.gravity(x1, m1, eps=0.01))
+    X1, M1 = torch.tensor(x1, device=dev), torch.tensor(m1, device=dev)
+    t_gpu = gpu(lambda: nb.forces(X1, M1, nb.gravity("fp64", softening=0.01)))
+    res["gravity_4096_fp64"] = {"oracle_s": t_or, "gpu_s": t_gpu, "speedup": t_or / t_gpu}
+    # config 2 at t = 0: gravity N = 65536, FP32 + Kahan on the GPU
+    x2, _, m2 = W.plummer(65536, 2)
+    t_or = clock(lambda: oracle.gravity(x2, m2, eps=0.01))
+    X2, M2 = torch.tensor(x2, device=dev), torch.tensor(m2, device=dev)
+    t_gpu = gpu(lambda: nb.forces(X2, M2, nb.gravity("fp32_kahan", softening=0.01)))
+    res["gravity_65536_t0"] = {"oracle_s": t_or, "gpu_s": t_gpu, "speedup": t_or / t_gpu}
+    # config 3: MD N = 8192 (64 A box), forward and force-matching adjoint
+    s3 = W.md_system(8192, 3)
+    g3 = W.unit_cotangent(s3.n, 57)
+    t_f = clock(lambda: oracle.ljc_linear(s3.pos, s3.q, s3.sigma, s3.epsilon))
+    t_b = clock(lambda: oracle.ljc_adjoint(s3.pos, s3.q, s3.sigma, s3.epsilon, g3))
+    X3, P3, G3 = (torch.tensor(a, device=dev) for a in (s3.pos, s3.params(), g3))
+    law3 = nb.ljc_linear("fp32_fp64acc")
+    t_gf = gpu(lambda: nb.forces(X3, P3, law3))
+    t_gb = gpu(lambda: nb.forces_backward(X3, P3, G3, law3))
+    res["md_8192_forward"] = {"oracle_s": t_f, "gpu_s": t_gf, "speedup": t_f / t_gf}
+    res["md_8192_adjoint"] = {"oracle_s": t_b, "gpu_s": t_gb, "speedup": t_b / t_gb}
+    # config 4: the ensemble, one oracle call per system
+    off, pos, par, systems = ens
+    t_or = clock(lambda: [oracle.ljc_linear(sy.pos, sy.q, sy.sigma, sy.epsilon) for sy in systems])
+    t_gpu = out["batched"]["batched_fp32_kahan_ms"] * 1e-3
+    res["ensemble_256"] = {"oracle_s": t_or, "gpu_s": t_gpu, "speedup": t_or / t_gpu}
+    log("oracle on the configurations:", res)
     return res
 
 

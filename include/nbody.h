@@ -323,9 +323,9 @@ int hermite_step(double *pos, double *vel, double *acc, double *jerk, const doub
 int hermite_block_init(const double *acc, const double *jerk, int64_t n, double eta_s,
                        double dt_max, double *t_i, double *dt_i, void *stream);
 
-/* `nblocks` block steps of the Hermite scheme with individual block time
- * steps: the setting in which Section 3.4 evaluates forces on a subset of
- * the particles.  One block step:
+/* Up to `nblocks` block steps of the Hermite scheme with individual block
+ * time steps: the setting in which Section 3.4 evaluates forces on a subset
+ * of the particles.  One block step:
  *   t = min_i (t_i + dt_i); the due set A = { i : t_i + dt_i == t };
  *   every particle is predicted to t from its own t_i (predictor above);
  *   acceleration and jerk of each i in A against all predicted particles;
@@ -333,20 +333,28 @@ int hermite_block_init(const double *acc, const double *jerk, int64_t n, double 
  *     dt* = sqrt(eta (|a1| |a2'| + |j1|^2) / (|j1| |a3| + |a2'|^2)),
  *     a2' = a2 + a3 h (Aarseth's criterion), quantised to the largest
  *     dt_max / 2^k <= dt* that is at most 2 h and divides t.
+ * A block step whose time t would exceed t_end is not taken: it and every
+ * later one leave all state untouched (pass +Inf for no bound).
  *  pos, vel, acc, jerk [n][3], t_i, dt_i [n]: device, updated in place
  *    (t_i, dt_i from hermite_block_init or a previous call).
  *  mass [n] device; law as nbody_forces_jerk; eta > 0; dt_max as given to
- *    hermite_block_init (a power of two).
- *  active_counts host int64 [nblocks] or NULL: |A| of each block step.
- *  t_now host or NULL: the time of the last block step.
- * The scheduling (the next time and the due list, in increasing index order)
- * runs on the device; the call synchronises `stream` once per block step to
- * size the launches by |A|.
+ *    hermite_block_init (a power of two); t_end not NaN.
+ *  active_counts host int64 [nblocks] or NULL: |A| of each block step, 0 for
+ *    the steps not taken.
+ *  t_now host or NULL: the time of the last block step taken (left as it is
+ *    when none is).
+ * The scheduling (the next time, the due list in increasing index order and
+ * the j split for |A| rows) runs on the device, and the launches read |A|
+ * from device memory, so block steps are enqueued without waiting for one
+ * another.  The call reads the due counts back (one synchronisation of
+ * `stream` per batch of up to 1024 block steps, batches growing from 8) and
+ * returns once a step is not taken or nblocks steps are done.
  * Workspace: nbody_workspace_bytes(NBODY_API_HERMITE, n, 1, law). */
 int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, double *t_i,
                         double *dt_i, const double *mass, int64_t n, const nbody_law *law,
-                        double eta, double dt_max, int32_t nblocks, int64_t *active_counts,
-                        double *t_now, void *ws, size_t ws_bytes, void *stream);
+                        double eta, double dt_max, double t_end, int32_t nblocks,
+                        int64_t *active_counts, double *t_now, void *ws, size_t ws_bytes,
+                        void *stream);
 
 /* Workspace size in bytes needed by entry point `api` for `n_total`
  * particles in `n_systems` systems (1 for the single-system entry points).

@@ -97,7 +97,7 @@ def lib():
             "nbody_forces_jerk": ([P, P, P, I64, P, I64, LAW, P, P, P, P, SZ, P], ctypes.c_int),
             "hermite_step": ([P, P, P, P, P, I64, LAW, D, I32, P, SZ, P], ctypes.c_int),
             "hermite_block_init": ([P, P, I64, D, D, P, P, P], ctypes.c_int),
-            "hermite_block_steps": ([P, P, P, P, P, P, P, I64, LAW, D, D, I32, P, P, P, SZ, P],
+            "hermite_block_steps": ([P, P, P, P, P, P, P, I64, LAW, D, D, D, I32, P, P, P, SZ, P],
                                     ctypes.c_int),
             "nbody_autotune_jerk": ([P, P, P, I64, LAW, P, P, P, P, SZ, P, CFG,
                                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),

@@ -118,6 +118,7 @@ Cfg g_override[kNumApi];
 
 using TuneKey = std::tuple<int, int, int, int, int, int>;   // api, law, prec, pot, nbucket, sbucket
 std::map<TuneKey, std::pair<Cfg, double>> g_tuned;
+uint64_t g_cfg_version = 0;   // bumped (under g_mu) whenever an override or a tuned entry changes
 
 int size_bucket(int64_t n)
 {
@@ -376,9 +377,10 @@ AdjWs adj_layout(const nbody_law *law, int64_t n)
 // and, for the integrator, the new acceleration / jerk of the evaluated rows,
 // the due list and the scheduling scratch.
 constexpr int kSchedBlocks = 1024;
+constexpr int64_t kBlockLog = 1024;   // block steps enqueued between two host read-backs, at most
 
 struct JerkWs {
-    size_t rec_off, part_off, a1_off, j1_off, list_off, pmin_off, pcnt_off, out_off, total;
+    size_t rec_off, part_off, a1_off, j1_off, list_off, pmin_off, pcnt_off, out_off, log_off, table_off, total;
 };
 
 JerkWs jerk_layout(int api, const nbody_law *law, int64_t n)
@@ -403,7 +405,11 @@ JerkWs jerk_layout(int api, const nbody_law *law, int64_t n)
         w.pcnt_off = off;
         off = align256(off + (size_t)kSchedBlocks * sizeof(int64_t));
         w.out_off = off;
-        off = align256(off + 2 * sizeof(double));
+        off = align256(off + sizeof(BlockState));
+        w.log_off = off;
+        off = align256(off + (size_t)kBlockLog * (sizeof(int64_t) + sizeof(double)));
+        w.table_off = off;
+        off = align256(off + (size_t)(npad / 64) * sizeof(int));
     }
     w.total = off;
     return w;
@@ -1030,6 +1036,13 @@ std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
                 pick.push_back(sp);
             }
             if (std::find(pick.begin(), pick.end(), 1) == pick.end()) pick.push_back(1);
+            if (jerk && !splits.empty())
+                // the jerk kernel gains from more, shorter waves than the model
+                // predicts (measured): also try 2x and 4x its best split
+                for (int f : {2, 4}) {
+                    const int sp = std::min(splits[0] * f, max_split(npad));
+                    if (std::find(pick.begin(), pick.end(), sp) == pick.end()) pick.push_back(sp);
+                }
             for (int sp : pick) {
                 Cfg c;
                 c.ipl = ipl;
@@ -1041,6 +1054,81 @@ std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
             }
         }
     return out;
+}
+
+// The j split of the Hermite entry points' jerk evaluations, by the number of
+// rows evaluated: entry w is for (w + 1) row waves (64 ipl rows each) against
+// all n records.  The split_cost model's best over 1..64 and a geometric
+// ladder above (the kernel keeps few registers per wave, so it runs best with
+// every wave slot of the chip busy, and a due set of a few rows needs a split
+// of hundreds to fill them), held to at least 128 records a j part and to
+// what the partial buffer holds (max_split(npad) x npad rows); the entry for
+// all n rows is therefore at most max_split(npad).  A forced configuration's
+// split instead, held to the same bounds.  Built once per law, size, kernel
+// shape and configuration state.
+std::shared_ptr<const std::vector<int>> hermite_split_table(const nbody_law *law, int64_t n, const Cfg &c)
+{
+    using Key = std::tuple<int, int64_t, int, int, int, uint64_t>;
+    static std::mutex mu;
+    static std::vector<std::pair<Key, std::shared_ptr<const std::vector<int>>>> cache;   // most recent last
+    uint64_t ver;
+    int forced = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ver = g_cfg_version;
+        if (g_override_set[NBODY_API_HERMITE]) forced = g_override[NBODY_API_HERMITE].j_split;
+    }
+    const Key key(law->precision, n, c.ipl, c.block, c.j_stage, ver);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (size_t k = 0; k < cache.size(); ++k)
+            if (cache[k].first == key) {
+                auto hit = cache[k];
+                cache.erase(cache.begin() + (std::ptrdiff_t)k);
+                cache.push_back(hit);
+                return hit.second;
+            }
+    }
+    const int64_t npad = round_up(n, 64), rpw = 64 * c.ipl;
+    const int64_t cap = (int64_t)max_split(npad) * npad;
+    const int64_t smax_all = std::max<int64_t>(1, std::min<int64_t>(npad / 128, 1 << 20));
+    int64_t R = resident_waves_jerk(law->precision, c.ipl, false, c.j_stage, c.block);
+    if (R <= 0) R = kTargetWaves;
+    const double rate = nominal_rate(NBODY_LAW_GRAVITY, law->precision) * 0.5;
+    std::vector<int64_t> ladder;
+    for (int64_t s = 1; s <= smax_all; s = s < 64 ? s + 1 : (s * 9 + 7) / 8) ladder.push_back(s);
+    auto t = std::make_shared<std::vector<int>>((size_t)((n + rpw - 1) / rpw));
+    for (size_t w = 0; w < t->size(); ++w) {
+        const int64_t rw = (int64_t)w + 1;
+        const int64_t rows = std::min<int64_t>(n, rw * rpw);
+        const int64_t smax = std::max<int64_t>(1, std::min(smax_all, cap / round_up(rows, 64)));
+        int64_t best = 1;
+        if (forced > 0) {
+            best = std::min<int64_t>(forced, smax);
+        } else {
+            double best_t = 1e300;
+            for (size_t k = 0; k <= ladder.size(); ++k) {
+                const int64_t sp = k < ladder.size() ? ladder[k] : smax;   // and smax itself
+                if (sp > smax) continue;
+                const double tt = split_cost(rows, npad, rw, R, (int)sp, rate);
+                if (tt < best_t) {
+                    best_t = tt;
+                    best = sp;
+                }
+            }
+        }
+        (*t)[w] = (int)best;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache.size() >= 4) cache.erase(cache.begin());
+    cache.push_back({key, t});
+    return t;
+}
+
+bool power_of_two(double x)
+{
+    int e = 0;
+    return x > 0.0 && std::isfinite(x) && std::frexp(x, &e) == 0.5;
 }
 
 }  // namespace
@@ -1382,8 +1470,9 @@ int hermite_step(double *pos, double *vel, double *acc, double *jerk, const doub
     hipStream_t s = (hipStream_t)stream;
     char *base = (char *)ws;
     double *a1 = (double *)(base + lay.a1_off), *j1 = (double *)(base + lay.j1_off);
-    const Cfg c = sanitize(choose(NBODY_API_HERMITE, law, n, 1, false), NBODY_API_HERMITE, law->kind,
-                           law->precision, round_up(n, 64));
+    Cfg c = sanitize(choose(NBODY_API_HERMITE, law, n, 1, false, n), NBODY_API_HERMITE, law->kind,
+                     law->precision, round_up(n, 64));
+    c.j_split = hermite_split_table(law, n, c)->back();   // the block steps' rule for all n rows
     for (int32_t k = 0; k < nsteps; ++k) {
         JerkPackLaunch pk{};
         pk.n = n;
@@ -1411,12 +1500,6 @@ int hermite_step(double *pos, double *vel, double *acc, double *jerk, const doub
     return NBODY_OK;
 }
 
-bool power_of_two(double x)
-{
-    int e = 0;
-    return x > 0.0 && std::isfinite(x) && std::frexp(x, &e) == 0.5;
-}
-
 int hermite_block_init(const double *acc, const double *jerk, int64_t n, double eta_s, double dt_max,
                        double *t_i, double *dt_i, void *stream)
 {
@@ -1432,14 +1515,15 @@ int hermite_block_init(const double *acc, const double *jerk, int64_t n, double 
 
 int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, double *t_i,
                         double *dt_i, const double *mass, int64_t n, const nbody_law *law,
-                        double eta, double dt_max, int32_t nblocks, int64_t *active_counts,
-                        double *t_now, void *ws, size_t ws_bytes, void *stream)
+                        double eta, double dt_max, double t_end, int32_t nblocks,
+                        int64_t *active_counts, double *t_now, void *ws, size_t ws_bytes, void *stream)
 {
     int rc = validate_jerk_law(law);
     if (rc) return rc;
     if (n < 0 || nblocks < 0) return fail(NBODY_EINVAL, "n < 0 or nblocks < 0");
     if (!(eta > 0.0) || !std::isfinite(eta)) return fail(NBODY_EINVAL, "eta must be finite and > 0");
     if (!power_of_two(dt_max)) return fail(NBODY_EINVAL, "dt_max must be a power of two");
+    if (std::isnan(t_end)) return fail(NBODY_EINVAL, "t_end is NaN");
     if (n == 0 || nblocks == 0) return NBODY_OK;
     if (!pos || !vel || !acc || !jerk || !t_i || !dt_i || !mass)
         return fail(NBODY_EINVAL, "pos, vel, acc, jerk, t_i, dt_i and mass must be non-NULL");
@@ -1448,9 +1532,32 @@ int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, dou
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     char *base = (char *)ws;
-    double *a1 = (double *)(base + lay.a1_off), *j1 = (double *)(base + lay.j1_off);
+    const int64_t npad = round_up(n, 64);
+    // one kernel shape for every block step; the split follows the due count
+    const Cfg c = sanitize(choose(NBODY_API_HERMITE, law, n, 1, false, n), NBODY_API_HERMITE, law->kind,
+                           law->precision, npad);
+    const int rpw = 64 * c.ipl;
+    const std::shared_ptr<const std::vector<int>> table = hermite_split_table(law, n, c);
+    // launch sizes covering every entry: jerk waves (row waves x split) and the
+    // corrector's threads (rows x lanes per row of the split sum)
+    int64_t grid_waves = 0, corr_threads = n, smax = 1;
+    for (size_t w = 0; w < table->size(); ++w) {
+        const int64_t sp = (*table)[w], rows = std::min<int64_t>(n, (int64_t)(w + 1) * rpw);
+        grid_waves = std::max(grid_waves, (int64_t)(w + 1) * sp);
+        if (sp > 1) corr_threads = std::max(corr_threads, rows * split_group(sp));
+        smax = std::max(smax, sp);
+    }
+    const int64_t cap_rows = (int64_t)max_split(npad) * npad;
+    int *dtable = (int *)(base + lay.table_off);
+    hipError_t e = hipMemcpyAsync(dtable, table->data(), table->size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "split table upload");
+
+    BlockState *st = (BlockState *)(base + lay.out_off);
+    int64_t *clog = (int64_t *)(base + lay.log_off);
+    double *tlog = (double *)(clog + kBlockLog);
     int64_t *list = (int64_t *)(base + lay.list_off);
-    double *out = (double *)(base + lay.out_off);
+    double *a1 = (double *)(base + lay.a1_off), *j1 = (double *)(base + lay.j1_off);
+
     SchedLaunch sl{};
     sl.n = n;
     sl.nb = (int)std::min<int64_t>(kSchedBlocks, (n + 255) / 256);
@@ -1460,52 +1567,131 @@ int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, dou
     sl.part_min = (double *)(base + lay.pmin_off);
     sl.part_cnt = (int64_t *)(base + lay.pcnt_off);
     sl.list = list;
-    sl.out = out;
-    for (int32_t b = 0; b < nblocks; ++b) {
-        hipError_t e = launch_schedule(sl, s);
-        if (e != hipSuccess) return hip_fail(e, "block scheduling");
-        double host[2];
-        e = hipMemcpyAsync(host, out, sizeof host, hipMemcpyDeviceToHost, s);
+    sl.state = st;
+    sl.t_end = t_end;
+    sl.split_table = dtable;
+    sl.table_len = (int64_t)table->size();
+    sl.rows_per_wave = rpw;
+    sl.count_log = clog;
+    sl.time_log = tlog;
+    sl.fuse_pack = 1;
+
+    JerkPackLaunch pk{};
+    pk.prec = law->precision;
+    pk.n = n;
+    pk.npad = npad;
+    pk.pos = pos;
+    pk.vel = vel;
+    pk.mass = mass;
+    pk.predict = 1;
+    pk.acc = acc;
+    pk.jerk = jerk;
+    pk.t_i = t_i;
+    pk.t_pred_dev = &st->t;
+    pk.live_dev = &st->count;
+    pk.rec = base + lay.rec_off;
+    sl.pack = pk;
+
+    JerkLaunch a{};
+    a.prec = law->precision;
+    a.ipl = c.ipl;
+    a.pot = 0;
+    a.block = c.block;
+    a.j_stage = c.j_stage;
+    a.npad = npad;
+    a.nrows = n;
+    a.nrows_dev = &st->count;
+    a.rows = list;
+    a.j_split = (int)smax;
+    a.split_dev = &st->split;
+    a.grid_waves = grid_waves;
+    a.partial_rows = cap_rows;
+    a.j_tile = c.j_tile;
+    a.eps2 = law->softening * law->softening;
+    a.G = law->G;
+    a.rec = base + lay.rec_off;
+    a.partial = (double *)(base + lay.part_off);
+    a.out_acc = a1;
+    a.out_jerk = j1;
+    a.out_pot = nullptr;
+
+    HermiteLaunch h{};
+    h.nrows = n;
+    h.nrows_dev = &st->count;
+    h.rows = list;
+    h.pos = pos;
+    h.vel = vel;
+    h.acc = acc;
+    h.jerk = jerk;
+    h.a1 = a1;
+    h.j1 = j1;
+    h.t_i = t_i;
+    h.dt_i = dt_i;
+    h.t_next = &st->t;
+    h.eta = eta;
+    h.dt_max = dt_max;
+    h.partial = a.partial;        // the split sum is done by the corrector
+    h.split_dev = &st->split;
+    h.split_max = smax;
+    h.grid_threads = corr_threads;
+    h.partial_rows = cap_rows;
+    h.Gc = law->G;
+
+    // Enqueue batches of block steps and read their due counts back after each
+    // batch; a step that is not taken ends the call.  Batches double from 8 up
+    // to kBlockLog; with a finite t_end, once two step times are known, a batch
+    // is also held to a quarter more than the steps the rate so far predicts
+    // before t_end (steps past t_end cost their launches).
+    std::vector<int64_t> cnt;
+    std::vector<double> tim;
+    int32_t done = 0, taken = 0;
+    int64_t batch = 8;
+    double t_first = 0.0, t_last = 0.0;
+    bool ended = false;
+    while (done < nblocks && !ended) {
+        const int64_t nb = std::min<int64_t>(batch, (int64_t)nblocks - done);
+        for (int64_t k = 0; k < nb; ++k) {
+            sl.log_index = k;
+            e = launch_schedule(sl, s);      // due list, split and predicted records
+            if (e != hipSuccess) return hip_fail(e, "block scheduling");
+            Timer tm(s);
+            e = launch_jerk(a, s);
+            tm.stop();
+            if (e != hipSuccess) return hip_fail(e, "jerk kernel");
+            e = launch_hermite_correct(h, s);   // split sum + corrector
+            if (e != hipSuccess) return hip_fail(e, "Hermite corrector");
+        }
+        cnt.resize((size_t)nb);
+        tim.resize((size_t)nb);
+        e = hipMemcpyAsync(cnt.data(), clog, (size_t)nb * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(tim.data(), tlog, (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_fail(e, "block scheduling read-back");
-        const double t = host[0];
-        int64_t na = 0;
-        std::memcpy(&na, &host[1], sizeof na);
-        if (!(na >= 1 && na <= n) || !std::isfinite(t))
-            return fail(NBODY_EHIP, "block scheduling produced an invalid due set (%lld)", (long long)na);
-        if (active_counts) active_counts[b] = na;
-        if (t_now) *t_now = t;
-        const Cfg c = sanitize(choose(NBODY_API_HERMITE, law, na, 1, false, n), NBODY_API_HERMITE,
-                               law->kind, law->precision, round_up(n, 64));
-        JerkPackLaunch pk{};
-        pk.n = n;
-        pk.pos = pos;
-        pk.vel = vel;
-        pk.mass = mass;
-        pk.predict = 1;
-        pk.acc = acc;
-        pk.jerk = jerk;
-        pk.t_i = t_i;
-        pk.t_pred = t;
-        rc = run_jerk(law, c, pk, list, na, a1, j1, nullptr, ws, lay, s);
-        if (rc) return rc;
-        HermiteLaunch h{};
-        h.nrows = na;
-        h.rows = list;
-        h.pos = pos;
-        h.vel = vel;
-        h.acc = acc;
-        h.jerk = jerk;
-        h.a1 = a1;
-        h.j1 = j1;
-        h.t_i = t_i;
-        h.dt_i = dt_i;
-        h.t_next = out;
-        h.eta = eta;
-        h.dt_max = dt_max;
-        e = launch_hermite_correct(h, s);
-        if (e != hipSuccess) return hip_fail(e, "Hermite corrector");
+        if (e != hipSuccess) return hip_fail(e, "block-step read-back");
+        for (int64_t k = 0; k < nb; ++k) {
+            const int64_t na = cnt[(size_t)k];
+            // a step with nothing due must be one past t_end
+            if (na < 0 || na > n || (na > 0 && (ended || !std::isfinite(tim[(size_t)k]))) ||
+                (na == 0 && tim[(size_t)k] <= t_end))
+                return fail(NBODY_EHIP, "block scheduling produced an invalid due set (%lld)", (long long)na);
+            if (active_counts) active_counts[done + k] = na;
+            if (na == 0) {
+                ended = true;
+            } else {
+                if (taken++ == 0) t_first = tim[(size_t)k];
+                t_last = tim[(size_t)k];
+                if (t_now) *t_now = t_last;
+            }
+        }
+        done += (int32_t)nb;
+        batch = std::min<int64_t>(2 * batch, kBlockLog);
+        if (std::isfinite(t_end) && taken >= 2 && t_last > t_first) {
+            const double est = (double)(taken - 1) * (t_end - t_last) / (t_last - t_first);
+            batch = std::max<int64_t>(1, (int64_t)std::min<double>((double)batch, std::ceil(1.25 * est) + 1.0));
+        }
     }
+    if (active_counts)
+        for (int32_t b = done; b < nblocks; ++b) active_counts[b] = 0;
     return NBODY_OK;
 }
 
@@ -1562,6 +1748,7 @@ int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass
         std::lock_guard<std::mutex> lk(g_mu);
         g_tuned[TuneKey(NBODY_API_JERK, law->kind, law->precision, out_potential ? 1 : 0,
                         size_bucket(n), tune_sbucket(NBODY_API_JERK, 1, n))] = {best, best_ms};
+        ++g_cfg_version;
     }
     rc = jerk_impl(pos, vel, mass, n, nullptr, n, law, out_acc, out_jerk, out_potential, ws, ws_bytes,
                    stream, &best);
@@ -1577,11 +1764,13 @@ int nbody_set_config(int32_t api, const nbody_config *cfg)
     std::lock_guard<std::mutex> lk(g_mu);
     if (!cfg) {
         g_override_set[api] = false;
+        ++g_cfg_version;
         return NBODY_OK;
     }
     if (!cfg_valid(cfg)) return fail(NBODY_EINVAL, "configuration outside the documented ranges");
     g_override[api] = from_abi(cfg);
     g_override_set[api] = true;
+    ++g_cfg_version;
     return NBODY_OK;
 }
 
@@ -1591,6 +1780,14 @@ int nbody_get_config(int32_t api, int64_t n, int64_t n_systems, const nbody_law 
     int rc = validate_law(law, false);
     if (rc) return rc;
     if (!out || n < 0) return fail(NBODY_EINVAL, "bad arguments");
+    if (api == NBODY_API_HERMITE && n > 0 && law->kind == NBODY_LAW_GRAVITY &&
+        law->precision != NBODY_FP32_PLAIN) {
+        // the Hermite steps' kernel shape with their split rule for all n rows
+        Cfg c = sanitize(choose(api, law, n, 1, false, n), api, law->kind, law->precision, round_up(n, 64));
+        c.j_split = hermite_split_table(law, n, c)->back();
+        to_abi(c, out);
+        return NBODY_OK;
+    }
     to_abi(choose(api, law, n, std::max<int64_t>(n_systems, 1), true), out);
     return NBODY_OK;
 }
@@ -1660,6 +1857,7 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
         std::lock_guard<std::mutex> lk(g_mu);
         g_tuned[TuneKey(api, law->kind, law->precision, out_potential ? 1 : 0, size_bucket(ntot),
                         tune_sbucket(api, S, ntot))] = {best, best_ms};
+        ++g_cfg_version;
     }
     // leave the winner's result in the outputs
     rc = api == NBODY_API_FORCES
@@ -1721,6 +1919,7 @@ int nbody_tune_load(const char *path)
             if (cfg_valid(&cc) && api >= 0 && api < kNumApi) {
                 std::lock_guard<std::mutex> lk(g_mu);
                 g_tuned[TuneKey(api, law, prec, pot, nb, sb)] = {from_abi(&cc), ms};
+                ++g_cfg_version;
                 ++loaded;
             }
         }

@@ -255,9 +255,63 @@ struct NSum {
         s = t;
     }
     __device__ double value() const { return s + c; }
+    // add another compensated sum; commutative bit for bit, so both lanes of a
+    // butterfly pair end with the same (s, c)
+    __device__ void merge(double s2, double c2)
+    {
+#pragma clang fp contract(off)
+        const double t = s + s2;
+        const double e = (__builtin_fabs(s) >= __builtin_fabs(s2)) ? ((s - t) + s2) : ((s2 - t) + s);
+        c = (c + c2) + e;
+        s = t;
+    }
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Fixed-order sum of the nsplit partials of row r (part s at
+// partial + s * part_stride + r * width, NC columns) by a group of G lanes (G
+// a power of two <= 64, groups aligned in the wave): lane q of the group adds
+// parts q, q + G, q + 2G, ... in that order, then the group merges its lanes
+// over log2 G butterfly steps.  Every lane of the group ends with the same
+// sums.  All lanes of the wave must take part (lanes without a row pass
+// valid = false).
+template <int NC>
+__device__ __forceinline__ void split_group_sum(const double *__restrict__ partial, int64_t part_stride,
+                                                int width, int64_t r, bool valid, int64_t nsplit, int q,
+                                                int G, double (&out)[NC])
+{
+    NSum v[NC];
+    if (valid) {
+        // four parts' loads in flight before their adds (the adds keep the order)
+        int64_t s = q;
+        for (; s + 3 * G < nsplit; s += 4 * G) {
+            double x[4][NC];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) x[u][c] = partial[(s + u * G) * part_stride + r * width + c];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) v[c].add(x[u][c]);
+        }
+        for (; s < nsplit; s += G) {
+            const double *o = partial + s * part_stride + r * width;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) v[c].add(o[c]);
+        }
+    }
+    for (int m = 1; m < G; m <<= 1)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double s2 = __shfl_xor(v[c].s, m);
+            const double c2 = __shfl_xor(v[c].c, m);
+            v[c].merge(s2, c2);
+        }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = v[c].value();
+}
 
 // wave-uniform "any lane" (result lives in an SGPR)
 __device__ __forceinline__ bool wave_any(bool v) { return __any(v) != 0; }

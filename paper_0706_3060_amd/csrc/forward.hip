@@ -334,25 +334,27 @@ hipError_t launch_forces(const FwdLaunch &f, hipStream_t s)
 }
 
 // ------------------------------------------------- fixed-order split sum ----
+// split_group(j_split) lanes per row (split_group_sum: a fixed order for a
+// given split, so results repeat bit for bit)
 __global__ __launch_bounds__(256) void k_reduce_split(const double *__restrict__ partial,
                                                       int64_t nrows, int j_split, int pot,
                                                       Epilogue epi)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrows) return;
-    NSum v[4];
-    for (int s = 0; s < j_split; ++s) {
-        const double *o = partial + ((int64_t)s * nrows + r) * 4;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) v[c].add(o[c]);
-    }
-    finish_row(epi, r, v[0].value(), v[1].value(), v[2].value(), v[3].value(), pot != 0);
+    const int G = split_group(j_split);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((tid & ~int64_t(kWave - 1)) / G >= nrows) return;   // the whole wave is past the rows
+    const int64_t r = tid / G;
+    const int q = (int)(tid - r * G);
+    double v[4];
+    split_group_sum<4>(partial, nrows * 4, 4, r, r < nrows, j_split, q, G, v);
+    if (q == 0 && r < nrows) finish_row(epi, r, v[0], v[1], v[2], v[3], pot != 0);
 }
 
 hipError_t launch_reduce_split(const FwdLaunch &f, hipStream_t s)
 {
     if (f.nrows <= 0 || f.j_split <= 1) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((f.nrows + 255) / 256)), dim3(256), 0, s,
+    const int64_t threads = f.nrows * split_group(f.j_split);
+    hipLaunchKernelGGL(k_reduce_split, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s,
                        (const double *)f.partial, f.nrows, f.j_split, f.pot, f.epi);
     return hipGetLastError();
 }

@@ -102,11 +102,10 @@ __device__ __forceinline__ void predict(const double *x, const double *v, const 
     }
 }
 
+// record i of the (optionally predicted) state; padding records past n
 template <typename T>
-__global__ __launch_bounds__(256) void k_pack_jerk(JerkPackLaunch a)
+__device__ __forceinline__ void pack_record(const JerkPackLaunch &a, int64_t i)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.npad) return;
     GajRec<T> r;
     if (i >= a.n) {
         r.x = r.y = r.z = (T)kPadCoord;
@@ -116,7 +115,8 @@ __global__ __launch_bounds__(256) void k_pack_jerk(JerkPackLaunch a)
     }
     double x[3], v[3];
     if (a.predict) {
-        const double tau = a.t_i ? a.t_pred - a.t_i[i] : a.tau;
+        const double tp = a.t_pred_dev ? *a.t_pred_dev : a.t_pred;
+        const double tau = a.t_i ? tp - a.t_i[i] : a.tau;
         predict(a.pos + 3 * i, a.vel + 3 * i, a.acc + 3 * i, a.jerk + 3 * i, tau, x, v);
     } else {
 #pragma unroll
@@ -136,6 +136,15 @@ __global__ __launch_bounds__(256) void k_pack_jerk(JerkPackLaunch a)
     ((GajRec<T> *)a.rec)[i] = r;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_pack_jerk(JerkPackLaunch a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.npad) return;
+    if (a.live_dev && *a.live_dev <= 0) return;      // a block step with nothing due
+    pack_record<T>(a, i);
+}
+
 hipError_t launch_pack_jerk(const JerkPackLaunch &p, hipStream_t s)
 {
     if (p.npad <= 0) return hipSuccess;
@@ -146,6 +155,26 @@ hipError_t launch_pack_jerk(const JerkPackLaunch &p, hipStream_t s)
 }
 
 // --------------------------------------------------------------- all pairs ----
+// rows to evaluate and the split, fixed or read from device memory (clamped to
+// the bounds the grid and the partial buffer were sized for)
+__device__ __forceinline__ int64_t dev_rows(int64_t fixed, const int64_t *dev)
+{
+    if (!dev) return fixed;
+    const int64_t d = *dev;
+    return d < fixed ? (d > 0 ? d : 0) : fixed;
+}
+
+// (a device split is also held to what the partial buffer holds for nrows rows;
+// the jerk kernel and the kernel summing its partials apply the same clamp)
+__device__ __forceinline__ int64_t dev_split(int64_t bound, const int64_t *dev, int64_t cap_rows,
+                                             int64_t nrows)
+{
+    if (!dev) return bound;
+    if (cap_rows > 0 && nrows > 0 && cap_rows / nrows < bound) bound = cap_rows / nrows;
+    const int64_t d = *dev;
+    return d < 1 ? 1 : (d > bound ? bound : d);
+}
+
 __device__ __forceinline__ void jerk_finish(const JerkLaunch &a, int64_t r, const double *v, bool pot)
 {
     a.out_acc[3 * r] = a.G * v[0];
@@ -166,19 +195,30 @@ __global__ __launch_bounds__(256) void k_jerk(const GajRec<typename RealOf<PREC>
     using Op = JerkOp<POT>;
     constexpr int NC = Op::NC;
     const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
-                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nrows = dev_rows(a.nrows, a.nrows_dev);
+    int64_t part = blockIdx.y, split_len = a.split_len, nsplit = a.j_split;
+    if (a.split_dev) {
+        // 1-D grid: wave w takes row wave w % rw of j part w / rw, for the split
+        // the scheduler chose
+        const int64_t rw = (nrows + kWave * I - 1) / (kWave * I);
+        nsplit = dev_split(a.j_split, a.split_dev, a.partial_rows, nrows);
+        if (rw == 0 || wave >= rw * nsplit) return;
+        part = wave / rw;
+        wave -= part * rw;
+        split_len = ((a.npad + nsplit - 1) / nsplit + kWave - 1) / kWave * kWave;
+    }
     const int64_t rbase = wave * (int64_t)(kWave * I);
-    if (rbase >= a.nrows) return;
-    const int64_t jb = (int64_t)blockIdx.y * a.split_len;
-    const int64_t je = (jb + a.split_len < a.npad) ? jb + a.split_len : a.npad;
+    if (rbase >= nrows) return;
+    const int64_t jb = part * split_len;
+    const int64_t je = (jb + split_len < a.npad) ? jb + split_len : a.npad;
 
     GajI<T> is[I];
     int64_t pid[I];
 #pragma unroll
     for (int k = 0; k < I; ++k) {
         int64_t r = rbase + lane + (int64_t)kWave * k;
-        r = r < a.nrows ? r : a.nrows - 1;
+        r = r < nrows ? r : nrows - 1;
         int64_t q = a.rows ? a.rows[r] : r;
         q = q < 0 ? 0 : (q < a.npad ? q : a.npad - 1);     // never read outside the records
         pid[k] = q;
@@ -196,12 +236,12 @@ __global__ __launch_bounds__(256) void k_jerk(const GajRec<typename RealOf<PREC>
 #pragma unroll
     for (int k = 0; k < I; ++k) {
         const int64_t r = rbase + lane + (int64_t)kWave * k;
-        if (r >= a.nrows) continue;
+        if (r >= nrows) continue;
         double v[8];
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c] = acc[k][c].value();
-        if (a.j_split > 1) {
-            double *o = a.partial + ((int64_t)blockIdx.y * a.nrows + r) * 8;
+        if (nsplit > 1) {
+            double *o = a.partial + (part * nrows + r) * 8;
 #pragma unroll
             for (int c = 0; c < NC; ++c) o[c] = v[c];
         } else {
@@ -244,33 +284,46 @@ static bool jerk_prec(const JerkLaunch &a, dim3 grid, hipStream_t s)
 hipError_t launch_jerk(const JerkLaunch &a, hipStream_t s)
 {
     if (a.nrows <= 0) return hipSuccess;
-    const int64_t waves = (a.nrows + (int64_t)kWave * a.ipl - 1) / ((int64_t)kWave * a.ipl);
+    const int64_t waves = a.split_dev ? a.grid_waves
+                                      : (a.nrows + (int64_t)kWave * a.ipl - 1) / ((int64_t)kWave * a.ipl);
     const int64_t wpb = a.block / kWave;
-    const dim3 grid((unsigned)((waves + wpb - 1) / wpb), (unsigned)a.j_split);
+    if (waves <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((waves + wpb - 1) / wpb), a.split_dev ? 1u : (unsigned)a.j_split);
     const bool ok = a.pot ? jerk_prec<true>(a, grid, s) : jerk_prec<false>(a, grid, s);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
+// Fixed-order sum of the j-split partials, split_group(split) lanes per row.
+template <bool POT>
 __global__ __launch_bounds__(256) void k_jerk_reduce(JerkLaunch a)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.nrows) return;
-    const int nc = a.pot ? 7 : 6;
-    NSum v[7];
-    for (int s = 0; s < a.j_split; ++s) {
-        const double *o = a.partial + ((int64_t)s * a.nrows + r) * 8;
-        for (int c = 0; c < nc; ++c) v[c].add(o[c]);
+    const int64_t nrows = dev_rows(a.nrows, a.nrows_dev);
+    const int64_t nsplit = dev_split(a.j_split, a.split_dev, a.partial_rows, nrows);
+    if (nsplit <= 1) return;                         // the kernel wrote the rows itself
+    const int G = split_group(nsplit);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((tid & ~int64_t(kWave - 1)) / G >= nrows) return;
+    const int64_t r = tid / G;
+    const int q = (int)(tid - r * G);
+    constexpr int NC = POT ? 7 : 6;
+    double v[NC];
+    split_group_sum<NC>(a.partial, nrows * 8, 8, r, r < nrows, nsplit, q, G, v);
+    if (q == 0 && r < nrows) {
+        double w[8];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) w[c] = v[c];
+        jerk_finish(a, r, w, POT);
     }
-    double out[8];
-    for (int c = 0; c < nc; ++c) out[c] = v[c].value();
-    jerk_finish(a, r, out, a.pot != 0);
 }
 
 hipError_t launch_jerk_reduce(const JerkLaunch &a, hipStream_t s)
 {
     if (a.nrows <= 0 || a.j_split <= 1) return hipSuccess;
-    hipLaunchKernelGGL(k_jerk_reduce, dim3((unsigned)((a.nrows + 255) / 256)), dim3(256), 0, s, a);
+    const int64_t threads = a.nrows * split_group(a.j_split);
+    const dim3 grid((unsigned)((threads + 255) / 256));
+    if (a.pot) hipLaunchKernelGGL(k_jerk_reduce<true>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_jerk_reduce<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -340,19 +393,45 @@ __device__ __forceinline__ double norm3(const double *v)
 //   dt* = sqrt(eta (|a1| |a2 + a3 h| + |j1|^2) / (|j1| |a3| + |a2 + a3 h|^2))
 __global__ __launch_bounds__(256) void k_hermite_correct(HermiteLaunch a)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.nrows) return;
-    const int64_t i = a.rows ? a.rows[r] : r;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nrows = dev_rows(a.nrows, a.nrows_dev);
+    // with the split partials: first their fixed-order sum, split_group lanes a row
+    const int64_t nsplit = a.partial ? dev_split(a.split_max, a.split_dev, a.partial_rows, nrows) : 1;
+    const int G = nsplit > 1 ? split_group(nsplit) : 1;
+    if ((tid & ~int64_t(kWave - 1)) / G >= nrows) return;
+    const int64_t r = tid / G;
+    const int q = (int)(tid - r * G);
+    // the particle's state first (every lane of the group loads the same
+    // addresses), so that its loads overlap the split sum's
+    const int64_t i = r < nrows ? (a.rows ? a.rows[r] : r) : 0;
     const double h = a.dt_i ? a.dt_i[i] : a.h;
-    double xp[3], vp[3], a0[3], j0[3], a1[3], j1[3], a2[3], a3[3];
-    predict(a.pos + 3 * i, a.vel + 3 * i, a.acc + 3 * i, a.jerk + 3 * i, h, xp, vp);
+    double x0[3], v0[3], a0[3], j0[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+        x0[c] = a.pos[3 * i + c];
+        v0[c] = a.vel[3 * i + c];
         a0[c] = a.acc[3 * i + c];
         j0[c] = a.jerk[3 * i + c];
-        a1[c] = a.a1[3 * r + c];
-        j1[c] = a.j1[3 * r + c];
     }
+    double a1[3], j1[3];
+    if (nsplit > 1) {
+        double v[6];
+        split_group_sum<6>(a.partial, nrows * 8, 8, r, r < nrows, nsplit, q, G, v);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a1[c] = a.Gc * v[c];
+            j1[c] = a.Gc * v[3 + c];
+        }
+    }
+    if (q != 0 || r >= nrows) return;
+    if (nsplit <= 1)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a1[c] = a.a1[3 * r + c];
+            j1[c] = a.j1[3 * r + c];
+        }
+    double xp[3], vp[3], a2[3], a3[3];
+    predict(x0, v0, a0, j0, h, xp, vp);
     const double h2 = h * h, h3 = h2 * h;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -379,7 +458,8 @@ __global__ __launch_bounds__(256) void k_hermite_correct(HermiteLaunch a)
 hipError_t launch_hermite_correct(const HermiteLaunch &a, hipStream_t s)
 {
     if (a.nrows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hermite_correct, dim3((unsigned)((a.nrows + 255) / 256)), dim3(256), 0, s, a);
+    const int64_t threads = a.partial ? a.grid_threads : a.nrows;
+    hipLaunchKernelGGL(k_hermite_correct, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -463,19 +543,22 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched_count(SchedLaunch a)
     const int64_t b0 = (int64_t)blockIdx.x * a.chunk;
     const int64_t b1 = b0 + a.chunk < a.n ? b0 + a.chunk : a.n;
     int64_t c = 0;
-    for (int64_t i = b0 + threadIdx.x; i < b1; i += kSchedThreads) c += (a.t_i[i] + a.dt_i[i] == t) ? 1 : 0;
+    if (t <= a.t_end)        // past t_end nothing is due: the block step is a no-op
+        for (int64_t i = b0 + threadIdx.x; i < b1; i += kSchedThreads) c += (a.t_i[i] + a.dt_i[i] == t) ? 1 : 0;
     c = block_sum(c, sc);
     if (threadIdx.x == 0) {
         a.part_cnt[blockIdx.x] = c;
-        if (blockIdx.x == 0) a.out[0] = t;
+        if (blockIdx.x == 0) a.state->t = t;
     }
 }
 
+template <typename T, bool PACK>
 __global__ __launch_bounds__(kSchedThreads) void k_sched_write(SchedLaunch a)
 {
     __shared__ int64_t sc[kSchedThreads];
     __shared__ int64_t flag[kSchedThreads];
-    const double t = a.out[0];
+    const double t = a.state->t;
+    const bool live = t <= a.t_end;
     int64_t before = 0;
     for (int k = threadIdx.x; k < (int)blockIdx.x; k += kSchedThreads) before += a.part_cnt[k];
     int64_t base = block_sum(before, sc);
@@ -483,7 +566,7 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched_write(SchedLaunch a)
     const int64_t b1 = b0 + a.chunk < a.n ? b0 + a.chunk : a.n;
     for (int64_t g = b0; g < b1; g += kSchedThreads) {
         const int64_t i = g + threadIdx.x;
-        const int64_t f = (i < b1 && a.t_i[i] + a.dt_i[i] == t) ? 1 : 0;
+        const int64_t f = (live && i < b1 && a.t_i[i] + a.dt_i[i] == t) ? 1 : 0;
         // inclusive scan of the flags (Hillis-Steele over the block)
         flag[threadIdx.x] = f;
         __syncthreads();
@@ -497,9 +580,25 @@ __global__ __launch_bounds__(kSchedThreads) void k_sched_write(SchedLaunch a)
         base += flag[kSchedThreads - 1];
         __syncthreads();
     }
+    if (PACK && live) {
+        // the records of this block's particles predicted to t (and the padding)
+        for (int64_t i = b0 + threadIdx.x; i < b1; i += kSchedThreads) pack_record<T>(a.pack, i);
+        if (blockIdx.x == gridDim.x - 1)
+            for (int64_t i = a.n + threadIdx.x; i < a.pack.npad; i += kSchedThreads) pack_record<T>(a.pack, i);
+    }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-        int64_t *cnt = reinterpret_cast<int64_t *>(a.out + 1);
-        cnt[0] = base;
+        int64_t split = 1;
+        if (a.split_table && a.table_len > 0 && base > 0) {
+            int64_t rw = (base + a.rows_per_wave - 1) / a.rows_per_wave;
+            rw = rw < a.table_len ? rw : a.table_len;
+            split = a.split_table[rw - 1];
+        }
+        a.state->count = base;
+        a.state->split = split;
+        if (a.count_log) {
+            a.count_log[a.log_index] = base;
+            a.time_log[a.log_index] = t;
+        }
     }
 }
 
@@ -508,7 +607,12 @@ hipError_t launch_schedule(const SchedLaunch &a, hipStream_t s)
     if (a.n <= 0 || a.nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sched_min, dim3((unsigned)a.nb), dim3(kSchedThreads), 0, s, a);
     hipLaunchKernelGGL(k_sched_count, dim3((unsigned)a.nb), dim3(kSchedThreads), 0, s, a);
-    hipLaunchKernelGGL(k_sched_write, dim3((unsigned)a.nb), dim3(kSchedThreads), 0, s, a);
+    if (!a.fuse_pack)
+        hipLaunchKernelGGL((k_sched_write<double, false>), dim3((unsigned)a.nb), dim3(kSchedThreads), 0, s, a);
+    else if (a.pack.prec != P_FP64)
+        hipLaunchKernelGGL((k_sched_write<float, true>), dim3((unsigned)a.nb), dim3(kSchedThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_sched_write<double, true>), dim3((unsigned)a.nb), dim3(kSchedThreads), 0, s, a);
     return hipGetLastError();
 }
 

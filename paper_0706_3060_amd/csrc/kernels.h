@@ -7,6 +7,15 @@
 
 namespace nbk {
 
+// Lanes per row of a fixed-order split reduction: the smallest power of two
+// >= nsplit, at most 64 (shared by the launchers and the kernels).
+__host__ __device__ inline int split_group(int64_t nsplit)
+{
+    int g = 1;
+    while (g < 64 && g < nsplit) g <<= 1;
+    return g;
+}
+
 // Per-particle exclusion lists (CSR over the caller's particle indices):
 // particle x excludes idx[off[x] .. off[x+1]) (ranges clamped to [0, count)).
 // off == nullptr: no exclusions.
@@ -167,6 +176,8 @@ struct JerkPackLaunch {
     const double *acc, *jerk;         // [n][3] (predict)
     const double *t_i;                // [n] per-particle times, or null: tau for every particle
     double t_pred;                    // prediction time (with t_i)
+    const double *t_pred_dev;         // or the prediction time in device memory (with t_i)
+    const int64_t *live_dev;          // or null: when set and zero, the pack is skipped
     double tau;                       // prediction interval (without t_i)
     void *rec;                        // GajRec records [npad]
 };
@@ -174,10 +185,14 @@ struct JerkLaunch {
     int prec, ipl, pot;
     int block, j_stage;
     int64_t npad;
-    int64_t nrows;
+    int64_t nrows;                    // rows (the grid is sized for this many)
+    const int64_t *nrows_dev;         // or, when set, the rows to evaluate (<= nrows) in device memory
     const int64_t *rows;              // row -> particle, or null (identity)
     int64_t split_len;
-    int j_split, j_tile;
+    int j_split, j_tile;              // j_split: the split, or its upper bound with split_dev
+    const int64_t *split_dev;         // or, when set, the split in device memory (1-D grid)
+    int64_t grid_waves;               // with split_dev: waves launched (>= row waves x split)
+    int64_t partial_rows;             // with split_dev: partial buffer capacity in rows (split x rows)
     double eps2, G;
     const void *rec;
     double *partial;                  // [j_split][nrows][8] when j_split > 1
@@ -185,7 +200,8 @@ struct JerkLaunch {
     double *out_pot;                  // [nrows] or null
 };
 struct HermiteLaunch {
-    int64_t nrows;
+    int64_t nrows;                    // grid size in rows
+    const int64_t *nrows_dev;         // or, when set, the rows to correct (<= nrows) in device memory
     const int64_t *rows;              // active particles, or null (all)
     double *pos, *vel, *acc, *jerk;   // [n][3], updated for the rows
     const double *a1, *j1;            // [nrows][3] at the predicted state, in row order
@@ -193,6 +209,22 @@ struct HermiteLaunch {
     double *t_i, *dt_i;               // block steps: per-particle time and step, or null
     const double *t_next;             // block steps: device scalar, the block time
     double eta, dt_max;
+    // or, when partial is set, a1 / j1 are G x the fixed-order sum of the j-split
+    // partials [split][nrows][8] (split from split_dev, at most split_max; with a
+    // split of 1 they are read from a1 / j1); the grid then has grid_threads threads
+    const double *partial;
+    const int64_t *split_dev;
+    int64_t split_max, grid_threads;
+    int64_t partial_rows;             // capacity clamp, as JerkLaunch::partial_rows
+    double Gc;
+};
+// State of one block step, written by the scheduler and read by the kernels
+// that follow it on the stream.
+struct BlockState {
+    double t;                         // block time: the smallest t_i + dt_i
+    int64_t count;                    // due particles (0 past t_end)
+    int64_t split;                    // j split of the jerk evaluation of the due rows
+    int64_t pad;
 };
 struct SchedLaunch {
     int64_t n, chunk;
@@ -201,7 +233,16 @@ struct SchedLaunch {
     double *part_min;                 // [nb]
     int64_t *part_cnt;                // [nb]
     int64_t *list;                    // [n] due particles, increasing
-    double *out;                      // out[0] = t_next, out[1] holds the due count (int64)
+    BlockState *state;
+    double t_end;                     // a block time beyond t_end has no due particles
+    const int *split_table;           // [table_len]: split for 1.. row waves of due rows, or null (1)
+    int64_t table_len;
+    int rows_per_wave;
+    int64_t *count_log;               // [log] due counts of successive block steps, or null
+    double *time_log;                 // [log] their block times
+    int64_t log_index;
+    int fuse_pack;                    // also write the predicted records of the block step
+    JerkPackLaunch pack;              // (t_pred_dev = &state->t, pack.n == n)
 };
 hipError_t launch_pack_jerk(const JerkPackLaunch &p, hipStream_t s);
 hipError_t launch_jerk(const JerkLaunch &a, hipStream_t s);

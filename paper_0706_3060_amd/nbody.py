@@ -17,6 +17,7 @@ step) and hermite_block (Hermite with block individual steps).
 from __future__ import annotations
 
 import ctypes
+import math
 from dataclasses import dataclass
 
 import numpy as np
@@ -392,10 +393,12 @@ def hermite_block_init(acc, jerk, eta_s: float, dt_max: float):
 
 
 def hermite_block(pos, vel, acc, jerk, t_i, dt_i, mass, law: Law, eta: float, dt_max: float,
-                  nblocks: int):
-    """nblocks block steps of the individual-step Hermite scheme, updating pos, vel,
-    acc, jerk, t_i, dt_i IN PLACE.  Returns (active counts per block step [nblocks]
-    int64 numpy array, time of the last block step)."""
+                  nblocks: int, t_end: float = math.inf):
+    """Up to nblocks block steps of the individual-step Hermite scheme, updating
+    pos, vel, acc, jerk, t_i, dt_i IN PLACE; a block step whose time would pass
+    t_end is not taken, nor is any after it.  Returns (due count of each block step
+    [nblocks] int64 numpy array, 0 for steps not taken; time of the last block step
+    taken, or nan if none was)."""
     n = pos.shape[0]
     for t, name in ((pos, "pos"), (vel, "vel"), (acc, "acc"), (jerk, "jerk")):
         _vec3(t, n, name)
@@ -405,11 +408,11 @@ def hermite_block(pos, vel, acc, jerk, t_i, dt_i, mass, law: Law, eta: float, dt
             raise ValueError("%s must be a contiguous float64 GPU tensor of shape (%d,)" % (name, n))
     m = _dev_f64(mass, (n,), "mass", pos.device)
     counts = np.zeros(max(int(nblocks), 1), dtype=np.int64)
-    t_now = ctypes.c_double(0.0)
+    t_now = ctypes.c_double(math.nan)
     ws = workspace(API_HERMITE, n, 1, law, pos.device)
     N.check(N.lib().hermite_block_steps(_ptr(pos), _ptr(vel), _ptr(acc), _ptr(jerk), _ptr(t_i),
                                         _ptr(dt_i), _ptr(m), n, ctypes.byref(law.c()), float(eta),
-                                        float(dt_max), int(nblocks),
+                                        float(dt_max), float(t_end), int(nblocks),
                                         counts.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t_now),
                                         _ptr(ws), ws.numel(), _stream(pos.device)))
     return counts[:int(nblocks)], t_now.value

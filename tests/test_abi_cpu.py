@@ -214,14 +214,15 @@ def test_jerk_and_hermite_validation(N):
     assert lib.hermite_block_init(fake(), fake(), 10, -1.0, 0.125, fake(), fake(), None) == N.NBODY_EINVAL
     assert lib.hermite_block_init(None, None, 0, 0.01, 0.125, None, None, None) == 0
 
-    def block(eta=0.02, dt_max=0.125, nb=3, lw=g, ws_bytes=1 << 30):
+    def block(eta=0.02, dt_max=0.125, nb=3, lw=g, ws_bytes=1 << 30, t_end=float("inf")):
         return lib.hermite_block_steps(fake(), fake(), fake(), fake(), fake(), fake(), fake(), 10,
-                                       ctypes.byref(lw), eta, dt_max, nb, None, None, fake(),
+                                       ctypes.byref(lw), eta, dt_max, t_end, nb, None, None, fake(),
                                        ws_bytes, None)
 
     assert block(eta=0.0) == N.NBODY_EINVAL
     assert block(dt_max=0.3) == N.NBODY_EINVAL
     assert block(nb=-1) == N.NBODY_EINVAL
+    assert block(t_end=float("nan")) == N.NBODY_EINVAL
     assert block(lw=lj) == N.NBODY_ENOTSUP
     assert block(ws_bytes=1024) == N.NBODY_EWORKSPACE
     assert block(nb=0) == 0

@@ -185,3 +185,53 @@ def test_block_steps_fp32_energy(nb):
     assert t_now == dt_max and torch.all(T == dt_max)
     assert total > 2048                                     # several block steps
     assert abs(energy(host(X), host(V)) - e0) < 1e-6 * abs(e0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan"])
+def test_block_steps_stop_at_t_end(nb, prec):
+    """Block steps enqueued in one call stop exactly at t_end; the result equals
+    one block step per call bitwise, and (FP64) the oracle's schedule."""
+    x, v, m = W.plummer(1500, 19)
+    eta_s, eta, dt_max = 0.01, 0.02, 1.0 / 32
+    law = nb.gravity(prec, softening=EPS)
+    a0, j0, _ = oracle.gravity_jerk(x, v, m, eps=EPS)
+
+    def fresh():
+        s = [dev(x), dev(v), dev(a0), dev(j0)]
+        return s + list(nb.hermite_block_init(s[2], s[3], eta_s, dt_max))
+
+    one = fresh()
+    counts, t_now = nb.hermite_block(*one, dev(m), law, eta, dt_max, 100000, t_end=dt_max)
+    k = int((counts > 0).sum())
+    assert k > 24 and np.all(counts[:k] > 0) and np.all(counts[k:] == 0)   # read-back batches 8, 16, 32
+    assert t_now == dt_max and torch.all(one[4] == dt_max)
+
+    loop = fresh()
+    per_call = []
+    while True:
+        c, tn = nb.hermite_block(*loop, dev(m), law, eta, dt_max, 1, t_end=dt_max)
+        if c[0] == 0:
+            assert np.isnan(tn)                                   # nothing taken: t_now untouched
+            break
+        per_call.append(int(c[0]))
+    np.testing.assert_array_equal(counts[:k], per_call)
+    for a, b in zip(one, loop):
+        assert torch.equal(a, b)
+
+    if prec == "fp64":
+        t_r, dt_r = oracle.hermite_block_init(a0, j0, eta_s, dt_max)
+        xr, vr, ar, jr, tr, dtr, cr, tnr = oracle.hermite_block(x, v, a0, j0, t_r, dt_r, m, k, eta,
+                                                                dt_max, eps=EPS)
+        np.testing.assert_array_equal(counts[:k], cr)
+        assert tnr == dt_max
+        np.testing.assert_array_equal(host(one[4]), tr)
+        np.testing.assert_array_equal(host(one[5]), dtr)
+        assert np.abs(host(one[0]) - xr).max() <= 1e-12 * np.abs(xr).max()
+        assert np.abs(host(one[1]) - vr).max() <= 1e-12 * np.abs(vr).max()
+
+    # past t_end nothing more is taken and nothing changes
+    before = [t.clone() for t in one]
+    c, tn = nb.hermite_block(*one, dev(m), law, eta, dt_max, 20, t_end=dt_max)
+    assert np.all(c == 0) and np.isnan(tn)
+    for a, b in zip(one, before):
+        assert torch.equal(a, b)
