@@ -59,7 +59,14 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic configuration")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target host time of the oracle sample")
+    ap.add_argument("--make-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
+                    help="no GPU work: write the traffic record of the headline kernel from the "
+                         "counter CSVs of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "'bench.py --legs main' and the JSON line one of them printed")
     args = ap.parse_args()
+    if args.make_traffic:
+        make_traffic(*args.make_traffic)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -206,6 +213,60 @@ def main():
         out["batched_backward"] = batched_backward_leg(nb, torch, dev, ens)
         out["oracle_configs"] = oracle_configs_leg(nb, torch, dev, W, ens, out)
     print(json.dumps(out), flush=True)
+
+
+TRAFFIC_SOURCES = ["paper_0706_3060_amd/csrc/forward.hip", "paper_0706_3060_amd/csrc/device.h",
+                   "paper_0706_3060_amd/csrc/allpairs.h", "paper_0706_3060_amd/csrc/kernels.h"]
+
+
+def make_traffic(fetch_csv, write_csv, bench_json):
+    """Traffic record of the timed all-pairs launch: the mean FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) of its launches in the counter runs, each scaled by bytes moved /
+    counter reading of the 256 MiB calibration copy the bench makes first, with a hash
+    of the kernel sources and the launch configuration they were taken on."""
+    import csv
+    import hashlib
+    import re
+    import statistics
+    line = [ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1]
+    cfg_run = json.loads(line)["config"]
+    n, cfg = cfg_run["n"], cfg_run["launch"]
+    waves = -(-n // (64 * cfg["i_per_lane"]))
+    wpb = cfg["block"] // 64
+    grid = str(-(-waves // wpb) * cfg["block"] * cfg["j_split"])
+    name = "k_forces<0, 1, %d, true, %d>" % (cfg["i_per_lane"], cfg["j_stage"])
+    copy_bytes = 256 << 20
+    copy_grid = "131072"                        # the grid rocprofv3 reports for the 256 MiB copy
+
+    def vals(path, counter, pred):
+        out = []
+        for r in csv.DictReader(open(path)):
+            kn = re.sub(r"\(.*", "", r["Kernel_Name"])
+            if r["Counter_Name"] == counter and pred(kn, r["Grid_Size"]):
+                out.append(float(r["Counter_Value"]))
+        return out
+
+    f = vals(fetch_csv, "FETCH_SIZE", lambda k, g: name in k and g == grid)
+    w = vals(write_csv, "WRITE_SIZE", lambda k, g: name in k and g == grid)
+    cf = vals(fetch_csv, "FETCH_SIZE", lambda k, g: "copyBuffer" in k and g == copy_grid)
+    cw = vals(write_csv, "WRITE_SIZE", lambda k, g: "copyBuffer" in k and g == copy_grid)
+    if not (f and w and cf and cw):
+        raise SystemExit("counter rows not found (kernel %s grid %s, copy grid %s)" % (name, grid, copy_grid))
+    fs, ws = copy_bytes / 1024 / cf[0], copy_bytes / 1024 / cw[0]
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in TRAFFIC_SOURCES)).hexdigest()
+    fk, wk = statistics.mean(f), statistics.mean(w)
+    rec = {"kernel": name,
+           "workload": "gravity N=%d FP32+Kahan with potential, block %d, i_per_lane %d, j_tile %d, "
+                       "j_split %d, j_stage %d" % (n, cfg["block"], cfg["i_per_lane"], cfg["j_tile"],
+                                                  cfg["j_split"], cfg["j_stage"]),
+           "sources": TRAFFIC_SOURCES, "sources_sha256": h, "dispatches": len(f),
+           "fetch_kib": fk, "write_kib": wk, "copy_fetch_kib": cf[0], "copy_write_kib": cw[0],
+           "copy_bytes": copy_bytes, "fetch_scale": fs, "write_scale": ws,
+           "bytes_per_launch": fk * 1024 * fs + wk * 1024 * ws, "config": cfg, "n": n}
+    path = os.path.join(ROOT, "profiles", "traffic_k_forces_gravity_fp32kahan_n%d.json" % n)
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
 
 
 def measured_traffic(n, cfg):

@@ -1036,9 +1036,11 @@ std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
                 pick.push_back(sp);
             }
             if (std::find(pick.begin(), pick.end(), 1) == pick.end()) pick.push_back(1);
-            if (jerk && !splits.empty())
-                // the jerk kernel gains from more, shorter waves than the model
-                // predicts (measured): also try 2x and 4x its best split
+            if ((jerk || n <= (int64_t(1) << 18)) && !splits.empty())
+                // the jerk kernel, and the forces kernels below a few hundred
+                // thousand rows, gain from more, shorter waves than the model
+                // predicts (the last round's imbalance shrinks; measured): also
+                // try 2x and 4x its best split
                 for (int f : {2, 4}) {
                     const int sp = std::min(splits[0] * f, max_split(npad));
                     if (std::find(pick.begin(), pick.end(), sp) == pick.end()) pick.push_back(sp);
