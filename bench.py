@@ -149,6 +149,19 @@ def main():
     log("step %.3f ms, %.1f G pairs/s; all-pairs kernel %.3f ms/launch over %d launches, %.2f TFLOP/s"
         % (ms_step, value, k_ms / max(k_launches, 1), k_launches, achieved))
 
+    # issue-rate ceiling of the gravity pair sequence, measured on this GPU: per
+    # pair-wave, 13 ordinary FP32 VALU instructions and one v_rsq_f32 carry 20 flops a
+    # lane, against 64 flops per SIMD-cycle at peak (157.3 TFLOP/s is that at 2.4 GHz).
+    # The clock under the pair kernel is not visible here: clock_for_kernel_ghz is the
+    # clock at which the measured launch time equals the modelled cycles.
+    rates = nb.probe_issue_rates(dev)
+    pair_cycles = 13 * rates["fma_cycles"] + rates["rsq_cycles"]
+    pair_waves_per_simd = pairs / 64.0 / (4 * props.multi_processor_count)
+    ceiling = {"probe": rates, "pair_wave_cycles_model": pair_cycles,
+               "cap_frac_of_clock_peak": 20.0 / pair_cycles,
+               "clock_for_kernel_ghz": pair_cycles * pair_waves_per_simd / k_avg_s / 1e9}
+    log("ceiling:", ceiling)
+
     # oracle on a row sample of the same (t = 0) workload, same FP32-rounded inputs
     import oracle
     rng = np.random.default_rng(55)
@@ -197,6 +210,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel_ms": k_ms / max(k_launches, 1), "launches": k_launches},
+        "ceiling": ceiling,
         "cpu_baseline": {"value": cpu_value, "unit": "G pair-interactions/s", "cores": threads,
                          "kind": "oracle",
                          "sample": "%d random rows of the N=%d Plummer workload against all N "

@@ -419,6 +419,23 @@ int32_t nbody_flops_per_pair(int32_t api, int32_t law_kind, int32_t with_potenti
 /* Library version string. */
 const char *nbody_version(void);
 
+/* ---- issue-rate probes (measurement support for the roofline; not part of
+ * the force path) ---- */
+
+/* Device workspace bytes nbody_probe_issue_rates needs. */
+size_t nbody_probe_workspace_bytes(void);
+
+/* Measure, on the current device, the shader cycles a SIMD spends per wave64
+ * instruction: out[0] FP32 FMA with all operands in VGPRs, out[1] FP32 FMA
+ * with one SGPR operand, out[2] v_rsq_f32; out[3] the shader clock in GHz
+ * while the FMA probe runs (shader-cycle counter over the fixed-rate wall
+ * counter); out[4] that wall counter's rate in MHz.  Each probe's cycles are
+ * taken at its own measured clock.  Each probe runs eight independent chains
+ * per lane with eight waves per SIMD, four untimed launches and one timed,
+ * about a millisecond each.  out: host double[5]; ws: device workspace of
+ * nbody_probe_workspace_bytes() bytes.  Synchronises `stream`. */
+int nbody_probe_issue_rates(double *out, void *ws, size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

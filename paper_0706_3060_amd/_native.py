@@ -34,6 +34,7 @@ EXPORTED = (
     "nbody_forces_jerk", "hermite_step", "hermite_block_init", "hermite_block_steps",
     "nbody_autotune_jerk", "nbody_forces_excl", "nbody_forces_batched_excl",
     "nbody_forces_backward_excl", "nbody_forces_backward_batched",
+    "nbody_probe_workspace_bytes", "nbody_probe_issue_rates",
 )
 
 
@@ -94,6 +95,8 @@ def lib():
                                   ctypes.c_int),
             "nbody_flops_per_pair": ([I32, I32, I32], I32),
             "nbody_version": ([], ctypes.c_char_p),
+            "nbody_probe_workspace_bytes": ([], SZ),
+            "nbody_probe_issue_rates": ([ctypes.POINTER(ctypes.c_double), P, SZ, P], ctypes.c_int),
             "nbody_forces_jerk": ([P, P, P, I64, P, I64, LAW, P, P, P, P, SZ, P], ctypes.c_int),
             "hermite_step": ([P, P, P, P, P, I64, LAW, D, I32, P, SZ, P], ctypes.c_int),
             "hermite_block_init": ([P, P, I64, D, D, P, P, P], ctypes.c_int),

@@ -418,6 +418,20 @@ def hermite_block(pos, vel, acc, jerk, t_i, dt_i, mass, law: Law, eta: float, dt
     return counts[:int(nblocks)], t_now.value
 
 
+def probe_issue_rates(device=None):
+    """Shader cycles a SIMD spends per wave64 instruction on this GPU (FP32 FMA with
+    VGPR operands, with one SGPR operand, v_rsq_f32) and the shader clock while the
+    FMA probe runs: a dict with keys fma_cycles, fma_sgpr_cycles, rsq_cycles,
+    clock_ghz, wall_counter_mhz.  Synchronises the device's current stream."""
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    nbytes = int(N.lib().nbody_probe_workspace_bytes())
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    out = (ctypes.c_double * 5)()
+    N.check(N.lib().nbody_probe_issue_rates(out, _ptr(ws), nbytes, _stream(dev)))
+    keys = ("fma_cycles", "fma_sgpr_cycles", "rsq_cycles", "clock_ghz", "wall_counter_mhz")
+    return dict(zip(keys, [float(v) for v in out]))
+
+
 def autotune_jerk(pos, vel, mass, law: Law, potential=True):
     """Measure launch configurations of the jerk kernel on this problem and remember
     the fastest (also used by the Hermite steps).  Returns (config dict, ms)."""

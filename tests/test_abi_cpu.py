@@ -174,6 +174,11 @@ def test_flop_convention_and_version(N):
     assert lib.nbody_flops_per_pair(0, 1, 0) == 30      # Table 1 lists 30 for LJC
     assert lib.nbody_flops_per_pair(2, 0, 0) == 41
     assert b"gfx950" in lib.nbody_version()
+    # issue-rate probe: argument checks only (it launches kernels)
+    assert lib.nbody_probe_workspace_bytes() > 0
+    out = (ctypes.c_double * 5)()
+    assert lib.nbody_probe_issue_rates(None, None, 0, None) == N.NBODY_EINVAL
+    assert lib.nbody_probe_issue_rates(out, ctypes.c_void_p(4096), 16, None) == N.NBODY_EWORKSPACE
 
 
 def test_python_binding_rejects_cpu_tensors(N):

@@ -187,3 +187,15 @@ def test_edge_cases(nb):
     # coincident particles with zero softening: undefined, as in the oracle
     f, p = nb.forces(dev(np.zeros((2, 3))), dev([1.0, 1.0]), nb.gravity("fp64", softening=0.0))
     assert not torch.isfinite(f).all()
+
+
+def test_issue_rate_probe(nb):
+    """The issue-rate probes behind the roofline ceiling return plausible figures: a
+    wave64 FP32 FMA issues in 2 to 4 shader cycles with VGPR operands, no faster with
+    an SGPR operand, v_rsq_f32 at a fraction of that rate, at a clock within the
+    part's range."""
+    r = nb.probe_issue_rates()
+    assert 1.8 <= r["fma_cycles"] <= 4.0, r
+    assert r["fma_sgpr_cycles"] >= 0.9 * r["fma_cycles"], r
+    assert 2.0 * r["fma_cycles"] <= r["rsq_cycles"] <= 40.0, r
+    assert 0.5 <= r["clock_ghz"] <= 3.0 and r["wall_counter_mhz"] > 0, r
