@@ -217,7 +217,9 @@ int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double
  *              grad_type_params [n_types][2] device receives the sums of
  *              dL/dsigma and dL/depsilon over the atoms of each type (the
  *              gradient with respect to per-type sigma and epsilon), reduced
- *              in a fixed order.
+ *              in a fixed order.  At most 16384 types (NBODY_ENOTSUP
+ *              beyond); atoms whose type is outside [0, n_types) are not
+ *              counted.
  * Workspace: nbody_workspace_bytes(NBODY_API_BACKWARD, n, 1, law).
  * Laws: gravity and LJC(linear) (other laws: NBODY_ENOTSUP).
  * Precisions: NBODY_FP64, NBODY_FP32_FP64ACC, NBODY_FP32_KAHAN. */

@@ -359,25 +359,33 @@ hipError_t launch_adjoint(const AdjLaunch &a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Fixed-order sum of the j-split partials, split_group(j_split) lanes per row
+// (NC = 3 sums for gravity, 6 for LJC).
+template <int NC>
 __global__ __launch_bounds__(256) void k_adj_reduce(AdjLaunch a)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.n) return;
-    const int nc = a.law == GRAVITY ? 3 : 6;
-    NSum v[6];
-    for (int s = 0; s < a.j_split; ++s) {
-        const double *o = a.partial + ((int64_t)s * a.n + r) * 8;
-        for (int c = 0; c < nc; ++c) v[c].add(o[c]);
+    const int G = split_group(a.j_split);
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if ((tid & ~int64_t(kWave - 1)) / G >= a.n) return;     // the whole wave is past the rows
+    const int64_t r = tid / G;
+    const int q = (int)(tid - r * G);
+    double v[NC];
+    split_group_sum<NC>(a.partial, a.n * 8, 8, r, r < a.n, a.j_split, q, G, v);
+    if (q == 0 && r < a.n) {
+        double out[8];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) out[c] = v[c];
+        adj_finish(a, NC == 3 ? (int)GRAVITY : a.law, r, out);
     }
-    double out[8];
-    for (int c = 0; c < nc; ++c) out[c] = v[c].value();
-    adj_finish(a, a.law, r, out);
 }
 
 hipError_t launch_adjoint_reduce(const AdjLaunch &a, hipStream_t s)
 {
     if (a.n <= 0 || a.j_split <= 1) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_reduce, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    const int64_t threads = a.n * split_group(a.j_split);
+    const dim3 grid((unsigned)((threads + 255) / 256));
+    if (a.law == GRAVITY) hipLaunchKernelGGL(k_adj_reduce<3>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_adj_reduce<6>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -602,52 +610,94 @@ int adjoint_batched_blocks_per_cu(const AdjBatchLaunch &a)
 }
 
 // ------------------------------------------------------ per-type reduction ----
-// One workgroup per type: each lane accumulates a strided slice of the atoms
-// in a fixed order (Neumaier), then the 64 lanes of each wave are combined by
-// a fixed xor-shuffle butterfly and the waves by LDS in wave order, so the
-// result is bitwise reproducible.
-__global__ __launch_bounds__(256) void k_type_reduce(const double *__restrict__ gp,
-                                                     const int32_t *__restrict__ types, int64_t n,
-                                                     double *__restrict__ out)
+// Per-type sums of the sigma and epsilon gradients (params columns 1 and 2) in
+// two passes, each in a fixed order, so that the sums repeat bit for bit:
+//   k_type_partial  block b owns the atoms [b chunk, (b + 1) chunk); for eight
+//                   types at a time every lane sums its strided atoms
+//                   (Neumaier; other types' atoms add an exact zero), the wave
+//                   merges its lanes in a butterfly and thread 0 the waves in
+//                   wave order, into partial[b][t][2];
+//   k_type_final    a group of 64 lanes per type sums the nb partials
+//                   (split_group_sum).
+// Types outside [0, n_types) are not counted.
+constexpr int kTypeGroup = 8;
+constexpr int kTypeThreads = 256;
+
+__global__ __launch_bounds__(kTypeThreads) void k_type_partial(const double *__restrict__ gp,
+                                                               const int32_t *__restrict__ types, int64_t n,
+                                                               int n_types, int64_t chunk,
+                                                               double *__restrict__ partial)
 {
-    const int t = blockIdx.x;
-    NSum ss, se;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        if (types[i] == t) {
-            ss.add(gp[3 * i + 1]);
-            se.add(gp[3 * i + 2]);
-        }
-    }
-    double a = ss.value(), b = se.value();
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        a += __shfl_xor(a, m, 64);
-        b += __shfl_xor(b, m, 64);
-    }
-    __shared__ double part[2][16];
+    __shared__ double sm[kTypeThreads / kWave][kTypeGroup][2][2];   // [wave][type][column][s, c]
+    const int64_t b0 = (int64_t)blockIdx.x * chunk;
+    const int64_t b1 = b0 + chunk < n ? b0 + chunk : n;
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        part[0][w] = a;
-        part[1][w] = b;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        NSum x, y;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
-            x.add(part[0][k]);
-            y.add(part[1][k]);
+    for (int tg = 0; tg < n_types; tg += kTypeGroup) {
+        NSum acc[kTypeGroup][2];
+        for (int64_t i = b0 + threadIdx.x; i < b1; i += kTypeThreads) {
+            const int t = types[i] - tg;
+            const double x1 = gp[3 * i + 1], x2 = gp[3 * i + 2];
+#pragma unroll
+            for (int k = 0; k < kTypeGroup; ++k) {
+                acc[k][0].add(t == k ? x1 : 0.0);
+                acc[k][1].add(t == k ? x2 : 0.0);
+            }
         }
-        out[2 * t] = x.value();
-        out[2 * t + 1] = y.value();
+#pragma unroll
+        for (int k = 0; k < kTypeGroup; ++k)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                for (int m = 1; m < kWave; m <<= 1) {
+                    const double s2 = __shfl_xor(acc[k][c].s, m);
+                    const double c2 = __shfl_xor(acc[k][c].c, m);
+                    acc[k][c].merge(s2, c2);
+                }
+                if ((threadIdx.x & (kWave - 1)) == 0) {
+                    sm[w][k][c][0] = acc[k][c].s;
+                    sm[w][k][c][1] = acc[k][c].c;
+                }
+            }
+        __syncthreads();
+        if (threadIdx.x < 2 * kTypeGroup) {
+            const int k = threadIdx.x >> 1, c = threadIdx.x & 1;
+            NSum v;
+            for (int ww = 0; ww < kTypeThreads / kWave; ++ww) v.merge(sm[ww][k][c][0], sm[ww][k][c][1]);
+            if (tg + k < n_types) partial[((int64_t)blockIdx.x * n_types + tg + k) * 2 + c] = v.value();
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_type_final(const double *__restrict__ partial, int n_types,
+                                                    int64_t nb, double *__restrict__ out)
+{
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = tid >> 6;
+    const int q = (int)(tid & (kWave - 1));
+    if ((tid & ~int64_t(kWave - 1)) >> 6 >= n_types) return;
+    double v[2];
+    split_group_sum<2>(partial, (int64_t)n_types * 2, 2, t, t < n_types, nb, q, kWave, v);
+    if (q == 0 && t < n_types) {
+        out[2 * t] = v[0];
+        out[2 * t + 1] = v[1];
     }
 }
 
 hipError_t launch_type_reduce(const double *grad_params, const int32_t *types, int64_t n,
-                              int32_t n_types, double *out, hipStream_t s)
+                              int32_t n_types, double *out, double *partial, int64_t partial_doubles,
+                              hipStream_t s)
 {
     if (n_types <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_type_reduce, dim3((unsigned)n_types), dim3(256), 0, s, grad_params, types,
-                       n, out);
+    // blocks: about 2048 atoms each, at most 1024, and as many as the partial buffer holds
+    int64_t nb = std::max<int64_t>(1, std::min<int64_t>((n + 2047) / 2048, 1024));
+    nb = std::min<int64_t>(nb, partial_doubles / (2 * (int64_t)n_types));
+    if (nb < 1) return hipErrorInvalidValue;
+    const int64_t chunk = (std::max<int64_t>(n, 1) + nb - 1) / nb;
+    hipLaunchKernelGGL(k_type_partial, dim3((unsigned)nb), dim3(kTypeThreads), 0, s, grad_params, types, n,
+                       (int)n_types, chunk, partial);
+    const int64_t threads = (int64_t)n_types * kWave;
+    hipLaunchKernelGGL(k_type_final, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, partial,
+                       (int)n_types, nb, out);
     return hipGetLastError();
 }
 

@@ -363,8 +363,11 @@ FwdWs fwd_layout(int api, const nbody_law *law, int64_t n)
 }
 
 struct AdjWs {
-    size_t rec_off, part_off, total;
+    size_t rec_off, part_off, type_off, total;
 };
+
+// Partials of the per-type gradient sums (blocks x types x 2 doubles).
+constexpr int64_t kTypePartDoubles = 32768;
 
 AdjWs adj_layout(const nbody_law *law, int64_t n)
 {
@@ -375,6 +378,8 @@ AdjWs adj_layout(const nbody_law *law, int64_t n)
     off = align256(off + (size_t)npad * adj_rec_bytes(law->kind, law->precision));
     w.part_off = off;
     off = align256(off + (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double));
+    w.type_off = off;
+    off = align256(off + (size_t)kTypePartDoubles * sizeof(double));
     w.total = off;
     return w;
 }
@@ -475,7 +480,7 @@ BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
 // Batched adjoint: adjoint records padded per system, the unit tables and the
 // part sums of split systems (8 doubles per row; half the forward's slot count).
 struct AdjBatWs {
-    size_t rec_off, unit_off, off_off, poff_off, systab_off, part_off, ticket_off, total;
+    size_t rec_off, unit_off, off_off, poff_off, systab_off, part_off, ticket_off, type_off, total;
     int64_t max_slots, max_units, max_records;
 };
 
@@ -502,6 +507,8 @@ AdjBatWs adjb_layout(const nbody_law *law, int64_t n_total, int64_t S)
     off = align256(off + (size_t)w.max_slots * 128 * 8 * sizeof(double));
     w.ticket_off = off;
     off = align256(off + 256);
+    w.type_off = off;
+    off = align256(off + (size_t)kTypePartDoubles * sizeof(double));
     w.total = off;
     return w;
 }
@@ -1266,6 +1273,8 @@ int backward_impl(const double *pos, const double *params, int64_t n, const nbod
         return fail(NBODY_EINVAL, "gravity has no parameter adjoint here: grad_params/types must be NULL");
     if (types && (n_types <= 0 || !grad_type_params))
         return fail(NBODY_EINVAL, "types given without n_types > 0 and grad_type_params");
+    if (types && n_types > kTypePartDoubles / 2)
+        return fail(NBODY_ENOTSUP, "at most %lld types", (long long)(kTypePartDoubles / 2));
     if (types && !grad_params)
         return fail(NBODY_EINVAL, "the per-type reduction needs grad_params");
     if (n == 0) return NBODY_OK;
@@ -1319,7 +1328,8 @@ int backward_impl(const double *pos, const double *params, int64_t n, const nbod
     e = launch_adjoint_reduce(a, s);
     if (e != hipSuccess) return hip_fail(e, "adjoint split reduction");
     if (types) {
-        e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params, s);
+        e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params,
+                               (double *)(base + lay.type_off), kTypePartDoubles, s);
         if (e != hipSuccess) return hip_fail(e, "per-type reduction");
     }
     return NBODY_OK;
@@ -1380,6 +1390,8 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
         return fail(NBODY_EINVAL, "gravity has no parameter adjoint here: grad_params/types must be NULL");
     if (types && (n_types <= 0 || !grad_type_params))
         return fail(NBODY_EINVAL, "types given without n_types > 0 and grad_type_params");
+    if (types && n_types > kTypePartDoubles / 2)
+        return fail(NBODY_ENOTSUP, "at most %lld types", (long long)(kTypePartDoubles / 2));
     if (types && !grad_params) return fail(NBODY_EINVAL, "the per-type reduction needs grad_params");
     const int64_t n = offsets[n_systems];
     if (n == 0) return NBODY_OK;
@@ -1461,7 +1473,8 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     t.stop();
     if (e != hipSuccess) return hip_fail(e, "batched adjoint kernel");
     if (types) {
-        e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params, s);
+        e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params,
+                               (double *)(base + lay.type_off), kTypePartDoubles, s);
         if (e != hipSuccess) return hip_fail(e, "per-type reduction");
     }
     return NBODY_OK;

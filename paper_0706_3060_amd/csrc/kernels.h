@@ -164,8 +164,11 @@ struct AdjPackLaunch {
 hipError_t launch_pack_adjoint(const AdjPackLaunch &p, hipStream_t s);
 hipError_t launch_adjoint(const AdjLaunch &a, hipStream_t s);
 hipError_t launch_adjoint_reduce(const AdjLaunch &a, hipStream_t s);
+// per-type sums of grad_params columns 1 and 2 into out [n_types][2], through
+// partial [blocks][n_types][2] (partial_doubles doubles; at least 2 n_types)
 hipError_t launch_type_reduce(const double *grad_params, const int32_t *types, int64_t n,
-                              int32_t n_types, double *out, hipStream_t s);
+                              int32_t n_types, double *out, double *partial, int64_t partial_doubles,
+                              hipStream_t s);
 
 // ---- acceleration + jerk and the Hermite integrator ----
 struct JerkPackLaunch {

@@ -184,3 +184,28 @@ def test_typed_force_matching_gradient(nb):
         sel = s.types == k
         np.testing.assert_allclose(host(st.grad)[k], rs[sel].sum(), rtol=1e-9)
         np.testing.assert_allclose(host(et.grad)[k], re[sel].sum(), rtol=1e-9)
+
+
+@pytest.mark.parametrize("n,prec", [(5000, "fp64"), (20000, "fp32_kahan")])
+def test_per_type_sums_many_types(nb, n, prec):
+    """Per-type sums over 11 types (two passes of the eight-type block pass) and
+    several blocks of atoms equal the per-atom gradients summed by type, for the
+    single-system and the batched adjoint."""
+    s = W.md_system(n, 5, box=(32.0 * n) ** (1.0 / 3.0))
+    types = np.random.default_rng(71).integers(0, 11, n).astype(np.int32)
+    g = W.unit_cotangent(n, 72)
+    law = nb.ljc_linear(prec)
+    X, P, G = dev(s.pos), dev(s.params()), dev(g)
+    _, gq, gt = nb.forces_backward(X, P, G, law, types=types, n_types=11)
+    per_atom = host(gq)
+    ref = np.array([[per_atom[types == k, 1].sum(), per_atom[types == k, 2].sum()] for k in range(11)])
+    np.testing.assert_allclose(host(gt), ref, rtol=1e-11, atol=1e-13 * np.abs(per_atom).sum())
+    # the same atoms as two systems of a batch: per-type sums over both
+    off = np.array([0, n // 3, n], dtype=np.int64)
+    _, gqb, gtb = nb.forces_backward_batched(off, X, P, G, law, types=types, n_types=11)
+    pb = host(gqb)
+    refb = np.array([[pb[types == k, 1].sum(), pb[types == k, 2].sum()] for k in range(11)])
+    np.testing.assert_allclose(host(gtb), refb, rtol=1e-11, atol=1e-13 * np.abs(pb).sum())
+    # repeatable bit for bit
+    _, _, gt2 = nb.forces_backward(X, P, G, law, types=types, n_types=11)
+    assert torch.equal(gt, gt2)
