@@ -42,7 +42,7 @@ __device__ __forceinline__ void store_rec(LjcRec<T> *rec, int64_t i, double x, d
     r.z = (T)z;
     r.qs = (T)(par[0] * qscale);
     r.sh = (T)(0.5 * par[1]);
-    r.se = (T)__builtin_sqrt(par[2]);
+    r.se = (T)__builtin_sqrt(24.0 * par[2]);
     r.p0 = T(0);
     r.p1 = T(0);
     rec[i] = r;

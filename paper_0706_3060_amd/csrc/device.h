@@ -7,7 +7,8 @@
 //   LJC      {x, y, z, qs, sh, se, 0, 0}                8 x T
 //            qs = q sqrt(2k/D)  so that qs_i qs_j = 2 k q_i q_j / D,
 //            sh = sigma / 2     so that sh_i + sh_j = (sigma_i + sigma_j) / 2,
-//            se = sqrt(eps)     so that se_i se_j = sqrt(eps_i eps_j).
+//            se = sqrt(24 eps)  so that se_i se_j = 24 sqrt(eps_i eps_j), the
+//                               Lennard-Jones force prefactor.
 //   adjoint records append the cotangent g_j = dL/dF_j (see adjoint.hip).
 //
 // The j index of the inner loop is wave-uniform.  The j records reach the
@@ -182,19 +183,18 @@ __device__ __forceinline__ void ljc_pair(const LjcI<T> &i, T xj, T yj, T zj, T q
     const T sg = i.sh + shj;
     const T s2 = (sg * sg) * x;
     const T s6 = (s2 * s2) * s2;
-    const T lj = e * s6;
+    const T lj = e * s6;                     // 24 eps_ij (sigma_ij / r)^6
     const T t = fma_(s6, T(2), T(-1));
-    const T wl = lj * t;
-    const T W = fma_(wl, T(24), wc) * x;
+    const T W = fma_(lj, t, wc) * x;         // (24 eps_ij (2 s^12 - s^6) + wc) / r^2
     p[0] = fma_(-W, dx, p[0]);
     p[1] = fma_(-W, dy, p[1]);
     p[2] = fma_(-W, dz, p[2]);
     if (POT) {
-        const T v = fma_(lj, s6, -lj);       // e (s6^2 - s6)
+        const T v = fma_(lj, s6, -lj);       // 24 eps_ij (s^12 - s^6)
         if constexpr (LAW == LJC)
-            p[3] += fma_(v, T(8), cx);       // 2 u_ij
+            p[3] += fma_(v, T(1.0 / 3.0), cx);   // 2 u_ij
         else
-            p[3] += fma_(v, T(4), cx);       // u_ij
+            p[3] += fma_(v, T(1.0 / 6.0), cx);   // u_ij
     }
 }
 
