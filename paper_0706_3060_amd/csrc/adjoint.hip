@@ -51,7 +51,7 @@ __device__ __forceinline__ void adj_put(LjcAdjRec<T> *rec, int64_t i, const doub
     r.z = (T)x[2];
     r.qs = (T)(par[0] * qscale);
     r.sh = (T)(0.5 * par[1]);
-    r.se = (T)__builtin_sqrt(par[2]);
+    r.se = (T)__builtin_sqrt(24.0 * par[2]);     // se_i se_j = 24 eps_ij, as the forward records
     r.gx = (T)g[0];
     r.gy = (T)g[1];
     r.gz = (T)g[2];
@@ -149,14 +149,16 @@ __device__ __forceinline__ void ljc_adj_pair(const LjcAdjRec<T> &i, const LjcAdj
     }
     const T x = rcp_(r2);
     const T sg = i.sh + j.sh;
-    const T s2 = (sg * sg) * x;
-    const T s6 = (s2 * s2) * s2;
-    const T lj = e * s6;
+    const T sgx = sg * x;
+    const T s2 = sg * sgx;                                         // (sigma_ij / r)^2
+    const T s4 = s2 * s2;
+    const T s6 = s4 * s2;
+    const T lj = e * s6;                                           // 24 eps_ij s^6
     const T t = fma_(s6, T(2), T(-1));
     const T cx = qq * x;
-    const T W = fma_(lj * t, T(24), cx) * x;                       // w = -W
+    const T W = fma_(lj, t, cx) * x;                               // w = -W
     const T x2 = x * x;
-    const T wpr = fma_(lj * fma_(s6, T(28), T(-8)), T(24), cx * T(4)) * x2;
+    const T wpr = fma_(lj, fma_(s6, T(28), T(-8)), cx * T(4)) * x2;
     const T ux = j.gx - i.gx, uy = j.gy - i.gy, uz = j.gz - i.gz;
     T du = dx * ux;
     du = fma_(dy, uy, du);
@@ -174,7 +176,8 @@ __device__ __forceinline__ void ljc_adj_pair(const LjcAdjRec<T> &i, const LjcAdj
     o[2] = fma_(tt, dz, o[2]);
     const T xdu = x * du;
     o[3] = fma_(j.qs, x * xdu, o[3]);
-    o[4] = fma_(lj * fma_(s6, T(4), T(-1)), xdu * rcp_(sg), o[4]);
+    // 24 eps_ij s^6 / sigma_ij = e s^4 (sigma_ij / r^2): no reciprocal of sigma
+    o[4] = fma_((e * (s4 * sgx)) * fma_(s6, T(4), T(-1)), xdu, o[4]);
     o[5] = fma_(j.se, s6 * t * xdu, o[5]);
 }
 
@@ -229,9 +232,10 @@ __device__ __forceinline__ void adj_finish(const AdjLaunch &a, int law, int64_t 
         a.grad_pos[3 * k + 2] = v[2];
     }
     if (a.grad_params) {
-        const double se_k = __builtin_sqrt(a.params[3 * k + 2]);
+        // the sums carry the records' factor 24 in eps (v[4]) and sqrt(24) in se_j (v[5])
+        const double se_k = __builtin_sqrt(24.0 * a.params[3 * k + 2]);
         a.grad_params[3 * k] = a.qscale * v[3];
-        a.grad_params[3 * k + 1] = 72.0 * v[4];
+        a.grad_params[3 * k + 1] = 3.0 * v[4];
         a.grad_params[3 * k + 2] = (12.0 / se_k) * v[5];
     }
 }
