@@ -115,20 +115,17 @@ __device__ __forceinline__ void grav_adj_pair(const GravAdjRec<T> &i, const Grav
     if (MASK) ri = self ? T(0) : ri;
     const T ri2 = ri * ri;
     const T ri3 = ri2 * ri;
-    const T r5x3 = ri3 * (ri2 * T(3));
     const T wx = fma_(-j.m, i.gx, i.m * j.gx);
     const T wy = fma_(-j.m, i.gy, i.m * j.gy);
     const T wz = fma_(-j.m, i.gz, i.m * j.gz);
     T dw = dx * wx;
     dw = fma_(dy, wy, dw);
     dw = fma_(dz, wz, dw);
-    const T e = dw * r5x3;
-    o[0] = fma_(ri3, wx, o[0]);
-    o[1] = fma_(ri3, wy, o[1]);
-    o[2] = fma_(ri3, wz, o[2]);
-    o[0] = fma_(-e, dx, o[0]);
-    o[1] = fma_(-e, dy, o[1]);
-    o[2] = fma_(-e, dz, o[2]);
+    // K(d) w = s^-3 (w - 3 s^-2 (d.w) d)
+    const T u = (ri2 * T(3)) * dw;
+    o[0] = fma_(ri3, fma_(-u, dx, wx), o[0]);
+    o[1] = fma_(ri3, fma_(-u, dy, wy), o[1]);
+    o[2] = fma_(ri3, fma_(-u, dz, wz), o[2]);
 }
 
 // LJC adjoint, per pair (position and parameter adjoints together).
