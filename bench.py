@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--legs", default="all", choices=["all", "main"],
                     help="'main' runs only the headline workload (for counter runs)")
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic configuration")
+    ap.add_argument("--launch", default=None, metavar="BLOCK,IPL,JTILE,SPLIT,STAGE",
+                    help="force the headline kernel's launch configuration (for counter runs of one "
+                         "configuration); implies no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target host time of the oracle sample")
     ap.add_argument("--make-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
@@ -111,7 +114,12 @@ def main():
 
     # ---- accuracy of the timed precision at t = 0 (FP64 GPU pass over all N,
     #      oracle on a random row sample)
-    if not args.no_tune:
+    if args.launch:
+        b, ipl, jt, sp, js = (int(v) for v in args.launch.split(","))
+        for api in (nb.API_FORCES, nb.API_LEAPFROG):
+            nb.set_config(api, b, ipl, jt, sp, js)
+        log("forced forces config:", args.launch)
+    elif not args.no_tune:
         cfg, tune_ms = nb.autotune(x, m, law, potential=True)
         log("autotuned forces config:", cfg, "%.2f ms" % tune_ms)
     a32, p32 = nb.forces(x, m, law)
@@ -277,9 +285,18 @@ def make_traffic(fetch_csv, write_csv, bench_json):
            "fetch_kib": fk, "write_kib": wk, "copy_fetch_kib": cf[0], "copy_write_kib": cw[0],
            "copy_bytes": copy_bytes, "fetch_scale": fs, "write_scale": ws,
            "bytes_per_launch": fk * 1024 * fs + wk * 1024 * ws, "config": cfg, "n": n}
+    # one record per launch configuration, all on the same kernel sources
     path = os.path.join(ROOT, "profiles", "traffic_k_forces_gravity_fp32kahan_n%d.json" % n)
+    records = []
+    try:
+        with open(path) as fh:
+            records = [r for r in json.load(fh).get("records", []) if r.get("sources_sha256") == h]
+    except (OSError, ValueError, AttributeError):
+        records = []
+    records = [r for r in records if r.get("config") != cfg] + [rec]
+    records.sort(key=lambda r: sorted(r["config"].items()))
     with open(path, "w") as fh:
-        json.dump(rec, fh, indent=1)
+        json.dump({"records": records}, fh, indent=1)
     print(json.dumps(rec, indent=1))
 
 
@@ -291,14 +308,15 @@ def measured_traffic(n, cfg):
     path = os.path.join(ROOT, "profiles", "traffic_k_forces_gravity_fp32kahan_n1048576.json")
     try:
         with open(path) as fh:
-            rec = json.load(fh)
+            records = json.load(fh)["records"]
         h = hashlib.sha256(b"".join(open(os.path.join(ROOT, s), "rb").read()
-                                    for s in rec["sources"])).hexdigest()
-    except (OSError, KeyError, ValueError):
+                                    for s in TRAFFIC_SOURCES)).hexdigest()
+    except (OSError, KeyError, ValueError, TypeError):
         return None
-    if h != rec.get("sources_sha256") or rec.get("config") != cfg or rec.get("n") != n:
-        return None
-    return rec["bytes_per_launch"]
+    for rec in records:
+        if rec.get("sources_sha256") == h and rec.get("config") == cfg and rec.get("n") == n:
+            return rec["bytes_per_launch"]
+    return None
 
 
 def batched_leg(nb, torch, dev, ens):

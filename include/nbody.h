@@ -400,7 +400,10 @@ int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass
                         double *out_potential, void *ws, size_t ws_bytes, void *stream,
                         nbody_config *out_best, double *out_ms);
 
-/* Save / load the tuning cache as a small JSON file (host path). */
+/* Save / load the tuning cache as a small JSON file (host path).  The file
+ * records the device's architecture name and compute-unit count; loading a
+ * file written for another architecture or CU count returns NBODY_EINVAL and
+ * loads nothing (tuned launch shapes do not carry over between devices). */
 int nbody_tune_save(const char *path);
 int nbody_tune_load(const char *path);
 

@@ -812,6 +812,18 @@ int device_cus()
     return g_num_cus;
 }
 
+// Architecture name of the current device ("gfx950"; feature suffixes dropped),
+// or "unknown" without one.
+std::string device_arch()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
 int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int64_t S,
                 const double *pos, const double *params, double *out_force, double *out_pot,
                 void *ws, const BatWs &lay, hipStream_t s, const ExclArgs &excl = ExclArgs{})
@@ -1014,7 +1026,27 @@ int batched_impl(const int64_t *offsets, int64_t S, const double *pos, const dou
 }
 
 // candidate list for the measured search
+std::vector<Cfg> candidate_set(int api, int law, int prec, int64_t n, bool pot);
+
+bool same_cfg(const Cfg &a, const Cfg &b)
+{
+    return a.block == b.block && a.ipl == b.ipl && a.j_tile == b.j_tile && a.j_split == b.j_split &&
+           a.j_stage == b.j_stage;
+}
+
+// The configurations the autotuners time, the heuristic's own choice first:
+// with kTuneMargin, a measured near-tie keeps it, so the choice repeats across
+// runs and devices of one kind.
 std::vector<Cfg> candidates(int api, int law, int prec, int64_t n, bool pot)
+{
+    std::vector<Cfg> out{sanitize(heuristic(api, law, prec, n, n, 1, pot), api, law, prec,
+                                  round_up(std::max<int64_t>(n, 1), 64))};
+    for (const Cfg &c : candidate_set(api, law, prec, n, pot))
+        if (!same_cfg(c, out[0])) out.push_back(c);
+    return out;
+}
+
+std::vector<Cfg> candidate_set(int api, int law, int prec, int64_t n, bool pot)
 {
     std::vector<Cfg> out;
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
@@ -1957,8 +1989,10 @@ int nbody_tune_save(const char *path)
     if (!path) return fail(NBODY_EINVAL, "path is NULL");
     FILE *f = fopen(path, "w");
     if (!f) return fail(NBODY_EINVAL, "cannot open %s", path);
+    const std::string arch = device_arch();
+    const int cus = device_cus();
     std::lock_guard<std::mutex> lk(g_mu);
-    fprintf(f, "{\"device_cus\": %d, \"entries\": [\n", device_cus());
+    fprintf(f, "{\"arch\": \"%s\", \"device_cus\": %d, \"entries\": [\n", arch.c_str(), cus);
     size_t k = 0;
     for (const auto &kv : g_tuned) {
         const TuneKey &t = kv.first;
@@ -1986,6 +2020,18 @@ int nbody_tune_load(const char *path)
     size_t got;
     while ((got = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
     fclose(f);
+    // the file's device must be this one
+    char farch[64] = {0};
+    int fcus = 0;
+    const size_t pa = txt.find("\"arch\": \""), pc = txt.find("\"device_cus\": ");
+    if (pa == std::string::npos || pc == std::string::npos ||
+        sscanf(txt.c_str() + pa, "\"arch\": \"%63[^\"]\"", farch) != 1 ||
+        sscanf(txt.c_str() + pc, "\"device_cus\": %d", &fcus) != 1)
+        return fail(NBODY_EINVAL, "%s does not name the device it was tuned on", path);
+    const std::string arch = device_arch();
+    if (arch != farch || fcus != device_cus())
+        return fail(NBODY_EINVAL, "%s was tuned on %s with %d CUs; this device is %s with %d CUs", path, farch,
+                    fcus, arch.c_str(), device_cus());
     int loaded = 0;
     size_t pos = 0;
     while ((pos = txt.find("{\"api\"", pos)) != std::string::npos) {

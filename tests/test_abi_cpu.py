@@ -299,3 +299,28 @@ def test_exclusions_and_batched_adjoint_validation(N):
     assert bb(lj, o=bad) == N.NBODY_EINVAL
     assert lib.nbody_workspace_bytes(6, 10000, 50, ctypes.byref(lj)) > 10000 * 64
     assert lib.nbody_flops_per_pair(6, 1, 0) == 68
+
+
+def test_tuning_file_is_tied_to_its_device(N, tmp_path):
+    """nbody_tune_load accepts a file written for this device (here: no GPU, so the
+    architecture reads "unknown" and the CU count the 256 fallback) and rejects one
+    written for another architecture or CU count, or naming no device."""
+    lib = N.lib()
+    entry = ('{"api": 0, "law": 3, "precision": 2, "potential": 0, "n_bucket": 5, "s_bucket": 5, '
+             '"block": 256, "i_per_lane": 1, "j_tile": 256, "j_split": 2, "j_stage": 1, "ms": 1.0}')
+
+    def write(name, head):
+        p = tmp_path / name
+        p.write_text('{%s"entries": [\n  %s\n]}\n' % (head, entry))
+        return str(p).encode()
+
+    assert lib.nbody_tune_load(write("ok.json", '"arch": "unknown", "device_cus": 256, ')) == 0
+    assert lib.nbody_tune_load(write("arch.json", '"arch": "gfx942", "device_cus": 256, ')) == N.NBODY_EINVAL
+    assert b"gfx942" in lib.nbody_last_error()
+    assert lib.nbody_tune_load(write("cus.json", '"arch": "unknown", "device_cus": 304, ')) == N.NBODY_EINVAL
+    assert lib.nbody_tune_load(write("none.json", "")) == N.NBODY_EINVAL
+    out = tmp_path / "saved.json"
+    assert lib.nbody_tune_save(str(out).encode()) == 0
+    text = out.read_text()
+    assert '"arch": "unknown"' in text and '"device_cus": 256' in text and '"j_split": 2' in text
+    assert lib.nbody_tune_load(str(out).encode()) == 0

@@ -199,3 +199,21 @@ def test_issue_rate_probe(nb):
     assert r["fma_sgpr_cycles"] >= 0.9 * r["fma_cycles"], r
     assert 2.0 * r["fma_cycles"] <= r["rsq_cycles"] <= 40.0, r
     assert 0.5 <= r["clock_ghz"] <= 3.0 and r["wall_counter_mhz"] > 0, r
+
+
+def test_tuning_cache_round_trip(nb, tmp_path):
+    """A tuned configuration saved on this GPU loads back; the same file relabelled for
+    another architecture is refused."""
+    x, _, m = W.plummer(2048, 21)
+    law = nb.gravity("fp32_kahan", softening=0.01)
+    cfg, ms = nb.autotune(dev(x), dev(m), law)
+    assert ms > 0
+    path = tmp_path / "tune.json"
+    nb.tune_save(path)
+    text = path.read_text()
+    assert '"arch": "gfx950"' in text and '"device_cus": %d' % torch.cuda.get_device_properties(0).multi_processor_count in text
+    nb.tune_load(path)
+    other = tmp_path / "other.json"
+    other.write_text(text.replace('"arch": "gfx950"', '"arch": "gfx942"'))
+    with pytest.raises(RuntimeError):
+        nb.tune_load(other)
