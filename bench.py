@@ -9,17 +9,22 @@ evaluation with its FP64 finalize, and the closing kick) -- N^2 ordered pair
 interactions.  The launch configuration comes from the autotuner, run before
 the timed region.
 
-Printed (one JSON line on stdout): interactions per second, the roofline of
-the all-pairs kernel (algorithmic flops per launch / its mean launch time,
-measured with HIP events on the launch stream), the oracle timed on a bounded
-sample on the host cores, the accuracy of the timed path against the FP64 GPU
-pass and the oracle, and three secondary legs: the batched ensemble (256 LJC
-systems, N_s in [500, 5000], one persistent launch vs one launch per system,
-each side autotuned), the position adjoint at N = 262,144 (FP32 vs FP64), and
-every pair law of Table 1 at N = 65,536, plus the acceleration-and-jerk kernel
-and the block-time-step Hermite integrator on a Plummer sphere of 65,536;
-bonded chains with exclusion lists (N = 8192) and the batched adjoint of the
-256-system ensemble; and the oracle timed in full on the small configurations.
+Printed (one JSON line on stdout):
+  * interactions per second of the headline step;
+  * the roofline of the all-pairs kernel (algorithmic flops per launch / its mean
+    launch time, measured with HIP events on the launch stream) and its HBM traffic
+    from the committed counter record;
+  * the issue-rate ceiling of the pair sequence from the library's probes;
+  * the oracle timed on a bounded row sample on the host cores;
+  * the accuracy of the timed path against the FP64 GPU pass and the oracle;
+and, by default, secondary legs: the batched ensemble (256 LJC systems, N_s in
+[500, 5000], one persistent launch vs one launch per system, each side autotuned);
+the position adjoint at N = 262,144 (FP32 vs FP64); every pair law of Table 1 at
+N = 65,536; the acceleration-and-jerk kernel and the block-time-step Hermite
+integrator on a Plummer sphere of 65,536; bonded chains with exclusion lists
+(N = 8192); the batched adjoint of the 256-system ensemble; 100 leapfrog steps at
+N = 65,536 with their energy drift; and the oracle timed in full on the small
+configurations.
 """
 from __future__ import annotations
 
@@ -233,6 +238,7 @@ def main():
         out["jerk"] = jerk_leg(nb, torch, dev, W)
         out["bonded"] = bonded_leg(nb, torch, dev, W, chains)
         out["batched_backward"] = batched_backward_leg(nb, torch, dev, ens)
+        out["leapfrog_100"] = leapfrog_leg(nb, torch, dev, W)
         out["oracle_configs"] = oracle_configs_leg(nb, torch, dev, W, ens, out)
     print(json.dumps(out), flush=True)
 
@@ -604,6 +610,39 @@ def batched_backward_leg(nb, torch, dev, ens):
            "batched_tflops": 68 * pairs / t_b / 1e12,
            "err_vs_fp64_per_system_median_max": max(med_sys), "err_vs_fp64_max": float(e.max())}
     log("batched backward:", res)
+    return res
+
+
+def leapfrog_leg(nb, torch, dev, W):
+    """100 KDK leapfrog steps of the N = 65,536 Plummer sphere (eps = 0.01, dt = 1e-3): wall time
+    of the FP32 + Kahan and FP64 trajectories, and their relative energy drift with E from the
+    FP64 potential pass in both cases."""
+    n, eps, dt, steps = 65536, 0.01, 1e-3, 100
+    pos, vel, m = W.plummer(n, 2)
+    M = torch.tensor(m, device=dev)
+    law64 = nb.gravity("fp64", softening=eps)
+
+    def energy(x, v):
+        _, phi = nb.forces(x, M, law64)
+        return float((0.5 * M * (v * v).sum(1)).sum() + 0.5 * (M * phi).sum())
+
+    res = {"n": n, "steps": steps, "dt": dt, "softening": eps}
+    e0 = None
+    for name in ("fp32_kahan", "fp64"):
+        law = nb.gravity(name, softening=eps)
+        X, V = torch.tensor(pos, device=dev), torch.tensor(vel, device=dev)
+        A, _ = nb.forces(X, M, law)
+        if e0 is None:
+            e0 = energy(X, V)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        nb.leapfrog(X, V, A, M, law, dt, steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        res[name] = {"wall_s": wall, "ms_per_step": wall / steps * 1e3,
+                     "g_pairs_per_s": float(n) * n * steps / wall / 1e9,
+                     "rel_energy_drift": abs(energy(X, V) - e0) / abs(e0)}
+    log("leapfrog 100 steps:", res)
     return res
 
 
