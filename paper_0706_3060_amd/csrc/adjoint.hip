@@ -560,7 +560,9 @@ static bool adjb_dispatch(const AdjBatchLaunch &a, hipStream_t s, const void **f
     return a.law == GRAVITY ? adjb_prec<GRAVITY>(a, s, fn) : (a.law == LJC ? adjb_prec<LJC>(a, s, fn) : false);
 }
 
-// Rows of systems cut into several j parts: the part sums in part order.
+// Rows of systems cut into several j parts: the part sums in part order
+// (NC = 3 sums for gravity, 6 for LJC).
+template <int NC>
 __global__ __launch_bounds__(256) void k_adjoint_batched_reduce(AdjBatchLaunch a)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -573,19 +575,20 @@ __global__ __launch_bounds__(256) void k_adjoint_batched_reduce(AdjBatchLaunch a
     }
     const int64_t nparts = a.systab[3 * lo];
     if (nparts <= 1) return;
-    const int nc = a.law == GRAVITY ? 3 : 6;
     const int64_t rows = (int64_t)kWave * a.ipl;
     const int64_t l = r - a.off[lo];
     const int64_t rb = l / rows, rr = l - rb * rows;
     const int64_t slot0 = a.systab[3 * lo + 2] + rb * nparts;
-    NSum v[6];
+    NSum v[NC];
     for (int64_t p = 0; p < nparts; ++p) {
         const double *q = a.partial + ((slot0 + p) * rows + rr) * 8;
-        for (int c = 0; c < nc; ++c) v[c].add(q[c]);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v[c].add(q[c]);
     }
     double out[8];
-    for (int c = 0; c < nc; ++c) out[c] = v[c].value();
-    adj_finish_b(a, a.law, r, out);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) out[c] = v[c].value();
+    adj_finish_b(a, NC == 3 ? (int)GRAVITY : a.law, r, out);
 }
 
 hipError_t launch_adjoint_batched(const AdjBatchLaunch &a, hipStream_t s)
@@ -596,8 +599,9 @@ hipError_t launch_adjoint_batched(const AdjBatchLaunch &a, hipStream_t s)
     if (!adjb_dispatch(a, s, nullptr)) return hipErrorInvalidValue;
     e = hipGetLastError();
     if (e != hipSuccess || !a.any_parts) return e;
-    hipLaunchKernelGGL(k_adjoint_batched_reduce, dim3((unsigned)((a.n_total + 255) / 256)), dim3(256), 0,
-                       s, a);
+    const dim3 grid((unsigned)((a.n_total + 255) / 256));
+    if (a.law == GRAVITY) hipLaunchKernelGGL(k_adjoint_batched_reduce<3>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_adjoint_batched_reduce<6>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -235,3 +235,32 @@ def test_block_steps_stop_at_t_end(nb, prec):
     assert np.all(c == 0) and np.isnan(tn)
     for a, b in zip(one, before):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("cfg", [(128, 2, 512, 3, 1), (256, 1, 64, 40, 1), (64, 2, 1024, 1, 0)])
+def test_block_steps_forced_configuration(nb, cfg):
+    """Block steps under a forced Hermite configuration (two rows per lane, a forced
+    split, scalar staging) keep the oracle's schedule and states: the device-side
+    split, the one-dimensional jerk grid and the corrector's split sums for every
+    shape."""
+    block, ipl, jt, js, stage = cfg
+    x, v, m = W.plummer(700, 23)
+    eta_s, eta, dt_max = 0.01, 0.02, 1.0 / 64
+    law = nb.gravity("fp64", softening=EPS)
+    a0, j0, _ = oracle.gravity_jerk(x, v, m, eps=EPS)
+    t_r, dt_r = oracle.hermite_block_init(a0, j0, eta_s, dt_max)
+    X, V, A, J = dev(x), dev(v), dev(a0), dev(j0)
+    T, DT = nb.hermite_block_init(A, J, eta_s, dt_max)
+    try:
+        nb.set_config(nb.API_HERMITE, block, ipl, jt, js, stage)
+        counts, t_now = nb.hermite_block(X, V, A, J, T, DT, dev(m), law, eta, dt_max, 30)
+    finally:
+        nb.clear_config(nb.API_HERMITE)
+    xr, vr, ar, jr, tr, dtr, cr, tnr = oracle.hermite_block(x, v, a0, j0, t_r, dt_r, m, 30, eta, dt_max,
+                                                            eps=EPS)
+    np.testing.assert_array_equal(counts, cr)
+    assert t_now == tnr
+    np.testing.assert_array_equal(host(DT), dtr)
+    assert np.abs(host(X) - xr).max() <= 1e-12 * np.abs(xr).max()
+    assert np.abs(host(V) - vr).max() <= 1e-12 * np.abs(vr).max()
+    assert rel_rows(host(A), ar).max() <= 1e-10
