@@ -285,6 +285,16 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         c.j_split = split;
         return sanitize(c, api, law, prec, npad);
     }
+    if (is_f32(prec)) {
+        // Measured on gfx950 (gravity, FP32 + Kahan, one row per lane, LDS staging): the
+        // best split keeps about 24k waves in flight, with at least 8 and at most 32
+        // parts (N = 16384: 32; 65536: 24; 262144 and 2^20: 8 to 32 within 1 %); the
+        // round-quantisation model alone stops at 5 and loses up to a fifth at N = 65536.
+        const int64_t waves = (n + 64 * c.ipl - 1) / (64 * c.ipl);
+        const int64_t want = std::min<int64_t>(32, std::max<int64_t>(8, (24576 + waves - 1) / waves));
+        c.j_split = (int)std::max<int64_t>(1, std::min<int64_t>(want, smax));
+        return sanitize(c, api, law, prec, npad);
+    }
     c.j_split = ranked_splits(law, prec, n, nj, c.ipl, pot, c.j_stage, c.block, smax)[0];
     return sanitize(c, api, law, prec, npad);
 }
