@@ -1,0 +1,66 @@
+// Internal interface between the host runtime (api.cpp) and the adjoint
+// kernels (adjoint.hip).  Not part of the public ABI (include/nbody.h).
+#pragma once
+#include "kernels.h"
+
+namespace nbk {
+
+// ---- adjoint ----
+struct AdjLaunch {
+    int law, prec, ipl;
+    int block;
+    int j_stage;                 // as FwdLaunch::j_stage
+    int64_t n, npad;
+    int64_t split_len;
+    int j_split, j_tile;
+    double eps2;
+    double G;                    // gravity
+    double qscale;               // LJC sqrt(2k/D)
+    const void *rec;
+    double *partial;             // [j_split][n][8] when j_split > 1
+    double *grad_pos;            // [n][3] or null
+    double *grad_params;         // [n][3] or null (LJC)
+    const double *params;        // caller params (for the per-atom scale factors)
+    ExclArgs excl;               // exclusion lists (LJC), or off == nullptr
+};
+// Batched adjoint: (system, row-block) units in one persistent launch.
+struct AdjBatchLaunch {
+    int law, prec, ipl;
+    int block, grid;
+    int j_stage;
+    int j_tile;
+    int64_t n_units;
+    const int32_t *units;        // [n_units][4] (system, row block, j part, 0)
+    const int64_t *off, *poff;   // [S+1] caller rows and padded record offsets
+    const int64_t *systab;       // [S][3] = (j parts P, records per part, first partial slot)
+    double *partial;             // [slots][64 * ipl][8] part sums of systems with P > 1
+    int any_parts;
+    int64_t n_systems, npad_total, n_total;
+    double eps2, G, qscale;
+    const double *pos, *params, *g;   // caller arrays (pack)
+    void *rec;
+    int *ticket;
+    double *grad_pos;            // [n][3] or null
+    double *grad_params;         // [n][3] or null (LJC)
+    ExclArgs excl;
+};
+hipError_t launch_pack_adjoint_batched(const AdjBatchLaunch &p, hipStream_t s);
+hipError_t launch_adjoint_batched(const AdjBatchLaunch &a, hipStream_t s);
+int adjoint_batched_blocks_per_cu(const AdjBatchLaunch &a);
+struct AdjPackLaunch {
+    int law, prec;
+    int64_t n, npad;
+    const double *pos, *params, *g;
+    double qscale;
+    void *rec;
+};
+hipError_t launch_pack_adjoint(const AdjPackLaunch &p, hipStream_t s);
+hipError_t launch_adjoint(const AdjLaunch &a, hipStream_t s);
+hipError_t launch_adjoint_reduce(const AdjLaunch &a, hipStream_t s);
+// per-type sums of grad_params columns 1 and 2 into out [n_types][2], through
+// partial [blocks][n_types][2] (partial_doubles doubles; at least 2 n_types)
+hipError_t launch_type_reduce(const double *grad_params, const int32_t *types, int64_t n,
+                              int32_t n_types, double *out, double *partial, int64_t partial_doubles,
+                              hipStream_t s);
+
+}  // namespace nbk

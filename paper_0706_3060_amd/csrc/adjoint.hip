@@ -17,6 +17,7 @@
 
 #include "allpairs.h"
 #include "kernels.h"
+#include "adjoint.h"
 
 namespace nbk {
 

@@ -15,6 +15,7 @@
 
 #include "allpairs.h"
 #include "kernels.h"
+#include "jerk.h"
 
 namespace nbk {
 
@@ -284,6 +285,10 @@ static bool jerk_prec(const JerkLaunch &a, dim3 grid, hipStream_t s)
 hipError_t launch_jerk(const JerkLaunch &a, hipStream_t s)
 {
     if (a.nrows <= 0) return hipSuccess;
+    // a launch description missing its buffers or tile is refused, never launched
+    if (!a.rec || !a.out_acc || !a.out_jerk || (a.j_split > 1 && !a.partial) || a.j_tile <= 0 ||
+        a.npad <= 0 || a.npad % kWave != 0)
+        return hipErrorInvalidValue;
     const int64_t waves = a.split_dev ? a.grid_waves
                                       : (a.nrows + (int64_t)kWave * a.ipl - 1) / ((int64_t)kWave * a.ipl);
     const int64_t wpb = a.block / kWave;
@@ -458,6 +463,8 @@ __global__ __launch_bounds__(256) void k_hermite_correct(HermiteLaunch a)
 hipError_t launch_hermite_correct(const HermiteLaunch &a, hipStream_t s)
 {
     if (a.nrows <= 0) return hipSuccess;
+    if (!a.pos || !a.vel || !a.acc || !a.jerk || !a.a1 || !a.j1 || (a.dt_i && (!a.t_i || !a.t_next)))
+        return hipErrorInvalidValue;
     const int64_t threads = a.partial ? a.grid_threads : a.nrows;
     hipLaunchKernelGGL(k_hermite_correct, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
