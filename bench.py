@@ -201,6 +201,14 @@ def main():
     t_cpu = time.perf_counter() - t1
     cpu_value = k_rows * n / t_cpu / 1e9
     log("oracle: %d rows x %d in %.1f s on %d threads = %.3f G pairs/s" % (k_rows, n, t_cpu, threads, cpu_value))
+    # the same oracle on one thread, on a sample of about a tenth of the time
+    k1 = int(max(16, min(n, 0.1 * args.cpu_seconds * rate / n / max(threads, 1))))
+    t1 = time.perf_counter()
+    oracle.gravity(pos, mass, eps=EPS_MAIN, ilist=sample[:k1], nthreads=1)
+    t_one = time.perf_counter() - t1
+    one_value = k1 * n / t_one / 1e9
+    host = {"nproc": os.cpu_count(), "cpu_model": _cpu_model()}
+    log("oracle on one thread: %d rows in %.1f s = %.4f G pairs/s; host %s" % (k1, t_one, one_value, host))
 
     traffic = measured_traffic(n, cfg_used)
     out = {
@@ -227,7 +235,8 @@ def main():
         "cpu_baseline": {"value": cpu_value, "unit": "G pair-interactions/s", "cores": threads,
                          "kind": "oracle",
                          "sample": "%d random rows of the N=%d Plummer workload against all N "
-                                   "(FP64 oracle, compensated sums), %.1f s" % (k_rows, n, t_cpu)},
+                                   "(FP64 oracle, compensated sums), %.1f s" % (k_rows, n, t_cpu),
+                         "one_thread_value": one_value, "one_thread_sample_rows": k1, "host": host},
         "accuracy": acc,
     }
 
@@ -304,6 +313,17 @@ def make_traffic(fetch_csv, write_csv, bench_json):
     with open(path, "w") as fh:
         json.dump({"records": records}, fh, indent=1)
     print(json.dumps(rec, indent=1))
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def measured_traffic(n, cfg):

@@ -52,7 +52,11 @@ static inline double nval(const nsum *a) { return a->s + a->c; }
 static int set_threads(int nthreads)
 {
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    /* 0 restores the count OpenMP started with (OMP_NUM_THREADS or the
+     * processor count), so that a request for one thread does not stick */
+    static int initial = 0;
+    if (initial == 0) initial = omp_get_max_threads();
+    omp_set_num_threads(nthreads > 0 ? nthreads : initial);
     return omp_get_max_threads();
 #else
     (void)nthreads;

@@ -125,3 +125,11 @@ def test_thread_count_does_not_change_results(oracle_mod):
     a4, p4 = oracle_mod.gravity(pos, mass, eps=0.01, nthreads=4)
     np.testing.assert_array_equal(a1, a4)
     np.testing.assert_array_equal(p1, p4)
+
+
+def test_thread_request_does_not_stick(oracle_mod):
+    """A one-thread request applies to that call only: a later request for all threads
+    gets the initial count back (the bench times the oracle both ways)."""
+    full = oracle_mod.threads(0)
+    assert oracle_mod.threads(1) == 1
+    assert oracle_mod.threads(0) == full
