@@ -434,10 +434,11 @@ size_t nbody_probe_workspace_bytes(void);
  * instruction: out[0] FP32 FMA with all operands in VGPRs, out[1] FP32 FMA
  * with one SGPR operand, out[2] v_rsq_f32; out[3] the shader clock in GHz
  * while the FMA probe runs (shader-cycle counter over the fixed-rate wall
- * counter); out[4] that wall counter's rate in MHz.  Each probe's cycles are
- * taken at its own measured clock.  Each probe runs eight independent chains
- * per lane with eight waves per SIMD, four untimed launches and one timed,
- * about a millisecond each.  out: host double[5]; ws: device workspace of
+ * counter); out[4] that wall counter's rate in MHz.  Each probe runs eight
+ * independent chains per lane with eight waves per SIMD: four untimed
+ * launches, then three timed ones of about a millisecond, each taken at its
+ * own measured clock; the median is reported.
+ * out: host double[5]; ws: device workspace of
  * nbody_probe_workspace_bytes() bytes.  Synchronises `stream`. */
 int nbody_probe_issue_rates(double *out, void *ws, size_t ws_bytes, void *stream);
 

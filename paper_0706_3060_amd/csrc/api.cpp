@@ -1223,7 +1223,10 @@ const char *nbody_version(void) { return "nbody-mi355x 0.1 (gfx950)"; }
 // ------------------------------------------------------------- probes ----
 constexpr int kProbeIters = 16384;
 
-static int probe_blocks() { return std::min(device_cus(), 4096) * 8; }   // eight waves per SIMD
+// eight waves per SIMD: the rate a dense VGPR-only stream sustains depends on the
+// waves a SIMD can alternate between (measured: 3.5 cycles per FMA at four waves,
+// 2.5 to 2.8 at eight), so the probe runs at the occupancy of the pair kernels
+static int probe_blocks() { return std::min(device_cus(), 4096) * 8; }
 
 size_t nbody_probe_workspace_bytes(void) { return (size_t)probe_blocks() * 256 * sizeof(float) + 256; }
 
@@ -1242,40 +1245,46 @@ int nbody_probe_issue_rates(double *out, void *ws, size_t ws_bytes, void *stream
         (void)hipEventDestroy(a);
         return fail(NBODY_EHIP, "event creation failed");
     }
-    double ms[3] = {0, 0, 0};
-    hipError_t e = hipSuccess;
-    for (int mode = 0; mode < 3 && e == hipSuccess; ++mode) {
-        for (int w = 0; w < 4 && e == hipSuccess; ++w)                          // warm-up: clocks settle
-            e = launch_probe(mode, o, clk, blocks, kProbeIters, s);
-        if (e == hipSuccess) e = hipEventRecord(a, s);
-        if (e == hipSuccess) e = launch_probe(mode, o, clk, blocks, kProbeIters, s);
-        if (e == hipSuccess) e = hipEventRecord(b, s);
-        if (e == hipSuccess) e = hipEventSynchronize(b);
-        float t = 0.0f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
-        ms[mode] = t;
-    }
-    long long h[6] = {0, 0, 0, 0, 0, 0};
-    if (e == hipSuccess) e = hipMemcpyAsync(h, clk, sizeof h, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    if (e != hipSuccess) return hip_fail(e, "issue-rate probe");
     int dev = 0, rtc_khz = 0, max_khz = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&rtc_khz, hipDeviceAttributeWallClockRate, dev);
     (void)hipDeviceGetAttribute(&max_khz, hipDeviceAttributeClockRate, dev);
-    // each probe's shader clock over its timing wave (the device's maximum if
-    // unreadable), so that a clock that moves between probes does not skew them
     const double simds = 4.0 * device_cus();
     const double instr = (double)blocks * 4.0 / simds * kProbeIters * 8.0;   // per SIMD
-    for (int m = 0; m < 3; ++m) {
-        double f = (rtc_khz > 0 && h[2 * m + 1] > 0) ? (double)h[2 * m] / ((double)h[2 * m + 1] / (rtc_khz * 1e3))
-                                                     : 0.0;
-        if (!(f > 1e8 && f < 1e10)) f = max_khz * 1e3;
-        out[m] = ms[m] * 1e-3 * f / instr;
-        if (m == 0) out[3] = f / 1e9;
+    // Per mode: warm-up launches (clocks settle), then three timed launches, each
+    // at its own clock (shader cycles over wall ticks of its timing wave; the
+    // device's maximum if unreadable); the median of the three is reported.
+    hipError_t e = hipSuccess;
+    double clock0 = 0.0;
+    for (int mode = 0; mode < 3 && e == hipSuccess; ++mode) {
+        for (int w = 0; w < 4 && e == hipSuccess; ++w) e = launch_probe(mode, o, clk, blocks, kProbeIters, s);
+        double cyc[3] = {0, 0, 0}, fr[3] = {0, 0, 0};
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) {
+            e = hipEventRecord(a, s);
+            if (e == hipSuccess) e = launch_probe(mode, o, clk, blocks, kProbeIters, s);
+            if (e == hipSuccess) e = hipEventRecord(b, s);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+            long long h[6] = {0, 0, 0, 0, 0, 0};
+            if (e == hipSuccess) e = hipMemcpyAsync(h, clk, sizeof h, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipStreamSynchronize(s);
+            double f = (rtc_khz > 0 && h[2 * mode + 1] > 0)
+                           ? (double)h[2 * mode] / ((double)h[2 * mode + 1] / (rtc_khz * 1e3))
+                           : 0.0;
+            if (!(f > 1e8 && f < 1e10)) f = max_khz * 1e3;
+            cyc[r] = t * 1e-3 * f / instr;
+            fr[r] = f;
+        }
+        std::sort(cyc, cyc + 3);
+        std::sort(fr, fr + 3);
+        out[mode] = cyc[1];
+        if (mode == 0) clock0 = fr[1];
     }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return hip_fail(e, "issue-rate probe");
+    out[3] = clock0 / 1e9;
     out[4] = rtc_khz / 1e3;
     return NBODY_OK;
 }

@@ -2,7 +2,8 @@
 // shader cycles a SIMD spends per wave64 FP32 FMA (all operands in VGPRs, and
 // with one SGPR operand) and per v_rsq_f32, and the shader clock while the
 // FMA probe runs.  Eight independent dependency chains per lane and eight
-// waves per SIMD keep each probe on issue throughput rather than latency.
+// waves per SIMD (the pair kernels' occupancy) keep each probe on issue
+// throughput; with fewer waves the rate drops (3.5 cycles per FMA at four).
 // Measurement support for the roofline only; no part of the force path.
 #include "probe.h"
 
