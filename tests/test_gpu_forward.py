@@ -217,3 +217,30 @@ def test_tuning_cache_round_trip(nb, tmp_path):
     other.write_text(text.replace('"arch": "gfx950"', '"arch": "gfx942"'))
     with pytest.raises(RuntimeError):
         nb.tune_load(other)
+
+
+@pytest.mark.parametrize("law_name", ["gravity", "ljc_linear"])
+def test_permutation_and_translation_invariance(nb, law_name):
+    """Permuting the particles permutes the outputs, and translating every position
+    leaves them unchanged, to FP64 rounding (FP64 path; the GPU sums in another order
+    after a permutation, so the comparison is to 1e-12 rather than bitwise)."""
+    if law_name == "gravity":
+        x, _, m = W.plummer(1500, 31)
+        par = m
+        law = nb.gravity("fp64", softening=EPS)
+        shift = np.array([3.5, -2.25, 7.0])
+    else:
+        s = W.md_system(1500, 32, box=36.0)
+        x, par = s.pos, s.params()
+        law = nb.ljc_linear("fp64")
+        shift = np.array([40.0, -25.0, 11.0])
+    f0, p0 = nb.forces(dev(x), dev(par), law)
+    perm = np.random.default_rng(33).permutation(len(x))
+    f1, p1 = nb.forces(dev(x[perm]), dev(np.asarray(par)[perm]), law)
+    f0h, p0h = host(f0), host(p0)
+    assert rel_rows(host(f1), f0h[perm]).max() <= 1e-12
+    assert rel_scalar(host(p1), p0h[perm]).max() <= 1e-12
+    f2, p2 = nb.forces(dev(x + shift), dev(par), law)
+    scale = np.abs(f0h).max()
+    assert np.abs(host(f2) - f0h).max() <= 1e-12 * scale
+    assert rel_scalar(host(p2), p0h).max() <= 1e-11
