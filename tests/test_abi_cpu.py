@@ -21,10 +21,14 @@ HEADER = os.path.join(ROOT, "include", "nbody.h")
 @pytest.fixture(scope="module")
 def N():
     from paper_0706_3060_amd import _native
-    if not os.path.exists(_native.LIB_PATH):
+    if os.environ.get("NBODY_TEST_LIB"):
+        # a sanitizer build of the same sources (tests/test_host_sanitize.py)
+        _native.LIB_PATH = os.environ["NBODY_TEST_LIB"]
+    elif not os.path.exists(_native.LIB_PATH):
         from paper_0706_3060_amd import build
         build.build(verbose=False)
     _native.lib()
+    assert any(_native.LIB_PATH in l for l in open("/proc/self/maps"))
     return _native
 
 
@@ -324,3 +328,34 @@ def test_tuning_file_is_tied_to_its_device(N, tmp_path):
     text = out.read_text()
     assert '"arch": "unknown"' in text and '"device_cus": 256' in text and '"j_split": 2' in text
     assert lib.nbody_tune_load(str(out).encode()) == 0
+
+
+def test_tuning_file_parser_refuses_malformed_files(N, tmp_path):
+    """Malformed tuning files (empty, truncated, binary, an over-long architecture
+    name, entries with invalid launch shapes, a very long run of partial entries)
+    are refused with NBODY_EINVAL; none of them may read or write out of bounds
+    (this test also runs against the sanitizer build)."""
+    lib = N.lib()
+    head = '{"arch": "unknown", "device_cus": 256, "entries": [\n'
+    good = ('{"api": 0, "law": 0, "precision": 2, "potential": 1, "n_bucket": 3, "s_bucket": 0, '
+            '"block": 256, "i_per_lane": 1, "j_tile": 256, "j_split": 1, "j_stage": 1, "ms": 2.0}')
+    cases = {
+        "empty.json": b"",
+        "truncated.json": (head + good[:60]).encode(),
+        "binary.json": bytes(range(256)) * 64,
+        "longarch.json": ('{"arch": "%s", "device_cus": 256, "entries": [%s]}' % ("g" * 5000, good)).encode(),
+        "badshape.json": (head + good.replace('"block": 256', '"block": 7') + "]}").encode(),
+        "badapi.json": (head + good.replace('"api": 0', '"api": 99') + "]}").encode(),
+        "partial_run.json": (head + '{"api": 0, ' * 20000 + "]}").encode(),
+        "noquote.json": b'{"arch": "unknown',
+    }
+    for name, data in cases.items():
+        p = tmp_path / name
+        p.write_bytes(data)
+        assert lib.nbody_tune_load(str(p).encode()) == N.NBODY_EINVAL, name
+        assert lib.nbody_last_error()
+    assert lib.nbody_tune_load(str(tmp_path / "missing.json").encode()) == N.NBODY_EINVAL
+    assert lib.nbody_tune_load(None) == N.NBODY_EINVAL
+    ok = tmp_path / "ok.json"
+    ok.write_text(head + good + "]}\n")
+    assert lib.nbody_tune_load(str(ok).encode()) == 0
