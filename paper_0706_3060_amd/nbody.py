@@ -13,6 +13,8 @@ Laws (see include/nbody.h for the full statement and citations):
                  Table 1's LJC laws, params = [N, 3] rows (q, sigma, epsilon)
 Integrators: leapfrog (kick-drift-kick), hermite (fourth-order Hermite, shared
 step) and hermite_block (Hermite with block individual steps).
+Checkpoints: save_state / load_state write and read an integrator's state as a
+plain .npz file.
 """
 from __future__ import annotations
 
@@ -327,6 +329,37 @@ def leapfrog(pos, vel, acc, params, law: Law, dt: float, nsteps: int, inv_mass=N
                                   ctypes.byref(law.c()), float(dt), int(nsteps), _ptr(p),
                                   _ptr(ws), ws.numel(), _stream(pos.device)))
     return p
+
+
+# ------------------------------------------------------------ checkpoints
+def save_state(path, **state):
+    """Write an integrator's state to the .npz file ``path``: tensors are copied to the
+    host with their dtype, plain numbers (time, step count, seeds) are stored as 0-d
+    arrays.  The integrators carry everything they need across calls (the leapfrog
+    a(t); the block scheme a, jerk, t_i and dt_i), and the kernels sum in a fixed
+    order, so a run resumed from such a file continues bit for bit."""
+    arrays = {}
+    for key, val in state.items():
+        arr = val.detach().cpu().numpy() if isinstance(val, torch.Tensor) else np.asarray(val)
+        if arr.dtype == object:
+            raise ValueError("state entry %r is neither a tensor nor a number" % key)
+        arrays[key] = arr
+    with open(path, "wb") as f:
+        np.savez(f, **arrays)
+
+
+def load_state(path, device=None):
+    """Read a file written by save_state: arrays come back as contiguous tensors on
+    ``device`` (default: the current GPU), 0-d entries as Python numbers.  Nothing
+    in the file is executed (no pickled objects are accepted)."""
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+    out = {}
+    with np.load(path, allow_pickle=False) as z:
+        for key in z.files:
+            arr = z[key]
+            out[key] = (arr.item() if arr.ndim == 0
+                        else torch.from_numpy(np.ascontiguousarray(arr)).to(device))
+    return out
 
 
 # ------------------------------------------------------- jerk and Hermite
