@@ -403,7 +403,13 @@ int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass
 /* Save / load the tuning cache as a small JSON file (host path).  The file
  * records the device's architecture name and compute-unit count; loading a
  * file written for another architecture or CU count returns NBODY_EINVAL and
- * loads nothing (tuned launch shapes do not carry over between devices). */
+ * loads nothing (tuned launch shapes do not carry over between devices).
+ *
+ * Environment: when NBODY_TUNE_CACHE names a file, the library loads it at
+ * the first configuration lookup of the process (if the file exists; a file
+ * for another device is skipped with one line on stderr) and saves the whole
+ * cache to it after every successful nbody_autotune / nbody_autotune_jerk, so
+ * tuned shapes carry over between processes on the same device. */
 int nbody_tune_save(const char *path);
 int nbody_tune_load(const char *path);
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -323,9 +324,41 @@ bool is_batched_api(int api) { return api == NBODY_API_BATCHED || api == NBODY_A
 // is not served the configuration tuned for a whole system of that row count).
 int tune_sbucket(int api, int64_t S, int64_t nj) { return size_bucket(is_batched_api(api) ? S : nj); }
 
+// NBODY_TUNE_CACHE names a tuning file shared between processes: it is read at
+// the first configuration lookup of the process (when it exists) and written
+// again after every autotuning run.  A file tuned on another device is not
+// used (one stderr line says why) and is replaced by the next run's results.
+const char *tune_cache_path()
+{
+    const char *p = getenv("NBODY_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+void tune_cache_load_once()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const char *p = tune_cache_path();
+        if (!p) return;
+        FILE *f = fopen(p, "r");
+        if (!f) return;  // nothing tuned yet
+        fclose(f);
+        if (nbody_tune_load(p) != NBODY_OK)
+            fprintf(stderr, "nbody: tuning cache %s not used: %s\n", p, nbody_last_error());
+    });
+}
+
+void tune_cache_store()
+{
+    const char *p = tune_cache_path();
+    if (p && nbody_tune_save(p) != NBODY_OK)
+        fprintf(stderr, "nbody: tuning cache %s not written: %s\n", p, nbody_last_error());
+}
+
 // The configuration for n output rows in S systems; nj j records (0: nj = n).
 Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot, int64_t nj = 0)
 {
+    tune_cache_load_once();
     if (nj <= 0) nj = n;
     const int64_t npad = round_up(std::max<int64_t>(std::max(n, nj), 1), 64);
     std::lock_guard<std::mutex> lk(g_mu);
@@ -1857,6 +1890,7 @@ int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass
     int rc = validate_jerk_law(law);
     if (rc) return rc;
     if (n <= 0) return fail(NBODY_EINVAL, "nothing to tune");
+    tune_cache_load_once();
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
@@ -1904,6 +1938,7 @@ int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass
                         size_bucket(n), tune_sbucket(NBODY_API_JERK, 1, n))] = {best, best_ms};
         ++g_cfg_version;
     }
+    tune_cache_store();
     rc = jerk_impl(pos, vel, mass, n, nullptr, n, law, out_acc, out_jerk, out_potential, ws, ws_bytes,
                    stream, &best);
     if (rc) return rc;
@@ -1963,6 +1998,7 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
         S = n_systems;
     }
     if (ntot <= 0) return fail(NBODY_EINVAL, "nothing to tune");
+    tune_cache_load_once();
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
@@ -2013,6 +2049,7 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
                         tune_sbucket(api, S, ntot))] = {best, best_ms};
         ++g_cfg_version;
     }
+    tune_cache_store();
     // leave the winner's result in the outputs
     rc = api == NBODY_API_FORCES
              ? forces_impl(pos, params, n, nullptr, n, law, out_force, out_potential, ws, ws_bytes,

@@ -359,3 +359,46 @@ def test_tuning_file_parser_refuses_malformed_files(N, tmp_path):
     ok = tmp_path / "ok.json"
     ok.write_text(head + good + "]}\n")
     assert lib.nbody_tune_load(str(ok).encode()) == 0
+
+
+def test_tune_cache_environment_variable(N, tmp_path):
+    """NBODY_TUNE_CACHE: a tuning file named there is read at the first configuration
+    lookup of a process (checked in a child process, since the read happens once per
+    process); without it the same lookup gives the built-in rule."""
+    import subprocess
+    import sys
+    entry = ('{"api": 0, "law": 0, "precision": 2, "potential": 1, "n_bucket": 13, "s_bucket": 13, '
+             '"block": 128, "i_per_lane": 2, "j_tile": 128, "j_split": 3, "j_stage": 1, "ms": 1.0}')
+    cache = tmp_path / "cache.json"
+    cache.write_text('{"arch": "unknown", "device_cus": 256, "entries": [\n  %s\n]}\n' % entry)
+    code = (
+        "import ctypes, sys\n"
+        "sys.path.insert(0, %r)\n"
+        "from paper_0706_3060_amd import _native as N\n"
+        "import os\n"
+        "if os.environ.get('NBODY_TEST_LIB'): N.LIB_PATH = os.environ['NBODY_TEST_LIB']\n"
+        "law = N.NBodyLaw(0, 2, 1.0, 0.01, 0.0, 1.0)\n"
+        "c = N.NBodyConfig()\n"
+        "assert N.lib().nbody_get_config(0, 5000, 1, ctypes.byref(law), ctypes.byref(c)) == 0\n"
+        "print(c.block, c.i_per_lane, c.j_tile, c.j_split, c.j_stage)\n" % ROOT)
+
+    def lookup(env_value):
+        env = dict(os.environ)
+        env.pop("NBODY_TUNE_CACHE", None)
+        if env_value is not None:
+            env["NBODY_TUNE_CACHE"] = env_value
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return r.stdout.split(), r.stderr
+
+    tuned, _ = lookup(str(cache))
+    assert tuned == ["128", "2", "128", "3", "1"]
+    builtin, _ = lookup(None)
+    assert builtin != tuned
+    missing, err = lookup(str(tmp_path / "not_yet_written.json"))
+    assert missing == builtin and "tuning cache" not in err
+    other = tmp_path / "other.json"
+    other.write_text(cache.read_text().replace('"arch": "unknown"', '"arch": "gfx942"'))
+    refused, err = lookup(str(other))
+    assert refused == builtin and "not used" in err

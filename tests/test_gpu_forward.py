@@ -5,6 +5,8 @@ Tolerances: FP64 paths <= 1e-12 in the maximum per-particle relative error;
 FP32 paths median <= 1e-5 and maximum <= 1e-3, measured against the oracle fed
 the FP32-rounded inputs (so input quantisation is not counted).
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -244,3 +246,28 @@ def test_permutation_and_translation_invariance(nb, law_name):
     scale = np.abs(f0h).max()
     assert np.abs(host(f2) - f0h).max() <= 1e-12 * scale
     assert rel_scalar(host(p2), p0h).max() <= 1e-11
+
+
+def test_tune_cache_environment_variable_carries_over(nb, tmp_path):
+    """With NBODY_TUNE_CACHE set, an autotuning run writes the file and a later process
+    reads it back: its lookup returns the tuned configuration (two child processes,
+    one after the other)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "cache.json"
+    common = ("import sys; sys.path.insert(0, %r)\n"
+              "import torch\n"
+              "from paper_0706_3060_amd import nbody as nb, workloads as W\n"
+              "law = nb.gravity('fp32_kahan', softening=0.01)\n" % root)
+    tune = common + ("x, _, m = W.plummer(3000, 61)\n"
+                     "cfg, ms = nb.autotune(torch.tensor(x, device='cuda'), torch.tensor(m, device='cuda'), law)\n"
+                     "print(sorted(cfg.items()))\n")
+    look = common + "print(sorted(nb.get_config(nb.API_FORCES, 3000, law).items()))\n"
+    env = dict(os.environ, NBODY_TUNE_CACHE=str(cache))
+    r1 = subprocess.run([sys.executable, "-c", tune], capture_output=True, text=True, env=env, timeout=240)
+    assert r1.returncode == 0, r1.stderr[-2000:]
+    assert cache.exists() and '"arch": "gfx950"' in cache.read_text()
+    r2 = subprocess.run([sys.executable, "-c", look], capture_output=True, text=True, env=env, timeout=240)
+    assert r2.returncode == 0, r2.stderr[-2000:]
+    assert r2.stdout.split() == r1.stdout.split()
