@@ -80,6 +80,31 @@ __device__ __forceinline__ void finish_row(const Epilogue &e, int64_t r, double 
 }
 
 // ------------------------------------------------------------- all pairs ----
+// Block -> (row block, j part).  The dispatcher hands workgroups to the eight
+// XCDs in turn (linear block id mod 8), each XCD with its own L2.  When the part
+// count S is a multiple of 8, XCD x owns the S/8 parts x, x + 8, x + 16, ...,
+// and takes them for one row block after another: its L2 then holds those
+// parts' j segments (npad/8 records, 2 MiB at N = 2^20 in FP32, whatever S)
+// and each row block's i records, so both are fetched from HBM about once per
+// XCD.  Otherwise the grid is taken as (row block, part) directly.  Either way
+// each (row block, part) pair is visited once, and the sums do not depend on
+// the mapping.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ void block_tile(int64_t &rblock, int64_t &part)
+{
+    const int64_t gx = gridDim.x, gy = gridDim.y;
+    if (gy % kXcds != 0) {
+        rblock = blockIdx.x;
+        part = blockIdx.y;
+        return;
+    }
+    const int64_t L = (int64_t)blockIdx.y * gx + blockIdx.x;
+    const int64_t k = L / kXcds, per_xcd = gy / kXcds;
+    part = L % kXcds + kXcds * (k % per_xcd);
+    rblock = k / per_xcd;
+}
+
 // One wave's rows against the j range of its split (EX: with exclusion lists,
 // LDS staging only).
 template <int LAW, int PREC, int I, bool POT, int JS, bool EX>
@@ -95,11 +120,12 @@ __device__ __forceinline__ void forces_body(
     constexpr int NC = POT ? 4 : 3;
 
     const int lane = lane_id();
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) +
-                         __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int64_t rblock, part;
+    block_tile(rblock, part);
+    const int64_t wave = rblock * (blockDim.x >> 6) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t rbase = wave * (int64_t)(kWave * I);
     if (rbase >= nrows) return;
-    const int64_t jb = (int64_t)blockIdx.y * split_len;
+    const int64_t jb = part * split_len;
     const int64_t je = (jb + split_len < npad) ? jb + split_len : npad;
 
     IS is[I];
@@ -139,7 +165,7 @@ __device__ __forceinline__ void forces_body(
         const double v0 = acc[k][0].value(), v1 = acc[k][1].value(), v2 = acc[k][2].value();
         const double v3 = POT ? acc[k][NC - 1].value() : 0.0;
         if (partial) {
-            double *o = partial + ((int64_t)blockIdx.y * nrows + r) * 4;
+            double *o = partial + (part * nrows + r) * 4;
             o[0] = v0;
             o[1] = v1;
             o[2] = v2;
