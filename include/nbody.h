@@ -151,7 +151,9 @@ typedef struct nbody_exclusions {
  *             compensated running sum: a multiple of 64;
  *  j_split    number of disjoint j ranges evaluated by separate waves and
  *             added afterwards in a fixed order (the i-replication of
- *             Section 3.4), 1..64.  Ignored by the batched entry point;
+ *             Section 3.4), 1..64; a launch uses at most one part per 64
+ *             j records and at most 2^25 / rows parts (the partial buffer of
+ *             the workspace).  Ignored by the batched entry point;
  *  j_stage    how j records reach the arithmetic: 0 = wave-uniform scalar
  *             loads into SGPRs, 1 = a wave-private LDS slot read back as
  *             broadcasts into VGPRs (so the pair arithmetic has only VGPR

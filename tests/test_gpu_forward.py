@@ -115,9 +115,11 @@ def test_fp32_plain_ablation_runs(nb):
 
 
 # ------------------------------------------------------- configurations
+# splits that are multiples of 8 take the XCD-ordered block mapping (8, 24, 32, 64), the
+# others the plain (row block, part) grid
 CONFIGS = [(64, 1, 64, 1, 0), (256, 2, 256, 3, 0), (128, 4, 128, 7, 0), (256, 8, 512, 2, 0),
            (64, 1, 1024, 64, 0), (256, 1, 256, 1, 1), (128, 2, 64, 5, 1), (256, 4, 512, 2, 1),
-           (64, 1, 64, 64, 1)]
+           (64, 1, 64, 64, 1), (256, 1, 256, 24, 1), (128, 2, 256, 8, 0), (256, 1, 256, 32, 1)]
 
 
 @pytest.mark.parametrize("cfg", CONFIGS)
