@@ -79,7 +79,7 @@ def gpu_law(nb, law, prec):
     return nb.ljc_sigmoidal(ZC, prec)
 
 
-@settings(max_examples=60, deadline=None, derandomize=True, database=None,
+@settings(max_examples=150, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(n=st.integers(min_value=0, max_value=700),
        law=st.sampled_from(["gravity", "ljc_linear", "ljc_constant", "ljc_sigmoidal"]),
