@@ -17,7 +17,9 @@ Printed (one JSON line on stdout):
   * the issue-rate ceiling of the pair sequence from the library's probes;
   * the oracle timed on a bounded row sample on the host cores;
   * the accuracy of the timed path against the FP64 GPU pass and the oracle;
-and, by default, secondary legs: the batched ensemble (256 LJC systems, N_s in
+and, by default, secondary legs: one GPU's share of the headline evaluation if its
+rows were sharded over 8 GPUs (N/8 rows against all N j records); the batched
+ensemble (256 LJC systems, N_s in
 [500, 5000], one persistent launch vs one launch per system, each side autotuned);
 the position adjoint at N = 262,144 (FP32 vs FP64); every pair law of Table 1 at
 N = 65,536; the acceleration-and-jerk kernel and the block-time-step Hermite
@@ -241,6 +243,7 @@ def main():
     }
 
     if args.legs == "all":
+        out["shard_share"] = shard_leg(nb, torch, dev, x, m, law, k_ms / max(k_launches, 1))
         out["batched"] = batched_leg(nb, torch, dev, ens)
         out["backward"] = backward_leg(nb, torch, dev, W)
         out["laws"] = laws_leg(nb, torch, dev, W, md)
@@ -343,6 +346,32 @@ def measured_traffic(n, cfg):
         if rec.get("sources_sha256") == h and rec.get("config") == cfg and rec.get("n") == n:
             return rec["bytes_per_launch"]
     return None
+
+
+def shard_leg(nb, torch, dev, x, m, law, full_kernel_ms, n_gpus=8):
+    """One GPU's share of the headline evaluation if the rows were sharded over n_gpus GPUs:
+    a contiguous block of N / n_gpus output rows against all N j records
+    (nbody_forces_subset), for the first and the last block.  Its kernel time against
+    1 / n_gpus of the full launch tells how well the share alone fills the chip."""
+    n = x.shape[0]
+    rows = n // n_gpus
+    res = {"n": n, "gpus": n_gpus, "rows": rows, "full_kernel_ms": full_kernel_ms}
+    for name, r0 in (("first", 0), ("last", n - rows)):
+        il = torch.arange(r0, r0 + rows, dtype=torch.int64, device=dev)
+        nb.forces_subset(x, m, il, law)
+        torch.cuda.synchronize()
+        nb.timing_read(reset=True)
+        nb.timing_enable(True)
+        for _ in range(2):
+            nb.forces_subset(x, m, il, law)
+        torch.cuda.synchronize()
+        nb.timing_enable(False)
+        k_ms, k_n = nb.timing_read(reset=True)
+        ms = k_ms / max(k_n, 1)
+        res[name] = {"kernel_ms": ms, "g_pairs_per_s": float(rows) * n / (ms * 1e-3) / 1e9,
+                     "efficiency_vs_full": full_kernel_ms / n_gpus / ms}
+    log("shard share:", res)
+    return res
 
 
 def batched_leg(nb, torch, dev, ens):
