@@ -80,9 +80,9 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        msg = ("bench.py measures one GPU: this build has no multi-GPU path (the forward would "
-               "shard the i range and all-gather the FP32 j records; see the design notes). "
-               "Run with --gpus 1.")
+        msg = ("bench.py measures one GPU: the library has no multi-GPU path (the forward would "
+               "shard the i range and all-gather the FP32 j records; the shard_share leg times "
+               "one GPU's share). Run with --gpus 1.")
         log(msg)
         if int(os.environ.get("RANK", "0")) == 0:
             print(json.dumps({"error": msg, "n_gpus": args.gpus}))

@@ -13,8 +13,8 @@
  * the dominant error when force terms cancel.  OpenMP runs over i only; the
  * j order is 0..N-1 for every i, so results do not depend on thread count.
  *
- * Readings of the paper used here (each is listed with its reason in the
- * design notes):
+ * Readings of the paper used here, where it is silent or its printed form is
+ * ambiguous:
  *   - displacement d_ij = r_j - r_i; gravity attracts (Eq. 1 with the
  *     Appendix listing's d = jpos - ipos and "+=");
  *   - the softening constant added to r^2 in the Appendix listing is eps^2,
