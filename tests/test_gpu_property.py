@@ -1,5 +1,5 @@
-"""Property-based GPU parity: random small systems, laws, precisions and forced launch
-configurations against the FP64 oracle.
+"""Property-based GPU parity: random small systems and ensembles, laws, precisions and
+forced launch configurations against the FP64 oracle.
 
 Each example draws a size (0 to 700 particles, so ragged tails of every kind), a law, a
 precision and a launch configuration (block, rows per lane, j tile, j split, j staging;
@@ -8,8 +8,10 @@ forward through the C ABI, and compares with the oracle on the same inputs:
 FP64 paths to 1e-12 per row, FP32 paths median <= 1e-5 and maximum <= 1e-3 (against
 the oracle fed the FP32-rounded inputs).  Row errors are taken relative to
 max(|F_i|, 1e-3 max_j |F_j|), so that a row whose force nearly cancels is held to the
-scale of the system rather than to its own tiny norm.  Examples are drawn from a fixed
-seed (derandomize), so every run checks the same cases.
+scale of the system rather than to its own tiny norm.  The batched test draws ensembles of
+up to 24 systems of 0 to 400 particles (empty and one-particle systems included) for the
+persistent launch and compares each system with its own oracle call.  Examples are drawn
+from a fixed seed (derandomize), so every run checks the same cases.
 """
 import numpy as np
 import pytest
@@ -119,3 +121,59 @@ def test_random_systems_and_configurations(nb, n, law, prec, block, ipl, j_tile,
             assert ep.max() <= 1e-12, (ep.max(), n, law, prec)
         else:
             assert np.median(ep) <= 1e-5 and ep.max() <= 1e-3, (np.median(ep), ep.max(), n, law, prec)
+
+
+def ensemble(law, sizes, seed):
+    """Concatenated independent systems of the given sizes (empty ones included)."""
+    xs, ps = [], []
+    for k, n in enumerate(sizes):
+        if n == 0:
+            xs.append(np.zeros((0, 3)))
+            ps.append(np.zeros(0) if law == "gravity" else np.zeros((0, 3)))
+        else:
+            x, par = inputs(law, n, seed + k)
+            xs.append(x)
+            ps.append(np.asarray(par))
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    if not sizes:
+        return off, np.zeros((0, 3)), (np.zeros(0) if law == "gravity" else np.zeros((0, 3)))
+    return off, np.concatenate(xs), np.concatenate(ps)
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+@given(sizes=st.lists(st.integers(min_value=0, max_value=400), min_size=0, max_size=24),
+       law=st.sampled_from(["gravity", "ljc_linear", "ljc_constant", "ljc_sigmoidal"]),
+       prec=st.sampled_from(["fp64", "fp32_kahan", "fp32_fp64acc"]),
+       block=st.sampled_from([64, 128, 256]),
+       ipl=st.sampled_from([1, 2, 4]),
+       j_tile=st.sampled_from([64, 256]),
+       j_stage=st.sampled_from([0, 1]),
+       seed=st.integers(min_value=0, max_value=10 ** 6))
+def test_random_batches(nb, sizes, law, prec, block, ipl, j_tile, j_stage, seed):
+    """The persistent batched launch over random ensembles (empty and one-particle systems
+    included) with a forced configuration equals the oracle system by system."""
+    lw = gpu_law(nb, law, prec)
+    off, x, par = ensemble(law, sizes, seed)
+    try:
+        nb.set_config(nb.API_BATCHED, block, ipl, j_tile, 1, j_stage)
+        f, p = nb.forces_batched(off, dev(x), dev(par), lw)
+    finally:
+        nb.clear_config(nb.API_BATCHED)
+    assert tuple(f.shape) == (int(off[-1]), 3)
+    f, p = host(f), host(p)
+    for s in range(len(sizes)):
+        a, b = int(off[s]), int(off[s + 1])
+        if b - a == 0:
+            continue
+        if b - a == 1:
+            assert np.all(f[a:b] == 0) and np.all(p[a:b] == 0)
+            continue
+        fr, pr = reference(law, x[a:b], par[a:b], prec)
+        e = row_errors(f[a:b], fr)
+        ep = np.abs(p[a:b] - pr) / max(np.abs(pr).max(), 1e-300)
+        if prec == "fp64":
+            assert e.max() <= 1e-12 and ep.max() <= 1e-12, (s, e.max(), ep.max(), law, prec)
+        else:
+            assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (s, np.median(e), e.max(), law, prec)
+            assert np.median(ep) <= 1e-5 and ep.max() <= 1e-3, (s, np.median(ep), ep.max(), law, prec)
