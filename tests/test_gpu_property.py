@@ -10,7 +10,8 @@ the oracle fed the FP32-rounded inputs).  Row errors are taken relative to
 max(|F_i|, 1e-3 max_j |F_j|), so that a row whose force nearly cancels is held to the
 scale of the system rather than to its own tiny norm.  The batched test draws ensembles of
 up to 24 systems of 0 to 400 particles (empty and one-particle systems included) for the
-persistent launch and compares each system with its own oracle call.  Examples are drawn
+persistent launch and compares each system with its own oracle call; the adjoint and the
+acceleration-and-jerk tests do the same for those kernels.  Examples are drawn
 from a fixed seed (derandomize), so every run checks the same cases.
 """
 import numpy as np
@@ -177,3 +178,91 @@ def test_random_batches(nb, sizes, law, prec, block, ipl, j_tile, j_stage, seed)
         else:
             assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (s, np.median(e), e.max(), law, prec)
             assert np.median(ep) <= 1e-5 and ep.max() <= 1e-3, (s, np.median(ep), ep.max(), law, prec)
+
+
+def rel_to_max(got, ref):
+    return np.abs(got - ref) / max(np.abs(ref).max(), 1e-300)
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+@given(n=st.integers(min_value=2, max_value=400),
+       law=st.sampled_from(["gravity", "ljc_linear"]),
+       prec=st.sampled_from(["fp64", "fp32_kahan", "fp32_fp64acc"]),
+       block=st.sampled_from([64, 128, 256]),
+       ipl=st.sampled_from([1, 2]),
+       j_tile=st.sampled_from([64, 256]),
+       j_split=st.integers(min_value=1, max_value=16),
+       j_stage=st.sampled_from([0, 1]),
+       seed=st.integers(min_value=0, max_value=10 ** 6))
+def test_random_adjoints(nb, n, law, prec, block, ipl, j_tile, j_split, j_stage, seed):
+    """The adjoint (gravity: dL/dpos; LJC(linear): dL/dpos and dL/d(q, sigma, eps)) on random
+    systems under a forced configuration against the oracle's analytic adjoint (FP64:
+    1e-10 of the scale, the cancelling sums of the adjoint; FP32 as the forward)."""
+    lw = gpu_law(nb, law, prec)
+    x, par = inputs(law, n, seed)
+    g = W.unit_cotangent(n, seed + 1)
+    try:
+        nb.set_config(nb.API_BACKWARD, block, ipl, j_tile, j_split, j_stage)
+        gp, gq, _ = nb.forces_backward(dev(x), dev(par), dev(g), lw)
+    finally:
+        nb.clear_config(nb.API_BACKWARD)
+    xr = x if prec == "fp64" else W.round_to_f32(x)
+    if law == "gravity":
+        assert gq is None
+        refs = [(host(gp), oracle.gravity_adjoint(xr, par, g, eps=EPS), True)]
+    else:
+        rp, rq, rs, re = oracle.ljc_adjoint(xr, par[:, 0], par[:, 1], par[:, 2], g)
+        gq = host(gq)
+        refs = [(host(gp), rp, True), (gq[:, 0], rq, False), (gq[:, 1], rs, False), (gq[:, 2], re, False)]
+    for got, ref, rows in refs:
+        e = row_errors(got, ref) if rows else rel_to_max(got, ref)
+        if prec == "fp64":
+            assert e.max() <= 1e-10, (e.max(), n, law, prec)
+        else:
+            assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max(), n, law, prec)
+
+
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+@given(n=st.integers(min_value=1, max_value=500),
+       prec=st.sampled_from(["fp64", "fp32_kahan", "fp32_fp64acc"]),
+       block=st.sampled_from([64, 128, 256]),
+       ipl=st.sampled_from([1, 2]),
+       j_tile=st.sampled_from([64, 256]),
+       j_split=st.integers(min_value=1, max_value=32),
+       j_stage=st.sampled_from([0, 1]),
+       potential=st.booleans(),
+       subset=st.booleans(),
+       seed=st.integers(min_value=0, max_value=10 ** 6))
+def test_random_jerk(nb, n, prec, block, ipl, j_tile, j_split, j_stage, potential, subset, seed):
+    """Acceleration, jerk and potential (Table 1 "Gravity (accel & jerk)") on random Plummer
+    spheres, for all rows or a random row subset, under a forced configuration, against the
+    oracle."""
+    x, v, m = W.plummer(n, seed)
+    rows = None
+    if subset:
+        rng = np.random.default_rng(seed + 2)
+        rows = np.sort(rng.choice(n, max(1, n // 3), replace=False)).astype(np.int64)
+    lw = nb.gravity(prec, softening=EPS)
+    try:
+        nb.set_config(nb.API_JERK, block, ipl, j_tile, j_split, j_stage)
+        a, j, p = nb.forces_jerk(dev(x), dev(v), dev(m), lw,
+                                 ilist=None if rows is None else torch.tensor(rows, device="cuda"),
+                                 potential=potential)
+    finally:
+        nb.clear_config(nb.API_JERK)
+    assert (p is not None) == potential
+    if prec == "fp64":
+        ra, rj, rp = oracle.gravity_jerk(x, v, m, eps=EPS, ilist=rows)
+    else:
+        ra, rj, rp = oracle.gravity_jerk(W.round_to_f32(x), W.round_to_f32(v), W.round_to_f32(m),
+                                         eps=EPS, ilist=rows)
+    checks = [row_errors(host(a), ra), row_errors(host(j), rj)]
+    if potential:
+        checks.append(rel_to_max(host(p), rp))
+    for e in checks:
+        if prec == "fp64":
+            assert e.max() <= 1e-12, (e.max(), n, prec)
+        else:
+            assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max(), n, prec)
