@@ -12,7 +12,8 @@ scale of the system rather than to its own tiny norm; potentials are held to the
 |U_i| of the system (FP32 ones from 16 particles up, see below).  The batched test draws ensembles of
 up to 24 systems of 0 to 400 particles (empty and one-particle systems included) for the
 persistent launch and compares each system with its own oracle call; the adjoint and the
-acceleration-and-jerk tests do the same for those kernels.  Examples are drawn
+acceleration-and-jerk, exclusion-list and integrator tests do the same for those paths.
+Examples are drawn
 from a fixed seed (derandomize), so every run checks the same cases.
 """
 import numpy as np
@@ -325,3 +326,68 @@ def test_random_exclusions(nb, n, law, prec, max_partners, block, ipl, j_tile, j
     else:
         assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max(), n, law, prec)
     check_potential(host(p), pr, prec, n, (n, law, prec))
+
+
+@settings(max_examples=30, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+@given(n=st.integers(min_value=2, max_value=300),
+       law=st.sampled_from(["gravity", "ljc_linear", "ljc_constant"]),
+       nsteps=st.integers(min_value=1, max_value=4),
+       with_inv_mass=st.booleans(),
+       j_split=st.integers(min_value=1, max_value=16),
+       j_stage=st.sampled_from([0, 1]),
+       seed=st.integers(min_value=0, max_value=10 ** 6))
+def test_random_leapfrog(nb, n, law, nsteps, with_inv_mass, j_split, j_stage, seed):
+    """FP64 kick-drift-kick steps (the update of the simulation cycle) on random systems
+    under a forced configuration against the oracle's: positions and velocities to 1e-12
+    of their scale, accelerations and potentials as the forward."""
+    x, par = inputs(law, n, seed)
+    rng = np.random.default_rng(seed + 4)
+    if law == "gravity":
+        v, dt, inv = rng.normal(0.0, 0.3, (n, 3)), 1e-3, None
+    else:
+        v, dt = rng.normal(0.0, 0.01, (n, 3)), 2e-4
+        inv = rng.uniform(1.0 / 16.0, 1.0 / 12.0, n) if with_inv_mass else None
+    lw = gpu_law(nb, law, "fp64")
+    okind = {"gravity": oracle.GRAVITY, "ljc_linear": oracle.LJC_LINEAR,
+             "ljc_constant": oracle.LJC_CONSTANT}[law]
+    a0, _ = reference(law, x, par, "fp64")
+    if inv is not None:
+        a0 = a0 * inv[:, None]
+    X, V, A = dev(x), dev(v), dev(a0)
+    try:
+        nb.set_config(nb.API_LEAPFROG, 256, 1, 256, j_split, j_stage)
+        pot = nb.leapfrog(X, V, A, dev(par), lw, dt, nsteps,
+                          inv_mass=None if inv is None else dev(inv), potential=True)
+    finally:
+        nb.clear_config(nb.API_LEAPFROG)
+    xr, vr, ar, pr = oracle.leapfrog(okind, x, v, a0, par, dt, nsteps, inv_mass=inv, eps=EPS)
+    assert np.abs(host(X) - xr).max() <= 1e-12 * np.abs(xr).max()
+    assert np.abs(host(V) - vr).max() <= 1e-12 * max(np.abs(vr).max(), 1e-300)
+    assert row_errors(host(A), ar).max() <= 1e-12
+    check_potential(host(pot), pr, "fp64", n, (n, law))
+
+
+@settings(max_examples=20, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+@given(n=st.integers(min_value=2, max_value=300),
+       nsteps=st.integers(min_value=1, max_value=4),
+       j_split=st.integers(min_value=1, max_value=16),
+       seed=st.integers(min_value=0, max_value=10 ** 6))
+def test_random_hermite(nb, n, nsteps, j_split, seed):
+    """FP64 shared-step Hermite steps on random Plummer spheres under a forced split against
+    the oracle's."""
+    x, v, m = W.plummer(n, seed)
+    lw = nb.gravity("fp64", softening=EPS)
+    a0, j0, _ = oracle.gravity_jerk(x, v, m, eps=EPS)
+    X, V, A, J = dev(x), dev(v), dev(a0), dev(j0)
+    try:
+        nb.set_config(nb.API_HERMITE, 256, 1, 1024, j_split, 0)
+        nb.hermite(X, V, A, J, dev(m), lw, 1.0 / 1024, nsteps)
+    finally:
+        nb.clear_config(nb.API_HERMITE)
+    xr, vr, ar, jr = oracle.hermite(x, v, a0, j0, m, 1.0 / 1024, nsteps, eps=EPS)
+    assert np.abs(host(X) - xr).max() <= 1e-12 * np.abs(xr).max()
+    assert np.abs(host(V) - vr).max() <= 1e-12 * np.abs(vr).max()
+    assert row_errors(host(A), ar).max() <= 1e-11
+    assert row_errors(host(J), jr).max() <= 1e-10
