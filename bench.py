@@ -238,7 +238,10 @@ def main():
                          "kind": "oracle",
                          "sample": "%d random rows of the N=%d Plummer workload against all N "
                                    "(FP64 oracle, compensated sums), %.1f s" % (k_rows, n, t_cpu),
-                         "one_thread_value": one_value, "one_thread_sample_rows": k1, "host": host},
+                         "one_thread_value": one_value, "one_thread_sample_rows": k1, "host": host,
+                         "extrapolated_full_evaluation_s": pairs / (cpu_value * 1e9),
+                         "extrapolated_full_evaluation_note": "N^2 pairs at the sampled rate, "
+                                                              "extrapolated, not timed"},
         "accuracy": acc,
     }
 
