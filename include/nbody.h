@@ -406,6 +406,8 @@ int nbody_autotune_jerk(const double *pos, const double *vel, const double *mass
  * records the device's architecture name and compute-unit count; loading a
  * file written for another architecture or CU count returns NBODY_EINVAL and
  * loads nothing (tuned launch shapes do not carry over between devices).
+ * Saving writes a temporary file beside `path` and renames it over `path`, so
+ * a concurrent reader sees the old file or the new one, never part of one.
  *
  * Environment: when NBODY_TUNE_CACHE names a file, the library loads it at
  * the first configuration lookup of the process (if the file exists; a file

@@ -17,6 +17,8 @@
 #include <tuple>
 #include <vector>
 
+#include <unistd.h>
+
 #include "../../include/nbody.h"
 #include "adjoint.h"
 #include "jerk.h"
@@ -2078,8 +2080,11 @@ int nbody_autotune(int32_t api, const int64_t *offsets, int64_t n_systems, const
 int nbody_tune_save(const char *path)
 {
     if (!path) return fail(NBODY_EINVAL, "path is NULL");
-    FILE *f = fopen(path, "w");
-    if (!f) return fail(NBODY_EINVAL, "cannot open %s", path);
+    // written beside the target and renamed over it, so that a reader (another
+    // process sharing the file) never sees a partly written file
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string((long long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(NBODY_EINVAL, "cannot open %s", tmp.c_str());
     const std::string arch = device_arch();
     const int cus = device_cus();
     std::lock_guard<std::mutex> lk(g_mu);
@@ -2097,7 +2102,15 @@ int nbody_tune_save(const char *path)
                 (++k < g_tuned.size()) ? "," : "");
     }
     fprintf(f, "]}\n");
-    fclose(f);
+    const bool written = !ferror(f);
+    if (fclose(f) != 0 || !written) {
+        remove(tmp.c_str());
+        return fail(NBODY_EINVAL, "cannot write %s", tmp.c_str());
+    }
+    if (rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        return fail(NBODY_EINVAL, "cannot replace %s", path);
+    }
     return NBODY_OK;
 }
 

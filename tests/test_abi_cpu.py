@@ -402,3 +402,17 @@ def test_tune_cache_environment_variable(N, tmp_path):
     other.write_text(cache.read_text().replace('"arch": "unknown"', '"arch": "gfx942"'))
     refused, err = lookup(str(other))
     assert refused == builtin and "not used" in err
+
+
+def test_tuning_file_save_is_atomic(N, tmp_path):
+    """nbody_tune_save writes beside the target and renames over it: no temporary file is
+    left behind, an existing file is replaced whole, and a path in a missing directory is
+    refused with NBODY_EINVAL."""
+    lib = N.lib()
+    target = tmp_path / "cache.json"
+    target.write_text("old contents")
+    assert lib.nbody_tune_save(str(target).encode()) == 0
+    assert target.read_text().startswith('{"arch": ')
+    assert sorted(p.name for p in tmp_path.iterdir()) == ["cache.json"]
+    assert lib.nbody_tune_save(str(tmp_path / "missing" / "cache.json").encode()) == N.NBODY_EINVAL
+    assert sorted(p.name for p in tmp_path.iterdir()) == ["cache.json"]
