@@ -98,7 +98,7 @@ def gpu_law(nb, law, prec):
     return nb.ljc_sigmoidal(ZC, prec)
 
 
-@settings(max_examples=150, deadline=None, derandomize=True, database=None,
+@settings(max_examples=300, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(n=st.integers(min_value=0, max_value=700),
        law=st.sampled_from(["gravity", "ljc_linear", "ljc_constant", "ljc_sigmoidal"]),
@@ -153,7 +153,7 @@ def ensemble(law, sizes, seed):
     return off, np.concatenate(xs), np.concatenate(ps)
 
 
-@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+@settings(max_examples=80, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(sizes=st.lists(st.integers(min_value=0, max_value=400), min_size=0, max_size=24),
        law=st.sampled_from(["gravity", "ljc_linear", "ljc_constant", "ljc_sigmoidal"]),
@@ -195,7 +195,7 @@ def rel_to_max(got, ref):
     return np.abs(got - ref) / max(np.abs(ref).max(), 1e-300)
 
 
-@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+@settings(max_examples=80, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(n=st.integers(min_value=2, max_value=400),
        law=st.sampled_from(["gravity", "ljc_linear"]),
@@ -234,7 +234,7 @@ def test_random_adjoints(nb, n, law, prec, block, ipl, j_tile, j_split, j_stage,
             assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max(), n, law, prec)
 
 
-@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+@settings(max_examples=80, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(n=st.integers(min_value=1, max_value=500),
        prec=st.sampled_from(["fp64", "fp32_kahan", "fp32_fp64acc"]),
@@ -282,7 +282,7 @@ def test_random_jerk(nb, n, prec, block, ipl, j_tile, j_split, j_stage, potentia
 KINDS = {"ljc_linear": 1, "ljc_constant": 2, "ljc_sigmoidal": 3}
 
 
-@settings(max_examples=40, deadline=None, derandomize=True, database=None,
+@settings(max_examples=80, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(n=st.integers(min_value=2, max_value=300),
        law=st.sampled_from(["ljc_linear", "ljc_constant", "ljc_sigmoidal"]),
@@ -328,7 +328,7 @@ def test_random_exclusions(nb, n, law, prec, max_partners, block, ipl, j_tile, j
     check_potential(host(p), pr, prec, n, (n, law, prec))
 
 
-@settings(max_examples=30, deadline=None, derandomize=True, database=None,
+@settings(max_examples=60, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(n=st.integers(min_value=2, max_value=300),
        law=st.sampled_from(["gravity", "ljc_linear", "ljc_constant"]),
@@ -368,7 +368,7 @@ def test_random_leapfrog(nb, n, law, nsteps, with_inv_mass, j_split, j_stage, se
     check_potential(host(pot), pr, "fp64", n, (n, law))
 
 
-@settings(max_examples=20, deadline=None, derandomize=True, database=None,
+@settings(max_examples=40, deadline=None, derandomize=True, database=None,
           suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
 @given(n=st.integers(min_value=2, max_value=300),
        nsteps=st.integers(min_value=1, max_value=4),
