@@ -69,6 +69,9 @@ def main():
                          "configuration); implies no autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target host time of the oracle sample")
+    ap.add_argument("--save-inputs", default=None, metavar="DIR",
+                    help="also write the drawn inputs (headline Plummer sphere; with the default "
+                         "legs the ensemble and the per-law MD box) as .npy files into DIR")
     ap.add_argument("--make-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "BENCH_JSON"),
                     help="no GPU work: write the traffic record of the headline kernel from the "
                          "counter CSVs of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
@@ -97,6 +100,8 @@ def main():
     md = W.md_system(N_LAWS, 3, box=(32.0 * N_LAWS) ** (1.0 / 3.0)) if args.legs == "all" else None
     chains = W.bonded_chains(256, 32, 3) if args.legs == "all" else None
     log("inputs drawn in %.1f s" % (time.time() - t0))
+    if args.save_inputs:
+        save_inputs(args.save_inputs, args.n, pos, vel, mass, ens, md)
 
     import torch
     from paper_0706_3060_amd import nbody as nb
@@ -349,6 +354,23 @@ def measured_traffic(n, cfg):
         if rec.get("sources_sha256") == h and rec.get("config") == cfg and rec.get("n") == n:
             return rec["bytes_per_launch"]
     return None
+
+
+def save_inputs(out_dir, n, pos, vel, mass, ens, md):
+    """The seeded inputs of the run as .npy files (plain arrays, no pickles)."""
+    os.makedirs(out_dir, exist_ok=True)
+    arrays = {"plummer_n%d_seed5_pos" % n: pos, "plummer_n%d_seed5_vel" % n: vel,
+              "plummer_n%d_seed5_mass" % n: mass}
+    if ens is not None:
+        off, epos, epar, _ = ens
+        arrays.update({"ensemble256_seed4_offsets": np.asarray(off, dtype=np.int64),
+                       "ensemble256_seed4_pos": epos, "ensemble256_seed4_params": epar})
+    if md is not None:
+        arrays.update({"md_n%d_seed3_pos" % md.n: md.pos, "md_n%d_seed3_params" % md.n: md.params(),
+                       "md_n%d_seed3_types" % md.n: md.types})
+    for name, a in arrays.items():
+        np.save(os.path.join(out_dir, name + ".npy"), np.asarray(a), allow_pickle=False)
+    log("inputs written to %s (%d arrays)" % (out_dir, len(arrays)))
 
 
 def shard_leg(nb, torch, dev, x, m, law, full_kernel_ms, n_gpus=8):
