@@ -166,8 +166,12 @@ __device__ __forceinline__ void tile_loop(const R *__restrict__ rec, int64_t t0,
 // particle).  `near` is the lane's test of whether the chunk may hold an
 // excluded pair (the wave runs the masked loop when any lane says so); `load`
 // prepares the chunk's masks; `excluded` is the per-pair test.
+// SelfMask keeps, per row, the row's offset in the chunk being masked (a
+// 32-bit value, so that the per-pair test compares with an inline constant
+// rather than holding 64-bit j indices in registers).
 template <int I> struct SelfMask {
     int64_t pid[I];
+    int32_t rel[I];
     __device__ __forceinline__ bool near(int64_t c) const
     {
         bool b = false;
@@ -175,8 +179,15 @@ template <int I> struct SelfMask {
         for (int k = 0; k < I; ++k) b |= (pid[k] >= c) & (pid[k] < c + kWave);
         return b;
     }
-    __device__ __forceinline__ void load(int64_t) {}
-    __device__ __forceinline__ bool excluded(int k, int64_t c, int jj) const { return pid[k] == c + jj; }
+    __device__ __forceinline__ void load(int64_t c)
+    {
+#pragma unroll
+        for (int k = 0; k < I; ++k) {
+            const int64_t d = pid[k] - c;
+            rel[k] = (d >= 0 && d < kWave) ? (int32_t)d : -1;
+        }
+    }
+    __device__ __forceinline__ bool excluded(int k, int64_t, int jj) const { return rel[k] == jj; }
 };
 
 // Row k is particle g[k] of the caller's arrays and record pid[k]; the
