@@ -68,6 +68,12 @@ def _load():
         I64 = ctypes.c_int64
         D = ctypes.c_double
         I = ctypes.c_int
+        lib.oracle_initial_step.argtypes = [P, P, D, D]
+        lib.oracle_initial_step.restype = D
+        lib.oracle_aarseth_step.argtypes = [P, P, P, P, D, D]
+        lib.oracle_aarseth_step.restype = D
+        lib.oracle_quantise_step.argtypes = [D, D, D, D]
+        lib.oracle_quantise_step.restype = D
         lib.oracle_threads.argtypes = [I]
         lib.oracle_threads.restype = I
         lib.oracle_gravity.argtypes = [P, P, I64, D, D, P, I64, I64, I64, P, P, I]
@@ -292,6 +298,25 @@ def hermite(pos, vel, acc, jerk, mass, dt, nsteps, G=1.0, eps=0.0, nthreads=0):
     if rc:
         raise ValueError("oracle_hermite rc=%d" % rc)
     return pos, vel, acc, jerk
+
+
+def initial_step(a, j, eta_s, dt_max):
+    """The block scheme's initial step estimate for one particle (before quantisation)."""
+    a, j = _f64(a, (3,)), _f64(j, (3,))
+    return float(_load().oracle_initial_step(_ptr(a), _ptr(j), float(eta_s), float(dt_max)))
+
+
+def aarseth_step(a, j, a2, a3, eta, dt_max):
+    """Aarseth's step criterion from a and its first three derivatives (before quantisation)."""
+    a, j, a2, a3 = (_f64(v, (3,)) for v in (a, j, a2, a3))
+    return float(_load().oracle_aarseth_step(_ptr(a), _ptr(j), _ptr(a2), _ptr(a3), float(eta),
+                                             float(dt_max)))
+
+
+def quantise_step(dts, dt_max, t, dt_old):
+    """The block scheme's step: a power-of-two fraction of dt_max, at most dts (and at most twice
+    dt_old when dt_old > 0), that divides t."""
+    return float(_load().oracle_quantise_step(float(dts), float(dt_max), float(t), float(dt_old)))
 
 
 def hermite_block_init(acc, jerk, eta_s, dt_max):

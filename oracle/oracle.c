@@ -674,13 +674,50 @@ static double quantise_step(double dts, double dt_max, double t, double dt_old)
     return h;
 }
 
+/* Initial step estimate eta_s |a| / |j| (dt_max when the jerk vanishes). */
+static double initial_step(const double *a, const double *j, double eta_s, double dt_max)
+{
+    const double aj = norm3(j);
+    return aj > 0.0 ? eta_s * norm3(a) / aj : dt_max;
+}
+
+/* Aarseth's criterion from a, its first three time derivatives at the end of
+ * the step and eta:  sqrt( eta (|a| |a2| + |j|^2) / (|j| |a3| + |a2|^2) )
+ * (dt_max when the denominator vanishes). */
+static double aarseth_step(const double *a, const double *j, const double *a2, const double *a3,
+                           double eta, double dt_max)
+{
+    const double na1 = norm3(a), nj1 = norm3(j);
+    const double na2 = norm3(a2), na3 = norm3(a3);
+    const double den = nj1 * na3 + na2 * na2;
+    return den > 0.0 ? sqrt(eta * (na1 * na2 + nj1 * nj1) / den) : dt_max;
+}
+
+/* The three pieces of the step choice, exported so that tests can pin them on
+ * hand-computed values; the block-step integrator below uses the same static
+ * functions. */
+double oracle_initial_step(const double *a, const double *j, double eta_s, double dt_max)
+{
+    return initial_step(a, j, eta_s, dt_max);
+}
+
+double oracle_aarseth_step(const double *a, const double *j, const double *a2, const double *a3,
+                           double eta, double dt_max)
+{
+    return aarseth_step(a, j, a2, a3, eta, dt_max);
+}
+
+double oracle_quantise_step(double dts, double dt_max, double t, double dt_old)
+{
+    return quantise_step(dts, dt_max, t, dt_old);
+}
+
 int oracle_hermite_block_init(const double *acc, const double *jerk, int64_t n, double eta_s,
                               double dt_max, double *t_i, double *dt_i)
 {
     if (n < 0 || !(dt_max > 0.0)) return -1;
     for (int64_t i = 0; i < n; ++i) {
-        const double aj = norm3(jerk + 3 * i);
-        const double dts = aj > 0.0 ? eta_s * norm3(acc + 3 * i) / aj : dt_max;
+        const double dts = initial_step(acc + 3 * i, jerk + 3 * i, eta_s, dt_max);
         t_i[i] = 0.0;
         dt_i[i] = quantise_step(dts, dt_max, 0.0, 0.0);
     }
@@ -729,10 +766,7 @@ int oracle_hermite_block(double *pos, double *vel, double *acc, double *jerk, do
                 acc[3 * i + c] = a1[3 * k + c];
                 jerk[3 * i + c] = j1[3 * k + c];
             }
-            const double na1 = norm3(a1 + 3 * k), nj1 = norm3(j1 + 3 * k);
-            const double na2 = norm3(a2), na3 = norm3(a3);
-            const double den = nj1 * na3 + na2 * na2;
-            const double dts = den > 0.0 ? sqrt(eta * (na1 * na2 + nj1 * nj1) / den) : dt_max;
+            const double dts = aarseth_step(a1 + 3 * k, j1 + 3 * k, a2, a3, eta, dt_max);
             t_i[i] = t;
             dt_i[i] = quantise_step(dts, dt_max, t, h);
         }
