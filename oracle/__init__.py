@@ -74,6 +74,7 @@ def _load():
         lib.oracle_aarseth_step.restype = D
         lib.oracle_quantise_step.argtypes = [D, D, D, D]
         lib.oracle_quantise_step.restype = D
+        lib.oracle_ljc_energy_abs.argtypes = [I, P, P, P, P, I64, D, D, P, P, P, P, I]
         lib.oracle_threads.argtypes = [I]
         lib.oracle_threads.restype = I
         lib.oracle_gravity.argtypes = [P, P, I64, D, D, P, I64, I64, I64, P, P, I]
@@ -383,6 +384,28 @@ def ljc_excl(kind, pos, q, sigma, epsilon, excl_offsets, excl_index, kc=332.0637
     if rc:
         raise ValueError("oracle_ljc_excl rc=%d" % rc)
     return f, u
+
+
+def ljc_energy_abs(kind, pos, q, sigma, epsilon, kc=332.0637, D=4.0, zeta_coef=None,
+                   excl_offsets=None, excl_index=None, nthreads=0):
+    """S_i = sum_{j != i} |u_ij| for LJC law `kind` (1 linear, 2 constant, 3 sigmoidal): the scale
+    that bounds the rounding error of the energy sum U_i (a plain loop over the same pair energies)."""
+    pos = _f64(pos)
+    n = pos.shape[0]
+    pos = _f64(pos, (n, 3))
+    q, sigma, epsilon = _f64(q, (n,)), _f64(sigma, (n,)), _f64(epsilon, (n,))
+    zc = None if zeta_coef is None else _f64(zeta_coef, (4,))
+    if excl_offsets is not None:
+        eoff, eidx = _excl(excl_offsets, excl_index, n)
+    else:
+        eoff = eidx = None
+    out = np.empty(n)
+    rc = _load().oracle_ljc_energy_abs(int(kind), _ptr(pos), _ptr(q), _ptr(sigma), _ptr(epsilon), n,
+                                       float(kc), float(D), _ptr(zc), _ptr(eoff), _ptr(eidx),
+                                       _ptr(out), int(nthreads))
+    if rc:
+        raise ValueError("oracle_ljc_energy_abs rc=%d" % rc)
+    return out
 
 
 def ljc_adjoint_excl(pos, q, sigma, epsilon, g, excl_offsets, excl_index, kc=332.0637, D=4.0,

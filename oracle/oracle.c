@@ -317,6 +317,43 @@ int oracle_ljc_excl(int kind, const double *pos, const double *q, const double *
     }
 }
 
+/* Scale of a row's pair-energy sum: S_i = sum_{j != i, not excluded} |u_ij| for
+ * the LJC laws above (kind 1 linear, 2 constant, 3 sigmoidal), with the same
+ * u_ij as the energy sums (plain loop; every term is non-negative).  A rounding
+ * error of the sum U_i is bounded by a small multiple of the unit roundoff
+ * times S_i, while U_i itself can be a near-cancelling sum of Coulomb and
+ * Lennard-Jones terms; eoff / eidx as in oracle_ljc_excl, or NULL. */
+int oracle_ljc_energy_abs(int kind, const double *pos, const double *q, const double *sigma,
+                          const double *epsl, int64_t n, double kc, double D, const double *zc,
+                          const int64_t *eoff, const int64_t *eidx, double *out, int nthreads)
+{
+    if (n < 0 || kind < 1 || kind > 3 || (kind == 3 && !zc)) return -1;
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i || excluded(eoff, eidx, i, j)) continue;
+            const double rx = pos[3 * i] - pos[3 * j];
+            const double ry = pos[3 * i + 1] - pos[3 * j + 1];
+            const double rz = pos[3 * i + 2] - pos[3 * j + 2];
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double r = sqrt(r2);
+            const double sij = 0.5 * (sigma[i] + sigma[j]);
+            const double eij = sqrt(epsl[i] * epsl[j]);
+            const double sr2 = sij * sij / r2;
+            const double sr6 = sr2 * sr2 * sr2;
+            double uc;
+            if (kind == 1) uc = kc * q[i] * q[j] / (D * r2);
+            else if (kind == 2) uc = kc * q[i] * q[j] / (D * r);
+            else uc = kc * q[i] * q[j] / (exp(zc[0] * r * r * r + zc[1] * r * r + zc[2] * r + zc[3]) * r);
+            acc += fabs(uc + 4.0 * eij * (sr6 * sr6 - sr6));
+        }
+        out[i] = acc;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------
  * Time-step cycle (Section 1: force evaluation, then the update step, then
  * repeat).  The paper names no integrator; the reading is kick-drift-kick

@@ -866,6 +866,43 @@ std::shared_ptr<const BatchPlan> cached_plan(const int64_t *offsets, int64_t S, 
     return plan;
 }
 
+// The plan of one batched launch: j parts of about 8 units per resident wave
+// (`resident` waves on the whole chip), no part shorter than kMinJUnit records,
+// the part length doubled until the partial slots of split systems fit the
+// workspace (max_slots slots of 128 rows; a slot holds one row block, 64 x ipl
+// rows).
+struct PlanChoice {
+    std::shared_ptr<const BatchPlan> plan;
+    int64_t j_unit;
+};
+
+PlanChoice plan_for_launch(const int64_t *offsets, int64_t S, int ipl, int64_t resident, int64_t max_slots)
+{
+    double work = 0.0;
+    for (int64_t q = 0; q < S; ++q) {
+        const int64_t ns = offsets[q + 1] - offsets[q];
+        work += (double)ns * (double)round_up(ns, 64);
+    }
+    resident = std::max<int64_t>(resident, 1);
+    int64_t j_unit = round_up((int64_t)(work / (8.0 * (double)resident * 64.0 * ipl)) + 1, 64);
+    j_unit = std::max(kMinJUnit, j_unit);
+    std::shared_ptr<const BatchPlan> pp = cached_plan(offsets, S, ipl, j_unit);
+    while (pp->n_slots * ipl > 2 * max_slots) {
+        j_unit *= 2;
+        pp = cached_plan(offsets, S, ipl, j_unit);
+    }
+    return {pp, j_unit};
+}
+
+// Whether a plan fits the workspace regions it is copied into and the part
+// slots its units address: the unit table (max_units units), the padded
+// records (max_records) and max_slots slots of 128 rows.
+bool plan_fits(const BatchPlan &p, int ipl, int64_t max_units, int64_t max_records, int64_t max_slots)
+{
+    return (int64_t)p.units.size() / 4 <= max_units && p.npad_total <= max_records &&
+           p.n_slots * ipl <= 2 * max_slots;
+}
+
 int g_num_cus = 0;
 
 int device_cus()
@@ -899,26 +936,10 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
         std::max(1, batched_max_blocks_per_cu(law->kind, law->precision, c.ipl, out_pot != nullptr,
                                               c.j_stage, c.block, excl.off != nullptr));
     const int64_t resident = (int64_t)device_cus() * per_cu * (c.block / 64);
-    // j parts: about 8 units per resident wave, no part shorter than kMinJUnit
-    // records, within the workspace's partial slots
-    double work = 0.0;
-    for (int64_t q = 0; q < S; ++q) {
-        const int64_t ns = offsets[q + 1] - offsets[q];
-        work += (double)ns * (double)round_up(ns, 64);
-    }
-    int64_t j_unit = round_up((int64_t)(work / (8.0 * (double)resident * 64.0 * c.ipl)) + 1, 64);
-    j_unit = std::max(kMinJUnit, j_unit);
-    std::shared_ptr<const BatchPlan> pp = cached_plan(offsets, S, c.ipl, j_unit);
-    // the slot budget holds max_slots x 128 rows; a slot takes 64 x ipl rows
-    while (pp->n_slots * c.ipl > 2 * lay.max_slots) {
-        j_unit *= 2;
-        pp = cached_plan(offsets, S, c.ipl, j_unit);
-    }
+    std::shared_ptr<const BatchPlan> pp = plan_for_launch(offsets, S, c.ipl, resident, lay.max_slots).plan;
     const BatchPlan &plan = *pp;
     if (plan.units.empty()) return NBODY_OK;
-    // the plan must fit the workspace regions it is copied into
-    if ((int64_t)plan.units.size() / 4 > lay.max_units || plan.npad_total > lay.max_records ||
-        plan.n_slots * c.ipl > 2 * lay.max_slots)
+    if (!plan_fits(plan, c.ipl, lay.max_units, lay.max_records, lay.max_slots))
         return fail(NBODY_EWORKSPACE, "internal: batched plan exceeds its workspace regions "
                     "(%lld units, %lld slots)", (long long)(plan.units.size() / 4), (long long)plan.n_slots);
     char *base = (char *)ws;
@@ -1595,20 +1616,10 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     a.excl = excl_args(excl);
     const int per_cu = std::max(1, adjoint_batched_blocks_per_cu(a));
     const int64_t resident = (int64_t)device_cus() * per_cu * (c.block / 64);
-    double work = 0.0;
-    for (int64_t q = 0; q < n_systems; ++q) {
-        const int64_t ns = offsets[q + 1] - offsets[q];
-        work += (double)ns * (double)round_up(ns, 64);
-    }
-    int64_t j_unit = std::max(kMinJUnit, round_up((int64_t)(work / (8.0 * (double)resident * 64.0 * ipl)) + 1, 64));
-    std::shared_ptr<const BatchPlan> pp = cached_plan(offsets, n_systems, ipl, j_unit);
-    while (pp->n_slots * ipl > 2 * lay.max_slots) {
-        j_unit *= 2;
-        pp = cached_plan(offsets, n_systems, ipl, j_unit);
-    }
+    std::shared_ptr<const BatchPlan> pp = plan_for_launch(offsets, n_systems, ipl, resident, lay.max_slots).plan;
     const BatchPlan &plan = *pp;
     if (plan.units.empty()) return NBODY_OK;
-    if ((int64_t)plan.units.size() / 4 > lay.max_units || plan.npad_total > lay.max_records)
+    if (!plan_fits(plan, ipl, lay.max_units, lay.max_records, lay.max_slots))
         return fail(NBODY_EWORKSPACE, "internal: batched adjoint plan exceeds its workspace regions");
     char *base = (char *)ws;
     int32_t *d_units = (int32_t *)(base + lay.unit_off);

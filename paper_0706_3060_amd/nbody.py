@@ -556,14 +556,26 @@ def flops_per_pair(api, law_kind, with_potential):
 
 
 # ---------------------------------------------------------------- autograd
+def _refuse_param_grad(ctx, law: Law, what):
+    """The parameter adjoint exists for LJC(linear) only (per-atom q, sigma, epsilon): a params
+    tensor that requires a gradient under another law is refused rather than left without one."""
+    if ctx.needs_input_grad[1] and law.kind != LJC_LINEAR:
+        name = {GRAVITY: "gravity masses", LJC_CONSTANT: "LJC(constant) parameters",
+                LJC_SIGMOIDAL: "LJC(sigmoidal) parameters"}.get(law.kind, "these parameters")
+        raise NotImplementedError("%s: no gradient with respect to %s (only positions, and the "
+                                  "LJC(linear) q / sigma / epsilon); pass params.detach()" % (what, name))
+
+
 class NBodyForcesFn(torch.autograd.Function):
     """F = forces(pos, params) with a hand-written adjoint (nbody_forces_backward), optionally
     with exclusion lists (LJC).
 
-    Gradients: pos always; params for LJC(linear) (per-atom q, sigma, epsilon)."""
+    Gradients: pos always; params for LJC(linear) (per-atom q, sigma, epsilon).  A params
+    tensor that requires a gradient under another law raises NotImplementedError."""
 
     @staticmethod
     def forward(ctx, pos, params, law: Law, exclusions: Exclusions = None):
+        _refuse_param_grad(ctx, law, "NBodyForcesFn")
         f, _ = forces(pos, params, law, potential=False, exclusions=exclusions)
         ctx.save_for_backward(pos, params)
         ctx.law = law
@@ -591,6 +603,7 @@ class NBodyBatchedForcesFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, pos, params, offsets, law: Law, exclusions: Exclusions = None):
+        _refuse_param_grad(ctx, law, "NBodyBatchedForcesFn")
         f, _ = forces_batched(offsets, pos, params, law, potential=False, exclusions=exclusions)
         ctx.save_for_backward(pos, params)
         ctx.offsets = _host_offsets(offsets)

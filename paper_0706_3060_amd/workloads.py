@@ -248,6 +248,12 @@ def perturbed(sys: MDSystem, seed: int, rel: float = 0.05) -> MDSystem:
     return MDSystem(pos=sys.pos, q=q, types=sys.types, sigma_t=st, eps_t=et, box=sys.box)
 
 
+def ensemble_sizes(n_systems: int = 256, seed: int = 4, n_min: int = 500, n_max: int = 5000):
+    """The system sizes of batched_md's ensemble: N_s ~ U{n_min .. n_max}, int64 [n_systems]."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(n_min, n_max + 1, n_systems).astype(np.int64)
+
+
 def batched_md(n_systems: int = 256, seed: int = 4, n_min: int = 500, n_max: int = 5000,
                density: float = 1.0 / 32.0, sizes=None, workers=None):
     """Ensemble of independent LJC systems at constant density.
@@ -257,9 +263,8 @@ def batched_md(n_systems: int = 256, seed: int = 4, n_min: int = 500, n_max: int
     processes when no GPU context exists yet in this process (a forked child of
     a process holding a GPU context is not safe).
     Returns (offsets [S+1] int64, pos [sum N,3], params [sum N,3], systems)."""
-    rng = np.random.default_rng(seed)
     if sizes is None:
-        sizes = rng.integers(n_min, n_max + 1, n_systems)
+        sizes = ensemble_sizes(n_systems, seed, n_min, n_max)
     sizes = np.asarray(sizes, dtype=np.int64)
     jobs = [(int(ns), seed * 1000 + s, (ns / density) ** (1.0 / 3.0) if ns > 0 else 1.0)
             for s, ns in enumerate(sizes)]

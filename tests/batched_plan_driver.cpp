@@ -1,0 +1,140 @@
+// CPU check of the batched planner and workspace layouts of the host runtime.
+//
+// This driver includes csrc/api.cpp itself, so it exercises the very functions
+// the batched entry points call (plan_for_launch, plan_batched, plan_fits,
+// bat_layout, adjb_layout) without a GPU: no kernel is launched.  For every
+// ensemble file given (raw int64 offsets, S + 1 values) and every combination
+// of chip size, blocks per CU, block size and rows per lane, it plans as a
+// launch would and then walks every unit the way the kernels address memory:
+// system, row block and part in range, j range inside the system's padded
+// records, part slot inside the partial region, tables inside their regions.
+// It also checks that a plan larger than a workspace's regions is refused.
+// Prints one line per ensemble and exits non-zero on the first violation.
+#include "api.cpp"
+
+#include <cstdio>
+#include <fstream>
+
+namespace {
+
+int g_bad = 0;
+
+#define EXPECT(cond, ...)                                                                          \
+    do {                                                                                           \
+        if (!(cond)) {                                                                             \
+            std::fprintf(stderr, "violation: %s: ", #cond);                                       \
+            std::fprintf(stderr, __VA_ARGS__);                                                     \
+            std::fprintf(stderr, "\n");                                                            \
+            if (++g_bad > 20) std::exit(1);                                                        \
+        }                                                                                          \
+    } while (0)
+
+// Walk one plan against the regions of a layout (partial slot of `dbl` doubles per row).
+void walk(const BatchPlan &p, const std::vector<int64_t> &off, int ipl, size_t rec_bytes_, size_t rec_off,
+          size_t unit_off, size_t next_off, size_t part_off, size_t part_end, int64_t max_slots, int dbl,
+          const char *what)
+{
+    const int64_t S = (int64_t)off.size() - 1;
+    const int64_t rows = 64 * ipl;
+    EXPECT(p.poff.size() == off.size() && p.systab.size() == 3 * (size_t)S, "%s: table sizes", what);
+    EXPECT(rec_off + (size_t)p.npad_total * rec_bytes_ <= unit_off, "%s: records overrun", what);
+    EXPECT(unit_off + p.units.size() * sizeof(int32_t) <= next_off, "%s: unit table overruns (%zu units)",
+           what, p.units.size() / 4);
+    EXPECT(p.n_slots * ipl <= 2 * max_slots, "%s: slots %lld x ipl %d > 2 x %lld", what,
+           (long long)p.n_slots, ipl, (long long)max_slots);
+    std::vector<int64_t> seen((size_t)std::max<int64_t>(p.n_slots, 1), 0);
+    int64_t pairs = 0;
+    for (size_t u = 0; u < p.units.size() / 4; ++u) {
+        const int64_t s = p.units[4 * u], rb = p.units[4 * u + 1], part = p.units[4 * u + 2];
+        EXPECT(s >= 0 && s < S, "%s: unit %zu system %lld", what, u, (long long)s);
+        if (s < 0 || s >= S) continue;
+        const int64_t ns = off[s + 1] - off[s], po = p.poff[s], pe = p.poff[s + 1];
+        const int64_t nparts = p.systab[3 * s], plen = p.systab[3 * s + 1], slot0 = p.systab[3 * s + 2];
+        EXPECT(pe - po == round_up(ns, 64), "%s: padded length of system %lld", what, (long long)s);
+        EXPECT(rb >= 0 && rb * rows < ns, "%s: unit %zu row block %lld of %lld rows", what, u, (long long)rb,
+               (long long)ns);
+        EXPECT(part >= 0 && part < nparts, "%s: unit %zu part %lld of %lld", what, u, (long long)part,
+               (long long)nparts);
+        const int64_t jb = po + part * plen, je = std::min(jb + plen, pe);
+        EXPECT(jb >= po && jb < je && je <= pe && pe <= p.npad_total, "%s: j range of unit %zu", what, u);
+        EXPECT((jb - po) % 64 == 0 && (je - jb) % 64 == 0, "%s: j range of unit %zu not whole chunks", what, u);
+        const int64_t last_row = po + std::min(ns, (rb + 1) * rows) - 1;
+        EXPECT(last_row < pe, "%s: rows of unit %zu", what, u);
+        pairs += (std::min(ns, (rb + 1) * rows) - rb * rows) * (je - jb);
+        if (nparts > 1) {
+            const int64_t slot = slot0 + rb * nparts + part;
+            EXPECT(slot >= 0 && slot < p.n_slots, "%s: unit %zu slot %lld of %lld", what, u, (long long)slot,
+                   (long long)p.n_slots);
+            const size_t hi = part_off + ((size_t)slot * rows + rows) * dbl * sizeof(double);
+            EXPECT(hi <= part_end, "%s: unit %zu slot %lld ends past the partial region", what, u,
+                   (long long)slot);
+            if (slot >= 0 && slot < p.n_slots) ++seen[(size_t)slot];
+        }
+    }
+    for (int64_t k = 0; k < p.n_slots; ++k) EXPECT(seen[(size_t)k] == 1, "%s: slot %lld written %lld times",
+                                                     what, (long long)k, (long long)seen[(size_t)k]);
+    int64_t want = 0;
+    for (int64_t s = 0; s < S; ++s) want += (off[s + 1] - off[s]) * round_up(off[s + 1] - off[s], 64);
+    EXPECT(pairs == want, "%s: units cover %lld row x record pairs, want %lld", what, (long long)pairs,
+           (long long)want);
+}
+
+}  // namespace
+
+int main(int argc, char **argv)
+{
+    nbody_law law{};
+    law.kind = NBODY_LAW_LJC_LINEAR;
+    law.precision = NBODY_FP32_KAHAN;
+    law.coulomb_k = 332.0637;
+    law.dielectric = 4.0;
+    for (int a = 1; a < argc; ++a) {
+        std::ifstream f(argv[a], std::ios::binary);
+        std::vector<int64_t> off;
+        int64_t v;
+        while (f.read(reinterpret_cast<char *>(&v), sizeof v)) off.push_back(v);
+        if (off.empty() || off[0] != 0) {
+            std::fprintf(stderr, "%s: bad offsets file\n", argv[a]);
+            return 2;
+        }
+        const int64_t S = (int64_t)off.size() - 1, n = off.back();
+        const BatWs lay = bat_layout(&law, n, S);
+        const AdjBatWs alay = adjb_layout(&law, n, S);
+        int plans = 0;
+        int64_t max_units = 0, max_slots_used = 0;
+        for (int cus : {80, 256, 304})
+            for (int per_cu = 1; per_cu <= 16; ++per_cu)
+                for (int block : {64, 128, 192, 256})
+                    for (int ipl : {1, 2, 4}) {
+                        const int64_t resident = (int64_t)cus * per_cu * (block / 64);
+                        const PlanChoice pc = plan_for_launch(off.data(), S, ipl, resident, lay.max_slots);
+                        const BatchPlan &p = *pc.plan;
+                        EXPECT(plan_fits(p, ipl, lay.max_units, lay.max_records, lay.max_slots),
+                               "forward plan (cus %d, per_cu %d, block %d, ipl %d)", cus, per_cu, block, ipl);
+                        walk(p, off, ipl, rec_bytes(law.kind, law.precision), lay.rec_off, lay.unit_off,
+                             lay.off_off, lay.part_off, lay.ticket_off, lay.max_slots, 4, "forward");
+                        max_units = std::max<int64_t>(max_units, (int64_t)p.units.size() / 4);
+                        max_slots_used = std::max<int64_t>(max_slots_used, p.n_slots * ipl);
+                        if (ipl <= 2) {       // the batched adjoint runs up to 2 rows per lane
+                            const PlanChoice pa = plan_for_launch(off.data(), S, ipl, resident, alay.max_slots);
+                            EXPECT(plan_fits(*pa.plan, ipl, alay.max_units, alay.max_records, alay.max_slots),
+                                   "adjoint plan (cus %d, per_cu %d, block %d, ipl %d)", cus, per_cu, block, ipl);
+                            walk(*pa.plan, off, ipl, adj_rec_bytes(law.kind, law.precision), alay.rec_off,
+                                 alay.unit_off, alay.off_off, alay.part_off, alay.ticket_off, alay.max_slots, 8,
+                                 "adjoint");
+                        }
+                        ++plans;
+                        // a workspace whose regions are one unit / one slot too small refuses the plan
+                        if (!p.units.empty())
+                            EXPECT(!plan_fits(p, ipl, (int64_t)p.units.size() / 4 - 1, lay.max_records,
+                                              lay.max_slots), "undersized unit table accepted");
+                        if (p.n_slots > 0)
+                            EXPECT(!plan_fits(p, ipl, lay.max_units, lay.max_records,
+                                              (p.n_slots * ipl + 1) / 2 - 1), "undersized slot region accepted");
+                    }
+        std::printf("%s: S=%lld n=%lld plans=%d max_units=%lld/%lld max_slot_rows=%lld/%lld violations=%d\n",
+                    argv[a], (long long)S, (long long)n, plans, (long long)max_units, (long long)lay.max_units,
+                    (long long)max_slots_used * 64, (long long)lay.max_slots * 128, g_bad);
+    }
+    return g_bad ? 1 : 0;
+}

@@ -108,6 +108,51 @@ def test_batched_equals_single_system_calls(nb, ensemble):
         assert d <= 1e-5 * max(1.0, fs.abs().max().item())
 
 
+@pytest.mark.parametrize("law_name", ["gravity", "ljc_linear"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_kahan", "fp32_fp64acc"])
+def test_batched_bitwise_equals_single_system_calls(nb, law_name, prec):
+    """Systems small enough that the planner cuts no j parts (at most 256 padded records): under
+    the same forced configuration (rows per lane, j tile, j staging) each system of the batch runs
+    the same j loop over the same records as its own single-system call, so the results are
+    identical bit for bit."""
+    rng = np.random.default_rng(31)
+    sizes = [int(v) for v in rng.integers(1, 257, 40)] + [0, 1, 2, 64, 65, 256]
+    rng.shuffle(sizes)
+    xs, ps = [], []
+    for k, n in enumerate(sizes):
+        if n < 2:
+            xs.append(rng.normal(size=(n, 3)))
+            ps.append(np.full(n, 0.5) if law_name == "gravity" else np.tile([0.3, 3.2, 0.1], (n, 1)))
+        elif law_name == "gravity":
+            x, _, m = W.plummer(n, 300 + k)
+            xs.append(x)
+            ps.append(m)
+        else:
+            sy = W.md_system(n, 300 + k, box=(32.0 * max(n, 1)) ** (1.0 / 3.0))
+            xs.append(sy.pos)
+            ps.append(sy.params())
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    pos = np.concatenate(xs)
+    par = np.concatenate(ps)
+    law = nb.gravity(prec, softening=0.01) if law_name == "gravity" else nb.ljc_linear(prec)
+    X, P = dev(pos), dev(par)
+    for cfg in [(64, 1, 64, 1, 0), (256, 1, 256, 1, 1), (128, 2, 128, 1, 1), (256, 4, 256, 1, 0)]:
+        try:
+            nb.set_config(nb.API_BATCHED, *cfg)
+            nb.set_config(nb.API_FORCES, *cfg)
+            fb, ub = nb.forces_batched(off, X, P, law)
+            for s in range(len(sizes)):
+                a, b = int(off[s]), int(off[s + 1])
+                if b == a:
+                    continue
+                fs, us = nb.forces(X[a:b], P[a:b], law)
+                assert torch.equal(fb[a:b], fs), (cfg, s, (fb[a:b] - fs).abs().max().item())
+                assert torch.equal(ub[a:b], us), (cfg, s)
+        finally:
+            nb.clear_config(nb.API_BATCHED)
+            nb.clear_config(nb.API_FORCES)
+
+
 # --------------------------------------------------------------- adjoint
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32_fp64acc", 1e-4), ("fp32_kahan", 1e-4)])
 def test_gravity_adjoint_matches_oracle(nb, prec, tol):

@@ -21,7 +21,8 @@ from paper_0706_3060_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-BENCH_CFG = (256, 1, 256, 1)      # the launch configuration the benchmark's autotuner picked
+# The forced alternative shape of the full-size case: one j part, scalar staging.
+SCALAR_CFG = (256, 1, 256, 1, 0)
 
 
 @pytest.fixture(scope="module")
@@ -174,13 +175,24 @@ def test_config3_euler_identities_on_gpu(nb):
     assert abs((s.sigma * gpar[:, 1]).sum() + (s.pos * gp).sum() + gflj + 3 * gfc) <= 1e-9 * scale
 
 
-def test_config4_full_ensemble(nb, full_ensemble):
+# The default rule, and two forced shapes of the persistent launch over the full ensemble: one
+# row per lane with scalar staging and two rows per lane with LDS staging.  Under the forced
+# shapes the planner cuts the large systems into j parts whose slots and unit table reach the
+# limits of the workspace layout (a unit table once sized below the planner's maximum made such
+# launches fault; the CPU test of the planner checks the layout for every occupancy).
+@pytest.mark.parametrize("shape", [None, (256, 1, 256, 1, 0), (256, 2, 256, 1, 1)])
+def test_config4_full_ensemble(nb, full_ensemble, shape):
     off, pos, par, systems = full_ensemble
     S = len(systems)
     x, p = dev(pos), dev(par)
     law = nb.ljc_linear("fp32_kahan")
     law64 = nb.ljc_linear("fp64")
-    fb, ub = nb.forces_batched(off, x, p, law)
+    try:
+        if shape is not None:
+            nb.set_config(nb.API_BATCHED, *shape)
+        fb, ub = nb.forces_batched(off, x, p, law)
+    finally:
+        nb.clear_config(nb.API_BATCHED)
     fb, ub = host(fb), host(ub)
     meds = []
     for s in range(S):
@@ -190,6 +202,8 @@ def test_config4_full_ensemble(nb, full_ensemble):
         meds.append(np.median(e))
         assert e.max() <= 1e-3, (s, e.max())
     assert max(meds) <= 1e-5, max(meds)
+    if shape is not None:
+        return
     # the oracle on 8 sampled systems, 64 sampled rows each
     rng = np.random.default_rng(44)
     for s in rng.choice(S, 8, replace=False):
@@ -201,16 +215,34 @@ def test_config4_full_ensemble(nb, full_ensemble):
         assert np.median(e) <= 1e-5 and e.max() <= 1e-3
 
 
-def test_config5_plummer_1m(nb):
-    n, eps = 1 << 20, 0.005
-    pos, _, m = W.plummer(n, 5)
+@pytest.mark.parametrize("shape", ["rule", "scalar"])
+def test_config5_plummer_1m(nb, shape):
+    """Gravity at N = 2^20, FP32 + Kahan, against the FP64 GPU pass over all rows and the oracle
+    on sampled rows.  "rule" runs the configuration the benchmark times (the library's rule for
+    this size: LDS staging, 32 j parts over XCD-ordered blocks and the fixed-order split
+    reduction), through both timed entry points: the forward and one kick-drift-kick step.
+    "scalar" forces one j part with scalar staging."""
+    n, eps, dt = 1 << 20, 0.005, 1e-3
+    pos, vel, m = W.plummer(n, 5)
     x, mm = dev(pos), dev(m)
+    law = nb.gravity("fp32_kahan", softening=eps)
+    law64 = nb.gravity("fp64", softening=eps)
+    if shape == "rule":
+        for api in (nb.API_FORCES, nb.API_LEAPFROG):
+            c = nb.get_config(api, n, law)
+            assert (c["j_stage"], c["j_split"], c["i_per_lane"]) == (1, 32, 1), (api, c)
     try:
-        nb.set_config(nb.API_FORCES, *BENCH_CFG)
-        f32, p32 = nb.forces(x, mm, nb.gravity("fp32_kahan", softening=eps))
+        if shape == "scalar":
+            for api in (nb.API_FORCES, nb.API_LEAPFROG):
+                nb.set_config(api, *SCALAR_CFG)
+        f32, p32 = nb.forces(x, mm, law)
+        # one step of the timed loop: a(t) from the forward, kick-drift, forces at x(t+dt), kick
+        X, V, A = x.clone(), dev(vel), f32.clone()
+        pot1 = nb.leapfrog(X, V, A, mm, law, dt, 1, potential=True)
     finally:
         nb.clear_config(nb.API_FORCES)
-    f64, p64 = nb.forces(x, mm, nb.gravity("fp64", softening=eps))
+        nb.clear_config(nb.API_LEAPFROG)
+    f64, p64 = nb.forces(x, mm, law64)
     f32, f64, p32, p64 = host(f32), host(f64), host(p32), host(p64)
     e = rel_rows(f32, f64)
     assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
@@ -220,9 +252,23 @@ def test_config5_plummer_1m(nb):
     a_ref, phi_ref = oracle.gravity(pos, m, eps=eps, ilist=rows)
     assert rel_rows(f64[rows], a_ref).max() <= 1e-12
     assert (np.abs(p64[rows] - phi_ref) / np.abs(phi_ref)).max() <= 1e-12
-    a32_ref, _ = oracle.gravity(W.round_to_f32(pos), W.round_to_f32(m), eps=eps, ilist=rows)
+    a32_ref, p32_ref = oracle.gravity(W.round_to_f32(pos), W.round_to_f32(m), eps=eps, ilist=rows)
     e32 = rel_rows(f32[rows], a32_ref)
     assert np.median(e32) <= 1e-5 and e32.max() <= 1e-3
+    ep32 = np.abs(p32[rows] - p32_ref) / np.abs(p32_ref)
+    assert np.median(ep32) <= 1e-5 and ep32.max() <= 1e-3
+    # the step: FP64 kick-drift from the same a(t) (so x(t+dt) agrees to FP64 rounding), then the
+    # FP32 forces at x(t+dt) against the oracle there, on the same rows
+    xh, vh = host(X), host(V)
+    v_half = vel + 0.5 * dt * f32
+    x1 = pos + dt * v_half
+    assert np.abs(xh - x1).max() <= 1e-14 * np.abs(x1).max()
+    a1_ref, phi1_ref = oracle.gravity(W.round_to_f32(xh), W.round_to_f32(m), eps=eps, ilist=rows)
+    e1 = rel_rows(host(A)[rows], a1_ref)
+    assert np.median(e1) <= 1e-5 and e1.max() <= 1e-3, (np.median(e1), e1.max())
+    np.testing.assert_allclose(vh[rows], v_half[rows] + 0.5 * dt * host(A)[rows], rtol=0, atol=1e-14)
+    ep1 = np.abs(host(pot1)[rows] - phi1_ref) / np.abs(phi1_ref)
+    assert np.median(ep1) <= 1e-5 and ep1.max() <= 1e-3
 
 
 def test_config5_hvp_262144(nb):

@@ -8,8 +8,8 @@ forward through the C ABI, and compares with the oracle on the same inputs:
 FP64 paths to 1e-12 per row, FP32 paths median <= 1e-5 and maximum <= 1e-3 (against
 the oracle fed the FP32-rounded inputs).  Row errors are taken relative to
 max(|F_i|, 1e-3 max_j |F_j|), so that a row whose force nearly cancels is held to the
-scale of the system rather than to its own tiny norm; potentials are held to the largest
-|U_i| of the system (FP32 ones from 16 particles up, see below).  The batched test draws ensembles of
+scale of the system rather than to its own tiny norm; potentials are held normwise, row by
+row, to S_i = sum_j |u_ij| (see check_potential), at every size.  The batched test draws ensembles of
 up to 24 systems of 0 to 400 particles (empty and one-particle systems included) for the
 persistent launch and compares each system with its own oracle call; the adjoint and the
 acceleration-and-jerk, exclusion-list and integrator tests do the same for those paths.
@@ -53,17 +53,34 @@ def row_errors(f, ref):
     return np.linalg.norm(f - ref, axis=1) / np.maximum(nref, max(floor, 1e-300))
 
 
-# Below this many particles a potential can be the near-cancelling sum of two or three pair
-# energies (Coulomb attraction against Lennard-Jones repulsion), whose FP32 rounding is a
-# property of FP32 arithmetic and not of the kernel: the FP32 potential checks start here.
-FP32_POTENTIAL_MIN_N = 16
+# Potentials are held normwise, row by row: |U_i - U_i^ref| / S_i with S_i = sum_j |u_ij| (the
+# oracle's plain loop over the same pair energies).  A rounding error of the sum is a small
+# multiple of the unit roundoff times S_i, whatever the cancellation: an LJC potential can be
+# the near-cancelling sum of a Coulomb attraction and a Lennard-Jones repulsion (e.g. -2.898 +
+# 2.915 kcal/mol in a three-particle system), whose FP32 error relative to the small total is a
+# property of FP32 arithmetic.  Gravity's pair energies all have one sign, so S_i = |phi_i|.
+KINDS = {"ljc_linear": 1, "ljc_constant": 2, "ljc_sigmoidal": 3}
 
 
-def check_potential(got, ref, prec, n, what):
-    e = np.abs(got - ref) / max(np.abs(ref).max(), 1e-300)
+def potential_scale(law, x, par, prec, eoff=None, eidx=None):
+    """S_i for the oracle inputs of `reference` (None for gravity: |phi_i| itself)."""
+    if law == "gravity":
+        return None
+    if prec != "fp64":
+        x, par = W.round_to_f32(x), W.round_to_f32(par)
+    return oracle.ljc_energy_abs(KINDS[law], x, par[:, 0], par[:, 1], par[:, 2], zeta_coef=ZC,
+                                 excl_offsets=eoff, excl_index=eidx)
+
+
+def check_potential(got, ref, prec, scale, what):
+    s = np.abs(ref) if scale is None else scale
+    tiny = 1e-300 if s.size == 0 else max(1e-300, 1e-30 * s.max())
+    e = np.abs(got - ref) / np.maximum(s, tiny)
+    if e.size == 0:
+        return
     if prec == "fp64":
         assert e.max() <= 1e-12, (e.max(), what)
-    elif n >= FP32_POTENTIAL_MIN_N:
+    else:
         assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max(), what)
 
 
@@ -133,7 +150,7 @@ def test_random_systems_and_configurations(nb, n, law, prec, block, ipl, j_tile,
     else:
         assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max(), n, law, prec)
     if potential:
-        check_potential(host(p), pr, prec, n, (n, law, prec))
+        check_potential(host(p), pr, prec, potential_scale(law, x, par, prec), (n, law, prec))
 
 
 def ensemble(law, sizes, seed):
@@ -188,7 +205,7 @@ def test_random_batches(nb, sizes, law, prec, block, ipl, j_tile, j_stage, seed)
             assert e.max() <= 1e-12, (s, e.max(), law, prec)
         else:
             assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (s, np.median(e), e.max(), law, prec)
-        check_potential(p[a:b], pr, prec, b - a, (s, law, prec))
+        check_potential(p[a:b], pr, prec, potential_scale(law, x[a:b], par[a:b], prec), (s, law, prec))
 
 
 def rel_to_max(got, ref):
@@ -271,15 +288,13 @@ def test_random_jerk(nb, n, prec, block, ipl, j_tile, j_split, j_stage, potentia
                                          eps=EPS, ilist=rows)
     checks = [row_errors(host(a), ra), row_errors(host(j), rj)]
     if potential:
-        check_potential(host(p), rp, prec, n, (n, prec))
+        check_potential(host(p), rp, prec, None, (n, prec))
     for e in checks:
         if prec == "fp64":
             assert e.max() <= 1e-12, (e.max(), n, prec)
         else:
             assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max(), n, prec)
 
-
-KINDS = {"ljc_linear": 1, "ljc_constant": 2, "ljc_sigmoidal": 3}
 
 
 @settings(max_examples=80, deadline=None, derandomize=True, database=None,
@@ -325,7 +340,9 @@ def test_random_exclusions(nb, n, law, prec, max_partners, block, ipl, j_tile, j
         assert e.max() <= 1e-12, (e.max(), n, law, prec)
     else:
         assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max(), n, law, prec)
-    check_potential(host(p), pr, prec, n, (n, law, prec))
+    sc = oracle.ljc_energy_abs(KINDS[law], xr, par[:, 0], par[:, 1], par[:, 2], zeta_coef=ZC,
+                               excl_offsets=eoff, excl_index=eidx)
+    check_potential(host(p), pr, prec, sc, (n, law, prec))
 
 
 @settings(max_examples=60, deadline=None, derandomize=True, database=None,
@@ -365,7 +382,7 @@ def test_random_leapfrog(nb, n, law, nsteps, with_inv_mass, j_split, j_stage, se
     assert np.abs(host(X) - xr).max() <= 1e-12 * np.abs(xr).max()
     assert np.abs(host(V) - vr).max() <= 1e-12 * max(np.abs(vr).max(), 1e-300)
     assert row_errors(host(A), ar).max() <= 1e-12
-    check_potential(host(pot), pr, "fp64", n, (n, law))
+    check_potential(host(pot), pr, "fp64", potential_scale(law, xr, par, "fp64"), (n, law))
 
 
 @settings(max_examples=40, deadline=None, derandomize=True, database=None,

@@ -295,3 +295,29 @@ def test_block_steps_on_a_circular_orbit(oracle_mod):
         state = (x, v, a1, j1, ts, dts)
         seen.append((tn, dts[0], dts[1]))
     assert seen == [(1.0 / 64, 1.0 / 64, 1.0 / 64), (1.0 / 32, 1.0 / 32, 1.0 / 32)], seen
+
+
+def test_energy_scale_hand_values(oracle_mod):
+    # k = 4, D = 4, charges (1, 1, -1), epsilon = 0 at distances 2 and 4 from particle 0:
+    # linear dielectric u = k q q / (D r^2): +1/4 and -1/16, so S_0 = 5/16 while U_0 = 3/16;
+    # constant dielectric u = k q q / (D r): +1/2 and -1/4, S_0 = 3/4; the sigmoidal law with
+    # zeta = exp(ln 4) = 4 is the constant one
+    pos = np.array([[0.0, 0, 0], [2.0, 0, 0], [0.0, -4.0, 0]])
+    q = np.array([1.0, 1.0, -1.0])
+    sig = np.full(3, 2.0)
+    eps = np.zeros(3)
+    s1 = oracle_mod.ljc_energy_abs(1, pos, q, sig, eps, kc=4.0, D=4.0)
+    s2 = oracle_mod.ljc_energy_abs(2, pos, q, sig, eps, kc=4.0, D=4.0)
+    s3 = oracle_mod.ljc_energy_abs(3, pos, q, sig, eps, kc=4.0, zeta_coef=[0, 0, 0, math.log(4.0)])
+    assert s1[0] == 0.3125 and s2[0] == 0.75 and abs(s3[0] - 0.75) <= 1e-15
+    _, u1 = oracle_mod.ljc_linear(pos, q, sig, eps, kc=4.0, D=4.0)
+    assert u1[0] == 0.1875
+    # Lennard-Jones minimum r = 2^(1/6) sigma, no charges: u = -epsilon, S = epsilon
+    r = 2.0 ** (1.0 / 6.0) * 3.0
+    pos2 = np.array([[0.0, 0, 0], [r, 0, 0]])
+    s = oracle_mod.ljc_energy_abs(1, pos2, np.zeros(2), np.full(2, 3.0), np.full(2, 0.2))
+    np.testing.assert_allclose(s, [0.2, 0.2], rtol=1e-14)
+    # an excluded partner drops out of the scale
+    s1x = oracle_mod.ljc_energy_abs(1, pos, q, sig, eps, kc=4.0, D=4.0,
+                                    excl_offsets=np.array([0, 1, 1, 1]), excl_index=np.array([2]))
+    assert s1x[0] == 0.25
