@@ -183,6 +183,24 @@ int nbody_forces(const double *pos, const double *params, int64_t n, const nbody
                  double *out_force, double *out_potential, void *ws, size_t ws_bytes,
                  void *stream);
 
+/* nbody_forces without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  It allocates nothing: its records and split partials
+ * live in a device scratch area of 64 MiB that the library holds on each GPU
+ * it runs on until the process ends (looked up once per device on the first
+ * call there).  The arguments mean what they mean for nbody_forces; the
+ * result is the same evaluation, up to the rounding of a j split that may be
+ * smaller (so that its partials fit the scratch area).
+ * Limit: n <= 67,108,864 / record bytes - 64, i.e. 4,194,240 particles for
+ * FP32 gravity, 2,097,088 for FP32 LJC and FP64 gravity, 1,048,512 for FP64
+ * LJC; larger n is refused with NBODY_EINVAL before anything is enqueued.
+ * Every call on one GPU uses that GPU's one scratch area: calls that overlap
+ * on one GPU (on different streams or from different threads) race and must
+ * be serialised by the caller.  Nothing in the area needs to start at zero.
+ * Errors: as nbody_forces, without NBODY_EWORKSPACE. */
+int nbody_forces_noalloc(const double *pos, const double *params, int64_t n, const nbody_law *law,
+                         double *out_force, double *out_potential, void *stream);
+
 /* Forces on an active subset of particles (the block time step of
  * Section 3.4: forces on a subset of i against all j).  `ilist` [ni] device
  * int64 holds indices in [0, n) (repeats allowed); row k of the outputs is

@@ -34,7 +34,7 @@ EXPORTED = (
     "nbody_forces_jerk", "hermite_step", "hermite_block_init", "hermite_block_steps",
     "nbody_autotune_jerk", "nbody_forces_excl", "nbody_forces_batched_excl",
     "nbody_forces_backward_excl", "nbody_forces_backward_batched",
-    "nbody_probe_workspace_bytes", "nbody_probe_issue_rates",
+    "nbody_probe_workspace_bytes", "nbody_probe_issue_rates", "nbody_forces_noalloc",
 )
 
 
@@ -78,6 +78,7 @@ def lib():
         CFG = ctypes.POINTER(NBodyConfig)
         sig = {
             "nbody_forces": ([P, P, I64, LAW, P, P, P, SZ, P], ctypes.c_int),
+            "nbody_forces_noalloc": ([P, P, I64, LAW, P, P, P], ctypes.c_int),
             "nbody_forces_subset": ([P, P, I64, P, I64, LAW, P, P, P, SZ, P], ctypes.c_int),
             "nbody_forces_batched": ([P, I64, P, P, LAW, P, P, P, SZ, P], ctypes.c_int),
             "nbody_forces_backward": ([P, P, I64, LAW, P, P, P, P, I32, P, P, SZ, P], ctypes.c_int),

@@ -23,6 +23,7 @@
 #include "adjoint.h"
 #include "jerk.h"
 #include "kernels.h"
+#include "noalloc.h"
 #include "probe.h"
 
 namespace {
@@ -388,11 +389,11 @@ struct Timer {
     hipStream_t s;
     hipEvent_t a = nullptr, b = nullptr;
     bool on;
-    explicit Timer(hipStream_t st) : s(st)
+    explicit Timer(hipStream_t st, bool allowed = true) : s(st)
     {
         {
             std::lock_guard<std::mutex> lk(g_mu);
-            on = g_timing;
+            on = allowed && g_timing;
         }
         if (on && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
             (void)hipEventRecord(a, s);
@@ -612,7 +613,7 @@ Epilogue make_epi(const nbody_law *law, double *out_force, double *out_pot)
 int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const double *params,
                 int64_t n, const int64_t *rows, int64_t nrows, const Epilogue &epi, bool pot,
                 void *ws, const FwdWs &lay, hipStream_t s, PackLaunch *pk_in,
-                const ExclArgs &excl = ExclArgs{})
+                const ExclArgs &excl = ExclArgs{}, bool timed = true)
 {
     const int64_t npad = round_up(n, 64);
     char *base = (char *)ws;
@@ -648,7 +649,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
     f.partial = (double *)(base + lay.part_off);
     f.epi = epi;
     f.excl = excl;
-    Timer t(s);
+    Timer t(s, timed);
     e = launch_forces(f, s);
     t.stop();
     if (e != hipSuccess) return hip_fail(e, "all-pairs kernel");
@@ -1444,6 +1445,39 @@ int nbody_forces(const double *pos, const double *params, int64_t n, const nbody
 {
     return forces_impl(pos, params, n, nullptr, n, law, out_force, out_potential, ws, ws_bytes,
                        stream, nullptr);
+}
+
+int nbody_forces_noalloc(const double *pos, const double *params, int64_t n, const nbody_law *law,
+                         double *out_force, double *out_potential, void *stream)
+{
+    int rc = validate_law(law, false);
+    if (rc) return rc;
+    if (n < 0) return fail(NBODY_EINVAL, "n < 0");
+    if (n == 0) return NBODY_OK;
+    if (!pos || !params || !out_force) return fail(NBODY_EINVAL, "pos, params and out_force must be non-NULL");
+    const int64_t npad = round_up(n, 64);
+    const size_t rbytes = rec_bytes(law->kind, law->precision);
+    if (n > (int64_t)(kScratchBytes / rbytes) - 64)
+        return fail(NBODY_EINVAL,
+                    "n = %lld exceeds the allocation-free entry point's limit of %lld particles for this "
+                    "law and precision (%zu-byte records in a %zu-byte device scratch area); use "
+                    "nbody_forces with a workspace",
+                    (long long)n, (long long)(kScratchBytes / rbytes) - 64, rbytes, kScratchBytes);
+    void *base = nullptr;
+    hipError_t e = scratch_area(&base);
+    if (e != hipSuccess) return hip_fail(e, "scratch area");
+    const bool pot = out_potential != nullptr;
+    Cfg c = sanitize(choose(NBODY_API_FORCES, law, n, 1, pot, n), NBODY_API_FORCES, law->kind,
+                     law->precision, npad);
+    // the records first, then the split partials of the chosen j split, as far as they fit
+    FwdWs lay{};
+    lay.rec_off = 0;
+    lay.part_off = align256((size_t)npad * rbytes);
+    lay.scratch_off = lay.total = kScratchBytes;
+    const int64_t fit = (int64_t)((kScratchBytes - lay.part_off) / ((size_t)n * 4 * sizeof(double)));
+    c.j_split = (int)std::max<int64_t>(1, std::min<int64_t>(c.j_split, fit));
+    return run_forward(law, c, pos, params, n, nullptr, n, make_epi(law, out_force, out_potential), pot,
+                       base, lay, (hipStream_t)stream, nullptr, ExclArgs{}, false);
 }
 
 int nbody_forces_subset(const double *pos, const double *params, int64_t n, const int64_t *ilist,

@@ -178,6 +178,25 @@ def forces(pos, params, law: Law, potential: bool = True, out=None, exclusions: 
     return f, p
 
 
+def forces_noalloc(pos, params, law: Law, potential: bool = True, out=None):
+    """forces() through the allocation-free entry point: no workspace, the library's device
+    scratch area instead (n limited by its size; calls overlapping on one GPU race).  ``out``
+    optionally gives preallocated (force [n,3], potential [n] or None) tensors, so that a
+    caller under graph capture allocates nothing either."""
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    pos = _dev_f64(pos, (n, 3), "pos")
+    par = _params(params, n, law, pos.device)
+    if out is None:
+        f = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+        p = torch.empty(n, dtype=torch.float64, device=pos.device) if potential else None
+    else:
+        f, p = out
+    N.check(N.lib().nbody_forces_noalloc(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(f),
+                                         _ptr(p), _stream(pos.device)))
+    return f, p
+
+
 def forces_subset(pos, params, ilist, law: Law, potential: bool = True):
     """Forces on particles ilist (int64 indices) against all particles (block time step)."""
     pos = _dev_f64(pos, None, "pos")
