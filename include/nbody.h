@@ -157,7 +157,13 @@ typedef struct nbody_exclusions {
  *  j_stage    how j records reach the arithmetic: 0 = wave-uniform scalar
  *             loads into SGPRs, 1 = a wave-private LDS slot read back as
  *             broadcasts into VGPRs (so the pair arithmetic has only VGPR
- *             operands). */
+ *             operands), 2 = symmetric pair tiles: each unordered pair is
+ *             evaluated once and its force applied to both particles
+ *             (Newton's third law), for gravity with FP32_KAHAN or
+ *             FP32_FP64ACC through nbody_forces and leapfrog_step on whole
+ *             systems (elsewhere 2 reads as 1).  With j_stage 2, j_tile is
+ *             the tile edge in records, 1024 (for n <= 262,144) or 2048,
+ *             and block, i_per_lane and j_split are fixed (512, 2, 1). */
 typedef struct nbody_config {
     int32_t block;
     int32_t i_per_lane;
@@ -380,7 +386,10 @@ int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, dou
 
 /* Workspace size in bytes needed by entry point `api` for `n_total`
  * particles in `n_systems` systems (1 for the single-system entry points).
- * Returns 0 when the arguments are invalid. */
+ * For gravity with FP32_KAHAN or FP32_FP64ACC through the forces and leapfrog
+ * entry points it covers the symmetric pair tiles (j_stage 2), whose FP32
+ * partial buffer holds one partial per row and tile row: about n^2 / 8 bytes
+ * (8.6 GB at n = 2^20).  Returns 0 when the arguments are invalid. */
 size_t nbody_workspace_bytes(int32_t api, int64_t n_total, int64_t n_systems,
                              const nbody_law *law);
 

@@ -88,6 +88,39 @@ int max_split_rows(int64_t rows, int64_t nj)
 
 int max_split(int64_t npad) { return npad <= 0 ? 1 : max_split_rows(npad, npad); }
 
+// ------------------------------------------------------ symmetric tiles
+// j_stage 2 selects the symmetric pair tiles (symmetric.hip): gravity with FP32
+// pair arithmetic and Kahan or FP64 tile sums, whole systems (the forces and
+// leapfrog entry points).  j_tile is the block edge in records, 1024 (16 chunks,
+// for N up to kSymSmallMax) or 2048 (32 chunks); the workgroup shape is fixed
+// (512 threads, 2 rows per lane).  Each row gets one FP32 partial per block, so
+// the partial buffer is npad^2 / (64 blk) x 16 bytes (8 GiB at N = 2^20).
+constexpr int kSymStage = 2;
+constexpr int64_t kSymSmallMax = int64_t(1) << 18;
+constexpr int64_t kSymMinN = int64_t(1) << 16;       // the rule's threshold for whole systems
+
+bool sym_eligible(int api, int law, int prec)
+{
+    return law == NBODY_LAW_GRAVITY && (prec == NBODY_FP32_KAHAN || prec == NBODY_FP32_FP64ACC) &&
+           (api == NBODY_API_FORCES || api == NBODY_API_LEAPFROG);
+}
+
+// block edge in chunks for a requested j_tile and system size
+int sym_blk(int j_tile, int64_t n) { return (j_tile <= 1024 && n <= kSymSmallMax) ? 16 : 32; }
+int64_t sym_npad(int64_t n, int blk) { return round_up(std::max<int64_t>(n, 1), (int64_t)blk * 64); }
+size_t sym_partial_bytes(int64_t n, int blk)
+{
+    const int64_t np = sym_npad(n, blk);
+    return (size_t)(np / ((int64_t)blk * 64)) * (size_t)np * 4 * sizeof(float);
+}
+// the largest partial buffer any allowed block edge needs for n rows
+size_t sym_max_partial_bytes(int64_t n)
+{
+    size_t b = sym_partial_bytes(n, 32);
+    if (n <= kSymSmallMax) b = std::max(b, sym_partial_bytes(n, 16));
+    return b;
+}
+
 int validate_law(const nbody_law *law, bool backward)
 {
     if (!law) return fail(NBODY_EINVAL, "law is NULL");
@@ -149,6 +182,17 @@ bool ipl_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 
 Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
 {
+    if (c.j_stage == kSymStage) {
+        if (sym_eligible(api, law, prec)) {
+            c.block = kSymThreads;
+            c.ipl = 2;
+            c.j_split = 1;
+            c.j_tile = sym_blk(c.j_tile, npad) * 64;
+            return c;
+        }
+        c.j_stage = 1;                                  // other laws, precisions, entry points
+    }
+    c.j_stage = std::max(0, std::min(c.j_stage, 1));
     c.ipl = std::min(c.ipl, max_ipl(api, prec));
     if (law >= NBODY_LAW_LJC_CONSTANT) c.ipl = std::min(c.ipl, 2);
     if (api == NBODY_API_JERK || api == NBODY_API_HERMITE) c.ipl = std::min(c.ipl, 2);
@@ -249,9 +293,14 @@ std::vector<int> ranked_splits(int law, int prec, int64_t rows, int64_t nj, int 
 }
 
 // n output rows against nj j records (nj = n for a whole system)
-Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool pot)
+Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool pot, bool allow_sym = true)
 {
     Cfg c;
+    if (allow_sym && sym_eligible(api, law, prec) && n == nj && n >= kSymMinN) {
+        c.j_stage = kSymStage;
+        c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
+        return sanitize(c, api, law, prec, round_up(n, 64));
+    }
     const int64_t npad = round_up(std::max<int64_t>(std::max(n, nj), 1), 64);
     const int smax = max_split_rows(n, nj);
     if (api == NBODY_API_BATCHED || api == NBODY_API_BACKWARD_BATCHED) {
@@ -376,6 +425,14 @@ Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot, int64_
     return heuristic(api, law->kind, law->precision, n, nj, S, pot);
 }
 
+// c, or the rule's one-sided configuration when c selects the symmetric tiles
+// (which evaluate whole systems only: not row subsets or exclusion lists)
+Cfg one_sided(const Cfg &c, int api, const nbody_law *law, int64_t n, int64_t nj, bool pot)
+{
+    if (c.j_stage != kSymStage) return c;
+    return heuristic(api, law->kind, law->precision, n, nj, 1, pot, false);
+}
+
 // ------------------------------------------------------------ measurement
 bool g_timing = false;
 struct TimedLaunch {
@@ -419,11 +476,17 @@ FwdWs fwd_layout(int api, const nbody_law *law, int64_t n)
 {
     FwdWs w{};
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    const bool sym = sym_eligible(api, law->kind, law->precision);
+    // the symmetric tiles pad the records to whole blocks and keep one FP32 partial per
+    // row and block; the one-sided split keeps [split][rows][4] FP64 partials
+    const int64_t nrec = sym ? sym_npad(n, 32) : npad;
+    size_t part = (size_t)max_split(npad) * (size_t)npad * 4 * sizeof(double);
+    if (sym) part = std::max(part, sym_max_partial_bytes(n));
     size_t off = 0;
     w.rec_off = off;
-    off = align256(off + (size_t)npad * rec_bytes(law->kind, law->precision));
+    off = align256(off + (size_t)nrec * rec_bytes(law->kind, law->precision));
     w.part_off = off;
-    off = align256(off + (size_t)max_split(npad) * (size_t)npad * 4 * sizeof(double));
+    off = align256(off + part);
     w.scratch_off = off;
     if (api == NBODY_API_LEAPFROG) off = align256(off + (size_t)npad * 3 * sizeof(double));
     w.total = off;
@@ -615,7 +678,11 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
                 void *ws, const FwdWs &lay, hipStream_t s, PackLaunch *pk_in,
                 const ExclArgs &excl = ExclArgs{}, bool timed = true)
 {
-    const int64_t npad = round_up(n, 64);
+    // the symmetric tiles (j_stage 2) evaluate whole systems; sanitize admits the
+    // configuration only for gravity with FP32_KAHAN / FP32_FP64ACC
+    const bool sym = c.j_stage == kSymStage && rows == nullptr && nrows == n && excl.off == nullptr;
+    const int blk = sym ? c.j_tile / 64 : 0;
+    const int64_t npad = sym ? sym_npad(n, blk) : round_up(n, 64);
     char *base = (char *)ws;
     PackLaunch pk{};
     if (pk_in) pk = *pk_in;
@@ -629,6 +696,27 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
     pk.rec = base + lay.rec_off;
     hipError_t e = launch_pack(pk, s);
     if (e != hipSuccess) return hip_fail(e, "pack");
+
+    if (sym) {
+        SymLaunch a{};
+        a.prec = law->precision;
+        a.pot = pot ? 1 : 0;
+        a.blk = blk;
+        a.nblk = npad / ((int64_t)blk * 64);
+        a.npad = npad;
+        a.n = n;
+        a.eps2 = law->softening * law->softening;
+        a.rec = base + lay.rec_off;
+        a.partial = (float4 *)(base + lay.part_off);
+        a.epi = epi;
+        Timer t(s, timed);
+        e = launch_sym(a, s);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "symmetric all-pairs kernel");
+        e = launch_sym_reduce(a, s);
+        if (e != hipSuccess) return hip_fail(e, "symmetric partial reduction");
+        return NBODY_OK;
+    }
 
     FwdLaunch f{};
     f.law = law->kind;
@@ -746,9 +834,10 @@ int jerk_impl(const double *pos, const double *vel, const double *mass, int64_t 
 
 bool cfg_valid(const nbody_config *c)
 {
-    return c && c->block >= 64 && c->block <= 256 && c->block % 64 == 0 && ipl_ok(c->i_per_lane) &&
-           c->j_tile >= 64 && c->j_tile % 64 == 0 && c->j_tile <= (1 << 20) && c->j_split >= 1 &&
-           c->j_split <= kMaxSplit && (c->j_stage == 0 || c->j_stage == 1);
+    return c && c->block >= 64 && c->block <= (c->j_stage == kSymStage ? kSymThreads : 256) &&
+           c->block % 64 == 0 && ipl_ok(c->i_per_lane) && c->j_tile >= 64 && c->j_tile % 64 == 0 &&
+           c->j_tile <= (1 << 20) && c->j_split >= 1 && c->j_split <= kMaxSplit &&
+           (c->j_stage == 0 || c->j_stage == 1 || c->j_stage == kSymStage);
 }
 
 Cfg from_abi(const nbody_config *c)
@@ -1084,7 +1173,9 @@ int forces_impl(const double *pos, const double *params, int64_t n, const int64_
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     const bool pot = out_potential != nullptr;
-    const Cfg c = forced ? *forced : choose(NBODY_API_FORCES, law, nrows, 1, pot, n);
+    Cfg c = sanitize(forced ? *forced : choose(NBODY_API_FORCES, law, nrows, 1, pot, n), NBODY_API_FORCES,
+                     law->kind, law->precision, round_up(std::max(n, nrows), 64));
+    if (rows || excl) c = one_sided(c, NBODY_API_FORCES, law, nrows, n, pot);
     const Cfg cs = with_excl(sanitize(c, NBODY_API_FORCES, law->kind, law->precision,
                                       round_up(std::max(n, nrows), 64)), excl != nullptr);
     return run_forward(law, cs, pos, params, n, rows, nrows, make_epi(law, out_force, out_potential),
@@ -1231,6 +1322,14 @@ std::vector<Cfg> candidate_set(int api, int law, int prec, int64_t n, bool pot)
                     }
         return out;
     }
+    if (sym_eligible(api, law, prec))
+        for (int jt : {1024, 2048}) {          // the symmetric tiles, both block edges
+            if (jt == 1024 && n > kSymSmallMax) continue;
+            Cfg c;
+            c.j_stage = kSymStage;
+            c.j_tile = jt;
+            out.push_back(sanitize(c, api, law, prec, npad));
+        }
     const bool jerk = api == NBODY_API_JERK;
     for (int js : {0, 1})
         for (int ipl : {1, 2, 4, 8}) {
@@ -1469,6 +1568,24 @@ int nbody_forces_noalloc(const double *pos, const double *params, int64_t n, con
     const bool pot = out_potential != nullptr;
     Cfg c = sanitize(choose(NBODY_API_FORCES, law, n, 1, pot, n), NBODY_API_FORCES, law->kind,
                      law->precision, npad);
+    if (c.j_stage == kSymStage) {
+        // the symmetric tiles when their padded records and slot partials fit the area
+        // (the chosen block edge, else the larger one, which needs fewer partials)
+        for (int blk : {c.j_tile / 64, 32}) {
+            const size_t recs = align256((size_t)sym_npad(n, blk) * rbytes);
+            if (recs + sym_partial_bytes(n, blk) > kScratchBytes) continue;
+            FwdWs lay{};
+            lay.rec_off = 0;
+            lay.part_off = recs;
+            lay.scratch_off = lay.total = kScratchBytes;
+            Cfg cb = c;
+            cb.j_tile = blk * 64;
+            return run_forward(law, cb, pos, params, n, nullptr, n, make_epi(law, out_force, out_potential),
+                               pot, base, lay, (hipStream_t)stream, nullptr, ExclArgs{}, false);
+        }
+        c = sanitize(one_sided(c, NBODY_API_FORCES, law, n, n, pot), NBODY_API_FORCES, law->kind,
+                     law->precision, npad);
+    }
     // the records first, then the split partials of the chosen j split, as far as they fit
     FwdWs lay{};
     lay.rec_off = 0;

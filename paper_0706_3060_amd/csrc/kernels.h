@@ -77,6 +77,24 @@ hipError_t launch_forces(const FwdLaunch &f, hipStream_t s);
 hipError_t launch_reduce_split(const FwdLaunch &f, hipStream_t s);
 int forces_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block);
 
+// ---- symmetric pair tiles (symmetric.hip): gravity, every unordered pair once ----
+constexpr int kSymThreads = 512;           // 8 waves per workgroup, 2 i chunks per wave
+constexpr int kSymMaxBlk = 32;             // largest block edge in chunks of 64 records
+struct SymLaunch {
+    int prec, pot;                 // P_KAHAN or P_FP64ACC tile sums; potential on/off
+    int blk;                       // block edge in chunks of 64 records: 16 or 32
+    int64_t nblk;                  // blocks; tiles = nblk (nblk + 1) / 2
+    int64_t npad;                  // records = nblk * blk * 64 (zero-mass padding past n)
+    int64_t n;                     // rows finished by the reduction
+    double eps2;
+    const void *rec;               // FP32 gravity records {x, y, z, m}
+    float4 *partial;               // [nblk][npad] (x, y, z, potential) FP32 slot partials
+    Epilogue epi;
+};
+hipError_t launch_sym(const SymLaunch &a, hipStream_t s);
+hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s);
+int sym_blocks_per_cu(int prec, int pot);
+
 // ---- batched (one persistent launch over (system, row-block) work units) ----
 struct BatchLaunch {
     int law, prec, ipl, pot;

@@ -1,0 +1,263 @@
+// Symmetric all-pairs gravity: every unordered pair {i, j} is evaluated once
+// and its force is applied to both particles (Newton's third law), so one
+// reciprocal square root serves two interactions.
+//
+// Decomposition.  The padded records form nblk blocks of blk chunks of 64
+// (blk = 16 or 32).  Workgroup t takes tile (b1, b2), b1 <= b2, of the upper
+// triangle of the block grid: the pairs between the rows of block b1 and the
+// rows of block b2 (on the diagonal, b1 == b2, each unordered pair once).  Its
+// 8 waves hold two i chunks each (128 rows per wave, 16 chunks per pass; two
+// passes for blk = 32) and sweep the j chunks of b2 in rounds: in round r wave
+// w takes j chunk (w + r) mod blk, so no two waves touch one j chunk in the
+// same round, and a barrier closes every round.  The order in which the
+// contributions of the waves reach a j chunk is therefore fixed, and the sums
+// repeat bit for bit.
+//
+// A 64 x 64 mini-tile (one i chunk against one j chunk) takes 64 steps.  At
+// step s lane l pairs its i particle with j = l + s (mod 64): the j records
+// are staged twice in a wave-private LDS slot, so each lane reads its own
+// record at a constant offset.  The j-side sums of the mini-tile travel with
+// their particle: after each step every lane takes its right neighbour's four
+// sums through the LDS crossbar (ds_bpermute), so after 64 steps lane l holds
+// the sums of j = l again.  Between mini-tiles the j sums of a tile live in LDS
+// (FP32, one slot per j of block b2); the i sums are FP32 mini-tile partials
+// folded into Kahan or FP64 running sums (the tile-level compensation of the
+// one-sided kernels).
+//
+// Output.  Tile (b1, b2) writes one FP32 partial (x, y, z, potential) per row
+// of b1 into slot b2 and one per row of b2 into slot b1 of the partial buffer
+// [nblk][npad][4] (a diagonal tile adds its i and j sums and writes slot b1),
+// so every (slot, row) is written exactly once.  k_sym_reduce then adds the
+// nblk slots of each row in slot order in FP64 (Neumaier) and applies the
+// epilogue (scales, leapfrog kick).
+#include "allpairs.h"
+#include "kernels.h"
+
+namespace nbk {
+
+constexpr int kSymWaves = kSymThreads / kWave;    // waves per workgroup
+constexpr int kSymPassChunks = 2 * kSymWaves;     // i chunks of one pass (two per wave)
+
+// the value of lane (l + 1) mod 64, through the LDS crossbar (no LDS memory)
+__device__ __forceinline__ float from_next_lane(int byte_addr, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, v)));
+}
+
+// tile t of the row-major upper triangle (b1 <= b2) of an n x n block grid
+__device__ __forceinline__ void sym_tile(int64_t t, int64_t n, int64_t &b1, int64_t &b2)
+{
+    // start(b) = b n - b (b - 1) / 2 is the first tile of row b
+    const double h = (double)n + 0.5;
+    int64_t b = (int64_t)(h - __builtin_sqrt(h * h - 2.0 * (double)t));
+    b = b < 0 ? 0 : (b > n - 1 ? n - 1 : b);
+    while (b > 0 && b * n - b * (b - 1) / 2 > t) --b;
+    while (b + 1 < n && (b + 1) * n - (b + 1) * b / 2 <= t) ++b;
+    b1 = b;
+    b2 = b + (t - (b * n - b * (b - 1) / 2));
+}
+
+// One mini-tile: the wave's two i chunks (records iv[0], iv[1], running
+// partials p) against the j chunk in the wave's LDS slot `st` (staged twice),
+// with the j sums jv entering and leaving in lane order.  MASK (diagonal
+// tiles only): per i slot k, wi[k] / wj[k] switch the i and j sides on or off
+// and self[k] marks a slot whose i chunk is the j chunk itself, whose pair at
+// step 0 is the particle with itself.
+template <bool POT, bool MASK>
+__device__ __forceinline__ void sym_minitile(const GravRec<float> *st, const GravRec<float> (&iv)[2],
+                                             float eps2, int bp_addr, float (&p)[2][4], float (&jv)[4],
+                                             const float (&wi)[2], const float (&wj)[2], const bool (&self)[2])
+{
+    const int lane = lane_id();
+#pragma unroll 8
+    for (int s = 0; s < kWave; ++s) {
+        const GravRec<float> J = st[lane + s];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float dx = J.x - iv[k].x, dy = J.y - iv[k].y, dz = J.z - iv[k].z;
+            float r2 = fma_(dx, dx, eps2);
+            r2 = fma_(dy, dy, r2);
+            r2 = fma_(dz, dz, r2);
+            float mj = J.m, mi = iv[k].m;
+            if (MASK) {
+                const bool sk = self[k] && s == 0;
+                r2 = sk ? 1.0f : r2;
+                mj = sk ? 0.0f : mj * wi[k];
+                mi = mi * wj[k];
+            }
+            const float ri = rsqrt_(r2);
+            const float ri3 = (ri * ri) * ri;
+            const float cj = mj * ri3, ci = mi * ri3;
+            p[k][0] = fma_(cj, dx, p[k][0]);
+            p[k][1] = fma_(cj, dy, p[k][1]);
+            p[k][2] = fma_(cj, dz, p[k][2]);
+            jv[0] = fma_(-ci, dx, jv[0]);
+            jv[1] = fma_(-ci, dy, jv[1]);
+            jv[2] = fma_(-ci, dz, jv[2]);
+            if (POT) {
+                p[k][3] = fma_(mj, ri, p[k][3]);
+                jv[3] = fma_(mi, ri, jv[3]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < (POT ? 4 : 3); ++c) jv[c] = from_next_lane(bp_addr, jv[c]);
+    }
+}
+
+template <int PREC, bool POT>
+__global__ __launch_bounds__(kSymThreads) void k_sym(SymLaunch a)
+{
+    using R = GravRec<float>;
+    const R *__restrict__ rec = (const R *)a.rec;
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int blk = a.blk;
+    int64_t b1, b2;
+    sym_tile(blockIdx.x, a.nblk, b1, b2);
+    const bool diag = b1 == b2;
+    const float eps2 = (float)a.eps2;
+    const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
+
+    __shared__ float4 jacc[kSymMaxBlk][kWave];            // j sums of block b2
+    __shared__ R st_all[kSymWaves][2 * kWave];            // each wave's j chunk, staged twice
+    R *st = st_all[w];
+    for (int k = threadIdx.x; k < blk * kWave; k += kSymThreads) jacc[k / kWave][k % kWave] = float4{0, 0, 0, 0};
+    const int64_t jrec0 = b2 * blk * kWave;                // first record of block b2
+    const int64_t irec0 = b1 * blk * kWave;                // first record of block b1
+    __syncthreads();
+
+    for (int pass = 0; pass < blk / kSymPassChunks; ++pass) {
+        const int aloc = pass * kSymPassChunks + 2 * w;    // local chunks aloc, aloc + 1 of block b1
+        R iv[2];
+        iv[0] = rec[irec0 + (int64_t)aloc * kWave + lane];
+        iv[1] = rec[irec0 + (int64_t)(aloc + 1) * kWave + lane];
+        RunSum<PREC> acc[2][4];
+        float p[2][4];
+        R g = rec[jrec0 + (int64_t)(w % blk) * kWave + lane];
+        for (int r = 0; r < blk; ++r) {
+            const int q = (w + r) % blk;
+            st[lane] = g;
+            st[lane + kWave] = g;
+            g = rec[jrec0 + (int64_t)((w + r + 1) % blk) * kWave + lane];   // next round's chunk
+            const float4 j4 = jacc[q][lane];
+            float jv[4] = {j4.x, j4.y, j4.z, j4.w};
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[k][c].begin(p[k][c]);
+            if (!diag) {
+                const float one[2] = {1.0f, 1.0f};
+                const bool none[2] = {false, false};
+                sym_minitile<POT, false>(st, iv, eps2, bp_addr, p, jv, one, one, none);
+            } else {
+                // chunk q against i chunk aloc + k: symmetric when q is after it, its own
+                // chunk's pairs one-sided when q is it, nothing when q is before it (that pair
+                // is evaluated by the wave holding q)
+                float wi[2], wj[2];
+                bool self[2];
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int rel = q - (aloc + k);
+                    wi[k] = rel >= 0 ? 1.0f : 0.0f;
+                    wj[k] = rel > 0 ? 1.0f : 0.0f;
+                    self[k] = rel == 0;
+                }
+                sym_minitile<POT, true>(st, iv, eps2, bp_addr, p, jv, wi, wj, self);
+            }
+            jacc[q][lane] = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
+#pragma unroll
+            for (int k = 0; k < 2; ++k)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[k][c].fold(p[k][c]);
+            __syncthreads();
+        }
+        // i sums of this pass: slot b2 of the rows of block b1, or, on the diagonal, added
+        // to the j sums of the same rows (no other wave touches these chunks now)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const float4 v = float4{(float)acc[k][0].value(), (float)acc[k][1].value(),
+                                    (float)acc[k][2].value(), POT ? (float)acc[k][3].value() : 0.0f};
+            if (!diag) {
+                a.partial[b2 * a.npad + irec0 + (int64_t)(aloc + k) * kWave + lane] = v;
+            } else {
+                float4 &t = jacc[aloc + k][lane];
+                t = float4{t.x + v.x, t.y + v.y, t.z + v.z, t.w + v.w};
+            }
+        }
+        __syncthreads();
+    }
+    // j sums: slot b1 of the rows of block b2
+    for (int q = w; q < blk; q += kSymWaves) a.partial[b1 * a.npad + jrec0 + (int64_t)q * kWave + lane] = jacc[q][lane];
+}
+
+// Row r: the nblk slot partials in slot order (FP64, Neumaier), then the epilogue.
+__global__ __launch_bounds__(256) void k_sym_reduce(SymLaunch a)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n) return;
+    NSum v[4];
+    const float4 *__restrict__ part = a.partial;
+    for (int64_t k = 0; k < a.nblk; ++k) {
+        const float4 x = part[k * a.npad + r];
+        v[0].add((double)x.x);
+        v[1].add((double)x.y);
+        v[2].add((double)x.z);
+        v[3].add((double)x.w);
+    }
+    const Epilogue &e = a.epi;
+    double f0 = e.fscale * v[0].value(), f1 = e.fscale * v[1].value(), f2 = e.fscale * v[2].value();
+    if (e.kick) {
+        const double s = e.inv_mass ? e.inv_mass[r] : 1.0;
+        f0 *= s;
+        f1 *= s;
+        f2 *= s;
+        e.vel[3 * r] += e.half_dt * f0;
+        e.vel[3 * r + 1] += e.half_dt * f1;
+        e.vel[3 * r + 2] += e.half_dt * f2;
+    }
+    e.out_force[3 * r] = f0;
+    e.out_force[3 * r + 1] = f1;
+    e.out_force[3 * r + 2] = f2;
+    if (a.pot && e.out_pot) e.out_pot[r] = e.pscale * v[3].value();
+}
+
+hipError_t launch_sym(const SymLaunch &a, hipStream_t s)
+{
+    if (a.nblk <= 0) return hipSuccess;
+    if (a.blk % kSymPassChunks != 0 || a.blk > kSymMaxBlk || a.npad != (int64_t)a.nblk * a.blk * kWave)
+        return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(a.nblk * (a.nblk + 1) / 2)), block(kSymThreads);
+    if (a.prec == P_KAHAN) {
+        if (a.pot) hipLaunchKernelGGL((k_sym<P_KAHAN, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_sym<P_KAHAN, false>), grid, block, 0, s, a);
+    } else if (a.prec == P_FP64ACC) {
+        if (a.pot) hipLaunchKernelGGL((k_sym<P_FP64ACC, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_sym<P_FP64ACC, false>), grid, block, 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s)
+{
+    if (a.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sym_reduce, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+int sym_blocks_per_cu(int prec, int pot)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (prec == P_KAHAN)
+        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_KAHAN, true>, kSymThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_KAHAN, false>, kSymThreads, 0);
+    else if (prec == P_FP64ACC)
+        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_FP64ACC, true>, kSymThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_FP64ACC, false>, kSymThreads, 0);
+    return e == hipSuccess ? nb : 0;
+}
+
+}  // namespace nbk

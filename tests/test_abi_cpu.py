@@ -163,9 +163,14 @@ def test_config_validation(N):
     good = N.NBodyConfig(256, 1, 256, 4, 1)
     assert lib.nbody_set_config(0, ctypes.byref(good)) == 0
     assert lib.nbody_set_config(0, None) == 0
+    # the symmetric pair tiles (j_stage 2) take the 512-thread workgroup
+    for ok in [N.NBodyConfig(512, 2, 2048, 1, 2), N.NBodyConfig(256, 1, 1024, 1, 2)]:
+        assert lib.nbody_set_config(0, ctypes.byref(ok)) == 0
+        assert lib.nbody_set_config(0, None) == 0
     for bad in [N.NBodyConfig(96, 1, 256, 1, 0), N.NBodyConfig(256, 3, 256, 1, 0),
                 N.NBodyConfig(256, 1, 100, 1, 0), N.NBodyConfig(256, 1, 256, 65, 0),
-                N.NBodyConfig(256, 1, 256, 1, 2), N.NBodyConfig(512, 1, 256, 1, 0)]:
+                N.NBodyConfig(256, 1, 256, 1, 3), N.NBodyConfig(512, 1, 256, 1, 0),
+                N.NBodyConfig(1024, 2, 2048, 1, 2)]:
         assert lib.nbody_set_config(0, ctypes.byref(bad)) == N.NBODY_EINVAL
     assert lib.nbody_set_config(7, ctypes.byref(good)) == N.NBODY_EINVAL
 

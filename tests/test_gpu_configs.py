@@ -21,8 +21,9 @@ from paper_0706_3060_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-# The forced alternative shape of the full-size case: one j part, scalar staging.
-SCALAR_CFG = (256, 1, 256, 1, 0)
+# The forced alternative shapes of the full-size case: the one-sided kernel with 32 j parts over
+# XCD-ordered blocks and LDS staging, and with one j part and scalar staging.
+ALT_CFG = {"one_sided": (256, 1, 256, 32, 1), "scalar": (256, 1, 256, 1, 0)}
 
 
 @pytest.fixture(scope="module")
@@ -215,13 +216,14 @@ def test_config4_full_ensemble(nb, full_ensemble, shape):
         assert np.median(e) <= 1e-5 and e.max() <= 1e-3
 
 
-@pytest.mark.parametrize("shape", ["rule", "scalar"])
+@pytest.mark.parametrize("shape", ["rule", "one_sided", "scalar"])
 def test_config5_plummer_1m(nb, shape):
     """Gravity at N = 2^20, FP32 + Kahan, against the FP64 GPU pass over all rows and the oracle
     on sampled rows.  "rule" runs the configuration the benchmark times (the library's rule for
-    this size: LDS staging, 32 j parts over XCD-ordered blocks and the fixed-order split
+    this size: the symmetric pair tiles with 2048-record blocks and the slot-ordered partial
     reduction), through both timed entry points: the forward and one kick-drift-kick step.
-    "scalar" forces one j part with scalar staging."""
+    "one_sided" forces the one-sided kernel with 32 j parts over XCD-ordered blocks and LDS
+    staging, "scalar" one j part with scalar staging."""
     n, eps, dt = 1 << 20, 0.005, 1e-3
     pos, vel, m = W.plummer(n, 5)
     x, mm = dev(pos), dev(m)
@@ -230,11 +232,11 @@ def test_config5_plummer_1m(nb, shape):
     if shape == "rule":
         for api in (nb.API_FORCES, nb.API_LEAPFROG):
             c = nb.get_config(api, n, law)
-            assert (c["j_stage"], c["j_split"], c["i_per_lane"]) == (1, 32, 1), (api, c)
+            assert (c["j_stage"], c["j_tile"], c["i_per_lane"]) == (2, 2048, 2), (api, c)
     try:
-        if shape == "scalar":
+        if shape != "rule":
             for api in (nb.API_FORCES, nb.API_LEAPFROG):
-                nb.set_config(api, *SCALAR_CFG)
+                nb.set_config(api, *ALT_CFG[shape])
         f32, p32 = nb.forces(x, mm, law)
         # one step of the timed loop: a(t) from the forward, kick-drift, forces at x(t+dt), kick
         X, V, A = x.clone(), dev(vel), f32.clone()

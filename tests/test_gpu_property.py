@@ -124,7 +124,7 @@ def gpu_law(nb, law, prec):
        ipl=st.sampled_from([1, 2, 4, 8]),
        j_tile=st.sampled_from([64, 128, 256, 512]),
        j_split=st.integers(min_value=1, max_value=64),
-       j_stage=st.sampled_from([0, 1]),
+       j_stage=st.sampled_from([0, 1, 2]),
        potential=st.booleans(),
        seed=st.integers(min_value=0, max_value=10 ** 6))
 def test_random_systems_and_configurations(nb, n, law, prec, block, ipl, j_tile, j_split, j_stage,
