@@ -7,7 +7,8 @@ Kahan-compensated accumulation.  One timed step is one kick-drift-kick
 leapfrog step in FP64 (pack + kick/drift, the all-pairs force and potential
 evaluation with its FP64 finalize, and the closing kick) -- N^2 ordered pair
 interactions.  The launch configuration comes from the autotuner, run before
-the timed region.
+the timed region (the rule's choice at this size: the symmetric pair tiles, which
+evaluate each unordered pair once and apply it to both particles).
 
 Printed (one JSON line on stdout):
   * interactions per second of the headline step;
@@ -169,17 +170,25 @@ def main():
     log("step %.3f ms, %.1f G pairs/s; all-pairs kernel %.3f ms/launch over %d launches, %.2f TFLOP/s"
         % (ms_step, value, k_ms / max(k_launches, 1), k_launches, achieved))
 
-    # issue-rate ceiling of the gravity pair sequence, measured on this GPU: per
-    # pair-wave, 13 ordinary FP32 VALU instructions and one v_rsq_f32 carry 20 flops a
-    # lane, against 64 flops per SIMD-cycle at peak (157.3 TFLOP/s is that at 2.4 GHz).
-    # The clock under the pair kernel is not visible here: clock_for_kernel_ghz is the
-    # clock at which the measured launch time equals the modelled cycles.
+    # issue-rate ceiling of the timed kernel's instruction sequence, measured on this GPU,
+    # per interaction-wave (64 interactions of 20 flops against 64 flops per SIMD-cycle at
+    # peak; 157.3 TFLOP/s is that at 2.4 GHz).  Symmetric pair tiles (j_stage 2): one
+    # unordered pair-wave is 18 ordinary FP32 VALU instructions and one v_rsq_f32 for two
+    # interactions (the j sums move through the LDS crossbar, off the VALU); one-sided
+    # kernels: 13 and one v_rsq_f32 for one interaction.  The clock under the pair kernel
+    # is not visible here: clock_for_kernel_ghz is the clock at which the measured launch
+    # time equals the modelled cycles.
     rates = nb.probe_issue_rates(dev)
-    pair_cycles = 13 * rates["fma_cycles"] + rates["rsq_cycles"]
-    pair_waves_per_simd = pairs / 64.0 / (4 * props.multi_processor_count)
-    ceiling = {"probe": rates, "pair_wave_cycles_model": pair_cycles,
-               "cap_frac_of_clock_peak": 20.0 / pair_cycles,
-               "clock_for_kernel_ghz": pair_cycles * pair_waves_per_simd / k_avg_s / 1e9}
+    if cfg_used["j_stage"] == 2:
+        inter_cycles = (18 * rates["fma_cycles"] + rates["rsq_cycles"]) / 2.0
+        model = "symmetric: (18 VALU + 1 rsq) per unordered pair-wave, two interactions"
+    else:
+        inter_cycles = 13 * rates["fma_cycles"] + rates["rsq_cycles"]
+        model = "one-sided: 13 VALU + 1 rsq per interaction-wave"
+    inter_waves_per_simd = pairs / 64.0 / (4 * props.multi_processor_count)
+    ceiling = {"probe": rates, "model": model, "interaction_wave_cycles_model": inter_cycles,
+               "cap_frac_of_clock_peak": 20.0 / inter_cycles,
+               "clock_for_kernel_ghz": inter_cycles * inter_waves_per_simd / k_avg_s / 1e9}
     log("ceiling:", ceiling)
 
     # oracle on a row sample of the same (t = 0) workload, same FP32-rounded inputs
@@ -264,7 +273,22 @@ def main():
 
 
 TRAFFIC_SOURCES = ["paper_0706_3060_amd/csrc/forward.hip", "paper_0706_3060_amd/csrc/device.h",
-                   "paper_0706_3060_amd/csrc/allpairs.h", "paper_0706_3060_amd/csrc/kernels.h"]
+                   "paper_0706_3060_amd/csrc/allpairs.h", "paper_0706_3060_amd/csrc/kernels.h",
+                   "paper_0706_3060_amd/csrc/symmetric.hip"]
+
+
+def timed_kernel(n, cfg):
+    """Name and grid (work-items) of the all-pairs launch of the headline configuration:
+    the symmetric pair tiles (j_stage 2; one 512-thread workgroup per tile of the block
+    grid's upper triangle) or the one-sided forces kernel."""
+    if cfg["j_stage"] == 2:
+        rec = cfg["j_tile"]
+        nblk = -(-n // rec)
+        return "k_sym<1, true>", str(nblk * (nblk + 1) // 2 * cfg["block"])
+    waves = -(-n // (64 * cfg["i_per_lane"]))
+    wpb = cfg["block"] // 64
+    return ("k_forces<0, 1, %d, true, %d>" % (cfg["i_per_lane"], cfg["j_stage"]),
+            str(-(-waves // wpb) * cfg["block"] * cfg["j_split"]))
 
 
 def make_traffic(fetch_csv, write_csv, bench_json):
@@ -279,10 +303,7 @@ def make_traffic(fetch_csv, write_csv, bench_json):
     line = [ln for ln in open(bench_json).read().splitlines() if ln.startswith("{")][-1]
     cfg_run = json.loads(line)["config"]
     n, cfg = cfg_run["n"], cfg_run["launch"]
-    waves = -(-n // (64 * cfg["i_per_lane"]))
-    wpb = cfg["block"] // 64
-    grid = str(-(-waves // wpb) * cfg["block"] * cfg["j_split"])
-    name = "k_forces<0, 1, %d, true, %d>" % (cfg["i_per_lane"], cfg["j_stage"])
+    name, grid = timed_kernel(n, cfg)
     copy_bytes = 256 << 20
     copy_grid = "131072"                        # the grid rocprofv3 reports for the 256 MiB copy
 
@@ -312,7 +333,7 @@ def make_traffic(fetch_csv, write_csv, bench_json):
            "copy_bytes": copy_bytes, "fetch_scale": fs, "write_scale": ws,
            "bytes_per_launch": fk * 1024 * fs + wk * 1024 * ws, "config": cfg, "n": n}
     # one record per launch configuration, all on the same kernel sources
-    path = os.path.join(ROOT, "profiles", "traffic_k_forces_gravity_fp32kahan_n%d.json" % n)
+    path = os.path.join(ROOT, "profiles", "traffic_allpairs_gravity_fp32kahan_n%d.json" % n)
     records = []
     try:
         with open(path) as fh:
@@ -342,7 +363,7 @@ def measured_traffic(n, cfg):
     (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the kernel sources or
     the launch configuration differ from the ones the counters were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_k_forces_gravity_fp32kahan_n1048576.json")
+    path = os.path.join(ROOT, "profiles", "traffic_allpairs_gravity_fp32kahan_n1048576.json")
     try:
         with open(path) as fh:
             records = json.load(fh)["records"]
@@ -374,10 +395,11 @@ def save_inputs(out_dir, n, pos, vel, mass, ens, md):
 
 
 def shard_leg(nb, torch, dev, x, m, law, full_kernel_ms, n_gpus=8):
-    """One GPU's share of the headline evaluation if the rows were sharded over n_gpus GPUs:
-    a contiguous block of N / n_gpus output rows against all N j records
-    (nbody_forces_subset), for the first and the last block.  Its kernel time against
-    1 / n_gpus of the full launch tells how well the share alone fills the chip."""
+    """One GPU's share of the headline evaluation if the rows were sharded over n_gpus GPUs
+    with the one-sided kernel: a contiguous block of N / n_gpus output rows against all N j
+    records (nbody_forces_subset), for the first and the last block.  Its kernel time
+    against 1 / n_gpus of the full (symmetric) launch: below one by the symmetric kernel's
+    advantage plus whatever the share loses in filling the chip."""
     n = x.shape[0]
     rows = n // n_gpus
     res = {"n": n, "gpus": n_gpus, "rows": rows, "full_kernel_ms": full_kernel_ms}

@@ -468,16 +468,25 @@ const char *nbody_version(void);
 size_t nbody_probe_workspace_bytes(void);
 
 /* Measure, on the current device, the shader cycles a SIMD spends per wave64
- * instruction: out[0] FP32 FMA with all operands in VGPRs, out[1] FP32 FMA
- * with one SGPR operand, out[2] v_rsq_f32; out[3] the shader clock in GHz
- * while the FMA probe runs (shader-cycle counter over the fixed-rate wall
- * counter); out[4] that wall counter's rate in MHz.  Each probe runs eight
- * independent chains per lane with eight waves per SIMD: four untimed
- * launches, then three timed ones of about a millisecond, each taken at its
- * own measured clock; the median is reported.
- * out: host double[5]; ws: device workspace of
+ * instruction at eight waves per SIMD, each probe running independent chains
+ * per lane (four untimed launches, then three timed ones of about a
+ * millisecond, each taken at its own measured clock; the median is reported):
+ *   out[0] v_fma_f32 with all operands in VGPRs (shared multiplier/addend)
+ *   out[1] v_fma_f32 with one SGPR operand
+ *   out[2] v_rsq_f32
+ *   out[3] the shader clock in GHz while the out[0] probe runs (shader-cycle
+ *          counter over the fixed-rate wall counter); out[4] that counter's
+ *          rate in MHz
+ *   out[5] one v_rsq_f32 with 13 independent FMAs interleaved: cycles per
+ *          group of 14 (an rsq that overlapped the FMAs would make this close
+ *          to 13 x out[0]; no overlap makes it 13 x out[0] + out[2] or more)
+ *   out[6] v_fma_f32 whose multiplier and addend are distinct VGPRs that
+ *          rotate over the chains
+ *   out[7] v_mov_b32 with a DPP row rotation (a cross-lane move on the VALU)
+ *   out[8] ds_bpermute_b32 (a cross-lane move through the LDS crossbar)
+ * out: host double[n_out], n_out >= 9; ws: device workspace of
  * nbody_probe_workspace_bytes() bytes.  Synchronises `stream`. */
-int nbody_probe_issue_rates(double *out, void *ws, size_t ws_bytes, void *stream);
+int nbody_probe_issue_rates(double *out, int32_t n_out, void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -97,7 +97,7 @@ def lib():
             "nbody_flops_per_pair": ([I32, I32, I32], I32),
             "nbody_version": ([], ctypes.c_char_p),
             "nbody_probe_workspace_bytes": ([], SZ),
-            "nbody_probe_issue_rates": ([ctypes.POINTER(ctypes.c_double), P, SZ, P], ctypes.c_int),
+            "nbody_probe_issue_rates": ([ctypes.POINTER(ctypes.c_double), I32, P, SZ, P], ctypes.c_int),
             "nbody_forces_jerk": ([P, P, P, I64, P, I64, LAW, P, P, P, P, SZ, P], ctypes.c_int),
             "hermite_step": ([P, P, P, P, P, I64, LAW, D, I32, P, SZ, P], ctypes.c_int),
             "hermite_block_init": ([P, P, I64, D, D, P, P, P], ctypes.c_int),

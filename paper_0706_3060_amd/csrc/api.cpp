@@ -193,6 +193,8 @@ Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
         c.j_stage = 1;                                  // other laws, precisions, entry points
     }
     c.j_stage = std::max(0, std::min(c.j_stage, 1));
+    // the one-sided, batched, adjoint and jerk kernels are built for up to 256 threads
+    c.block = std::max(64, std::min(c.block, 256)) / 64 * 64;
     c.ipl = std::min(c.ipl, max_ipl(api, prec));
     if (law >= NBODY_LAW_LJC_CONSTANT) c.ipl = std::min(c.ipl, 2);
     if (api == NBODY_API_JERK || api == NBODY_API_HERMITE) c.ipl = std::min(c.ipl, 2);
@@ -1453,6 +1455,7 @@ const char *nbody_version(void) { return "nbody-mi355x 0.1 (gfx950)"; }
 
 // ------------------------------------------------------------- probes ----
 constexpr int kProbeIters = 16384;
+constexpr int kProbeOutputs = 9;
 
 // eight waves per SIMD: the rate a dense VGPR-only stream sustains depends on the
 // waves a SIMD can alternate between (measured: 3.5 cycles per FMA at four waves,
@@ -1461,9 +1464,10 @@ static int probe_blocks() { return std::min(device_cus(), 4096) * 8; }
 
 size_t nbody_probe_workspace_bytes(void) { return (size_t)probe_blocks() * 256 * sizeof(float) + 256; }
 
-int nbody_probe_issue_rates(double *out, void *ws, size_t ws_bytes, void *stream)
+int nbody_probe_issue_rates(double *out, int32_t n_out, void *ws, size_t ws_bytes, void *stream)
 {
     if (!out) return fail(NBODY_EINVAL, "out is NULL");
+    if (n_out < kProbeOutputs) return fail(NBODY_EINVAL, "out holds %d values, %d needed", n_out, kProbeOutputs);
     const int blocks = probe_blocks();
     int rc = check_ws(ws, ws_bytes, nbody_probe_workspace_bytes());
     if (rc) return rc;
@@ -1481,13 +1485,14 @@ int nbody_probe_issue_rates(double *out, void *ws, size_t ws_bytes, void *stream
     (void)hipDeviceGetAttribute(&rtc_khz, hipDeviceAttributeWallClockRate, dev);
     (void)hipDeviceGetAttribute(&max_khz, hipDeviceAttributeClockRate, dev);
     const double simds = 4.0 * device_cus();
-    const double instr = (double)blocks * 4.0 / simds * kProbeIters * 8.0;   // per SIMD
     // Per mode: warm-up launches (clocks settle), then three timed launches, each
     // at its own clock (shader cycles over wall ticks of its timing wave; the
     // device's maximum if unreadable); the median of the three is reported.
+    static const int slot[kProbeModes] = {0, 1, 2, 5, 6, 7, 8};
     hipError_t e = hipSuccess;
     double clock0 = 0.0;
-    for (int mode = 0; mode < 3 && e == hipSuccess; ++mode) {
+    for (int mode = 0; mode < kProbeModes && e == hipSuccess; ++mode) {
+        const double instr = (double)blocks * 4.0 / simds * kProbeIters * probe_units_per_iter(mode);
         for (int w = 0; w < 4 && e == hipSuccess; ++w) e = launch_probe(mode, o, clk, blocks, kProbeIters, s);
         double cyc[3] = {0, 0, 0}, fr[3] = {0, 0, 0};
         for (int r = 0; r < 3 && e == hipSuccess; ++r) {
@@ -1497,19 +1502,17 @@ int nbody_probe_issue_rates(double *out, void *ws, size_t ws_bytes, void *stream
             if (e == hipSuccess) e = hipEventSynchronize(b);
             float t = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
-            long long h[6] = {0, 0, 0, 0, 0, 0};
+            long long h[2] = {0, 0};
             if (e == hipSuccess) e = hipMemcpyAsync(h, clk, sizeof h, hipMemcpyDeviceToHost, s);
             if (e == hipSuccess) e = hipStreamSynchronize(s);
-            double f = (rtc_khz > 0 && h[2 * mode + 1] > 0)
-                           ? (double)h[2 * mode] / ((double)h[2 * mode + 1] / (rtc_khz * 1e3))
-                           : 0.0;
+            double f = (rtc_khz > 0 && h[1] > 0) ? (double)h[0] / ((double)h[1] / (rtc_khz * 1e3)) : 0.0;
             if (!(f > 1e8 && f < 1e10)) f = max_khz * 1e3;
             cyc[r] = t * 1e-3 * f / instr;
             fr[r] = f;
         }
         std::sort(cyc, cyc + 3);
         std::sort(fr, fr + 3);
-        out[mode] = cyc[1];
+        out[slot[mode]] = cyc[1];
         if (mode == 0) clock0 = fr[1];
     }
     (void)hipEventDestroy(a);

@@ -350,6 +350,7 @@ static bool dispatch_law(const FwdLaunch &f, dim3 grid, hipStream_t s)
 
 hipError_t launch_forces(const FwdLaunch &f, hipStream_t s)
 {
+    if (f.block < 64 || f.block > 256 || f.block % 64 != 0) return hipErrorInvalidValue;   // launch bounds
     if (f.nrows <= 0) return hipSuccess;
     const int64_t waves = (f.nrows + (int64_t)kWave * f.ipl - 1) / ((int64_t)kWave * f.ipl);
     const int64_t wpb = f.block / kWave;

@@ -4,9 +4,12 @@
 
 namespace nbk {
 
-// mode 0: FP32 FMA with VGPR operands; 1: with one SGPR operand; 2: v_rsq_f32.
-// out: [blocks * 256] floats (keeps the chains live); clk: [6], the shader
-// cycles and wall-counter ticks of each mode's timing wave.
+// Probe modes 0..6 (see probe.hip).  out: [blocks * 256] floats (keeps the
+// chains live); clk: [2], the shader cycles and wall-counter ticks of the
+// timing wave of the last launch.
+constexpr int kProbeModes = 7;
 hipError_t launch_probe(int mode, float *out, long long *clk, int blocks, int iters, hipStream_t s);
+// measured instructions (mode 3: groups of one rsq and 13 FMAs) per loop iteration and lane
+int probe_units_per_iter(int mode);
 
 }  // namespace nbk

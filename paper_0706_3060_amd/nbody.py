@@ -471,16 +471,21 @@ def hermite_block(pos, vel, acc, jerk, t_i, dt_i, mass, law: Law, eta: float, dt
 
 
 def probe_issue_rates(device=None):
-    """Shader cycles a SIMD spends per wave64 instruction on this GPU (FP32 FMA with
-    VGPR operands, with one SGPR operand, v_rsq_f32) and the shader clock while the
-    FMA probe runs: a dict with keys fma_cycles, fma_sgpr_cycles, rsq_cycles,
-    clock_ghz, wall_counter_mhz.  Synchronises the device's current stream."""
+    """Shader cycles a SIMD spends per wave64 instruction on this GPU, at eight waves per SIMD:
+    a dict with fma_cycles (FP32 FMA, VGPR operands), fma_sgpr_cycles (one SGPR operand),
+    rsq_cycles (v_rsq_f32), clock_ghz and wall_counter_mhz (the shader clock during the FMA
+    probe and the fixed counter's rate), rsq_13fma_cycles (one rsq interleaved with 13
+    independent FMAs, per group of 14), fma_distinct_cycles (multiplier and addend in distinct
+    VGPRs rotating over the chains), dpp_mov_cycles (a DPP row rotation on the VALU) and
+    bpermute_cycles (ds_bpermute through the LDS crossbar).  Synchronises the device's current
+    stream."""
     dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
     nbytes = int(N.lib().nbody_probe_workspace_bytes())
     ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
-    out = (ctypes.c_double * 5)()
-    N.check(N.lib().nbody_probe_issue_rates(out, _ptr(ws), nbytes, _stream(dev)))
-    keys = ("fma_cycles", "fma_sgpr_cycles", "rsq_cycles", "clock_ghz", "wall_counter_mhz")
+    out = (ctypes.c_double * 9)()
+    N.check(N.lib().nbody_probe_issue_rates(out, 9, _ptr(ws), nbytes, _stream(dev)))
+    keys = ("fma_cycles", "fma_sgpr_cycles", "rsq_cycles", "clock_ghz", "wall_counter_mhz",
+            "rsq_13fma_cycles", "fma_distinct_cycles", "dpp_mov_cycles", "bpermute_cycles")
     return dict(zip(keys, [float(v) for v in out]))
 
 

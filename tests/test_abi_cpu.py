@@ -173,6 +173,26 @@ def test_config_validation(N):
                 N.NBodyConfig(1024, 2, 2048, 1, 2)]:
         assert lib.nbody_set_config(0, ctypes.byref(bad)) == N.NBODY_EINVAL
     assert lib.nbody_set_config(7, ctypes.byref(good)) == N.NBODY_EINVAL
+    # a forced symmetric configuration (512-thread workgroups) stays one where the symmetric
+    # tiles apply, and elsewhere reads as a one-sided shape with a workgroup of at most 256
+    # threads, which the other kernels are built for
+    sym = N.NBodyConfig(512, 2, 2048, 1, 2)
+    grav = lambda prec: N.NBodyLaw(0, prec, 1.0, 0.01, 0.0, 1.0)
+    ljc = N.NBodyLaw(1, 1, 1.0, 0.0, 332.0637, 4.0)
+    cases = [(0, grav(1), True), (3, grav(2), True), (0, grav(0), False), (0, grav(3), False),
+             (0, ljc, False), (1, ljc, False), (1, grav(1), False), (2, grav(1), False),
+             (4, grav(1), False), (5, grav(2), False), (6, ljc, False)]
+    for api, law, symmetric in cases:
+        c = N.NBodyConfig()
+        try:
+            assert lib.nbody_set_config(api, ctypes.byref(sym)) == 0
+            assert lib.nbody_get_config(api, 1 << 20, 1, ctypes.byref(law), ctypes.byref(c)) == 0
+        finally:
+            lib.nbody_set_config(api, None)
+        if symmetric:
+            assert (c.block, c.i_per_lane, c.j_tile, c.j_stage) == (512, 2, 2048, 2), (api, law.kind)
+        else:
+            assert 64 <= c.block <= 256 and c.j_stage in (0, 1), (api, law.kind, law.precision, c.block)
 
 
 def test_flop_convention_and_version(N):
@@ -185,9 +205,10 @@ def test_flop_convention_and_version(N):
     assert b"gfx950" in lib.nbody_version()
     # issue-rate probe: argument checks only (it launches kernels)
     assert lib.nbody_probe_workspace_bytes() > 0
-    out = (ctypes.c_double * 5)()
-    assert lib.nbody_probe_issue_rates(None, None, 0, None) == N.NBODY_EINVAL
-    assert lib.nbody_probe_issue_rates(out, ctypes.c_void_p(4096), 16, None) == N.NBODY_EWORKSPACE
+    out = (ctypes.c_double * 9)()
+    assert lib.nbody_probe_issue_rates(None, 9, None, 0, None) == N.NBODY_EINVAL
+    assert lib.nbody_probe_issue_rates(out, 5, None, 0, None) == N.NBODY_EINVAL      # too few outputs
+    assert lib.nbody_probe_issue_rates(out, 9, ctypes.c_void_p(4096), 16, None) == N.NBODY_EWORKSPACE
 
 
 def test_python_binding_rejects_cpu_tensors(N):

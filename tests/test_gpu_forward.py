@@ -203,6 +203,11 @@ def test_issue_rate_probe(nb):
     assert r["fma_sgpr_cycles"] >= 0.9 * r["fma_cycles"], r
     assert 2.0 * r["fma_cycles"] <= r["rsq_cycles"] <= 40.0, r
     assert 0.5 <= r["clock_ghz"] <= 3.0 and r["wall_counter_mhz"] > 0, r
+    # a group of one rsq and 13 FMAs costs at least the 13 FMAs; distinct operands change
+    # the FMA rate by little; the cross-lane moves cost at least a VALU slot
+    assert r["rsq_13fma_cycles"] >= 12.0 * r["fma_cycles"], r
+    assert 0.7 * r["fma_cycles"] <= r["fma_distinct_cycles"] <= 1.5 * r["fma_cycles"], r
+    assert r["dpp_mov_cycles"] >= 0.9 * r["fma_cycles"] and r["bpermute_cycles"] > 0, r
 
 
 def test_tuning_cache_round_trip(nb, tmp_path):
