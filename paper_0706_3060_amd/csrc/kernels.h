@@ -91,6 +91,50 @@ struct SymLaunch {
     float4 *partial;               // [nblk][npad] (x, y, z, potential) FP32 slot partials
     Epilogue epi;
 };
+// Tile order of the symmetric launch.  The upper triangle (b1 <= b2) of the nblk x nblk block
+// grid is walked in strips of kSymStrip block rows, column by column inside a strip, so that
+// consecutive tiles share their blocks; the walk is cut into kSymXcds equal portions, one per
+// XCD (workgroups reach the XCDs in turn by linear id), so that each XCD's L2 sees a compact
+// region of the grid at a time.  Workgroup `wg` of sym_grid(nblk) workgroups gets tile
+// (b1, b2); sym_tile_of returns false for the few workgroups past the last tile.
+constexpr int kSymStrip = 8;
+constexpr int kSymXcds = 8;
+__host__ __device__ inline int64_t sym_tiles(int64_t nblk) { return nblk * (nblk + 1) / 2; }
+__host__ __device__ inline int64_t sym_grid(int64_t nblk)
+{
+    return (sym_tiles(nblk) + kSymXcds - 1) / kSymXcds * kSymXcds;
+}
+// first tile of strip s (every strip before it is a full one)
+__host__ __device__ inline int64_t sym_strip_start(int64_t s, int64_t nblk)
+{
+    const int64_t h = kSymStrip;
+    return s * (h * (h + 1) / 2) + h * (s * nblk - h * s * (s + 1) / 2);
+}
+__host__ __device__ inline bool sym_tile_of(int64_t wg, int64_t nblk, int64_t &b1, int64_t &b2)
+{
+    const int64_t tiles = sym_tiles(nblk), per = sym_grid(nblk) / kSymXcds;
+    const int64_t t = (wg % kSymXcds) * per + wg / kSymXcds;
+    if (t >= tiles) return false;
+    int64_t lo = 0, hi = (nblk + kSymStrip - 1) / kSymStrip - 1;      // strip: last start <= t
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) / 2;
+        if (sym_strip_start(mid, nblk) <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t r0 = lo * kSymStrip, h = nblk - r0 < kSymStrip ? nblk - r0 : kSymStrip;
+    const int64_t u = t - sym_strip_start(lo, nblk), tri = h * (h + 1) / 2;
+    if (u < tri) {
+        // columns r0 .. r0 + h - 1 hold 1 .. h tiles
+        int64_t k = 0;
+        while ((k + 1) * (k + 2) / 2 <= u) ++k;
+        b2 = r0 + k;
+        b1 = r0 + (u - k * (k + 1) / 2);
+    } else {
+        b2 = r0 + h + (u - tri) / h;
+        b1 = r0 + (u - tri) % h;
+    }
+    return true;
+}
 hipError_t launch_sym(const SymLaunch &a, hipStream_t s);
 hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s);
 int sym_blocks_per_cu(int prec, int pot);

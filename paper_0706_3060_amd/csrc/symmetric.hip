@@ -3,9 +3,10 @@
 // reciprocal square root serves two interactions.
 //
 // Decomposition.  The padded records form nblk blocks of blk chunks of 64
-// (blk = 16 or 32).  Workgroup t takes tile (b1, b2), b1 <= b2, of the upper
-// triangle of the block grid: the pairs between the rows of block b1 and the
-// rows of block b2 (on the diagonal, b1 == b2, each unordered pair once).  Its
+// (blk = 16 or 32).  Each workgroup takes one tile (b1, b2), b1 <= b2, of the
+// upper triangle of the block grid (in the XCD-aware strip order of
+// sym_tile_of): the pairs between the rows of block b1 and the rows of block
+// b2 (on the diagonal, b1 == b2, each unordered pair once).  Its
 // 8 waves hold two i chunks each (128 rows per wave, 16 chunks per pass; two
 // passes for blk = 32) and sweep the j chunks of b2 in rounds: in round r wave
 // w takes j chunk (w + r) mod blk, so no two waves touch one j chunk in the
@@ -42,19 +43,6 @@ constexpr int kSymPassChunks = 2 * kSymWaves;     // i chunks of one pass (two p
 __device__ __forceinline__ float from_next_lane(int byte_addr, float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, v)));
-}
-
-// tile t of the row-major upper triangle (b1 <= b2) of an n x n block grid
-__device__ __forceinline__ void sym_tile(int64_t t, int64_t n, int64_t &b1, int64_t &b2)
-{
-    // start(b) = b n - b (b - 1) / 2 is the first tile of row b
-    const double h = (double)n + 0.5;
-    int64_t b = (int64_t)(h - __builtin_sqrt(h * h - 2.0 * (double)t));
-    b = b < 0 ? 0 : (b > n - 1 ? n - 1 : b);
-    while (b > 0 && b * n - b * (b - 1) / 2 > t) --b;
-    while (b + 1 < n && (b + 1) * n - (b + 1) * b / 2 <= t) ++b;
-    b1 = b;
-    b2 = b + (t - (b * n - b * (b - 1) / 2));
 }
 
 // One mini-tile: the wave's two i chunks (records iv[0], iv[1], running
@@ -105,7 +93,7 @@ __device__ __forceinline__ void sym_minitile(const GravRec<float> *st, const Gra
 }
 
 template <int PREC, bool POT>
-__global__ __launch_bounds__(kSymThreads) void k_sym(SymLaunch a)
+__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_sym(SymLaunch a)
 {
     using R = GravRec<float>;
     const R *__restrict__ rec = (const R *)a.rec;
@@ -113,7 +101,7 @@ __global__ __launch_bounds__(kSymThreads) void k_sym(SymLaunch a)
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int blk = a.blk;
     int64_t b1, b2;
-    sym_tile(blockIdx.x, a.nblk, b1, b2);
+    if (!sym_tile_of(blockIdx.x, a.nblk, b1, b2)) return;       // whole workgroup, before any barrier
     const bool diag = b1 == b2;
     const float eps2 = (float)a.eps2;
     const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
@@ -133,12 +121,16 @@ __global__ __launch_bounds__(kSymThreads) void k_sym(SymLaunch a)
         iv[1] = rec[irec0 + (int64_t)(aloc + 1) * kWave + lane];
         RunSum<PREC> acc[2][4];
         float p[2][4];
-        R g = rec[jrec0 + (int64_t)(w % blk) * kWave + lane];
+        // the next round's j record of this lane, loaded a round ahead (as a vector, so that it
+        // stays in registers)
+        const float4 *__restrict__ rec4 = (const float4 *)a.rec;
+        float4 *st4 = (float4 *)st;
+        float4 g = rec4[jrec0 + (int64_t)(w % blk) * kWave + lane];
         for (int r = 0; r < blk; ++r) {
             const int q = (w + r) % blk;
-            st[lane] = g;
-            st[lane + kWave] = g;
-            g = rec[jrec0 + (int64_t)((w + r + 1) % blk) * kWave + lane];   // next round's chunk
+            st4[lane] = g;
+            st4[lane + kWave] = g;
+            g = rec4[jrec0 + (int64_t)((w + r + 1) % blk) * kWave + lane];
             const float4 j4 = jacc[q][lane];
             float jv[4] = {j4.x, j4.y, j4.z, j4.w};
             __builtin_amdgcn_wave_barrier();
@@ -227,7 +219,7 @@ hipError_t launch_sym(const SymLaunch &a, hipStream_t s)
     if (a.nblk <= 0) return hipSuccess;
     if (a.blk % kSymPassChunks != 0 || a.blk > kSymMaxBlk || a.npad != (int64_t)a.nblk * a.blk * kWave)
         return hipErrorInvalidValue;
-    const dim3 grid((unsigned)(a.nblk * (a.nblk + 1) / 2)), block(kSymThreads);
+    const dim3 grid((unsigned)sym_grid(a.nblk)), block(kSymThreads);
     if (a.prec == P_KAHAN) {
         if (a.pot) hipLaunchKernelGGL((k_sym<P_KAHAN, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_sym<P_KAHAN, false>), grid, block, 0, s, a);
