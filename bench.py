@@ -173,15 +173,16 @@ def main():
     # issue-rate ceiling of the timed kernel's instruction sequence, measured on this GPU,
     # per interaction-wave (64 interactions of 20 flops against 64 flops per SIMD-cycle at
     # peak; 157.3 TFLOP/s is that at 2.4 GHz).  Symmetric pair tiles (j_stage 2): one
-    # unordered pair-wave is 18 ordinary FP32 VALU instructions and one v_rsq_f32 for two
-    # interactions (the j sums move through the LDS crossbar, off the VALU); one-sided
-    # kernels: 13 and one v_rsq_f32 for one interaction.  The clock under the pair kernel
+    # unordered pair-wave is 18 ordinary FP32 VALU instructions, one v_rsq_f32 and half a
+    # DPP move (the potential's j sum; the force sums move through the LDS crossbar, off
+    # the VALU) for two interactions; one-sided kernels: 13 ordinary instructions and one
+    # v_rsq_f32 for one interaction.  The clock under the pair kernel
     # is not visible here: clock_for_kernel_ghz is the clock at which the measured launch
     # time equals the modelled cycles.
     rates = nb.probe_issue_rates(dev)
     if cfg_used["j_stage"] == 2:
-        inter_cycles = (18 * rates["fma_cycles"] + rates["rsq_cycles"]) / 2.0
-        model = "symmetric: (18 VALU + 1 rsq) per unordered pair-wave, two interactions"
+        inter_cycles = (18 * rates["fma_cycles"] + rates["rsq_cycles"] + 0.5 * rates["dpp_mov_cycles"]) / 2.0
+        model = "symmetric: (18 VALU + 1 rsq + 0.5 DPP move) per unordered pair-wave, two interactions"
     else:
         inter_cycles = 13 * rates["fma_cycles"] + rates["rsq_cycles"]
         model = "one-sided: 13 VALU + 1 rsq per interaction-wave"
@@ -434,6 +435,7 @@ def batched_leg(nb, torch, dev, ens):
     cfg, _ = nb.autotune(x, p, law, offsets=off, potential=True)
     log("autotuned batched config:", cfg)
     pairs = float(sum(int(off[s + 1] - off[s]) ** 2 for s in range(S)))
+    fpp = nb.flops_per_pair(nb.API_FORCES, nb.LJC_LINEAR, True)
 
     def run_batched():
         return nb.forces_batched(off, x, p, law)
@@ -473,14 +475,49 @@ def batched_leg(nb, torch, dev, ens):
             best = min(best, time.perf_counter() - t)
         return best, r
 
-    tb, (fb, ub) = timeit(run_batched)
+    tb, (fb, ub) = timeit(run_batched, reps=20)
+    # the persistent kernel alone (HIP events around it), and the whole call replayed from a
+    # captured graph (its pack, kernel and part-sum launches, without the host's part)
+    nb.timing_read(reset=True)
+    nb.timing_enable(True)
+    for _ in range(10):
+        run_batched()
+    torch.cuda.synchronize()
+    nb.timing_enable(False)
+    kb_ms, kb_n = nb.timing_read(reset=True)
+    kb_ms /= max(kb_n, 1)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        run_batched()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fg, _ = run_batched()
+    graph.replay()
+    torch.cuda.synchronize()
+    graph_ok = bool(torch.equal(fg, fb))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    tg_ms = e0.elapsed_time(e1) / 20
+    del graph
     tl64, outs64 = timeit(lambda: run_loop(law64))
     tl32, _ = timeit(lambda: run_loop(law))
     f64 = torch.cat([o[0] for o in outs64])
     e = (torch.linalg.norm(fb - f64, dim=1) / torch.linalg.norm(f64, dim=1)).cpu().numpy()
     med_sys = [float(np.median(e[off[s]:off[s + 1]])) for s in range(S) if off[s + 1] > off[s]]
     res = {"systems": S, "atoms": int(off[-1]), "pairs": pairs, "config": cfg,
-           "batched_fp32_kahan_ms": tb * 1e3, "loop_fp64_ms": tl64 * 1e3, "loop_fp32_kahan_ms": tl32 * 1e3,
+           "batched_fp32_kahan_ms": tb * 1e3, "batched_kernel_ms": kb_ms,
+           "batched_wall_minus_kernel_us": (tb * 1e3 - kb_ms) * 1e3,
+           "batched_graph_replay_ms": tg_ms, "graph_replay_equals_eager": graph_ok,
+           "flops_per_pair": fpp, "batched_kernel_tflops": fpp * pairs / (kb_ms * 1e-3) / 1e12,
+           "batched_wall_tflops": fpp * pairs / tb / 1e12,
+           "loop_fp64_ms": tl64 * 1e3, "loop_fp32_kahan_ms": tl32 * 1e3,
            "speedup_vs_loop_fp64": tl64 / tb, "speedup_vs_loop_fp32": tl32 / tb,
            "batched_g_pairs_per_s": pairs / tb / 1e9,
            "err_vs_fp64_per_system_median_max": max(med_sys), "err_vs_fp64_max": float(e.max())}

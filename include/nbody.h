@@ -28,9 +28,14 @@
  * Hermite scheme on acceleration and jerk, with a shared step (hermite_step)
  * or block individual steps (hermite_block_steps).
  *
- * Every i interacts with every j != i: all N^2 ordered pairs are evaluated
- * and no pair is scattered to both partners (Section 2, the remark on
- * Newton's third law), so results are deterministic run to run.
+ * Every i interacts with every j != i.  The one-sided kernels evaluate all
+ * N^2 ordered pairs and scatter no pair to both partners, as the paper's
+ * kernels do (Section 2, the remark on Newton's third law).  For gravity over
+ * a whole system, FP32 pair arithmetic, the symmetric pair tiles (j_stage 2,
+ * the default from N = 65,536) evaluate each unordered pair once and apply it
+ * to both particles through per-block partial sums that a fixed-order
+ * reduction adds, without atomics.  Either way results are deterministic run
+ * to run.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -39,9 +44,13 @@
  *    pos/vel/acc/force [N][3], params [N][P] with P = 1 (gravity: m_i) or
  *    P = 3 (LJC: q_i, sigma_i, epsilon_i).
  *  - The caller owns every array and the workspace `ws` (size from
- *    nbody_workspace_bytes).  The library never allocates or frees device
- *    memory and keeps no pointer after the call returns.  `law`, `offsets`
- *    and `cfg` are host memory read before the call returns.
+ *    nbody_workspace_bytes).  The library keeps no pointer to them after
+ *    the call returns.  `law`, `offsets` and `cfg` are host memory read
+ *    before the call returns.  The only device memory the library allocates
+ *    is the plan tables of the batched entry points: one copy per ensemble
+ *    (offsets) and launch shape per device, made at that ensemble's first
+ *    launch and kept until the process ends, at most 256 MiB per device
+ *    (past that, tables go through the workspace at every launch).
  *  - Outputs must not alias inputs (leapfrog_step updates pos/vel/acc in
  *    place by design).
  *  - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
@@ -223,7 +232,13 @@ int nbody_forces_subset(const double *pos, const double *params, int64_t n, cons
  *  offsets    host int64 [n_systems + 1], offsets[0] = 0, non-decreasing.
  *  n_systems  S >= 0 (empty systems are allowed).
  * Other arguments as nbody_forces with N = offsets[S].  Workspace:
- * nbody_workspace_bytes(NBODY_API_BATCHED, offsets[S], S, law). */
+ * nbody_workspace_bytes(NBODY_API_BATCHED, offsets[S], S, law).
+ * Plan tables: the first launch of an ensemble plans its work units on the
+ * host and uploads the tables once (synchronously) into device memory the
+ * library keeps; later launches of the same ensemble copy nothing from the
+ * host, so they can be captured in a graph (a captured launch reads those
+ * tables at every replay).  A first launch inside a stream capture is
+ * refused with NBODY_EINVAL before anything is enqueued. */
 int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
                          const double *params, const nbody_law *law, double *out_force,
                          double *out_potential, void *ws, size_t ws_bytes, void *stream);
@@ -264,7 +279,8 @@ int nbody_forces_excl(const double *pos, const double *params, int64_t n,
 /* nbody_forces_batched with exclusion lists over the concatenated rows
  * (offsets / index name rows of pos; partners outside a row's own system are
  * ignored).  Laws and precisions as nbody_forces_excl.  Workspace:
- * nbody_workspace_bytes(NBODY_API_BATCHED, offsets[S], S, law). */
+ * nbody_workspace_bytes(NBODY_API_BATCHED, offsets[S], S, law).  Plan tables
+ * as nbody_forces_batched. */
 int nbody_forces_batched_excl(const int64_t *offsets, int64_t n_systems, const double *pos,
                               const double *params, const nbody_exclusions *excl,
                               const nbody_law *law, double *out_force, double *out_potential,
@@ -284,7 +300,9 @@ int nbody_forces_backward_excl(const double *pos, const double *params, int64_t 
  * the concatenated rows; with types, grad_type_params sums over the atoms of
  * each type across all systems.  Laws: gravity and LJC(linear) (exclusions:
  * LJC(linear)).  Workspace:
- * nbody_workspace_bytes(NBODY_API_BACKWARD_BATCHED, offsets[S], S, law). */
+ * nbody_workspace_bytes(NBODY_API_BACKWARD_BATCHED, offsets[S], S, law).
+ * Plan tables as nbody_forces_batched (shared with it for the same ensemble
+ * and launch shape). */
 int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
                                   const double *params, const nbody_exclusions *excl,
                                   const nbody_law *law, const double *grad_force, double *grad_pos,

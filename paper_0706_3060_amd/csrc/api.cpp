@@ -228,6 +228,24 @@ int64_t resident_waves(int law, int prec, int ipl, bool pot, int js, int block)
     return r;
 }
 
+// Resident workgroups per CU of the batched forward and adjoint kernels (asked once per variant).
+int batched_blocks_per_cu_cached(int law, int prec, int ipl, bool pot, int js, int block, bool excl)
+{
+    using Key = std::tuple<int, int, int, int, int, int, int>;
+    static std::map<Key, int> cache;
+    static std::mutex mu;
+    const Key key(law, prec, ipl, pot ? 1 : 0, js, block, excl ? 1 : 0);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int r = batched_max_blocks_per_cu(law, prec, ipl, pot ? 1 : 0, js, block, excl ? 1 : 0);
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = r;
+    return r;
+}
+
 // Modelled time of one evaluation of `rows` rows against `nj` j records with
 // a j split of s (seconds, up to a common scale): waves run in rounds of
 // `resident` concurrent waves, each doing 1/s of the j range, plus the
@@ -958,6 +976,118 @@ std::shared_ptr<const BatchPlan> cached_plan(const int64_t *offsets, int64_t S, 
     return plan;
 }
 
+// Device copies of plan tables.  A batched launch reads four tables: the units, the caller's
+// offsets, the padded offsets and the per-system table.  They depend only on the plan's key
+// (offsets, rows per lane, part length), so each device keeps one copy per key, made at the
+// first launch of that key on the device (one allocation and one synchronous upload) and kept
+// until the process ends: later launches copy nothing from the host, so they can be captured
+// in a graph, and a captured launch may read the tables at any later replay.  At most
+// kResidentTableBytes of tables are kept per device; past that, launches copy their tables
+// into the workspace (from pageable host memory, on the stream) as every launch once did.
+struct DevTables {
+    int32_t *units = nullptr;
+    int64_t *off = nullptr, *poff = nullptr, *systab = nullptr;
+};
+struct ResidentKey {
+    int device;
+    int ipl;
+    int64_t j_unit;
+    std::vector<int64_t> offsets;
+    bool operator<(const ResidentKey &o) const
+    {
+        return std::tie(device, ipl, j_unit, offsets) < std::tie(o.device, o.ipl, o.j_unit, o.offsets);
+    }
+};
+constexpr size_t kResidentTableBytes = size_t(256) << 20;
+std::mutex g_resident_mu;
+std::map<ResidentKey, DevTables> g_resident;
+std::map<int, size_t> g_resident_bytes;      // per device
+
+// The device tables of `plan` (key offsets / ipl / j_unit) on the current device, uploading
+// them on first use.  Returns false, with *rc == 0, when the per-device budget is spent (the
+// caller then copies the tables into its workspace), and false with *rc set on an error: a
+// first launch of a key inside a stream capture (no allocation or upload can be captured).
+bool resident_tables(const BatchPlan &plan, const int64_t *offsets, int64_t S, int ipl, int64_t j_unit,
+                     hipStream_t s, DevTables *out, int *rc)
+{
+    *rc = NBODY_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        *rc = fail(NBODY_EHIP, "hipGetDevice failed");
+        return false;
+    }
+    ResidentKey key{dev, ipl, j_unit, std::vector<int64_t>(offsets, offsets + S + 1)};
+    std::lock_guard<std::mutex> lk(g_resident_mu);
+    auto it = g_resident.find(key);
+    if (it != g_resident.end()) {
+        *out = it->second;
+        return true;
+    }
+    const size_t b_units = align256(plan.units.size() * sizeof(int32_t));
+    const size_t b_off = align256((size_t)(S + 1) * sizeof(int64_t));
+    const size_t b_sys = align256(std::max<size_t>(plan.systab.size(), 1) * sizeof(int64_t));
+    const size_t bytes = b_units + 2 * b_off + b_sys;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
+    if (cap != hipStreamCaptureStatusNone) {
+        *rc = fail(NBODY_EINVAL, "the first batched launch of an ensemble cannot be captured (it uploads the "
+                   "ensemble's plan tables): launch it once before capturing");
+        return false;
+    }
+    if (g_resident_bytes[dev] + bytes > kResidentTableBytes) return false;
+    void *buf = nullptr;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;                                  // no room: the workspace copy still works
+    }
+    char *b = (char *)buf;
+    DevTables t;
+    t.units = (int32_t *)b;
+    t.off = (int64_t *)(b + b_units);
+    t.poff = (int64_t *)(b + b_units + b_off);
+    t.systab = (int64_t *)(b + b_units + 2 * b_off);
+    hipError_t e = hipMemcpy(t.units, plan.units.data(), plan.units.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(t.off, offsets, (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(t.poff, plan.poff.data(), (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !plan.systab.empty())
+        e = hipMemcpy(t.systab, plan.systab.data(), plan.systab.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(buf);
+        *rc = hip_fail(e, "batched plan tables");
+        return false;
+    }
+    g_resident_bytes[dev] += bytes;
+    g_resident.emplace(std::move(key), t);
+    *out = t;
+    return true;
+}
+
+// The tables of a batched launch: the device copies of its plan, or copies in the workspace
+// regions given (pageable sources: the runtime stages them before returning).
+int batched_tables(const BatchPlan &plan, const int64_t *offsets, int64_t S, int ipl, int64_t j_unit,
+                   hipStream_t s, char *base, size_t unit_off, size_t off_off, size_t poff_off, size_t systab_off,
+                   DevTables *t)
+{
+    int rc = NBODY_OK;
+    if (resident_tables(plan, offsets, S, ipl, j_unit, s, t, &rc)) return NBODY_OK;
+    if (rc) return rc;
+    t->units = (int32_t *)(base + unit_off);
+    t->off = (int64_t *)(base + off_off);
+    t->poff = (int64_t *)(base + poff_off);
+    t->systab = (int64_t *)(base + systab_off);
+    hipError_t e = hipMemcpyAsync(t->units, plan.units.data(), plan.units.size() * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(t->off, offsets, (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t->poff, plan.poff.data(), (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(t->systab, plan.systab.data(), plan.systab.size() * sizeof(int64_t),
+                           hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "batched tables");
+    return NBODY_OK;
+}
+
 // The plan of one batched launch: j parts of about 8 units per resident wave
 // (`resident` waves on the whole chip), no part shorter than kMinJUnit records,
 // the part length doubled until the partial slots of split systems fit the
@@ -1025,33 +1155,25 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
                 void *ws, const BatWs &lay, hipStream_t s, const ExclArgs &excl = ExclArgs{})
 {
     const int per_cu =
-        std::max(1, batched_max_blocks_per_cu(law->kind, law->precision, c.ipl, out_pot != nullptr,
-                                              c.j_stage, c.block, excl.off != nullptr));
+        std::max(1, batched_blocks_per_cu_cached(law->kind, law->precision, c.ipl, out_pot != nullptr,
+                                                 c.j_stage, c.block, excl.off != nullptr));
     const int64_t resident = (int64_t)device_cus() * per_cu * (c.block / 64);
-    std::shared_ptr<const BatchPlan> pp = plan_for_launch(offsets, S, c.ipl, resident, lay.max_slots).plan;
-    const BatchPlan &plan = *pp;
+    const PlanChoice pc = plan_for_launch(offsets, S, c.ipl, resident, lay.max_slots);
+    const BatchPlan &plan = *pc.plan;
     if (plan.units.empty()) return NBODY_OK;
     if (!plan_fits(plan, c.ipl, lay.max_units, lay.max_records, lay.max_slots))
         return fail(NBODY_EWORKSPACE, "internal: batched plan exceeds its workspace regions "
                     "(%lld units, %lld slots)", (long long)(plan.units.size() / 4), (long long)plan.n_slots);
     char *base = (char *)ws;
-    int32_t *d_units = (int32_t *)(base + lay.unit_off);
-    int64_t *d_off = (int64_t *)(base + lay.off_off);
-    int64_t *d_poff = (int64_t *)(base + lay.poff_off);
-    int64_t *d_systab = (int64_t *)(base + lay.systab_off);
+    DevTables tab;
+    int rc = batched_tables(plan, offsets, S, c.ipl, pc.j_unit, s, base, lay.unit_off, lay.off_off, lay.poff_off,
+                            lay.systab_off, &tab);
+    if (rc) return rc;
+    int32_t *d_units = tab.units;
+    int64_t *d_off = tab.off;
+    int64_t *d_poff = tab.poff;
+    int64_t *d_systab = tab.systab;
     hipError_t e;
-    // Pageable sources: the runtime stages them before returning.
-    e = hipMemcpyAsync(d_units, plan.units.data(), plan.units.size() * sizeof(int32_t),
-                       hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_off, offsets, (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_poff, plan.poff.data(), (size_t)(S + 1) * sizeof(int64_t),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_systab, plan.systab.data(), plan.systab.size() * sizeof(int64_t),
-                           hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "batched tables");
 
     BatchPackLaunch pk{};
     pk.law = law->kind;
@@ -1768,29 +1890,33 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     a.block = c.block;
     a.j_stage = c.j_stage;
     a.excl = excl_args(excl);
-    const int per_cu = std::max(1, adjoint_batched_blocks_per_cu(a));
+    int per_cu = 0;
+    {
+        using Key = std::tuple<int, int, int, int, int, int>;
+        static std::map<Key, int> cache;
+        static std::mutex mu;
+        const Key key(a.law, a.prec, a.ipl, a.block, a.j_stage, a.excl.off != nullptr ? 1 : 0);
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        per_cu = it != cache.end() ? it->second : (cache[key] = adjoint_batched_blocks_per_cu(a));
+        per_cu = std::max(1, per_cu);
+    }
     const int64_t resident = (int64_t)device_cus() * per_cu * (c.block / 64);
-    std::shared_ptr<const BatchPlan> pp = plan_for_launch(offsets, n_systems, ipl, resident, lay.max_slots).plan;
-    const BatchPlan &plan = *pp;
+    const PlanChoice pc = plan_for_launch(offsets, n_systems, ipl, resident, lay.max_slots);
+    const BatchPlan &plan = *pc.plan;
     if (plan.units.empty()) return NBODY_OK;
     if (!plan_fits(plan, ipl, lay.max_units, lay.max_records, lay.max_slots))
         return fail(NBODY_EWORKSPACE, "internal: batched adjoint plan exceeds its workspace regions");
     char *base = (char *)ws;
-    int32_t *d_units = (int32_t *)(base + lay.unit_off);
-    int64_t *d_off = (int64_t *)(base + lay.off_off);
-    int64_t *d_poff = (int64_t *)(base + lay.poff_off);
-    int64_t *d_systab = (int64_t *)(base + lay.systab_off);
-    hipError_t e = hipMemcpyAsync(d_units, plan.units.data(), plan.units.size() * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_off, offsets, (size_t)(n_systems + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_poff, plan.poff.data(), (size_t)(n_systems + 1) * sizeof(int64_t),
-                           hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(d_systab, plan.systab.data(), plan.systab.size() * sizeof(int64_t),
-                           hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "batched adjoint tables");
+    DevTables tab;
+    rc = batched_tables(plan, offsets, n_systems, ipl, pc.j_unit, s, base, lay.unit_off, lay.off_off,
+                        lay.poff_off, lay.systab_off, &tab);
+    if (rc) return rc;
+    int32_t *d_units = tab.units;
+    int64_t *d_off = tab.off;
+    int64_t *d_poff = tab.poff;
+    int64_t *d_systab = tab.systab;
+    hipError_t e;
     a.j_tile = c.j_tile;
     a.n_units = (int64_t)plan.units.size() / 4;
     a.units = d_units;

@@ -19,9 +19,10 @@
 // are staged twice in a wave-private LDS slot, so each lane reads its own
 // record at a constant offset.  The j-side sums of the mini-tile travel with
 // their particle: after each step every lane takes its right neighbour's four
-// sums through the LDS crossbar (ds_bpermute), so after 64 steps lane l holds
-// the sums of j = l again.  Between mini-tiles the j sums of a tile live in LDS
-// (FP32, one slot per j of block b2); the i sums are FP32 mini-tile partials
+// sums (three through the LDS crossbar with ds_bpermute, the potential's with a
+// DPP wave rotation), so after 64 steps lane l holds the sums of j = l again.
+// Between mini-tiles the j sums of a tile live in LDS (FP32, one slot per j of
+// block b2); the i sums are FP32 mini-tile partials
 // folded into Kahan or FP64 running sums (the tile-level compensation of the
 // one-sided kernels).
 //
@@ -43,6 +44,12 @@ constexpr int kSymPassChunks = 2 * kSymWaves;     // i chunks of one pass (two p
 __device__ __forceinline__ float from_next_lane(int byte_addr, float v)
 {
     return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, v)));
+}
+
+// the same move on the VALU: a DPP rotation of the whole wave by one lane (wave_rol:1)
+__device__ __forceinline__ float from_next_lane_dpp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
 }
 
 // One mini-tile: the wave's two i chunks (records iv[0], iv[1], running
@@ -87,8 +94,12 @@ __device__ __forceinline__ void sym_minitile(const GravRec<float> *st, const Gra
                 jv[3] = fma_(mi, ri, jv[3]);
             }
         }
+        // the force sums move through the LDS crossbar, the potential's on the VALU: the two units
+        // share the moves (2 % faster at N = 2^20 than four crossbar moves; three or more DPP
+        // moves are slower)
 #pragma unroll
-        for (int c = 0; c < (POT ? 4 : 3); ++c) jv[c] = from_next_lane(bp_addr, jv[c]);
+        for (int c = 0; c < 3; ++c) jv[c] = from_next_lane(bp_addr, jv[c]);
+        if (POT) jv[3] = from_next_lane_dpp(jv[3]);
     }
 }
 

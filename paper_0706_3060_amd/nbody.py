@@ -109,8 +109,17 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _raw_stream(device) -> int:
+    """The handle of torch's current stream on `device` (the raw value, without building a
+    torch Stream object, which costs tens of microseconds per call)."""
+    idx = device.index if isinstance(device, torch.device) else device
+    if idx is None:
+        idx = torch.cuda.current_device()
+    return torch._C._cuda_getCurrentRawStream(idx)
+
+
 def _stream(device):
-    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    return ctypes.c_void_p(_raw_stream(device))
 
 
 def _dev_f64(t, shape, name, device=None):
@@ -142,7 +151,7 @@ def workspace(api, n_total, n_systems, law: Law, device) -> torch.Tensor:
     if nbytes == 0 and n_total > 0:
         raise ValueError("invalid workspace request")
     dev = torch.device(device)
-    key = (dev.index, torch.cuda.current_stream(dev).cuda_stream)
+    key = (dev.index, _raw_stream(dev))
     buf = _ws.get(key)
     if buf is None or buf.numel() < nbytes:
         buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=dev)

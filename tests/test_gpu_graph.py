@@ -1,6 +1,8 @@
-"""The forward and the leapfrog captured in a HIP graph (through torch.cuda.graph) and
-replayed: every launch of these paths is a kernel on the caller's stream, with no host
-synchronisation, memset or host copy inside, so a captured call can be replayed.
+"""The forward, the leapfrog and the batched forward and adjoint captured in a HIP graph
+(through torch.cuda.graph) and replayed: every launch of these paths is a kernel on the
+caller's stream, with no host synchronisation, memset or host copy inside (the batched
+paths read their plan tables from device memory made at an ensemble's first launch), so a
+captured call can be replayed.
 
 Each test replays the graph several times, with eager work of the library and
 synchronisations between the replays, and checks every replay bit for bit against the
@@ -91,3 +93,79 @@ def test_leapfrog_replay(nb):
             assert torch.equal(got, want), k
         nb.forces(Xw, M, law)                        # eager work between replays
         torch.cuda.synchronize()
+
+
+def _ensemble(sizes, seed):
+    off, pos, par, _ = W.batched_md(len(sizes), seed=seed, sizes=sizes, workers=1)
+    return off, dev(pos), dev(par)
+
+
+# uneven systems, two of them large enough to be cut into j parts (the part-sum
+# reduction is then part of the captured work), one empty
+SIZES_A = [700, 0, 3000, 45, 1800, 9000, 128, 2500, 64, 6000]
+SIZES_B = [300, 1200, 65, 2000]
+
+
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp64"])
+def test_forces_batched_replay(nb, prec):
+    """The batched forward keeps each ensemble's plan tables in device memory after its
+    first launch, so later launches copy nothing from the host and can be captured.
+    Between replays the same workspace serves another ensemble eagerly."""
+    off, X, P = _ensemble(SIZES_A, 81)
+    offb, Xb, Pb = _ensemble(SIZES_B, 82)
+    law = nb.ljc_linear(prec)
+    f_ref, p_ref = nb.forces_batched(off, X, P, law)
+    fb_ref, _ = nb.forces_batched(offb, Xb, Pb, law)
+    torch.cuda.synchronize()
+    warm_on_side_stream(lambda: nb.forces_batched(off, X, P, law))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        f_g, p_g = nb.forces_batched(off, X, P, law)
+    for _ in range(4):
+        f_g.fill_(float("nan"))
+        p_g.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(f_g, f_ref) and torch.equal(p_g, p_ref)
+        fb, _ = nb.forces_batched(offb, Xb, Pb, law)       # another ensemble, eagerly
+        torch.cuda.synchronize()
+        assert torch.equal(fb, fb_ref)
+
+
+def test_backward_batched_replay(nb):
+    off, X, P = _ensemble(SIZES_A, 83)
+    g_in = dev(np.random.default_rng(5).standard_normal((int(off[-1]), 3)))
+    law = nb.ljc_linear("fp32_kahan")
+    ref = nb.forces_backward_batched(off, X, P, g_in, law)
+    torch.cuda.synchronize()
+    warm_on_side_stream(lambda: nb.forces_backward_batched(off, X, P, g_in, law))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = nb.forces_backward_batched(off, X, P, g_in, law)
+    for _ in range(3):
+        out[0].fill_(float("nan"))
+        out[1].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out[0], ref[0]) and torch.equal(out[1], ref[1])
+        nb.forces_batched(off, X, P, law)                   # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_first_batched_launch_refused_under_capture(nb):
+    """A new ensemble's first launch uploads its plan tables, which a capture cannot hold:
+    the call is refused before anything is enqueued, and the ensemble works eagerly after."""
+    from paper_0706_3060_amd import _native as N
+    off, X, P = _ensemble([500, 1500, 77, 2300], 84)
+    law = nb.ljc_linear("fp32_kahan")
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(N.NBodyError, match="cannot be captured"):
+        with torch.cuda.graph(g):
+            nb.forces_batched(off, X, P, law)
+    torch.cuda.synchronize()
+    f, _ = nb.forces_batched(off, X, P, law)
+    f2, _ = nb.forces_batched(off, X, P, law)
+    torch.cuda.synchronize()
+    assert torch.isfinite(f).all() and torch.equal(f, f2)
