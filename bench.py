@@ -398,27 +398,37 @@ def save_inputs(out_dir, n, pos, vel, mass, ens, md):
 
 
 def shard_leg(nb, torch, dev, x, m, law, full_kernel_ms, n_gpus=8):
-    """One GPU's share of the headline evaluation if the rows were sharded over n_gpus GPUs
-    with the one-sided kernel: a contiguous block of N / n_gpus output rows against all N j
-    records (nbody_forces_subset), for the first and the last block.  Its kernel time
-    against 1 / n_gpus of the full (symmetric) launch: below one by the symmetric kernel's
-    advantage plus whatever the share loses in filling the chip."""
+    """One GPU's share of the headline evaluation if it were spread over n_gpus GPUs.
+    Symmetric tiles (nbody_forces_share): share k of n_gpus equal ranges of the tile
+    triangle, per-row partial sums of all rows (which a reduce-scatter would add across the
+    GPUs), for the first and the last share.  One-sided rows (nbody_forces_subset): a
+    contiguous block of N / n_gpus rows against all N records, for the first and the last
+    block.  Each kernel time is set against 1 / n_gpus of the full symmetric launch."""
     n = x.shape[0]
     rows = n // n_gpus
-    res = {"n": n, "gpus": n_gpus, "rows": rows, "full_kernel_ms": full_kernel_ms}
-    for name, r0 in (("first", 0), ("last", n - rows)):
-        il = torch.arange(r0, r0 + rows, dtype=torch.int64, device=dev)
-        nb.forces_subset(x, m, il, law)
+    res = {"n": n, "gpus": n_gpus, "full_kernel_ms": full_kernel_ms}
+
+    def kernel_ms(fn):
+        fn()
         torch.cuda.synchronize()
         nb.timing_read(reset=True)
         nb.timing_enable(True)
         for _ in range(2):
-            nb.forces_subset(x, m, il, law)
+            fn()
         torch.cuda.synchronize()
         nb.timing_enable(False)
         k_ms, k_n = nb.timing_read(reset=True)
-        ms = k_ms / max(k_n, 1)
-        res[name] = {"kernel_ms": ms, "g_pairs_per_s": float(rows) * n / (ms * 1e-3) / 1e9,
+        return k_ms / max(k_n, 1)
+
+    pairs_share = float(n) * n / n_gpus
+    for name, sh in (("tiles_first", 0), ("tiles_last", n_gpus - 1)):
+        ms = kernel_ms(lambda: nb.forces_share(x, m, law, sh, n_gpus))
+        res[name] = {"share": sh, "kernel_ms": ms, "g_pairs_per_s": pairs_share / (ms * 1e-3) / 1e9,
+                     "efficiency_vs_full": full_kernel_ms / n_gpus / ms}
+    for name, r0 in (("rows_first", 0), ("rows_last", n - rows)):
+        il = torch.arange(r0, r0 + rows, dtype=torch.int64, device=dev)
+        ms = kernel_ms(lambda: nb.forces_subset(x, m, il, law))
+        res[name] = {"rows": rows, "kernel_ms": ms, "g_pairs_per_s": float(rows) * n / (ms * 1e-3) / 1e9,
                      "efficiency_vs_full": full_kernel_ms / n_gpus / ms}
     log("shard share:", res)
     return res

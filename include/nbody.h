@@ -32,10 +32,10 @@
  * N^2 ordered pairs and scatter no pair to both partners, as the paper's
  * kernels do (Section 2, the remark on Newton's third law).  For gravity over
  * a whole system, FP32 pair arithmetic, the symmetric pair tiles (j_stage 2,
- * the default from N = 65,536) evaluate each unordered pair once and apply it
- * to both particles through per-block partial sums that a fixed-order
- * reduction adds, without atomics.  Either way results are deterministic run
- * to run.
+ * the default from N = 65,536 to 2,097,152) evaluate each unordered pair once
+ * and apply it to both particles through per-block partial sums that a
+ * fixed-order reduction adds, without atomics.  Either way results are
+ * deterministic run to run.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -162,7 +162,11 @@ typedef struct nbody_exclusions {
  *             added afterwards in a fixed order (the i-replication of
  *             Section 3.4), 1..64; a launch uses at most one part per 64
  *             j records and at most 2^25 / rows parts (the partial buffer of
- *             the workspace).  Ignored by the batched entry point;
+ *             the workspace).  For the batched entry points, the number of
+ *             work units per resident wave the planner aims at, 1..64 (the
+ *             j ranges of large systems are cut into parts to reach it: more
+ *             parts balance the persistent launch, fewer leave fewer part
+ *             sums to add; 8 by the rule);
  *  j_stage    how j records reach the arithmetic: 0 = wave-uniform scalar
  *             loads into SGPRs, 1 = a wave-private LDS slot read back as
  *             broadcasts into VGPRs (so the pair arithmetic has only VGPR
@@ -170,7 +174,9 @@ typedef struct nbody_exclusions {
  *             evaluated once and its force applied to both particles
  *             (Newton's third law), for gravity with FP32_KAHAN or
  *             FP32_FP64ACC through nbody_forces and leapfrog_step on whole
- *             systems (elsewhere 2 reads as 1).  With j_stage 2, j_tile is
+ *             systems of up to 2,097,152 particles (its per-block partials
+ *             grow as n^2: 8.6 GB at n = 2^20, 34 GB at 2^21; elsewhere 2
+ *             reads as 1).  With j_stage 2, j_tile is
  *             the tile edge in records, 1024 (for n <= 262,144) or 2048,
  *             and block, i_per_lane and j_split are fixed (512, 2, 1). */
 typedef struct nbody_config {
@@ -224,6 +230,29 @@ int nbody_forces_noalloc(const double *pos, const double *params, int64_t n, con
 int nbody_forces_subset(const double *pos, const double *params, int64_t n, const int64_t *ilist,
                         int64_t ni, const nbody_law *law, double *out_force,
                         double *out_potential, void *ws, size_t ws_bytes, void *stream);
+
+/* One share of a gravity evaluation, for a caller that spreads one system
+ * over several GPUs (each GPU holds every particle and evaluates one share;
+ * summing the shares' outputs gives the forces).  The unordered pairs are
+ * cut as the symmetric pair tiles cut them (Section 2's all-pairs sum with
+ * each pair applied to both particles): the upper triangle of the grid of
+ * blocks of 1024 (n <= 262,144) or 2048 records, walked in a fixed order,
+ * is split into n_shares ranges of equal tile count, and share `share`
+ * evaluates the tiles of its range.  out_force [n][3] and out_potential [n]
+ * (optional) receive, for EVERY row, the FP64 sum of that row's contributions
+ * from the share's tiles, scaled as nbody_forces scales them (G, -G); rows
+ * the share does not touch get zero.  The sum over all shares equals
+ * nbody_forces' result up to the rounding of the final FP64 additions; with
+ * n_shares = 1 it is that result.
+ *  share, n_shares   0 <= share < n_shares.
+ * Law: gravity with NBODY_FP32_KAHAN or NBODY_FP32_FP64ACC, n <= 2,097,152
+ * (NBODY_ENOTSUP otherwise: other laws shard by rows, with
+ * nbody_forces_subset on a contiguous row list).  Workspace:
+ * nbody_workspace_bytes(NBODY_API_FORCES, n, 1, law).  Errors: as
+ * nbody_forces, and NBODY_EINVAL for a share outside [0, n_shares). */
+int nbody_forces_share(const double *pos, const double *params, int64_t n, const nbody_law *law,
+                       int32_t share, int32_t n_shares, double *out_force, double *out_potential,
+                       void *ws, size_t ws_bytes, void *stream);
 
 /* Forces of many independent systems of uneven size in ONE persistent launch
  * (small-system motivation of Section 3.4).  System s owns rows
@@ -405,9 +434,10 @@ int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, dou
 /* Workspace size in bytes needed by entry point `api` for `n_total`
  * particles in `n_systems` systems (1 for the single-system entry points).
  * For gravity with FP32_KAHAN or FP32_FP64ACC through the forces and leapfrog
- * entry points it covers the symmetric pair tiles (j_stage 2), whose FP32
- * partial buffer holds one partial per row and tile row: about n^2 / 8 bytes
- * (8.6 GB at n = 2^20).  Returns 0 when the arguments are invalid. */
+ * entry points, n <= 2,097,152, it covers the symmetric pair tiles (j_stage
+ * 2), whose FP32 partial buffer holds one partial per row and block of 2048
+ * records: about n^2 / 128 bytes (8.6 GB at n = 2^20).  Returns 0 when the
+ * arguments are invalid. */
 size_t nbody_workspace_bytes(int32_t api, int64_t n_total, int64_t n_systems,
                              const nbody_law *law);
 

@@ -35,6 +35,7 @@ EXPORTED = (
     "nbody_autotune_jerk", "nbody_forces_excl", "nbody_forces_batched_excl",
     "nbody_forces_backward_excl", "nbody_forces_backward_batched",
     "nbody_probe_workspace_bytes", "nbody_probe_issue_rates", "nbody_forces_noalloc",
+    "nbody_forces_share",
 )
 
 
@@ -80,6 +81,7 @@ def lib():
             "nbody_forces": ([P, P, I64, LAW, P, P, P, SZ, P], ctypes.c_int),
             "nbody_forces_noalloc": ([P, P, I64, LAW, P, P, P], ctypes.c_int),
             "nbody_forces_subset": ([P, P, I64, P, I64, LAW, P, P, P, SZ, P], ctypes.c_int),
+            "nbody_forces_share": ([P, P, I64, LAW, I32, I32, P, P, P, SZ, P], ctypes.c_int),
             "nbody_forces_batched": ([P, I64, P, P, LAW, P, P, P, SZ, P], ctypes.c_int),
             "nbody_forces_backward": ([P, P, I64, LAW, P, P, P, P, I32, P, P, SZ, P], ctypes.c_int),
             "leapfrog_step": ([P, P, P, P, P, I64, LAW, D, I32, P, P, SZ, P], ctypes.c_int),

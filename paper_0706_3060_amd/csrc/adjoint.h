@@ -35,11 +35,14 @@ struct AdjBatchLaunch {
     const int64_t *systab;       // [S][3] = (j parts P, records per part, first partial slot)
     double *partial;             // [slots][64 * ipl][8] part sums of systems with P > 1
     int any_parts;
+    const int32_t *red;          // [n_red][2] (system, row block) of the row blocks with P > 1
+    int64_t n_red;
     int64_t n_systems, npad_total, n_total;
     double eps2, G, qscale;
     const double *pos, *params, *g;   // caller arrays (pack)
     void *rec;
-    int *ticket;
+    int *ticket;                 // zeroed by the pack (ticket_zeroed) or by launch_adjoint_batched
+    int ticket_zeroed;
     double *grad_pos;            // [n][3] or null
     double *grad_params;         // [n][3] or null (LJC)
     ExclArgs excl;

@@ -400,6 +400,7 @@ template <typename R, int P>
 __global__ __launch_bounds__(256) void k_pack_adj_batched(AdjBatchLaunch a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.ticket_zeroed && i < 64) a.ticket[i] = 0;     // the work ticket of the launch that follows
     if (i >= a.npad_total) return;
     int64_t lo = 0, hi = a.n_systems;          // poff[lo] <= i < poff[hi]
     while (hi - lo > 1) {
@@ -561,48 +562,41 @@ static bool adjb_dispatch(const AdjBatchLaunch &a, hipStream_t s, const void **f
     return a.law == GRAVITY ? adjb_prec<GRAVITY>(a, s, fn) : (a.law == LJC ? adjb_prec<LJC>(a, s, fn) : false);
 }
 
-// Rows of systems cut into several j parts: the part sums in part order
-// (NC = 3 sums for gravity, 6 for LJC).
+// Row block red[blockIdx.x] of a system cut into several j parts: each thread adds its
+// row's part sums in part order (NC = 3 sums for gravity, 6 for LJC).
 template <int NC>
-__global__ __launch_bounds__(256) void k_adjoint_batched_reduce(AdjBatchLaunch a)
+__global__ __launch_bounds__(128) void k_adjoint_batched_reduce(AdjBatchLaunch a)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.n_total) return;
-    int64_t lo = 0, hi = a.n_systems;          // off[lo] <= r < off[hi]
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (a.off[mid] <= r) lo = mid;
-        else hi = mid;
-    }
-    const int64_t nparts = a.systab[3 * lo];
-    if (nparts <= 1) return;
+    const int64_t s = a.red[2 * blockIdx.x], rb = a.red[2 * blockIdx.x + 1];
     const int64_t rows = (int64_t)kWave * a.ipl;
-    const int64_t l = r - a.off[lo];
-    const int64_t rb = l / rows, rr = l - rb * rows;
-    const int64_t slot0 = a.systab[3 * lo + 2] + rb * nparts;
+    const int64_t l = rb * rows + threadIdx.x;
+    if (l >= a.off[s + 1] - a.off[s]) return;
+    const int64_t nparts = a.systab[3 * s];
+    const int64_t slot0 = a.systab[3 * s + 2] + rb * nparts;
     NSum v[NC];
     for (int64_t p = 0; p < nparts; ++p) {
-        const double *q = a.partial + ((slot0 + p) * rows + rr) * 8;
+        const double *q = a.partial + ((slot0 + p) * rows + threadIdx.x) * 8;
 #pragma unroll
         for (int c = 0; c < NC; ++c) v[c].add(q[c]);
     }
     double out[8];
 #pragma unroll
     for (int c = 0; c < NC; ++c) out[c] = v[c].value();
-    adj_finish_b(a, NC == 3 ? (int)GRAVITY : a.law, r, out);
+    adj_finish_b(a, NC == 3 ? (int)GRAVITY : a.law, a.off[s] + l, out);
 }
 
 hipError_t launch_adjoint_batched(const AdjBatchLaunch &a, hipStream_t s)
 {
     if (a.n_units <= 0) return hipSuccess;
-    hipError_t e = launch_fill_zero(a.ticket, 256, s);
+    if (a.ipl < 1 || a.ipl > 2) return hipErrorInvalidValue;     // the reduction's 128-thread bound
+    hipError_t e = a.ticket_zeroed ? hipSuccess : launch_fill_zero(a.ticket, 256, s);
     if (e != hipSuccess) return e;
     if (!adjb_dispatch(a, s, nullptr)) return hipErrorInvalidValue;
     e = hipGetLastError();
-    if (e != hipSuccess || !a.any_parts) return e;
-    const dim3 grid((unsigned)((a.n_total + 255) / 256));
-    if (a.law == GRAVITY) hipLaunchKernelGGL(k_adjoint_batched_reduce<3>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_adjoint_batched_reduce<6>, grid, dim3(256), 0, s, a);
+    if (e != hipSuccess || !a.any_parts || a.n_red <= 0) return e;
+    const dim3 grid((unsigned)a.n_red), block((unsigned)(kWave * a.ipl));
+    if (a.law == GRAVITY) hipLaunchKernelGGL(k_adjoint_batched_reduce<3>, grid, block, 0, s, a);
+    else hipLaunchKernelGGL(k_adjoint_batched_reduce<6>, grid, block, 0, s, a);
     return hipGetLastError();
 }
 

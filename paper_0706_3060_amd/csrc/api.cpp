@@ -94,10 +94,14 @@ int max_split(int64_t npad) { return npad <= 0 ? 1 : max_split_rows(npad, npad);
 // leapfrog entry points).  j_tile is the block edge in records, 1024 (16 chunks,
 // for N up to kSymSmallMax) or 2048 (32 chunks); the workgroup shape is fixed
 // (512 threads, 2 rows per lane).  Each row gets one FP32 partial per block, so
-// the partial buffer is npad^2 / (64 blk) x 16 bytes (8 GiB at N = 2^20).
+// the partial buffer is npad^2 / (64 blk) x 16 bytes (8 GiB at N = 2^20); above
+// kSymMaxN (32 GiB of partials) the one-sided kernels, whose partials are O(N),
+// take over.
+constexpr int kBatchUnitsPerWave = 8;    // the rule's work units per resident wave (batched j_split)
 constexpr int kSymStage = 2;
 constexpr int64_t kSymSmallMax = int64_t(1) << 18;
 constexpr int64_t kSymMinN = int64_t(1) << 16;       // the rule's threshold for whole systems
+constexpr int64_t kSymMaxN = int64_t(1) << 21;
 
 bool sym_eligible(int api, int law, int prec)
 {
@@ -183,14 +187,14 @@ bool ipl_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
 {
     if (c.j_stage == kSymStage) {
-        if (sym_eligible(api, law, prec)) {
+        if (sym_eligible(api, law, prec) && npad <= kSymMaxN) {
             c.block = kSymThreads;
             c.ipl = 2;
             c.j_split = 1;
             c.j_tile = sym_blk(c.j_tile, npad) * 64;
             return c;
         }
-        c.j_stage = 1;                                  // other laws, precisions, entry points
+        c.j_stage = 1;                                  // other laws, precisions, entry points, sizes
     }
     c.j_stage = std::max(0, std::min(c.j_stage, 1));
     // the one-sided, batched, adjoint and jerk kernels are built for up to 256 threads
@@ -199,8 +203,10 @@ Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
     if (law >= NBODY_LAW_LJC_CONSTANT) c.ipl = std::min(c.ipl, 2);
     if (api == NBODY_API_JERK || api == NBODY_API_HERMITE) c.ipl = std::min(c.ipl, 2);
     if (c.j_stage == 1) c.ipl = std::min(c.ipl, 4);    // LDS staging: up to 4 rows per lane
-    c.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
-    if (api == NBODY_API_BATCHED || api == NBODY_API_BACKWARD_BATCHED) c.j_split = 1;
+    if (api == NBODY_API_BATCHED || api == NBODY_API_BACKWARD_BATCHED)
+        c.j_split = std::max(1, std::min(c.j_split, 64));      // work units per resident wave
+    else
+        c.j_split = std::max(1, std::min(c.j_split, max_split(npad)));
     if (api == NBODY_API_BACKWARD_BATCHED) c.ipl = std::min(c.ipl, 2);
     return c;
 }
@@ -316,7 +322,7 @@ std::vector<int> ranked_splits(int law, int prec, int64_t rows, int64_t nj, int 
 Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool pot, bool allow_sym = true)
 {
     Cfg c;
-    if (allow_sym && sym_eligible(api, law, prec) && n == nj && n >= kSymMinN) {
+    if (allow_sym && sym_eligible(api, law, prec) && n == nj && n >= kSymMinN && n <= kSymMaxN) {
         c.j_stage = kSymStage;
         c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
         return sanitize(c, api, law, prec, round_up(n, 64));
@@ -327,7 +333,7 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         c.ipl = 1;
         c.block = 256;
         c.j_tile = 256;
-        c.j_split = 1;
+        c.j_split = kBatchUnitsPerWave;
         c.j_stage = is_f32(prec) ? 1 : 0;
         (void)S;
         return c;
@@ -496,7 +502,7 @@ FwdWs fwd_layout(int api, const nbody_law *law, int64_t n)
 {
     FwdWs w{};
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
-    const bool sym = sym_eligible(api, law->kind, law->precision);
+    const bool sym = sym_eligible(api, law->kind, law->precision) && n <= kSymMaxN;
     // the symmetric tiles pad the records to whole blocks and keep one FP32 partial per
     // row and block; the one-sided split keeps [split][rows][4] FP64 partials
     const int64_t nrec = sym ? sym_npad(n, 32) : npad;
@@ -593,11 +599,14 @@ int64_t batch_slot_cap(int64_t n_total, int64_t S)
 }
 
 struct BatWs {
-    size_t rec_off, unit_off, off_off, poff_off, systab_off, part_off, ticket_off, total;
+    size_t rec_off, unit_off, off_off, poff_off, systab_off, red_off, part_off, ticket_off, total;
     int64_t max_slots;       // partial budget: max_slots slots of 128 rows
     int64_t max_units;       // capacity of the unit table
     int64_t max_records;     // capacity of the record buffer
 };
+
+// row blocks of an ensemble (any rows per lane): at most one per 64 rows plus one per system
+int64_t red_capacity(int64_t n_total, int64_t S) { return n_total / 64 + std::max<int64_t>(S, 1) + 1; }
 
 BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
 {
@@ -620,6 +629,8 @@ BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
     off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
     w.systab_off = off;
     off = align256(off + (size_t)std::max<int64_t>(S, 1) * 3 * sizeof(int64_t));
+    w.red_off = off;
+    off = align256(off + (size_t)red_capacity(n_total, S) * 2 * sizeof(int32_t));
     w.part_off = off;
     off = align256(off + (size_t)w.max_slots * 128 * 4 * sizeof(double));
     w.ticket_off = off;
@@ -631,7 +642,7 @@ BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
 // Batched adjoint: adjoint records padded per system, the unit tables and the
 // part sums of split systems (8 doubles per row; half the forward's slot count).
 struct AdjBatWs {
-    size_t rec_off, unit_off, off_off, poff_off, systab_off, part_off, ticket_off, type_off, total;
+    size_t rec_off, unit_off, off_off, poff_off, systab_off, red_off, part_off, ticket_off, type_off, total;
     int64_t max_slots, max_units, max_records;
 };
 
@@ -654,6 +665,8 @@ AdjBatWs adjb_layout(const nbody_law *law, int64_t n_total, int64_t S)
     off = align256(off + (size_t)(S + 1) * sizeof(int64_t));
     w.systab_off = off;
     off = align256(off + (size_t)std::max<int64_t>(S, 1) * 3 * sizeof(int64_t));
+    w.red_off = off;
+    off = align256(off + (size_t)red_capacity(n_total, S) * 2 * sizeof(int32_t));
     w.part_off = off;
     off = align256(off + (size_t)w.max_slots * 128 * 8 * sizeof(double));
     w.ticket_off = off;
@@ -696,7 +709,8 @@ Epilogue make_epi(const nbody_law *law, double *out_force, double *out_pot)
 int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const double *params,
                 int64_t n, const int64_t *rows, int64_t nrows, const Epilogue &epi, bool pot,
                 void *ws, const FwdWs &lay, hipStream_t s, PackLaunch *pk_in,
-                const ExclArgs &excl = ExclArgs{}, bool timed = true)
+                const ExclArgs &excl = ExclArgs{}, bool timed = true, int64_t share = 0,
+                int64_t n_shares = 1)
 {
     // the symmetric tiles (j_stage 2) evaluate whole systems; sanitize admits the
     // configuration only for gravity with FP32_KAHAN / FP32_FP64ACC
@@ -728,6 +742,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
         a.eps2 = law->softening * law->softening;
         a.rec = base + lay.rec_off;
         a.partial = (float4 *)(base + lay.part_off);
+        sym_share_range(a.nblk, share, n_shares, a.t0, a.count);
         a.epi = epi;
         Timer t(s, timed);
         e = launch_sym(a, s);
@@ -885,6 +900,7 @@ struct BatchPlan {
     std::vector<int64_t> poff;
     std::vector<int64_t> systab;      // [S][3] parts, records per part, first slot
     std::vector<int32_t> units;       // [n][4]
+    std::vector<int32_t> red;         // [n_red][2] (system, row block) of the row blocks with P > 1
     int64_t npad_total = 0;
     int64_t n_slots = 0;
 };
@@ -917,7 +933,13 @@ BatchPlan plan_batched(const int64_t *offsets, int64_t S, int ipl, int64_t j_uni
         p.systab[3 * s] = parts;
         p.systab[3 * s + 1] = plen;
         p.systab[3 * s + 2] = parts > 1 ? slots : 0;
-        if (parts > 1) slots += nrb * parts;
+        if (parts > 1) {
+            slots += nrb * parts;
+            for (int64_t rb = 0; rb < nrb; ++rb) {
+                p.red.push_back((int32_t)s);
+                p.red.push_back((int32_t)rb);
+            }
+        }
         for (int64_t rb = 0; rb < nrb; ++rb) {
             const int64_t r = std::min(rows, ns - rb * rows);
             for (int64_t q = 0; q < parts; ++q) {
@@ -987,6 +1009,7 @@ std::shared_ptr<const BatchPlan> cached_plan(const int64_t *offsets, int64_t S, 
 struct DevTables {
     int32_t *units = nullptr;
     int64_t *off = nullptr, *poff = nullptr, *systab = nullptr;
+    int32_t *red = nullptr;
 };
 struct ResidentKey {
     int device;
@@ -1026,7 +1049,8 @@ bool resident_tables(const BatchPlan &plan, const int64_t *offsets, int64_t S, i
     const size_t b_units = align256(plan.units.size() * sizeof(int32_t));
     const size_t b_off = align256((size_t)(S + 1) * sizeof(int64_t));
     const size_t b_sys = align256(std::max<size_t>(plan.systab.size(), 1) * sizeof(int64_t));
-    const size_t bytes = b_units + 2 * b_off + b_sys;
+    const size_t b_red = align256(std::max<size_t>(plan.red.size(), 1) * sizeof(int32_t));
+    const size_t bytes = b_units + 2 * b_off + b_sys + b_red;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess) cap = hipStreamCaptureStatusNone;
     if (cap != hipStreamCaptureStatusNone) {
@@ -1046,12 +1070,15 @@ bool resident_tables(const BatchPlan &plan, const int64_t *offsets, int64_t S, i
     t.off = (int64_t *)(b + b_units);
     t.poff = (int64_t *)(b + b_units + b_off);
     t.systab = (int64_t *)(b + b_units + 2 * b_off);
+    t.red = (int32_t *)(b + b_units + 2 * b_off + b_sys);
     hipError_t e = hipMemcpy(t.units, plan.units.data(), plan.units.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(t.off, offsets, (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(t.poff, plan.poff.data(), (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice);
     if (e == hipSuccess && !plan.systab.empty())
         e = hipMemcpy(t.systab, plan.systab.data(), plan.systab.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !plan.red.empty())
+        e = hipMemcpy(t.red, plan.red.data(), plan.red.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(buf);
         *rc = hip_fail(e, "batched plan tables");
@@ -1067,7 +1094,7 @@ bool resident_tables(const BatchPlan &plan, const int64_t *offsets, int64_t S, i
 // regions given (pageable sources: the runtime stages them before returning).
 int batched_tables(const BatchPlan &plan, const int64_t *offsets, int64_t S, int ipl, int64_t j_unit,
                    hipStream_t s, char *base, size_t unit_off, size_t off_off, size_t poff_off, size_t systab_off,
-                   DevTables *t)
+                   size_t red_off, DevTables *t)
 {
     int rc = NBODY_OK;
     if (resident_tables(plan, offsets, S, ipl, j_unit, s, t, &rc)) return NBODY_OK;
@@ -1076,6 +1103,7 @@ int batched_tables(const BatchPlan &plan, const int64_t *offsets, int64_t S, int
     t->off = (int64_t *)(base + off_off);
     t->poff = (int64_t *)(base + poff_off);
     t->systab = (int64_t *)(base + systab_off);
+    t->red = (int32_t *)(base + red_off);
     hipError_t e = hipMemcpyAsync(t->units, plan.units.data(), plan.units.size() * sizeof(int32_t),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(t->off, offsets, (size_t)(S + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s);
@@ -1084,12 +1112,16 @@ int batched_tables(const BatchPlan &plan, const int64_t *offsets, int64_t S, int
     if (e == hipSuccess)
         e = hipMemcpyAsync(t->systab, plan.systab.data(), plan.systab.size() * sizeof(int64_t),
                            hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !plan.red.empty())
+        e = hipMemcpyAsync(t->red, plan.red.data(), plan.red.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(e, "batched tables");
     return NBODY_OK;
 }
 
-// The plan of one batched launch: j parts of about 8 units per resident wave
-// (`resident` waves on the whole chip), no part shorter than kMinJUnit records,
+// The plan of one batched launch: j parts of about `per_wave` units per resident wave
+// (`resident` waves on the whole chip; the configuration's j_split, 8 by the rule: more
+// parts balance the persistent grid better, fewer parts leave fewer partial sums to add),
+// no part shorter than kMinJUnit records,
 // the part length doubled until the partial slots of split systems fit the
 // workspace (max_slots slots of 128 rows; a slot holds one row block, 64 x ipl
 // rows).
@@ -1098,7 +1130,8 @@ struct PlanChoice {
     int64_t j_unit;
 };
 
-PlanChoice plan_for_launch(const int64_t *offsets, int64_t S, int ipl, int64_t resident, int64_t max_slots)
+PlanChoice plan_for_launch(const int64_t *offsets, int64_t S, int ipl, int64_t resident, int64_t max_slots,
+                           int per_wave = kBatchUnitsPerWave)
 {
     double work = 0.0;
     for (int64_t q = 0; q < S; ++q) {
@@ -1106,7 +1139,8 @@ PlanChoice plan_for_launch(const int64_t *offsets, int64_t S, int ipl, int64_t r
         work += (double)ns * (double)round_up(ns, 64);
     }
     resident = std::max<int64_t>(resident, 1);
-    int64_t j_unit = round_up((int64_t)(work / (8.0 * (double)resident * 64.0 * ipl)) + 1, 64);
+    per_wave = std::max(1, per_wave);
+    int64_t j_unit = round_up((int64_t)(work / ((double)per_wave * (double)resident * 64.0 * ipl)) + 1, 64);
     j_unit = std::max(kMinJUnit, j_unit);
     std::shared_ptr<const BatchPlan> pp = cached_plan(offsets, S, ipl, j_unit);
     while (pp->n_slots * ipl > 2 * max_slots) {
@@ -1119,10 +1153,11 @@ PlanChoice plan_for_launch(const int64_t *offsets, int64_t S, int ipl, int64_t r
 // Whether a plan fits the workspace regions it is copied into and the part
 // slots its units address: the unit table (max_units units), the padded
 // records (max_records) and max_slots slots of 128 rows.
-bool plan_fits(const BatchPlan &p, int ipl, int64_t max_units, int64_t max_records, int64_t max_slots)
+bool plan_fits(const BatchPlan &p, int ipl, int64_t max_units, int64_t max_records, int64_t max_slots,
+               int64_t max_red)
 {
     return (int64_t)p.units.size() / 4 <= max_units && p.npad_total <= max_records &&
-           p.n_slots * ipl <= 2 * max_slots;
+           p.n_slots * ipl <= 2 * max_slots && (int64_t)p.red.size() / 2 <= max_red;
 }
 
 int g_num_cus = 0;
@@ -1158,16 +1193,16 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
         std::max(1, batched_blocks_per_cu_cached(law->kind, law->precision, c.ipl, out_pot != nullptr,
                                                  c.j_stage, c.block, excl.off != nullptr));
     const int64_t resident = (int64_t)device_cus() * per_cu * (c.block / 64);
-    const PlanChoice pc = plan_for_launch(offsets, S, c.ipl, resident, lay.max_slots);
+    const PlanChoice pc = plan_for_launch(offsets, S, c.ipl, resident, lay.max_slots, c.j_split);
     const BatchPlan &plan = *pc.plan;
     if (plan.units.empty()) return NBODY_OK;
-    if (!plan_fits(plan, c.ipl, lay.max_units, lay.max_records, lay.max_slots))
+    if (!plan_fits(plan, c.ipl, lay.max_units, lay.max_records, lay.max_slots, red_capacity(offsets[S], S)))
         return fail(NBODY_EWORKSPACE, "internal: batched plan exceeds its workspace regions "
                     "(%lld units, %lld slots)", (long long)(plan.units.size() / 4), (long long)plan.n_slots);
     char *base = (char *)ws;
     DevTables tab;
     int rc = batched_tables(plan, offsets, S, c.ipl, pc.j_unit, s, base, lay.unit_off, lay.off_off, lay.poff_off,
-                            lay.systab_off, &tab);
+                            lay.systab_off, lay.red_off, &tab);
     if (rc) return rc;
     int32_t *d_units = tab.units;
     int64_t *d_off = tab.off;
@@ -1186,6 +1221,7 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     pk.params = params;
     pk.qscale = qscale_of(law);
     pk.rec = base + lay.rec_off;
+    pk.ticket = (int *)(base + lay.ticket_off);
     e = launch_pack_batched(pk, s);
     if (e != hipSuccess) return hip_fail(e, "batched pack");
 
@@ -1207,6 +1243,8 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     b.systab = d_systab;
     b.partial = (double *)(base + lay.part_off);
     b.any_parts = plan.n_slots > 0;
+    b.red = tab.red;
+    b.n_red = (int64_t)plan.red.size() / 2;
     b.n_systems = S;
     b.n_total = offsets[S];
     b.npad_total = plan.npad_total;
@@ -1215,6 +1253,7 @@ int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int6
     for (int c = 0; c < 4; ++c) b.zeta[c] = law->kind == NBODY_LAW_LJC_SIGMOIDAL ? law->zeta[c] : 0.0;
     b.rec = base + lay.rec_off;
     b.ticket = (int *)(base + lay.ticket_off);
+    b.ticket_zeroed = 1;
     b.epi = make_epi(law, out_force, out_pot);
     b.excl = excl;
     Timer t(s);
@@ -1304,6 +1343,39 @@ int forces_impl(const double *pos, const double *params, int64_t n, const int64_
                                       round_up(std::max(n, nrows), 64)), excl != nullptr);
     return run_forward(law, cs, pos, params, n, rows, nrows, make_epi(law, out_force, out_potential),
                        pot, ws, lay, (hipStream_t)stream, nullptr, excl_args(excl));
+}
+
+// One share of the symmetric pair tiles (gravity, FP32 pair arithmetic): the tiles of order
+// range share / n_shares of the triangle, reduced into per-row partial sums of all n rows.
+int share_impl(const double *pos, const double *params, int64_t n, const nbody_law *law, int32_t share,
+               int32_t n_shares, double *out_force, double *out_potential, void *ws, size_t ws_bytes,
+               void *stream)
+{
+    int rc = validate_law(law, false);
+    if (rc) return rc;
+    if (!sym_eligible(NBODY_API_FORCES, law->kind, law->precision))
+        return fail(NBODY_ENOTSUP, "shares of the symmetric pair tiles are provided for gravity with "
+                    "FP32_KAHAN or FP32_FP64ACC (other laws shard by rows: nbody_forces_subset)");
+    if (n < 0) return fail(NBODY_EINVAL, "n < 0");
+    if (n > kSymMaxN) return fail(NBODY_ENOTSUP, "the symmetric pair tiles take up to %lld particles",
+                                  (long long)kSymMaxN);
+    if (n_shares < 1 || share < 0 || share >= n_shares)
+        return fail(NBODY_EINVAL, "share %d of %d: need 0 <= share < n_shares", (int)share, (int)n_shares);
+    if (n == 0) return NBODY_OK;
+    if (!pos || !params || !out_force) return fail(NBODY_EINVAL, "pos, params and out_force must be non-NULL");
+    const FwdWs lay = fwd_layout(NBODY_API_FORCES, law, n);
+    rc = check_ws(ws, ws_bytes, lay.total);
+    if (rc) return rc;
+    const bool pot = out_potential != nullptr;
+    const int64_t npad = round_up(n, 64);
+    Cfg c = choose(NBODY_API_FORCES, law, n, 1, pot);
+    if (c.j_stage != kSymStage) {                      // the rule's block edge for this size
+        c.j_stage = kSymStage;
+        c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
+    }
+    c = sanitize(c, NBODY_API_FORCES, law->kind, law->precision, npad);
+    return run_forward(law, c, pos, params, n, nullptr, n, make_epi(law, out_force, out_potential), pot, ws,
+                       lay, (hipStream_t)stream, nullptr, ExclArgs{}, true, share, n_shares);
 }
 
 int batched_impl(const int64_t *offsets, int64_t S, const double *pos, const double *params,
@@ -1433,20 +1505,21 @@ std::vector<Cfg> candidate_set(int api, int law, int prec, int64_t n, bool pot)
         for (int js : {0, 1})
             for (int ipl : {1, 2})
                 for (int b : {64, 128, 256})
-                    for (int jt : {64, 256}) {
-                        if (js == 0 && !is_f32(prec) && ipl > 1) continue;
-                        (void)law;
-                        Cfg c;
-                        c.ipl = ipl;
-                        c.block = b;
-                        c.j_tile = jt;
-                        c.j_split = 1;
-                        c.j_stage = js;
-                        out.push_back(c);
-                    }
+                    for (int jt : {64, 256})
+                        for (int upw : {kBatchUnitsPerWave, 4, 16}) {
+                            if (js == 0 && !is_f32(prec) && ipl > 1) continue;
+                            (void)law;
+                            Cfg c;
+                            c.ipl = ipl;
+                            c.block = b;
+                            c.j_tile = jt;
+                            c.j_split = upw;
+                            c.j_stage = js;
+                            out.push_back(c);
+                        }
         return out;
     }
-    if (sym_eligible(api, law, prec))
+    if (sym_eligible(api, law, prec) && npad <= kSymMaxN)
         for (int jt : {1024, 2048}) {          // the symmetric tiles, both block edges
             if (jt == 1024 && n > kSymSmallMax) continue;
             Cfg c;
@@ -1731,6 +1804,13 @@ int nbody_forces_subset(const double *pos, const double *params, int64_t n, cons
                        stream, nullptr);
 }
 
+int nbody_forces_share(const double *pos, const double *params, int64_t n, const nbody_law *law, int32_t share,
+                       int32_t n_shares, double *out_force, double *out_potential, void *ws, size_t ws_bytes,
+                       void *stream)
+{
+    return share_impl(pos, params, n, law, share, n_shares, out_force, out_potential, ws, ws_bytes, stream);
+}
+
 int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
                          const double *params, const nbody_law *law, double *out_force,
                          double *out_potential, void *ws, size_t ws_bytes, void *stream)
@@ -1902,15 +1982,15 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
         per_cu = std::max(1, per_cu);
     }
     const int64_t resident = (int64_t)device_cus() * per_cu * (c.block / 64);
-    const PlanChoice pc = plan_for_launch(offsets, n_systems, ipl, resident, lay.max_slots);
+    const PlanChoice pc = plan_for_launch(offsets, n_systems, ipl, resident, lay.max_slots, c.j_split);
     const BatchPlan &plan = *pc.plan;
     if (plan.units.empty()) return NBODY_OK;
-    if (!plan_fits(plan, ipl, lay.max_units, lay.max_records, lay.max_slots))
+    if (!plan_fits(plan, ipl, lay.max_units, lay.max_records, lay.max_slots, red_capacity(n, n_systems)))
         return fail(NBODY_EWORKSPACE, "internal: batched adjoint plan exceeds its workspace regions");
     char *base = (char *)ws;
     DevTables tab;
     rc = batched_tables(plan, offsets, n_systems, ipl, pc.j_unit, s, base, lay.unit_off, lay.off_off,
-                        lay.poff_off, lay.systab_off, &tab);
+                        lay.poff_off, lay.systab_off, lay.red_off, &tab);
     if (rc) return rc;
     int32_t *d_units = tab.units;
     int64_t *d_off = tab.off;
@@ -1928,6 +2008,8 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     a.systab = d_systab;
     a.partial = (double *)(base + lay.part_off);
     a.any_parts = plan.n_slots > 0;
+    a.red = tab.red;
+    a.n_red = (int64_t)plan.red.size() / 2;
     a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
     a.G = law->G;
     a.qscale = qscale_of(law);
@@ -1936,6 +2018,7 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     a.g = grad_force;
     a.rec = base + lay.rec_off;
     a.ticket = (int *)(base + lay.ticket_off);
+    a.ticket_zeroed = 1;
     a.grad_pos = grad_pos;
     a.grad_params = grad_params;
     e = launch_pack_adjoint_batched(a, s);

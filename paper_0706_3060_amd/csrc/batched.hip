@@ -9,7 +9,8 @@
 // kernel, restricted to one part of the records of its own system.  A system
 // whose j range is cut into P > 1 parts (Section 3.4's replication, applied
 // per system so that there are enough units to balance the machine) writes
-// per-part partial sums, which k_batched_reduce adds in part order.
+// per-part partial sums, which k_batched_reduce adds in part order (one
+// workgroup per row block of such a system, from the plan's list).
 #include <type_traits>
 
 #include "allpairs.h"
@@ -100,27 +101,39 @@ __device__ __forceinline__ void batched_body(
 
 // The rows of systems cut into several j parts: the part sums in part order
 // (Neumaier, so the result does not depend on the schedule).
+// Row block red[blockIdx.x] of a system cut into P > 1 parts: each thread adds its row's P
+// part sums in part order (FP64, Neumaier) and writes the row.  The P loads of a row are
+// issued before the sums, four parts at a time.
 __global__ __launch_bounds__(256) void k_batched_reduce(BatchLaunch b)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= b.n_total) return;
-    int64_t lo = 0, hi = b.n_systems;          // off[lo] <= r < off[hi]
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (b.off[mid] <= r) lo = mid;
-        else hi = mid;
-    }
-    const int64_t nparts = b.systab[3 * lo];
-    if (nparts <= 1) return;
+    const int64_t s = b.red[2 * blockIdx.x], rb = b.red[2 * blockIdx.x + 1];
     const int64_t rows = (int64_t)kWave * b.ipl;
-    const int64_t l = r - b.off[lo];
-    const int64_t rb = l / rows, rr = l - rb * rows;
-    const int64_t slot0 = b.systab[3 * lo + 2] + rb * nparts;
+    const int64_t l = rb * rows + threadIdx.x;
+    if (l >= b.off[s + 1] - b.off[s]) return;
+    const int64_t r = b.off[s] + l;
+    const int64_t nparts = b.systab[3 * s];
+    const int64_t slot0 = b.systab[3 * s + 2] + rb * nparts;
+    const double4 *__restrict__ q = (const double4 *)b.partial + slot0 * rows + threadIdx.x;
     NSum v[4];
-    for (int64_t p = 0; p < nparts; ++p) {
-        const double *q = b.partial + ((slot0 + p) * rows + rr) * 4;
+    int64_t p = 0;
+    for (; p + 4 <= nparts; p += 4) {
+        double4 x[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) v[c].add(q[c]);
+        for (int k = 0; k < 4; ++k) x[k] = q[(p + k) * rows];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[0].add(x[k].x);
+            v[1].add(x[k].y);
+            v[2].add(x[k].z);
+            v[3].add(x[k].w);
+        }
+    }
+    for (; p < nparts; ++p) {
+        const double4 x = q[p * rows];
+        v[0].add(x.x);
+        v[1].add(x.y);
+        v[2].add(x.z);
+        v[3].add(x.w);
     }
     const Epilogue &e = b.epi;
     e.out_force[3 * r] = e.fscale * v[0].value();
@@ -152,6 +165,7 @@ template <typename R, int P>
 __global__ __launch_bounds__(256) void k_pack_batched(BatchPackLaunch a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.ticket && i < 64) a.ticket[i] = 0;     // the work ticket of the launch that follows
     if (i >= a.npad_total) return;
     int64_t lo = 0, hi = a.n_systems;          // poff[lo] <= i < poff[hi]
     while (hi - lo > 1) {
@@ -287,14 +301,14 @@ struct PtrB {
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t s)
 {
     if (b.n_units <= 0) return hipSuccess;
-    hipError_t e = launch_fill_zero(b.ticket, 256, s);
+    hipError_t e = b.ticket_zeroed ? hipSuccess : launch_fill_zero(b.ticket, 256, s);
     if (e != hipSuccess) return e;
     if (b.excl.off && (b.law == GRAVITY || b.ipl > 2 || b.prec == P_PLAIN)) return hipErrorInvalidValue;
     LaunchB l{b, s};
     if (!batched_dispatch(b.law, b.prec, b.ipl, b.pot != 0, l)) return hipErrorInvalidValue;
     e = hipGetLastError();
-    if (e != hipSuccess || !b.any_parts) return e;
-    hipLaunchKernelGGL(k_batched_reduce, dim3((unsigned)((b.n_total + 255) / 256)), dim3(256), 0, s, b);
+    if (e != hipSuccess || !b.any_parts || b.n_red <= 0) return e;
+    hipLaunchKernelGGL(k_batched_reduce, dim3((unsigned)b.n_red), dim3((unsigned)(kWave * b.ipl)), 0, s, b);
     return hipGetLastError();
 }
 

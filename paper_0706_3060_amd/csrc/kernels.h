@@ -89,32 +89,32 @@ struct SymLaunch {
     double eps2;
     const void *rec;               // FP32 gravity records {x, y, z, m}
     float4 *partial;               // [nblk][npad] (x, y, z, potential) FP32 slot partials
+    int64_t t0, count;             // order range of the launch's tiles (whole triangle: 0, sym_tiles)
     Epilogue epi;
 };
 // Tile order of the symmetric launch.  The upper triangle (b1 <= b2) of the nblk x nblk block
 // grid is walked in strips of kSymStrip block rows, column by column inside a strip, so that
-// consecutive tiles share their blocks; the walk is cut into kSymXcds equal portions, one per
-// XCD (workgroups reach the XCDs in turn by linear id), so that each XCD's L2 sees a compact
-// region of the grid at a time.  Workgroup `wg` of sym_grid(nblk) workgroups gets tile
-// (b1, b2); sym_tile_of returns false for the few workgroups past the last tile.
+// consecutive tiles share their blocks: sym_tile_at maps an order index to its tile and
+// sym_index_of is its inverse.  A launch covers the order range [t0, t0 + count) (the whole
+// triangle, or one share of it); the range is cut into kSymXcds equal portions, one per XCD
+// (workgroups reach the XCDs in turn by linear id), so that each XCD's L2 sees a compact region
+// of the grid at a time.  Workgroup `wg` of sym_grid(count) gets its tile from sym_tile_of,
+// which returns false for the few workgroups past the last tile.
 constexpr int kSymStrip = 8;
 constexpr int kSymXcds = 8;
 __host__ __device__ inline int64_t sym_tiles(int64_t nblk) { return nblk * (nblk + 1) / 2; }
-__host__ __device__ inline int64_t sym_grid(int64_t nblk)
+__host__ __device__ inline int64_t sym_grid(int64_t count)
 {
-    return (sym_tiles(nblk) + kSymXcds - 1) / kSymXcds * kSymXcds;
+    return (count + kSymXcds - 1) / kSymXcds * kSymXcds;
 }
-// first tile of strip s (every strip before it is a full one)
+// first order index of strip s (every strip before it is a full one)
 __host__ __device__ inline int64_t sym_strip_start(int64_t s, int64_t nblk)
 {
     const int64_t h = kSymStrip;
     return s * (h * (h + 1) / 2) + h * (s * nblk - h * s * (s + 1) / 2);
 }
-__host__ __device__ inline bool sym_tile_of(int64_t wg, int64_t nblk, int64_t &b1, int64_t &b2)
+__host__ __device__ inline void sym_tile_at(int64_t t, int64_t nblk, int64_t &b1, int64_t &b2)
 {
-    const int64_t tiles = sym_tiles(nblk), per = sym_grid(nblk) / kSymXcds;
-    const int64_t t = (wg % kSymXcds) * per + wg / kSymXcds;
-    if (t >= tiles) return false;
     int64_t lo = 0, hi = (nblk + kSymStrip - 1) / kSymStrip - 1;      // strip: last start <= t
     while (lo < hi) {
         const int64_t mid = (lo + hi + 1) / 2;
@@ -133,7 +133,31 @@ __host__ __device__ inline bool sym_tile_of(int64_t wg, int64_t nblk, int64_t &b
         b2 = r0 + h + (u - tri) / h;
         b1 = r0 + (u - tri) % h;
     }
+}
+__host__ __device__ inline int64_t sym_index_of(int64_t b1, int64_t b2, int64_t nblk)
+{
+    const int64_t s = b1 / kSymStrip, r0 = s * kSymStrip;
+    const int64_t h = nblk - r0 < kSymStrip ? nblk - r0 : kSymStrip;
+    const int64_t k = b2 - r0;
+    const int64_t u = k < h ? k * (k + 1) / 2 + (b1 - r0) : h * (h + 1) / 2 + (k - h) * h + (b1 - r0);
+    return sym_strip_start(s, nblk) + u;
+}
+__host__ __device__ inline bool sym_tile_of(int64_t wg, int64_t nblk, int64_t t0, int64_t count, int64_t &b1,
+                                            int64_t &b2)
+{
+    const int64_t per = sym_grid(count) / kSymXcds;
+    const int64_t local = (wg % kSymXcds) * per + wg / kSymXcds;
+    if (local >= count) return false;
+    sym_tile_at(t0 + local, nblk, b1, b2);
     return true;
+}
+// Order range of share `share` of `shares` equal shares of the triangle.
+__host__ __device__ inline void sym_share_range(int64_t nblk, int64_t share, int64_t shares, int64_t &t0,
+                                                int64_t &count)
+{
+    const int64_t T = sym_tiles(nblk);
+    t0 = T * share / shares;
+    count = T * (share + 1) / shares - t0;
 }
 hipError_t launch_sym(const SymLaunch &a, hipStream_t s);
 hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s);
@@ -151,6 +175,8 @@ struct BatchLaunch {
     const int64_t *systab;       // [S][3] = (j parts P, records per part, first partial slot)
     double *partial;             // [slots][64 * ipl][4] part sums of systems with P > 1
     int any_parts;               // some system has P > 1 (the part sums need reducing)
+    const int32_t *red;          // [n_red][2] (system, row block) of the row blocks with P > 1
+    int64_t n_red;
     int64_t n_systems;
     int64_t n_total, npad_total;
     int j_tile;
@@ -158,7 +184,8 @@ struct BatchLaunch {
     double eps2;
     double zeta[4];              // as FwdLaunch::zeta
     const void *rec;
-    int *ticket;                 // zeroed by launch_batched before the kernel
+    int *ticket;                 // zeroed by the batched pack (ticket_zeroed) or by launch_batched
+    int ticket_zeroed;           // the pack of this launch has zeroed the ticket
     Epilogue epi;
     ExclArgs excl;               // exclusion lists over the caller's rows, or off == nullptr
 };
@@ -169,6 +196,7 @@ struct BatchPackLaunch {
     const double *pos, *params;
     double qscale;
     void *rec;
+    int *ticket;                 // or null: 256 bytes the pack zeroes for the batched kernel
 };
 hipError_t launch_pack_batched(const BatchPackLaunch &p, hipStream_t s);
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t s);

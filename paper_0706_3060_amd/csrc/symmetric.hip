@@ -5,7 +5,7 @@
 // Decomposition.  The padded records form nblk blocks of blk chunks of 64
 // (blk = 16 or 32).  Each workgroup takes one tile (b1, b2), b1 <= b2, of the
 // upper triangle of the block grid (in the XCD-aware strip order of
-// sym_tile_of): the pairs between the rows of block b1 and the rows of block
+// sym_tile_of; a launch covers the whole triangle or one share of it): the pairs between the rows of block b1 and the rows of block
 // b2 (on the diagonal, b1 == b2, each unordered pair once).  Its
 // 8 waves hold two i chunks each (128 rows per wave, 16 chunks per pass; two
 // passes for blk = 32) and sweep the j chunks of b2 in rounds: in round r wave
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(6))
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int blk = a.blk;
     int64_t b1, b2;
-    if (!sym_tile_of(blockIdx.x, a.nblk, b1, b2)) return;       // whole workgroup, before any barrier
+    if (!sym_tile_of(blockIdx.x, a.nblk, a.t0, a.count, b1, b2)) return;   // whole workgroup, before any barrier
     const bool diag = b1 == b2;
     const float eps2 = (float)a.eps2;
     const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
@@ -194,14 +194,23 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(6))
     for (int q = w; q < blk; q += kSymWaves) a.partial[b1 * a.npad + jrec0 + (int64_t)q * kWave + lane] = jacc[q][lane];
 }
 
-// Row r: the nblk slot partials in slot order (FP64, Neumaier), then the epilogue.
+// Row r: the nblk slot partials in slot order (FP64, Neumaier), then the epilogue.  When
+// the launch covered one share of the tiles, slot k of a row of block b holds a partial
+// only if tile (min(b, k), max(b, k)) is in the share; the other slots are skipped (the
+// test is the same for every row of a workgroup: 256 rows lie in one block).
 __global__ __launch_bounds__(256) void k_sym_reduce(SymLaunch a)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= a.n) return;
     NSum v[4];
     const float4 *__restrict__ part = a.partial;
+    const bool whole = a.t0 == 0 && a.count == sym_tiles(a.nblk);
+    const int64_t b = r / ((int64_t)a.blk * kWave);
     for (int64_t k = 0; k < a.nblk; ++k) {
+        if (!whole) {
+            const int64_t t = b <= k ? sym_index_of(b, k, a.nblk) : sym_index_of(k, b, a.nblk);
+            if (t < a.t0 || t >= a.t0 + a.count) continue;
+        }
         const float4 x = part[k * a.npad + r];
         v[0].add((double)x.x);
         v[1].add((double)x.y);
@@ -227,10 +236,11 @@ __global__ __launch_bounds__(256) void k_sym_reduce(SymLaunch a)
 
 hipError_t launch_sym(const SymLaunch &a, hipStream_t s)
 {
-    if (a.nblk <= 0) return hipSuccess;
-    if (a.blk % kSymPassChunks != 0 || a.blk > kSymMaxBlk || a.npad != (int64_t)a.nblk * a.blk * kWave)
+    if (a.nblk <= 0 || a.count <= 0) return hipSuccess;
+    if (a.blk % kSymPassChunks != 0 || a.blk > kSymMaxBlk || a.npad != (int64_t)a.nblk * a.blk * kWave ||
+        a.t0 < 0 || a.t0 + a.count > sym_tiles(a.nblk))
         return hipErrorInvalidValue;
-    const dim3 grid((unsigned)sym_grid(a.nblk)), block(kSymThreads);
+    const dim3 grid((unsigned)sym_grid(a.count)), block(kSymThreads);
     if (a.prec == P_KAHAN) {
         if (a.pot) hipLaunchKernelGGL((k_sym<P_KAHAN, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_sym<P_KAHAN, false>), grid, block, 0, s, a);

@@ -225,6 +225,23 @@ def forces_subset(pos, params, ilist, law: Law, potential: bool = True):
     return f, p
 
 
+def forces_share(pos, params, law: Law, share: int, n_shares: int, potential: bool = True):
+    """Share `share` of `n_shares` of a gravity evaluation over unordered pairs (what one of
+    n_shares GPUs would evaluate): per-row partial sums of every row; the shares' outputs add
+    up to forces()."""
+    pos = _dev_f64(pos, None, "pos")
+    n = pos.shape[0]
+    pos = _dev_f64(pos, (n, 3), "pos")
+    par = _params(params, n, law, pos.device)
+    f = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    p = torch.empty(n, dtype=torch.float64, device=pos.device) if potential else None
+    ws = workspace(API_FORCES, n, 1, law, pos.device)
+    N.check(N.lib().nbody_forces_share(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), int(share),
+                                       int(n_shares), _ptr(f), _ptr(p), _ptr(ws), ws.numel(),
+                                       _stream(pos.device)))
+    return f, p
+
+
 def _host_offsets(offsets):
     if isinstance(offsets, torch.Tensor):
         offsets = offsets.detach().cpu().numpy()

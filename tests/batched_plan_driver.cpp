@@ -4,10 +4,12 @@
 // the batched entry points call (plan_for_launch, plan_batched, plan_fits,
 // bat_layout, adjb_layout) without a GPU: no kernel is launched.  For every
 // ensemble file given (raw int64 offsets, S + 1 values) and every combination
-// of chip size, blocks per CU, block size and rows per lane, it plans as a
+// of chip size, blocks per CU, block size, rows per lane and work units per
+// wave, it plans as a
 // launch would and then walks every unit the way the kernels address memory:
 // system, row block and part in range, j range inside the system's padded
-// records, part slot inside the partial region, tables inside their regions.
+// records, part slot inside the partial region, tables inside their regions,
+// and the reduction list (every row block of every split system once).
 // It also checks that a plan larger than a workspace's regions is refused.
 // Prints one line per ensemble and exits non-zero on the first violation.
 #include "api.cpp"
@@ -31,8 +33,8 @@ int g_bad = 0;
 
 // Walk one plan against the regions of a layout (partial slot of `dbl` doubles per row).
 void walk(const BatchPlan &p, const std::vector<int64_t> &off, int ipl, size_t rec_bytes_, size_t rec_off,
-          size_t unit_off, size_t next_off, size_t part_off, size_t part_end, int64_t max_slots, int dbl,
-          const char *what)
+          size_t unit_off, size_t next_off, size_t red_off, size_t red_end, size_t part_off, size_t part_end,
+          int64_t max_slots, int dbl, const char *what)
 {
     const int64_t S = (int64_t)off.size() - 1;
     const int64_t rows = 64 * ipl;
@@ -73,6 +75,26 @@ void walk(const BatchPlan &p, const std::vector<int64_t> &off, int ipl, size_t r
     }
     for (int64_t k = 0; k < p.n_slots; ++k) EXPECT(seen[(size_t)k] == 1, "%s: slot %lld written %lld times",
                                                      what, (long long)k, (long long)seen[(size_t)k]);
+    // the reduction list: every row block of every split system exactly once, inside its region,
+    // and each row block's slots inside the slot range
+    EXPECT(red_off + p.red.size() * sizeof(int32_t) <= red_end, "%s: reduction list overruns", what);
+    std::vector<int64_t> want_red;
+    for (int64_t s = 0; s < S; ++s)
+        if (p.systab[3 * s] > 1)
+            for (int64_t rb = 0; rb * rows < off[s + 1] - off[s]; ++rb) {
+                want_red.push_back(s);
+                want_red.push_back(rb);
+            }
+    EXPECT(want_red.size() == p.red.size(), "%s: reduction list has %zu entries, want %zu", what,
+           p.red.size() / 2, want_red.size() / 2);
+    for (size_t k = 0; k < std::min(want_red.size(), p.red.size()); ++k)
+        EXPECT(want_red[k] == p.red[k], "%s: reduction list entry %zu", what, k / 2);
+    for (size_t k = 0; k + 1 < p.red.size(); k += 2) {
+        const int64_t s = p.red[k], rb = p.red[k + 1];
+        const int64_t last = p.systab[3 * s + 2] + (rb + 1) * p.systab[3 * s] - 1;
+        EXPECT(last < p.n_slots, "%s: row block (%lld, %lld) reads slot %lld of %lld", what, (long long)s,
+               (long long)rb, (long long)last, (long long)p.n_slots);
+    }
     int64_t want = 0;
     for (int64_t s = 0; s < S; ++s) want += (off[s + 1] - off[s]) * round_up(off[s + 1] - off[s], 64);
     EXPECT(pairs == want, "%s: units cover %lld row x record pairs, want %lld", what, (long long)pairs,
@@ -105,32 +127,42 @@ int main(int argc, char **argv)
         for (int cus : {80, 256, 304})
             for (int per_cu = 1; per_cu <= 16; ++per_cu)
                 for (int block : {64, 128, 192, 256})
-                    for (int ipl : {1, 2, 4}) {
+                    for (int ipl : {1, 2, 4})
+                    for (int upw : {1, 8, 64}) {
                         const int64_t resident = (int64_t)cus * per_cu * (block / 64);
-                        const PlanChoice pc = plan_for_launch(off.data(), S, ipl, resident, lay.max_slots);
+                        const int64_t max_red = red_capacity(n, S);
+                        const PlanChoice pc = plan_for_launch(off.data(), S, ipl, resident, lay.max_slots, upw);
                         const BatchPlan &p = *pc.plan;
-                        EXPECT(plan_fits(p, ipl, lay.max_units, lay.max_records, lay.max_slots),
-                               "forward plan (cus %d, per_cu %d, block %d, ipl %d)", cus, per_cu, block, ipl);
+                        EXPECT(plan_fits(p, ipl, lay.max_units, lay.max_records, lay.max_slots, max_red),
+                               "forward plan (cus %d, per_cu %d, block %d, ipl %d, upw %d)", cus, per_cu, block,
+                               ipl, upw);
                         walk(p, off, ipl, rec_bytes(law.kind, law.precision), lay.rec_off, lay.unit_off,
-                             lay.off_off, lay.part_off, lay.ticket_off, lay.max_slots, 4, "forward");
+                             lay.off_off, lay.red_off, lay.part_off, lay.part_off, lay.ticket_off, lay.max_slots, 4,
+                             "forward");
                         max_units = std::max<int64_t>(max_units, (int64_t)p.units.size() / 4);
                         max_slots_used = std::max<int64_t>(max_slots_used, p.n_slots * ipl);
                         if (ipl <= 2) {       // the batched adjoint runs up to 2 rows per lane
-                            const PlanChoice pa = plan_for_launch(off.data(), S, ipl, resident, alay.max_slots);
-                            EXPECT(plan_fits(*pa.plan, ipl, alay.max_units, alay.max_records, alay.max_slots),
+                            const PlanChoice pa =
+                                plan_for_launch(off.data(), S, ipl, resident, alay.max_slots, upw);
+                            EXPECT(plan_fits(*pa.plan, ipl, alay.max_units, alay.max_records, alay.max_slots,
+                                             max_red),
                                    "adjoint plan (cus %d, per_cu %d, block %d, ipl %d)", cus, per_cu, block, ipl);
                             walk(*pa.plan, off, ipl, adj_rec_bytes(law.kind, law.precision), alay.rec_off,
-                                 alay.unit_off, alay.off_off, alay.part_off, alay.ticket_off, alay.max_slots, 8,
-                                 "adjoint");
+                                 alay.unit_off, alay.off_off, alay.red_off, alay.part_off, alay.part_off,
+                                 alay.ticket_off, alay.max_slots, 8, "adjoint");
                         }
                         ++plans;
                         // a workspace whose regions are one unit / one slot too small refuses the plan
                         if (!p.units.empty())
                             EXPECT(!plan_fits(p, ipl, (int64_t)p.units.size() / 4 - 1, lay.max_records,
-                                              lay.max_slots), "undersized unit table accepted");
+                                              lay.max_slots, max_red), "undersized unit table accepted");
                         if (p.n_slots > 0)
                             EXPECT(!plan_fits(p, ipl, lay.max_units, lay.max_records,
-                                              (p.n_slots * ipl + 1) / 2 - 1), "undersized slot region accepted");
+                                              (p.n_slots * ipl + 1) / 2 - 1, max_red),
+                                   "undersized slot region accepted");
+                        if (!p.red.empty())
+                            EXPECT(!plan_fits(p, ipl, lay.max_units, lay.max_records, lay.max_slots,
+                                              (int64_t)p.red.size() / 2 - 1), "undersized reduction list accepted");
                     }
         std::printf("%s: S=%lld n=%lld plans=%d max_units=%lld/%lld max_slot_rows=%lld/%lld violations=%d\n",
                     argv[a], (long long)S, (long long)n, plans, (long long)max_units, (long long)lay.max_units,

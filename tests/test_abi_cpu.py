@@ -114,6 +114,28 @@ def test_forces_validation(N):
     assert lib.nbody_forces(None, None, 0, ctypes.byref(law(N)), None, None, None, 0, None) == 0
 
 
+def test_share_validation(N):
+    lib = N.lib()
+
+    def share(n, lw, sh, nsh, ws_bytes=1 << 40, out=True):
+        return lib.nbody_forces_share(fake(), fake(), n, ctypes.byref(lw) if lw is not None else None,
+                                      sh, nsh, fake() if out else None, None, fake(), ws_bytes, None)
+
+    g = law(N, prec=2)
+    assert share(10, None, 0, 1) == N.NBODY_EINVAL
+    for sh, nsh in [(-1, 4), (4, 4), (0, 0), (0, -3)]:
+        assert share(10, g, sh, nsh) == N.NBODY_EINVAL, (sh, nsh)
+        assert b"share" in lib.nbody_last_error()
+    # other laws and precisions shard by rows; the symmetric tiles stop at 2^21 particles
+    assert share(10, law(N, kind=1), 0, 2) == N.NBODY_ENOTSUP
+    assert share(10, law(N, prec=0), 0, 2) == N.NBODY_ENOTSUP
+    assert share(10, law(N, prec=3), 0, 2) == N.NBODY_ENOTSUP
+    assert share((1 << 21) + 1, g, 0, 2) == N.NBODY_ENOTSUP
+    assert share(10, g, 0, 2, out=False) == N.NBODY_EINVAL
+    assert share(10, g, 1, 2, ws_bytes=16) == N.NBODY_EWORKSPACE
+    assert lib.nbody_forces_share(None, None, 0, ctypes.byref(g), 0, 1, None, None, None, 0, None) == 0
+
+
 def test_batched_validation(N):
     lib = N.lib()
     lw = law(N, kind=1)
@@ -193,6 +215,23 @@ def test_config_validation(N):
             assert (c.block, c.i_per_lane, c.j_tile, c.j_stage) == (512, 2, 2048, 2), (api, law.kind)
         else:
             assert 64 <= c.block <= 256 and c.j_stage in (0, 1), (api, law.kind, law.precision, c.block)
+    # the rule takes the symmetric tiles for whole gravity systems from 65,536 to 2,097,152
+    # particles; above that their O(n^2) partials (34 GB at 2^21) would outgrow the workspace,
+    # and a forced symmetric configuration reads as one-sided there
+    g1 = grav(2)
+    for n, want in [(65535, False), (65536, True), (1 << 21, True), ((1 << 21) + 1, False), (1 << 22, False)]:
+        c = N.NBodyConfig()
+        assert lib.nbody_get_config(0, n, 1, ctypes.byref(g1), ctypes.byref(c)) == 0
+        assert (c.j_stage == 2) == want, (n, c.j_stage)
+        try:
+            assert lib.nbody_set_config(0, ctypes.byref(sym)) == 0
+            assert lib.nbody_get_config(0, n, 1, ctypes.byref(g1), ctypes.byref(c)) == 0
+        finally:
+            lib.nbody_set_config(0, None)
+        assert (c.j_stage == 2) == (n <= 1 << 21), (n, c.j_stage)
+    w_sym = lib.nbody_workspace_bytes(0, 1 << 21, 1, ctypes.byref(g1))
+    w_one = lib.nbody_workspace_bytes(0, (1 << 21) + 64, 1, ctypes.byref(g1))
+    assert w_sym >= 1024 * (1 << 21) * 16 and w_one < 4 << 30, (w_sym, w_one)
 
 
 def test_flop_convention_and_version(N):

@@ -164,3 +164,52 @@ def test_subset_and_noalloc_fall_back(nb):
     a_ref, _ = oracle.gravity(W.round_to_f32(x), W.round_to_f32(m), eps=0.01, ilist=rows)
     e = row_errors(host(fn)[rows], a_ref)
     assert np.median(e) <= 1e-5 and e.max() <= 1e-3
+
+
+@pytest.mark.parametrize("n,G", [(3001, 1.0), (70000, 2.5)])
+def test_shares_add_up_to_the_forces(nb, n, G):
+    """nbody_forces_share: the shares of the tile triangle (what each of several GPUs would
+    evaluate) add up to the whole evaluation; one share is the whole evaluation bit for bit.
+    The sum of 8 shares also meets the oracle on sampled rows."""
+    x, _, m = W.plummer(n, 710 + n % 97)
+    law = nb.gravity("fp32_kahan", softening=0.01, G=G)
+    X, M = dev(x), dev(m)
+    nb.set_config(nb.API_FORCES, 512, 2, 1024, 1, 2)
+    try:
+        f_full, p_full = nb.forces(X, M, law)
+        f1, p1 = nb.forces_share(X, M, law, 0, 1)
+        assert torch.equal(f1, f_full) and torch.equal(p1, p_full)
+        fmax, pmax = f_full.abs().max().item(), p_full.abs().max().item()
+        for shares in (2, 3, 8):
+            fs = torch.zeros_like(f_full)
+            ps = torch.zeros_like(p_full)
+            for sh in range(shares):
+                f, p = nb.forces_share(X, M, law, sh, shares)
+                fs += f
+                ps += p
+            assert (fs - f_full).abs().max().item() <= 1e-12 * fmax, shares
+            assert (ps - p_full).abs().max().item() <= 1e-12 * pmax, shares
+    finally:
+        nb.clear_config(nb.API_FORCES)
+    rows = np.sort(np.random.default_rng(8).choice(n, 200, replace=False))
+    a_ref, phi_ref = oracle.gravity(W.round_to_f32(x), W.round_to_f32(m), G=G, eps=0.01, ilist=rows)
+    e = row_errors(host(fs)[rows], a_ref)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3
+    ep = np.abs(host(ps)[rows] - phi_ref) / np.abs(phi_ref)
+    assert np.median(ep) <= 1e-5 and ep.max() <= 1e-3
+
+
+def test_share_more_shares_than_tiles(nb):
+    # 5 particles make one tile: every share but the one holding it returns zeros
+    x, _, m = W.plummer(5, 720)
+    law = nb.gravity("fp32_kahan", softening=0.01)
+    X, M = dev(x), dev(m)
+    f_full, _ = nb.forces(X, M, law)
+    total = torch.zeros_like(f_full)
+    nonzero = 0
+    for sh in range(4):
+        f, _ = nb.forces_share(X, M, law, sh, 4)
+        nonzero += int(bool((f != 0).any()))
+        total += f
+    assert nonzero == 1
+    assert (total - f_full).abs().max().item() <= 1e-5 * f_full.abs().max().item()

@@ -1,12 +1,14 @@
 """The tile order of the symmetric all-pairs launch, on the CPU.
 
 tests/sym_order_driver.cpp includes csrc/kernels.h, whose sym_tile_of maps each
-workgroup of the launch to its tile (the kernel calls the same function).  For
+workgroup of a launch to its tile (the kernels call the same functions).  For
 block counts from 1 to 2048, including every remainder modulo the strip height
 and the XCD count, the tiles must be the upper triangle of the block grid, each
-exactly once, with fewer than 8 idle workgroups; and the tiles that one XCD runs
-at a time must share their blocks (at most 25 distinct blocks in any 96
-consecutive workgroups of an XCD, against about 97 for a row-major order).
+exactly once, with fewer than 8 idle workgroups; the order index must invert;
+the shares of 1, 2, 3, 8 and 13 equal parts (nbody_forces_share) must cover the
+triangle exactly once; and the tiles that one XCD runs at a time must share
+their blocks (at most 25 distinct blocks in any 96 consecutive workgroups of an
+XCD, against about 97 for a row-major order).
 """
 import os
 import re
@@ -21,7 +23,7 @@ CSRC = os.path.join(ROOT, "paper_0706_3060_amd", "csrc")
 ROCM_INCLUDE = "/opt/rocm/include"
 
 
-def test_symmetric_tile_order_is_a_bijection_with_local_windows(tmp_path):
+def test_symmetric_tile_order_shares_and_windows(tmp_path):
     if shutil.which("g++") is None or not os.path.isdir(ROCM_INCLUDE):
         pytest.skip("g++ and the ROCm headers are needed")
     exe = tmp_path / "sym_order"
