@@ -287,7 +287,9 @@ def timed_kernel(n, cfg):
         rec = cfg["j_tile"]
         nblk = -(-n // rec)
         tiles = nblk * (nblk + 1) // 2
-        return "k_sym<1, true>", str(-(-tiles // 8) * 8 * cfg["block"])   # padded to the 8 XCDs
+        waves = cfg["block"] // 64
+        return ("k_sym<1, true, %d, %d>" % (waves, cfg["i_per_lane"]),
+                str(-(-tiles // 8) * 8 * cfg["block"]))              # padded to the 8 XCDs
     waves = -(-n // (64 * cfg["i_per_lane"]))
     wpb = cfg["block"] // 64
     return ("k_forces<0, 1, %d, true, %d>" % (cfg["i_per_lane"], cfg["j_stage"]),

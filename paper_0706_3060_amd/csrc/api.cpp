@@ -188,8 +188,10 @@ Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
 {
     if (c.j_stage == kSymStage) {
         if (sym_eligible(api, law, prec) && npad <= kSymMaxN) {
-            c.block = kSymThreads;
-            c.ipl = 2;
+            // two workgroup shapes: 8 waves of 2 i chunks, or 4 waves of 4 i chunks
+            const bool four = c.ipl >= 4 && c.block <= 256;
+            c.block = four ? 256 : kSymThreads;
+            c.ipl = four ? 4 : 2;
             c.j_split = 1;
             c.j_tile = sym_blk(c.j_tile, npad) * 64;
             return c;
@@ -325,6 +327,12 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
     if (allow_sym && sym_eligible(api, law, prec) && n == nj && n >= kSymMinN && n <= kSymMaxN) {
         c.j_stage = kSymStage;
         c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
+        // 4 waves of 4 i chunks (half the cross-lane moves per pair, 4 waves per SIMD) against
+        // 8 waves of 2 (6 waves per SIMD): measured 5-7 % faster with the potential, and from
+        // N = 2^17 without it
+        const bool four = pot || n > (int64_t(1) << 17);
+        c.ipl = four ? 4 : 2;
+        c.block = four ? 256 : kSymThreads;
         return sanitize(c, api, law, prec, round_up(n, 64));
     }
     const int64_t npad = round_up(std::max<int64_t>(std::max(n, nj), 1), 64);
@@ -736,6 +744,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
         a.prec = law->precision;
         a.pot = pot ? 1 : 0;
         a.blk = blk;
+        a.ich = c.ipl;
         a.nblk = npad / ((int64_t)blk * 64);
         a.npad = npad;
         a.n = n;
@@ -1369,7 +1378,8 @@ int share_impl(const double *pos, const double *params, int64_t n, const nbody_l
     const bool pot = out_potential != nullptr;
     const int64_t npad = round_up(n, 64);
     Cfg c = choose(NBODY_API_FORCES, law, n, 1, pot);
-    if (c.j_stage != kSymStage) {                      // the rule's block edge for this size
+    if (c.j_stage != kSymStage) {                      // the rule's symmetric shape for this size
+        c = Cfg{};
         c.j_stage = kSymStage;
         c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
     }
@@ -1520,13 +1530,16 @@ std::vector<Cfg> candidate_set(int api, int law, int prec, int64_t n, bool pot)
         return out;
     }
     if (sym_eligible(api, law, prec) && npad <= kSymMaxN)
-        for (int jt : {1024, 2048}) {          // the symmetric tiles, both block edges
-            if (jt == 1024 && n > kSymSmallMax) continue;
-            Cfg c;
-            c.j_stage = kSymStage;
-            c.j_tile = jt;
-            out.push_back(sanitize(c, api, law, prec, npad));
-        }
+        for (int jt : {1024, 2048})            // the symmetric tiles, both block edges and shapes
+            for (int ipl : {2, 4}) {
+                if (jt == 1024 && n > kSymSmallMax) continue;
+                Cfg c;
+                c.j_stage = kSymStage;
+                c.j_tile = jt;
+                c.ipl = ipl;
+                c.block = ipl == 4 ? 256 : kSymThreads;
+                out.push_back(sanitize(c, api, law, prec, npad));
+            }
     const bool jerk = api == NBODY_API_JERK;
     for (int js : {0, 1})
         for (int ipl : {1, 2, 4, 8}) {

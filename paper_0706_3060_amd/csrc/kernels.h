@@ -78,11 +78,12 @@ hipError_t launch_reduce_split(const FwdLaunch &f, hipStream_t s);
 int forces_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block);
 
 // ---- symmetric pair tiles (symmetric.hip): gravity, every unordered pair once ----
-constexpr int kSymThreads = 512;           // 8 waves per workgroup, 2 i chunks per wave
+constexpr int kSymThreads = 512;           // the larger workgroup: 8 waves, 2 i chunks per wave (or 4 x 4)
 constexpr int kSymMaxBlk = 32;             // largest block edge in chunks of 64 records
 struct SymLaunch {
     int prec, pot;                 // P_KAHAN or P_FP64ACC tile sums; potential on/off
     int blk;                       // block edge in chunks of 64 records: 16 or 32
+    int ich;                       // i chunks per wave: 2 (8-wave workgroups) or 4 (4-wave workgroups)
     int64_t nblk;                  // blocks; tiles = nblk (nblk + 1) / 2
     int64_t npad;                  // records = nblk * blk * 64 (zero-mass padding past n)
     int64_t n;                     // rows finished by the reduction
@@ -161,7 +162,7 @@ __host__ __device__ inline void sym_share_range(int64_t nblk, int64_t share, int
 }
 hipError_t launch_sym(const SymLaunch &a, hipStream_t s);
 hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s);
-int sym_blocks_per_cu(int prec, int pot);
+int sym_blocks_per_cu(int prec, int pot, int ich);
 
 // ---- batched (one persistent launch over (system, row-block) work units) ----
 struct BatchLaunch {

@@ -5,14 +5,16 @@
 // Decomposition.  The padded records form nblk blocks of blk chunks of 64
 // (blk = 16 or 32).  Each workgroup takes one tile (b1, b2), b1 <= b2, of the
 // upper triangle of the block grid (in the XCD-aware strip order of
-// sym_tile_of; a launch covers the whole triangle or one share of it): the pairs between the rows of block b1 and the rows of block
-// b2 (on the diagonal, b1 == b2, each unordered pair once).  Its
-// 8 waves hold two i chunks each (128 rows per wave, 16 chunks per pass; two
-// passes for blk = 32) and sweep the j chunks of b2 in rounds: in round r wave
-// w takes j chunk (w + r) mod blk, so no two waves touch one j chunk in the
-// same round, and a barrier closes every round.  The order in which the
-// contributions of the waves reach a j chunk is therefore fixed, and the sums
-// repeat bit for bit.
+// sym_tile_of; a launch covers the whole triangle or one share of it): the
+// pairs between the rows of block b1 and the rows of block b2 (on the
+// diagonal, b1 == b2, each unordered pair once).  Its waves hold the i chunks
+// of a pass in registers (8 waves of 2 chunks or 4 waves of 4: 16 chunks per
+// pass, two passes for blk = 32; four chunks per wave halve the cross-lane
+// moves per pair at the cost of registers) and sweep the j chunks of b2 in
+// rounds: in round r wave w takes j chunk (w + r) mod blk, so no two waves
+// touch one j chunk in the same round, and a barrier closes every round.  The
+// order in which the contributions of the waves reach a j chunk is therefore
+// fixed, and the sums repeat bit for bit.
 //
 // A 64 x 64 mini-tile (one i chunk against one j chunk) takes 64 steps.  At
 // step s lane l pairs its i particle with j = l + s (mod 64): the j records
@@ -22,9 +24,8 @@
 // sums (three through the LDS crossbar with ds_bpermute, the potential's with a
 // DPP wave rotation), so after 64 steps lane l holds the sums of j = l again.
 // Between mini-tiles the j sums of a tile live in LDS (FP32, one slot per j of
-// block b2); the i sums are FP32 mini-tile partials
-// folded into Kahan or FP64 running sums (the tile-level compensation of the
-// one-sided kernels).
+// block b2); the i sums are FP32 mini-tile partials folded into Kahan or FP64
+// running sums (the tile-level compensation of the one-sided kernels).
 //
 // Output.  Tile (b1, b2) writes one FP32 partial (x, y, z, potential) per row
 // of b1 into slot b2 and one per row of b2 into slot b1 of the partial buffer
@@ -37,8 +38,6 @@
 
 namespace nbk {
 
-constexpr int kSymWaves = kSymThreads / kWave;    // waves per workgroup
-constexpr int kSymPassChunks = 2 * kSymWaves;     // i chunks of one pass (two per wave)
 
 // the value of lane (l + 1) mod 64, through the LDS crossbar (no LDS memory)
 __device__ __forceinline__ float from_next_lane(int byte_addr, float v)
@@ -58,17 +57,18 @@ __device__ __forceinline__ float from_next_lane_dpp(float v)
 // tiles only): per i slot k, wi[k] / wj[k] switch the i and j sides on or off
 // and self[k] marks a slot whose i chunk is the j chunk itself, whose pair at
 // step 0 is the particle with itself.
-template <bool POT, bool MASK>
-__device__ __forceinline__ void sym_minitile(const GravRec<float> *st, const GravRec<float> (&iv)[2],
-                                             float eps2, int bp_addr, float (&p)[2][4], float (&jv)[4],
-                                             const float (&wi)[2], const float (&wj)[2], const bool (&self)[2])
+template <int ICH, bool POT, bool MASK>
+__device__ __forceinline__ void sym_minitile(const GravRec<float> *st, const GravRec<float> (&iv)[ICH],
+                                             float eps2, int bp_addr, float (&p)[ICH][4], float (&jv)[4],
+                                             const float (&wi)[ICH], const float (&wj)[ICH],
+                                             const bool (&self)[ICH])
 {
     const int lane = lane_id();
-#pragma unroll 8
+#pragma unroll(16 / ICH)
     for (int s = 0; s < kWave; ++s) {
         const GravRec<float> J = st[lane + s];
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < ICH; ++k) {
             const float dx = J.x - iv[k].x, dy = J.y - iv[k].y, dz = J.z - iv[k].z;
             float r2 = fma_(dx, dx, eps2);
             r2 = fma_(dy, dy, r2);
@@ -103,10 +103,14 @@ __device__ __forceinline__ void sym_minitile(const GravRec<float> *st, const Gra
     }
 }
 
-template <int PREC, bool POT>
-__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(6))) void k_sym(SymLaunch a)
+// WAVES waves per workgroup hold ICH i chunks each: (8, 2) or (4, 4), a pass of 16 i chunks.
+template <int PREC, bool POT, int WAVES, int ICH>
+__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 8 ? 6 : 4)))
+void k_sym(SymLaunch a)
 {
     using R = GravRec<float>;
+    constexpr int kThreads = WAVES * kWave;
+    constexpr int kPass = WAVES * ICH;                     // i chunks of one pass
     const R *__restrict__ rec = (const R *)a.rec;
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -118,20 +122,20 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(6))
     const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
 
     __shared__ float4 jacc[kSymMaxBlk][kWave];            // j sums of block b2
-    __shared__ R st_all[kSymWaves][2 * kWave];            // each wave's j chunk, staged twice
+    __shared__ R st_all[WAVES][2 * kWave];                // each wave's j chunk, staged twice
     R *st = st_all[w];
-    for (int k = threadIdx.x; k < blk * kWave; k += kSymThreads) jacc[k / kWave][k % kWave] = float4{0, 0, 0, 0};
+    for (int k = threadIdx.x; k < blk * kWave; k += kThreads) jacc[k / kWave][k % kWave] = float4{0, 0, 0, 0};
     const int64_t jrec0 = b2 * blk * kWave;                // first record of block b2
     const int64_t irec0 = b1 * blk * kWave;                // first record of block b1
     __syncthreads();
 
-    for (int pass = 0; pass < blk / kSymPassChunks; ++pass) {
-        const int aloc = pass * kSymPassChunks + 2 * w;    // local chunks aloc, aloc + 1 of block b1
-        R iv[2];
-        iv[0] = rec[irec0 + (int64_t)aloc * kWave + lane];
-        iv[1] = rec[irec0 + (int64_t)(aloc + 1) * kWave + lane];
-        RunSum<PREC> acc[2][4];
-        float p[2][4];
+    for (int pass = 0; pass < blk / kPass; ++pass) {
+        const int aloc = pass * kPass + ICH * w;           // local chunks aloc .. aloc + ICH - 1 of block b1
+        R iv[ICH];
+#pragma unroll
+        for (int k = 0; k < ICH; ++k) iv[k] = rec[irec0 + (int64_t)(aloc + k) * kWave + lane];
+        RunSum<PREC> acc[ICH][4];
+        float p[ICH][4];
         // the next round's j record of this lane, loaded a round ahead (as a vector, so that it
         // stays in registers)
         const float4 *__restrict__ rec4 = (const float4 *)a.rec;
@@ -146,31 +150,36 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(6))
             float jv[4] = {j4.x, j4.y, j4.z, j4.w};
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < ICH; ++k)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc[k][c].begin(p[k][c]);
             if (!diag) {
-                const float one[2] = {1.0f, 1.0f};
-                const bool none[2] = {false, false};
-                sym_minitile<POT, false>(st, iv, eps2, bp_addr, p, jv, one, one, none);
+                float one[ICH];
+                bool none[ICH];
+#pragma unroll
+                for (int k = 0; k < ICH; ++k) {
+                    one[k] = 1.0f;
+                    none[k] = false;
+                }
+                sym_minitile<ICH, POT, false>(st, iv, eps2, bp_addr, p, jv, one, one, none);
             } else {
                 // chunk q against i chunk aloc + k: symmetric when q is after it, its own
                 // chunk's pairs one-sided when q is it, nothing when q is before it (that pair
                 // is evaluated by the wave holding q)
-                float wi[2], wj[2];
-                bool self[2];
+                float wi[ICH], wj[ICH];
+                bool self[ICH];
 #pragma unroll
-                for (int k = 0; k < 2; ++k) {
+                for (int k = 0; k < ICH; ++k) {
                     const int rel = q - (aloc + k);
                     wi[k] = rel >= 0 ? 1.0f : 0.0f;
                     wj[k] = rel > 0 ? 1.0f : 0.0f;
                     self[k] = rel == 0;
                 }
-                sym_minitile<POT, true>(st, iv, eps2, bp_addr, p, jv, wi, wj, self);
+                sym_minitile<ICH, POT, true>(st, iv, eps2, bp_addr, p, jv, wi, wj, self);
             }
             jacc[q][lane] = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
 #pragma unroll
-            for (int k = 0; k < 2; ++k)
+            for (int k = 0; k < ICH; ++k)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc[k][c].fold(p[k][c]);
             __syncthreads();
@@ -178,7 +187,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(6))
         // i sums of this pass: slot b2 of the rows of block b1, or, on the diagonal, added
         // to the j sums of the same rows (no other wave touches these chunks now)
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < ICH; ++k) {
             const float4 v = float4{(float)acc[k][0].value(), (float)acc[k][1].value(),
                                     (float)acc[k][2].value(), POT ? (float)acc[k][3].value() : 0.0f};
             if (!diag) {
@@ -191,7 +200,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(6))
         __syncthreads();
     }
     // j sums: slot b1 of the rows of block b2
-    for (int q = w; q < blk; q += kSymWaves) a.partial[b1 * a.npad + jrec0 + (int64_t)q * kWave + lane] = jacc[q][lane];
+    for (int q = w; q < blk; q += WAVES) a.partial[b1 * a.npad + jrec0 + (int64_t)q * kWave + lane] = jacc[q][lane];
 }
 
 // Row r: the nblk slot partials in slot order (FP64, Neumaier), then the epilogue.  When
@@ -234,23 +243,31 @@ __global__ __launch_bounds__(256) void k_sym_reduce(SymLaunch a)
     if (a.pot && e.out_pot) e.out_pot[r] = e.pscale * v[3].value();
 }
 
-hipError_t launch_sym(const SymLaunch &a, hipStream_t s)
+template <int WAVES, int ICH>
+static hipError_t launch_sym_shape(const SymLaunch &a, hipStream_t s)
 {
-    if (a.nblk <= 0 || a.count <= 0) return hipSuccess;
-    if (a.blk % kSymPassChunks != 0 || a.blk > kSymMaxBlk || a.npad != (int64_t)a.nblk * a.blk * kWave ||
-        a.t0 < 0 || a.t0 + a.count > sym_tiles(a.nblk))
-        return hipErrorInvalidValue;
-    const dim3 grid((unsigned)sym_grid(a.count)), block(kSymThreads);
+    const dim3 grid((unsigned)sym_grid(a.count)), block(WAVES * kWave);
     if (a.prec == P_KAHAN) {
-        if (a.pot) hipLaunchKernelGGL((k_sym<P_KAHAN, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_sym<P_KAHAN, false>), grid, block, 0, s, a);
+        if (a.pot) hipLaunchKernelGGL((k_sym<P_KAHAN, true, WAVES, ICH>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_sym<P_KAHAN, false, WAVES, ICH>), grid, block, 0, s, a);
     } else if (a.prec == P_FP64ACC) {
-        if (a.pot) hipLaunchKernelGGL((k_sym<P_FP64ACC, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_sym<P_FP64ACC, false>), grid, block, 0, s, a);
+        if (a.pot) hipLaunchKernelGGL((k_sym<P_FP64ACC, true, WAVES, ICH>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_sym<P_FP64ACC, false, WAVES, ICH>), grid, block, 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_sym(const SymLaunch &a, hipStream_t s)
+{
+    if (a.nblk <= 0 || a.count <= 0) return hipSuccess;
+    if (a.blk % 16 != 0 || a.blk > kSymMaxBlk || a.npad != (int64_t)a.nblk * a.blk * kWave ||
+        a.t0 < 0 || a.t0 + a.count > sym_tiles(a.nblk))
+        return hipErrorInvalidValue;
+    if (a.ich == 2) return launch_sym_shape<8, 2>(a, s);
+    if (a.ich == 4) return launch_sym_shape<4, 4>(a, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s)
@@ -260,17 +277,24 @@ hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s)
     return hipGetLastError();
 }
 
-int sym_blocks_per_cu(int prec, int pot)
+template <int WAVES, int ICH>
+static int sym_blocks_shape(int prec, int pot)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
+    const int threads = WAVES * kWave;
     if (prec == P_KAHAN)
-        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_KAHAN, true>, kSymThreads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_KAHAN, false>, kSymThreads, 0);
+        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_KAHAN, true, WAVES, ICH>, threads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_KAHAN, false, WAVES, ICH>, threads, 0);
     else if (prec == P_FP64ACC)
-        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_FP64ACC, true>, kSymThreads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_FP64ACC, false>, kSymThreads, 0);
+        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_FP64ACC, true, WAVES, ICH>, threads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_FP64ACC, false, WAVES, ICH>, threads, 0);
     return e == hipSuccess ? nb : 0;
+}
+
+int sym_blocks_per_cu(int prec, int pot, int ich)
+{
+    return ich == 4 ? sym_blocks_shape<4, 4>(prec, pot) : sym_blocks_shape<8, 2>(prec, pot);
 }
 
 }  // namespace nbk

@@ -23,7 +23,7 @@ pytestmark = pytest.mark.gpu
 
 # The forced alternative shapes of the full-size case: the one-sided kernel with 32 j parts over
 # XCD-ordered blocks and LDS staging, and with one j part and scalar staging.
-ALT_CFG = {"one_sided": (256, 1, 256, 32, 1), "scalar": (256, 1, 256, 1, 0)}
+ALT_CFG = {"sym_8x2": (512, 2, 2048, 1, 2), "one_sided": (256, 1, 256, 32, 1), "scalar": (256, 1, 256, 1, 0)}
 
 
 @pytest.fixture(scope="module")
@@ -217,13 +217,14 @@ def test_config4_full_ensemble(nb, full_ensemble, shape):
         assert np.median(e) <= 1e-5 and e.max() <= 1e-3
 
 
-@pytest.mark.parametrize("shape", ["rule", "one_sided", "scalar"])
+@pytest.mark.parametrize("shape", ["rule", "sym_8x2", "one_sided", "scalar"])
 def test_config5_plummer_1m(nb, shape):
     """Gravity at N = 2^20, FP32 + Kahan, against the FP64 GPU pass over all rows and the oracle
     on sampled rows.  "rule" runs the configuration the benchmark times (the library's rule for
-    this size: the symmetric pair tiles with 2048-record blocks and the slot-ordered partial
-    reduction), through both timed entry points: the forward and one kick-drift-kick step.
-    "one_sided" forces the one-sided kernel with 32 j parts over XCD-ordered blocks and LDS
+    this size: the symmetric pair tiles with 2048-record blocks, 4-wave workgroups of 4 i chunks
+    per wave, and the slot-ordered partial reduction), through both timed entry points: the
+    forward and one kick-drift-kick step.  "sym_8x2" forces the other symmetric shape (8 waves
+    of 2 i chunks); "one_sided" forces the one-sided kernel with 32 j parts over XCD-ordered blocks and LDS
     staging, "scalar" one j part with scalar staging."""
     n, eps, dt = 1 << 20, 0.005, 1e-3
     pos, vel, m = W.plummer(n, 5)
@@ -233,7 +234,7 @@ def test_config5_plummer_1m(nb, shape):
     if shape == "rule":
         for api in (nb.API_FORCES, nb.API_LEAPFROG):
             c = nb.get_config(api, n, law)
-            assert (c["j_stage"], c["j_tile"], c["i_per_lane"]) == (2, 2048, 2), (api, c)
+            assert (c["j_stage"], c["j_tile"], c["i_per_lane"], c["block"]) == (2, 2048, 4, 256), (api, c)
     try:
         if shape != "rule":
             for api in (nb.API_FORCES, nb.API_LEAPFROG):

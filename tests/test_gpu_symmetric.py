@@ -53,16 +53,19 @@ def check(f, p, x, m, eps, G, potential):
         assert p is None
 
 
+@pytest.mark.parametrize("shape", [(512, 2), (256, 4)])
 @pytest.mark.parametrize("j_tile", [1024, 2048])
 @pytest.mark.parametrize("prec", ["fp32_kahan", "fp32_fp64acc"])
-def test_symmetric_ragged_sizes(nb, j_tile, prec):
+def test_symmetric_ragged_sizes(nb, j_tile, prec, shape):
+    # two workgroup shapes: 8 waves of 2 i chunks, 4 waves of 4 i chunks
     law = nb.gravity(prec, softening=0.01)
     for k, n in enumerate(SIZES):
         x, _, m = W.plummer(n, 500 + k) if n > 1 else (np.zeros((1, 3)), None, np.ones(1))
         m = m * np.random.default_rng(k).uniform(0.5, 1.5, n)         # unequal masses
         try:
-            nb.set_config(nb.API_FORCES, 512, 2, j_tile, 1, 2)
-            assert nb.get_config(nb.API_FORCES, n, law)["j_stage"] == 2
+            nb.set_config(nb.API_FORCES, shape[0], shape[1], j_tile, 1, 2)
+            c = nb.get_config(nb.API_FORCES, n, law)
+            assert (c["j_stage"], c["block"], c["i_per_lane"]) == (2,) + shape, c
             for potential in (True, False):
                 f, p = nb.forces(dev(x), dev(m), law, potential=potential)
                 if n == 1:
@@ -73,12 +76,13 @@ def test_symmetric_ragged_sizes(nb, j_tile, prec):
             nb.clear_config(nb.API_FORCES)
 
 
-def test_symmetric_without_softening_and_with_G(nb):
+@pytest.mark.parametrize("shape", [(512, 2), (256, 4)])
+def test_symmetric_without_softening_and_with_G(nb, shape):
     # eps = 0: the self pair of every diagonal chunk must be masked, not evaluated at r = 0
     law = nb.gravity("fp32_kahan", softening=0.0, G=6.674e-3)
     for n in (65, 1500, 4096):
         x, _, m = W.plummer(n, 600 + n)
-        nb.set_config(nb.API_FORCES, 512, 2, 1024, 1, 2)
+        nb.set_config(nb.API_FORCES, shape[0], shape[1], 1024, 1, 2)
         try:
             f, p = nb.forces(dev(x), dev(m), law)
         finally:
@@ -92,7 +96,7 @@ def test_symmetric_is_the_rule_and_repeats_bitwise(nb):
     x, _, m = W.plummer(n, 77)
     law = nb.gravity("fp32_kahan", softening=0.01)
     c = nb.get_config(nb.API_FORCES, n, law)
-    assert (c["j_stage"], c["j_tile"], c["i_per_lane"], c["block"]) == (2, 1024, 2, 512), c
+    assert (c["j_stage"], c["j_tile"], c["i_per_lane"], c["block"]) == (2, 1024, 4, 256), c
     X, M = dev(x), dev(m)
     f1, p1 = nb.forces(X, M, law)
     f2, p2 = nb.forces(X, M, law)
