@@ -116,14 +116,15 @@ def test_symmetric_is_the_rule_and_repeats_bitwise(nb):
     assert np.median(e) <= 1e-5 and e.max() <= 1e-3
 
 
+@pytest.mark.parametrize("shape", [(512, 2), (256, 4)])
 @pytest.mark.parametrize("j_tile", [1024, 2048])
-def test_symmetric_leapfrog_step(nb, j_tile):
+def test_symmetric_leapfrog_step(nb, j_tile, shape):
     n, eps, dt = 3001, 0.01, 1e-3
     x, v, m = W.plummer(n, 88)
     law = nb.gravity("fp32_kahan", softening=eps)
     a0, _ = oracle.gravity(x, m, eps=eps)
     X, V, A, M = dev(x), dev(v), dev(a0), dev(m)
-    nb.set_config(nb.API_LEAPFROG, 512, 2, j_tile, 1, 2)
+    nb.set_config(nb.API_LEAPFROG, shape[0], shape[1], j_tile, 1, 2)
     try:
         pot = nb.leapfrog(X, V, A, M, law, dt, 2, potential=True)
     finally:
@@ -143,14 +144,15 @@ def test_symmetric_leapfrog_step(nb, j_tile):
     assert np.abs(host(V) - vr).max() <= 4 * dt * 1e-3 * amax
 
 
-def test_subset_and_noalloc_fall_back(nb):
+@pytest.mark.parametrize("shape", [(512, 2), (256, 4)])
+def test_subset_and_noalloc_fall_back(nb, shape):
     n = 5000
     x, _, m = W.plummer(n, 99)
     law = nb.gravity("fp32_kahan", softening=0.01)
     X, M = dev(x), dev(m)
     rows = np.sort(np.random.default_rng(3).choice(n, 300, replace=False)).astype(np.int64)
     a_ref, _ = oracle.gravity(W.round_to_f32(x), W.round_to_f32(m), eps=0.01, ilist=rows)
-    nb.set_config(nb.API_FORCES, 512, 2, 1024, 1, 2)
+    nb.set_config(nb.API_FORCES, shape[0], shape[1], 1024, 1, 2)
     try:
         fs, _ = nb.forces_subset(X, M, torch.tensor(rows, device="cuda"), law)
         e = row_errors(host(fs), a_ref)
@@ -170,15 +172,15 @@ def test_subset_and_noalloc_fall_back(nb):
     assert np.median(e) <= 1e-5 and e.max() <= 1e-3
 
 
-@pytest.mark.parametrize("n,G", [(3001, 1.0), (70000, 2.5)])
-def test_shares_add_up_to_the_forces(nb, n, G):
+@pytest.mark.parametrize("n,G,shape", [(3001, 1.0, (512, 2)), (70000, 2.5, (256, 4))])
+def test_shares_add_up_to_the_forces(nb, n, G, shape):
     """nbody_forces_share: the shares of the tile triangle (what each of several GPUs would
     evaluate) add up to the whole evaluation; one share is the whole evaluation bit for bit.
     The sum of 8 shares also meets the oracle on sampled rows."""
     x, _, m = W.plummer(n, 710 + n % 97)
     law = nb.gravity("fp32_kahan", softening=0.01, G=G)
     X, M = dev(x), dev(m)
-    nb.set_config(nb.API_FORCES, 512, 2, 1024, 1, 2)
+    nb.set_config(nb.API_FORCES, shape[0], shape[1], 1024, 1, 2)
     try:
         f_full, p_full = nb.forces(X, M, law)
         f1, p1 = nb.forces_share(X, M, law, 0, 1)
