@@ -34,8 +34,9 @@
  * a whole system, FP32 pair arithmetic, the symmetric pair tiles (j_stage 2,
  * the default from N = 65,536 to 2,097,152) evaluate each unordered pair once
  * and apply it to both particles through per-block partial sums that a
- * fixed-order reduction adds, without atomics.  Either way results are
- * deterministic run to run.
+ * fixed-order reduction adds, without atomics; the batched entry point has
+ * symmetric tiles of its own for gravity and LJC(linear) ensembles.  Either
+ * way results are deterministic run to run.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -176,7 +177,14 @@ typedef struct nbody_exclusions {
  *             FP32_FP64ACC through nbody_forces and leapfrog_step on whole
  *             systems of up to 2,097,152 particles (its per-block partials
  *             grow as n^2: 8.6 GB at n = 2^20, 34 GB at 2^21; elsewhere 2
- *             reads as 1).  With j_stage 2, j_tile is
+ *             reads as 1).  For nbody_forces_batched, j_stage 2 selects the
+ *             batched symmetric tiles (gravity and LJC(linear) with
+ *             FP32_KAHAN or FP32_FP64ACC, no exclusion lists, every system of
+ *             at most 8192 particles; otherwise the launch runs one-sided),
+ *             in a fixed shape (block 256, i_per_lane 4, j_tile 256, j_split
+ *             1): one wave per pair of 256-record blocks of a system, each
+ *             unordered pair once; the rule's choice when systems average 512
+ *             particles or more.  With j_stage 2, j_tile is
  *             the tile edge in records, 1024 (for n <= 262,144) or 2048,
  *             and block, i_per_lane and j_split are fixed (512, 2, 1). */
 typedef struct nbody_config {
@@ -267,7 +275,14 @@ int nbody_forces_share(const double *pos, const double *params, int64_t n, const
  * library keeps; later launches of the same ensemble copy nothing from the
  * host, so they can be captured in a graph (a captured launch reads those
  * tables at every replay).  A first launch inside a stream capture is
- * refused with NBODY_EINVAL before anything is enqueued. */
+ * refused with NBODY_EINVAL before anything is enqueued.
+ * Decompositions (nbody_config.j_stage): one-sided units of rows against
+ * parts of their system's j range (each ordered pair evaluated), or, for
+ * gravity and LJC(linear) with FP32 pair arithmetic and systems of at most
+ * 8192 particles, symmetric tiles of 256 x 256 records (each unordered pair
+ * of a system evaluated once, per-system FP32 slot partials added in a fixed
+ * order in FP64).  The workspace covers both: for those laws it holds up to
+ * 512 bytes of slot partials per particle (32 slots of 16 bytes). */
 int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
                          const double *params, const nbody_law *law, double *out_force,
                          double *out_potential, void *ws, size_t ws_bytes, void *stream);

@@ -98,6 +98,7 @@ int max_split(int64_t npad) { return npad <= 0 ? 1 : max_split_rows(npad, npad);
 // kSymMaxN (32 GiB of partials) the one-sided kernels, whose partials are O(N),
 // take over.
 constexpr int kBatchUnitsPerWave = 8;    // the rule's work units per resident wave (batched j_split)
+constexpr int kBSymWaves = 4;            // waves (one tile each) per workgroup of the batched symmetric tiles
 constexpr int kSymStage = 2;
 constexpr int64_t kSymSmallMax = int64_t(1) << 18;
 constexpr int64_t kSymMinN = int64_t(1) << 16;       // the rule's threshold for whole systems
@@ -186,6 +187,13 @@ bool ipl_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 
 Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
 {
+    if (c.j_stage == kSymStage && api == NBODY_API_BATCHED && bsym_supported(law, prec)) {
+        c.block = kBSymWaves * 64;                    // the batched symmetric tiles' fixed shape
+        c.ipl = kBSymRecords / 64;
+        c.j_tile = kBSymRecords;
+        c.j_split = 1;
+        return c;
+    }
     if (c.j_stage == kSymStage) {
         if (sym_eligible(api, law, prec) && npad <= kSymMaxN) {
             // two workgroup shapes: 8 waves of 2 i chunks, or 4 waves of 4 i chunks
@@ -343,7 +351,13 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         c.j_tile = 256;
         c.j_split = kBatchUnitsPerWave;
         c.j_stage = is_f32(prec) ? 1 : 0;
-        (void)S;
+        // the symmetric tiles for systems of 512 particles on average and more (smaller ones
+        // lose too much to the padding of 256-record blocks and the diagonal tiles; a launch
+        // with a system above 8192 particles runs one-sided all the same)
+        if (api == NBODY_API_BATCHED && allow_sym && bsym_supported(law, prec) && n >= 512 * std::max<int64_t>(S, 1)) {
+            c.j_stage = kSymStage;
+            return sanitize(c, api, law, prec, 64);
+        }
         return c;
     }
     if (is_f32(prec)) {
@@ -608,22 +622,42 @@ int64_t batch_slot_cap(int64_t n_total, int64_t S)
 
 struct BatWs {
     size_t rec_off, unit_off, off_off, poff_off, systab_off, red_off, part_off, ticket_off, total;
+    size_t part_bytes;       // the partial region
     int64_t max_slots;       // partial budget: max_slots slots of 128 rows
     int64_t max_units;       // capacity of the unit table
     int64_t max_records;     // capacity of the record buffer
 };
 
+// the batched symmetric tiles apply to this law and precision
+bool law_has_bsym(const nbody_law *law) { return bsym_supported(law->kind, law->precision); }
+
 // row blocks of an ensemble (any rows per lane): at most one per 64 rows plus one per system
 int64_t red_capacity(int64_t n_total, int64_t S) { return n_total / 64 + std::max<int64_t>(S, 1) + 1; }
+
+// The batched symmetric tiles (systems of at most kBSymMaxSystem particles, padded to blocks of
+// kBSymRecords): their tiles, and their FP32 slot partials (one per row and block of its system),
+// bounded over every ensemble of n_total particles in S systems.
+int64_t bsym_blocks_bound(int64_t n_total, int64_t S) { return n_total / kBSymRecords + std::max<int64_t>(S, 1); }
+int64_t bsym_units_bound(int64_t n_total, int64_t S)
+{
+    return bsym_blocks_bound(n_total, S) * (kBSymMaxSystem / kBSymRecords + 1) / 2 + 1;
+}
+size_t bsym_slot_bytes_bound(int64_t n_total, int64_t S)
+{
+    return (size_t)(n_total + (int64_t)(kBSymRecords - 1) * std::max<int64_t>(S, 1)) *
+           (size_t)(kBSymMaxSystem / kBSymRecords) * 4 * sizeof(float);
+}
 
 BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
 {
     BatWs w{};
-    const int64_t npad_max = n_total + 64 * std::max<int64_t>(S, 1);
+    // records padded per system to 64 (one-sided) or to 256 (symmetric tiles)
+    const int64_t npad_max = n_total + kBSymRecords * std::max<int64_t>(S, 1);
     w.max_slots = batch_slot_cap(n_total, S);
     // units = (row blocks of single-part systems) + (slots of split systems); the
-    // planner admits up to 2 * max_slots / ipl slots (ipl >= 1)
-    const int64_t units_max = n_total / 64 + std::max<int64_t>(S, 1) + 1 + 2 * w.max_slots;
+    // planner admits up to 2 * max_slots / ipl slots (ipl >= 1); or the symmetric tiles
+    const int64_t units_max = std::max(n_total / 64 + std::max<int64_t>(S, 1) + 1 + 2 * w.max_slots,
+                                       bsym_units_bound(n_total, S));
     w.max_units = units_max;
     w.max_records = npad_max;
     size_t off = 0;
@@ -640,7 +674,10 @@ BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
     w.red_off = off;
     off = align256(off + (size_t)red_capacity(n_total, S) * 2 * sizeof(int32_t));
     w.part_off = off;
-    off = align256(off + (size_t)w.max_slots * 128 * 4 * sizeof(double));
+    // the one-sided part sums or the symmetric tiles' slot partials (never both in one launch)
+    w.part_bytes = std::max((size_t)w.max_slots * 128 * 4 * sizeof(double),
+                            law_has_bsym(law) ? bsym_slot_bytes_bound(n_total, S) : (size_t)0);
+    off = align256(off + w.part_bytes);
     w.ticket_off = off;
     off = align256(off + 256);
     w.total = off;
@@ -971,6 +1008,44 @@ BatchPlan plan_batched(const int64_t *offsets, int64_t S, int ipl, int64_t j_uni
     return p;
 }
 
+// The batched symmetric tiles' plan: systems padded to blocks of kBSymRecords; units (s, b1, b2)
+// for b1 <= b2 < nb_s, the off-diagonal tiles first (the diagonal ones cost about 10/16 of
+// them); per system (nb_s, 0, first float4 of its [nb_s][npad_s] slot partials); and the row
+// blocks of 256 rows that the reduction walks.  n_slots counts float4 slot partials.
+BatchPlan plan_bsym(const int64_t *offsets, int64_t S)
+{
+    BatchPlan p;
+    p.poff.assign((size_t)S + 1, 0);
+    p.systab.assign((size_t)S * 3, 0);
+    std::vector<int32_t> diag;
+    int64_t slots = 0;
+    for (int64_t s = 0; s < S; ++s) {
+        const int64_t ns = offsets[s + 1] - offsets[s];
+        const int64_t pn = round_up(ns, kBSymRecords);
+        const int64_t nb = pn / kBSymRecords;
+        p.poff[s + 1] = p.poff[s] + pn;
+        p.systab[3 * s] = nb;
+        p.systab[3 * s + 2] = slots;
+        slots += nb * pn;
+        for (int64_t b1 = 0; b1 < nb; ++b1) {
+            for (int64_t b2 = b1 + 1; b2 < nb; ++b2)
+                for (int32_t v : {(int32_t)s, (int32_t)b1, (int32_t)b2, 0}) p.units.push_back(v);
+            for (int32_t v : {(int32_t)s, (int32_t)b1, (int32_t)b1, 0}) diag.push_back(v);
+        }
+        for (int64_t rb = 0; rb * kBSymRecords < ns; ++rb) {
+            p.red.push_back((int32_t)s);
+            p.red.push_back((int32_t)rb);
+        }
+    }
+    p.units.insert(p.units.end(), diag.begin(), diag.end());
+    p.npad_total = p.poff[S];
+    p.n_slots = slots;
+    return p;
+}
+
+// the plan-cache key of the symmetric tiles (rows per lane -1: not a one-sided plan)
+constexpr int kBSymPlanKey = -1;
+
 // Plans depend only on (offsets, ipl, j_unit), and a simulation evaluates the
 // same ensemble step after step: the last few plans are kept (exact match of
 // the offsets, least recently used first out), so planning (a sort of all
@@ -1000,7 +1075,8 @@ std::shared_ptr<const BatchPlan> cached_plan(const int64_t *offsets, int64_t S, 
             }
         }
     }
-    auto plan = std::make_shared<const BatchPlan>(plan_batched(offsets, S, ipl, j_unit));
+    auto plan = std::make_shared<const BatchPlan>(ipl == kBSymPlanKey ? plan_bsym(offsets, S)
+                                                                      : plan_batched(offsets, S, ipl, j_unit));
     std::lock_guard<std::mutex> lk(g_plan_mu);
     if (g_plans.size() >= kPlanCache) g_plans.erase(g_plans.begin());
     g_plans.push_back({std::vector<int64_t>(offsets, offsets + S + 1), ipl, j_unit, plan});
@@ -1192,6 +1268,71 @@ std::string device_arch()
     std::string a = prop.gcnArchName;
     const size_t c = a.find(':');
     return c == std::string::npos ? a : a.substr(0, c);
+}
+
+// whether the symmetric tiles take this ensemble: law and precision, no exclusion lists, and
+// every system within kBSymMaxSystem
+bool bsym_takes(const nbody_law *law, const int64_t *offsets, int64_t S, bool excl)
+{
+    if (excl || !law_has_bsym(law)) return false;
+    for (int64_t s = 0; s < S; ++s)
+        if (offsets[s + 1] - offsets[s] > kBSymMaxSystem) return false;
+    return true;
+}
+
+// pack (systems padded to blocks of 256) + symmetric tiles + slot-ordered reduction
+int run_bsym(const nbody_law *law, const int64_t *offsets, int64_t S, const double *pos, const double *params,
+             double *out_force, double *out_pot, void *ws, const BatWs &lay, hipStream_t s)
+{
+    std::shared_ptr<const BatchPlan> pp = cached_plan(offsets, S, kBSymPlanKey, 0);
+    const BatchPlan &plan = *pp;
+    if (plan.units.empty()) return NBODY_OK;
+    if ((int64_t)plan.units.size() / 4 > lay.max_units || plan.npad_total > lay.max_records ||
+        (size_t)plan.n_slots * 4 * sizeof(float) > lay.part_bytes ||
+        (int64_t)plan.red.size() / 2 > red_capacity(offsets[S], S))
+        return fail(NBODY_EWORKSPACE, "internal: batched symmetric plan exceeds its workspace regions "
+                    "(%lld tiles, %lld slot partials)", (long long)(plan.units.size() / 4), (long long)plan.n_slots);
+    char *base = (char *)ws;
+    DevTables tab;
+    int rc = batched_tables(plan, offsets, S, kBSymPlanKey, 0, s, base, lay.unit_off, lay.off_off, lay.poff_off,
+                            lay.systab_off, lay.red_off, &tab);
+    if (rc) return rc;
+    BatchPackLaunch pk{};
+    pk.law = law->kind;
+    pk.prec = law->precision;
+    pk.n_systems = S;
+    pk.npad_total = plan.npad_total;
+    pk.off = tab.off;
+    pk.poff = tab.poff;
+    pk.pos = pos;
+    pk.params = params;
+    pk.qscale = qscale_of(law);
+    pk.rec = base + lay.rec_off;
+    hipError_t e = launch_pack_batched(pk, s);
+    if (e != hipSuccess) return hip_fail(e, "batched pack");
+    BSymLaunch a{};
+    a.law = law->kind;
+    a.prec = law->precision;
+    a.pot = out_pot != nullptr;
+    a.n_units = (int64_t)plan.units.size() / 4;
+    a.units = tab.units;
+    a.off = tab.off;
+    a.poff = tab.poff;
+    a.systab = tab.systab;
+    a.red = tab.red;
+    a.n_red = (int64_t)plan.red.size() / 2;
+    a.n_systems = S;
+    a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    a.rec = base + lay.rec_off;
+    a.partial = (float4 *)(base + lay.part_off);
+    a.epi = make_epi(law, out_force, out_pot);
+    Timer t(s);
+    e = launch_bsym(a, s);
+    t.stop();
+    if (e != hipSuccess) return hip_fail(e, "batched symmetric kernel");
+    e = launch_bsym_reduce(a, s);
+    if (e != hipSuccess) return hip_fail(e, "batched symmetric reduction");
+    return NBODY_OK;
 }
 
 int run_batched(const nbody_law *law, const Cfg &c, const int64_t *offsets, int64_t S,
@@ -1405,10 +1546,15 @@ int batched_impl(const int64_t *offsets, int64_t S, const double *pos, const dou
     const BatWs lay = bat_layout(law, n, S);
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
-    const Cfg c = forced ? *forced : choose(NBODY_API_BATCHED, law, n, S, out_potential != nullptr);
-    return run_batched(law, with_excl(sanitize(c, NBODY_API_BATCHED, law->kind, law->precision, 64),
-                                      excl != nullptr), offsets, S, pos,
-                       params, out_force, out_potential, ws, lay, (hipStream_t)stream, excl_args(excl));
+    Cfg c = sanitize(forced ? *forced : choose(NBODY_API_BATCHED, law, n, S, out_potential != nullptr),
+                     NBODY_API_BATCHED, law->kind, law->precision, 64);
+    if (c.j_stage == kSymStage) {
+        if (bsym_takes(law, offsets, S, excl != nullptr))
+            return run_bsym(law, offsets, S, pos, params, out_force, out_potential, ws, lay, (hipStream_t)stream);
+        c = heuristic(NBODY_API_BATCHED, law->kind, law->precision, n, n, S, out_potential != nullptr, false);
+    }
+    return run_batched(law, with_excl(c, excl != nullptr), offsets, S, pos, params, out_force, out_potential, ws,
+                       lay, (hipStream_t)stream, excl_args(excl));
 }
 
 // candidate list for the measured search
@@ -1512,6 +1658,11 @@ std::vector<Cfg> candidate_set(int api, int law, int prec, int64_t n, bool pot)
     std::vector<Cfg> out;
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
     if (api == NBODY_API_BATCHED) {
+        if (bsym_supported(law, prec)) {         // the symmetric tiles (taken when every system fits)
+            Cfg c;
+            c.j_stage = kSymStage;
+            out.push_back(sanitize(c, api, law, prec, npad));
+        }
         for (int js : {0, 1})
             for (int ipl : {1, 2})
                 for (int b : {64, 128, 256})

@@ -1,0 +1,296 @@
+// Symmetric pair tiles for the batched entry points: in every system of an
+// ensemble each unordered pair {i, j} is evaluated once and its force applied
+// to both particles (Newton's third law), the small-system setting of Section
+// 3.4 with the pair arithmetic of Eq. 1 (gravity) or Table 1's LJC(linear).
+//
+// Decomposition.  The records of system s are padded to nb_s blocks of 256
+// (four chunks of 64).  A work unit is one tile (s, b1, b2), b1 <= b2, and one
+// wave evaluates it alone (no barriers): it holds the four i chunks of block
+// b1 in registers and sweeps the four j chunks of block b2.  For j chunk q a
+// 64-step mini-sweep pairs lane l's i particles with j = l + t (mod 64), the
+// chunk staged twice in a wave-private LDS slot so that each lane reads its
+// record at a constant offset.  The j sums travel with their particle from
+// lane to lane (three through the LDS crossbar, the potential's by a DPP
+// rotation); after 64 steps lane l holds the sums of j = l, complete for this
+// tile, and writes them.  On the diagonal (b1 == b2) i chunk k meets j chunk q
+// symmetrically when q > k, one-sidedly (i side only) when q == k, and not at
+// all when q < k: the wave holding chunk k evaluated that pair already.
+//
+// Sums.  The i sums are FP32 mini-sweep partials (4 pairs per step, 64 steps)
+// folded into Kahan or FP64 running sums over the tile; the j sums are FP32
+// over a mini-sweep (256 terms, the one-sided kernels' tile length).  Tile
+// (s, b1, b2) writes one FP32 partial (x, y, z, potential) per row of b1 into
+// slot b2 and one per row of b2 into slot b1 of system s's slot buffer
+// [nb_s][npad_s] (a diagonal tile adds both into slot b1), so every (slot,
+// row) is written exactly once; k_bsym_reduce adds a row's nb_s slots in slot
+// order in FP64 (Neumaier) and applies the epilogue.
+#include "allpairs.h"
+#include "kernels.h"
+
+namespace nbk {
+
+constexpr int kBSymWaves = 4;                       // waves (independent tiles) per workgroup
+constexpr int kBSymChunks = kBSymRecords / kWave;   // chunks per block = i chunks per lane
+
+// the value of lane (l + 1) mod 64: through the LDS crossbar, or by a DPP rotation
+__device__ __forceinline__ float bs_next_lane(int byte_addr, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float bs_next_lane_dpp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+
+// i-particle state of a lane (position and the law's own parameters)
+template <int LAW> struct BsI;
+template <> struct BsI<GRAVITY> { float x, y, z, m; };
+template <> struct BsI<LJC> { float x, y, z, qs, sh, se; };
+
+__device__ __forceinline__ void bs_load(const GravRec<float> *rec, int64_t p, BsI<GRAVITY> &s)
+{
+    const GravRec<float> r = rec[p];
+    s = BsI<GRAVITY>{r.x, r.y, r.z, r.m};
+}
+__device__ __forceinline__ void bs_load(const LjcRec<float> *rec, int64_t p, BsI<LJC> &s)
+{
+    const LjcRec<float> r = rec[p];
+    s = BsI<LJC>{r.x, r.y, r.z, r.qs, r.sh, r.se};
+}
+
+// One unordered pair (i of this lane, j of the step): i-side sums p, j-side sums jv.
+// SELF: the i side only (a pair of the chunk with itself, seen from both lanes), with the
+// particle's own pair (step 0) neutralised.  JSIDE: add the j side.
+template <bool POT, bool JSIDE>
+__device__ __forceinline__ void bs_pair(const BsI<GRAVITY> &i, const GravRec<float> &J, float eps2, bool self0,
+                                        float (&p)[4], float (&jv)[4])
+{
+    const float dx = J.x - i.x, dy = J.y - i.y, dz = J.z - i.z;
+    float r2 = fma_(dx, dx, eps2);
+    r2 = fma_(dy, dy, r2);
+    r2 = fma_(dz, dz, r2);
+    float mj = J.m;
+    r2 = self0 ? 1.0f : r2;
+    mj = self0 ? 0.0f : mj;
+    const float ri = rsqrt_(r2);
+    const float ri3 = (ri * ri) * ri;
+    const float cj = mj * ri3;
+    p[0] = fma_(cj, dx, p[0]);
+    p[1] = fma_(cj, dy, p[1]);
+    p[2] = fma_(cj, dz, p[2]);
+    if (POT) p[3] = fma_(mj, ri, p[3]);
+    if (JSIDE) {
+        const float ci = i.m * ri3;
+        jv[0] = fma_(-ci, dx, jv[0]);
+        jv[1] = fma_(-ci, dy, jv[1]);
+        jv[2] = fma_(-ci, dz, jv[2]);
+        if (POT) jv[3] = fma_(i.m, ri, jv[3]);
+    }
+}
+
+// LJC(linear): F_i += W (r_i - r_j), F_j -= W (r_i - r_j); both get the pair's 2 u_ij
+// (the potential sums carry 2u, halved by the epilogue), as the one-sided ljc_pair.
+template <bool POT, bool JSIDE>
+__device__ __forceinline__ void bs_pair(const BsI<LJC> &i, const LjcRec<float> &J, float, bool self0,
+                                        float (&p)[4], float (&jv)[4])
+{
+    const float dx = J.x - i.x, dy = J.y - i.y, dz = J.z - i.z;
+    float r2 = dx * dx;
+    r2 = fma_(dy, dy, r2);
+    r2 = fma_(dz, dz, r2);
+    float qq = i.qs * J.qs;
+    float e = i.se * J.se;
+    r2 = self0 ? 1.0f : r2;
+    qq = self0 ? 0.0f : qq;
+    e = self0 ? 0.0f : e;
+    const float x = rcp_(r2);
+    const float cx = qq * x;
+    const float sg = i.sh + J.sh;
+    const float s2 = (sg * sg) * x;
+    const float s6 = (s2 * s2) * s2;
+    const float lj = e * s6;                       // 24 eps_ij (sigma_ij / r)^6
+    const float t = fma_(s6, 2.0f, -1.0f);
+    const float W = fma_(lj, t, cx) * x;           // (24 eps_ij (2 s^12 - s^6) + qq x) / r^2
+    p[0] = fma_(-W, dx, p[0]);
+    p[1] = fma_(-W, dy, p[1]);
+    p[2] = fma_(-W, dz, p[2]);
+    float u = 0.0f;
+    if (POT) {
+        const float v = fma_(lj, s6, -lj);         // 24 eps_ij (s^12 - s^6)
+        u = fma_(v, 1.0f / 3.0f, cx);              // 2 u_ij
+        p[3] += u;
+    }
+    if (JSIDE) {
+        jv[0] = fma_(W, dx, jv[0]);
+        jv[1] = fma_(W, dy, jv[1]);
+        jv[2] = fma_(W, dz, jv[2]);
+        if (POT) jv[3] += u;
+    }
+}
+
+// One mini-sweep: the wave's four i chunks against the j chunk staged in `st`.  DIAG: i chunk
+// k pairs symmetrically only when q > k, one-sidedly when q == k, and not when q < k.
+template <int LAW, bool POT, bool DIAG, typename R>
+__device__ __forceinline__ void bs_sweep(const R *st, const BsI<LAW> (&iv)[kBSymChunks], float eps2, int q,
+                                         int bp_addr, float (&p)[kBSymChunks][4], float (&jv)[4])
+{
+    const int lane = lane_id();
+#pragma unroll 4
+    for (int t = 0; t < kWave; ++t) {
+        const R J = st[lane + t];
+#pragma unroll
+        for (int k = 0; k < kBSymChunks; ++k) {
+            if (!DIAG) {
+                bs_pair<POT, true>(iv[k], J, eps2, false, p[k], jv);
+            } else if (k < q) {
+                bs_pair<POT, true>(iv[k], J, eps2, false, p[k], jv);
+            } else if (k == q) {
+                bs_pair<POT, false>(iv[k], J, eps2, t == 0, p[k], jv);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) jv[c] = bs_next_lane(bp_addr, jv[c]);
+        if (POT) jv[3] = bs_next_lane_dpp(jv[3]);
+    }
+}
+
+template <int LAW, int PREC, bool POT>
+__global__ __launch_bounds__(kBSymWaves * kWave) __attribute__((amdgpu_waves_per_eu(PREC == P_KAHAN ? 4 : 3))) void k_bsym(BSymLaunch a)
+{
+    using R = typename RecOf<float, LAW>::type;
+    const R *__restrict__ rec = (const R *)a.rec;
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t u = (int64_t)blockIdx.x * kBSymWaves + w;
+    __shared__ R st_all[kBSymWaves][2 * kWave];                 // each wave's j chunk, staged twice
+    __shared__ float4 jd_all[kBSymWaves][kBSymChunks][kWave];   // diagonal tiles: the j sums of block b1
+    if (u >= a.n_units) return;                                 // whole wave; the kernel has no barriers
+    const int32_t *un = a.units + 4 * u;
+    const int64_t s = un[0], b1 = un[1], b2 = un[2];
+    if (s < 0 || s >= a.n_systems) return;
+    const int64_t po = a.poff[s];
+    const int64_t npad = a.poff[s + 1] - po;
+    const int64_t nb = npad / kBSymRecords;
+    if (b1 < 0 || b2 < b1 || b2 >= nb) return;                  // never index outside the tables
+    const bool diag = b1 == b2;
+    const int64_t irec0 = po + b1 * kBSymRecords, jrec0 = po + b2 * kBSymRecords;
+    float4 *slots = a.partial + a.systab[3 * s + 2];            // [nb][npad] of system s
+    R *st = st_all[w];
+    const float eps2 = (float)a.eps2;
+    const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
+
+    BsI<LAW> iv[kBSymChunks];
+#pragma unroll
+    for (int k = 0; k < kBSymChunks; ++k) bs_load(rec, irec0 + k * kWave + lane, iv[k]);
+    RunSum<PREC> acc[kBSymChunks][4];
+    float p[kBSymChunks][4];
+    // the next chunk's record of this lane, loaded a chunk ahead as 128-bit vectors (so that it
+    // stays in registers)
+    constexpr int V = sizeof(R) / sizeof(float4);               // 1 (gravity) or 2 (LJC)
+    static_assert(V == 1 || V == 2, "records of one or two 128-bit vectors");
+    const float4 *__restrict__ rec4 = (const float4 *)a.rec;
+    float4 *st4 = (float4 *)st;
+    float4 g0 = rec4[(jrec0 + lane) * V], g1 = V == 2 ? rec4[(jrec0 + lane) * V + 1] : float4{0, 0, 0, 0};
+    for (int q = 0; q < kBSymChunks; ++q) {
+        st4[lane * V] = g0;
+        st4[(lane + kWave) * V] = g0;
+        if (V == 2) {
+            st4[lane * V + 1] = g1;
+            st4[(lane + kWave) * V + 1] = g1;
+        }
+        // the next chunk (the last round reloads its own, unused)
+        const int64_t qn = q + 1 < kBSymChunks ? q + 1 : q;
+        g0 = rec4[(jrec0 + qn * kWave + lane) * V];
+        if (V == 2) g1 = rec4[(jrec0 + qn * kWave + lane) * V + 1];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < kBSymChunks; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[k][c].begin(p[k][c]);
+        float jv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (!diag) bs_sweep<LAW, POT, false>(st, iv, eps2, q, bp_addr, p, jv);
+        else bs_sweep<LAW, POT, true>(st, iv, eps2, q, bp_addr, p, jv);
+#pragma unroll
+        for (int k = 0; k < kBSymChunks; ++k)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[k][c].fold(p[k][c]);
+        const float4 jq = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
+        if (!diag) slots[b1 * npad + b2 * kBSymRecords + q * kWave + lane] = jq;   // slot b1, rows of b2
+        else jd_all[w][q][lane] = jq;
+        __builtin_amdgcn_wave_barrier();                         // the slot is restaged next
+    }
+    // i sums: slot b2 of the rows of block b1 (on the diagonal with the j sums of the same rows)
+#pragma unroll
+    for (int k = 0; k < kBSymChunks; ++k) {
+        float4 v = float4{(float)acc[k][0].value(), (float)acc[k][1].value(), (float)acc[k][2].value(),
+                          POT ? (float)acc[k][3].value() : 0.0f};
+        if (diag) {
+            const float4 t = jd_all[w][k][lane];
+            v = float4{v.x + t.x, v.y + t.y, v.z + t.z, v.w + t.w};
+        }
+        slots[b2 * npad + b1 * kBSymRecords + k * kWave + lane] = v;
+    }
+}
+
+// Row block red[blockIdx.x] = (s, rb) of 256 rows: each row adds its system's nb_s slots in
+// slot order (FP64, Neumaier) and applies the epilogue.
+__global__ __launch_bounds__(kBSymRecords) void k_bsym_reduce(BSymLaunch a)
+{
+    const int64_t s = a.red[2 * blockIdx.x], rb = a.red[2 * blockIdx.x + 1];
+    const int64_t l = rb * kBSymRecords + threadIdx.x;
+    const int64_t o = a.off[s];
+    if (l >= a.off[s + 1] - o) return;
+    const int64_t npad = a.poff[s + 1] - a.poff[s];
+    const int64_t nb = npad / kBSymRecords;
+    const float4 *__restrict__ slots = a.partial + a.systab[3 * s + 2];
+    NSum v[4];
+    for (int64_t k = 0; k < nb; ++k) {
+        const float4 x = slots[k * npad + l];
+        v[0].add((double)x.x);
+        v[1].add((double)x.y);
+        v[2].add((double)x.z);
+        v[3].add((double)x.w);
+    }
+    const int64_t r = o + l;
+    const Epilogue &e = a.epi;
+    e.out_force[3 * r] = e.fscale * v[0].value();
+    e.out_force[3 * r + 1] = e.fscale * v[1].value();
+    e.out_force[3 * r + 2] = e.fscale * v[2].value();
+    if (a.pot && e.out_pot) e.out_pot[r] = e.pscale * v[3].value();
+}
+
+template <int LAW, int PREC>
+static void bsym_go(const BSymLaunch &a, const dim3 &grid, const dim3 &block, hipStream_t s)
+{
+    if (a.pot) hipLaunchKernelGGL((k_bsym<LAW, PREC, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_bsym<LAW, PREC, false>), grid, block, 0, s, a);
+}
+
+bool bsym_supported(int law, int prec)
+{
+    return (law == GRAVITY || law == LJC) && (prec == P_KAHAN || prec == P_FP64ACC);
+}
+
+hipError_t launch_bsym(const BSymLaunch &a, hipStream_t s)
+{
+    if (a.n_units <= 0) return hipSuccess;
+    if (!bsym_supported(a.law, a.prec)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((a.n_units + kBSymWaves - 1) / kBSymWaves)), block(kBSymWaves * kWave);
+    if (a.law == GRAVITY) {
+        if (a.prec == P_KAHAN) bsym_go<GRAVITY, P_KAHAN>(a, grid, block, s);
+        else bsym_go<GRAVITY, P_FP64ACC>(a, grid, block, s);
+    } else {
+        if (a.prec == P_KAHAN) bsym_go<LJC, P_KAHAN>(a, grid, block, s);
+        else bsym_go<LJC, P_FP64ACC>(a, grid, block, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_bsym_reduce(const BSymLaunch &a, hipStream_t s)
+{
+    if (a.n_red <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bsym_reduce, dim3((unsigned)a.n_red), dim3(kBSymRecords), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace nbk

@@ -203,6 +203,29 @@ hipError_t launch_pack_batched(const BatchPackLaunch &p, hipStream_t s);
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t s);
 int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block, int excl);
 
+// ---- batched symmetric pair tiles (bsym.hip): gravity or LJC(linear), every unordered pair of a
+// system once, one wave per tile of two 256-record blocks ----
+constexpr int kBSymRecords = 256;          // records per block (four chunks of 64)
+constexpr int64_t kBSymMaxSystem = 8192;   // largest system of a symmetric batched launch (32 blocks)
+struct BSymLaunch {
+    int law, prec, pot;
+    int64_t n_units;
+    const int32_t *units;        // [n_units][4] = (system, b1, b2, 0), b1 <= b2
+    const int64_t *off;          // [S+1] caller row offsets
+    const int64_t *poff;         // [S+1] record offsets, systems padded to whole blocks
+    const int64_t *systab;       // [S][3] = (blocks nb, 0, first float4 of the system's slots)
+    const int32_t *red;          // [n_red][2] (system, row block of 256)
+    int64_t n_red;
+    int64_t n_systems;
+    double eps2;
+    const void *rec;             // FP32 records
+    float4 *partial;             // per system [nb][npad] (x, y, z, potential) FP32 slot partials
+    Epilogue epi;
+};
+bool bsym_supported(int law, int prec);
+hipError_t launch_bsym(const BSymLaunch &a, hipStream_t s);
+hipError_t launch_bsym_reduce(const BSymLaunch &a, hipStream_t s);
+
 // zero-fill with a kernel (no memset nodes, so the calls stay capturable)
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 

@@ -101,6 +101,63 @@ void walk(const BatchPlan &p, const std::vector<int64_t> &off, int ipl, size_t r
            (long long)want);
 }
 
+// The batched symmetric tiles' plan: every system's upper triangle of blocks exactly once, slot
+// partials inside the system's slots and the workspace's bound, the reduction list over every
+// row block of 256, records inside their region.
+void walk_bsym(const BatchPlan &p, const std::vector<int64_t> &off, const BatWs &lay)
+{
+    const int64_t S = (int64_t)off.size() - 1;
+    EXPECT((int64_t)p.units.size() / 4 <= lay.max_units, "bsym: %zu tiles > %lld", p.units.size() / 4,
+           (long long)lay.max_units);
+    EXPECT(p.npad_total <= lay.max_records, "bsym: %lld records > %lld", (long long)p.npad_total,
+           (long long)lay.max_records);
+    EXPECT((size_t)p.n_slots * 16 <= lay.part_bytes, "bsym: %lld slot partials exceed the partial region",
+           (long long)p.n_slots);
+    EXPECT((int64_t)p.red.size() / 2 <= red_capacity(off.back(), S), "bsym: reduction list overruns");
+    std::vector<std::vector<char>> seen((size_t)S);
+    int64_t slot_end = 0;
+    for (int64_t s = 0; s < S; ++s) {
+        const int64_t ns = off[s + 1] - off[s], pn = p.poff[s + 1] - p.poff[s], nb = p.systab[3 * s];
+        EXPECT(pn == round_up(ns, 256) && nb * 256 == pn, "bsym: system %lld padding", (long long)s);
+        EXPECT(p.systab[3 * s + 2] == slot_end, "bsym: system %lld slot base", (long long)s);
+        slot_end += nb * pn;
+        seen[(size_t)s].assign((size_t)(nb * nb), 0);
+    }
+    EXPECT(slot_end == p.n_slots, "bsym: slot count");
+    bool diag_seen = false;
+    for (size_t u = 0; u < p.units.size() / 4; ++u) {
+        const int64_t s = p.units[4 * u], b1 = p.units[4 * u + 1], b2 = p.units[4 * u + 2];
+        EXPECT(s >= 0 && s < S, "bsym: tile %zu system %lld", u, (long long)s);
+        if (s < 0 || s >= S) continue;
+        const int64_t nb = p.systab[3 * s], pn = p.poff[s + 1] - p.poff[s];
+        EXPECT(b1 >= 0 && b1 <= b2 && b2 < nb, "bsym: tile %zu blocks (%lld, %lld) of %lld", u, (long long)b1,
+               (long long)b2, (long long)nb);
+        if (b1 < 0 || b1 > b2 || b2 >= nb) continue;
+        EXPECT(!diag_seen || b1 == b2, "bsym: off-diagonal tile %zu after the diagonal ones", u);
+        diag_seen = diag_seen || b1 == b2;
+        char &c = seen[(size_t)s][(size_t)(b1 * nb + b2)];
+        EXPECT(!c, "bsym: tile (%lld, %lld, %lld) twice", (long long)s, (long long)b1, (long long)b2);
+        c = 1;
+        // the slots this tile writes: (b2, rows of b1) and (b1, rows of b2)
+        const int64_t hi = p.systab[3 * s + 2] + std::max(b1, b2) * pn + std::max(b1, b2) * 256 + 255;
+        EXPECT(hi < p.n_slots, "bsym: tile %zu writes past the slot partials", u);
+        EXPECT(p.poff[s] + b2 * 256 + 255 < p.npad_total, "bsym: tile %zu reads past the records", u);
+    }
+    for (int64_t s = 0; s < S; ++s) {
+        const int64_t nb = p.systab[3 * s];
+        for (int64_t b1 = 0; b1 < nb; ++b1)
+            for (int64_t b2 = b1; b2 < nb; ++b2)
+                EXPECT(seen[(size_t)s][(size_t)(b1 * nb + b2)], "bsym: tile (%lld, %lld, %lld) missing", (long long)s,
+                       (long long)b1, (long long)b2);
+    }
+    size_t k = 0;
+    for (int64_t s = 0; s < S; ++s)
+        for (int64_t rb = 0; rb * 256 < off[s + 1] - off[s]; ++rb, k += 2)
+            EXPECT(k + 1 < p.red.size() && p.red[k] == s && p.red[k + 1] == rb, "bsym: reduction list entry %zu",
+                   k / 2);
+    EXPECT(k == p.red.size(), "bsym: reduction list length");
+}
+
 }  // namespace
 
 int main(int argc, char **argv)
@@ -164,6 +221,21 @@ int main(int argc, char **argv)
                             EXPECT(!plan_fits(p, ipl, lay.max_units, lay.max_records, lay.max_slots,
                                               (int64_t)p.red.size() / 2 - 1), "undersized reduction list accepted");
                     }
+        // the symmetric tiles, for the laws that have them, where every system fits
+        {
+            nbody_law grav{};
+            grav.kind = NBODY_LAW_GRAVITY;
+            grav.precision = NBODY_FP32_KAHAN;
+            for (const nbody_law *lw : {(const nbody_law *)&law, (const nbody_law *)&grav}) {
+                const BatWs blay = bat_layout(lw, n, S);
+                const bool takes = bsym_takes(lw, off.data(), S, false);
+                bool fits = true;
+                for (int64_t s = 0; s < S; ++s) fits = fits && off[s + 1] - off[s] <= kBSymMaxSystem;
+                EXPECT(takes == fits, "bsym_takes %d for an ensemble whose systems fit: %d", (int)takes, (int)fits);
+                EXPECT(!bsym_takes(lw, off.data(), S, true), "bsym_takes with exclusion lists");
+                if (takes) walk_bsym(plan_bsym(off.data(), S), off, blay);
+            }
+        }
         std::printf("%s: S=%lld n=%lld plans=%d max_units=%lld/%lld max_slot_rows=%lld/%lld violations=%d\n",
                     argv[a], (long long)S, (long long)n, plans, (long long)max_units, (long long)lay.max_units,
                     (long long)max_slots_used * 64, (long long)lay.max_slots * 128, g_bad);

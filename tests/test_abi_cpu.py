@@ -201,18 +201,23 @@ def test_config_validation(N):
     sym = N.NBodyConfig(512, 2, 2048, 1, 2)
     grav = lambda prec: N.NBodyLaw(0, prec, 1.0, 0.01, 0.0, 1.0)
     ljc = N.NBodyLaw(1, 1, 1.0, 0.0, 332.0637, 4.0)
-    cases = [(0, grav(1), True), (3, grav(2), True), (0, grav(0), False), (0, grav(3), False),
-             (0, ljc, False), (1, ljc, False), (1, grav(1), False), (2, grav(1), False),
-             (4, grav(1), False), (5, grav(2), False), (6, ljc, False)]
-    for api, law, symmetric in cases:
+    # the batched entry point keeps j_stage 2 as its own symmetric tiles (gravity and LJC(linear)
+    # with FP32 pair arithmetic), in their fixed shape of 4 waves over 256-record blocks
+    cases = [(0, grav(1), "sym"), (3, grav(2), "sym"), (0, grav(0), None), (0, grav(3), None),
+             (0, ljc, None), (1, ljc, "bsym"), (1, grav(1), "bsym"), (1, grav(0), None),
+             (1, N.NBodyLaw(2, 1, 1.0, 0.0, 332.0637, 4.0), None), (2, grav(1), None),
+             (4, grav(1), None), (5, grav(2), None), (6, ljc, None)]
+    for api, law, kind in cases:
         c = N.NBodyConfig()
         try:
             assert lib.nbody_set_config(api, ctypes.byref(sym)) == 0
             assert lib.nbody_get_config(api, 1 << 20, 1, ctypes.byref(law), ctypes.byref(c)) == 0
         finally:
             lib.nbody_set_config(api, None)
-        if symmetric:
+        if kind == "sym":
             assert (c.block, c.i_per_lane, c.j_tile, c.j_stage) == (512, 2, 2048, 2), (api, law.kind)
+        elif kind == "bsym":
+            assert (c.block, c.i_per_lane, c.j_tile, c.j_stage) == (256, 4, 256, 2), (api, law.kind)
         else:
             assert 64 <= c.block <= 256 and c.j_stage in (0, 1), (api, law.kind, law.precision, c.block)
     # the rule takes the symmetric tiles for whole gravity systems from 65,536 to 2,097,152

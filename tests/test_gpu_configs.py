@@ -176,13 +176,15 @@ def test_config3_euler_identities_on_gpu(nb):
     assert abs((s.sigma * gpar[:, 1]).sum() + (s.pos * gp).sum() + gflj + 3 * gfc) <= 1e-9 * scale
 
 
-# The default rule, and three forced shapes of the persistent launch over the full ensemble: one
+# The default rule, and four forced shapes of the persistent launch over the full ensemble: one
 # row per lane with scalar staging and two rows per lane with LDS staging.  Under the forced
 # shapes the planner cuts the large systems into j parts whose slots and unit table reach the
 # limits of the workspace layout (a unit table once sized below the planner's maximum made such
-# launches fault; the CPU test of the planner checks the layout for every occupancy); the last
-# shape aims at 64 work units per wave, the most parts the planner makes.
-@pytest.mark.parametrize("shape", [None, (256, 1, 256, 8, 0), (256, 2, 256, 8, 1), (128, 1, 64, 64, 1)])
+# launches fault; the CPU test of the planner checks the layout for every occupancy); the fourth
+# shape aims at 64 work units per wave, the most parts the planner makes, and the last runs the
+# symmetric tiles (each unordered pair of a system once).
+@pytest.mark.parametrize("shape", [None, (256, 1, 256, 8, 0), (256, 2, 256, 8, 1), (128, 1, 64, 64, 1),
+                                   (256, 4, 256, 1, 2)])
 def test_config4_full_ensemble(nb, full_ensemble, shape):
     off, pos, par, systems = full_ensemble
     S = len(systems)

@@ -106,14 +106,24 @@ SIZES_A = [700, 0, 3000, 45, 1800, 9000, 128, 2500, 64, 6000]
 SIZES_B = [300, 1200, 65, 2000]
 
 
-@pytest.mark.parametrize("prec", ["fp32_kahan", "fp64"])
-def test_forces_batched_replay(nb, prec):
+@pytest.mark.parametrize("prec,shape", [("fp32_kahan", None), ("fp64", None), ("fp32_kahan", (256, 4, 256, 1, 2))])
+def test_forces_batched_replay(nb, prec, shape):
     """The batched forward keeps each ensemble's plan tables in device memory after its
     first launch, so later launches copy nothing from the host and can be captured.
     Between replays the same workspace serves another ensemble eagerly."""
-    off, X, P = _ensemble(SIZES_A, 81)
+    # the symmetric tiles take systems of up to 8192 particles
+    off, X, P = _ensemble(SIZES_A if shape is None else [s if s <= 8192 else 8000 for s in SIZES_A], 81)
     offb, Xb, Pb = _ensemble(SIZES_B, 82)
     law = nb.ljc_linear(prec)
+    if shape is not None:                    # the symmetric tiles
+        nb.set_config(nb.API_BATCHED, *shape)
+    try:
+        _replay_batched(nb, off, X, P, offb, Xb, Pb, law)
+    finally:
+        nb.clear_config(nb.API_BATCHED)
+
+
+def _replay_batched(nb, off, X, P, offb, Xb, Pb, law):
     f_ref, p_ref = nb.forces_batched(off, X, P, law)
     fb_ref, _ = nb.forces_batched(offb, Xb, Pb, law)
     torch.cuda.synchronize()

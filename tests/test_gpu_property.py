@@ -178,13 +178,15 @@ def ensemble(law, sizes, seed):
        block=st.sampled_from([64, 128, 256]),
        ipl=st.sampled_from([1, 2, 4]),
        j_tile=st.sampled_from([64, 256]),
-       j_stage=st.sampled_from([0, 1]),
+       j_stage=st.sampled_from([0, 1, 2]),
        per_wave=st.sampled_from([1, 8, 64]),
        seed=st.integers(min_value=0, max_value=10 ** 6))
 def test_random_batches(nb, sizes, law, prec, block, ipl, j_tile, j_stage, per_wave, seed):
     """The persistent batched launch over random ensembles (empty and one-particle systems
     included) with a forced configuration equals the oracle system by system.  The work-unit
-    target per wave (the batched j_split) decides how far large systems are cut into parts."""
+    target per wave (the batched j_split) decides how far large systems are cut into parts;
+    j_stage 2 selects the symmetric tiles (gravity and LJC(linear) with FP32 pair arithmetic;
+    elsewhere it reads as 1)."""
     lw = gpu_law(nb, law, prec)
     off, x, par = ensemble(law, sizes, seed)
     try:
