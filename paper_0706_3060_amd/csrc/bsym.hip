@@ -242,10 +242,23 @@ __global__ __launch_bounds__(kBSymRecords) void k_bsym_reduce(BSymLaunch a)
     if (l >= a.off[s + 1] - o) return;
     const int64_t npad = a.poff[s + 1] - a.poff[s];
     const int64_t nb = npad / kBSymRecords;
-    const float4 *__restrict__ slots = a.partial + a.systab[3 * s + 2];
+    const float4 *__restrict__ slots = a.partial + a.systab[3 * s + 2] + l;
     NSum v[4];
-    for (int64_t k = 0; k < nb; ++k) {
-        const float4 x = slots[k * npad + l];
+    int64_t k = 0;
+    for (; k + 4 <= nb; k += 4) {            // four slots' loads in flight before their sums
+        float4 x[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[t] = slots[(k + t) * npad];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            v[0].add((double)x[t].x);
+            v[1].add((double)x[t].y);
+            v[2].add((double)x[t].z);
+            v[3].add((double)x[t].w);
+        }
+    }
+    for (; k < nb; ++k) {
+        const float4 x = slots[k * npad];
         v[0].add((double)x.x);
         v[1].add((double)x.y);
         v[2].add((double)x.z);
