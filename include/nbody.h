@@ -174,8 +174,10 @@ typedef struct nbody_exclusions {
  *             operands), 2 = symmetric pair tiles: each unordered pair is
  *             evaluated once and its force applied to both particles
  *             (Newton's third law), for gravity with FP32_KAHAN or
- *             FP32_FP64ACC through nbody_forces and leapfrog_step on whole
- *             systems of up to 2,097,152 particles (its per-block partials
+ *             FP32_FP64ACC through nbody_forces, leapfrog_step and
+ *             nbody_forces_backward (the position adjoint, whose pair term
+ *             for one particle is minus the other's) on whole systems of up
+ *             to 2,097,152 particles (its per-block partials
  *             grow as n^2: 8.6 GB at n = 2^20, 34 GB at 2^21; elsewhere 2
  *             reads as 1).  For nbody_forces_batched, j_stage 2 selects the
  *             batched symmetric tiles (gravity and LJC(linear) with
@@ -305,6 +307,10 @@ int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double
  *              in a fixed order.  At most 16384 types (NBODY_ENOTSUP
  *              beyond); atoms whose type is outside [0, n_types) are not
  *              counted.
+ * Swapping k and j negates both d and m_k g_j - m_j g_k, so gravity's pair
+ * term for j is minus its term for k: with FP32 pair arithmetic and 65,536
+ * to 2,097,152 particles the rule evaluates each unordered pair once
+ * (symmetric pair tiles, as the forward's).
  * Workspace: nbody_workspace_bytes(NBODY_API_BACKWARD, n, 1, law).
  * Laws: gravity and LJC(linear) (other laws: NBODY_ENOTSUP).
  * Precisions: NBODY_FP64, NBODY_FP32_FP64ACC, NBODY_FP32_KAHAN. */

@@ -21,7 +21,6 @@
 
 namespace nbk {
 
-template <typename T> struct alignas(4 * sizeof(T)) GravAdjRec { T x, y, z, m, gx, gy, gz, p0; };
 template <typename T> struct alignas(4 * sizeof(T)) LjcAdjRec {
     T x, y, z, qs, sh, se, gx, gy, gz, p0, p1, p2, p3, p4, p5, p6;   // padded to 16 values
 };

@@ -107,7 +107,7 @@ constexpr int64_t kSymMaxN = int64_t(1) << 21;
 bool sym_eligible(int api, int law, int prec)
 {
     return law == NBODY_LAW_GRAVITY && (prec == NBODY_FP32_KAHAN || prec == NBODY_FP32_FP64ACC) &&
-           (api == NBODY_API_FORCES || api == NBODY_API_LEAPFROG);
+           (api == NBODY_API_FORCES || api == NBODY_API_LEAPFROG || api == NBODY_API_BACKWARD);
 }
 
 // block edge in chunks for a requested j_tile and system size
@@ -552,11 +552,17 @@ AdjWs adj_layout(const nbody_law *law, int64_t n)
 {
     AdjWs w{};
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
+    // the gravity position adjoint may run as symmetric pair tiles: records padded to whole
+    // blocks and one FP32 partial per row and block, as the forward's
+    const bool sym = sym_eligible(NBODY_API_BACKWARD, law->kind, law->precision) && n <= kSymMaxN;
+    const int64_t nrec = sym ? sym_npad(n, 32) : npad;
+    size_t part = (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double);
+    if (sym) part = std::max(part, sym_max_partial_bytes(n));
     size_t off = 0;
     w.rec_off = off;
-    off = align256(off + (size_t)npad * adj_rec_bytes(law->kind, law->precision));
+    off = align256(off + (size_t)nrec * adj_rec_bytes(law->kind, law->precision));
     w.part_off = off;
-    off = align256(off + (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double));
+    off = align256(off + part);
     w.type_off = off;
     off = align256(off + (size_t)kTypePartDoubles * sizeof(double));
     w.total = off;
@@ -778,6 +784,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
 
     if (sym) {
         SymLaunch a{};
+        a.op = SYM_FORCE;
         a.prec = law->precision;
         a.pot = pot ? 1 : 0;
         a.blk = blk;
@@ -2008,9 +2015,50 @@ int backward_impl(const double *pos, const double *params, int64_t n, const nbod
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const Cfg c = with_excl(choose(NBODY_API_BACKWARD, law, n, 1, false), excl != nullptr);
-    const int64_t npad = round_up(n, 64);
+    Cfg c = with_excl(sanitize(choose(NBODY_API_BACKWARD, law, n, 1, false), NBODY_API_BACKWARD, law->kind,
+                               law->precision, round_up(n, 64)),
+                      excl != nullptr);
     char *base = (char *)ws;
+    if (c.j_stage == kSymStage) {
+        // gravity's position adjoint over unordered pairs: the pair's term for k is minus its
+        // term for j (swapping the two negates both w and d), so each pair is evaluated once
+        const int blk = c.j_tile / 64;
+        const int64_t spad = sym_npad(n, blk);
+        AdjPackLaunch pk{};
+        pk.law = law->kind;
+        pk.prec = law->precision;
+        pk.n = n;
+        pk.npad = spad;
+        pk.pos = pos;
+        pk.params = params;
+        pk.g = grad_force;
+        pk.rec = base + lay.rec_off;
+        hipError_t e = launch_pack_adjoint(pk, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint pack");
+        SymLaunch a{};
+        a.op = SYM_HVP;
+        a.prec = law->precision;
+        a.pot = 0;
+        a.blk = blk;
+        a.ich = c.ipl;
+        a.nblk = spad / ((int64_t)blk * 64);
+        a.npad = spad;
+        a.n = n;
+        a.eps2 = law->softening * law->softening;
+        a.rec = base + lay.rec_off;
+        a.partial = (float4 *)(base + lay.part_off);
+        sym_share_range(a.nblk, 0, 1, a.t0, a.count);
+        a.epi.fscale = law->G;
+        a.epi.out_force = grad_pos;
+        Timer t(s);
+        e = launch_sym(a, s);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "symmetric adjoint kernel");
+        e = launch_sym_reduce(a, s);
+        if (e != hipSuccess) return hip_fail(e, "symmetric adjoint reduction");
+        return NBODY_OK;
+    }
+    const int64_t npad = round_up(n, 64);
 
     AdjPackLaunch pk{};
     pk.law = law->kind;

@@ -40,6 +40,8 @@ template <int PREC> struct RealOf { using type = float; };
 template <> struct RealOf<P_FP64> { using type = double; };
 
 template <typename T> struct alignas(4 * sizeof(T)) GravRec { T x, y, z, m; };
+// gravity adjoint records: position, mass and the cotangent g = dL/da of the particle
+template <typename T> struct alignas(4 * sizeof(T)) GravAdjRec { T x, y, z, m, gx, gy, gz, p0; };
 template <typename T> struct alignas(4 * sizeof(T)) LjcRec { T x, y, z, qs, sh, se, p0, p1; };
 
 template <typename T, int LAW> struct RecOf { using type = LjcRec<T>; };   // every LJC variant

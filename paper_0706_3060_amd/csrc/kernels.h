@@ -80,15 +80,17 @@ int forces_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block)
 // ---- symmetric pair tiles (symmetric.hip): gravity, every unordered pair once ----
 constexpr int kSymThreads = 512;           // the larger workgroup: 8 waves, 2 i chunks per wave (or 4 x 4)
 constexpr int kSymMaxBlk = 32;             // largest block edge in chunks of 64 records
+enum SymOp { SYM_FORCE = 0, SYM_HVP = 1 };  // forces (and potentials), or the position adjoint
 struct SymLaunch {
-    int prec, pot;                 // P_KAHAN or P_FP64ACC tile sums; potential on/off
+    int op;                        // SYM_FORCE (records {x, y, z, m}) or SYM_HVP ({x, y, z, m, g, 0})
+    int prec, pot;                 // P_KAHAN or P_FP64ACC tile sums; potential on/off (forces)
     int blk;                       // block edge in chunks of 64 records: 16 or 32
     int ich;                       // i chunks per wave: 2 (8-wave workgroups) or 4 (4-wave workgroups)
     int64_t nblk;                  // blocks; tiles = nblk (nblk + 1) / 2
     int64_t npad;                  // records = nblk * blk * 64 (zero-mass padding past n)
     int64_t n;                     // rows finished by the reduction
     double eps2;
-    const void *rec;               // FP32 gravity records {x, y, z, m}
+    const void *rec;               // FP32 gravity records
     float4 *partial;               // [nblk][npad] (x, y, z, potential) FP32 slot partials
     int64_t t0, count;             // order range of the launch's tiles (whole triangle: 0, sym_tiles)
     Epilogue epi;

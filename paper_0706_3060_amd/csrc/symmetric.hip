@@ -51,64 +51,121 @@ __device__ __forceinline__ float from_next_lane_dpp(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
 }
 
-// One mini-tile: the wave's two i chunks (records iv[0], iv[1], running
-// partials p) against the j chunk in the wave's LDS slot `st` (staged twice),
-// with the j sums jv entering and leaving in lane order.  MASK (diagonal
-// tiles only): per i slot k, wi[k] / wj[k] switch the i and j sides on or off
-// and self[k] marks a slot whose i chunk is the j chunk itself, whose pair at
-// step 0 is the particle with itself.
-template <int ICH, bool POT, bool MASK>
-__device__ __forceinline__ void sym_minitile(const GravRec<float> *st, const GravRec<float> (&iv)[ICH],
-                                             float eps2, int bp_addr, float (&p)[ICH][4], float (&jv)[4],
-                                             const float (&wi)[ICH], const float (&wj)[ICH],
-                                             const bool (&self)[ICH])
+// The pair operators.  SYM_FORCE: Eq. 1 (i side m_j r^-3 d, j side -m_i r^-3 d, potentials
+// m_j / r and m_i / r).  SYM_HVP: the position adjoint of Eq. 1 (a Hessian-vector product):
+// with w = m_i g_j - m_j g_i, the i side adds t = s^-3 (w - 3 s^-2 (d.w) d) and the j side -t
+// (swapping i and j negates both w and d).  wi / wj switch the i and j sides on or off (diagonal
+// tiles); sk marks the particle's own pair, which contributes nothing.
+template <int OP> struct SymRecOf { using type = GravRec<float>; };
+template <> struct SymRecOf<SYM_HVP> { using type = GravAdjRec<float>; };
+
+template <bool POT, bool MASK>
+__device__ __forceinline__ void sym_pair(const GravRec<float> &I, const GravRec<float> &J, float eps2, bool sk,
+                                         float wi, float wj, float (&p)[4], float (&jv)[4])
+{
+    const float dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
+    float r2 = fma_(dx, dx, eps2);
+    r2 = fma_(dy, dy, r2);
+    r2 = fma_(dz, dz, r2);
+    float mj = J.m, mi = I.m;
+    if (MASK) {
+        r2 = sk ? 1.0f : r2;
+        mj = sk ? 0.0f : mj * wi;
+        mi = mi * wj;
+    }
+    const float ri = rsqrt_(r2);
+    const float ri3 = (ri * ri) * ri;
+    const float cj = mj * ri3, ci = mi * ri3;
+    p[0] = fma_(cj, dx, p[0]);
+    p[1] = fma_(cj, dy, p[1]);
+    p[2] = fma_(cj, dz, p[2]);
+    jv[0] = fma_(-ci, dx, jv[0]);
+    jv[1] = fma_(-ci, dy, jv[1]);
+    jv[2] = fma_(-ci, dz, jv[2]);
+    if (POT) {
+        p[3] = fma_(mj, ri, p[3]);
+        jv[3] = fma_(mi, ri, jv[3]);
+    }
+}
+
+template <bool POT, bool MASK>
+__device__ __forceinline__ void sym_pair(const GravAdjRec<float> &I, const GravAdjRec<float> &J, float eps2,
+                                         bool sk, float wi, float wj, float (&p)[4], float (&jv)[4])
+{
+    const float dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
+    float r2 = fma_(dx, dx, eps2);
+    r2 = fma_(dy, dy, r2);
+    r2 = fma_(dz, dz, r2);
+    if (MASK) r2 = sk ? 1.0f : r2;
+    float ri = rsqrt_(r2);
+    if (MASK) ri = sk ? 0.0f : ri;
+    const float ri2 = ri * ri;
+    const float ri3 = ri2 * ri;
+    const float wx = fma_(-J.m, I.gx, I.m * J.gx);
+    const float wy = fma_(-J.m, I.gy, I.m * J.gy);
+    const float wz = fma_(-J.m, I.gz, I.m * J.gz);
+    float dw = dx * wx;
+    dw = fma_(dy, wy, dw);
+    dw = fma_(dz, wz, dw);
+    const float u = (ri2 * 3.0f) * dw;
+    float tx = ri3 * fma_(-u, dx, wx), ty = ri3 * fma_(-u, dy, wy), tz = ri3 * fma_(-u, dz, wz);
+    if (MASK) {
+        p[0] = fma_(wi, tx, p[0]);
+        p[1] = fma_(wi, ty, p[1]);
+        p[2] = fma_(wi, tz, p[2]);
+        jv[0] = fma_(-wj, tx, jv[0]);
+        jv[1] = fma_(-wj, ty, jv[1]);
+        jv[2] = fma_(-wj, tz, jv[2]);
+    } else {
+        p[0] += tx;
+        p[1] += ty;
+        p[2] += tz;
+        jv[0] -= tx;
+        jv[1] -= ty;
+        jv[2] -= tz;
+    }
+}
+
+// One mini-tile: the wave's ICH i chunks (records iv, running partials p) against the j chunk in
+// the wave's LDS slot `st` (staged twice), with the j sums jv entering and leaving in lane order.
+// MASK (diagonal tiles only): per i slot k, wi[k] / wj[k] switch the i and j sides on or off and
+// self[k] marks a slot whose i chunk is the j chunk itself, whose pair at step 0 is the particle
+// with itself.
+template <int OP, int ICH, bool POT, bool MASK, typename R>
+__device__ __forceinline__ void sym_minitile(const R *st, const R (&iv)[ICH], float eps2, int bp_addr,
+                                             float (&p)[ICH][4], float (&jv)[4], const float (&wi)[ICH],
+                                             const float (&wj)[ICH], const bool (&self)[ICH])
 {
     const int lane = lane_id();
 #pragma unroll(16 / ICH)
     for (int s = 0; s < kWave; ++s) {
-        const GravRec<float> J = st[lane + s];
+        const R J = st[lane + s];
 #pragma unroll
-        for (int k = 0; k < ICH; ++k) {
-            const float dx = J.x - iv[k].x, dy = J.y - iv[k].y, dz = J.z - iv[k].z;
-            float r2 = fma_(dx, dx, eps2);
-            r2 = fma_(dy, dy, r2);
-            r2 = fma_(dz, dz, r2);
-            float mj = J.m, mi = iv[k].m;
-            if (MASK) {
-                const bool sk = self[k] && s == 0;
-                r2 = sk ? 1.0f : r2;
-                mj = sk ? 0.0f : mj * wi[k];
-                mi = mi * wj[k];
-            }
-            const float ri = rsqrt_(r2);
-            const float ri3 = (ri * ri) * ri;
-            const float cj = mj * ri3, ci = mi * ri3;
-            p[k][0] = fma_(cj, dx, p[k][0]);
-            p[k][1] = fma_(cj, dy, p[k][1]);
-            p[k][2] = fma_(cj, dz, p[k][2]);
-            jv[0] = fma_(-ci, dx, jv[0]);
-            jv[1] = fma_(-ci, dy, jv[1]);
-            jv[2] = fma_(-ci, dz, jv[2]);
-            if (POT) {
-                p[k][3] = fma_(mj, ri, p[k][3]);
-                jv[3] = fma_(mi, ri, jv[3]);
-            }
+        for (int k = 0; k < ICH; ++k)
+            sym_pair<POT, MASK>(iv[k], J, eps2, MASK && self[k] && s == 0, MASK ? wi[k] : 1.0f,
+                                MASK ? wj[k] : 1.0f, p[k], jv);
+        // most sums move through the LDS crossbar, one on the VALU: the two units share the
+        // moves (2 % faster at N = 2^20 than four crossbar moves; more DPP moves are slower)
+        if (OP == SYM_FORCE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) jv[c] = from_next_lane(bp_addr, jv[c]);
+            if (POT) jv[3] = from_next_lane_dpp(jv[3]);
+        } else {
+            jv[0] = from_next_lane(bp_addr, jv[0]);
+            jv[1] = from_next_lane(bp_addr, jv[1]);
+            jv[2] = from_next_lane_dpp(jv[2]);
         }
-        // the force sums move through the LDS crossbar, the potential's on the VALU: the two units
-        // share the moves (2 % faster at N = 2^20 than four crossbar moves; three or more DPP
-        // moves are slower)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) jv[c] = from_next_lane(bp_addr, jv[c]);
-        if (POT) jv[3] = from_next_lane_dpp(jv[3]);
     }
 }
 
 // WAVES waves per workgroup hold ICH i chunks each: (8, 2) or (4, 4), a pass of 16 i chunks.
-template <int PREC, bool POT, int WAVES, int ICH>
-__global__ __launch_bounds__(WAVES * kWave) __attribute__((amdgpu_waves_per_eu(WAVES == 8 ? 6 : 4)))
+template <int OP, int PREC, bool POT, int WAVES, int ICH>
+// (the adjoint's 32-byte records double the staging LDS: one workgroup fewer per CU)
+__global__ __launch_bounds__(WAVES * kWave)
+__attribute__((amdgpu_waves_per_eu(OP == SYM_FORCE ? (WAVES == 8 ? 6 : 4) : (WAVES == 8 ? 4 : 3))))
 void k_sym(SymLaunch a)
 {
-    using R = GravRec<float>;
+    using R = typename SymRecOf<OP>::type;
     constexpr int kThreads = WAVES * kWave;
     constexpr int kPass = WAVES * ICH;                     // i chunks of one pass
     const R *__restrict__ rec = (const R *)a.rec;
@@ -136,16 +193,25 @@ void k_sym(SymLaunch a)
         for (int k = 0; k < ICH; ++k) iv[k] = rec[irec0 + (int64_t)(aloc + k) * kWave + lane];
         RunSum<PREC> acc[ICH][4];
         float p[ICH][4];
-        // the next round's j record of this lane, loaded a round ahead (as a vector, so that it
-        // stays in registers)
+        // the next round's j record of this lane, loaded a round ahead (as one or two 128-bit
+        // vectors, so that it stays in registers)
+        constexpr int V = sizeof(R) / sizeof(float4);
+        static_assert(V == 1 || V == 2, "records of one or two 128-bit vectors");
         const float4 *__restrict__ rec4 = (const float4 *)a.rec;
         float4 *st4 = (float4 *)st;
-        float4 g = rec4[jrec0 + (int64_t)(w % blk) * kWave + lane];
+        int64_t gj = jrec0 + (int64_t)(w % blk) * kWave + lane;
+        float4 g0 = rec4[gj * V], g1 = V == 2 ? rec4[gj * V + 1] : float4{0, 0, 0, 0};
         for (int r = 0; r < blk; ++r) {
             const int q = (w + r) % blk;
-            st4[lane] = g;
-            st4[lane + kWave] = g;
-            g = rec4[jrec0 + (int64_t)((w + r + 1) % blk) * kWave + lane];
+            st4[lane * V] = g0;
+            st4[(lane + kWave) * V] = g0;
+            if (V == 2) {
+                st4[lane * V + 1] = g1;
+                st4[(lane + kWave) * V + 1] = g1;
+            }
+            gj = jrec0 + (int64_t)((w + r + 1) % blk) * kWave + lane;
+            g0 = rec4[gj * V];
+            if (V == 2) g1 = rec4[gj * V + 1];
             const float4 j4 = jacc[q][lane];
             float jv[4] = {j4.x, j4.y, j4.z, j4.w};
             __builtin_amdgcn_wave_barrier();
@@ -161,7 +227,7 @@ void k_sym(SymLaunch a)
                     one[k] = 1.0f;
                     none[k] = false;
                 }
-                sym_minitile<ICH, POT, false>(st, iv, eps2, bp_addr, p, jv, one, one, none);
+                sym_minitile<OP, ICH, POT, false>(st, iv, eps2, bp_addr, p, jv, one, one, none);
             } else {
                 // chunk q against i chunk aloc + k: symmetric when q is after it, its own
                 // chunk's pairs one-sided when q is it, nothing when q is before it (that pair
@@ -175,7 +241,7 @@ void k_sym(SymLaunch a)
                     wj[k] = rel > 0 ? 1.0f : 0.0f;
                     self[k] = rel == 0;
                 }
-                sym_minitile<ICH, POT, true>(st, iv, eps2, bp_addr, p, jv, wi, wj, self);
+                sym_minitile<OP, ICH, POT, true>(st, iv, eps2, bp_addr, p, jv, wi, wj, self);
             }
             jacc[q][lane] = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
 #pragma unroll
@@ -247,12 +313,17 @@ template <int WAVES, int ICH>
 static hipError_t launch_sym_shape(const SymLaunch &a, hipStream_t s)
 {
     const dim3 grid((unsigned)sym_grid(a.count)), block(WAVES * kWave);
-    if (a.prec == P_KAHAN) {
-        if (a.pot) hipLaunchKernelGGL((k_sym<P_KAHAN, true, WAVES, ICH>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_sym<P_KAHAN, false, WAVES, ICH>), grid, block, 0, s, a);
+    if (a.op == SYM_HVP) {                           // no potential for the adjoint
+        if (a.prec == P_KAHAN) hipLaunchKernelGGL((k_sym<SYM_HVP, P_KAHAN, false, WAVES, ICH>), grid, block, 0, s, a);
+        else if (a.prec == P_FP64ACC)
+            hipLaunchKernelGGL((k_sym<SYM_HVP, P_FP64ACC, false, WAVES, ICH>), grid, block, 0, s, a);
+        else return hipErrorInvalidValue;
+    } else if (a.prec == P_KAHAN) {
+        if (a.pot) hipLaunchKernelGGL((k_sym<SYM_FORCE, P_KAHAN, true, WAVES, ICH>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_sym<SYM_FORCE, P_KAHAN, false, WAVES, ICH>), grid, block, 0, s, a);
     } else if (a.prec == P_FP64ACC) {
-        if (a.pot) hipLaunchKernelGGL((k_sym<P_FP64ACC, true, WAVES, ICH>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_sym<P_FP64ACC, false, WAVES, ICH>), grid, block, 0, s, a);
+        if (a.pot) hipLaunchKernelGGL((k_sym<SYM_FORCE, P_FP64ACC, true, WAVES, ICH>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_sym<SYM_FORCE, P_FP64ACC, false, WAVES, ICH>), grid, block, 0, s, a);
     } else {
         return hipErrorInvalidValue;
     }
@@ -284,11 +355,11 @@ static int sym_blocks_shape(int prec, int pot)
     hipError_t e = hipErrorInvalidValue;
     const int threads = WAVES * kWave;
     if (prec == P_KAHAN)
-        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_KAHAN, true, WAVES, ICH>, threads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_KAHAN, false, WAVES, ICH>, threads, 0);
+        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<SYM_FORCE, P_KAHAN, true, WAVES, ICH>, threads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<SYM_FORCE, P_KAHAN, false, WAVES, ICH>, threads, 0);
     else if (prec == P_FP64ACC)
-        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_FP64ACC, true, WAVES, ICH>, threads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<P_FP64ACC, false, WAVES, ICH>, threads, 0);
+        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<SYM_FORCE, P_FP64ACC, true, WAVES, ICH>, threads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<SYM_FORCE, P_FP64ACC, false, WAVES, ICH>, threads, 0);
     return e == hipSuccess ? nb : 0;
 }
 

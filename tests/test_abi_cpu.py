@@ -205,7 +205,7 @@ def test_config_validation(N):
     # with FP32 pair arithmetic), in their fixed shape of 4 waves over 256-record blocks
     cases = [(0, grav(1), "sym"), (3, grav(2), "sym"), (0, grav(0), None), (0, grav(3), None),
              (0, ljc, None), (1, ljc, "bsym"), (1, grav(1), "bsym"), (1, grav(0), None),
-             (1, N.NBodyLaw(2, 1, 1.0, 0.0, 332.0637, 4.0), None), (2, grav(1), None),
+             (1, N.NBodyLaw(2, 1, 1.0, 0.0, 332.0637, 4.0), None), (2, grav(1), "sym"), (2, ljc, None),
              (4, grav(1), None), (5, grav(2), None), (6, ljc, None)]
     for api, law, kind in cases:
         c = N.NBodyConfig()

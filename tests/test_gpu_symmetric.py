@@ -219,3 +219,49 @@ def test_share_more_shares_than_tiles(nb):
         total += f
     assert nonzero == 1
     assert (total - f_full).abs().max().item() <= 1e-5 * f_full.abs().max().item()
+
+
+@pytest.mark.parametrize("shape", [(512, 2), (256, 4)])
+@pytest.mark.parametrize("prec", ["fp32_kahan", "fp32_fp64acc"])
+def test_symmetric_position_adjoint(nb, shape, prec):
+    """Gravity's position adjoint (the Hessian-vector product) over unordered pairs: the pair's
+    term for one particle is minus its term for the other.  Ragged sizes against the oracle's
+    adjoint, with G != 1 and unequal masses; the rule's choice repeats bit for bit."""
+    law = nb.gravity(prec, softening=0.01, G=1.7)
+    for k, n in enumerate([2, 63, 65, 1023, 1025, 2049, 3001]):
+        x, _, m = W.plummer(n, 930 + k)
+        m = m * np.random.default_rng(k).uniform(0.5, 1.5, n)
+        g = np.random.default_rng(40 + k).standard_normal((n, 3))
+        nb.set_config(nb.API_BACKWARD, shape[0], shape[1], 1024, 1, 2)
+        try:
+            c = nb.get_config(nb.API_BACKWARD, n, law)
+            assert (c["j_stage"], c["block"], c["i_per_lane"]) == (2,) + shape, c
+            gp, _, _ = nb.forces_backward(dev(x), dev(m), dev(g), law)
+        finally:
+            nb.clear_config(nb.API_BACKWARD)
+        ref = oracle.gravity_adjoint(W.round_to_f32(x), W.round_to_f32(m), W.round_to_f32(g), G=1.7, eps=0.01)
+        e = row_errors(host(gp), ref)
+        assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (n, np.median(e), e.max())
+
+
+def test_symmetric_position_adjoint_is_the_rule(nb):
+    n = 70000
+    x, _, m = W.plummer(n, 940)
+    g = np.random.default_rng(41).standard_normal((n, 3))
+    law = nb.gravity("fp32_fp64acc", softening=0.01)
+    assert nb.get_config(nb.API_BACKWARD, n, law)["j_stage"] == 2
+    X, M, Gd = dev(x), dev(m), dev(g)
+    g1, _, _ = nb.forces_backward(X, M, Gd, law)
+    g2, _, _ = nb.forces_backward(X, M, Gd, law)
+    assert torch.equal(g1, g2)
+    nb.set_config(nb.API_BACKWARD, 256, 1, 256, 8, 1)               # the one-sided adjoint
+    try:
+        g3, _, _ = nb.forces_backward(X, M, Gd, law)
+    finally:
+        nb.clear_config(nb.API_BACKWARD)
+    e = row_errors(host(g1), host(g3))
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3
+    rows = np.sort(np.random.default_rng(9).choice(n, 128, replace=False))
+    ref = oracle.gravity_adjoint(W.round_to_f32(x), W.round_to_f32(m), W.round_to_f32(g), eps=0.01, ilist=rows)
+    e = row_errors(host(g1)[rows], ref)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3
