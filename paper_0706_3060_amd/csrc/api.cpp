@@ -89,14 +89,15 @@ int max_split_rows(int64_t rows, int64_t nj)
 int max_split(int64_t npad) { return npad <= 0 ? 1 : max_split_rows(npad, npad); }
 
 // ------------------------------------------------------ symmetric tiles
-// j_stage 2 selects the symmetric pair tiles (symmetric.hip): gravity with FP32
-// pair arithmetic and Kahan or FP64 tile sums, whole systems (the forces and
-// leapfrog entry points).  j_tile is the block edge in records, 1024 (16 chunks,
-// for N up to kSymSmallMax) or 2048 (32 chunks); the workgroup shape is fixed
-// (512 threads, 2 rows per lane).  Each row gets one FP32 partial per block, so
-// the partial buffer is npad^2 / (64 blk) x 16 bytes (8 GiB at N = 2^20); above
-// kSymMaxN (32 GiB of partials) the one-sided kernels, whose partials are O(N),
-// take over.
+// j_stage 2 selects the symmetric pair tiles (symmetric.hip): gravity (forces,
+// leapfrog, the position adjoint) or LJC with the linear dielectric (forces,
+// leapfrog), FP32 pair arithmetic and Kahan or FP64 tile sums, whole systems.
+// j_tile is the block edge in records, 1024 (16 chunks, for N up to
+// kSymSmallMax) or 2048 (32 chunks); ipl picks the workgroup shape (2: 512
+// threads of 2 i chunks per wave, 4: 256 threads of 4).  Each row gets one FP32
+// partial per block, so the partial buffer is npad^2 / (64 blk) x 16 bytes
+// (8 GiB at N = 2^20); above kSymMaxN (32 GiB of partials) the one-sided
+// kernels, whose partials are O(N), take over.
 constexpr int kBatchUnitsPerWave = 8;    // the rule's work units per resident wave (batched j_split)
 constexpr int kBSymWaves = 4;            // waves (one tile each) per workgroup of the batched symmetric tiles
 constexpr int kSymStage = 2;
@@ -106,8 +107,10 @@ constexpr int64_t kSymMaxN = int64_t(1) << 21;
 
 bool sym_eligible(int api, int law, int prec)
 {
-    return law == NBODY_LAW_GRAVITY && (prec == NBODY_FP32_KAHAN || prec == NBODY_FP32_FP64ACC) &&
-           (api == NBODY_API_FORCES || api == NBODY_API_LEAPFROG || api == NBODY_API_BACKWARD);
+    if (prec != NBODY_FP32_KAHAN && prec != NBODY_FP32_FP64ACC) return false;
+    const bool fwd = api == NBODY_API_FORCES || api == NBODY_API_LEAPFROG;
+    if (law == NBODY_LAW_GRAVITY) return fwd || api == NBODY_API_BACKWARD;
+    return law == NBODY_LAW_LJC_LINEAR && fwd;
 }
 
 // block edge in chunks for a requested j_tile and system size
@@ -336,9 +339,10 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         c.j_stage = kSymStage;
         c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
         // 4 waves of 4 i chunks (half the cross-lane moves per pair, 4 waves per SIMD) against
-        // 8 waves of 2 (6 waves per SIMD): measured 5-7 % faster with the potential, and from
-        // N = 2^17 without it
-        const bool four = pot || n > (int64_t(1) << 17);
+        // 8 waves of 2 (6 waves per SIMD): for gravity measured 5-7 % faster with the
+        // potential, and from N = 2^17 without it; for LJC as fast with the energies and
+        // 15-20 % faster without them
+        const bool four = law != NBODY_LAW_GRAVITY || pot || n > (int64_t(1) << 17);
         c.ipl = four ? 4 : 2;
         c.block = four ? 256 : kSymThreads;
         return sanitize(c, api, law, prec, round_up(n, 64));
@@ -764,7 +768,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
                 int64_t n_shares = 1)
 {
     // the symmetric tiles (j_stage 2) evaluate whole systems; sanitize admits the
-    // configuration only for gravity with FP32_KAHAN / FP32_FP64ACC
+    // configuration only for gravity and LJC(linear) with FP32_KAHAN / FP32_FP64ACC
     const bool sym = c.j_stage == kSymStage && rows == nullptr && nrows == n && excl.off == nullptr;
     const int blk = sym ? c.j_tile / 64 : 0;
     const int64_t npad = sym ? sym_npad(n, blk) : round_up(n, 64);
@@ -784,7 +788,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
 
     if (sym) {
         SymLaunch a{};
-        a.op = SYM_FORCE;
+        a.op = law->kind == NBODY_LAW_GRAVITY ? SYM_FORCE : SYM_LJC;
         a.prec = law->precision;
         a.pot = pot ? 1 : 0;
         a.blk = blk;
@@ -792,7 +796,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
         a.nblk = npad / ((int64_t)blk * 64);
         a.npad = npad;
         a.n = n;
-        a.eps2 = law->softening * law->softening;
+        a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
         a.rec = base + lay.rec_off;
         a.partial = (float4 *)(base + lay.part_off);
         sym_share_range(a.nblk, share, n_shares, a.t0, a.count);
@@ -1502,7 +1506,7 @@ int forces_impl(const double *pos, const double *params, int64_t n, const int64_
                        pot, ws, lay, (hipStream_t)stream, nullptr, excl_args(excl));
 }
 
-// One share of the symmetric pair tiles (gravity, FP32 pair arithmetic): the tiles of order
+// One share of the symmetric pair tiles (gravity or LJC(linear), FP32 pair arithmetic): the tiles of order
 // range share / n_shares of the triangle, reduced into per-row partial sums of all n rows.
 int share_impl(const double *pos, const double *params, int64_t n, const nbody_law *law, int32_t share,
                int32_t n_shares, double *out_force, double *out_potential, void *ws, size_t ws_bytes,
@@ -1511,8 +1515,9 @@ int share_impl(const double *pos, const double *params, int64_t n, const nbody_l
     int rc = validate_law(law, false);
     if (rc) return rc;
     if (!sym_eligible(NBODY_API_FORCES, law->kind, law->precision))
-        return fail(NBODY_ENOTSUP, "shares of the symmetric pair tiles are provided for gravity with "
-                    "FP32_KAHAN or FP32_FP64ACC (other laws shard by rows: nbody_forces_subset)");
+        return fail(NBODY_ENOTSUP, "shares of the symmetric pair tiles are provided for gravity and "
+                    "LJC(linear) with FP32_KAHAN or FP32_FP64ACC (other laws shard by rows: "
+                    "nbody_forces_subset)");
     if (n < 0) return fail(NBODY_EINVAL, "n < 0");
     if (n > kSymMaxN) return fail(NBODY_ENOTSUP, "the symmetric pair tiles take up to %lld particles",
                                   (long long)kSymMaxN);

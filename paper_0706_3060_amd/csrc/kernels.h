@@ -77,12 +77,14 @@ hipError_t launch_forces(const FwdLaunch &f, hipStream_t s);
 hipError_t launch_reduce_split(const FwdLaunch &f, hipStream_t s);
 int forces_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block);
 
-// ---- symmetric pair tiles (symmetric.hip): gravity, every unordered pair once ----
+// ---- symmetric pair tiles (symmetric.hip): gravity and LJC(linear), every unordered pair once ----
 constexpr int kSymThreads = 512;           // the larger workgroup: 8 waves, 2 i chunks per wave (or 4 x 4)
 constexpr int kSymMaxBlk = 32;             // largest block edge in chunks of 64 records
-enum SymOp { SYM_FORCE = 0, SYM_HVP = 1 };  // forces (and potentials), or the position adjoint
+// gravity forces (and potentials), gravity's position adjoint, LJC(linear) forces (and energies)
+enum SymOp { SYM_FORCE = 0, SYM_HVP = 1, SYM_LJC = 2 };
 struct SymLaunch {
-    int op;                        // SYM_FORCE (records {x, y, z, m}) or SYM_HVP ({x, y, z, m, g, 0})
+    int op;                        // SYM_FORCE ({x, y, z, m}), SYM_HVP ({x, y, z, m, g, 0}) or SYM_LJC
+                                   // ({x, y, z, qs, sh, se, 0, 0}) records
     int prec, pot;                 // P_KAHAN or P_FP64ACC tile sums; potential on/off (forces)
     int blk;                       // block edge in chunks of 64 records: 16 or 32
     int ich;                       // i chunks per wave: 2 (8-wave workgroups) or 4 (4-wave workgroups)
@@ -90,7 +92,7 @@ struct SymLaunch {
     int64_t npad;                  // records = nblk * blk * 64 (zero-mass padding past n)
     int64_t n;                     // rows finished by the reduction
     double eps2;
-    const void *rec;               // FP32 gravity records
+    const void *rec;               // FP32 records of the operator
     float4 *partial;               // [nblk][npad] (x, y, z, potential) FP32 slot partials
     int64_t t0, count;             // order range of the launch's tiles (whole triangle: 0, sym_tiles)
     Epilogue epi;
@@ -164,7 +166,6 @@ __host__ __device__ inline void sym_share_range(int64_t nblk, int64_t share, int
 }
 hipError_t launch_sym(const SymLaunch &a, hipStream_t s);
 hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s);
-int sym_blocks_per_cu(int prec, int pot, int ich);
 
 // ---- batched (one persistent launch over (system, row-block) work units) ----
 struct BatchLaunch {

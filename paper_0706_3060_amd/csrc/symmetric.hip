@@ -1,6 +1,9 @@
-// Symmetric all-pairs gravity: every unordered pair {i, j} is evaluated once
+// Symmetric all-pairs tiles: every unordered pair {i, j} is evaluated once
 // and its force is applied to both particles (Newton's third law), so one
-// reciprocal square root serves two interactions.
+// reciprocal square root (gravity) or reciprocal (LJC with the linear
+// dielectric) serves two interactions.  Three pair operators share the tiles:
+// gravity's forces and potentials, gravity's position adjoint, and LJC(linear)
+// forces and energies.
 //
 // Decomposition.  The padded records form nblk blocks of blk chunks of 64
 // (blk = 16 or 32).  Each workgroup takes one tile (b1, b2), b1 <= b2, of the
@@ -58,6 +61,7 @@ __device__ __forceinline__ float from_next_lane_dpp(float v)
 // tiles); sk marks the particle's own pair, which contributes nothing.
 template <int OP> struct SymRecOf { using type = GravRec<float>; };
 template <> struct SymRecOf<SYM_HVP> { using type = GravAdjRec<float>; };
+template <> struct SymRecOf<SYM_LJC> { using type = LjcRec<float>; };
 
 template <bool POT, bool MASK>
 __device__ __forceinline__ void sym_pair(const GravRec<float> &I, const GravRec<float> &J, float eps2, bool sk,
@@ -126,6 +130,60 @@ __device__ __forceinline__ void sym_pair(const GravAdjRec<float> &I, const GravA
     }
 }
 
+// SYM_LJC: Table 1's LJC(linear), symmetric in its two particles: F_i += W (r_i - r_j) and
+// F_j -= W (r_i - r_j) with one W, and both energy sums get the pair's 2 u (halved by the
+// epilogue), as the one-sided ljc_pair computes them.
+template <bool POT, bool MASK>
+__device__ __forceinline__ void sym_pair(const LjcRec<float> &I, const LjcRec<float> &J, float, bool sk, float wi,
+                                         float wj, float (&p)[4], float (&jv)[4])
+{
+    const float dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
+    float r2 = dx * dx;
+    r2 = fma_(dy, dy, r2);
+    r2 = fma_(dz, dz, r2);
+    float qq = I.qs * J.qs;
+    float e = I.se * J.se;
+    if (MASK) {
+        r2 = sk ? 1.0f : r2;
+        qq = sk ? 0.0f : qq;
+        e = sk ? 0.0f : e;
+    }
+    const float x = rcp_(r2);
+    const float cx = qq * x;
+    const float sg = I.sh + J.sh;
+    const float s2 = (sg * sg) * x;
+    const float s6 = (s2 * s2) * s2;
+    const float lj = e * s6;                       // 24 eps_ij (sigma_ij / r)^6
+    const float t = fma_(s6, 2.0f, -1.0f);
+    const float W = fma_(lj, t, cx) * x;           // (24 eps_ij (2 s^12 - s^6) + qq x) / r^2
+    float u = 0.0f;
+    if (POT) u = fma_(fma_(lj, s6, -lj), 1.0f / 3.0f, cx);   // 2 u_ij
+    if (MASK) {
+        const float Wi = W * wi, Wj = W * wj;
+        p[0] = fma_(-Wi, dx, p[0]);
+        p[1] = fma_(-Wi, dy, p[1]);
+        p[2] = fma_(-Wi, dz, p[2]);
+        jv[0] = fma_(Wj, dx, jv[0]);
+        jv[1] = fma_(Wj, dy, jv[1]);
+        jv[2] = fma_(Wj, dz, jv[2]);
+        if (POT) {
+            p[3] = fma_(u, wi, p[3]);
+            jv[3] = fma_(u, wj, jv[3]);
+        }
+    } else {
+        p[0] = fma_(-W, dx, p[0]);
+        p[1] = fma_(-W, dy, p[1]);
+        p[2] = fma_(-W, dz, p[2]);
+        jv[0] = fma_(W, dx, jv[0]);
+        jv[1] = fma_(W, dy, jv[1]);
+        jv[2] = fma_(W, dz, jv[2]);
+        if (POT) {
+            p[3] += u;
+            jv[3] += u;
+        }
+    }
+}
+
 // One mini-tile: the wave's ICH i chunks (records iv, running partials p) against the j chunk in
 // the wave's LDS slot `st` (staged twice), with the j sums jv entering and leaving in lane order.
 // MASK (diagonal tiles only): per i slot k, wi[k] / wj[k] switch the i and j sides on or off and
@@ -146,7 +204,7 @@ __device__ __forceinline__ void sym_minitile(const R *st, const R (&iv)[ICH], fl
                                 MASK ? wj[k] : 1.0f, p[k], jv);
         // most sums move through the LDS crossbar, one on the VALU: the two units share the
         // moves (2 % faster at N = 2^20 than four crossbar moves; more DPP moves are slower)
-        if (OP == SYM_FORCE) {
+        if (OP != SYM_HVP) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) jv[c] = from_next_lane(bp_addr, jv[c]);
             if (POT) jv[3] = from_next_lane_dpp(jv[3]);
@@ -158,11 +216,21 @@ __device__ __forceinline__ void sym_minitile(const R *st, const R (&iv)[ICH], fl
     }
 }
 
+// Waves per SIMD the register allocation aims at: 8-wave workgroups fit three per CU at six
+// waves per SIMD (80 VGPRs), 4-wave ones four at four (128 VGPRs).  The adjoint's longer pair
+// sequence, and the 8-wave LJC sequence with the energy, need more registers than that without
+// spilling; they aim one workgroup lower.
+template <int OP, bool POT, int WAVES> constexpr int sym_waves_per_eu()
+{
+    if (OP == SYM_HVP) return WAVES == 8 ? 4 : 3;
+    if (OP == SYM_LJC && POT && WAVES == 8) return 4;
+    return WAVES == 8 ? 6 : 4;
+}
+
 // WAVES waves per workgroup hold ICH i chunks each: (8, 2) or (4, 4), a pass of 16 i chunks.
 template <int OP, int PREC, bool POT, int WAVES, int ICH>
-// (the adjoint's 32-byte records double the staging LDS: one workgroup fewer per CU)
 __global__ __launch_bounds__(WAVES * kWave)
-__attribute__((amdgpu_waves_per_eu(OP == SYM_FORCE ? (WAVES == 8 ? 6 : 4) : (WAVES == 8 ? 4 : 3))))
+__attribute__((amdgpu_waves_per_eu(sym_waves_per_eu<OP, POT, WAVES>())))
 void k_sym(SymLaunch a)
 {
     using R = typename SymRecOf<OP>::type;
@@ -178,10 +246,12 @@ void k_sym(SymLaunch a)
     const float eps2 = (float)a.eps2;
     const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
 
-    __shared__ float4 jacc[kSymMaxBlk][kWave];            // j sums of block b2
+    // j sums of block b2: blk x 64 float4 of dynamic LDS (sized by the launch for its block
+    // edge, so that 1024-record blocks leave room for more workgroups per CU)
+    extern __shared__ float4 jacc[];
     __shared__ R st_all[WAVES][2 * kWave];                // each wave's j chunk, staged twice
     R *st = st_all[w];
-    for (int k = threadIdx.x; k < blk * kWave; k += kThreads) jacc[k / kWave][k % kWave] = float4{0, 0, 0, 0};
+    for (int k = threadIdx.x; k < blk * kWave; k += kThreads) jacc[k] = float4{0, 0, 0, 0};
     const int64_t jrec0 = b2 * blk * kWave;                // first record of block b2
     const int64_t irec0 = b1 * blk * kWave;                // first record of block b1
     __syncthreads();
@@ -212,7 +282,7 @@ void k_sym(SymLaunch a)
             gj = jrec0 + (int64_t)((w + r + 1) % blk) * kWave + lane;
             g0 = rec4[gj * V];
             if (V == 2) g1 = rec4[gj * V + 1];
-            const float4 j4 = jacc[q][lane];
+            const float4 j4 = jacc[q * kWave + lane];
             float jv[4] = {j4.x, j4.y, j4.z, j4.w};
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -243,7 +313,7 @@ void k_sym(SymLaunch a)
                 }
                 sym_minitile<OP, ICH, POT, true>(st, iv, eps2, bp_addr, p, jv, wi, wj, self);
             }
-            jacc[q][lane] = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
+            jacc[q * kWave + lane] = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
 #pragma unroll
             for (int k = 0; k < ICH; ++k)
 #pragma unroll
@@ -259,14 +329,14 @@ void k_sym(SymLaunch a)
             if (!diag) {
                 a.partial[b2 * a.npad + irec0 + (int64_t)(aloc + k) * kWave + lane] = v;
             } else {
-                float4 &t = jacc[aloc + k][lane];
+                float4 &t = jacc[(aloc + k) * kWave + lane];
                 t = float4{t.x + v.x, t.y + v.y, t.z + v.z, t.w + v.w};
             }
         }
         __syncthreads();
     }
     // j sums: slot b1 of the rows of block b2
-    for (int q = w; q < blk; q += WAVES) a.partial[b1 * a.npad + jrec0 + (int64_t)q * kWave + lane] = jacc[q][lane];
+    for (int q = w; q < blk; q += WAVES) a.partial[b1 * a.npad + jrec0 + (int64_t)q * kWave + lane] = jacc[q * kWave + lane];
 }
 
 // Row r: the nblk slot partials in slot order (FP64, Neumaier), then the epilogue.  When
@@ -313,17 +383,28 @@ template <int WAVES, int ICH>
 static hipError_t launch_sym_shape(const SymLaunch &a, hipStream_t s)
 {
     const dim3 grid((unsigned)sym_grid(a.count)), block(WAVES * kWave);
-    if (a.op == SYM_HVP) {                           // no potential for the adjoint
-        if (a.prec == P_KAHAN) hipLaunchKernelGGL((k_sym<SYM_HVP, P_KAHAN, false, WAVES, ICH>), grid, block, 0, s, a);
+    const size_t lds = (size_t)a.blk * kWave * sizeof(float4);       // the j sums of one block
+    if (a.op == SYM_LJC) {
+        if (a.prec == P_KAHAN) {
+            if (a.pot) hipLaunchKernelGGL((k_sym<SYM_LJC, P_KAHAN, true, WAVES, ICH>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((k_sym<SYM_LJC, P_KAHAN, false, WAVES, ICH>), grid, block, lds, s, a);
+        } else if (a.prec == P_FP64ACC) {
+            if (a.pot) hipLaunchKernelGGL((k_sym<SYM_LJC, P_FP64ACC, true, WAVES, ICH>), grid, block, lds, s, a);
+            else hipLaunchKernelGGL((k_sym<SYM_LJC, P_FP64ACC, false, WAVES, ICH>), grid, block, lds, s, a);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (a.op == SYM_HVP) {                    // no potential for the adjoint
+        if (a.prec == P_KAHAN) hipLaunchKernelGGL((k_sym<SYM_HVP, P_KAHAN, false, WAVES, ICH>), grid, block, lds, s, a);
         else if (a.prec == P_FP64ACC)
-            hipLaunchKernelGGL((k_sym<SYM_HVP, P_FP64ACC, false, WAVES, ICH>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((k_sym<SYM_HVP, P_FP64ACC, false, WAVES, ICH>), grid, block, lds, s, a);
         else return hipErrorInvalidValue;
     } else if (a.prec == P_KAHAN) {
-        if (a.pot) hipLaunchKernelGGL((k_sym<SYM_FORCE, P_KAHAN, true, WAVES, ICH>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_sym<SYM_FORCE, P_KAHAN, false, WAVES, ICH>), grid, block, 0, s, a);
+        if (a.pot) hipLaunchKernelGGL((k_sym<SYM_FORCE, P_KAHAN, true, WAVES, ICH>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_sym<SYM_FORCE, P_KAHAN, false, WAVES, ICH>), grid, block, lds, s, a);
     } else if (a.prec == P_FP64ACC) {
-        if (a.pot) hipLaunchKernelGGL((k_sym<SYM_FORCE, P_FP64ACC, true, WAVES, ICH>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_sym<SYM_FORCE, P_FP64ACC, false, WAVES, ICH>), grid, block, 0, s, a);
+        if (a.pot) hipLaunchKernelGGL((k_sym<SYM_FORCE, P_FP64ACC, true, WAVES, ICH>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_sym<SYM_FORCE, P_FP64ACC, false, WAVES, ICH>), grid, block, lds, s, a);
     } else {
         return hipErrorInvalidValue;
     }
@@ -346,26 +427,6 @@ hipError_t launch_sym_reduce(const SymLaunch &a, hipStream_t s)
     if (a.n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_sym_reduce, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
-}
-
-template <int WAVES, int ICH>
-static int sym_blocks_shape(int prec, int pot)
-{
-    int nb = 0;
-    hipError_t e = hipErrorInvalidValue;
-    const int threads = WAVES * kWave;
-    if (prec == P_KAHAN)
-        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<SYM_FORCE, P_KAHAN, true, WAVES, ICH>, threads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<SYM_FORCE, P_KAHAN, false, WAVES, ICH>, threads, 0);
-    else if (prec == P_FP64ACC)
-        e = pot ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<SYM_FORCE, P_FP64ACC, true, WAVES, ICH>, threads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sym<SYM_FORCE, P_FP64ACC, false, WAVES, ICH>, threads, 0);
-    return e == hipSuccess ? nb : 0;
-}
-
-int sym_blocks_per_cu(int prec, int pot, int ich)
-{
-    return ich == 4 ? sym_blocks_shape<4, 4>(prec, pot) : sym_blocks_shape<8, 2>(prec, pot);
 }
 
 }  // namespace nbk

@@ -226,7 +226,7 @@ def forces_subset(pos, params, ilist, law: Law, potential: bool = True):
 
 
 def forces_share(pos, params, law: Law, share: int, n_shares: int, potential: bool = True):
-    """Share `share` of `n_shares` of a gravity evaluation over unordered pairs (what one of
+    """Share `share` of `n_shares` of a gravity or LJC(linear) evaluation over unordered pairs (what one of
     n_shares GPUs would evaluate): per-row partial sums of every row; the shares' outputs add
     up to forces()."""
     pos = _dev_f64(pos, None, "pos")

@@ -127,7 +127,10 @@ def test_share_validation(N):
         assert share(10, g, sh, nsh) == N.NBODY_EINVAL, (sh, nsh)
         assert b"share" in lib.nbody_last_error()
     # other laws and precisions shard by rows; the symmetric tiles stop at 2^21 particles
-    assert share(10, law(N, kind=1), 0, 2) == N.NBODY_ENOTSUP
+    for kind in (2, 3):
+        assert share(10, law(N, kind=kind), 0, 2) == N.NBODY_ENOTSUP, kind
+    assert share(10, law(N, kind=1, prec=0), 0, 2) == N.NBODY_ENOTSUP
+    assert share((1 << 21) + 1, law(N, kind=1), 0, 2) == N.NBODY_ENOTSUP
     assert share(10, law(N, prec=0), 0, 2) == N.NBODY_ENOTSUP
     assert share(10, law(N, prec=3), 0, 2) == N.NBODY_ENOTSUP
     assert share((1 << 21) + 1, g, 0, 2) == N.NBODY_ENOTSUP
@@ -203,9 +206,14 @@ def test_config_validation(N):
     ljc = N.NBodyLaw(1, 1, 1.0, 0.0, 332.0637, 4.0)
     # the batched entry point keeps j_stage 2 as its own symmetric tiles (gravity and LJC(linear)
     # with FP32 pair arithmetic), in their fixed shape of 4 waves over 256-record blocks
+    # the single-system tiles take gravity and LJC(linear) forces and leapfrog, and gravity's
+    # backward (LJC's backward, the other LJC dielectrics and FP64 pair arithmetic run one-sided)
+    ljc_const = N.NBodyLaw(2, 1, 1.0, 0.0, 332.0637, 4.0)
     cases = [(0, grav(1), "sym"), (3, grav(2), "sym"), (0, grav(0), None), (0, grav(3), None),
-             (0, ljc, None), (1, ljc, "bsym"), (1, grav(1), "bsym"), (1, grav(0), None),
-             (1, N.NBodyLaw(2, 1, 1.0, 0.0, 332.0637, 4.0), None), (2, grav(1), "sym"), (2, ljc, None),
+             (0, ljc, "sym"), (3, ljc, "sym"), (0, ljc_const, None), (3, ljc_const, None),
+             (0, N.NBodyLaw(1, 0, 1.0, 0.0, 332.0637, 4.0), None),
+             (1, ljc, "bsym"), (1, grav(1), "bsym"), (1, grav(0), None),
+             (1, ljc_const, None), (2, grav(1), "sym"), (2, ljc, None),
              (4, grav(1), None), (5, grav(2), None), (6, ljc, None)]
     for api, law, kind in cases:
         c = N.NBodyConfig()
@@ -220,23 +228,29 @@ def test_config_validation(N):
             assert (c.block, c.i_per_lane, c.j_tile, c.j_stage) == (256, 4, 256, 2), (api, law.kind)
         else:
             assert 64 <= c.block <= 256 and c.j_stage in (0, 1), (api, law.kind, law.precision, c.block)
-    # the rule takes the symmetric tiles for whole gravity systems from 65,536 to 2,097,152
-    # particles; above that their O(n^2) partials (34 GB at 2^21) would outgrow the workspace,
-    # and a forced symmetric configuration reads as one-sided there
+    # the rule takes the symmetric tiles for whole gravity and LJC(linear) systems from 65,536
+    # to 2,097,152 particles; above that their O(n^2) partials (34 GB at 2^21) would outgrow
+    # the workspace, and a forced symmetric configuration reads as one-sided there.  LJC takes
+    # the 4-wave shape at every size.
     g1 = grav(2)
-    for n, want in [(65535, False), (65536, True), (1 << 21, True), ((1 << 21) + 1, False), (1 << 22, False)]:
-        c = N.NBodyConfig()
-        assert lib.nbody_get_config(0, n, 1, ctypes.byref(g1), ctypes.byref(c)) == 0
-        assert (c.j_stage == 2) == want, (n, c.j_stage)
-        try:
-            assert lib.nbody_set_config(0, ctypes.byref(sym)) == 0
-            assert lib.nbody_get_config(0, n, 1, ctypes.byref(g1), ctypes.byref(c)) == 0
-        finally:
-            lib.nbody_set_config(0, None)
-        assert (c.j_stage == 2) == (n <= 1 << 21), (n, c.j_stage)
-    w_sym = lib.nbody_workspace_bytes(0, 1 << 21, 1, ctypes.byref(g1))
-    w_one = lib.nbody_workspace_bytes(0, (1 << 21) + 64, 1, ctypes.byref(g1))
-    assert w_sym >= 1024 * (1 << 21) * 16 and w_one < 4 << 30, (w_sym, w_one)
+    for lw in (g1, ljc):
+        for n, want in [(65535, False), (65536, True), (1 << 21, True), ((1 << 21) + 1, False),
+                        (1 << 22, False)]:
+            c = N.NBodyConfig()
+            assert lib.nbody_get_config(0, n, 1, ctypes.byref(lw), ctypes.byref(c)) == 0
+            assert (c.j_stage == 2) == want, (lw.kind, n, c.j_stage)
+            if want and lw.kind == 1:
+                assert (c.block, c.i_per_lane) == (256, 4), (n, c.block, c.i_per_lane)
+            try:
+                assert lib.nbody_set_config(0, ctypes.byref(sym)) == 0
+                assert lib.nbody_get_config(0, n, 1, ctypes.byref(lw), ctypes.byref(c)) == 0
+            finally:
+                lib.nbody_set_config(0, None)
+            assert (c.j_stage == 2) == (n <= 1 << 21), (lw.kind, n, c.j_stage)
+    for lw in (g1, ljc):
+        w_sym = lib.nbody_workspace_bytes(0, 1 << 21, 1, ctypes.byref(lw))
+        w_one = lib.nbody_workspace_bytes(0, (1 << 21) + 64, 1, ctypes.byref(lw))
+        assert w_sym >= 1024 * (1 << 21) * 16 and w_one < 4 << 30, (lw.kind, w_sym, w_one)
 
 
 def test_flop_convention_and_version(N):
