@@ -62,8 +62,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=N_MAIN, help="particles of the headline workload")
-    ap.add_argument("--legs", default="all", choices=["all", "main"],
-                    help="'main' runs only the headline workload (for counter runs)")
+    ap.add_argument("--legs", default="all", choices=["all", "main", "laws"],
+                    help="'main' runs only the headline workload (for counter runs), 'laws' the "
+                         "headline workload and the per-law leg")
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic configuration")
     ap.add_argument("--launch", default=None, metavar="BLOCK,IPL,JTILE,SPLIT,STAGE",
                     help="force the headline kernel's launch configuration (for counter runs of one "
@@ -98,7 +99,7 @@ def main():
     t0 = time.time()
     pos, vel, mass = W.plummer(args.n, 5)
     ens = W.batched_md(256, seed=4) if args.legs == "all" else None
-    md = W.md_system(N_LAWS, 3, box=(32.0 * N_LAWS) ** (1.0 / 3.0)) if args.legs == "all" else None
+    md = W.md_system(N_LAWS, 3, box=(32.0 * N_LAWS) ** (1.0 / 3.0)) if args.legs != "main" else None
     chains = W.bonded_chains(256, 32, 3) if args.legs == "all" else None
     log("inputs drawn in %.1f s" % (time.time() - t0))
     if args.save_inputs:
@@ -270,6 +271,8 @@ def main():
         out["batched_backward"] = batched_backward_leg(nb, torch, dev, ens)
         out["leapfrog_100"] = leapfrog_leg(nb, torch, dev, W)
         out["oracle_configs"] = oracle_configs_leg(nb, torch, dev, W, ens, out)
+    elif args.legs == "laws":
+        out["laws"] = laws_leg(nb, torch, dev, W, md)
     print(json.dumps(out), flush=True)
 
 
@@ -288,7 +291,7 @@ def timed_kernel(n, cfg):
         nblk = -(-n // rec)
         tiles = nblk * (nblk + 1) // 2
         waves = cfg["block"] // 64
-        return ("k_sym<1, true, %d, %d>" % (waves, cfg["i_per_lane"]),
+        return ("k_sym<0, 1, true, %d, %d>" % (waves, cfg["i_per_lane"]),
                 str(-(-tiles // 8) * 8 * cfg["block"]))              # padded to the 8 XCDs
     waves = -(-n // (64 * cfg["i_per_lane"]))
     wpb = cfg["block"] // 64
