@@ -31,7 +31,7 @@
  * Every i interacts with every j != i.  The one-sided kernels evaluate all
  * N^2 ordered pairs and scatter no pair to both partners, as the paper's
  * kernels do (Section 2, the remark on Newton's third law).  For gravity and
- * LJC(linear) over a whole system, FP32 pair arithmetic, the symmetric pair
+ * the LJC laws over a whole system, FP32 pair arithmetic, the symmetric pair
  * tiles (j_stage 2,
  * the default from N = 65,536 to 2,097,152) evaluate each unordered pair once
  * and apply it to both particles through per-block partial sums that a
@@ -177,9 +177,9 @@ typedef struct nbody_exclusions {
  *             (Newton's third law), for gravity with FP32_KAHAN or
  *             FP32_FP64ACC through nbody_forces, leapfrog_step and
  *             nbody_forces_backward (the position adjoint, whose pair term
- *             for one particle is minus the other's), and for LJC(linear)
- *             with those precisions through nbody_forces and leapfrog_step
- *             (no exclusion lists), on whole systems of up
+ *             for one particle is minus the other's), and for the three LJC
+ *             laws with those precisions through nbody_forces and
+ *             leapfrog_step (no exclusion lists), on whole systems of up
  *             to 2,097,152 particles (its per-block partials
  *             grow as n^2: 8.6 GB at n = 2^20, 34 GB at 2^21; elsewhere 2
  *             reads as 1).  For nbody_forces_batched, j_stage 2 selects the
@@ -244,7 +244,7 @@ int nbody_forces_subset(const double *pos, const double *params, int64_t n, cons
                         int64_t ni, const nbody_law *law, double *out_force,
                         double *out_potential, void *ws, size_t ws_bytes, void *stream);
 
-/* One share of a gravity or LJC(linear) evaluation, for a caller that spreads one system
+/* One share of a gravity or LJC evaluation, for a caller that spreads one system
  * over several GPUs (each GPU holds every particle and evaluates one share;
  * summing the shares' outputs gives the forces).  The unordered pairs are
  * cut as the symmetric pair tiles cut them (Section 2's all-pairs sum with
@@ -254,13 +254,13 @@ int nbody_forces_subset(const double *pos, const double *params, int64_t n, cons
  * evaluates the tiles of its range.  out_force [n][3] and out_potential [n]
  * (optional) receive, for EVERY row, the FP64 sum of that row's contributions
  * from the share's tiles, scaled as nbody_forces scales them (G, -G for
- * gravity; 1, 1/2 for LJC); rows
+ * gravity; 1 and 1/2 or 1 for LJC); rows
  * the share does not touch get zero.  The sum over all shares equals
  * nbody_forces' result up to the rounding of the final FP64 additions; with
  * n_shares = 1 it is that result.
  *  share, n_shares   0 <= share < n_shares.
- * Law: gravity or LJC(linear) with NBODY_FP32_KAHAN or NBODY_FP32_FP64ACC, n <= 2,097,152
- * (NBODY_ENOTSUP otherwise: other laws shard by rows, with
+ * Law: any, with NBODY_FP32_KAHAN or NBODY_FP32_FP64ACC, n <= 2,097,152
+ * (NBODY_ENOTSUP otherwise: FP64 and FP32_PLAIN shard by rows, with
  * nbody_forces_subset on a contiguous row list).  Workspace:
  * nbody_workspace_bytes(NBODY_API_FORCES, n, 1, law).  Errors: as
  * nbody_forces, and NBODY_EINVAL for a share outside [0, n_shares). */
@@ -458,8 +458,8 @@ int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, dou
 
 /* Workspace size in bytes needed by entry point `api` for `n_total`
  * particles in `n_systems` systems (1 for the single-system entry points).
- * For gravity and LJC(linear) with FP32_KAHAN or FP32_FP64ACC through the
- * forces and leapfrog entry points (and gravity's backward), n <= 2,097,152,
+ * For every law with FP32_KAHAN or FP32_FP64ACC through the forces and
+ * leapfrog entry points (and gravity's backward), n <= 2,097,152,
  * it covers the symmetric pair tiles (j_stage
  * 2), whose FP32 partial buffer holds one partial per row and block of 2048
  * records: about n^2 / 128 bytes (8.6 GB at n = 2^20).  Returns 0 when the

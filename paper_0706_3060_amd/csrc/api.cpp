@@ -90,8 +90,8 @@ int max_split(int64_t npad) { return npad <= 0 ? 1 : max_split_rows(npad, npad);
 
 // ------------------------------------------------------ symmetric tiles
 // j_stage 2 selects the symmetric pair tiles (symmetric.hip): gravity (forces,
-// leapfrog, the position adjoint) or LJC with the linear dielectric (forces,
-// leapfrog), FP32 pair arithmetic and Kahan or FP64 tile sums, whole systems.
+// leapfrog, the position adjoint) or the LJC laws (forces, leapfrog), FP32 pair
+// arithmetic and Kahan or FP64 tile sums, whole systems.
 // j_tile is the block edge in records, 1024 (16 chunks, for N up to
 // kSymSmallMax) or 2048 (32 chunks); ipl picks the workgroup shape (2: 512
 // threads of 2 i chunks per wave, 4: 256 threads of 4).  Each row gets one FP32
@@ -110,7 +110,18 @@ bool sym_eligible(int api, int law, int prec)
     if (prec != NBODY_FP32_KAHAN && prec != NBODY_FP32_FP64ACC) return false;
     const bool fwd = api == NBODY_API_FORCES || api == NBODY_API_LEAPFROG;
     if (law == NBODY_LAW_GRAVITY) return fwd || api == NBODY_API_BACKWARD;
-    return law == NBODY_LAW_LJC_LINEAR && fwd;
+    return fwd;                                         // the three LJC dielectrics
+}
+
+// the symmetric tiles' pair operator of a forward law
+int sym_op_of(int law)
+{
+    switch (law) {
+    case NBODY_LAW_GRAVITY: return SYM_FORCE;
+    case NBODY_LAW_LJC_LINEAR: return SYM_LJC;
+    case NBODY_LAW_LJC_CONSTANT: return SYM_LJC_CONST;
+    default: return SYM_LJC_SIG;
+    }
 }
 
 // block edge in chunks for a requested j_tile and system size
@@ -340,9 +351,12 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
         // 4 waves of 4 i chunks (half the cross-lane moves per pair, 4 waves per SIMD) against
         // 8 waves of 2 (6 waves per SIMD): for gravity measured 5-7 % faster with the
-        // potential, and from N = 2^17 without it; for LJC as fast with the energies and
-        // 15-20 % faster without them
-        const bool four = law != NBODY_LAW_GRAVITY || pot || n > (int64_t(1) << 17);
+        // potential, and from N = 2^17 without it.  For LJC(linear) and LJC(constant) the
+        // 8-wave shape is as fast or up to 5 % faster with the energies, the 4-wave one 15-20 %
+        // faster without them; the sigmoidal dielectric's longer sequence leaves the 4-wave
+        // shape three waves per SIMD, and 8 waves of 2 are 10 % faster either way.
+        const bool four = law == NBODY_LAW_GRAVITY ? (pot || n > (int64_t(1) << 17))
+                                                   : (!pot && law != NBODY_LAW_LJC_SIGMOIDAL);
         c.ipl = four ? 4 : 2;
         c.block = four ? 256 : kSymThreads;
         return sanitize(c, api, law, prec, round_up(n, 64));
@@ -768,7 +782,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
                 int64_t n_shares = 1)
 {
     // the symmetric tiles (j_stage 2) evaluate whole systems; sanitize admits the
-    // configuration only for gravity and LJC(linear) with FP32_KAHAN / FP32_FP64ACC
+    // configuration only for FP32_KAHAN / FP32_FP64ACC forward laws and gravity's backward
     const bool sym = c.j_stage == kSymStage && rows == nullptr && nrows == n && excl.off == nullptr;
     const int blk = sym ? c.j_tile / 64 : 0;
     const int64_t npad = sym ? sym_npad(n, blk) : round_up(n, 64);
@@ -788,7 +802,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
 
     if (sym) {
         SymLaunch a{};
-        a.op = law->kind == NBODY_LAW_GRAVITY ? SYM_FORCE : SYM_LJC;
+        a.op = sym_op_of(law->kind);
         a.prec = law->precision;
         a.pot = pot ? 1 : 0;
         a.blk = blk;
@@ -797,6 +811,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
         a.npad = npad;
         a.n = n;
         a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+        for (int c = 0; c < 4; ++c) a.zeta[c] = law->kind == NBODY_LAW_LJC_SIGMOIDAL ? law->zeta[c] : 0.0;
         a.rec = base + lay.rec_off;
         a.partial = (float4 *)(base + lay.part_off);
         sym_share_range(a.nblk, share, n_shares, a.t0, a.count);
@@ -1506,7 +1521,7 @@ int forces_impl(const double *pos, const double *params, int64_t n, const int64_
                        pot, ws, lay, (hipStream_t)stream, nullptr, excl_args(excl));
 }
 
-// One share of the symmetric pair tiles (gravity or LJC(linear), FP32 pair arithmetic): the tiles of order
+// One share of the symmetric pair tiles (gravity or an LJC law, FP32 pair arithmetic): the tiles of order
 // range share / n_shares of the triangle, reduced into per-row partial sums of all n rows.
 int share_impl(const double *pos, const double *params, int64_t n, const nbody_law *law, int32_t share,
                int32_t n_shares, double *out_force, double *out_potential, void *ws, size_t ws_bytes,
@@ -1515,9 +1530,8 @@ int share_impl(const double *pos, const double *params, int64_t n, const nbody_l
     int rc = validate_law(law, false);
     if (rc) return rc;
     if (!sym_eligible(NBODY_API_FORCES, law->kind, law->precision))
-        return fail(NBODY_ENOTSUP, "shares of the symmetric pair tiles are provided for gravity and "
-                    "LJC(linear) with FP32_KAHAN or FP32_FP64ACC (other laws shard by rows: "
-                    "nbody_forces_subset)");
+        return fail(NBODY_ENOTSUP, "shares of the symmetric pair tiles are provided for FP32_KAHAN or "
+                    "FP32_FP64ACC (FP64 and FP32_PLAIN shard by rows: nbody_forces_subset)");
     if (n < 0) return fail(NBODY_EINVAL, "n < 0");
     if (n > kSymMaxN) return fail(NBODY_ENOTSUP, "the symmetric pair tiles take up to %lld particles",
                                   (long long)kSymMaxN);

@@ -146,21 +146,13 @@ template <typename T> struct LjcI { T x, y, z, qs, sh, se; };
 // rsq + 1 mul (31 / 36 flops); LJC_SIG adds r, the two polynomials, exp and
 // the (1 + r zeta'/zeta) factor (48 / 53 flops; the two clamps of the zeta
 // factors are comparisons, not counted).
-template <bool MASK, bool POT, int LAW, typename T>
-__device__ __forceinline__ void ljc_pair(const LjcI<T> &i, T xj, T yj, T zj, T qsj, T shj, T sej,
-                                         const PairK<T> &k, bool self, T (&p)[4])
+// The scalar part of an LJC pair, symmetric in its two atoms: from r^2 and the combined
+// charge (qq), Lennard-Jones (e) and sigma (sg) factors, the force factor W (F_i = -W d,
+// d = r_j - r_i) and, with POT, the pair's energy term du (2 u_ij for LJC, u_ij for the other
+// dielectrics).  The one-sided pair adds W to one atom; the symmetric tiles to both.
+template <bool POT, int LAW, typename T>
+__device__ __forceinline__ void ljc_terms(T r2, T qq, T e, T sg, const PairK<T> &k, T &W, T &du)
 {
-    const T dx = xj - i.x, dy = yj - i.y, dz = zj - i.z;
-    T r2 = dx * dx;
-    r2 = fma_(dy, dy, r2);
-    r2 = fma_(dz, dz, r2);
-    T qq = i.qs * qsj;
-    T e = i.se * sej;
-    if (MASK) {
-        r2 = self ? T(1) : r2;
-        qq = self ? T(0) : qq;
-        e = self ? T(0) : e;
-    }
     T x, cx, wc;
     if constexpr (LAW == LJC) {
         x = rcp_(r2);
@@ -182,22 +174,41 @@ __device__ __forceinline__ void ljc_pair(const LjcI<T> &i, T xj, T yj, T zj, T q
         cx = (qq * ri) * exp_neg_(poly);
         wc = fma_(cx, rdl, cx);
     }
-    const T sg = i.sh + shj;
     const T s2 = (sg * sg) * x;
     const T s6 = (s2 * s2) * s2;
     const T lj = e * s6;                     // 24 eps_ij (sigma_ij / r)^6
     const T t = fma_(s6, T(2), T(-1));
-    const T W = fma_(lj, t, wc) * x;         // (24 eps_ij (2 s^12 - s^6) + wc) / r^2
-    p[0] = fma_(-W, dx, p[0]);
-    p[1] = fma_(-W, dy, p[1]);
-    p[2] = fma_(-W, dz, p[2]);
+    W = fma_(lj, t, wc) * x;                 // (24 eps_ij (2 s^12 - s^6) + wc) / r^2
     if (POT) {
         const T v = fma_(lj, s6, -lj);       // 24 eps_ij (s^12 - s^6)
         if constexpr (LAW == LJC)
-            p[3] += fma_(v, T(1.0 / 3.0), cx);   // 2 u_ij
+            du = fma_(v, T(1.0 / 3.0), cx);  // 2 u_ij
         else
-            p[3] += fma_(v, T(1.0 / 6.0), cx);   // u_ij
+            du = fma_(v, T(1.0 / 6.0), cx);  // u_ij
     }
+}
+
+template <bool MASK, bool POT, int LAW, typename T>
+__device__ __forceinline__ void ljc_pair(const LjcI<T> &i, T xj, T yj, T zj, T qsj, T shj, T sej,
+                                         const PairK<T> &k, bool self, T (&p)[4])
+{
+    const T dx = xj - i.x, dy = yj - i.y, dz = zj - i.z;
+    T r2 = dx * dx;
+    r2 = fma_(dy, dy, r2);
+    r2 = fma_(dz, dz, r2);
+    T qq = i.qs * qsj;
+    T e = i.se * sej;
+    if (MASK) {
+        r2 = self ? T(1) : r2;
+        qq = self ? T(0) : qq;
+        e = self ? T(0) : e;
+    }
+    T W, du = T(0);
+    ljc_terms<POT, LAW>(r2, qq, e, i.sh + shj, k, W, du);
+    p[0] = fma_(-W, dx, p[0]);
+    p[1] = fma_(-W, dy, p[1]);
+    p[2] = fma_(-W, dz, p[2]);
+    if (POT) p[3] += du;
 }
 
 // ------------------------------------------------------------ running sums

@@ -77,21 +77,23 @@ hipError_t launch_forces(const FwdLaunch &f, hipStream_t s);
 hipError_t launch_reduce_split(const FwdLaunch &f, hipStream_t s);
 int forces_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block);
 
-// ---- symmetric pair tiles (symmetric.hip): gravity and LJC(linear), every unordered pair once ----
+// ---- symmetric pair tiles (symmetric.hip): gravity and the LJC laws, every unordered pair once ----
 constexpr int kSymThreads = 512;           // the larger workgroup: 8 waves, 2 i chunks per wave (or 4 x 4)
 constexpr int kSymMaxBlk = 32;             // largest block edge in chunks of 64 records
-// gravity forces (and potentials), gravity's position adjoint, LJC(linear) forces (and energies)
-enum SymOp { SYM_FORCE = 0, SYM_HVP = 1, SYM_LJC = 2 };
+// gravity forces (and potentials), gravity's position adjoint, and the forces (and energies) of
+// LJC with the linear, constant or sigmoidal dielectric
+enum SymOp { SYM_FORCE = 0, SYM_HVP = 1, SYM_LJC = 2, SYM_LJC_CONST = 3, SYM_LJC_SIG = 4 };
 struct SymLaunch {
-    int op;                        // SYM_FORCE ({x, y, z, m}), SYM_HVP ({x, y, z, m, g, 0}) or SYM_LJC
-                                   // ({x, y, z, qs, sh, se, 0, 0}) records
+    int op;                        // SYM_FORCE ({x, y, z, m}), SYM_HVP ({x, y, z, m, g, 0}) or an LJC
+                                   // operator ({x, y, z, qs, sh, se, 0, 0}) records
     int prec, pot;                 // P_KAHAN or P_FP64ACC tile sums; potential on/off (forces)
     int blk;                       // block edge in chunks of 64 records: 16 or 32
     int ich;                       // i chunks per wave: 2 (8-wave workgroups) or 4 (4-wave workgroups)
     int64_t nblk;                  // blocks; tiles = nblk (nblk + 1) / 2
     int64_t npad;                  // records = nblk * blk * 64 (zero-mass padding past n)
     int64_t n;                     // rows finished by the reduction
-    double eps2;
+    double eps2;                   // gravity softening squared
+    double zeta[4];                // SYM_LJC_SIG: exp(z0 r^3 + z1 r^2 + z2 r + z3), as FwdLaunch::zeta
     const void *rec;               // FP32 records of the operator
     float4 *partial;               // [nblk][npad] (x, y, z, potential) FP32 slot partials
     int64_t t0, count;             // order range of the launch's tiles (whole triangle: 0, sym_tiles)

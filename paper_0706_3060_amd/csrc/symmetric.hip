@@ -1,9 +1,8 @@
 // Symmetric all-pairs tiles: every unordered pair {i, j} is evaluated once
 // and its force is applied to both particles (Newton's third law), so one
-// reciprocal square root (gravity) or reciprocal (LJC with the linear
-// dielectric) serves two interactions.  Three pair operators share the tiles:
-// gravity's forces and potentials, gravity's position adjoint, and LJC(linear)
-// forces and energies.
+// reciprocal square root (or reciprocal) serves two interactions.  The pair
+// operators that share the tiles: gravity's forces and potentials, gravity's
+// position adjoint, and the forces and energies of the three LJC dielectrics.
 //
 // Decomposition.  The padded records form nblk blocks of blk chunks of 64
 // (blk = 16 or 32).  Each workgroup takes one tile (b1, b2), b1 <= b2, of the
@@ -62,10 +61,14 @@ __device__ __forceinline__ float from_next_lane_dpp(float v)
 template <int OP> struct SymRecOf { using type = GravRec<float>; };
 template <> struct SymRecOf<SYM_HVP> { using type = GravAdjRec<float>; };
 template <> struct SymRecOf<SYM_LJC> { using type = LjcRec<float>; };
+template <> struct SymRecOf<SYM_LJC_CONST> { using type = LjcRec<float>; };
+template <> struct SymRecOf<SYM_LJC_SIG> { using type = LjcRec<float>; };
+// the Table 1 law of an LJC operator
+template <int OP> constexpr int sym_ljc_law() { return OP == SYM_LJC ? LJC : (OP == SYM_LJC_CONST ? LJC_CONST : LJC_SIG); }
 
 template <bool POT, bool MASK>
-__device__ __forceinline__ void sym_pair(const GravRec<float> &I, const GravRec<float> &J, float eps2, bool sk,
-                                         float wi, float wj, float (&p)[4], float (&jv)[4])
+__device__ __forceinline__ void sym_pair_grav(const GravRec<float> &I, const GravRec<float> &J, float eps2, bool sk,
+                                              float wi, float wj, float (&p)[4], float (&jv)[4])
 {
     const float dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
     float r2 = fma_(dx, dx, eps2);
@@ -92,9 +95,9 @@ __device__ __forceinline__ void sym_pair(const GravRec<float> &I, const GravRec<
     }
 }
 
-template <bool POT, bool MASK>
-__device__ __forceinline__ void sym_pair(const GravAdjRec<float> &I, const GravAdjRec<float> &J, float eps2,
-                                         bool sk, float wi, float wj, float (&p)[4], float (&jv)[4])
+template <bool MASK>
+__device__ __forceinline__ void sym_pair_hvp(const GravAdjRec<float> &I, const GravAdjRec<float> &J, float eps2,
+                                             bool sk, float wi, float wj, float (&p)[4], float (&jv)[4])
 {
     const float dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
     float r2 = fma_(dx, dx, eps2);
@@ -130,12 +133,13 @@ __device__ __forceinline__ void sym_pair(const GravAdjRec<float> &I, const GravA
     }
 }
 
-// SYM_LJC: Table 1's LJC(linear), symmetric in its two particles: F_i += W (r_i - r_j) and
-// F_j -= W (r_i - r_j) with one W, and both energy sums get the pair's 2 u (halved by the
-// epilogue), as the one-sided ljc_pair computes them.
-template <bool POT, bool MASK>
-__device__ __forceinline__ void sym_pair(const LjcRec<float> &I, const LjcRec<float> &J, float, bool sk, float wi,
-                                         float wj, float (&p)[4], float (&jv)[4])
+// The LJC operators: Table 1's LJC pair is symmetric in its two atoms (ljc_terms), so one W
+// and one energy term serve both: F_i -= W d and F_j += W d (d = r_j - r_i), and both energy
+// sums get the pair's term (2 u_ij for the linear dielectric, halved by the epilogue; u_ij for
+// the others), as the one-sided ljc_pair computes them.
+template <int LAW, bool POT, bool MASK>
+__device__ __forceinline__ void sym_pair_ljc(const LjcRec<float> &I, const LjcRec<float> &J, const PairK<float> &k,
+                                             bool sk, float wi, float wj, float (&p)[4], float (&jv)[4])
 {
     const float dx = J.x - I.x, dy = J.y - I.y, dz = J.z - I.z;
     float r2 = dx * dx;
@@ -148,16 +152,8 @@ __device__ __forceinline__ void sym_pair(const LjcRec<float> &I, const LjcRec<fl
         qq = sk ? 0.0f : qq;
         e = sk ? 0.0f : e;
     }
-    const float x = rcp_(r2);
-    const float cx = qq * x;
-    const float sg = I.sh + J.sh;
-    const float s2 = (sg * sg) * x;
-    const float s6 = (s2 * s2) * s2;
-    const float lj = e * s6;                       // 24 eps_ij (sigma_ij / r)^6
-    const float t = fma_(s6, 2.0f, -1.0f);
-    const float W = fma_(lj, t, cx) * x;           // (24 eps_ij (2 s^12 - s^6) + qq x) / r^2
-    float u = 0.0f;
-    if (POT) u = fma_(fma_(lj, s6, -lj), 1.0f / 3.0f, cx);   // 2 u_ij
+    float W, u = 0.0f;
+    ljc_terms<POT, LAW>(r2, qq, e, I.sh + J.sh, k, W, u);
     if (MASK) {
         const float Wi = W * wi, Wj = W * wj;
         p[0] = fma_(-Wi, dx, p[0]);
@@ -184,13 +180,22 @@ __device__ __forceinline__ void sym_pair(const LjcRec<float> &I, const LjcRec<fl
     }
 }
 
+template <int OP, bool POT, bool MASK, typename R>
+__device__ __forceinline__ void sym_pair(const R &I, const R &J, const PairK<float> &k, bool sk, float wi, float wj,
+                                         float (&p)[4], float (&jv)[4])
+{
+    if constexpr (OP == SYM_FORCE) sym_pair_grav<POT, MASK>(I, J, k.eps2, sk, wi, wj, p, jv);
+    else if constexpr (OP == SYM_HVP) sym_pair_hvp<MASK>(I, J, k.eps2, sk, wi, wj, p, jv);
+    else sym_pair_ljc<sym_ljc_law<OP>(), POT, MASK>(I, J, k, sk, wi, wj, p, jv);
+}
+
 // One mini-tile: the wave's ICH i chunks (records iv, running partials p) against the j chunk in
 // the wave's LDS slot `st` (staged twice), with the j sums jv entering and leaving in lane order.
 // MASK (diagonal tiles only): per i slot k, wi[k] / wj[k] switch the i and j sides on or off and
 // self[k] marks a slot whose i chunk is the j chunk itself, whose pair at step 0 is the particle
 // with itself.
 template <int OP, int ICH, bool POT, bool MASK, typename R>
-__device__ __forceinline__ void sym_minitile(const R *st, const R (&iv)[ICH], float eps2, int bp_addr,
+__device__ __forceinline__ void sym_minitile(const R *st, const R (&iv)[ICH], const PairK<float> &kc, int bp_addr,
                                              float (&p)[ICH][4], float (&jv)[4], const float (&wi)[ICH],
                                              const float (&wj)[ICH], const bool (&self)[ICH])
 {
@@ -200,8 +205,8 @@ __device__ __forceinline__ void sym_minitile(const R *st, const R (&iv)[ICH], fl
         const R J = st[lane + s];
 #pragma unroll
         for (int k = 0; k < ICH; ++k)
-            sym_pair<POT, MASK>(iv[k], J, eps2, MASK && self[k] && s == 0, MASK ? wi[k] : 1.0f,
-                                MASK ? wj[k] : 1.0f, p[k], jv);
+            sym_pair<OP, POT, MASK>(iv[k], J, kc, MASK && self[k] && s == 0, MASK ? wi[k] : 1.0f,
+                                    MASK ? wj[k] : 1.0f, p[k], jv);
         // most sums move through the LDS crossbar, one on the VALU: the two units share the
         // moves (2 % faster at N = 2^20 than four crossbar moves; more DPP moves are slower)
         if (OP != SYM_HVP) {
@@ -217,13 +222,13 @@ __device__ __forceinline__ void sym_minitile(const R *st, const R (&iv)[ICH], fl
 }
 
 // Waves per SIMD the register allocation aims at: 8-wave workgroups fit three per CU at six
-// waves per SIMD (80 VGPRs), 4-wave ones four at four (128 VGPRs).  The adjoint's longer pair
-// sequence, and the 8-wave LJC sequence with the energy, need more registers than that without
-// spilling; they aim one workgroup lower.
+// waves per SIMD (80 VGPRs), 4-wave ones four at four (128 VGPRs).  The longer pair sequences
+// (the adjoint, the sigmoidal dielectric, and the 8-wave LJC sequences with the energy) need
+// more registers than that without spilling; they aim one workgroup lower.
 template <int OP, bool POT, int WAVES> constexpr int sym_waves_per_eu()
 {
-    if (OP == SYM_HVP) return WAVES == 8 ? 4 : 3;
-    if (OP == SYM_LJC && POT && WAVES == 8) return 4;
+    if (OP == SYM_HVP || OP == SYM_LJC_SIG) return WAVES == 8 ? 4 : 3;
+    if (OP >= SYM_LJC && POT && WAVES == 8) return 4;
     return WAVES == 8 ? 6 : 4;
 }
 
@@ -243,7 +248,14 @@ void k_sym(SymLaunch a)
     int64_t b1, b2;
     if (!sym_tile_of(blockIdx.x, a.nblk, a.t0, a.count, b1, b2)) return;   // whole workgroup, before any barrier
     const bool diag = b1 == b2;
-    const float eps2 = (float)a.eps2;
+    PairK<float> kc;
+    kc.eps2 = (float)a.eps2;
+    kc.za = (float)a.zeta[0];
+    kc.zb = (float)a.zeta[1];
+    kc.zc = (float)a.zeta[2];
+    kc.zd = (float)a.zeta[3];
+    kc.za3 = (float)(3.0 * a.zeta[0]);
+    kc.zb2 = (float)(2.0 * a.zeta[1]);
     const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
 
     // j sums of block b2: blk x 64 float4 of dynamic LDS (sized by the launch for its block
@@ -297,7 +309,7 @@ void k_sym(SymLaunch a)
                     one[k] = 1.0f;
                     none[k] = false;
                 }
-                sym_minitile<OP, ICH, POT, false>(st, iv, eps2, bp_addr, p, jv, one, one, none);
+                sym_minitile<OP, ICH, POT, false>(st, iv, kc, bp_addr, p, jv, one, one, none);
             } else {
                 // chunk q against i chunk aloc + k: symmetric when q is after it, its own
                 // chunk's pairs one-sided when q is it, nothing when q is before it (that pair
@@ -311,7 +323,7 @@ void k_sym(SymLaunch a)
                     wj[k] = rel > 0 ? 1.0f : 0.0f;
                     self[k] = rel == 0;
                 }
-                sym_minitile<OP, ICH, POT, true>(st, iv, eps2, bp_addr, p, jv, wi, wj, self);
+                sym_minitile<OP, ICH, POT, true>(st, iv, kc, bp_addr, p, jv, wi, wj, self);
             }
             jacc[q * kWave + lane] = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
 #pragma unroll
@@ -379,36 +391,35 @@ __global__ __launch_bounds__(256) void k_sym_reduce(SymLaunch a)
     if (a.pot && e.out_pot) e.out_pot[r] = e.pscale * v[3].value();
 }
 
+template <int OP, int WAVES, int ICH>
+static hipError_t launch_sym_op(const SymLaunch &a, dim3 grid, dim3 block, size_t lds, hipStream_t s)
+{
+    constexpr bool kPot = OP != SYM_HVP;                  // no potential for the adjoint
+    if (a.prec == P_KAHAN) {
+        if (kPot && a.pot) hipLaunchKernelGGL((k_sym<OP, P_KAHAN, kPot, WAVES, ICH>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_sym<OP, P_KAHAN, false, WAVES, ICH>), grid, block, lds, s, a);
+    } else if (a.prec == P_FP64ACC) {
+        if (kPot && a.pot) hipLaunchKernelGGL((k_sym<OP, P_FP64ACC, kPot, WAVES, ICH>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((k_sym<OP, P_FP64ACC, false, WAVES, ICH>), grid, block, lds, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <int WAVES, int ICH>
 static hipError_t launch_sym_shape(const SymLaunch &a, hipStream_t s)
 {
     const dim3 grid((unsigned)sym_grid(a.count)), block(WAVES * kWave);
     const size_t lds = (size_t)a.blk * kWave * sizeof(float4);       // the j sums of one block
-    if (a.op == SYM_LJC) {
-        if (a.prec == P_KAHAN) {
-            if (a.pot) hipLaunchKernelGGL((k_sym<SYM_LJC, P_KAHAN, true, WAVES, ICH>), grid, block, lds, s, a);
-            else hipLaunchKernelGGL((k_sym<SYM_LJC, P_KAHAN, false, WAVES, ICH>), grid, block, lds, s, a);
-        } else if (a.prec == P_FP64ACC) {
-            if (a.pot) hipLaunchKernelGGL((k_sym<SYM_LJC, P_FP64ACC, true, WAVES, ICH>), grid, block, lds, s, a);
-            else hipLaunchKernelGGL((k_sym<SYM_LJC, P_FP64ACC, false, WAVES, ICH>), grid, block, lds, s, a);
-        } else {
-            return hipErrorInvalidValue;
-        }
-    } else if (a.op == SYM_HVP) {                    // no potential for the adjoint
-        if (a.prec == P_KAHAN) hipLaunchKernelGGL((k_sym<SYM_HVP, P_KAHAN, false, WAVES, ICH>), grid, block, lds, s, a);
-        else if (a.prec == P_FP64ACC)
-            hipLaunchKernelGGL((k_sym<SYM_HVP, P_FP64ACC, false, WAVES, ICH>), grid, block, lds, s, a);
-        else return hipErrorInvalidValue;
-    } else if (a.prec == P_KAHAN) {
-        if (a.pot) hipLaunchKernelGGL((k_sym<SYM_FORCE, P_KAHAN, true, WAVES, ICH>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_sym<SYM_FORCE, P_KAHAN, false, WAVES, ICH>), grid, block, lds, s, a);
-    } else if (a.prec == P_FP64ACC) {
-        if (a.pot) hipLaunchKernelGGL((k_sym<SYM_FORCE, P_FP64ACC, true, WAVES, ICH>), grid, block, lds, s, a);
-        else hipLaunchKernelGGL((k_sym<SYM_FORCE, P_FP64ACC, false, WAVES, ICH>), grid, block, lds, s, a);
-    } else {
-        return hipErrorInvalidValue;
+    switch (a.op) {
+    case SYM_FORCE: return launch_sym_op<SYM_FORCE, WAVES, ICH>(a, grid, block, lds, s);
+    case SYM_HVP: return launch_sym_op<SYM_HVP, WAVES, ICH>(a, grid, block, lds, s);
+    case SYM_LJC: return launch_sym_op<SYM_LJC, WAVES, ICH>(a, grid, block, lds, s);
+    case SYM_LJC_CONST: return launch_sym_op<SYM_LJC_CONST, WAVES, ICH>(a, grid, block, lds, s);
+    case SYM_LJC_SIG: return launch_sym_op<SYM_LJC_SIG, WAVES, ICH>(a, grid, block, lds, s);
+    default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_sym(const SymLaunch &a, hipStream_t s)

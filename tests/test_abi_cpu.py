@@ -126,11 +126,11 @@ def test_share_validation(N):
     for sh, nsh in [(-1, 4), (4, 4), (0, 0), (0, -3)]:
         assert share(10, g, sh, nsh) == N.NBODY_EINVAL, (sh, nsh)
         assert b"share" in lib.nbody_last_error()
-    # other laws and precisions shard by rows; the symmetric tiles stop at 2^21 particles
-    for kind in (2, 3):
-        assert share(10, law(N, kind=kind), 0, 2) == N.NBODY_ENOTSUP, kind
-    assert share(10, law(N, kind=1, prec=0), 0, 2) == N.NBODY_ENOTSUP
-    assert share((1 << 21) + 1, law(N, kind=1), 0, 2) == N.NBODY_ENOTSUP
+    # FP64 and plain FP32 shard by rows; the symmetric tiles stop at 2^21 particles
+    for kind in (1, 2, 3):
+        for prec in (0, 3):
+            assert share(10, law(N, kind=kind, prec=prec), 0, 2) == N.NBODY_ENOTSUP, (kind, prec)
+        assert share((1 << 21) + 1, law(N, kind=kind), 0, 2) == N.NBODY_ENOTSUP, kind
     assert share(10, law(N, prec=0), 0, 2) == N.NBODY_ENOTSUP
     assert share(10, law(N, prec=3), 0, 2) == N.NBODY_ENOTSUP
     assert share((1 << 21) + 1, g, 0, 2) == N.NBODY_ENOTSUP
@@ -206,14 +206,16 @@ def test_config_validation(N):
     ljc = N.NBodyLaw(1, 1, 1.0, 0.0, 332.0637, 4.0)
     # the batched entry point keeps j_stage 2 as its own symmetric tiles (gravity and LJC(linear)
     # with FP32 pair arithmetic), in their fixed shape of 4 waves over 256-record blocks
-    # the single-system tiles take gravity and LJC(linear) forces and leapfrog, and gravity's
-    # backward (LJC's backward, the other LJC dielectrics and FP64 pair arithmetic run one-sided)
+    # the single-system tiles take the forces and leapfrog of every law and gravity's backward
+    # (LJC's backward and FP64 pair arithmetic run one-sided)
     ljc_const = N.NBodyLaw(2, 1, 1.0, 0.0, 332.0637, 4.0)
+    ljc_sig = N.NBodyLaw(3, 2, 1.0, 0.0, 332.0637, 1.0)
     cases = [(0, grav(1), "sym"), (3, grav(2), "sym"), (0, grav(0), None), (0, grav(3), None),
-             (0, ljc, "sym"), (3, ljc, "sym"), (0, ljc_const, None), (3, ljc_const, None),
+             (0, ljc, "sym"), (3, ljc, "sym"), (0, ljc_const, "sym"), (3, ljc_const, "sym"),
+             (0, ljc_sig, "sym"), (2, ljc_sig, None),
              (0, N.NBodyLaw(1, 0, 1.0, 0.0, 332.0637, 4.0), None),
              (1, ljc, "bsym"), (1, grav(1), "bsym"), (1, grav(0), None),
-             (1, ljc_const, None), (2, grav(1), "sym"), (2, ljc, None),
+             (1, ljc_const, None), (2, grav(1), "sym"), (2, ljc, None), (2, ljc_const, None),
              (4, grav(1), None), (5, grav(2), None), (6, ljc, None)]
     for api, law, kind in cases:
         c = N.NBodyConfig()
@@ -228,19 +230,19 @@ def test_config_validation(N):
             assert (c.block, c.i_per_lane, c.j_tile, c.j_stage) == (256, 4, 256, 2), (api, law.kind)
         else:
             assert 64 <= c.block <= 256 and c.j_stage in (0, 1), (api, law.kind, law.precision, c.block)
-    # the rule takes the symmetric tiles for whole gravity and LJC(linear) systems from 65,536
-    # to 2,097,152 particles; above that their O(n^2) partials (34 GB at 2^21) would outgrow
-    # the workspace, and a forced symmetric configuration reads as one-sided there.  LJC takes
-    # the 4-wave shape at every size.
+    # the rule takes the symmetric tiles for whole systems of every law from 65,536 to
+    # 2,097,152 particles; above that their O(n^2) partials (34 GB at 2^21) would outgrow the
+    # workspace, and a forced symmetric configuration reads as one-sided there.  With the
+    # energies (nbody_get_config assumes them) every LJC law takes the 8-wave shape.
     g1 = grav(2)
-    for lw in (g1, ljc):
+    for lw in (g1, ljc, ljc_const, ljc_sig):
         for n, want in [(65535, False), (65536, True), (1 << 21, True), ((1 << 21) + 1, False),
                         (1 << 22, False)]:
             c = N.NBodyConfig()
             assert lib.nbody_get_config(0, n, 1, ctypes.byref(lw), ctypes.byref(c)) == 0
             assert (c.j_stage == 2) == want, (lw.kind, n, c.j_stage)
-            if want and lw.kind == 1:
-                assert (c.block, c.i_per_lane) == (256, 4), (n, c.block, c.i_per_lane)
+            if want and lw.kind >= 1:
+                assert (c.block, c.i_per_lane) == (512, 2), (lw.kind, n, c.block, c.i_per_lane)
             try:
                 assert lib.nbody_set_config(0, ctypes.byref(sym)) == 0
                 assert lib.nbody_get_config(0, n, 1, ctypes.byref(lw), ctypes.byref(c)) == 0
