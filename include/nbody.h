@@ -189,9 +189,16 @@ typedef struct nbody_exclusions {
  *             in a fixed shape (block 256, i_per_lane 4, j_tile 256, j_split
  *             1): one wave per pair of 256-record blocks of a system, each
  *             unordered pair once; the rule's choice when systems average 512
- *             particles or more.  With j_stage 2, j_tile is
- *             the tile edge in records, 1024 (for n <= 262,144) or 2048,
- *             and block, i_per_lane and j_split are fixed (512, 2, 1). */
+ *             particles or more.  With j_stage 2 (single systems), j_tile
+ *             is the tile edge in records, 1024 (for n <= 262,144) or 2048;
+ *             block and i_per_lane pick the workgroup shape, (512, 2) for 8
+ *             waves of 2 i chunks or (256, 4) for 4 waves of 4; and j_split
+ *             cuts each tile's j chunks into 1, 2 or 4 parts run by workgroups
+ *             of their own (for n <= 131,072, each part at least as many
+ *             64-record chunks as the workgroup has waves; otherwise 1): more
+ *             parts fill the chip's last round of tiles better and leave more
+ *             slot partials for the reduction to read.  The requested value is
+ *             rounded down to the nearest allowed one. */
 typedef struct nbody_config {
     int32_t block;
     int32_t i_per_lane;
@@ -462,7 +469,9 @@ int hermite_block_steps(double *pos, double *vel, double *acc, double *jerk, dou
  * leapfrog entry points (and gravity's backward), n <= 2,097,152,
  * it covers the symmetric pair tiles (j_stage
  * 2), whose FP32 partial buffer holds one partial per row and block of 2048
- * records: about n^2 / 128 bytes (8.6 GB at n = 2^20).  Returns 0 when the
+ * records: about n^2 / 128 bytes (8.6 GB at n = 2^20); up to n = 262,144 it
+ * covers blocks of 1024 records (n^2 / 64 bytes), and up to n = 131,072 tiles
+ * in 4 j parts (n^2 / 16 bytes, 1.1 GB at n = 2^17).  Returns 0 when the
  * arguments are invalid. */
 size_t nbody_workspace_bytes(int32_t api, int64_t n_total, int64_t n_systems,
                              const nbody_law *law);

@@ -104,6 +104,9 @@ constexpr int kSymStage = 2;
 constexpr int64_t kSymSmallMax = int64_t(1) << 18;
 constexpr int64_t kSymMinN = int64_t(1) << 16;       // the rule's threshold for whole systems
 constexpr int64_t kSymMaxN = int64_t(1) << 21;
+// j parts per tile above 1 (j_split 2 or 4 with j_stage 2) for systems up to this size, where a
+// whole-tile launch fills the chip only a few rounds deep
+constexpr int64_t kSymSplitMaxN = int64_t(1) << 17;
 
 bool sym_eligible(int api, int law, int prec)
 {
@@ -127,16 +130,25 @@ int sym_op_of(int law)
 // block edge in chunks for a requested j_tile and system size
 int sym_blk(int j_tile, int64_t n) { return (j_tile <= 1024 && n <= kSymSmallMax) ? 16 : 32; }
 int64_t sym_npad(int64_t n, int blk) { return round_up(std::max<int64_t>(n, 1), (int64_t)blk * 64); }
-size_t sym_partial_bytes(int64_t n, int blk)
+size_t sym_partial_bytes(int64_t n, int blk, int split = 1)
 {
     const int64_t np = sym_npad(n, blk);
-    return (size_t)(np / ((int64_t)blk * 64)) * (size_t)np * 4 * sizeof(float);
+    return (size_t)split * (size_t)(np / ((int64_t)blk * 64)) * (size_t)np * 4 * sizeof(float);
 }
-// the largest partial buffer any allowed block edge needs for n rows
+// the largest j-part count allowed for n rows, blocks of blk chunks and `waves` waves per
+// workgroup (every part needs at least as many chunks as the workgroup has waves)
+int sym_max_split(int64_t n, int blk, int waves)
+{
+    if (n > kSymSplitMaxN) return 1;
+    int s = 4;
+    while (s > 1 && blk / s < waves) s /= 2;
+    return s;
+}
+// the largest partial buffer any allowed block edge and j-part count needs for n rows
 size_t sym_max_partial_bytes(int64_t n)
 {
-    size_t b = sym_partial_bytes(n, 32);
-    if (n <= kSymSmallMax) b = std::max(b, sym_partial_bytes(n, 16));
+    size_t b = sym_partial_bytes(n, 32, sym_max_split(n, 32, 4));
+    if (n <= kSymSmallMax) b = std::max(b, sym_partial_bytes(n, 16, sym_max_split(n, 16, 4)));
     return b;
 }
 
@@ -214,8 +226,12 @@ Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
             const bool four = c.ipl >= 4 && c.block <= 256;
             c.block = four ? 256 : kSymThreads;
             c.ipl = four ? 4 : 2;
-            c.j_split = 1;
             c.j_tile = sym_blk(c.j_tile, npad) * 64;
+            // j parts per tile: 1, 2 or 4, as many as requested and allowed
+            const int smax = sym_max_split(npad, c.j_tile / 64, c.block / 64);
+            int sp = 1;
+            while (sp * 2 <= std::min(c.j_split, smax)) sp *= 2;
+            c.j_split = sp;
             return c;
         }
         c.j_stage = 1;                                  // other laws, precisions, entry points, sizes
@@ -359,6 +375,12 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
                                                    : (!pot && law != NBODY_LAW_LJC_SIGMOIDAL);
         c.ipl = four ? 4 : 2;
         c.block = four ? 256 : kSymThreads;
+        // up to 2^17 the 2,080 to 8,256 tiles fill the chip only 2 to 8 rounds deep, and the
+        // last round is partly empty: two j parts per tile (one workgroup each) halve the
+        // rounds' length, measured 4-10 % faster per call (kernel and slot reduction) at
+        // N = 65,536 to 131,072; four parts shorten the kernel further but double the
+        // reduction's reads again
+        c.j_split = n <= kSymSplitMaxN ? 2 : 1;
         return sanitize(c, api, law, prec, round_up(n, 64));
     }
     const int64_t npad = round_up(std::max<int64_t>(std::max(n, nj), 1), 64);
@@ -807,6 +829,7 @@ int run_forward(const nbody_law *law, const Cfg &c, const double *pos, const dou
         a.pot = pot ? 1 : 0;
         a.blk = blk;
         a.ich = c.ipl;
+        a.split = c.j_split;
         a.nblk = npad / ((int64_t)blk * 64);
         a.npad = npad;
         a.n = n;
@@ -1707,16 +1730,19 @@ std::vector<Cfg> candidate_set(int api, int law, int prec, int64_t n, bool pot)
         return out;
     }
     if (sym_eligible(api, law, prec) && npad <= kSymMaxN)
-        for (int jt : {1024, 2048})            // the symmetric tiles, both block edges and shapes
-            for (int ipl : {2, 4}) {
-                if (jt == 1024 && n > kSymSmallMax) continue;
-                Cfg c;
-                c.j_stage = kSymStage;
-                c.j_tile = jt;
-                c.ipl = ipl;
-                c.block = ipl == 4 ? 256 : kSymThreads;
-                out.push_back(sanitize(c, api, law, prec, npad));
-            }
+        for (int jt : {1024, 2048})            // the symmetric tiles, both block edges and shapes,
+            for (int ipl : {2, 4})             // whole tiles or tiles in 2 or 4 j parts
+                for (int sp : {1, 2, 4}) {
+                    if (jt == 1024 && n > kSymSmallMax) continue;
+                    Cfg c;
+                    c.j_stage = kSymStage;
+                    c.j_tile = jt;
+                    c.ipl = ipl;
+                    c.block = ipl == 4 ? 256 : kSymThreads;
+                    c.j_split = sp;
+                    c = sanitize(c, api, law, prec, npad);
+                    if (c.j_split == sp) out.push_back(c);      // (parts not allowed here: skipped)
+                }
     const bool jerk = api == NBODY_API_JERK;
     for (int js : {0, 1})
         for (int ipl : {1, 2, 4, 8}) {
@@ -1959,15 +1985,21 @@ int nbody_forces_noalloc(const double *pos, const double *params, int64_t n, con
     if (c.j_stage == kSymStage) {
         // the symmetric tiles when their padded records and slot partials fit the area
         // (the chosen block edge, else the larger one, which needs fewer partials)
-        for (int blk : {c.j_tile / 64, 32}) {
+        // (the chosen block edge and j parts, else whole tiles, else the larger block edge,
+        // which needs fewer partials)
+        const int blk0 = c.j_tile / 64;
+        const std::pair<int, int> tries[] = {{blk0, c.j_split}, {blk0, 1}, {32, 1}};
+        for (const auto &bs : tries) {
+            const int blk = bs.first;
             const size_t recs = align256((size_t)sym_npad(n, blk) * rbytes);
-            if (recs + sym_partial_bytes(n, blk) > kScratchBytes) continue;
+            if (recs + sym_partial_bytes(n, blk, bs.second) > kScratchBytes) continue;
             FwdWs lay{};
             lay.rec_off = 0;
             lay.part_off = recs;
             lay.scratch_off = lay.total = kScratchBytes;
             Cfg cb = c;
             cb.j_tile = blk * 64;
+            cb.j_split = bs.second;
             return run_forward(law, cb, pos, params, n, nullptr, n, make_epi(law, out_force, out_potential),
                                pot, base, lay, (hipStream_t)stream, nullptr, ExclArgs{}, false);
         }
@@ -2060,6 +2092,7 @@ int backward_impl(const double *pos, const double *params, int64_t n, const nbod
         a.pot = 0;
         a.blk = blk;
         a.ich = c.ipl;
+        a.split = c.j_split;
         a.nblk = spad / ((int64_t)blk * 64);
         a.npad = spad;
         a.n = n;

@@ -89,13 +89,15 @@ struct SymLaunch {
     int prec, pot;                 // P_KAHAN or P_FP64ACC tile sums; potential on/off (forces)
     int blk;                       // block edge in chunks of 64 records: 16 or 32
     int ich;                       // i chunks per wave: 2 (8-wave workgroups) or 4 (4-wave workgroups)
+    int split;                     // j parts per tile (1, 2 or 4), one workgroup each; blk / split
+                                   // must be at least the workgroup's waves
     int64_t nblk;                  // blocks; tiles = nblk (nblk + 1) / 2
     int64_t npad;                  // records = nblk * blk * 64 (zero-mass padding past n)
     int64_t n;                     // rows finished by the reduction
     double eps2;                   // gravity softening squared
     double zeta[4];                // SYM_LJC_SIG: exp(z0 r^3 + z1 r^2 + z2 r + z3), as FwdLaunch::zeta
     const void *rec;               // FP32 records of the operator
-    float4 *partial;               // [nblk][npad] (x, y, z, potential) FP32 slot partials
+    float4 *partial;               // [split * nblk][npad] (x, y, z, potential) FP32 slot partials
     int64_t t0, count;             // order range of the launch's tiles (whole triangle: 0, sym_tiles)
     Epilogue epi;
 };
@@ -149,14 +151,25 @@ __host__ __device__ inline int64_t sym_index_of(int64_t b1, int64_t b2, int64_t 
     const int64_t u = k < h ? k * (k + 1) / 2 + (b1 - r0) : h * (h + 1) / 2 + (k - h) * h + (b1 - r0);
     return sym_strip_start(s, nblk) + u;
 }
+// With the j chunks of each tile cut into `split` parts, the launch's work items are the
+// count * split (tile, part) pairs, the parts of a tile consecutive: workgroup wg of
+// sym_grid(count * split) runs part h of tile (b1, b2).
+__host__ __device__ inline bool sym_item_of(int64_t wg, int64_t nblk, int64_t t0, int64_t count, int split,
+                                            int64_t &b1, int64_t &b2, int &h)
+{
+    const int64_t items = count * split;
+    const int64_t per = sym_grid(items) / kSymXcds;
+    const int64_t local = (wg % kSymXcds) * per + wg / kSymXcds;
+    if (local >= items) return false;
+    h = (int)(local % split);
+    sym_tile_at(t0 + local / split, nblk, b1, b2);
+    return true;
+}
 __host__ __device__ inline bool sym_tile_of(int64_t wg, int64_t nblk, int64_t t0, int64_t count, int64_t &b1,
                                             int64_t &b2)
 {
-    const int64_t per = sym_grid(count) / kSymXcds;
-    const int64_t local = (wg % kSymXcds) * per + wg / kSymXcds;
-    if (local >= count) return false;
-    sym_tile_at(t0 + local, nblk, b1, b2);
-    return true;
+    int h;
+    return sym_item_of(wg, nblk, t0, count, 1, b1, b2, h);
 }
 // Order range of share `share` of `shares` equal shares of the triangle.
 __host__ __device__ inline void sym_share_range(int64_t nblk, int64_t share, int64_t shares, int64_t &t0,

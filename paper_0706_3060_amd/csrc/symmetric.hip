@@ -35,6 +35,15 @@
 // so every (slot, row) is written exactly once.  k_sym_reduce then adds the
 // nblk slots of each row in slot order in FP64 (Neumaier) and applies the
 // epilogue (scales, leapfrog kick).
+//
+// Parts.  For systems that give few tiles per CU, the j chunks of each tile can
+// be cut into `split` parts (2 or 4) run by workgroups of their own, so that
+// the launch's last round of workgroups is shorter.  Part h sweeps chunks
+// h blk/split .. (h + 1) blk/split - 1 of b2 with all the i chunks of b1; its
+// i sums go to slot split b2 + h and the j sums of its chunks' rows to slot
+// split b1 + h of a [split nblk][npad][4] buffer.  The reduction adds, in slot
+// order, every part's slot of the tiles holding a row on their i side and the
+// one part's slot of the tiles holding it on their j side.
 #include "allpairs.h"
 #include "kernels.h"
 
@@ -245,8 +254,11 @@ void k_sym(SymLaunch a)
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int blk = a.blk;
+    const int split = a.split;
+    const int jr = blk / split;                            // j chunks of this part (rounds of a pass)
     int64_t b1, b2;
-    if (!sym_tile_of(blockIdx.x, a.nblk, a.t0, a.count, b1, b2)) return;   // whole workgroup, before any barrier
+    int h;                                                 // the part: j chunks h jr .. h jr + jr - 1 of b2
+    if (!sym_item_of(blockIdx.x, a.nblk, a.t0, a.count, split, b1, b2, h)) return;   // whole workgroup
     const bool diag = b1 == b2;
     PairK<float> kc;
     kc.eps2 = (float)a.eps2;
@@ -258,14 +270,18 @@ void k_sym(SymLaunch a)
     kc.zb2 = (float)(2.0 * a.zeta[1]);
     const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
 
-    // j sums of block b2: blk x 64 float4 of dynamic LDS (sized by the launch for its block
-    // edge, so that 1024-record blocks leave room for more workgroups per CU)
+    // j sums of the part's chunks of block b2: jr x 64 float4 of dynamic LDS (sized by the
+    // launch, so that small parts leave room for more workgroups per CU)
     extern __shared__ float4 jacc[];
     __shared__ R st_all[WAVES][2 * kWave];                // each wave's j chunk, staged twice
     R *st = st_all[w];
-    for (int k = threadIdx.x; k < blk * kWave; k += kThreads) jacc[k] = float4{0, 0, 0, 0};
-    const int64_t jrec0 = b2 * blk * kWave;                // first record of block b2
+    for (int k = threadIdx.x; k < jr * kWave; k += kThreads) jacc[k] = float4{0, 0, 0, 0};
+    const int64_t jrec0 = (b2 * blk + h * jr) * kWave;     // first record of the part's j chunks
     const int64_t irec0 = b1 * blk * kWave;                // first record of block b1
+    // slot of this part's partials: rows of b1 (the i side) in slot split b2 + h, rows of the
+    // part's chunks of b2 (the j side) in slot split b1 + h
+    float4 *const part_i = a.partial + (split * b2 + h) * a.npad;
+    float4 *const part_j = a.partial + (split * b1 + h) * a.npad;
     __syncthreads();
 
     for (int pass = 0; pass < blk / kPass; ++pass) {
@@ -281,20 +297,21 @@ void k_sym(SymLaunch a)
         static_assert(V == 1 || V == 2, "records of one or two 128-bit vectors");
         const float4 *__restrict__ rec4 = (const float4 *)a.rec;
         float4 *st4 = (float4 *)st;
-        int64_t gj = jrec0 + (int64_t)(w % blk) * kWave + lane;
+        int64_t gj = jrec0 + (int64_t)(w % jr) * kWave + lane;
         float4 g0 = rec4[gj * V], g1 = V == 2 ? rec4[gj * V + 1] : float4{0, 0, 0, 0};
-        for (int r = 0; r < blk; ++r) {
-            const int q = (w + r) % blk;
+        for (int r = 0; r < jr; ++r) {
+            const int ql = (w + r) % jr;                   // the part's chunk of this round
+            const int q = h * jr + ql;                     // the same chunk, counted in block b2
             st4[lane * V] = g0;
             st4[(lane + kWave) * V] = g0;
             if (V == 2) {
                 st4[lane * V + 1] = g1;
                 st4[(lane + kWave) * V + 1] = g1;
             }
-            gj = jrec0 + (int64_t)((w + r + 1) % blk) * kWave + lane;
+            gj = jrec0 + (int64_t)((w + r + 1) % jr) * kWave + lane;
             g0 = rec4[gj * V];
             if (V == 2) g1 = rec4[gj * V + 1];
-            const float4 j4 = jacc[q * kWave + lane];
+            const float4 j4 = jacc[ql * kWave + lane];
             float jv[4] = {j4.x, j4.y, j4.z, j4.w};
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -325,36 +342,40 @@ void k_sym(SymLaunch a)
                 }
                 sym_minitile<OP, ICH, POT, true>(st, iv, kc, bp_addr, p, jv, wi, wj, self);
             }
-            jacc[q * kWave + lane] = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
+            jacc[ql * kWave + lane] = float4{jv[0], jv[1], jv[2], POT ? jv[3] : 0.0f};
 #pragma unroll
             for (int k = 0; k < ICH; ++k)
 #pragma unroll
                 for (int c = 0; c < 4; ++c) acc[k][c].fold(p[k][c]);
             __syncthreads();
         }
-        // i sums of this pass: slot b2 of the rows of block b1, or, on the diagonal, added
-        // to the j sums of the same rows (no other wave touches these chunks now)
+        // i sums of this pass: the i-side slot of the rows of block b1, or, on the diagonal,
+        // added to the j sums of the same rows where the chunk is one of the part's (no other
+        // wave touches these chunks now); the diagonal's other chunks have i sums only
 #pragma unroll
         for (int k = 0; k < ICH; ++k) {
             const float4 v = float4{(float)acc[k][0].value(), (float)acc[k][1].value(),
                                     (float)acc[k][2].value(), POT ? (float)acc[k][3].value() : 0.0f};
-            if (!diag) {
-                a.partial[b2 * a.npad + irec0 + (int64_t)(aloc + k) * kWave + lane] = v;
+            const int c = aloc + k;
+            if (!diag || c / jr != h) {
+                part_i[irec0 + (int64_t)c * kWave + lane] = v;
             } else {
-                float4 &t = jacc[(aloc + k) * kWave + lane];
+                float4 &t = jacc[(c - h * jr) * kWave + lane];
                 t = float4{t.x + v.x, t.y + v.y, t.z + v.z, t.w + v.w};
             }
         }
         __syncthreads();
     }
-    // j sums: slot b1 of the rows of block b2
-    for (int q = w; q < blk; q += WAVES) a.partial[b1 * a.npad + jrec0 + (int64_t)q * kWave + lane] = jacc[q * kWave + lane];
+    // j sums: the j-side slot of the rows of the part's chunks of block b2
+    for (int ql = w; ql < jr; ql += WAVES) part_j[jrec0 + (int64_t)ql * kWave + lane] = jacc[ql * kWave + lane];
 }
 
-// Row r: the nblk slot partials in slot order (FP64, Neumaier), then the epilogue.  When
-// the launch covered one share of the tiles, slot k of a row of block b holds a partial
-// only if tile (min(b, k), max(b, k)) is in the share; the other slots are skipped (the
-// test is the same for every row of a workgroup: 256 rows lie in one block).
+// Row r of block b: its slot partials in slot order (FP64, Neumaier), then the epilogue.  A
+// tile (b, k), k >= b, holds r on its i side: each of its parts wrote a partial for r (slots
+// split k .. split k + split - 1).  A tile (k, b), k < b, holds r on its j side: only the part
+// whose chunks include r's wrote one (slot split k + h_r).  When the launch covered one share
+// of the tiles, only the tiles in the share count (the test is the same for every row of a
+// workgroup: 256 rows lie in one block).
 __global__ __launch_bounds__(256) void k_sym_reduce(SymLaunch a)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -363,16 +384,20 @@ __global__ __launch_bounds__(256) void k_sym_reduce(SymLaunch a)
     const float4 *__restrict__ part = a.partial;
     const bool whole = a.t0 == 0 && a.count == sym_tiles(a.nblk);
     const int64_t b = r / ((int64_t)a.blk * kWave);
+    const int split = a.split;
+    const int hr = (int)((r % ((int64_t)a.blk * kWave)) / kWave) / (a.blk / split);   // r's part
     for (int64_t k = 0; k < a.nblk; ++k) {
         if (!whole) {
             const int64_t t = b <= k ? sym_index_of(b, k, a.nblk) : sym_index_of(k, b, a.nblk);
             if (t < a.t0 || t >= a.t0 + a.count) continue;
         }
-        const float4 x = part[k * a.npad + r];
-        v[0].add((double)x.x);
-        v[1].add((double)x.y);
-        v[2].add((double)x.z);
-        v[3].add((double)x.w);
+        for (int hh = k < b ? hr : 0; hh < (k < b ? hr + 1 : split); ++hh) {
+            const float4 x = part[(split * k + hh) * a.npad + r];
+            v[0].add((double)x.x);
+            v[1].add((double)x.y);
+            v[2].add((double)x.z);
+            v[3].add((double)x.w);
+        }
     }
     const Epilogue &e = a.epi;
     double f0 = e.fscale * v[0].value(), f1 = e.fscale * v[1].value(), f2 = e.fscale * v[2].value();
@@ -410,8 +435,8 @@ static hipError_t launch_sym_op(const SymLaunch &a, dim3 grid, dim3 block, size_
 template <int WAVES, int ICH>
 static hipError_t launch_sym_shape(const SymLaunch &a, hipStream_t s)
 {
-    const dim3 grid((unsigned)sym_grid(a.count)), block(WAVES * kWave);
-    const size_t lds = (size_t)a.blk * kWave * sizeof(float4);       // the j sums of one block
+    const dim3 grid((unsigned)sym_grid(a.count * a.split)), block(WAVES * kWave);
+    const size_t lds = (size_t)(a.blk / a.split) * kWave * sizeof(float4);   // the j sums of one part
     switch (a.op) {
     case SYM_FORCE: return launch_sym_op<SYM_FORCE, WAVES, ICH>(a, grid, block, lds, s);
     case SYM_HVP: return launch_sym_op<SYM_HVP, WAVES, ICH>(a, grid, block, lds, s);
@@ -427,6 +452,10 @@ hipError_t launch_sym(const SymLaunch &a, hipStream_t s)
     if (a.nblk <= 0 || a.count <= 0) return hipSuccess;
     if (a.blk % 16 != 0 || a.blk > kSymMaxBlk || a.npad != (int64_t)a.nblk * a.blk * kWave ||
         a.t0 < 0 || a.t0 + a.count > sym_tiles(a.nblk))
+        return hipErrorInvalidValue;
+    // j parts of at least as many chunks as the workgroup has waves (distinct chunks per round)
+    const int waves = a.ich == 2 ? 8 : 4;
+    if ((a.split != 1 && a.split != 2 && a.split != 4) || a.blk % a.split != 0 || a.blk / a.split < waves)
         return hipErrorInvalidValue;
     if (a.ich == 2) return launch_sym_shape<8, 2>(a, s);
     if (a.ich == 4) return launch_sym_shape<4, 4>(a, s);

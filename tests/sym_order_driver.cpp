@@ -9,7 +9,8 @@
 // and it reports the most distinct blocks that the tiles of 96 consecutive
 // workgroups of one XCD touch (the blocks its L2 holds at a time with 32 CUs
 // of 3 workgroups).  Prints one line per block count and exits non-zero on the
-// first violation.
+// first violation.  The launches with the j chunks of each tile cut into 2 or 4 parts
+// (sym_item_of) must run every (tile, part) exactly once.
 #include "kernels.h"
 
 #include <cstdio>
@@ -83,6 +84,46 @@ int main(int argc, char **argv)
         if (count != tiles) {
             std::printf("nblk=%lld: %lld of %lld tiles\n", (long long)nblk, (long long)count, (long long)tiles);
             return 1;
+        }
+        // j parts: every (tile, part) exactly once, the parts of a tile on one XCD next to
+        // each other, fewer than kSymXcds idle workgroups
+        for (int split : {2, 4}) {
+            std::vector<char> seen_p((size_t)(nblk * nblk * split), 0);
+            const int64_t grid = nbk::sym_grid(tiles * split);
+            int64_t idle_p = 0;
+            for (int64_t wg = 0; wg < grid; ++wg) {
+                int64_t b1 = -1, b2 = -1;
+                int h = -1;
+                if (!nbk::sym_item_of(wg, nblk, 0, tiles, split, b1, b2, h)) {
+                    ++idle_p;
+                    continue;
+                }
+                char &c = seen_p[(size_t)((b1 * nblk + b2) * split + h)];
+                if (b1 < 0 || b2 < b1 || b2 >= nblk || h < 0 || h >= split || c) {
+                    std::printf("nblk=%lld split=%d: item (%lld, %lld, %d) invalid or twice\n", (long long)nblk,
+                                split, (long long)b1, (long long)b2, h);
+                    return 1;
+                }
+                c = 1;
+                // the previous workgroup of this XCD ran the previous part of the same tile
+                if (h > 0 && wg >= nbk::kSymXcds) {
+                    int64_t p1, p2;
+                    int ph;
+                    if (!nbk::sym_item_of(wg - nbk::kSymXcds, nblk, 0, tiles, split, p1, p2, ph) || p1 != b1 ||
+                        p2 != b2 || ph != h - 1) {
+                        std::printf("nblk=%lld split=%d: parts of (%lld, %lld) not consecutive\n", (long long)nblk,
+                                    split, (long long)b1, (long long)b2);
+                        return 1;
+                    }
+                }
+            }
+            int64_t c = 0;
+            for (char x : seen_p) c += x;
+            if (c != tiles * split || idle_p >= nbk::kSymXcds) {
+                std::printf("nblk=%lld split=%d: %lld of %lld items, %lld idle\n", (long long)nblk, split,
+                            (long long)c, (long long)(tiles * split), (long long)idle_p);
+                return 1;
+            }
         }
         // shares, each in a launch of its own
         for (int64_t shares : {1, 2, 3, 8, 13}) {

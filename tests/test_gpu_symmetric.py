@@ -76,6 +76,54 @@ def test_symmetric_ragged_sizes(nb, j_tile, prec, shape):
             nb.clear_config(nb.API_FORCES)
 
 
+# (workgroup shape, j_tile, j parts per tile): every allowed combination (a part needs at least
+# as many chunks as the workgroup has waves)
+PART_CASES = [((512, 2), 1024, 2), ((512, 2), 2048, 2), ((512, 2), 2048, 4), ((256, 4), 1024, 2),
+              ((256, 4), 1024, 4), ((256, 4), 2048, 2), ((256, 4), 2048, 4)]
+
+
+@pytest.mark.parametrize("shape,j_tile,split", PART_CASES)
+def test_symmetric_j_parts(nb, shape, j_tile, split):
+    """The j chunks of each tile cut into 2 or 4 parts, one workgroup each (j_split with
+    j_stage 2): each part writes its own i-side slot and the j-side slot of its own rows, and the
+    reduction adds a row's slots in order.  Ragged sizes against the oracle, potential on and
+    off, both tile-sum precisions, G != 1; a single-block system is one diagonal tile in parts."""
+    for prec in ("fp32_kahan", "fp32_fp64acc"):
+        law = nb.gravity(prec, softening=0.01, G=1.3)
+        for k, n in enumerate([2, 65, 1025, 2049, 3001, 5000]):
+            x, _, m = W.plummer(n, 540 + k)
+            m = m * np.random.default_rng(k).uniform(0.5, 1.5, n)
+            nb.set_config(nb.API_FORCES, shape[0], shape[1], j_tile, split, 2)
+            try:
+                c = nb.get_config(nb.API_FORCES, n, law)
+                assert (c["j_stage"], c["j_split"], c["block"]) == (2, split, shape[0]), c
+                for potential in (True, False):
+                    f, p = nb.forces(dev(x), dev(m), law, potential=potential)
+                    check(f, p, x, m, 0.01, 1.3, potential)
+            finally:
+                nb.clear_config(nb.API_FORCES)
+
+
+def test_symmetric_j_parts_repeat_and_match_whole_tiles(nb):
+    # at N = 70,000 with 4 parts per tile: bit-for-bit repeatable, and equal to whole tiles to
+    # the FP32 bar (the parts group the j sums differently)
+    n = 70000
+    x, _, m = W.plummer(n, 545)
+    law = nb.gravity("fp32_kahan", softening=0.01)
+    X, M = dev(x), dev(m)
+    out = {}
+    for split in (1, 4):
+        nb.set_config(nb.API_FORCES, 256, 4, 1024, split, 2)
+        try:
+            out[split] = [nb.forces(X, M, law) for _ in range(2)]
+        finally:
+            nb.clear_config(nb.API_FORCES)
+    (f1, p1), (f2, p2) = out[4]
+    assert torch.equal(f1, f2) and torch.equal(p1, p2)
+    e = row_errors(host(f1), host(out[1][0][0]))
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3
+
+
 @pytest.mark.parametrize("shape", [(512, 2), (256, 4)])
 def test_symmetric_without_softening_and_with_G(nb, shape):
     # eps = 0: the self pair of every diagonal chunk must be masked, not evaluated at r = 0
@@ -172,15 +220,16 @@ def test_subset_and_noalloc_fall_back(nb, shape):
     assert np.median(e) <= 1e-5 and e.max() <= 1e-3
 
 
-@pytest.mark.parametrize("n,G,shape", [(3001, 1.0, (512, 2)), (70000, 2.5, (256, 4))])
-def test_shares_add_up_to_the_forces(nb, n, G, shape):
+@pytest.mark.parametrize("n,G,shape,split", [(3001, 1.0, (512, 2), 1), (70000, 2.5, (256, 4), 1),
+                                              (5000, 1.0, (256, 4), 4)])
+def test_shares_add_up_to_the_forces(nb, n, G, shape, split):
     """nbody_forces_share: the shares of the tile triangle (what each of several GPUs would
     evaluate) add up to the whole evaluation; one share is the whole evaluation bit for bit.
     The sum of 8 shares also meets the oracle on sampled rows."""
     x, _, m = W.plummer(n, 710 + n % 97)
     law = nb.gravity("fp32_kahan", softening=0.01, G=G)
     X, M = dev(x), dev(m)
-    nb.set_config(nb.API_FORCES, shape[0], shape[1], 1024, 1, 2)
+    nb.set_config(nb.API_FORCES, shape[0], shape[1], 1024, split, 2)
     try:
         f_full, p_full = nb.forces(X, M, law)
         f1, p1 = nb.forces_share(X, M, law, 0, 1)
@@ -221,9 +270,9 @@ def test_share_more_shares_than_tiles(nb):
     assert (total - f_full).abs().max().item() <= 1e-5 * f_full.abs().max().item()
 
 
-@pytest.mark.parametrize("shape", [(512, 2), (256, 4)])
+@pytest.mark.parametrize("shape,split", [((512, 2), 1), ((256, 4), 1), ((256, 4), 4)])
 @pytest.mark.parametrize("prec", ["fp32_kahan", "fp32_fp64acc"])
-def test_symmetric_position_adjoint(nb, shape, prec):
+def test_symmetric_position_adjoint(nb, shape, split, prec):
     """Gravity's position adjoint (the Hessian-vector product) over unordered pairs: the pair's
     term for one particle is minus its term for the other.  Ragged sizes against the oracle's
     adjoint, with G != 1 and unequal masses; the rule's choice repeats bit for bit."""
@@ -232,10 +281,10 @@ def test_symmetric_position_adjoint(nb, shape, prec):
         x, _, m = W.plummer(n, 930 + k)
         m = m * np.random.default_rng(k).uniform(0.5, 1.5, n)
         g = np.random.default_rng(40 + k).standard_normal((n, 3))
-        nb.set_config(nb.API_BACKWARD, shape[0], shape[1], 1024, 1, 2)
+        nb.set_config(nb.API_BACKWARD, shape[0], shape[1], 1024, split, 2)
         try:
             c = nb.get_config(nb.API_BACKWARD, n, law)
-            assert (c["j_stage"], c["block"], c["i_per_lane"]) == (2,) + shape, c
+            assert (c["j_stage"], c["block"], c["i_per_lane"], c["j_split"]) == (2,) + shape + (split,), c
             gp, _, _ = nb.forces_backward(dev(x), dev(m), dev(g), law)
         finally:
             nb.clear_config(nb.API_BACKWARD)

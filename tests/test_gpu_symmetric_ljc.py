@@ -99,6 +99,22 @@ def test_ljc_symmetric_ragged_sizes(nb, kind, shape, j_tile, prec):
 
 
 @pytest.mark.parametrize("kind", KINDS)
+def test_ljc_symmetric_j_parts(nb, kind):
+    # each tile's j chunks in 4 parts, one workgroup each
+    law = gpu_law(nb, kind, "fp32_kahan")
+    for k, n in enumerate([65, 2049, 3001]):
+        s = system(n, 330 + k)
+        fr, ur = oracle_law(kind, W.round_to_f32(s.pos), s)
+        nb.set_config(nb.API_FORCES, 256, 4, 1024, 4, 2)
+        try:
+            assert nb.get_config(nb.API_FORCES, n, law)["j_split"] == 4
+            f, u = nb.forces(dev(s.pos), dev(s.params()), law)
+        finally:
+            nb.clear_config(nb.API_FORCES)
+        check(host(f), host(u), fr, ur)
+
+
+@pytest.mark.parametrize("kind", KINDS)
 def test_ljc_symmetric_is_the_rule_and_repeats_bitwise(nb, big, kind):
     s, n = big, 70000
     law = gpu_law(nb, kind, "fp32_kahan")
