@@ -36,7 +36,7 @@
  * the default from N = 65,536 to 2,097,152) evaluate each unordered pair once
  * and apply it to both particles through per-block partial sums that a
  * fixed-order reduction adds, without atomics; the batched entry point has
- * symmetric tiles of its own for gravity and LJC(linear) ensembles.  Either
+ * symmetric tiles of its own for gravity and LJC ensembles.  Either
  * way results are deterministic run to run.
  *
  * Conventions shared by every entry point
@@ -183,7 +183,7 @@ typedef struct nbody_exclusions {
  *             to 2,097,152 particles (its per-block partials
  *             grow as n^2: 8.6 GB at n = 2^20, 34 GB at 2^21; elsewhere 2
  *             reads as 1).  For nbody_forces_batched, j_stage 2 selects the
- *             batched symmetric tiles (gravity and LJC(linear) with
+ *             batched symmetric tiles (gravity and the LJC laws with
  *             FP32_KAHAN or FP32_FP64ACC, no exclusion lists, every system of
  *             at most 8192 particles; otherwise the launch runs one-sided),
  *             in a fixed shape (block 256, i_per_lane 4, j_tile 256, j_split
@@ -291,7 +291,7 @@ int nbody_forces_share(const double *pos, const double *params, int64_t n, const
  * refused with NBODY_EINVAL before anything is enqueued.
  * Decompositions (nbody_config.j_stage): one-sided units of rows against
  * parts of their system's j range (each ordered pair evaluated), or, for
- * gravity and LJC(linear) with FP32 pair arithmetic and systems of at most
+ * every law with FP32 pair arithmetic and systems of at most
  * 8192 particles, symmetric tiles of 256 x 256 records (each unordered pair
  * of a system evaluated once, per-system FP32 slot partials added in a fixed
  * order in FP64).  The workspace covers both: for those laws it holds up to

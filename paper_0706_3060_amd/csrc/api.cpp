@@ -1372,6 +1372,7 @@ int run_bsym(const nbody_law *law, const int64_t *offsets, int64_t S, const doub
     a.n_red = (int64_t)plan.red.size() / 2;
     a.n_systems = S;
     a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    for (int c = 0; c < 4; ++c) a.zeta[c] = law->kind == NBODY_LAW_LJC_SIGMOIDAL ? law->zeta[c] : 0.0;
     a.rec = base + lay.rec_off;
     a.partial = (float4 *)(base + lay.part_off);
     a.epi = make_epi(law, out_force, out_pot);

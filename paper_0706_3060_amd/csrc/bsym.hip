@@ -1,7 +1,7 @@
 // Symmetric pair tiles for the batched entry points: in every system of an
 // ensemble each unordered pair {i, j} is evaluated once and its force applied
 // to both particles (Newton's third law), the small-system setting of Section
-// 3.4 with the pair arithmetic of Eq. 1 (gravity) or Table 1's LJC(linear).
+// 3.4 with the pair arithmetic of Eq. 1 (gravity) or one of Table 1's LJC laws.
 //
 // Decomposition.  The records of system s are padded to nb_s blocks of 256
 // (four chunks of 64).  A work unit is one tile (s, b1, b2), b1 <= b2, and one
@@ -42,31 +42,32 @@ __device__ __forceinline__ float bs_next_lane_dpp(float v)
     return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
 }
 
-// i-particle state of a lane (position and the law's own parameters)
-template <int LAW> struct BsI;
+// i-particle state of a lane (position and the law's own parameters; every LJC dielectric has
+// the same)
+template <int LAW> struct BsI { float x, y, z, qs, sh, se; };
 template <> struct BsI<GRAVITY> { float x, y, z, m; };
-template <> struct BsI<LJC> { float x, y, z, qs, sh, se; };
 
 __device__ __forceinline__ void bs_load(const GravRec<float> *rec, int64_t p, BsI<GRAVITY> &s)
 {
     const GravRec<float> r = rec[p];
     s = BsI<GRAVITY>{r.x, r.y, r.z, r.m};
 }
-__device__ __forceinline__ void bs_load(const LjcRec<float> *rec, int64_t p, BsI<LJC> &s)
+template <int LAW>
+__device__ __forceinline__ void bs_load(const LjcRec<float> *rec, int64_t p, BsI<LAW> &s)
 {
     const LjcRec<float> r = rec[p];
-    s = BsI<LJC>{r.x, r.y, r.z, r.qs, r.sh, r.se};
+    s = BsI<LAW>{r.x, r.y, r.z, r.qs, r.sh, r.se};
 }
 
 // One unordered pair (i of this lane, j of the step): i-side sums p, j-side sums jv.
 // SELF: the i side only (a pair of the chunk with itself, seen from both lanes), with the
 // particle's own pair (step 0) neutralised.  JSIDE: add the j side.
 template <bool POT, bool JSIDE>
-__device__ __forceinline__ void bs_pair(const BsI<GRAVITY> &i, const GravRec<float> &J, float eps2, bool self0,
-                                        float (&p)[4], float (&jv)[4])
+__device__ __forceinline__ void bs_pair(const BsI<GRAVITY> &i, const GravRec<float> &J, const PairK<float> &k,
+                                        bool self0, float (&p)[4], float (&jv)[4])
 {
     const float dx = J.x - i.x, dy = J.y - i.y, dz = J.z - i.z;
-    float r2 = fma_(dx, dx, eps2);
+    float r2 = fma_(dx, dx, k.eps2);
     r2 = fma_(dy, dy, r2);
     r2 = fma_(dz, dz, r2);
     float mj = J.m;
@@ -88,11 +89,12 @@ __device__ __forceinline__ void bs_pair(const BsI<GRAVITY> &i, const GravRec<flo
     }
 }
 
-// LJC(linear): F_i += W (r_i - r_j), F_j -= W (r_i - r_j); both get the pair's 2 u_ij
-// (the potential sums carry 2u, halved by the epilogue), as the one-sided ljc_pair.
-template <bool POT, bool JSIDE>
-__device__ __forceinline__ void bs_pair(const BsI<LJC> &i, const LjcRec<float> &J, float, bool self0,
-                                        float (&p)[4], float (&jv)[4])
+// LJC: F_i += W (r_i - r_j), F_j -= W (r_i - r_j); both get the pair's energy term (2 u_ij for
+// the linear dielectric, halved by the epilogue; u_ij for the others), from the scalar part
+// of the pair that the one-sided ljc_pair uses (ljc_terms).
+template <bool POT, bool JSIDE, int LAW>
+__device__ __forceinline__ void bs_pair(const BsI<LAW> &i, const LjcRec<float> &J, const PairK<float> &k,
+                                        bool self0, float (&p)[4], float (&jv)[4])
 {
     const float dx = J.x - i.x, dy = J.y - i.y, dz = J.z - i.z;
     float r2 = dx * dx;
@@ -103,23 +105,12 @@ __device__ __forceinline__ void bs_pair(const BsI<LJC> &i, const LjcRec<float> &
     r2 = self0 ? 1.0f : r2;
     qq = self0 ? 0.0f : qq;
     e = self0 ? 0.0f : e;
-    const float x = rcp_(r2);
-    const float cx = qq * x;
-    const float sg = i.sh + J.sh;
-    const float s2 = (sg * sg) * x;
-    const float s6 = (s2 * s2) * s2;
-    const float lj = e * s6;                       // 24 eps_ij (sigma_ij / r)^6
-    const float t = fma_(s6, 2.0f, -1.0f);
-    const float W = fma_(lj, t, cx) * x;           // (24 eps_ij (2 s^12 - s^6) + qq x) / r^2
+    float W, u = 0.0f;
+    ljc_terms<POT, LAW>(r2, qq, e, i.sh + J.sh, k, W, u);
     p[0] = fma_(-W, dx, p[0]);
     p[1] = fma_(-W, dy, p[1]);
     p[2] = fma_(-W, dz, p[2]);
-    float u = 0.0f;
-    if (POT) {
-        const float v = fma_(lj, s6, -lj);         // 24 eps_ij (s^12 - s^6)
-        u = fma_(v, 1.0f / 3.0f, cx);              // 2 u_ij
-        p[3] += u;
-    }
+    if (POT) p[3] += u;
     if (JSIDE) {
         jv[0] = fma_(W, dx, jv[0]);
         jv[1] = fma_(W, dy, jv[1]);
@@ -131,7 +122,7 @@ __device__ __forceinline__ void bs_pair(const BsI<LJC> &i, const LjcRec<float> &
 // One mini-sweep: the wave's four i chunks against the j chunk staged in `st`.  DIAG: i chunk
 // k pairs symmetrically only when q > k, one-sidedly when q == k, and not when q < k.
 template <int LAW, bool POT, bool DIAG, typename R>
-__device__ __forceinline__ void bs_sweep(const R *st, const BsI<LAW> (&iv)[kBSymChunks], float eps2, int q,
+__device__ __forceinline__ void bs_sweep(const R *st, const BsI<LAW> (&iv)[kBSymChunks], const PairK<float> &kc, int q,
                                          int bp_addr, float (&p)[kBSymChunks][4], float (&jv)[4])
 {
     const int lane = lane_id();
@@ -141,11 +132,11 @@ __device__ __forceinline__ void bs_sweep(const R *st, const BsI<LAW> (&iv)[kBSym
 #pragma unroll
         for (int k = 0; k < kBSymChunks; ++k) {
             if (!DIAG) {
-                bs_pair<POT, true>(iv[k], J, eps2, false, p[k], jv);
+                bs_pair<POT, true>(iv[k], J, kc, false, p[k], jv);
             } else if (k < q) {
-                bs_pair<POT, true>(iv[k], J, eps2, false, p[k], jv);
+                bs_pair<POT, true>(iv[k], J, kc, false, p[k], jv);
             } else if (k == q) {
-                bs_pair<POT, false>(iv[k], J, eps2, t == 0, p[k], jv);
+                bs_pair<POT, false>(iv[k], J, kc, t == 0, p[k], jv);
             }
         }
 #pragma unroll
@@ -154,8 +145,12 @@ __device__ __forceinline__ void bs_sweep(const R *st, const BsI<LAW> (&iv)[kBSym
     }
 }
 
+// waves per SIMD the register allocation aims at: four with Kahan sums (128 VGPRs), three with
+// FP64 sums or the sigmoidal dielectric's longer sequence
+template <int LAW, int PREC> constexpr int bsym_waves_per_eu() { return PREC == P_KAHAN && LAW != LJC_SIG ? 4 : 3; }
+
 template <int LAW, int PREC, bool POT>
-__global__ __launch_bounds__(kBSymWaves * kWave) __attribute__((amdgpu_waves_per_eu(PREC == P_KAHAN ? 4 : 3))) void k_bsym(BSymLaunch a)
+__global__ __launch_bounds__(kBSymWaves * kWave) __attribute__((amdgpu_waves_per_eu(bsym_waves_per_eu<LAW, PREC>()))) void k_bsym(BSymLaunch a)
 {
     using R = typename RecOf<float, LAW>::type;
     const R *__restrict__ rec = (const R *)a.rec;
@@ -176,7 +171,14 @@ __global__ __launch_bounds__(kBSymWaves * kWave) __attribute__((amdgpu_waves_per
     const int64_t irec0 = po + b1 * kBSymRecords, jrec0 = po + b2 * kBSymRecords;
     float4 *slots = a.partial + a.systab[3 * s + 2];            // [nb][npad] of system s
     R *st = st_all[w];
-    const float eps2 = (float)a.eps2;
+    PairK<float> kc;
+    kc.eps2 = (float)a.eps2;
+    kc.za = (float)a.zeta[0];
+    kc.zb = (float)a.zeta[1];
+    kc.zc = (float)a.zeta[2];
+    kc.zd = (float)a.zeta[3];
+    kc.za3 = (float)(3.0 * a.zeta[0]);
+    kc.zb2 = (float)(2.0 * a.zeta[1]);
     const int bp_addr = ((lane + 1) & (kWave - 1)) * 4;
 
     BsI<LAW> iv[kBSymChunks];
@@ -208,8 +210,8 @@ __global__ __launch_bounds__(kBSymWaves * kWave) __attribute__((amdgpu_waves_per
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[k][c].begin(p[k][c]);
         float jv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (!diag) bs_sweep<LAW, POT, false>(st, iv, eps2, q, bp_addr, p, jv);
-        else bs_sweep<LAW, POT, true>(st, iv, eps2, q, bp_addr, p, jv);
+        if (!diag) bs_sweep<LAW, POT, false>(st, iv, kc, q, bp_addr, p, jv);
+        else bs_sweep<LAW, POT, true>(st, iv, kc, q, bp_addr, p, jv);
 #pragma unroll
         for (int k = 0; k < kBSymChunks; ++k)
 #pragma unroll
@@ -281,7 +283,8 @@ static void bsym_go(const BSymLaunch &a, const dim3 &grid, const dim3 &block, hi
 
 bool bsym_supported(int law, int prec)
 {
-    return (law == GRAVITY || law == LJC) && (prec == P_KAHAN || prec == P_FP64ACC);
+    return (law == GRAVITY || law == LJC || law == LJC_CONST || law == LJC_SIG) &&
+           (prec == P_KAHAN || prec == P_FP64ACC);
 }
 
 hipError_t launch_bsym(const BSymLaunch &a, hipStream_t s)
@@ -289,12 +292,14 @@ hipError_t launch_bsym(const BSymLaunch &a, hipStream_t s)
     if (a.n_units <= 0) return hipSuccess;
     if (!bsym_supported(a.law, a.prec)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((a.n_units + kBSymWaves - 1) / kBSymWaves)), block(kBSymWaves * kWave);
-    if (a.law == GRAVITY) {
-        if (a.prec == P_KAHAN) bsym_go<GRAVITY, P_KAHAN>(a, grid, block, s);
-        else bsym_go<GRAVITY, P_FP64ACC>(a, grid, block, s);
-    } else {
-        if (a.prec == P_KAHAN) bsym_go<LJC, P_KAHAN>(a, grid, block, s);
-        else bsym_go<LJC, P_FP64ACC>(a, grid, block, s);
+    const bool kahan = a.prec == P_KAHAN;
+    switch (a.law) {
+    case GRAVITY: kahan ? bsym_go<GRAVITY, P_KAHAN>(a, grid, block, s) : bsym_go<GRAVITY, P_FP64ACC>(a, grid, block, s); break;
+    case LJC: kahan ? bsym_go<LJC, P_KAHAN>(a, grid, block, s) : bsym_go<LJC, P_FP64ACC>(a, grid, block, s); break;
+    case LJC_CONST:
+        kahan ? bsym_go<LJC_CONST, P_KAHAN>(a, grid, block, s) : bsym_go<LJC_CONST, P_FP64ACC>(a, grid, block, s);
+        break;
+    default: kahan ? bsym_go<LJC_SIG, P_KAHAN>(a, grid, block, s) : bsym_go<LJC_SIG, P_FP64ACC>(a, grid, block, s);
     }
     return hipGetLastError();
 }

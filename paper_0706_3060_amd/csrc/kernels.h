@@ -221,7 +221,7 @@ hipError_t launch_pack_batched(const BatchPackLaunch &p, hipStream_t s);
 hipError_t launch_batched(const BatchLaunch &b, hipStream_t s);
 int batched_max_blocks_per_cu(int law, int prec, int ipl, int pot, int js, int block, int excl);
 
-// ---- batched symmetric pair tiles (bsym.hip): gravity or LJC(linear), every unordered pair of a
+// ---- batched symmetric pair tiles (bsym.hip): gravity or an LJC law, every unordered pair of a
 // system once, one wave per tile of two 256-record blocks ----
 constexpr int kBSymRecords = 256;          // records per block (four chunks of 64)
 constexpr int64_t kBSymMaxSystem = 8192;   // largest system of a symmetric batched launch (32 blocks)
@@ -236,6 +236,7 @@ struct BSymLaunch {
     int64_t n_red;
     int64_t n_systems;
     double eps2;
+    double zeta[4];              // the sigmoidal dielectric's coefficients, as FwdLaunch::zeta
     const void *rec;             // FP32 records
     float4 *partial;             // per system [nb][npad] (x, y, z, potential) FP32 slot partials
     Epilogue epi;

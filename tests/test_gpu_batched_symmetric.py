@@ -4,7 +4,7 @@ system evaluated once, one wave per tile of two 256-record blocks) against the F
 System sizes are ragged around the chunk (64) and block (256) edges and reach the largest
 system the tiles take (8192, 32 blocks), with empty and one-particle systems between them,
 so that every kind of tile occurs: off-diagonal, diagonal with one-sided self chunks, and
-padding.  Gravity and LJC(linear), both FP32 tile-sum precisions, potential on and off; the
+padding.  Gravity and the three LJC laws, both FP32 tile-sum precisions, potential on and off; the
 result repeats bit for bit and agrees with the one-sided persistent launch; an ensemble with
 a system above 8192 falls back to the one-sided launch; exclusion lists fall back too.
 """
@@ -18,6 +18,8 @@ from paper_0706_3060_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 EPS = 0.01
+ZC = (2e-4, -6e-3, 0.25, 0.4)           # the sigmoidal dielectric of the per-law tests
+KIND = {"ljc_linear": 1, "ljc_constant": 2, "ljc_sigmoidal": 3}
 SIZES = [300, 0, 1, 2, 63, 64, 65, 255, 256, 257, 700, 1, 1024, 1500, 2048, 2049, 4000]
 BSYM = (256, 4, 256, 1, 2)
 
@@ -62,7 +64,13 @@ def ensemble(law, sizes, seed):
 
 
 def gpu_law(nb, law, prec):
-    return nb.gravity(prec, softening=EPS) if law == "gravity" else nb.ljc_linear(prec)
+    if law == "gravity":
+        return nb.gravity(prec, softening=EPS)
+    if law == "ljc_linear":
+        return nb.ljc_linear(prec)
+    if law == "ljc_constant":
+        return nb.ljc_constant(prec, dielectric=4.0)
+    return nb.ljc_sigmoidal(ZC, prec)
 
 
 def check_system(law, x, par, f, p, potential):
@@ -77,8 +85,15 @@ def check_system(law, x, par, f, p, potential):
         fr, ur = oracle.gravity(xr, pr, eps=EPS)
         scale = np.abs(ur)
     else:
-        fr, ur = oracle.ljc_linear(xr, pr[:, 0], pr[:, 1], pr[:, 2])
-        scale = oracle.ljc_energy_abs(1, xr, pr[:, 0], pr[:, 1], pr[:, 2])
+        q, sg, ep = pr[:, 0], pr[:, 1], pr[:, 2]
+        if law == "ljc_linear":
+            fr, ur = oracle.ljc_linear(xr, q, sg, ep)
+        elif law == "ljc_constant":
+            fr, ur = oracle.ljc_constant(xr, q, sg, ep, D=4.0)
+        else:
+            fr, ur = oracle.ljc_sigmoidal(xr, q, sg, ep, ZC)
+        scale = oracle.ljc_energy_abs(KIND[law], xr, q, sg, ep, D=4.0,
+                                      zeta_coef=ZC if law == "ljc_sigmoidal" else None)
     e = row_errors(f, fr)
     assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (n, np.median(e), e.max())
     if potential:
@@ -96,7 +111,7 @@ def run(nb, off, x, par, lw, potential, cfg):
         nb.clear_config(nb.API_BATCHED)
 
 
-@pytest.mark.parametrize("law", ["gravity", "ljc_linear"])
+@pytest.mark.parametrize("law", ["gravity", "ljc_linear", "ljc_constant", "ljc_sigmoidal"])
 @pytest.mark.parametrize("prec", ["fp32_kahan", "fp32_fp64acc"])
 @pytest.mark.parametrize("potential", [True, False])
 def test_batched_symmetric_against_the_oracle(nb, law, prec, potential):
