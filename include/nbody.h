@@ -360,7 +360,14 @@ int nbody_forces_backward_excl(const double *pos, const double *params, int64_t 
  * launch, as the batched forward.  Arguments as nbody_forces_backward over
  * the concatenated rows; with types, grad_type_params sums over the atoms of
  * each type across all systems.  Laws: gravity and LJC(linear) (exclusions:
- * LJC(linear)).  Workspace:
+ * LJC(linear)).  Decompositions as nbody_forces_batched: one-sided units,
+ * or, with FP32 pair arithmetic, no exclusion lists and every system of at
+ * most 8192 particles, symmetric tiles of 256 x 256 records (j_stage 2, the
+ * rule's choice when systems average 512 particles or more): each unordered
+ * pair's adjoint terms evaluated once and applied to both particles (the
+ * position terms of the two are opposite; the charge, sigma and epsilon
+ * terms share one scalar), per-system FP32 slot partials added in a fixed
+ * order in FP64.  Workspace:
  * nbody_workspace_bytes(NBODY_API_BACKWARD_BATCHED, offsets[S], S, law).
  * Plan tables as nbody_forces_batched (shared with it for the same ensemble
  * and launch shape). */

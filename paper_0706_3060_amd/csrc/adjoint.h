@@ -60,6 +60,30 @@ struct AdjPackLaunch {
 hipError_t launch_pack_adjoint(const AdjPackLaunch &p, hipStream_t s);
 hipError_t launch_adjoint(const AdjLaunch &a, hipStream_t s);
 hipError_t launch_adjoint_reduce(const AdjLaunch &a, hipStream_t s);
+// Batched adjoint over unordered pairs (bsym_adj.hip): one wave per tile (s, b1, b2) of two
+// 256-record blocks of a system, the tiles and row blocks listed by the plan of the batched
+// symmetric tiles (kernels.h BSymLaunch); records from the batched adjoint pack, systems padded
+// to whole blocks.
+struct BSymAdjLaunch {
+    int law, prec;
+    int64_t n_units;
+    const int32_t *units;        // [n_units][4] = (system, b1, b2, 0), b1 <= b2
+    const int64_t *off, *poff;   // [S+1] caller rows and record offsets (whole blocks)
+    const int64_t *systab;       // [S][3] = (blocks nb, 0, first slot row of the system)
+    const int32_t *red;          // [n_red][2] (system, row block of 256)
+    int64_t n_red;
+    int64_t n_systems;
+    double eps2, G, qscale;
+    const void *rec;             // FP32 adjoint records
+    float4 *partial;             // per system [nb][npad][bsym_adj_sums(law) / 4 rounded up] FP32 slot sums
+    const double *params;        // caller params (LJC: the epsilon gradient's scale)
+    double *grad_pos;            // [n][3] or null
+    double *grad_params;         // [n][3] or null (LJC)
+};
+bool bsym_adj_supported(int law, int prec);
+int bsym_adj_sums(int law);      // sums per particle: 3 (gravity) or 6 (LJC)
+hipError_t launch_bsym_adj(const BSymAdjLaunch &a, hipStream_t s);
+hipError_t launch_bsym_adj_reduce(const BSymAdjLaunch &a, hipStream_t s);
 // per-type sums of grad_params columns 1 and 2 into out [n_types][2], through
 // partial [blocks][n_types][2] (partial_doubles doubles; at least 2 n_types)
 hipError_t launch_type_reduce(const double *grad_params, const int32_t *types, int64_t n,

@@ -213,7 +213,8 @@ bool ipl_ok(int v) { return v == 1 || v == 2 || v == 4 || v == 8; }
 
 Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
 {
-    if (c.j_stage == kSymStage && api == NBODY_API_BATCHED && bsym_supported(law, prec)) {
+    if (c.j_stage == kSymStage && ((api == NBODY_API_BATCHED && bsym_supported(law, prec)) ||
+                                   (api == NBODY_API_BACKWARD_BATCHED && bsym_adj_supported(law, prec)))) {
         c.block = kBSymWaves * 64;                    // the batched symmetric tiles' fixed shape
         c.ipl = kBSymRecords / 64;
         c.j_tile = kBSymRecords;
@@ -394,7 +395,9 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         // the symmetric tiles for systems of 512 particles on average and more (smaller ones
         // lose too much to the padding of 256-record blocks and the diagonal tiles; a launch
         // with a system above 8192 particles runs one-sided all the same)
-        if (api == NBODY_API_BATCHED && allow_sym && bsym_supported(law, prec) && n >= 512 * std::max<int64_t>(S, 1)) {
+        // (the batched adjoint's tiles: 1.77 against 2.42-2.47 ms for the 256-system LJC ensemble)
+        const bool tiles = api == NBODY_API_BATCHED ? bsym_supported(law, prec) : bsym_adj_supported(law, prec);
+        if (allow_sym && tiles && n >= 512 * std::max<int64_t>(S, 1)) {
             c.j_stage = kSymStage;
             return sanitize(c, api, law, prec, 64);
         }
@@ -734,15 +737,21 @@ BatWs bat_layout(const nbody_law *law, int64_t n_total, int64_t S)
 // part sums of split systems (8 doubles per row; half the forward's slot count).
 struct AdjBatWs {
     size_t rec_off, unit_off, off_off, poff_off, systab_off, red_off, part_off, ticket_off, type_off, total;
+    size_t part_bytes;
     int64_t max_slots, max_units, max_records;
 };
+
+// the batched adjoint's symmetric tiles apply to this law and precision
+bool law_has_bsym_adj(const nbody_law *law) { return bsym_adj_supported(law->kind, law->precision); }
 
 AdjBatWs adjb_layout(const nbody_law *law, int64_t n_total, int64_t S)
 {
     AdjBatWs w{};
-    const int64_t npad_max = n_total + 64 * std::max<int64_t>(S, 1);
+    // records padded per system to 64 (one-sided) or to 256 (symmetric tiles)
+    const int64_t npad_max = n_total + kBSymRecords * std::max<int64_t>(S, 1);
     w.max_slots = std::max<int64_t>(1, batch_slot_cap(n_total, S) / 2);
-    const int64_t units_max = n_total / 64 + std::max<int64_t>(S, 1) + 1 + 2 * w.max_slots;
+    const int64_t units_max = std::max(n_total / 64 + std::max<int64_t>(S, 1) + 1 + 2 * w.max_slots,
+                                       bsym_units_bound(n_total, S));
     w.max_units = units_max;
     w.max_records = npad_max;
     size_t off = 0;
@@ -759,7 +768,13 @@ AdjBatWs adjb_layout(const nbody_law *law, int64_t n_total, int64_t S)
     w.red_off = off;
     off = align256(off + (size_t)red_capacity(n_total, S) * 2 * sizeof(int32_t));
     w.part_off = off;
-    off = align256(off + (size_t)w.max_slots * 128 * 8 * sizeof(double));
+    // the one-sided part sums or the symmetric tiles' slot partials (3 or 6 FP32 sums per slot
+    // row, in 128-bit vectors)
+    w.part_bytes = std::max((size_t)w.max_slots * 128 * 8 * sizeof(double),
+                            law_has_bsym_adj(law) ? bsym_slot_bytes_bound(n_total, S) *
+                                                        (size_t)((bsym_adj_sums(law->kind) + 3) / 4)
+                                                  : (size_t)0);
+    off = align256(off + w.part_bytes);
     w.ticket_off = off;
     off = align256(off + 256);
     w.type_off = off;
@@ -2199,6 +2214,82 @@ int nbody_forces_batched_excl(const int64_t *offsets, int64_t n_systems, const d
                         ws_bytes, stream, nullptr, excl);
 }
 
+namespace {
+
+// whether the adjoint's symmetric tiles take this ensemble: law and precision, no exclusion
+// lists, and every system within kBSymMaxSystem
+bool bsym_adj_takes(const nbody_law *law, const int64_t *offsets, int64_t S, bool excl)
+{
+    if (excl || !law_has_bsym_adj(law)) return false;
+    for (int64_t s = 0; s < S; ++s)
+        if (offsets[s + 1] - offsets[s] > kBSymMaxSystem) return false;
+    return true;
+}
+
+// pack (systems padded to blocks of 256) + symmetric adjoint tiles + slot-ordered reduction
+int run_bsym_adj(const nbody_law *law, const int64_t *offsets, int64_t S, const double *pos,
+                 const double *params, const double *grad_force, double *grad_pos, double *grad_params,
+                 void *ws, const AdjBatWs &lay, hipStream_t s)
+{
+    std::shared_ptr<const BatchPlan> pp = cached_plan(offsets, S, kBSymPlanKey, 0);
+    const BatchPlan &plan = *pp;
+    if (plan.units.empty()) return NBODY_OK;
+    const int nv = (bsym_adj_sums(law->kind) + 3) / 4;
+    if ((int64_t)plan.units.size() / 4 > lay.max_units || plan.npad_total > lay.max_records ||
+        (size_t)plan.n_slots * (size_t)nv * 4 * sizeof(float) > lay.part_bytes ||
+        (int64_t)plan.red.size() / 2 > red_capacity(offsets[S], S))
+        return fail(NBODY_EWORKSPACE, "internal: batched symmetric adjoint plan exceeds its workspace regions "
+                    "(%lld tiles, %lld slot rows)", (long long)(plan.units.size() / 4), (long long)plan.n_slots);
+    char *base = (char *)ws;
+    DevTables tab;
+    int rc = batched_tables(plan, offsets, S, kBSymPlanKey, 0, s, base, lay.unit_off, lay.off_off, lay.poff_off,
+                            lay.systab_off, lay.red_off, &tab);
+    if (rc) return rc;
+    AdjBatchLaunch pk{};
+    pk.law = law->kind;
+    pk.prec = law->precision;
+    pk.n_systems = S;
+    pk.npad_total = plan.npad_total;
+    pk.off = tab.off;
+    pk.poff = tab.poff;
+    pk.pos = pos;
+    pk.params = params;
+    pk.g = grad_force;
+    pk.qscale = qscale_of(law);
+    pk.rec = base + lay.rec_off;
+    pk.ticket_zeroed = 0;                      // no work ticket: one wave per listed tile
+    hipError_t e = launch_pack_adjoint_batched(pk, s);
+    if (e != hipSuccess) return hip_fail(e, "batched adjoint pack");
+    BSymAdjLaunch a{};
+    a.law = law->kind;
+    a.prec = law->precision;
+    a.n_units = (int64_t)plan.units.size() / 4;
+    a.units = tab.units;
+    a.off = tab.off;
+    a.poff = tab.poff;
+    a.systab = tab.systab;
+    a.red = tab.red;
+    a.n_red = (int64_t)plan.red.size() / 2;
+    a.n_systems = S;
+    a.eps2 = law->kind == NBODY_LAW_GRAVITY ? law->softening * law->softening : 0.0;
+    a.G = law->G;
+    a.qscale = qscale_of(law);
+    a.rec = base + lay.rec_off;
+    a.partial = (float4 *)(base + lay.part_off);
+    a.params = params;
+    a.grad_pos = grad_pos;
+    a.grad_params = grad_params;
+    Timer t(s);
+    e = launch_bsym_adj(a, s);
+    t.stop();
+    if (e != hipSuccess) return hip_fail(e, "batched symmetric adjoint kernel");
+    e = launch_bsym_adj_reduce(a, s);
+    if (e != hipSuccess) return hip_fail(e, "batched symmetric adjoint reduction");
+    return NBODY_OK;
+}
+
+}  // namespace
+
 int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, const double *pos,
                                   const double *params, const nbody_exclusions *excl,
                                   const nbody_law *law, const double *grad_force, double *grad_pos,
@@ -2226,7 +2317,22 @@ int nbody_forces_backward_batched(const int64_t *offsets, int64_t n_systems, con
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    const Cfg c = with_excl(choose(NBODY_API_BACKWARD_BATCHED, law, n, n_systems, false), excl != nullptr);
+    Cfg c = choose(NBODY_API_BACKWARD_BATCHED, law, n, n_systems, false);
+    if (c.j_stage == kSymStage) {
+        if (bsym_adj_takes(law, offsets, n_systems, excl != nullptr)) {
+            rc = run_bsym_adj(law, offsets, n_systems, pos, params, grad_force, grad_pos, grad_params, ws, lay, s);
+            if (rc) return rc;
+            if (types) {
+                const hipError_t e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params,
+                                                        (double *)((char *)ws + lay.type_off), kTypePartDoubles, s);
+                if (e != hipSuccess) return hip_fail(e, "per-type reduction");
+            }
+            return NBODY_OK;
+        }
+        // a system above the tiles' size, or exclusion lists: the rule's one-sided configuration
+        c = heuristic(NBODY_API_BACKWARD_BATCHED, law->kind, law->precision, n, n, n_systems, false, false);
+    }
+    c = with_excl(c, excl != nullptr);
     const int ipl = std::min(c.ipl, 2);
     AdjBatchLaunch a{};
     a.law = law->kind;

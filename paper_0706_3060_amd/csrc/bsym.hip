@@ -32,16 +32,6 @@ namespace nbk {
 constexpr int kBSymWaves = 4;                       // waves (independent tiles) per workgroup
 constexpr int kBSymChunks = kBSymRecords / kWave;   // chunks per block = i chunks per lane
 
-// the value of lane (l + 1) mod 64: through the LDS crossbar, or by a DPP rotation
-__device__ __forceinline__ float bs_next_lane(int byte_addr, float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, v)));
-}
-__device__ __forceinline__ float bs_next_lane_dpp(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
-}
-
 // i-particle state of a lane (position and the law's own parameters; every LJC dielectric has
 // the same)
 template <int LAW> struct BsI { float x, y, z, qs, sh, se; };
@@ -140,8 +130,8 @@ __device__ __forceinline__ void bs_sweep(const R *st, const BsI<LAW> (&iv)[kBSym
             }
         }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) jv[c] = bs_next_lane(bp_addr, jv[c]);
-        if (POT) jv[3] = bs_next_lane_dpp(jv[3]);
+        for (int c = 0; c < 3; ++c) jv[c] = from_next_lane(bp_addr, jv[c]);
+        if (POT) jv[3] = from_next_lane_dpp(jv[3]);
     }
 }
 

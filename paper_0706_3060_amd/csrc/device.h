@@ -282,6 +282,18 @@ struct NSum {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// The value of lane (l + 1) mod 64, for the symmetric tiles' j sums that travel with their
+// particle: through the LDS crossbar (ds_bpermute, no LDS memory; byte_addr = 4 ((l + 1) mod 64)),
+// or on the VALU by a DPP rotation of the whole wave by one lane (wave_rol:1).
+__device__ __forceinline__ float from_next_lane(int byte_addr, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ float from_next_lane_dpp(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
+}
+
 // Fixed-order sum of the nsplit partials of row r (part s at
 // partial + s * part_stride + r * width, NC columns) by a group of G lanes (G
 // a power of two <= 64, groups aligned in the wave): lane q of the group adds

@@ -50,18 +50,6 @@
 namespace nbk {
 
 
-// the value of lane (l + 1) mod 64, through the LDS crossbar (no LDS memory)
-__device__ __forceinline__ float from_next_lane(int byte_addr, float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(byte_addr, __builtin_bit_cast(int, v)));
-}
-
-// the same move on the VALU: a DPP rotation of the whole wave by one lane (wave_rol:1)
-__device__ __forceinline__ float from_next_lane_dpp(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x134, 0xF, 0xF, false));
-}
-
 // The pair operators.  SYM_FORCE: Eq. 1 (i side m_j r^-3 d, j side -m_i r^-3 d, potentials
 // m_j / r and m_i / r).  SYM_HVP: the position adjoint of Eq. 1 (a Hessian-vector product):
 // with w = m_i g_j - m_j g_i, the i side adds t = s^-3 (w - 3 s^-2 (d.w) d) and the j side -t

@@ -205,7 +205,8 @@ def test_config_validation(N):
     grav = lambda prec: N.NBodyLaw(0, prec, 1.0, 0.01, 0.0, 1.0)
     ljc = N.NBodyLaw(1, 1, 1.0, 0.0, 332.0637, 4.0)
     # the batched entry point keeps j_stage 2 as its own symmetric tiles (every law with FP32 pair
-    # arithmetic), in their fixed shape of 4 waves over 256-record blocks
+    # arithmetic), in their fixed shape of 4 waves over 256-record blocks; so does the batched
+    # backward for the laws it differentiates (gravity and LJC(linear))
     # the single-system tiles take the forces and leapfrog of every law and gravity's backward
     # (LJC's backward and FP64 pair arithmetic run one-sided)
     ljc_const = N.NBodyLaw(2, 1, 1.0, 0.0, 332.0637, 4.0)
@@ -216,7 +217,8 @@ def test_config_validation(N):
              (0, N.NBodyLaw(1, 0, 1.0, 0.0, 332.0637, 4.0), None),
              (1, ljc, "bsym"), (1, grav(1), "bsym"), (1, grav(0), None),
              (1, ljc_const, "bsym"), (1, ljc_sig, "bsym"), (2, grav(1), "sym"), (2, ljc, None), (2, ljc_const, None),
-             (4, grav(1), None), (5, grav(2), None), (6, ljc, None)]
+             (4, grav(1), None), (5, grav(2), None), (6, ljc, "bsym"), (6, grav(2), "bsym"),
+             (6, ljc_const, None), (6, grav(0), None)]
     for api, law, kind in cases:
         c = N.NBodyConfig()
         try:
