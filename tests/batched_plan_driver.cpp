@@ -104,14 +104,18 @@ void walk(const BatchPlan &p, const std::vector<int64_t> &off, int ipl, size_t r
 // The batched symmetric tiles' plan: every system's upper triangle of blocks exactly once, slot
 // partials inside the system's slots and the workspace's bound, the reduction list over every
 // row block of 256, records inside their region.
-void walk_bsym(const BatchPlan &p, const std::vector<int64_t> &off, const BatWs &lay)
+// a plan of the symmetric tiles against a workspace: its unit and record capacities and its
+// partial region, which holds row_bytes per slot row (16 for the forward's four FP32 sums, 16 or
+// 32 for the adjoint's three or six)
+void walk_bsym(const BatchPlan &p, const std::vector<int64_t> &off, int64_t max_units, int64_t max_records,
+               size_t part_bytes, size_t row_bytes)
 {
     const int64_t S = (int64_t)off.size() - 1;
-    EXPECT((int64_t)p.units.size() / 4 <= lay.max_units, "bsym: %zu tiles > %lld", p.units.size() / 4,
-           (long long)lay.max_units);
-    EXPECT(p.npad_total <= lay.max_records, "bsym: %lld records > %lld", (long long)p.npad_total,
-           (long long)lay.max_records);
-    EXPECT((size_t)p.n_slots * 16 <= lay.part_bytes, "bsym: %lld slot partials exceed the partial region",
+    EXPECT((int64_t)p.units.size() / 4 <= max_units, "bsym: %zu tiles > %lld", p.units.size() / 4,
+           (long long)max_units);
+    EXPECT(p.npad_total <= max_records, "bsym: %lld records > %lld", (long long)p.npad_total,
+           (long long)max_records);
+    EXPECT((size_t)p.n_slots * row_bytes <= part_bytes, "bsym: %lld slot rows exceed the partial region",
            (long long)p.n_slots);
     EXPECT((int64_t)p.red.size() / 2 <= red_capacity(off.back(), S), "bsym: reduction list overruns");
     std::vector<std::vector<char>> seen((size_t)S);
@@ -233,7 +237,15 @@ int main(int argc, char **argv)
                 for (int64_t s = 0; s < S; ++s) fits = fits && off[s + 1] - off[s] <= kBSymMaxSystem;
                 EXPECT(takes == fits, "bsym_takes %d for an ensemble whose systems fit: %d", (int)takes, (int)fits);
                 EXPECT(!bsym_takes(lw, off.data(), S, true), "bsym_takes with exclusion lists");
-                if (takes) walk_bsym(plan_bsym(off.data(), S), off, blay);
+                if (takes) walk_bsym(plan_bsym(off.data(), S), off, blay.max_units, blay.max_records, blay.part_bytes, 16);
+                // the batched adjoint's tiles, in the adjoint's workspace
+                const AdjBatWs alay = adjb_layout(lw, n, S);
+                const bool atakes = bsym_adj_takes(lw, off.data(), S, false);
+                EXPECT(atakes == fits, "bsym_adj_takes %d for an ensemble whose systems fit: %d", (int)atakes, (int)fits);
+                EXPECT(!bsym_adj_takes(lw, off.data(), S, true), "bsym_adj_takes with exclusion lists");
+                if (atakes)
+                    walk_bsym(plan_bsym(off.data(), S), off, alay.max_units, alay.max_records, alay.part_bytes,
+                              (size_t)(bsym_adj_sums(lw->kind) + 3) / 4 * 16);
             }
         }
         std::printf("%s: S=%lld n=%lld plans=%d max_units=%lld/%lld max_slot_rows=%lld/%lld violations=%d\n",
