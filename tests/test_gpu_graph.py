@@ -143,10 +143,15 @@ def _replay_batched(nb, off, X, P, offb, Xb, Pb, law):
         assert torch.equal(fb, fb_ref)
 
 
-def test_backward_batched_replay(nb):
-    off, X, P = _ensemble(SIZES_A, 83)
+@pytest.mark.parametrize("tiles", [False, True])
+def test_backward_batched_replay(nb, tiles):
+    # the rule takes the adjoint's symmetric tiles when every system fits 8192 particles; with
+    # the 9000-particle system the launch runs one-sided
+    off, X, P = _ensemble(SIZES_A if not tiles else [s if s <= 8192 else 8000 for s in SIZES_A], 83)
     g_in = dev(np.random.default_rng(5).standard_normal((int(off[-1]), 3)))
     law = nb.ljc_linear("fp32_kahan")
+    c = nb.get_config(nb.API_BACKWARD_BATCHED, int(off[-1]), law, n_systems=len(off) - 1)
+    assert c["j_stage"] == 2, c                     # the rule (a 9000-particle system runs one-sided)
     ref = nb.forces_backward_batched(off, X, P, g_in, law)
     torch.cuda.synchronize()
     warm_on_side_stream(lambda: nb.forces_backward_batched(off, X, P, g_in, law))
