@@ -12,7 +12,8 @@ scale of the system rather than to its own tiny norm; potentials are held normwi
 row, to S_i = sum_j |u_ij| (see check_potential), at every size.  The batched test draws ensembles of
 up to 24 systems of 0 to 400 particles (empty and one-particle systems included) for the
 persistent launch and compares each system with its own oracle call; the adjoint and the
-acceleration-and-jerk, exclusion-list and integrator tests do the same for those paths.
+acceleration-and-jerk, exclusion-list and integrator tests, and the batched adjoint over random
+ensembles, do the same for those paths.
 Examples are drawn
 from a fixed seed (derandomize), so every run checks the same cases.
 """
@@ -185,8 +186,8 @@ def test_random_batches(nb, sizes, law, prec, block, ipl, j_tile, j_stage, per_w
     """The persistent batched launch over random ensembles (empty and one-particle systems
     included) with a forced configuration equals the oracle system by system.  The work-unit
     target per wave (the batched j_split) decides how far large systems are cut into parts;
-    j_stage 2 selects the symmetric tiles (gravity and LJC(linear) with FP32 pair arithmetic;
-    elsewhere it reads as 1)."""
+    j_stage 2 selects the symmetric tiles (every law with FP32 pair arithmetic; with FP64 it
+    reads as 1)."""
     lw = gpu_law(nb, law, prec)
     off, x, par = ensemble(law, sizes, seed)
     try:
@@ -214,6 +215,52 @@ def test_random_batches(nb, sizes, law, prec, block, ipl, j_tile, j_stage, per_w
 
 def rel_to_max(got, ref):
     return np.abs(got - ref) / max(np.abs(ref).max(), 1e-300)
+
+
+@settings(max_examples=60, deadline=None, derandomize=True, database=None,
+          suppress_health_check=[HealthCheck.too_slow, HealthCheck.function_scoped_fixture])
+@given(sizes=st.lists(st.integers(min_value=0, max_value=400), min_size=0, max_size=16),
+       law=st.sampled_from(["gravity", "ljc_linear"]),
+       prec=st.sampled_from(["fp64", "fp32_kahan", "fp32_fp64acc"]),
+       ipl=st.sampled_from([1, 2]),
+       j_stage=st.sampled_from([0, 1, 2]),
+       per_wave=st.sampled_from([1, 8]),
+       seed=st.integers(min_value=0, max_value=10 ** 6))
+def test_random_batched_adjoints(nb, sizes, law, prec, ipl, j_stage, per_wave, seed):
+    """The batched adjoint over random ensembles (empty and one-particle systems included)
+    under a forced configuration equals the oracle's analytic adjoint system by system (as the
+    single-system adjoints).  j_stage 2 selects the adjoint's symmetric tiles for FP32 pair
+    arithmetic (with FP64 it reads as 1)."""
+    lw = gpu_law(nb, law, prec)
+    off, x, par = ensemble(law, sizes, seed)
+    n = int(off[-1])
+    g = W.unit_cotangent(n, seed + 3) if n else np.zeros((0, 3))
+    try:
+        nb.set_config(nb.API_BACKWARD_BATCHED, 256, ipl, 256, per_wave, j_stage)
+        gp, gq, _ = nb.forces_backward_batched(off, dev(x), dev(par), dev(g), lw)
+    finally:
+        nb.clear_config(nb.API_BACKWARD_BATCHED)
+    gp = host(gp)
+    gq = host(gq) if gq is not None else None
+    for s in range(len(sizes)):
+        a, b = int(off[s]), int(off[s + 1])
+        if b - a < 2:
+            assert np.all(gp[a:b] == 0) and (gq is None or np.all(gq[a:b] == 0))
+            continue
+        xs, ps = x[a:b], par[a:b]
+        xr = xs if prec == "fp64" else W.round_to_f32(xs)
+        if law == "gravity":
+            refs = [(gp[a:b], oracle.gravity_adjoint(xr, ps, g[a:b], eps=EPS), True)]
+        else:
+            rp, rq, rs, re = oracle.ljc_adjoint(xr, ps[:, 0], ps[:, 1], ps[:, 2], g[a:b])
+            refs = [(gp[a:b], rp, True), (gq[a:b, 0], rq, False), (gq[a:b, 1], rs, False),
+                    (gq[a:b, 2], re, False)]
+        for got, ref, rows in refs:
+            e = row_errors(got, ref) if rows else rel_to_max(got, ref)
+            if prec == "fp64":
+                assert e.max() <= 1e-10, (s, e.max(), law, prec)
+            else:
+                assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (s, np.median(e), e.max(), law, prec)
 
 
 @settings(max_examples=80, deadline=None, derandomize=True, database=None,
