@@ -309,7 +309,10 @@ int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double
  *              for LJC, with F_i = sum_j w(r) d_ij,
  *                dL/dr_k = sum_{j!=k} [w u + (w'/r)(d.u) d],  u = g_j - g_k.
  *  grad_params [n][P] device or NULL: LJC only, per-atom dL/dq, dL/dsigma,
- *              dL/depsilon (gravity: must be NULL).
+ *              dL/depsilon (gravity: must be NULL).  The mixing rule
+ *              eps_ij = sqrt(eps_i eps_j) has no finite derivative at
+ *              eps_k = 0: an atom with epsilon 0 gets a non-finite
+ *              dL/depsilon (its other gradients are unaffected).
  *  types, n_types, grad_type_params: optional (LJC only).  When types
  *              (device int32 [n], values in [0, n_types)) is non-NULL,
  *              grad_type_params [n_types][2] device receives the sums of
