@@ -20,7 +20,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnbody.so")
 SOURCES = ["forward.hip", "batched.hip", "adjoint.hip", "jerk.hip", "probe.hip", "noalloc.hip", "symmetric.hip",
-           "bsym.hip", "bsym_adj.hip", "api.cpp"]
+           "bsym.hip", "bsym_adj.hip", "symjerk.hip", "api.cpp"]
 ARCH = "gfx950"
 
 

@@ -108,6 +108,23 @@ constexpr int64_t kSymMaxN = int64_t(1) << 21;
 // whole-tile launch fills the chip only a few rounds deep
 constexpr int64_t kSymSplitMaxN = int64_t(1) << 17;
 
+// The acceleration-and-jerk tiles (symjerk.hip, j_stage 2 of the jerk entry point): gravity
+// with FP32 pair arithmetic, whole systems of up to kSymJerkMaxN particles, one workgroup shape
+// (8 waves of 2 i chunks, blocks of 1024 records) and 1 or 2 j parts; each row gets one FP32
+// partial of 32 bytes per block and part (2 GiB at kSymJerkMaxN).
+constexpr int64_t kSymJerkMaxN = int64_t(1) << 18;
+bool symjerk_ok(int law, int prec)
+{
+    return law == NBODY_LAW_GRAVITY && (prec == NBODY_FP32_KAHAN || prec == NBODY_FP32_FP64ACC);
+}
+int64_t symjerk_npad(int64_t n) { return round_up(std::max<int64_t>(n, 1), (int64_t)kSymJerkBlk * 64); }
+int symjerk_max_split(int64_t n) { return n <= kSymSplitMaxN ? 2 : 1; }
+size_t symjerk_partial_bytes(int64_t n, int split)
+{
+    const int64_t np = symjerk_npad(n);
+    return (size_t)split * (size_t)(np / ((int64_t)kSymJerkBlk * 64)) * (size_t)np * 8 * sizeof(float);
+}
+
 bool sym_eligible(int api, int law, int prec)
 {
     if (prec != NBODY_FP32_KAHAN && prec != NBODY_FP32_FP64ACC) return false;
@@ -222,6 +239,13 @@ Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
         return c;
     }
     if (c.j_stage == kSymStage) {
+        if (api == NBODY_API_JERK && symjerk_ok(law, prec) && npad <= kSymJerkMaxN) {
+            c.block = kSymThreads;                      // the jerk tiles' one shape
+            c.ipl = 2;
+            c.j_tile = kSymJerkBlk * 64;
+            c.j_split = c.j_split >= 2 ? symjerk_max_split(npad) : 1;
+            return c;
+        }
         if (sym_eligible(api, law, prec) && npad <= kSymMaxN) {
             // two workgroup shapes: 8 waves of 2 i chunks, or 4 waves of 4 i chunks
             const bool four = c.ipl >= 4 && c.block <= 256;
@@ -418,6 +442,14 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         // follows the due count (hermite_split_table)
         c.ipl = 1;
         c.j_split = ranked_splits(law, prec, n, nj, c.ipl, pot, c.j_stage, c.block, smax, true)[0];
+        return sanitize(c, api, law, prec, npad);
+    }
+    if (api == NBODY_API_JERK && allow_sym && symjerk_ok(law, prec) && n == nj && n >= kSymMinN &&
+        n <= kSymJerkMaxN) {
+        // whole systems from 65,536 particles: the symmetric tiles, in two j parts up to 2^17
+        // (the tiles fill the chip only a few rounds deep there)
+        c.j_stage = kSymStage;
+        c.j_split = 2;
         return sanitize(c, api, law, prec, npad);
     }
     if (api == NBODY_API_JERK) {
@@ -627,11 +659,17 @@ JerkWs jerk_layout(int api, const nbody_law *law, int64_t n)
     JerkWs w{};
     const int64_t npad = round_up(std::max<int64_t>(n, 1), 64);
     const size_t t = is_f32(law->precision) ? 4 : 8;
+    // the symmetric tiles' records (padded to whole blocks) and slot partials, for the sizes
+    // they take
+    const bool sym = symjerk_ok(law->kind, law->precision) && n <= kSymJerkMaxN;
+    const int64_t nrec = sym ? std::max(npad, symjerk_npad(n)) : npad;
+    size_t part = (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double);
+    if (sym) part = std::max(part, symjerk_partial_bytes(n, symjerk_max_split(n)));
     size_t off = 0;
     w.rec_off = off;
-    off = align256(off + (size_t)npad * 8 * t);
+    off = align256(off + (size_t)nrec * 8 * t);
     w.part_off = off;
-    off = align256(off + (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double));
+    off = align256(off + part);
     if (api == NBODY_API_HERMITE) {
         w.a1_off = off;
         off = align256(off + (size_t)npad * 3 * sizeof(double));
@@ -913,7 +951,12 @@ int run_jerk(const nbody_law *law, const Cfg &c, const JerkPackLaunch &pk_in, co
              int64_t nrows, double *out_acc, double *out_jerk, double *out_pot, void *ws,
              const JerkWs &lay, hipStream_t s)
 {
-    const int64_t npad = round_up(pk_in.n, 64);
+    // the symmetric tiles evaluate every row of the system (the callers pass them no row list)
+    const bool sym = c.j_stage == kSymStage;
+    if (sym && (rows != nullptr || nrows != pk_in.n || !symjerk_ok(law->kind, law->precision) ||
+                pk_in.n > kSymJerkMaxN))
+        return fail(NBODY_EINVAL, "the symmetric jerk tiles evaluate whole systems of FP32 gravity only");
+    const int64_t npad = sym ? symjerk_npad(pk_in.n) : round_up(pk_in.n, 64);
     char *base = (char *)ws;
     JerkPackLaunch pk = pk_in;
     pk.prec = law->precision;
@@ -921,6 +964,29 @@ int run_jerk(const nbody_law *law, const Cfg &c, const JerkPackLaunch &pk_in, co
     pk.rec = base + lay.rec_off;
     hipError_t e = launch_pack_jerk(pk, s);
     if (e != hipSuccess) return hip_fail(e, "jerk pack");
+    if (sym) {
+        SymJerkLaunch a{};
+        a.prec = law->precision;
+        a.pot = out_pot != nullptr;
+        a.split = c.j_split == 2 ? 2 : 1;
+        a.nblk = npad / ((int64_t)kSymJerkBlk * 64);
+        a.npad = npad;
+        a.n = pk_in.n;
+        a.eps2 = law->softening * law->softening;
+        a.G = law->G;
+        a.rec = base + lay.rec_off;
+        a.partial = (float4 *)(base + lay.part_off);
+        a.out_acc = out_acc;
+        a.out_jerk = out_jerk;
+        a.out_pot = out_pot;
+        Timer t(s);
+        e = launch_symjerk(a, s);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "symmetric jerk tiles");
+        e = launch_symjerk_reduce(a, s);
+        if (e != hipSuccess) return hip_fail(e, "symmetric jerk slot reduction");
+        return NBODY_OK;
+    }
     JerkLaunch a{};
     a.prec = law->precision;
     a.ipl = c.ipl;
@@ -967,8 +1033,10 @@ int jerk_impl(const double *pos, const double *vel, const double *mass, int64_t 
     rc = check_ws(ws, ws_bytes, lay.total);
     if (rc) return rc;
     const int64_t npad = round_up(std::max(n, ni), 64);
-    const Cfg c = sanitize(forced ? *forced : choose(NBODY_API_JERK, law, ni, 1, out_potential != nullptr, n),
-                           NBODY_API_JERK, law->kind, law->precision, npad);
+    Cfg c = sanitize(forced ? *forced : choose(NBODY_API_JERK, law, ni, 1, out_potential != nullptr, n),
+                     NBODY_API_JERK, law->kind, law->precision, npad);
+    if (c.j_stage == kSymStage && (ilist || ni != n))   // the tiles take whole systems only
+        c = one_sided(c, NBODY_API_JERK, law, ni, n, out_potential != nullptr);
     JerkPackLaunch pk{};
     pk.n = n;
     pk.pos = pos;
@@ -1759,6 +1827,14 @@ std::vector<Cfg> candidate_set(int api, int law, int prec, int64_t n, bool pot)
                     c = sanitize(c, api, law, prec, npad);
                     if (c.j_split == sp) out.push_back(c);      // (parts not allowed here: skipped)
                 }
+    if (api == NBODY_API_JERK && symjerk_ok(law, prec) && npad <= kSymJerkMaxN)
+        for (int sp : {1, 2}) {                 // the symmetric tiles, whole or in 2 j parts
+            if (sp > symjerk_max_split(npad)) continue;
+            Cfg c;
+            c.j_stage = kSymStage;
+            c.j_split = sp;
+            out.push_back(sanitize(c, api, law, prec, npad));
+        }
     const bool jerk = api == NBODY_API_JERK;
     for (int js : {0, 1})
         for (int ipl : {1, 2, 4, 8}) {
@@ -2482,6 +2558,11 @@ int hermite_step(double *pos, double *vel, double *acc, double *jerk, const doub
     Cfg c = sanitize(choose(NBODY_API_HERMITE, law, n, 1, false, n), NBODY_API_HERMITE, law->kind,
                      law->precision, round_up(n, 64));
     c.j_split = hermite_split_table(law, n, c)->back();   // the block steps' rule for all n rows
+    // a shared step evaluates every row: the symmetric tiles where the acceleration-and-jerk
+    // entry point's configuration for the whole system selects them
+    const Cfg cj = sanitize(choose(NBODY_API_JERK, law, n, 1, false, n), NBODY_API_JERK, law->kind,
+                            law->precision, round_up(n, 64));
+    if (cj.j_stage == kSymStage) c = cj;
     for (int32_t k = 0; k < nsteps; ++k) {
         JerkPackLaunch pk{};
         pk.n = n;

@@ -82,6 +82,25 @@ struct SchedLaunch {
     int fuse_pack;                    // also write the predicted records of the block step
     JerkPackLaunch pack;              // (t_pred_dev = &state->t, pack.n == n)
 };
+// Symmetric pair tiles of the acceleration and jerk (symjerk.hip): each unordered pair of a
+// whole system evaluated once and applied to both particles, FP32 pair arithmetic, per-row
+// FP32 slot partials added in slot order in FP64.
+constexpr int kSymJerkBlk = 16;       // block edge in chunks of 64 records (1024 records)
+struct SymJerkLaunch {
+    int prec, pot;                    // P_KAHAN or P_FP64ACC tile sums; potential on/off
+    int split;                        // j parts per tile (1 or 2), one workgroup each
+    int64_t nblk;                     // blocks; tiles = nblk (nblk + 1) / 2
+    int64_t npad;                     // records = nblk * kSymJerkBlk * 64 (zero-mass padding past n)
+    int64_t n;                        // rows finished by the reduction
+    double eps2, G;
+    const void *rec;                  // GajRec<float> records [npad]
+    float4 *partial;                  // [split * nblk][npad][2]: (a, jerk_x) and (jerk_y, jerk_z, phi, 0)
+    double *out_acc, *out_jerk;       // [n][3]
+    double *out_pot;                  // [n] or null
+};
+hipError_t launch_symjerk(const SymJerkLaunch &a, hipStream_t s);
+hipError_t launch_symjerk_reduce(const SymJerkLaunch &a, hipStream_t s);
+
 hipError_t launch_pack_jerk(const JerkPackLaunch &p, hipStream_t s);
 hipError_t launch_jerk(const JerkLaunch &a, hipStream_t s);
 hipError_t launch_jerk_reduce(const JerkLaunch &a, hipStream_t s);

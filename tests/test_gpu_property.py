@@ -311,14 +311,14 @@ def test_random_adjoints(nb, n, law, prec, block, ipl, j_tile, j_split, j_stage,
        ipl=st.sampled_from([1, 2]),
        j_tile=st.sampled_from([64, 256]),
        j_split=st.integers(min_value=1, max_value=32),
-       j_stage=st.sampled_from([0, 1]),
+       j_stage=st.sampled_from([0, 1, 2]),
        potential=st.booleans(),
        subset=st.booleans(),
        seed=st.integers(min_value=0, max_value=10 ** 6))
 def test_random_jerk(nb, n, prec, block, ipl, j_tile, j_split, j_stage, potential, subset, seed):
     """Acceleration, jerk and potential (Table 1 "Gravity (accel & jerk)") on random Plummer
-    spheres, for all rows or a random row subset, under a forced configuration, against the
-    oracle."""
+    spheres, for all rows or a random row subset, under a forced configuration (the symmetric
+    tiles for whole systems with FP32 pair arithmetic, one-sided otherwise), against the oracle."""
     x, v, m = W.plummer(n, seed)
     rows = None
     if subset:

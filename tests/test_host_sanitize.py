@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 PKG = os.path.join(ROOT, "paper_0706_3060_amd")
 CSRC = os.path.join(PKG, "csrc")
-KERNEL_OBJECTS = ["forward.o", "batched.o", "adjoint.o", "jerk.o", "probe.o", "noalloc.o", "symmetric.o", "bsym.o", "bsym_adj.o"]
+KERNEL_OBJECTS = ["forward.o", "batched.o", "adjoint.o", "jerk.o", "probe.o", "noalloc.o", "symmetric.o", "bsym.o", "bsym_adj.o", "symjerk.o"]
 ROCM_INCLUDE = "/opt/rocm/include"
 ROCM_LIB = "/opt/rocm/lib"
 
