@@ -410,7 +410,17 @@ int leapfrog_step(double *pos, double *vel, double *acc, const double *params,
  *  law        host; kind NBODY_LAW_GRAVITY; precision NBODY_FP64,
  *             NBODY_FP32_FP64ACC or NBODY_FP32_KAHAN (else NBODY_ENOTSUP).
  *  out_acc, out_jerk [ni][3] device; out_potential [ni] device or NULL.
- * Workspace: nbody_workspace_bytes(NBODY_API_JERK, max(n, ni), 1, law). */
+ * Swapping i and j negates d, w and the bracket and leaves s unchanged, so
+ * each unordered pair's terms serve both particles: for every particle
+ * (ilist NULL), FP32 pair arithmetic and up to 262,144 particles,
+ * nbody_config.j_stage 2 selects symmetric pair tiles (blocks of 1024
+ * records, 8 waves of 2 i chunks, 1 or 2 j parts per tile; FP32 slot
+ * partials per row and block added in a fixed order in FP64), the rule's
+ * choice from 65,536 particles; an index list runs one-sided.
+ * Workspace: nbody_workspace_bytes(NBODY_API_JERK, max(n, ni), 1, law); for
+ * FP32 and n <= 262,144 it covers the tiles' records padded to whole blocks
+ * and 32 bytes of slot partials per particle, block and part (1 GiB at
+ * 2^17, 2 GiB at 2^18). */
 int nbody_forces_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
                       const int64_t *ilist, int64_t ni, const nbody_law *law, double *out_acc,
                       double *out_jerk, double *out_potential, void *ws, size_t ws_bytes,
@@ -427,7 +437,10 @@ int nbody_forces_jerk(const double *pos, const double *vel, const double *mass, 
  *  pos, vel, acc, jerk [n][3] device, updated in place; acc and jerk hold
  *  the values at the entry state (e.g. from nbody_forces_jerk).  mass [n]
  *  device.  law as nbody_forces_jerk.  dt > 0 finite, nsteps >= 0.  The
- *  update is FP64; the pair arithmetic follows law->precision.
+ *  update is FP64; the pair arithmetic follows law->precision.  Each step
+ *  evaluates every particle as nbody_forces_jerk would for the whole system
+ *  where its configuration (NBODY_API_JERK) selects the symmetric tiles,
+ *  and otherwise with the NBODY_API_HERMITE configuration.
  * Workspace: nbody_workspace_bytes(NBODY_API_HERMITE, n, 1, law). */
 int hermite_step(double *pos, double *vel, double *acc, double *jerk, const double *mass,
                  int64_t n, const nbody_law *law, double dt, int32_t nsteps, void *ws,

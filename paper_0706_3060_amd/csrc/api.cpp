@@ -544,6 +544,10 @@ Cfg choose(int api, const nbody_law *law, int64_t n, int64_t S, bool pot, int64_
         // a leapfrog step runs the forces kernel, a Hermite step the jerk kernel
         it = g_tuned.find(TuneKey(api == NBODY_API_LEAPFROG ? NBODY_API_FORCES : NBODY_API_JERK,
                                   law->kind, law->precision, pot ? 1 : 0, size_bucket(n), sb));
+    // (the jerk's symmetric tiles evaluate whole systems: not a shape for the block steps, which
+    // a shared Hermite step takes from the jerk's own configuration)
+    if (it != g_tuned.end() && api == NBODY_API_HERMITE && it->second.first.j_stage == kSymStage)
+        it = g_tuned.end();
     if (it != g_tuned.end()) return sanitize(it->second.first, api, law->kind, law->precision, npad);
     return heuristic(api, law->kind, law->precision, n, nj, S, pot);
 }
