@@ -1,8 +1,8 @@
-"""The forward, the leapfrog and the batched forward and adjoint captured in a HIP graph
-(through torch.cuda.graph) and replayed: every launch of these paths is a kernel on the
-caller's stream, with no host synchronisation, memset or host copy inside (the batched
-paths read their plan tables from device memory made at an ensemble's first launch), so a
-captured call can be replayed.
+"""The forward, the leapfrog, the shared Hermite step and the batched forward and adjoint
+captured in a HIP graph (through torch.cuda.graph) and replayed: every launch of these paths is
+a kernel on the caller's stream, with no host synchronisation, memset or host copy inside (the
+batched paths read their plan tables from device memory made at an ensemble's first launch), so
+a captured call can be replayed.
 
 Each test replays the graph several times, with eager work of the library and
 synchronisations between the replays, and checks every replay bit for bit against the
@@ -93,6 +93,44 @@ def test_leapfrog_replay(nb):
             assert torch.equal(got, want), k
         nb.forces(Xw, M, law)                        # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("tiles", [False, True])
+def test_hermite_replay(nb, tiles):
+    """Shared Hermite steps (the predictor's pack, the acceleration and jerk, one-sided or over
+    unordered pairs with their slot reduction, and the corrector) captured and replayed."""
+    x, v, m = W.plummer(3000, 73)
+    law = nb.gravity("fp32_kahan", softening=0.05)
+    M = dev(m)
+    dt, steps = 1.0 / 1024, 2
+    try:
+        nb.set_config(nb.API_JERK, *((512, 2, 1024, 2, 2) if tiles else (256, 1, 256, 4, 0)))
+        a0, j0, _ = nb.forces_jerk(dev(x), dev(v), M, law, potential=False)
+        torch.cuda.synchronize()
+        # eager reference: three calls of two steps
+        Xe, Ve, Ae, Je = dev(x), dev(v), a0.clone(), j0.clone()
+        refs = []
+        for _ in range(3):
+            nb.hermite(Xe, Ve, Ae, Je, M, law, dt, steps)
+            torch.cuda.synchronize()
+            refs.append((Xe.clone(), Ve.clone(), Ae.clone(), Je.clone()))
+        # captured: one call of two steps, replayed three times on the same state
+        Xg, Vg, Ag, Jg = dev(x), dev(v), a0.clone(), j0.clone()
+        Xw, Vw, Aw, Jw = dev(x), dev(v), a0.clone(), j0.clone()
+        warm_on_side_stream(lambda: nb.hermite(Xw, Vw, Aw, Jw, M, law, dt, steps))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            nb.hermite(Xg, Vg, Ag, Jg, M, law, dt, steps)
+        assert torch.equal(Xg, dev(x))                   # capture itself runs nothing
+        for k in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            for got, want in zip((Xg, Vg, Ag, Jg), refs[k]):
+                assert torch.equal(got, want), k
+            nb.forces_jerk(Xw, Vw, M, law)                # eager work between replays
+            torch.cuda.synchronize()
+    finally:
+        nb.clear_config(nb.API_JERK)
 
 
 def _ensemble(sizes, seed):
