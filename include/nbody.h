@@ -324,8 +324,15 @@ int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double
  * Swapping k and j negates both d and m_k g_j - m_j g_k, so gravity's pair
  * term for j is minus its term for k: with FP32 pair arithmetic and 65,536
  * to 2,097,152 particles the rule evaluates each unordered pair once
- * (symmetric pair tiles, as the forward's).
- * Workspace: nbody_workspace_bytes(NBODY_API_BACKWARD, n, 1, law).
+ * (symmetric pair tiles, as the forward's).  LJC(linear)'s position terms
+ * of the two atoms are likewise opposite and its charge, sigma and epsilon
+ * terms share one scalar: with FP32 pair arithmetic, no exclusion lists and
+ * 32,768 to 131,072 atoms the rule evaluates each unordered pair once too
+ * (j_stage 2: the batched backward's tiles of 256 x 256 records over the one
+ * system; any size up to 131,072 when forced).
+ * Workspace: nbody_workspace_bytes(NBODY_API_BACKWARD, n, 1, law); for
+ * LJC(linear) with FP32 and n <= 131,072 it covers 32 bytes of slot
+ * partials per atom and 256-record block (2 GiB at 131,072).
  * Laws: gravity and LJC(linear) (other laws: NBODY_ENOTSUP).
  * Precisions: NBODY_FP64, NBODY_FP32_FP64ACC, NBODY_FP32_KAHAN. */
 int nbody_forces_backward(const double *pos, const double *params, int64_t n,

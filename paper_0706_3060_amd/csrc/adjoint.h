@@ -79,6 +79,10 @@ struct BSymAdjLaunch {
     const double *params;        // caller params (LJC: the epsilon gradient's scale)
     double *grad_pos;            // [n][3] or null
     double *grad_params;         // [n][3] or null (LJC)
+    // or, with units and red null, one whole system of single_n rows (records padded to
+    // single_npad, a multiple of 256): its nb (nb + 1) / 2 tiles taken in the XCD-aware strip
+    // order, its row blocks in order, its slots from partial[0]
+    int64_t single_n, single_npad;
 };
 bool bsym_adj_supported(int law, int prec);
 int bsym_adj_sums(int law);      // sums per particle: 3 (gravity) or 6 (LJC)

@@ -125,6 +125,24 @@ size_t symjerk_partial_bytes(int64_t n, int split)
     return (size_t)split * (size_t)(np / ((int64_t)kSymJerkBlk * 64)) * (size_t)np * 8 * sizeof(float);
 }
 
+// LJC(linear)'s single-system adjoint over unordered pairs: the batched adjoint's tiles
+// (bsym_adj.hip, one wave per tile of two 256-record blocks) over one whole system, FP32 pair
+// arithmetic, up to kSymAdjLjcMaxN atoms (32 bytes of slot partials per atom and block: 2 GiB
+// at 2^17).  The rule takes them from kSymAdjLjcMinN atoms: measured 1.37x the one-sided
+// adjoint's kernel at 32,768 atoms, 1.43x at 65,536 and 1.53x at 131,072 (1.16x at 16,384;
+// at 8,192 the 528 tiles leave most of the chip idle and the one-sided kernel is faster).
+constexpr int64_t kSymAdjLjcMinN = int64_t(1) << 15;
+constexpr int64_t kSymAdjLjcMaxN = int64_t(1) << 17;
+bool symadj_ljc_ok(int law, int prec)
+{
+    return law == NBODY_LAW_LJC_LINEAR && (prec == NBODY_FP32_KAHAN || prec == NBODY_FP32_FP64ACC);
+}
+size_t symadj_ljc_partial_bytes(int64_t n)
+{
+    const int64_t np = round_up(std::max<int64_t>(n, 1), kBSymRecords);
+    return (size_t)(np / kBSymRecords) * (size_t)np * 8 * sizeof(float);
+}
+
 bool sym_eligible(int api, int law, int prec)
 {
     if (prec != NBODY_FP32_KAHAN && prec != NBODY_FP32_FP64ACC) return false;
@@ -239,6 +257,13 @@ Cfg sanitize(Cfg c, int api, int law, int prec, int64_t npad)
         return c;
     }
     if (c.j_stage == kSymStage) {
+        if (api == NBODY_API_BACKWARD && symadj_ljc_ok(law, prec) && npad <= kSymAdjLjcMaxN) {
+            c.block = kBSymWaves * 64;                  // the batched adjoint tiles' fixed shape
+            c.ipl = kBSymRecords / 64;
+            c.j_tile = kBSymRecords;
+            c.j_split = 1;
+            return c;
+        }
         if (api == NBODY_API_JERK && symjerk_ok(law, prec) && npad <= kSymJerkMaxN) {
             c.block = kSymThreads;                      // the jerk tiles' one shape
             c.ipl = 2;
@@ -465,6 +490,11 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         c.j_split = (int)std::max<int64_t>(1, std::min<int64_t>(want, smax));
         return sanitize(c, api, law, prec, npad);
     }
+    if (api == NBODY_API_BACKWARD && allow_sym && symadj_ljc_ok(law, prec) && n == nj && n >= kSymAdjLjcMinN &&
+        n <= kSymAdjLjcMaxN) {
+        c.j_stage = kSymStage;
+        return sanitize(c, api, law, prec, npad);
+    }
     if (api == NBODY_API_BACKWARD) {
         c.ipl = std::min(c.ipl, 2);
         c.j_stage = is_f32(prec) ? 1 : 0;
@@ -634,9 +664,13 @@ AdjWs adj_layout(const nbody_law *law, int64_t n)
     // the gravity position adjoint may run as symmetric pair tiles: records padded to whole
     // blocks and one FP32 partial per row and block, as the forward's
     const bool sym = sym_eligible(NBODY_API_BACKWARD, law->kind, law->precision) && n <= kSymMaxN;
-    const int64_t nrec = sym ? sym_npad(n, 32) : npad;
+    // LJC(linear)'s: records padded to whole 256-record blocks, 32 bytes per row and block
+    const bool ljs = symadj_ljc_ok(law->kind, law->precision) && n <= kSymAdjLjcMaxN;
+    int64_t nrec = sym ? sym_npad(n, 32) : npad;
+    if (ljs) nrec = std::max(nrec, round_up(std::max<int64_t>(n, 1), kBSymRecords));
     size_t part = (size_t)max_split(npad) * (size_t)npad * 8 * sizeof(double);
     if (sym) part = std::max(part, sym_max_partial_bytes(n));
+    if (ljs) part = std::max(part, symadj_ljc_partial_bytes(n));
     size_t off = 0;
     w.rec_off = off;
     off = align256(off + (size_t)nrec * adj_rec_bytes(law->kind, law->precision));
@@ -2166,6 +2200,49 @@ int backward_impl(const double *pos, const double *params, int64_t n, const nbod
                                law->precision, round_up(n, 64)),
                       excl != nullptr);
     char *base = (char *)ws;
+    if (c.j_stage == kSymStage && law->kind == NBODY_LAW_LJC_LINEAR) {
+        // LJC(linear)'s adjoint over unordered pairs (the position terms of the two atoms are
+        // opposite, the charge, sigma and epsilon terms share one scalar): the batched adjoint's
+        // tiles over the one system, then the per-type sums as below
+        const int64_t spad = round_up(n, kBSymRecords);
+        AdjPackLaunch pk{};
+        pk.law = law->kind;
+        pk.prec = law->precision;
+        pk.n = n;
+        pk.npad = spad;
+        pk.pos = pos;
+        pk.params = params;
+        pk.g = grad_force;
+        pk.qscale = qscale_of(law);
+        pk.rec = base + lay.rec_off;
+        hipError_t e = launch_pack_adjoint(pk, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint pack");
+        BSymAdjLaunch b{};
+        b.law = law->kind;
+        b.prec = law->precision;
+        b.n_systems = 1;
+        b.single_n = n;
+        b.single_npad = spad;
+        b.G = law->G;
+        b.qscale = qscale_of(law);
+        b.rec = base + lay.rec_off;
+        b.partial = (float4 *)(base + lay.part_off);
+        b.params = params;
+        b.grad_pos = grad_pos;
+        b.grad_params = grad_params;
+        Timer t(s);
+        e = launch_bsym_adj(b, s);
+        t.stop();
+        if (e != hipSuccess) return hip_fail(e, "symmetric LJC adjoint tiles");
+        e = launch_bsym_adj_reduce(b, s);
+        if (e != hipSuccess) return hip_fail(e, "symmetric LJC adjoint reduction");
+        if (types) {
+            e = launch_type_reduce(grad_params, types, n, n_types, grad_type_params,
+                                   (double *)(base + lay.type_off), kTypePartDoubles, s);
+            if (e != hipSuccess) return hip_fail(e, "per-type reduction");
+        }
+        return NBODY_OK;
+    }
     if (c.j_stage == kSymStage) {
         // gravity's position adjoint over unordered pairs: the pair's term for k is minus its
         // term for j (swapping the two negates both w and d), so each pair is evaluated once

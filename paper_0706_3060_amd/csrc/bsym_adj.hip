@@ -190,20 +190,37 @@ void k_bsym_adj(BSymAdjLaunch a)
     constexpr int NV = (NS + 3) / 4;                              // 128-bit vectors per slot row
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t u = (int64_t)blockIdx.x * kWaves + w;
     __shared__ R st_all[kWaves][2 * kWave];                      // each wave's j chunk, staged twice
     __shared__ float jd_all[kWaves][kChunks][NS][kWave];         // the j sums of block b2, per wave
-    if (u >= a.n_units) return;                                  // whole wave; the kernel has no barriers
-    const int32_t *un = a.units + 4 * u;
-    const int64_t s = un[0], b1 = un[1], b2 = un[2];
-    if (s < 0 || s >= a.n_systems) return;
-    const int64_t po = a.poff[s];
-    const int64_t npad = a.poff[s + 1] - po;
+    int64_t b1, b2, po, npad, slot0;
+    if (a.units) {
+        const int64_t u = (int64_t)blockIdx.x * kWaves + w;
+        if (u >= a.n_units) return;                              // whole wave; the kernel has no barriers
+        const int32_t *un = a.units + 4 * u;
+        const int64_t s = un[0];
+        b1 = un[1];
+        b2 = un[2];
+        if (s < 0 || s >= a.n_systems) return;
+        po = a.poff[s];
+        npad = a.poff[s + 1] - po;
+        slot0 = a.systab[3 * s + 2];
+    } else {
+        // one system: the workgroups reach the XCDs in turn, so each XCD is given a contiguous
+        // run of workgroups, four consecutive tiles of the strip order each
+        npad = a.single_npad;
+        const int64_t nbs = npad / kBSymRecords, tiles = sym_tiles(nbs);
+        const int64_t per = sym_grid((tiles + kWaves - 1) / kWaves) / kSymXcds;
+        const int64_t u = ((int64_t)(blockIdx.x % kSymXcds) * per + blockIdx.x / kSymXcds) * kWaves + w;
+        if (u >= tiles) return;
+        sym_tile_at(u, nbs, b1, b2);
+        po = 0;
+        slot0 = 0;
+    }
     const int64_t nb = npad / kBSymRecords;
     if (b1 < 0 || b2 < b1 || b2 >= nb) return;                   // never index outside the tables
     const bool diag = b1 == b2;
     const int64_t irec0 = po + b1 * kBSymRecords, jrec0 = po + b2 * kBSymRecords;
-    float4 *slots = a.partial + a.systab[3 * s + 2] * NV;        // [nb][npad][NV] of system s
+    float4 *slots = a.partial + slot0 * NV;                      // [nb][npad][NV] of the system
     R *st = st_all[w];
     float(*jd)[NS][kWave] = jd_all[w];
     const float eps2 = (float)a.eps2;
@@ -302,13 +319,14 @@ template <int LAW>
 __global__ __launch_bounds__(kBSymRecords) void k_bsym_adj_reduce(BSymAdjLaunch a)
 {
     constexpr int NS = BaShape<LAW>::NS, NV = (NS + 3) / 4;
-    const int64_t s = a.red[2 * blockIdx.x], rb = a.red[2 * blockIdx.x + 1];
+    const bool one = a.red == nullptr;                           // one whole system
+    const int64_t s = one ? 0 : a.red[2 * blockIdx.x], rb = one ? blockIdx.x : a.red[2 * blockIdx.x + 1];
     const int64_t l = rb * kBSymRecords + threadIdx.x;
-    const int64_t o = a.off[s];
-    if (l >= a.off[s + 1] - o) return;
-    const int64_t npad = a.poff[s + 1] - a.poff[s];
+    const int64_t o = one ? 0 : a.off[s];
+    if (l >= (one ? a.single_n : a.off[s + 1] - o)) return;
+    const int64_t npad = one ? a.single_npad : a.poff[s + 1] - a.poff[s];
     const int64_t nb = npad / kBSymRecords;
-    const float4 *__restrict__ slots = a.partial + (a.systab[3 * s + 2] + l) * NV;
+    const float4 *__restrict__ slots = a.partial + ((one ? 0 : a.systab[3 * s + 2]) + l) * NV;
     NSum v[NS];
     for (int64_t k = 0; k < nb; ++k) {
 #pragma unroll
@@ -346,9 +364,17 @@ int bsym_adj_sums(int law) { return law == GRAVITY ? BaShape<GRAVITY>::NS : BaSh
 
 hipError_t launch_bsym_adj(const BSymAdjLaunch &a, hipStream_t s)
 {
-    if (a.n_units <= 0) return hipSuccess;
     if (!bsym_adj_supported(a.law, a.prec)) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((a.n_units + kWaves - 1) / kWaves)), block(kWaves * kWave);
+    int64_t wgs;
+    if (a.units) {
+        if (a.n_units <= 0) return hipSuccess;
+        wgs = (a.n_units + kWaves - 1) / kWaves;
+    } else {
+        if (a.single_n <= 0) return hipSuccess;
+        if (a.single_npad % kBSymRecords != 0 || a.single_n > a.single_npad || a.red) return hipErrorInvalidValue;
+        wgs = sym_grid((sym_tiles(a.single_npad / kBSymRecords) + kWaves - 1) / kWaves);
+    }
+    const dim3 grid((unsigned)wgs), block(kWaves * kWave);
     const bool kahan = a.prec == P_KAHAN;
     if (a.law == GRAVITY) {
         if (kahan) hipLaunchKernelGGL((k_bsym_adj<GRAVITY, P_KAHAN>), grid, block, 0, s, a);
@@ -362,10 +388,13 @@ hipError_t launch_bsym_adj(const BSymAdjLaunch &a, hipStream_t s)
 
 hipError_t launch_bsym_adj_reduce(const BSymAdjLaunch &a, hipStream_t s)
 {
-    if (a.n_red <= 0) return hipSuccess;
     if (!bsym_adj_supported(a.law, a.prec)) return hipErrorInvalidValue;
-    if (a.law == GRAVITY) hipLaunchKernelGGL((k_bsym_adj_reduce<GRAVITY>), dim3((unsigned)a.n_red), dim3(kBSymRecords), 0, s, a);
-    else hipLaunchKernelGGL((k_bsym_adj_reduce<LJC>), dim3((unsigned)a.n_red), dim3(kBSymRecords), 0, s, a);
+    const int64_t blocks = a.red ? a.n_red : (a.single_n + kBSymRecords - 1) / kBSymRecords;
+    if (blocks <= 0) return hipSuccess;
+    if (!a.red && (a.units || a.single_npad % kBSymRecords != 0 || a.single_n > a.single_npad))
+        return hipErrorInvalidValue;
+    if (a.law == GRAVITY) hipLaunchKernelGGL((k_bsym_adj_reduce<GRAVITY>), dim3((unsigned)blocks), dim3(kBSymRecords), 0, s, a);
+    else hipLaunchKernelGGL((k_bsym_adj_reduce<LJC>), dim3((unsigned)blocks), dim3(kBSymRecords), 0, s, a);
     return hipGetLastError();
 }
 

@@ -207,8 +207,9 @@ def test_config_validation(N):
     # the batched entry point keeps j_stage 2 as its own symmetric tiles (every law with FP32 pair
     # arithmetic), in their fixed shape of 4 waves over 256-record blocks; so does the batched
     # backward for the laws it differentiates (gravity and LJC(linear))
-    # the single-system tiles take the forces and leapfrog of every law and gravity's backward
-    # (LJC's backward and FP64 pair arithmetic run one-sided)
+    # the single-system tiles take the forces and leapfrog of every law and gravity's backward at
+    # this size (2^20; LJC(linear)'s backward takes tiles of its own up to 2^17, and FP64 pair
+    # arithmetic runs one-sided)
     ljc_const = N.NBodyLaw(2, 1, 1.0, 0.0, 332.0637, 4.0)
     ljc_sig = N.NBodyLaw(3, 2, 1.0, 0.0, 332.0637, 1.0)
     cases = [(0, grav(1), "sym"), (3, grav(2), "sym"), (0, grav(0), None), (0, grav(3), None),
@@ -382,6 +383,44 @@ def test_jerk_tiles_rule(N):
             parts = 2 if n <= 1 << 17 else 1
             w = lib.nbody_workspace_bytes(api, n, 1, ctypes.byref(g(2)))
             assert w >= parts * blocks * (blocks * 1024) * 32 + blocks * 1024 * 32, (api, n, w)
+
+
+def test_ljc_adjoint_tiles_rule(N):
+    # LJC(linear)'s single-system backward over unordered pairs (the batched adjoint's tiles over
+    # one system, j_stage 2): FP32 pair arithmetic, whole systems of 32,768 to 131,072 atoms by
+    # rule, any size up to 2^17 when forced, in the tiles' fixed shape; other laws' and FP64
+    # backwards, and larger systems, stay as they were
+    lib = N.lib()
+    ljc = lambda prec: N.NBodyLaw(1, prec, 1.0, 0.0, 332.0637, 4.0)
+
+    def get(lw, n):
+        c = N.NBodyConfig()
+        assert lib.nbody_get_config(2, n, 1, ctypes.byref(lw), ctypes.byref(c)) == 0
+        return c
+
+    for prec in (1, 2):
+        for n, want in [(32767, False), (32768, True), (1 << 17, True), ((1 << 17) + 1, False)]:
+            c = get(ljc(prec), n)
+            assert (c.j_stage == 2) == want, (prec, n, c.j_stage)
+            if want:
+                assert (c.block, c.i_per_lane, c.j_tile, c.j_split) == (256, 4, 256, 1), (prec, n)
+    assert get(ljc(0), 1 << 16).j_stage == 0
+    forced = N.NBodyConfig(512, 2, 2048, 2, 2)
+    try:
+        assert lib.nbody_set_config(2, ctypes.byref(forced)) == 0
+        for n in (1, 3001, 1 << 17):
+            c = get(ljc(2), n)
+            assert (c.block, c.i_per_lane, c.j_tile, c.j_split, c.j_stage) == (256, 4, 256, 1, 2), n
+        c = get(ljc(2), (1 << 17) + 1)
+        assert c.j_stage in (0, 1) and c.block <= 256
+    finally:
+        lib.nbody_set_config(2, None)
+    # the workspace holds the records padded to whole 256-record blocks and 32 bytes of slot
+    # partials per atom and block
+    for n in (1000, 1 << 16, 1 << 17):
+        blocks = -(-n // 256)
+        w = lib.nbody_workspace_bytes(2, n, 1, ctypes.byref(ljc(2)))
+        assert w >= blocks * (blocks * 256) * 32 + blocks * 256 * 64, (n, w)
 
 
 def test_exclusions_and_batched_adjoint_validation(N):

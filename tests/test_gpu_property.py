@@ -278,7 +278,8 @@ def test_random_adjoints(nb, n, law, prec, block, ipl, j_tile, j_split, j_stage,
     """The adjoint (gravity: dL/dpos; LJC(linear): dL/dpos and dL/d(q, sigma, eps)) on random
     systems under a forced configuration against the oracle's analytic adjoint (FP64:
     1e-10 of the scale, the cancelling sums of the adjoint; FP32 as the forward).  j_stage 2
-    selects the symmetric tiles for gravity's FP32 position adjoint (elsewhere it reads as 1)."""
+    selects the symmetric tiles for the FP32 adjoints (gravity's position adjoint over the block
+    grid, LJC(linear)'s over 256-record blocks; with FP64 it reads as 1)."""
     lw = gpu_law(nb, law, prec)
     x, par = inputs(law, n, seed)
     g = W.unit_cotangent(n, seed + 1)
