@@ -214,7 +214,7 @@ def forces_subset(pos, params, ilist, law: Law, potential: bool = True):
     par = _params(params, n, law, pos.device)
     il = torch.as_tensor(ilist, device=pos.device).to(torch.int64).contiguous()
     ni = il.numel()
-    if ni and (int(il.min()) < 0 or int(il.max()) >= n):
+    if ni and _checks_values() and (int(il.min()) < 0 or int(il.max()) >= n):
         raise ValueError("ilist indices must lie in [0, %d)" % n)
     f = torch.empty((ni, 3), dtype=torch.float64, device=pos.device)
     p = torch.empty(ni, dtype=torch.float64, device=pos.device) if potential else None
@@ -277,13 +277,20 @@ def forces_batched(offsets, pos, params, law: Law, potential: bool = True,
 
 
 # --------------------------------------------------------------- adjoint
+def _checks_values():
+    """Whether a value check may read device data back: not while a stream is captured (the
+    library keeps such inputs in bounds itself: out-of-range types are not counted, row indices
+    are clamped to the records)."""
+    return not torch.cuda.is_current_stream_capturing()
+
+
 def _types(types, n, n_types, dev):
     if types is None:
         return None, None
     ty = torch.as_tensor(types, device=dev).to(torch.int32).contiguous()
     if ty.shape != (n,):
         raise ValueError("types must have shape (%d,)" % n)
-    if n and (int(ty.min()) < 0 or int(ty.max()) >= n_types):
+    if n and _checks_values() and (int(ty.min()) < 0 or int(ty.max()) >= n_types):
         raise ValueError("types must lie in [0, n_types)")
     return ty, torch.empty((int(n_types), 2), dtype=torch.float64, device=dev)
 
@@ -331,14 +338,7 @@ def forces_backward(pos, params, grad_force, law: Law, want_pos=True, want_param
     dev = pos.device
     gp = torch.empty((n, 3), dtype=torch.float64, device=dev) if want_pos else None
     gq = torch.empty((n, law.n_params), dtype=torch.float64, device=dev) if want_params else None
-    ty = gt = None
-    if types is not None:
-        ty = torch.as_tensor(types, device=dev).to(torch.int32).contiguous()
-        if ty.shape != (n,):
-            raise ValueError("types must have shape (%d,)" % n)
-        if n and (int(ty.min()) < 0 or int(ty.max()) >= n_types):
-            raise ValueError("types must lie in [0, n_types)")
-        gt = torch.empty((int(n_types), 2), dtype=torch.float64, device=dev)
+    ty, gt = _types(types, n, n_types, dev)
     ws = workspace(API_BACKWARD, n, 1, law, dev)
     if exclusions is None:
         N.check(N.lib().nbody_forces_backward(_ptr(pos), _ptr(par), n, ctypes.byref(law.c()), _ptr(g),
@@ -432,7 +432,7 @@ def forces_jerk(pos, vel, mass, law: Law, ilist=None, potential: bool = True):
     if ilist is not None:
         il = torch.as_tensor(ilist, device=pos.device).to(torch.int64).contiguous()
         ni = il.numel()
-        if ni and (int(il.min()) < 0 or int(il.max()) >= n):
+        if ni and _checks_values() and (int(il.min()) < 0 or int(il.max()) >= n):
             raise ValueError("ilist indices must lie in [0, %d)" % n)
     dev = pos.device
     a = torch.empty((ni, 3), dtype=torch.float64, device=dev)

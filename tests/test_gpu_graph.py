@@ -207,6 +207,35 @@ def test_backward_batched_replay(nb, tiles):
         torch.cuda.synchronize()
 
 
+def test_backward_single_system_tiles_replay(nb):
+    """LJC(linear)'s single-system adjoint over unordered pairs (pack, tiles, slot reduction,
+    per-type sums) captured and replayed: its tile order is arithmetic, with no plan tables."""
+    s = W.md_system(3001, 84, box=48.0)
+    X, P = dev(s.pos), dev(s.params())
+    g_in = dev(np.random.default_rng(6).standard_normal((3001, 3)))
+    types = torch.tensor(s.types.astype(np.int32), device="cuda")
+    law = nb.ljc_linear("fp32_kahan")
+    try:
+        nb.set_config(nb.API_BACKWARD, 256, 4, 256, 1, 2)
+        ref = nb.forces_backward(X, P, g_in, law, types=types, n_types=4)
+        torch.cuda.synchronize()
+        warm_on_side_stream(lambda: nb.forces_backward(X, P, g_in, law, types=types, n_types=4))
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            out = nb.forces_backward(X, P, g_in, law, types=types, n_types=4)
+        for _ in range(3):
+            for t in out:
+                t.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert all(torch.equal(a, b) for a, b in zip(out, ref))
+            nb.forces(X, P, law)                                # eager work between replays
+            torch.cuda.synchronize()
+    finally:
+        nb.clear_config(nb.API_BACKWARD)
+
+
 def test_first_batched_launch_refused_under_capture(nb):
     """A new ensemble's first launch uploads its plan tables, which a capture cannot hold:
     the call is refused before anything is enqueued, and the ensemble works eagerly after."""
