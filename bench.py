@@ -266,7 +266,7 @@ def main():
     if args.legs == "all":
         out["shard_share"] = shard_leg(nb, torch, dev, x, m, law, k_ms / max(k_launches, 1))
         out["batched"] = batched_leg(nb, torch, dev, ens)
-        out["backward"] = backward_leg(nb, torch, dev, W)
+        out["backward"] = backward_leg(nb, torch, dev, W, md)
         out["laws"] = laws_leg(nb, torch, dev, W, md)
         out["jerk"] = jerk_leg(nb, torch, dev, W, not args.no_tune)
         out["bonded"] = bonded_leg(nb, torch, dev, W, chains)
@@ -555,8 +555,10 @@ def batched_leg(nb, torch, dev, ens):
     return res
 
 
-def backward_leg(nb, torch, dev, W):
-    """Position adjoint (Hessian-vector product) of gravity at N = 262,144, FP32 vs FP64."""
+def backward_leg(nb, torch, dev, W, md=None):
+    """Position adjoint (Hessian-vector product) of gravity at N = 262,144, FP32 vs FP64; with
+    the per-law leg's MD box (65,536 atoms), LJC(linear)'s adjoint (positions, charges, sigma and
+    epsilon) in FP32 + Kahan by the rule (unordered pairs), one-sided, and in FP64."""
     n = 262144
     pos, _, m = W.plummer(n, 6)
     g = W.unit_cotangent(n, 56)
@@ -583,7 +585,47 @@ def backward_leg(nb, torch, dev, W):
     res["flops_per_pair"] = nb.flops_per_pair(nb.API_BACKWARD, nb.GRAVITY, False)
     res["fp32_tflops"] = res["flops_per_pair"] * float(n) ** 2 / (res["fp32_fp64acc_ms"] * 1e-3) / 1e12
     res["err_vs_fp64"] = {"median": float(np.median(e)), "max": float(e.max())}
+    if md is not None:
+        res["ljc_linear"] = ljc_backward(nb, torch, dev, W, md)
     log("backward:", res)
+    return res
+
+
+def ljc_backward(nb, torch, dev, W, md):
+    n = md.n
+    x = torch.tensor(md.pos, device=dev)
+    p = torch.tensor(md.params(), device=dev)
+    gg = torch.tensor(W.unit_cotangent(n, 57), device=dev)
+    res = {"n": n, "flops_per_pair": nb.flops_per_pair(nb.API_BACKWARD, nb.LJC_LINEAR, False)}
+    outs = {}
+    for name, prec, cfg in (("fp32_kahan", "fp32_kahan", None), ("fp32_kahan_one_sided", "fp32_kahan", (256, 1, 256, 8, 1)),
+                            ("fp64", "fp64", None)):
+        law = nb.ljc_linear(prec)
+        if cfg:
+            nb.set_config(nb.API_BACKWARD, *cfg)
+        try:
+            c = nb.get_config(nb.API_BACKWARD, n, law)
+            nb.forces_backward(x, p, gg, law)
+            torch.cuda.synchronize()
+            best = 1e30
+            for _ in range(3):
+                t = time.perf_counter()
+                out = nb.forces_backward(x, p, gg, law)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t)
+        finally:
+            if cfg:
+                nb.clear_config(nb.API_BACKWARD)
+        outs[name] = out
+        res[name] = {"ms": best * 1e3, "config": c,
+                     "tflops": res["flops_per_pair"] * float(n) ** 2 / best / 1e12}
+    ref = outs["fp64"]
+    e = (torch.linalg.norm(outs["fp32_kahan"][0] - ref[0], dim=1) / torch.linalg.norm(ref[0], dim=1)).cpu().numpy()
+    ep = ((outs["fp32_kahan"][1] - ref[1]).abs() / ref[1].abs().max(dim=0).values).cpu().numpy()
+    res["speedup_vs_one_sided"] = res["fp32_kahan_one_sided"]["ms"] / res["fp32_kahan"]["ms"]
+    res["speedup_vs_fp64"] = res["fp64"]["ms"] / res["fp32_kahan"]["ms"]
+    res["err_vs_fp64"] = {"pos_median": float(np.median(e)), "pos_max": float(e.max()),
+                          "params_median": float(np.median(ep)), "params_max": float(ep.max())}
     return res
 
 
