@@ -62,11 +62,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=N_MAIN, help="particles of the headline workload")
-    ap.add_argument("--legs", default="all", choices=["all", "main", "laws", "batched", "jerk"],
+    ap.add_argument("--legs", default="all", choices=["all", "main", "laws", "batched", "jerk", "backward"],
                     help="'main' runs only the headline workload (for counter runs), 'laws' the "
                          "headline workload and the per-law leg, 'batched' the headline workload "
                          "and the batched forward and backward legs, 'jerk' the headline workload "
-                         "and the acceleration-and-jerk leg")
+                         "and the acceleration-and-jerk leg, 'backward' the headline workload and "
+                         "the single-system adjoints")
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic configuration")
     ap.add_argument("--launch", default=None, metavar="BLOCK,IPL,JTILE,SPLIT,STAGE",
                     help="force the headline kernel's launch configuration (for counter runs of one "
@@ -101,7 +102,8 @@ def main():
     t0 = time.time()
     pos, vel, mass = W.plummer(args.n, 5)
     ens = W.batched_md(256, seed=4) if args.legs in ("all", "batched") else None
-    md = W.md_system(N_LAWS, 3, box=(32.0 * N_LAWS) ** (1.0 / 3.0)) if args.legs in ("all", "laws") else None
+    md = (W.md_system(N_LAWS, 3, box=(32.0 * N_LAWS) ** (1.0 / 3.0)) if args.legs in ("all", "laws", "backward")
+          else None)
     chains = W.bonded_chains(256, 32, 3) if args.legs == "all" else None
     log("inputs drawn in %.1f s" % (time.time() - t0))
     if args.save_inputs:
@@ -280,6 +282,8 @@ def main():
         out["batched_backward"] = batched_backward_leg(nb, torch, dev, ens)
     elif args.legs == "jerk":
         out["jerk"] = jerk_leg(nb, torch, dev, W, not args.no_tune)
+    elif args.legs == "backward":
+        out["backward"] = backward_leg(nb, torch, dev, W, md)
     print(json.dumps(out), flush=True)
 
 
