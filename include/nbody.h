@@ -33,7 +33,7 @@
  * kernels do (Section 2, the remark on Newton's third law).  For gravity and
  * the LJC laws over a whole system, FP32 pair arithmetic, the symmetric pair
  * tiles (j_stage 2,
- * the default from N = 65,536 to 2,097,152) evaluate each unordered pair once
+ * the default for the forces from N = 32,768 to 2,097,152) evaluate each unordered pair once
  * and apply it to both particles through per-block partial sums that a
  * fixed-order reduction adds, without atomics; the batched entry point has
  * symmetric tiles of its own for gravity and LJC ensembles.  Either

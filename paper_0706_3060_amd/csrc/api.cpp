@@ -103,6 +103,7 @@ constexpr int kBSymWaves = 4;            // waves (one tile each) per workgroup 
 constexpr int kSymStage = 2;
 constexpr int64_t kSymSmallMax = int64_t(1) << 18;
 constexpr int64_t kSymMinN = int64_t(1) << 16;       // the rule's threshold for whole systems
+constexpr int64_t kSymFwdMinN = int64_t(1) << 15;    // the forward's (forces and leapfrog)
 constexpr int64_t kSymMaxN = int64_t(1) << 21;
 // j parts per tile above 1 (j_split 2 or 4 with j_stage 2) for systems up to this size, where a
 // whole-tile launch fills the chip only a few rounds deep
@@ -412,7 +413,9 @@ std::vector<int> ranked_splits(int law, int prec, int64_t rows, int64_t nj, int 
 Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool pot, bool allow_sym = true)
 {
     Cfg c;
-    if (allow_sym && sym_eligible(api, law, prec) && n == nj && n >= kSymMinN && n <= kSymMaxN) {
+    const bool fwd = api == NBODY_API_FORCES || api == NBODY_API_LEAPFROG;
+    if (allow_sym && sym_eligible(api, law, prec) && n == nj && n >= (fwd ? kSymFwdMinN : kSymMinN) &&
+        n <= kSymMaxN) {
         c.j_stage = kSymStage;
         c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
         // 4 waves of 4 i chunks (half the cross-lane moves per pair, 4 waves per SIMD) against
@@ -429,8 +432,12 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         // last round is partly empty: two j parts per tile (one workgroup each) halve the
         // rounds' length, measured 4-10 % faster per call (kernel and slot reduction) at
         // N = 65,536 to 131,072; four parts shorten the kernel further but double the
-        // reduction's reads again
-        c.j_split = n <= kSymSplitMaxN ? 2 : 1;
+        // reduction's reads again.  Below 65,536 (the forward from 32,768) the 528 to 2,080
+        // tiles fill the chip less than two rounds deep: four parts (the 8-wave shape takes two),
+        // measured 1.24-1.34x the one-sided kernel per call for gravity and 1.32-1.40x for
+        // LJC(linear) with the energies at 32,768 and 49,152 particles (at 16,384 the one-sided
+        // kernel is as fast or faster)
+        c.j_split = n < kSymMinN ? 4 : (n <= kSymSplitMaxN ? 2 : 1);
         return sanitize(c, api, law, prec, round_up(n, 64));
     }
     const int64_t npad = round_up(std::max<int64_t>(std::max(n, nj), 1), 64);

@@ -233,19 +233,23 @@ def test_config_validation(N):
             assert (c.block, c.i_per_lane, c.j_tile, c.j_stage) == (256, 4, 256, 2), (api, law.kind)
         else:
             assert 64 <= c.block <= 256 and c.j_stage in (0, 1), (api, law.kind, law.precision, c.block)
-    # the rule takes the symmetric tiles for whole systems of every law from 65,536 to
-    # 2,097,152 particles; above that their O(n^2) partials (34 GB at 2^21) would outgrow the
-    # workspace, and a forced symmetric configuration reads as one-sided there.  With the
-    # energies (nbody_get_config assumes them) every LJC law takes the 8-wave shape.
+    # the rule takes the symmetric tiles for the forces of whole systems of every law from
+    # 32,768 to 2,097,152 particles (four j parts below 65,536 where the shape takes them);
+    # above that their O(n^2) partials (34 GB at 2^21) would outgrow the workspace, and a forced
+    # symmetric configuration reads as one-sided there.  With the energies (nbody_get_config
+    # assumes them) every LJC law takes the 8-wave shape.
     g1 = grav(2)
     for lw in (g1, ljc, ljc_const, ljc_sig):
-        for n, want in [(65535, False), (65536, True), (1 << 21, True), ((1 << 21) + 1, False),
+        for n, want in [(32767, False), (32768, True), (1 << 21, True), ((1 << 21) + 1, False),
                         (1 << 22, False)]:
             c = N.NBodyConfig()
             assert lib.nbody_get_config(0, n, 1, ctypes.byref(lw), ctypes.byref(c)) == 0
             assert (c.j_stage == 2) == want, (lw.kind, n, c.j_stage)
             if want and lw.kind >= 1:
                 assert (c.block, c.i_per_lane) == (512, 2), (lw.kind, n, c.block, c.i_per_lane)
+            if want:
+                parts = (4 if c.block == 256 else 2) if n < 1 << 16 else (2 if n <= 1 << 17 else 1)
+                assert c.j_split == parts, (lw.kind, n, c.j_split)
             try:
                 assert lib.nbody_set_config(0, ctypes.byref(sym)) == 0
                 assert lib.nbody_get_config(0, n, 1, ctypes.byref(lw), ctypes.byref(c)) == 0

@@ -139,12 +139,13 @@ def test_symmetric_without_softening_and_with_G(nb, shape):
         check(f, p, x, m, 0.0, 6.674e-3, True)
 
 
-def test_symmetric_is_the_rule_and_repeats_bitwise(nb):
-    n = 70000
+@pytest.mark.parametrize("n,parts", [(40000, 4), (70000, 2)])
+def test_symmetric_is_the_rule_and_repeats_bitwise(nb, n, parts):
+    # from 32,768 particles; four j parts below 65,536, two up to 2^17
     x, _, m = W.plummer(n, 77)
     law = nb.gravity("fp32_kahan", softening=0.01)
     c = nb.get_config(nb.API_FORCES, n, law)
-    assert (c["j_stage"], c["j_tile"], c["i_per_lane"], c["block"]) == (2, 1024, 4, 256), c
+    assert (c["j_stage"], c["j_tile"], c["i_per_lane"], c["block"], c["j_split"]) == (2, 1024, 4, 256, parts), c
     X, M = dev(x), dev(m)
     f1, p1 = nb.forces(X, M, law)
     f2, p2 = nb.forces(X, M, law)

@@ -139,6 +139,28 @@ def test_ljc_symmetric_is_the_rule_and_repeats_bitwise(nb, big, kind):
     assert np.median(eu) <= 1e-5 and eu.max() <= 1e-3, (np.median(eu), eu.max())
 
 
+def test_ljc_symmetric_rule_below_65536(nb):
+    # from 32,768 atoms the rule takes the tiles (the 8-wave shape with the energies, in two j
+    # parts, the most it takes), against the one-sided kernel and sampled oracle rows
+    n = 40000
+    s = system(n, 72)
+    law = gpu_law(nb, "linear", "fp32_kahan")
+    c = nb.get_config(nb.API_FORCES, n, law)
+    assert (c["j_stage"], c["j_tile"], c["block"], c["i_per_lane"], c["j_split"]) == (2, 1024, 512, 2, 2), c
+    X, P = dev(s.pos), dev(s.params())
+    f1, u1 = nb.forces(X, P, law)
+    nb.set_config(nb.API_FORCES, 256, 1, 256, 32, 1)                # the one-sided kernel
+    try:
+        f3, u3 = nb.forces(X, P, law)
+    finally:
+        nb.clear_config(nb.API_FORCES)
+    check(host(f1), host(u1), host(f3), host(u3))
+    rows = np.sort(np.random.default_rng(8).choice(n, 256, replace=False))
+    fr, ur = oracle_law("linear", W.round_to_f32(s.pos), s, ilist=rows)
+    e = np.linalg.norm(host(f1)[rows] - fr, axis=1) / np.linalg.norm(fr, axis=1)
+    assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (np.median(e), e.max())
+
+
 @pytest.mark.parametrize("shape", [(512, 2), (256, 4)])
 @pytest.mark.parametrize("kind", ["linear", "constant"])
 def test_ljc_symmetric_leapfrog_step(nb, kind, shape):
