@@ -423,7 +423,7 @@ int leapfrog_step(double *pos, double *vel, double *acc, const double *params,
  * nbody_config.j_stage 2 selects symmetric pair tiles (blocks of 1024
  * records, 8 waves of 2 i chunks, 1 or 2 j parts per tile; FP32 slot
  * partials per row and block added in a fixed order in FP64), the rule's
- * choice from 65,536 particles; an index list runs one-sided.
+ * choice from 32,768 particles; an index list runs one-sided.
  * Workspace: nbody_workspace_bytes(NBODY_API_JERK, max(n, ni), 1, law); for
  * FP32 and n <= 262,144 it covers the tiles' records padded to whole blocks
  * and 32 bytes of slot partials per particle, block and part (1 GiB at

@@ -102,8 +102,8 @@ constexpr int kBatchUnitsPerWave = 8;    // the rule's work units per resident w
 constexpr int kBSymWaves = 4;            // waves (one tile each) per workgroup of the batched symmetric tiles
 constexpr int kSymStage = 2;
 constexpr int64_t kSymSmallMax = int64_t(1) << 18;
-constexpr int64_t kSymMinN = int64_t(1) << 16;       // the rule's threshold for whole systems
-constexpr int64_t kSymFwdMinN = int64_t(1) << 15;    // the forward's (forces and leapfrog)
+constexpr int64_t kSymMinN = int64_t(1) << 15;       // the rule's threshold for whole systems
+constexpr int64_t kSymSplit4Below = int64_t(1) << 16; // four j parts below this size
 constexpr int64_t kSymMaxN = int64_t(1) << 21;
 // j parts per tile above 1 (j_split 2 or 4 with j_stage 2) for systems up to this size, where a
 // whole-tile launch fills the chip only a few rounds deep
@@ -413,9 +413,7 @@ std::vector<int> ranked_splits(int law, int prec, int64_t rows, int64_t nj, int 
 Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool pot, bool allow_sym = true)
 {
     Cfg c;
-    const bool fwd = api == NBODY_API_FORCES || api == NBODY_API_LEAPFROG;
-    if (allow_sym && sym_eligible(api, law, prec) && n == nj && n >= (fwd ? kSymFwdMinN : kSymMinN) &&
-        n <= kSymMaxN) {
+    if (allow_sym && sym_eligible(api, law, prec) && n == nj && n >= kSymMinN && n <= kSymMaxN) {
         c.j_stage = kSymStage;
         c.j_tile = n <= kSymSmallMax ? 1024 : 2048;
         // 4 waves of 4 i chunks (half the cross-lane moves per pair, 4 waves per SIMD) against
@@ -424,20 +422,22 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
         // 8-wave shape is as fast or up to 5 % faster with the energies, the 4-wave one 15-20 %
         // faster without them; the sigmoidal dielectric's longer sequence leaves the 4-wave
         // shape three waves per SIMD, and 8 waves of 2 are 10 % faster either way.
-        const bool four = law == NBODY_LAW_GRAVITY ? (pot || n > (int64_t(1) << 17))
-                                                   : (!pot && law != NBODY_LAW_LJC_SIGMOIDAL);
+        // (the adjoint has no potential, whatever the caller's flag says)
+        const bool with_pot = pot && api != NBODY_API_BACKWARD;
+        const bool four = law == NBODY_LAW_GRAVITY ? (with_pot || n > (int64_t(1) << 17))
+                                                   : (!with_pot && law != NBODY_LAW_LJC_SIGMOIDAL);
         c.ipl = four ? 4 : 2;
         c.block = four ? 256 : kSymThreads;
         // up to 2^17 the 2,080 to 8,256 tiles fill the chip only 2 to 8 rounds deep, and the
         // last round is partly empty: two j parts per tile (one workgroup each) halve the
         // rounds' length, measured 4-10 % faster per call (kernel and slot reduction) at
         // N = 65,536 to 131,072; four parts shorten the kernel further but double the
-        // reduction's reads again.  Below 65,536 (the forward from 32,768) the 528 to 2,080
-        // tiles fill the chip less than two rounds deep: four parts (the 8-wave shape takes two),
-        // measured 1.24-1.34x the one-sided kernel per call for gravity and 1.32-1.40x for
-        // LJC(linear) with the energies at 32,768 and 49,152 particles (at 16,384 the one-sided
-        // kernel is as fast or faster)
-        c.j_split = n < kSymMinN ? 4 : (n <= kSymSplitMaxN ? 2 : 1);
+        // reduction's reads again.  Below 65,536 (from 32,768) the 528 to 2,080 tiles fill the
+        // chip less than two rounds deep: four parts (the 8-wave shape takes two), measured at
+        // 32,768 and 49,152 particles 1.24-1.34x the one-sided kernel per call for gravity's
+        // forces, 1.32-1.40x for LJC(linear)'s with the energies and 1.37-1.45x for gravity's
+        // adjoint (at 16,384 the one-sided kernels are as fast or faster)
+        c.j_split = n < kSymSplit4Below ? 4 : (n <= kSymSplitMaxN ? 2 : 1);
         return sanitize(c, api, law, prec, round_up(n, 64));
     }
     const int64_t npad = round_up(std::max<int64_t>(std::max(n, nj), 1), 64);
@@ -478,8 +478,9 @@ Cfg heuristic(int api, int law, int prec, int64_t n, int64_t nj, int64_t S, bool
     }
     if (api == NBODY_API_JERK && allow_sym && symjerk_ok(law, prec) && n == nj && n >= kSymMinN &&
         n <= kSymJerkMaxN) {
-        // whole systems from 65,536 particles: the symmetric tiles, in two j parts up to 2^17
-        // (the tiles fill the chip only a few rounds deep there)
+        // whole systems from 32,768 particles: the symmetric tiles, in two j parts up to 2^17
+        // (the tiles fill the chip only a few rounds deep there); measured 1.19x the one-sided
+        // kernel per call at 32,768, 1.27x at 49,152 (at 16,384 the one-sided kernel is faster)
         c.j_stage = kSymStage;
         c.j_split = 2;
         return sanitize(c, api, law, prec, npad);

@@ -348,7 +348,7 @@ def test_jerk_and_hermite_validation(N):
 
 def test_jerk_tiles_rule(N):
     # the acceleration-and-jerk tiles (j_stage 2 of the jerk entry point): FP32 gravity, whole
-    # systems of 65,536 to 262,144 particles by rule (two j parts up to 2^17), any size up to
+    # systems of 32,768 to 262,144 particles by rule (two j parts up to 2^17), any size up to
     # 2^18 when forced, in their one shape (8 waves of 2 i chunks over 1024-record blocks);
     # FP64 pair arithmetic and larger systems run one-sided
     lib = N.lib()
@@ -360,7 +360,7 @@ def test_jerk_tiles_rule(N):
         return c
 
     for prec in (1, 2):
-        for n, split in [(65535, None), (65536, 2), (1 << 17, 2), ((1 << 17) + 1, 1), (1 << 18, 1),
+        for n, split in [(32767, None), (32768, 2), (65536, 2), (1 << 17, 2), ((1 << 17) + 1, 1), (1 << 18, 1),
                          ((1 << 18) + 1, None)]:
             c = get(g(prec), n)
             assert (c.j_stage == 2) == (split is not None), (prec, n, c.j_stage)

@@ -294,12 +294,14 @@ def test_symmetric_position_adjoint(nb, shape, split, prec):
         assert np.median(e) <= 1e-5 and e.max() <= 1e-3, (n, np.median(e), e.max())
 
 
-def test_symmetric_position_adjoint_is_the_rule(nb):
-    n = 70000
+@pytest.mark.parametrize("n,parts", [(40000, 2), (70000, 2)])
+def test_symmetric_position_adjoint_is_the_rule(nb, n, parts):
+    # from 32,768 particles (8 waves of 2 chunks without a potential: two j parts at most)
     x, _, m = W.plummer(n, 940)
     g = np.random.default_rng(41).standard_normal((n, 3))
     law = nb.gravity("fp32_fp64acc", softening=0.01)
-    assert nb.get_config(nb.API_BACKWARD, n, law)["j_stage"] == 2
+    c = nb.get_config(nb.API_BACKWARD, n, law)
+    assert (c["j_stage"], c["j_split"]) == (2, parts), c
     X, M, Gd = dev(x), dev(m), dev(g)
     g1, _, _ = nb.forces_backward(X, M, Gd, law)
     g2, _, _ = nb.forces_backward(X, M, Gd, law)
