@@ -5,8 +5,9 @@ oracle's analytic derivatives on the FP32-rounded inputs.
 
 Ragged sizes around the chunk (64) and block (256 records) edges, both FP32 tile-sum precisions,
 positions and parameters with per-type sums; the rule's choice at N = 70,000 (bitwise repeatable,
-equal to the one-sided adjoint to the FP32 bar, sampled rows against the oracle); and exclusion
-lists, which the tiles do not take, running the one-sided kernel.  Bars as for the other FP32
+equal to the one-sided adjoint to the FP32 bar, sampled rows against the oracle); the position or
+the parameter gradients alone (bitwise the same); and exclusion lists, which the tiles do not
+take, running the one-sided kernel.  Bars as for the other FP32
 adjoints: per-atom relative position-gradient error median <= 1e-5 and max <= 1e-3; parameter
 gradients relative to their largest magnitude.
 """
@@ -133,3 +134,17 @@ def test_ljc_adjoint_exclusions_run_one_sided(nb):
     x, p = W.round_to_f32(sy.pos), W.round_to_f32(sy.params())
     ref = oracle.ljc_adjoint_excl(x, p[:, 0], p[:, 1], p[:, 2], W.round_to_f32(g), eoff, eidx)
     check(host(a[0]), host(a[1]), ref)
+
+
+def test_ljc_adjoint_tiles_partial_outputs(nb):
+    # only the position gradient, or only the parameter gradients: the same values bit for bit
+    n = 3001
+    s = system(n, 83)
+    g = W.unit_cotangent(n, 84)
+    law = nb.ljc_linear("fp32_kahan")
+    X, P, G = dev(s.pos), dev(s.params()), dev(g)
+    gp, gq, _ = backward(nb, TILES, X, P, G, law)
+    gp2, gq2, _ = backward(nb, TILES, X, P, G, law, want_params=False)
+    gp3, gq3, _ = backward(nb, TILES, X, P, G, law, want_pos=False)
+    assert gq2 is None and gp3 is None
+    assert torch.equal(gp, gp2) and torch.equal(gq, gq3)
