@@ -419,15 +419,15 @@ int leapfrog_step(double *pos, double *vel, double *acc, const double *params,
  *  out_acc, out_jerk [ni][3] device; out_potential [ni] device or NULL.
  * Swapping i and j negates d, w and the bracket and leaves s unchanged, so
  * each unordered pair's terms serve both particles: for every particle
- * (ilist NULL), FP32 pair arithmetic and up to 262,144 particles,
+ * (ilist NULL), FP32 pair arithmetic and up to 524,288 particles,
  * nbody_config.j_stage 2 selects symmetric pair tiles (blocks of 1024
  * records, 8 waves of 2 i chunks, 1 or 2 j parts per tile; FP32 slot
  * partials per row and block added in a fixed order in FP64), the rule's
  * choice from 32,768 particles; an index list runs one-sided.
  * Workspace: nbody_workspace_bytes(NBODY_API_JERK, max(n, ni), 1, law); for
- * FP32 and n <= 262,144 it covers the tiles' records padded to whole blocks
+ * FP32 and n <= 524,288 it covers the tiles' records padded to whole blocks
  * and 32 bytes of slot partials per particle, block and part (1 GiB at
- * 2^17, 2 GiB at 2^18). */
+ * 2^17, 8 GiB at 2^19). */
 int nbody_forces_jerk(const double *pos, const double *vel, const double *mass, int64_t n,
                       const int64_t *ilist, int64_t ni, const nbody_law *law, double *out_acc,
                       double *out_jerk, double *out_potential, void *ws, size_t ws_bytes,

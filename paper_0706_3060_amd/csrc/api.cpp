@@ -112,8 +112,8 @@ constexpr int64_t kSymSplitMaxN = int64_t(1) << 17;
 // The acceleration-and-jerk tiles (symjerk.hip, j_stage 2 of the jerk entry point): gravity
 // with FP32 pair arithmetic, whole systems of up to kSymJerkMaxN particles, one workgroup shape
 // (8 waves of 2 i chunks, blocks of 1024 records) and 1 or 2 j parts; each row gets one FP32
-// partial of 32 bytes per block and part (2 GiB at kSymJerkMaxN).
-constexpr int64_t kSymJerkMaxN = int64_t(1) << 18;
+// partial of 32 bytes per block and part (8 GiB at kSymJerkMaxN).
+constexpr int64_t kSymJerkMaxN = int64_t(1) << 19;
 bool symjerk_ok(int law, int prec)
 {
     return law == NBODY_LAW_GRAVITY && (prec == NBODY_FP32_KAHAN || prec == NBODY_FP32_FP64ACC);

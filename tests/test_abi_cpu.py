@@ -348,8 +348,8 @@ def test_jerk_and_hermite_validation(N):
 
 def test_jerk_tiles_rule(N):
     # the acceleration-and-jerk tiles (j_stage 2 of the jerk entry point): FP32 gravity, whole
-    # systems of 32,768 to 262,144 particles by rule (two j parts up to 2^17), any size up to
-    # 2^18 when forced, in their one shape (8 waves of 2 i chunks over 1024-record blocks);
+    # systems of 32,768 to 524,288 particles by rule (two j parts up to 2^17), any size up to
+    # 2^19 when forced, in their one shape (8 waves of 2 i chunks over 1024-record blocks);
     # FP64 pair arithmetic and larger systems run one-sided
     lib = N.lib()
     g = lambda prec: N.NBodyLaw(0, prec, 1.0, 0.01, 0.0, 1.0)
@@ -360,8 +360,8 @@ def test_jerk_tiles_rule(N):
         return c
 
     for prec in (1, 2):
-        for n, split in [(32767, None), (32768, 2), (65536, 2), (1 << 17, 2), ((1 << 17) + 1, 1), (1 << 18, 1),
-                         ((1 << 18) + 1, None)]:
+        for n, split in [(32767, None), (32768, 2), (65536, 2), (1 << 17, 2), ((1 << 17) + 1, 1), (1 << 19, 1),
+                         ((1 << 19) + 1, None)]:
             c = get(g(prec), n)
             assert (c.j_stage == 2) == (split is not None), (prec, n, c.j_stage)
             if split:
@@ -370,11 +370,11 @@ def test_jerk_tiles_rule(N):
     forced = N.NBodyConfig(256, 4, 2048, 4, 2)
     try:
         assert lib.nbody_set_config(4, ctypes.byref(forced)) == 0
-        for n in (1, 3001, 1 << 17, (1 << 17) + 1, 1 << 18):
+        for n in (1, 3001, 1 << 17, (1 << 17) + 1, 1 << 19):
             c = get(g(2), n)
             assert (c.block, c.i_per_lane, c.j_tile, c.j_split, c.j_stage) == \
                 (512, 2, 1024, 2 if n <= 1 << 17 else 1, 2), n
-        for lw, n in ((g(2), (1 << 18) + 1), (g(0), 4096)):
+        for lw, n in ((g(2), (1 << 19) + 1), (g(0), 4096)):
             c = get(lw, n)
             assert c.j_stage in (0, 1) and c.block <= 256, (lw.precision, n)
     finally:
@@ -382,7 +382,7 @@ def test_jerk_tiles_rule(N):
     # the workspace holds the tiles' block-padded records and their slot partials (32 bytes per
     # row, block and part), for the jerk entry point and for the shared Hermite step
     for api in (4, 5):
-        for n in (1000, 1 << 17, 1 << 18):
+        for n in (1000, 1 << 17, 1 << 19):
             blocks = -(-n // 1024)
             parts = 2 if n <= 1 << 17 else 1
             w = lib.nbody_workspace_bytes(api, n, 1, ctypes.byref(g(2)))

@@ -4,7 +4,7 @@ oracle on the FP32-rounded state.
 
 Ragged sizes around the chunk (64) and block (1024 records) edges, both tile-sum precisions, one
 or two j parts, with and without the potential (the acceleration and jerk bitwise the same); the
-rule's choice at N = 40,000 and 70,000 (bitwise repeatable, equal to the one-sided kernel to the FP32 bar,
+rule's choice at N = 40,000, 70,000 and 300,000 (bitwise repeatable, equal to the one-sided kernel to the FP32 bar,
 sampled rows against the oracle); shared Hermite steps through the tiles against the one-sided
 kernel's and the oracle's FP64 trajectory; and row lists, which the tiles do not take, falling back
 to the one-sided kernel.  Bars as for the other FP32 paths: per-particle relative error of the
@@ -88,12 +88,12 @@ def test_jerk_tiles_ragged_sizes(nb, prec, split):
         assert p2 is None and torch.equal(a, a2) and torch.equal(j, j2), n
 
 
-@pytest.mark.parametrize("n", [40000, 70000])
-def test_jerk_tiles_are_the_rule_and_repeat_bitwise(nb, n):
+@pytest.mark.parametrize("n,parts", [(40000, 2), (70000, 2), (300000, 1)])
+def test_jerk_tiles_are_the_rule_and_repeat_bitwise(nb, n, parts):
     x, v, m = W.plummer(n, 77)
     law = nb.gravity("fp32_kahan", softening=EPS, G=G)
     c = nb.get_config(nb.API_JERK, n, law)
-    assert (c["j_stage"], c["block"], c["j_tile"], c["j_split"]) == (2, 512, 1024, 2), c
+    assert (c["j_stage"], c["block"], c["j_tile"], c["j_split"]) == (2, 512, 1024, parts), c
     X, V, M = dev(x), dev(v), dev(m)
     r1 = nb.forces_jerk(X, V, M, law)
     r2 = nb.forces_jerk(X, V, M, law)
