@@ -327,12 +327,12 @@ int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double
  * (symmetric pair tiles, as the forward's).  LJC(linear)'s position terms
  * of the two atoms are likewise opposite and its charge, sigma and epsilon
  * terms share one scalar: with FP32 pair arithmetic, no exclusion lists and
- * 32,768 to 131,072 atoms the rule evaluates each unordered pair once too
+ * 32,768 to 262,144 atoms the rule evaluates each unordered pair once too
  * (j_stage 2: the batched backward's tiles of 256 x 256 records over the one
- * system; any size up to 131,072 when forced).
+ * system; any size up to 262,144 when forced).
  * Workspace: nbody_workspace_bytes(NBODY_API_BACKWARD, n, 1, law); for
- * LJC(linear) with FP32 and n <= 131,072 it covers 32 bytes of slot
- * partials per atom and 256-record block (2 GiB at 131,072).
+ * LJC(linear) with FP32 and n <= 262,144 it covers 32 bytes of slot
+ * partials per atom and 256-record block (8 GiB at 262,144).
  * Laws: gravity and LJC(linear) (other laws: NBODY_ENOTSUP).
  * Precisions: NBODY_FP64, NBODY_FP32_FP64ACC, NBODY_FP32_KAHAN. */
 int nbody_forces_backward(const double *pos, const double *params, int64_t n,

@@ -391,8 +391,8 @@ def test_jerk_tiles_rule(N):
 
 def test_ljc_adjoint_tiles_rule(N):
     # LJC(linear)'s single-system backward over unordered pairs (the batched adjoint's tiles over
-    # one system, j_stage 2): FP32 pair arithmetic, whole systems of 32,768 to 131,072 atoms by
-    # rule, any size up to 2^17 when forced, in the tiles' fixed shape; other laws' and FP64
+    # one system, j_stage 2): FP32 pair arithmetic, whole systems of 32,768 to 262,144 atoms by
+    # rule, any size up to 2^18 when forced, in the tiles' fixed shape; other laws' and FP64
     # backwards, and larger systems, stay as they were
     lib = N.lib()
     ljc = lambda prec: N.NBodyLaw(1, prec, 1.0, 0.0, 332.0637, 4.0)
@@ -403,7 +403,7 @@ def test_ljc_adjoint_tiles_rule(N):
         return c
 
     for prec in (1, 2):
-        for n, want in [(32767, False), (32768, True), (1 << 17, True), ((1 << 17) + 1, False)]:
+        for n, want in [(32767, False), (32768, True), (1 << 18, True), ((1 << 18) + 1, False)]:
             c = get(ljc(prec), n)
             assert (c.j_stage == 2) == want, (prec, n, c.j_stage)
             if want:
@@ -412,16 +412,16 @@ def test_ljc_adjoint_tiles_rule(N):
     forced = N.NBodyConfig(512, 2, 2048, 2, 2)
     try:
         assert lib.nbody_set_config(2, ctypes.byref(forced)) == 0
-        for n in (1, 3001, 1 << 17):
+        for n in (1, 3001, 1 << 18):
             c = get(ljc(2), n)
             assert (c.block, c.i_per_lane, c.j_tile, c.j_split, c.j_stage) == (256, 4, 256, 1, 2), n
-        c = get(ljc(2), (1 << 17) + 1)
+        c = get(ljc(2), (1 << 18) + 1)
         assert c.j_stage in (0, 1) and c.block <= 256
     finally:
         lib.nbody_set_config(2, None)
     # the workspace holds the records padded to whole 256-record blocks and 32 bytes of slot
     # partials per atom and block
-    for n in (1000, 1 << 16, 1 << 17):
+    for n in (1000, 1 << 16, 1 << 18):
         blocks = -(-n // 256)
         w = lib.nbody_workspace_bytes(2, n, 1, ctypes.byref(ljc(2)))
         assert w >= blocks * (blocks * 256) * 32 + blocks * 256 * 64, (n, w)

@@ -4,7 +4,7 @@ opposite signs, its charge, sigma and epsilon terms from one shared scalar) agai
 oracle's analytic derivatives on the FP32-rounded inputs.
 
 Ragged sizes around the chunk (64) and block (256 records) edges, both FP32 tile-sum precisions,
-positions and parameters with per-type sums; the rule's choice at N = 70,000 (bitwise repeatable,
+positions and parameters with per-type sums; the rule's choice at N = 70,000 and 150,000 (bitwise repeatable,
 equal to the one-sided adjoint to the FP32 bar, sampled rows against the oracle); the position or
 the parameter gradients alone (bitwise the same); and exclusion lists, which the tiles do not
 take, running the one-sided kernel.  Bars as for the other FP32
@@ -98,8 +98,8 @@ def test_ljc_adjoint_tiles_ragged_sizes(nb, prec):
                                            atol=1e-12 * np.abs(gq[:, col]).sum())
 
 
-def test_ljc_adjoint_tiles_are_the_rule_and_repeat_bitwise(nb):
-    n = 70000
+@pytest.mark.parametrize("n", [70000, 150000])
+def test_ljc_adjoint_tiles_are_the_rule_and_repeat_bitwise(nb, n):
     s = system(n, 81)
     g = W.unit_cotangent(n, 82)
     law = nb.ljc_linear("fp32_kahan")
