@@ -327,7 +327,7 @@ int nbody_forces_batched(const int64_t *offsets, int64_t n_systems, const double
  * (symmetric pair tiles, as the forward's).  LJC(linear)'s position terms
  * of the two atoms are likewise opposite and its charge, sigma and epsilon
  * terms share one scalar: with FP32 pair arithmetic, no exclusion lists and
- * 32,768 to 262,144 atoms the rule evaluates each unordered pair once too
+ * 16,384 to 262,144 atoms the rule evaluates each unordered pair once too
  * (j_stage 2: the batched backward's tiles of 256 x 256 records over the one
  * system; any size up to 262,144 when forced).
  * Workspace: nbody_workspace_bytes(NBODY_API_BACKWARD, n, 1, law); for

@@ -129,10 +129,11 @@ size_t symjerk_partial_bytes(int64_t n, int split)
 // LJC(linear)'s single-system adjoint over unordered pairs: the batched adjoint's tiles
 // (bsym_adj.hip, one wave per tile of two 256-record blocks) over one whole system, FP32 pair
 // arithmetic, up to kSymAdjLjcMaxN atoms (32 bytes of slot partials per atom and block: 8 GiB
-// at 2^18).  The rule takes them from kSymAdjLjcMinN atoms: measured 1.37x the one-sided
-// adjoint's kernel at 32,768 atoms, 1.43x at 65,536 and 1.53x at 131,072 (1.16x at 16,384;
-// at 8,192 the 528 tiles leave most of the chip idle and the one-sided kernel is faster).
-constexpr int64_t kSymAdjLjcMinN = int64_t(1) << 15;
+// at 2^18).  The rule takes them from kSymAdjLjcMinN atoms: measured per call 1.03-1.08x the
+// one-sided adjoint at 16,384 atoms, 1.3x at 24,576, and per kernel 1.37x at 32,768, 1.43x at
+// 65,536 and 1.53x at 131,072 (at 8,192 the 528 tiles leave most of the chip idle and the
+// one-sided kernel is faster).
+constexpr int64_t kSymAdjLjcMinN = int64_t(1) << 14;
 constexpr int64_t kSymAdjLjcMaxN = int64_t(1) << 18;
 bool symadj_ljc_ok(int law, int prec)
 {

@@ -391,7 +391,7 @@ def test_jerk_tiles_rule(N):
 
 def test_ljc_adjoint_tiles_rule(N):
     # LJC(linear)'s single-system backward over unordered pairs (the batched adjoint's tiles over
-    # one system, j_stage 2): FP32 pair arithmetic, whole systems of 32,768 to 262,144 atoms by
+    # one system, j_stage 2): FP32 pair arithmetic, whole systems of 16,384 to 262,144 atoms by
     # rule, any size up to 2^18 when forced, in the tiles' fixed shape; other laws' and FP64
     # backwards, and larger systems, stay as they were
     lib = N.lib()
@@ -403,7 +403,7 @@ def test_ljc_adjoint_tiles_rule(N):
         return c
 
     for prec in (1, 2):
-        for n, want in [(32767, False), (32768, True), (1 << 18, True), ((1 << 18) + 1, False)]:
+        for n, want in [(16383, False), (16384, True), (1 << 18, True), ((1 << 18) + 1, False)]:
             c = get(ljc(prec), n)
             assert (c.j_stage == 2) == want, (prec, n, c.j_stage)
             if want:
